@@ -1,0 +1,22 @@
+"""FP64 CPU oracle for the HDG linearised shallow-water solve.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path imports, links or
+executes this package; only the tests, the smoke check and the CPU-baseline
+leg of the benchmark do.  It shares no code with the HIP library: its basis,
+quadrature, topology, assembly, condensation and solvers are written here
+from the paper, in plain numpy / scipy, for a reader to check by eye.
+
+What it computes (paper section / equation):
+* the standard upwind DG system of the linearised SWE, one implicit stage
+  (Appendix A, Eq. bilinear_standardDG_upwind; general linear system), solved
+  directly with SuperLU -- the plain definition of the result;
+* the HDG system (Eq. bilinear_HDG_upwind), its operator split
+  (Eq. ABCMform) and the three-step Schur solve (Steps 1-3, Eqs.
+  schur_system, reconstruct_solution);
+* the non-nested two-level V-cycle (Alg. twolevel_vcycle) with the P1 coarse
+  space, injection prolongation and coarse form (Eq. coarse_problem_upwind);
+* the learned-smoother MLP forward / backward in fp64.
+
+Functions without an independent pin say "parity unpinned" in their
+docstring.
+"""

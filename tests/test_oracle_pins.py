@@ -1,0 +1,310 @@
+"""Pins of the CPU oracle against facts the paper and the mathematics fix.
+
+Each test names what it pins.  None of them compares the oracle with itself
+re-typed: they use closed forms, invariants, the paper's printed tables,
+theorems (HDG == DG), convergence rates and exact special cases.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import hdg_inputs as hi
+from oracle.fem import CellBasis, geometry, lagrange1d, topology, volume_points
+from oracle.hdg import DgOracle, HdgOracle
+from oracle.p1 import TraceMultigrid, p1_matrices
+from oracle.quadrature import gauss01, triangle_rule
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _read_table(name):
+    rows = []
+    for line in open(os.path.join(GOLD, name)):
+        if line.startswith("#") or not line.strip():
+            continue
+        rows.append([None if t == "-" else int(t) for t in line.split()])
+    return rows
+
+
+# ----------------------------------------------------------------- quadrature / basis
+
+@pytest.mark.parametrize("degree", [0, 2, 4, 7, 8])
+def test_triangle_rule_monomials(degree):
+    """Closed form: int_T xi^a eta^b = a! b! / (a+b+2)!."""
+    pts, w = triangle_rule(degree)
+    for a in range(degree + 1):
+        for b in range(degree + 1 - a):
+            exact = math.factorial(a) * math.factorial(b) / math.factorial(a + b + 2)
+            got = np.sum(w * pts[:, 0] ** a * pts[:, 1] ** b)
+            assert abs(got - exact) < 1e-15
+
+
+def test_gauss01_exact():
+    s, w = gauss01(4)
+    for k in range(8):
+        assert abs(np.sum(w * s ** k) - 1.0 / (k + 1)) < 1e-15
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_lagrange_basis_nodal_and_reproducing(p):
+    """Nodal property, partition of unity and exact reproduction/derivative of
+    a degree-p polynomial on skewed cells."""
+    mesh = hi.icosphere(1, radius=3.0)
+    geo = geometry(mesh)
+    bas = CellBasis(geo, p)
+    V = bas.values(bas.nodes)
+    assert np.abs(V - np.eye(V.shape[1])[None]).max() < 1e-11
+    Z, _ = volume_points(geo, 2 * p)
+    vals = bas.values(Z)
+    assert np.abs(vals.sum(-1) - 1).max() < 1e-11
+    poly = lambda z: z[..., 0] ** p - 2 * z[..., 0] * z[..., 1] ** (p - 1) + 0.5
+    dpoly_x = lambda z: p * z[..., 0] ** (p - 1) - 2 * z[..., 1] ** (p - 1)
+    coef = poly(bas.nodes)
+    assert np.abs(np.einsum("cqi,ci->cq", vals, coef) - poly(Z)).max() < 1e-10
+    g = bas.grads(Z)
+    assert np.abs(np.einsum("cqi,ci->cq", g[..., 0], coef) - dpoly_x(Z)).max() < 1e-9
+
+
+def test_lagrange1d():
+    s = np.linspace(0, 1, 7)
+    for p in (1, 2, 3):
+        L = lagrange1d(p, np.arange(p + 1) / p)
+        assert np.abs(L - np.eye(p + 1)).max() < 1e-14
+        assert np.abs(lagrange1d(p, s).sum(1) - 1).max() < 1e-14
+
+
+# ----------------------------------------------------------------- meshes and DOF counts
+
+def test_flat_dof_table():
+    """Tab. grid_setup: N_cell and N_dof (cell / facet) from Eq. ndofs; facet
+    count from the actual skeleton."""
+    for r, ncell, *cols in _read_table("grid_setup_flat.txt"):
+        n = 2 ** r
+        assert 2 * n * n == ncell
+        for p, (c, f) in zip((1, 3, 5), zip(cols[0::2], cols[1::2])):
+            if c is None:
+                continue
+            assert 3 * (p + 1) * (p + 2) // 2 * ncell == c
+            assert 3 * (p + 1) * ncell // 2 == f
+        if r <= 5:
+            mesh = hi.torus(n)
+            topo = topology(mesh)
+            assert mesh.n_cell == ncell
+            assert topo.n_facet * 2 == cols[1]          # p = 1: 2 nodes per facet
+
+
+def test_sphere_dof_table():
+    """Tab. grid_setup_spherical."""
+    rows = _read_table("grid_setup_sphere.txt")
+    for r, ncell, c3, f3, c5, f5 in rows:
+        assert 20 * 4 ** r == ncell
+        assert 3 * 10 * ncell == c3 and 3 * 4 * ncell // 2 == f3
+        assert 3 * 21 * ncell == c5 and 3 * 6 * ncell // 2 == f5
+    mesh = hi.icosphere(3)
+    assert mesh.n_cell == rows[1][1]
+    assert topology(mesh).n_facet * 4 == rows[1][3]
+
+
+@pytest.mark.parametrize("mesh,chi", [(hi.torus(1), 0), (hi.torus(2), 0), (hi.torus(5), 0),
+                                      (hi.icosphere(0), 2), (hi.icosphere(2), 2)])
+def test_euler_characteristic(mesh, chi):
+    topo = topology(mesh)
+    assert mesh.n_vert - topo.n_facet + mesh.n_cell == chi
+    # every facet has two different sides with opposite directions
+    assert (topo.facet_cell[:, 0] != topo.facet_cell[:, 1]).all() or mesh.n_cell <= 2
+
+
+def test_torus_two_cell_mesh():
+    """1x1 periodic square: 2 cells, 3 facets, 1 vertex."""
+    mesh = hi.torus(1)
+    topo = topology(mesh)
+    assert (mesh.n_cell, topo.n_facet, mesh.n_vert) == (2, 3, 1)
+
+
+# ----------------------------------------------------------------- discretisation pins
+
+CASES = [
+    # mesh, p, dt, g, H, f0, omega
+    (hi.torus(1), 1, 0.5, 1.0, 1.0, 0.0, 0.0),
+    (hi.torus(2), 2, 0.4, 2.0, 0.5, 0.7, 0.0),
+    (hi.torus(8), 1, 0.5, 1.0, 1.0, 0.0, 0.0),
+    (hi.torus(6), 3, 0.3, 1.0, 1.0, 1.0, 0.0),
+    (hi.icosphere(2, 6.371e6), 2, 1800.0, 9.81, 5960.0, 0.0, 7.292e-5),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0].kind}{c[0].n}-p{c[1]}")
+def test_hdg_equals_dg(case):
+    """HDG solution identical to the standard DG solution (hybridisation
+    section, cited theorem); the trace equals {{phi}} + [[u]]/(2 tau)."""
+    mesh, p, dt, g, H, f0, om = case
+    r = hi.iid_rhs(mesh, p, 7)[..., 0]
+    qh, lh = HdgOracle(mesh, p, dt, g, H, f0, om).solve(r)
+    qd, ld = DgOracle(mesh, p, dt, g, H, f0, om).solve(r)
+    assert np.linalg.norm(qh - qd) / np.linalg.norm(qd) < 1e-10
+    assert np.linalg.norm(lh - ld) / np.linalg.norm(ld) < 1e-10
+
+
+@pytest.mark.parametrize("f0", [0.0, 1.3])
+def test_constant_state(f0):
+    """Constant right-hand side on the torus: h = h0, u = (I + dt f J)^-1 U0,
+    lam = h0 sqrt(g/H) (closed form of the implicit step for constant fields)."""
+    mesh, p, dt, g, H = hi.torus(4), 2, 0.3, 2.0, 0.5
+    h0, U0 = 0.7, np.array([0.3, -1.1])
+    n = (p + 1) * (p + 2) // 2
+    r = np.zeros((mesh.n_cell, 3, n))
+    r[:, 0], r[:, 1], r[:, 2] = h0, U0[0], U0[1]
+    q, lam = HdgOracle(mesh, p, dt, g, H, f0).solve(r)
+    J = np.array([[0.0, -1.0], [1.0, 0.0]])
+    u = np.linalg.solve(np.eye(2) + dt * f0 * J, U0)
+    assert np.abs(q[:, 0] - h0).max() < 1e-12
+    assert np.abs(q[:, 1] - u[0]).max() < 1e-12 and np.abs(q[:, 2] - u[1]).max() < 1e-12
+    assert np.abs(lam - h0 * np.sqrt(g / H)).max() < 1e-12
+
+
+@pytest.mark.parametrize("case", [CASES[3], CASES[4]], ids=["torus", "sphere"])
+def test_mass_conservation(case):
+    """The mu = 1 trace equation makes facet fluxes telescope: int h = int r_h."""
+    mesh, p, dt, g, H, f0, om = case
+    o = HdgOracle(mesh, p, dt, g, H, f0, om)
+    r = hi.iid_rhs(mesh, p, 3)[..., 0]
+    q, _ = o.solve(r)
+    ints = lambda c: np.einsum("cij,cj->", o.M, c)
+    assert abs(ints(q[:, 0]) - ints(r[:, 0])) < 1e-10 * np.einsum("cij,cj->", o.M, np.abs(r[:, 0]))
+
+
+def test_single_valued_flux():
+    """Flux condition: the two one-sided normal mass fluxes
+    u.n + tau (phi - lam) cancel pointwise on every facet."""
+    mesh, p = hi.torus(4), 3
+    o = HdgOracle(mesh, p, 0.25, 1.0, 1.0, 0.8)
+    q, lam = o.solve(hi.iid_rhs(mesh, p, 11)[..., 0])
+    s, _ = gauss01(p + 2)
+    mu = lagrange1d(p, s)
+    from oracle.fem import facet_points
+    tot = np.zeros((o.topo.n_facet, len(s)))
+    for side in (0, 1):
+        K, i = o.topo.facet_cell[:, side], o.topo.facet_loc[:, side]
+        ss = s if side == 0 else s[::-1]
+        V = np.stack([o.basis.values(facet_points(o.geo, ii, ss))[kk] for kk, ii in zip(K, i)])
+        nrm = o.geo.fnormal[K, i]
+        phi = np.einsum("eqi,ei->eq", V, q[K, 0] * o.hscale)
+        un = np.einsum("eqi,ei->eq", V, q[K, 1]) * nrm[:, 0:1] + np.einsum("eqi,ei->eq", V, q[K, 2]) * nrm[:, 1:2]
+        lq = lam.reshape(-1, p + 1) @ mu.T
+        tot += un + o.tau * (phi - lq)
+    assert np.abs(tot).max() < 1e-11 * np.abs(lam).max()
+
+
+def test_schur_symmetric_positive_definite():
+    """f = 0: the trace operator is symmetric positive definite (relationship
+    to previous work section; CG is used for flat bathymetry).  f != 0: not
+    symmetric."""
+    mesh, p = hi.torus(6), 2
+    S = HdgOracle(mesh, p, 0.4).S.toarray()
+    assert np.abs(S - S.T).max() < 1e-14 * np.abs(S).max()
+    np.linalg.cholesky(S)
+    S2 = HdgOracle(mesh, p, 0.4, f0=1.0).S.toarray()
+    assert np.abs(S2 - S2.T).max() > 1e-3 * np.abs(S2).max()
+
+
+def _mms_error(n, p, kappa_dt=0.05, f0=0.9, g=1.3, H=0.8):
+    """Manufactured smooth periodic solution; returns the L2 error."""
+    mesh = hi.torus(n)
+    o = HdgOracle(mesh, p, kappa_dt, g, H, f0)
+    kap, dt, hs = o.kappa, o.dt, o.hscale
+    tp = 2 * np.pi
+    phi = lambda x, y: np.sin(tp * x) * np.cos(tp * y)
+    ux = lambda x, y: 0.5 * np.cos(tp * x) * np.sin(tp * y)
+    uy = lambda x, y: np.sin(tp * (x + y))
+    divu = lambda x, y: -0.5 * tp * np.sin(tp * x) * np.sin(tp * y) + tp * np.cos(tp * (x + y))
+    gphx = lambda x, y: tp * np.cos(tp * x) * np.cos(tp * y)
+    gphy = lambda x, y: -tp * np.sin(tp * x) * np.sin(tp * y)
+    rphi = lambda x, y: phi(x, y) + kap * divu(x, y)
+    rux = lambda x, y: ux(x, y) - dt * f0 * uy(x, y) + kap * gphx(x, y)
+    ruy = lambda x, y: uy(x, y) + dt * f0 * ux(x, y) + kap * gphy(x, y)
+    Z, w = volume_points(o.geo, 2 * p + 6)
+    X = Z + o.geo.corners3[:, None, 0, :2]
+    V = o.basis.values(Z)
+    Minv = np.linalg.inv(o.M)
+
+    def proj(fun):
+        return np.einsum("cij,cj->ci", Minv, np.einsum("cq,cqi,cq->ci", w, V, fun(X[..., 0], X[..., 1])))
+
+    r = np.stack([proj(rphi) / hs, proj(rux), proj(ruy)], 1)
+    q, _ = o.solve(r)
+    err = 0.0
+    for fld, fun, sc in ((0, phi, 1.0 / hs), (1, ux, 1.0), (2, uy, 1.0)):
+        e = np.einsum("cqi,ci->cq", V, q[:, fld]) - sc * fun(X[..., 0], X[..., 1])
+        err += np.sum(w * e ** 2)
+    return np.sqrt(err)
+
+
+@pytest.mark.parametrize("p", [1, 2])
+def test_mms_convergence(p):
+    """Error decreases at least at rate p + 1/2 (accuracy section), expected
+    close to p + 1."""
+    errs = [_mms_error(n, p) for n in (4, 8, 16)]
+    rates = [np.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert rates[-1] > p + 0.5, (errs, rates)
+
+
+# ----------------------------------------------------------------- multigrid pins
+
+def test_p1_matrices():
+    """P1 mass sums to the domain area; stiffness annihilates constants."""
+    for mesh, area in ((hi.torus(6), 1.0), (hi.icosphere(3), None)):
+        M, K = p1_matrices(mesh)
+        if area is not None:
+            assert abs(M.sum() - area) < 1e-13
+        else:
+            assert abs(M.sum() - geometry(mesh).area.sum()) < 1e-12
+        assert np.abs(K @ np.ones(mesh.n_vert)).max() < 1e-12
+
+
+def test_galerkin_ratio():
+    """Scale of the coarse form: (pi phi)^T S (pi phi) / S_c(phi, phi) -> 1 for
+    a smooth P1 function as h -> 0 at fixed kappa (second order in h).  A
+    coarse form without the 1/kappa factor would give a ratio of kappa."""
+    ratios = []
+    for n in (8, 16, 32):
+        h = hi.torus_hierarchy(n, 4)
+        o = HdgOracle(h.fine, 2, 0.1)
+        tm = TraceMultigrid(o, h)
+        X = h.fine.vert_xyz
+        phi = np.cos(2 * np.pi * X[:, 0]) * np.sin(2 * np.pi * X[:, 1]) + 0.3
+        lam = tm.pi @ phi
+        ratios.append((lam @ (o.S @ lam)) / (phi @ (tm.Sc @ phi)))
+    err = np.abs(np.array(ratios) - 1)
+    assert err[-1] < 2e-3
+    assert err[0] / err[1] > 3.0 and err[1] / err[2] > 3.0
+
+
+def test_vcycle_symmetric_and_convergent():
+    """f = 0: the V-cycle is a fixed symmetric linear operator and PCG with it
+    converges quickly (iteration counts roughly flat in h, cf. Tab. nIterLinear)."""
+    its = []
+    for n in (8, 16, 32):
+        h = hi.torus_hierarchy(n, 4)
+        o = HdgOracle(h.fine, 1, 8.0 / n)
+        tm = TraceMultigrid(o, h)
+        rng = np.random.default_rng(0)
+        x, y = rng.standard_normal((2, o.n_trace))
+        assert abs(x @ tm.vcycle(y) - y @ tm.vcycle(x)) < 1e-11 * abs(x @ tm.vcycle(x))
+        b = o.rhat(hi.iid_rhs(h.fine, 1, 5)[..., 0])
+        xk, r = np.zeros_like(b), b.copy()
+        z = tm.vcycle(r)
+        d, rz = z.copy(), r @ z
+        for k in range(60):
+            Ad = o.S @ d
+            a = rz / (d @ Ad)
+            xk += a * d
+            r -= a * Ad
+            if np.linalg.norm(r) < 1e-8 * np.linalg.norm(b):
+                break
+            z = tm.vcycle(r)
+            rz, rz0 = r @ z, rz
+            d = z + rz / rz0 * d
+        its.append(k + 1)
+    assert max(its) <= 16 and max(its) - min(its) <= 3, its
