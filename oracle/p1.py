@@ -105,6 +105,17 @@ class P1Multigrid:
         return x
 
 
+def facet_blocks(S, ne, m):
+    """Diagonal m x m block of S for every facet: D_e[a, b] = S[e m + a, e m + b]."""
+    Sd = S.tocsr()
+    e = np.arange(ne)
+    D = np.zeros((ne, m, m))
+    for a in range(m):
+        for b in range(m):
+            D[:, a, b] = np.asarray(Sd[e * m + a, e * m + b]).ravel()
+    return D
+
+
 class TraceMultigrid:
     """Non-nested two-level V-cycle on the trace space (Alg. twolevel_vcycle)."""
 
@@ -115,13 +126,8 @@ class TraceMultigrid:
         self.S = hdg.S
         m = hdg.m
         ne = hdg.topo.n_facet
-        Sd = self.S.tocsr()
-        D = np.zeros((ne, m, m))
-        idx = np.arange(ne * m)
-        for a in range(m):
-            for b in range(m):
-                D[:, a, b] = np.asarray(Sd[idx[a::m], idx[b::m]].diagonal())
-        self.Dinv = np.linalg.inv(D)
+        self.D = facet_blocks(self.S, ne, m)
+        self.Dinv = np.linalg.inv(self.D)
         self.m, self.ne = m, ne
         self.pi = injection(hdg.topo, hdg.p, hdg.mesh.n_vert)
         self.mg = P1Multigrid(hier, hdg.kappa, p1_omega, p1_nu)
@@ -153,4 +159,4 @@ class TraceMultigrid:
 
 def default_omega():
     """Damping of the facet block-Jacobi sweep (a stated constant, see tests)."""
-    return 0.5
+    return 0.7

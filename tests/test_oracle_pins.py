@@ -263,6 +263,19 @@ def test_p1_matrices():
         assert np.abs(K @ np.ones(mesh.n_vert)).max() < 1e-12
 
 
+def test_facet_blocks_are_diagonal_blocks_of_S():
+    """The block-Jacobi smoother inverts each facet's own diagonal block:
+    D_e^-1 times the dense (e, e) block of S is the identity for every facet."""
+    h = hi.torus_hierarchy(4, 2)
+    o = HdgOracle(h.fine, 2, 0.3, f0=0.5)
+    tm = TraceMultigrid(o, h)
+    S = o.S.toarray()
+    m = o.m
+    for e in range(o.topo.n_facet):
+        blk = S[e * m:(e + 1) * m, e * m:(e + 1) * m]
+        assert np.abs(tm.Dinv[e] @ blk - np.eye(m)).max() < 1e-12
+
+
 def test_galerkin_ratio():
     """Scale of the coarse form: (pi phi)^T S (pi phi) / S_c(phi, phi) -> 1 for
     a smooth P1 function as h -> 0 at fixed kappa (second order in h).  A
