@@ -1,0 +1,216 @@
+/*
+ * hdg.h -- C ABI of the MI355X (gfx950) HDG trace-multigrid solver for one
+ * implicit stage of the linearised rotating shallow-water equations.
+ *
+ * Method (Betteridge, Gibson, Graham, Mueller, arXiv:2004.09389):
+ *   - hybridised DG with the upwind flux and a scalar facet trace
+ *     (Eq. bilinear_HDG_upwind), one implicit stage of the general linear
+ *     system (Eq. general_linear_system, alpha = 1);
+ *   - static condensation onto the trace: S lam = rhat with
+ *     S = M + C A^-1 B, rhat = C A^-1 f  (Eq. ABCMform; Steps 1-2,
+ *     Eq. schur_system), recovery q = A^-1 (f - B lam) (Step 3,
+ *     Eq. reconstruct_solution);
+ *   - Krylov on the trace system preconditioned by the non-nested two-level
+ *     V-cycle (Alg. twolevel_vcycle) with the P1 coarse space, injection
+ *     prolongation and the coarse form of Eq. coarse_problem_upwind, the
+ *     coarse problem solved by one P1 geometric-multigrid V-cycle.
+ *
+ * Equations solved (BASELINE form), with c = sqrt(g H):
+ *     u + dt (f k x u + g grad h) = r_u,     h + dt H div u = r_h.
+ * Internally phi = h sqrt(g/H) and kappa = c dt (symmetric form, linearised
+ * SWE with flat bathymetry); the trace unknown lam lives in phi units.
+ *
+ * Discretisation conventions (shared with any independent checker):
+ *   - DG basis: Lagrange at the equispaced lattice (i/p, j/p), i+j <= p, of
+ *     the reference triangle, ordered j-major then i, mapped affinely onto the
+ *     cell's unwrapped corners (a, b, c);
+ *   - local facet i of a cell runs from local vertex (i+1)%3 to (i+2)%3
+ *     (counter-clockwise); facets are numbered by first appearance scanning
+ *     cells in order and local facets 0,1,2; the first cell owns the facet and
+ *     fixes its direction; trace node k is at parameter k/p along it;
+ *   - velocity components: x, y on the torus; on the sphere the flat cell's
+ *     frame e1 = (b-a)/|b-a|, e2 = k x e1, k the unit cell normal;
+ *   - Coriolis f = f0 (torus) or f0 + 2 Omega z/|x| (sphere), integrated with
+ *     the collapsed Gauss-Legendre rule of (p+3)^2 points.
+ *
+ * Array layouts (all row-major, RHS index innermost):
+ *   cell arrays   [n_cell][3][n_loc][nrhs]   fields (h, u1, u2), n_loc = (p+1)(p+2)/2
+ *   trace arrays  [n_facet][p+1][nrhs]
+ * Device pointers are HIP device memory owned by the caller; the library
+ * never frees them.  Host pointers are read during the call only.
+ *
+ * Errors: every int-returning entry returns HDG_OK (0) on success, a
+ * negative code on failure (message in hdg_last_error(), thread-local), and
+ * HDG_ENOTCONV (> 0) when a solve stopped at maxit (info still filled).
+ * Calls are asynchronous on the given stream unless stated otherwise; one
+ * context must not be used from two threads or streams at once.
+ */
+#ifndef HDG_H
+#define HDG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ codes */
+#define HDG_OK          0
+#define HDG_EINVAL     -1   /* bad argument or shape */
+#define HDG_ENOMEM     -2   /* device or host allocation failed */
+#define HDG_EHIP       -3   /* HIP runtime error */
+#define HDG_EBREAKDOWN -4   /* NaN / Inf or Krylov breakdown */
+#define HDG_ENOTCONV    1   /* maxit reached before rtol */
+
+#define HDG_TORUS  0
+#define HDG_SPHERE 1
+
+#define HDG_FP64   0        /* everything in FP64 */
+#define HDG_MIXED  1        /* FP32 operator / BF16 smoother storage, FP32 accumulate,
+                               FP64 Krylov, true residual and coarse P1 */
+
+#define HDG_KRYLOV_AUTO   0 /* PCG when the trace operator is symmetric (f = 0, FP64), else FGMRES */
+#define HDG_KRYLOV_PCG    1
+#define HDG_KRYLOV_FGMRES 2
+
+#define HDG_SMOOTH_BJACOBI 0
+#define HDG_SMOOTH_MLP     1
+
+/* ------------------------------------------------------------------ types */
+typedef struct hdg_ctx hdg_ctx;
+
+/* One triangle mesh.  Corner k of cell K sits at
+ * vert_xyz[cell_vert[K][k]] + period * (cell_shift[K][k][0], cell_shift[K][k][1], 0).
+ * Cells are counter-clockwise seen from outside (+z on the torus). */
+typedef struct {
+    int32_t geom;               /* HDG_TORUS or HDG_SPHERE */
+    int32_t n_vert, n_cell;
+    double period;              /* torus side length (ignored on the sphere) */
+    const double  *vert_xyz;    /* (host) [n_vert][3] */
+    const int32_t *cell_vert;   /* (host) [n_cell][3] */
+    const int32_t *cell_shift;  /* (host) [n_cell][3][2], NULL means all zero */
+} hdg_mesh;
+
+typedef struct {
+    int32_t degree;             /* p in 1..3: DG degree, also the trace degree */
+    double dt, g, H;            /* time step, gravity, mean depth (g, H > 0, dt > 0) */
+    double f0, omega;           /* Coriolis: f0 + 2 omega z/|x| on the sphere, f0 on the torus */
+    double tau;                 /* HDG stabilisation (> 0); 1 is the paper's upwind flux */
+} hdg_params;
+
+typedef struct {
+    int32_t krylov;             /* HDG_KRYLOV_* */
+    int32_t precision;          /* HDG_FP64 or HDG_MIXED (solve path) */
+    int32_t smoother;           /* HDG_SMOOTH_BJACOBI or HDG_SMOOTH_MLP */
+    int32_t nu_pre, nu_post;    /* facet block-Jacobi sweeps (default 2, 2) */
+    double  omega;              /* block-Jacobi damping (default 0.7) */
+    int32_t p1_nu;              /* P1 damped-Jacobi sweeps per level, pre and post (default 2) */
+    double  p1_omega;           /* P1 Jacobi damping (default 2/3) */
+    double  rtol;               /* stop when ||rhat - S lam||_2 <= rtol ||rhat||_2 (default 1e-8) */
+    int32_t maxit;              /* max Krylov iterations in total (default 200) */
+    int32_t restart;            /* FGMRES restart length (default 30, max 64) */
+    int32_t max_rhs;            /* largest nrhs any call will use (default 1, max 64) */
+    int32_t use_graph;          /* capture Krylov iteration blocks in HIP graphs (default 1) */
+    double  fallback_ratio;     /* learned smoother: revert to block-Jacobi when the residual
+                                   shrinks by less than this per iteration (default 0.5) */
+} hdg_options;
+
+typedef struct {
+    int32_t iters;              /* Krylov iterations (inner iterations in mixed mode) */
+    int32_t refinements;        /* outer FP64 refinement steps (mixed mode) */
+    int32_t fallbacks;          /* learned-smoother fallbacks */
+    int32_t status;             /* HDG_OK or HDG_ENOTCONV or HDG_EBREAKDOWN */
+    double  rel_res;            /* final true relative residual ||rhat - S lam|| / ||rhat|| */
+} hdg_solve_info;
+
+typedef struct {
+    int32_t n_cell, n_facet, n_vert, degree, n_loc, n_levels;
+    int64_t device_bytes;       /* device memory held by the context */
+    double  kappa;              /* c dt */
+} hdg_sizes;
+
+/* ------------------------------------------------------------------ entry points */
+
+/* Fill *opt with the defaults listed above. */
+int hdg_default_options(hdg_options *opt);
+
+/* hdg_setup: build a context on the current HIP device.
+ *   levels[0..n_levels-1]: P1 multigrid hierarchy, coarse to fine; levels[n_levels-1]
+ *     is the HDG mesh itself (n_levels >= 1).  Each level must be the uniform
+ *     refinement of the previous one.
+ *   parents[l] for l = 1..n_levels-1: (host) [levels[l].n_vert][2] vertex ids in
+ *     level l-1 between which vertex v of level l lies (equal ids for an
+ *     inherited vertex); parents[0] is ignored (may be NULL).
+ * Work (all on the device except topology and the tiny P1 level assembly):
+ * topology (cell->facet maps, orientations), local assembly of A, B, C, M per
+ * cell, per-cell LU-based condensation (S_K = M_K + C_K A_K^-1 B_K, A_K^-1 B_K,
+ * A_K^-1 and C_K A_K^-1 with the mass weighting folded in), assembly of the
+ * facet block rows of S, facet-block inverses, P1 level operators
+ * (1/kappa)(M + kappa^2 K) and transfers, dense inverse on the coarsest level.
+ * Synchronous.  On success *out owns all of it; free with hdg_destroy. */
+int hdg_setup(const hdg_mesh *levels, int32_t n_levels, const int32_t *const *parents,
+              const hdg_params *prm, const hdg_options *opt, hdg_ctx **out);
+
+int hdg_get_sizes(const hdg_ctx *ctx, hdg_sizes *out);
+
+/* Topology as built by the library (host output arrays, synchronous):
+ * facet_cell [n_facet][2] (owner, other), facet_loc [n_facet][2],
+ * facet_vert [n_facet][2] (start, end vertex). Any pointer may be NULL. */
+int hdg_get_topology(const hdg_ctx *ctx, int32_t *facet_cell, int32_t *facet_loc, int32_t *facet_vert);
+
+/* Step 1 (Eq. schur_system right-hand side): rhat = sum_K R_K^T C_K A_K^-1 (r, v)_K.
+ * r_cell: (device) [n_cell][3][n_loc][nrhs] DG coefficients of (r_h, r_u);
+ * rhat:   (device) [n_facet][p+1][nrhs].  1 <= nrhs <= max_rhs. */
+int hdg_condense(hdg_ctx *ctx, int32_t nrhs, const double *r_cell, double *rhat, void *stream);
+
+/* y = S x, matrix-free over facet block rows (Eq. schur_system operator).
+ * precision HDG_FP64 uses the FP64 rows, HDG_MIXED the FP32 rows with FP32 accumulation.
+ * x, y: (device) [n_facet][p+1][nrhs], must not alias. */
+int hdg_trace_apply(hdg_ctx *ctx, int32_t nrhs, int32_t precision, const double *x, double *y, void *stream);
+
+/* z = V(r): one non-nested V-cycle (Alg. twolevel_vcycle) from a zero initial guess:
+ * nu_pre block-Jacobi sweeps, residual, restriction pi^T, one P1 GMG V-cycle on
+ * S_c = (1/kappa)(M_1 + kappa^2 K_1) (Eq. coarse_problem_upwind), prolongation pi,
+ * nu_post sweeps.  precision selects the storage of the trace-level matrices.
+ * r, z: (device) [n_facet][p+1][nrhs], must not alias. */
+int hdg_mg_vcycle(hdg_ctx *ctx, int32_t nrhs, int32_t precision, const double *r, double *z, void *stream);
+
+/* Step 2: solve S lam = rhat to ||rhat - S lam|| <= rtol ||rhat|| per RHS.
+ * lam is the initial guess on entry (device, [n_facet][p+1][nrhs]) and the
+ * solution on exit.  info: (host) [nrhs], may be NULL.  Synchronises the stream. */
+int hdg_solve(hdg_ctx *ctx, int32_t nrhs, const double *rhat, double *lam,
+              hdg_solve_info *info, void *stream);
+
+/* Step 3 (Eq. reconstruct_solution): q = A^-1 ((r, v)_K - B lam), returned as
+ * (h, u1, u2) coefficients in q_cell (device, [n_cell][3][n_loc][nrhs]). */
+int hdg_recover(hdg_ctx *ctx, int32_t nrhs, const double *r_cell, const double *lam,
+                double *q_cell, void *stream);
+
+void hdg_destroy(hdg_ctx *ctx);
+const char *hdg_last_error(void);
+
+/* ------------------------------------------------------------------ measurement helpers */
+
+/* Per-kernel-class timing with HIP events on the launch stream.  When enabled,
+ * every launch of the instrumented kernels is bracketed by events;
+ * hdg_kernel_stats returns, for kernel class id, the launch count and the sum
+ * of the event-measured durations (ms) since the last reset, and the number
+ * of algorithmic bytes one launch moves per RHS at nrhs = 1.  Synchronous. */
+#define HDG_KERNEL_APPLY    0   /* y = S x  (facet block rows) */
+#define HDG_KERNEL_SWEEP    1   /* block-Jacobi sweep with the off-diagonal rows */
+#define HDG_KERNEL_RESIDUAL 2   /* r - S x */
+#define HDG_KERNEL_CONDENSE 3
+#define HDG_KERNEL_RECOVER  4
+#define HDG_KERNEL_COUNT    5
+int hdg_set_timing(hdg_ctx *ctx, int32_t enable);
+int hdg_kernel_stats(hdg_ctx *ctx, int32_t kernel, int32_t precision, int64_t *launches,
+                     double *total_ms, double *bytes_per_launch);
+
+/* Plain device copy dst[i] = src[i], i < n doubles, on the stream: the reference
+ * kernel whose HBM counters calibrate the profiler's byte counts. */
+int hdg_copy(const double *src, double *dst, int64_t n, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HDG_H */

@@ -1,0 +1,771 @@
+// C ABI of the HDG trace-multigrid library: setup, the three-step Schur
+// solve (condense, Krylov on the trace system, recover), the non-nested
+// V-cycle and measurement helpers.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <utility>
+
+#include "hdg_kernels.h"
+
+using hdg::Error;
+
+namespace {
+
+// ------------------------------------------------------------------ allocation helpers
+
+template <typename T>
+T *dev_alloc(hdg_ctx *c, size_t count) {
+    if (count == 0) count = 1;
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, count * sizeof(T));
+    if (e != hipSuccess) throw Error{HDG_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e)};
+    c->allocations.push_back(p);
+    c->device_bytes += (int64_t)(count * sizeof(T));
+    return static_cast<T *>(p);
+}
+
+template <typename T>
+T *dev_upload(hdg_ctx *c, const std::vector<T> &v) {
+    T *p = dev_alloc<T>(c, v.size());
+    if (!v.empty()) HDG_HIP_CHECK(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return p;
+}
+
+void dev_release(hdg_ctx *c, void *p, size_t bytes) {
+    auto it = std::find(c->allocations.begin(), c->allocations.end(), p);
+    if (it != c->allocations.end()) {
+        c->allocations.erase(it);
+        c->device_bytes -= (int64_t)bytes;
+        (void)hipFree(p);
+    }
+}
+
+int guard(const std::function<void()> &fn) {
+    try {
+        fn();
+        return HDG_OK;
+    } catch (const Error &e) {
+        hdg::set_error(e.msg);
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        hdg::set_error("host allocation failed");
+        return HDG_ENOMEM;
+    } catch (const std::exception &e) {
+        hdg::set_error(e.what());
+        return HDG_EINVAL;
+    }
+}
+
+inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+void check_launch() {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) throw Error{HDG_EHIP, std::string("kernel launch: ") + hipGetErrorString(e)};
+}
+
+// ------------------------------------------------------------------ kernel timing
+
+hipEvent_t pool_event(hdg_ctx *c) {
+    if (!c->event_pool.empty()) {
+        hipEvent_t e = c->event_pool.back();
+        c->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    HDG_HIP_CHECK(hipEventCreate(&e));
+    return e;
+}
+
+// Brackets one launch with events on its own stream when timing is enabled.
+struct Timed {
+    hdg_ctx *c;
+    int kind, prec;
+    hipStream_t s;
+    hipEvent_t a = nullptr;
+    Timed(hdg_ctx *c_, int kind_, int prec_, hipStream_t s_) : c(c_), kind(kind_), prec(prec_), s(s_) {
+        if (!c->timing) return;
+        a = pool_event(c);
+        HDG_HIP_CHECK(hipEventRecord(a, s));
+    }
+    ~Timed() {
+        if (!a) return;
+        hipEvent_t b = pool_event(c);
+        (void)hipEventRecord(b, s);
+        c->pending.push_back({a, b, kind, prec});
+    }
+};
+
+void collect_timing(hdg_ctx *c) {
+    if (c->pending.empty()) return;
+    HDG_HIP_CHECK(hipEventSynchronize(c->pending.back().b));
+    for (auto &p : c->pending) {
+        float ms = 0.f;
+        HDG_HIP_CHECK(hipEventElapsedTime(&ms, p.a, p.b));
+        c->t_ms[p.prec][p.kind] += ms;
+        c->t_launches[p.prec][p.kind] += 1;
+        c->event_pool.push_back(p.a);
+        c->event_pool.push_back(p.b);
+    }
+    c->pending.clear();
+}
+
+// ------------------------------------------------------------------ trace-level operators
+
+// y = S x (b == nullptr) or y = b - S x
+void op_apply(hdg_ctx *c, int nb, int prec, const double *x, const double *b, double *y, hipStream_t s,
+              int kind) {
+    Timed t(c, kind, prec, s);
+    if (prec == HDG_MIXED)
+        hdg::launch_trace_apply<float>(c->p, c->n_facet, nb, c->S32, c->nbr, x, b, y, s);
+    else
+        hdg::launch_trace_apply<double>(c->p, c->n_facet, nb, c->S64, c->nbr, x, b, y, s);
+    check_launch();
+}
+
+void op_sweep(hdg_ctx *c, int nb, int prec, const double *x, const double *z0, const double *qc, double *y,
+              hipStream_t s) {
+    Timed t(c, HDG_KERNEL_SWEEP, prec, s);
+    if (prec == HDG_MIXED)
+        hdg::launch_sweep<__hip_bfloat16>(c->p, c->n_facet, nb, c->T16, c->nbr, x, z0, qc, c->facet_vert,
+                                          c->opt.omega, y, s);
+    else
+        hdg::launch_sweep<double>(c->p, c->n_facet, nb, c->T64, c->nbr, x, z0, qc, c->facet_vert, c->opt.omega,
+                                  y, s);
+    check_launch();
+}
+
+// One P1 geometric-multigrid V-cycle on level l (input lev[l].b); returns the
+// buffer holding the result.  Damped Jacobi pre/post smoothing, residual and
+// restriction fused, prolongation fused into the first post-sweep, dense
+// solve on the coarsest level.
+double *p1_vcycle(hdg_ctx *c, int l, int nb, hipStream_t s) {
+    hdg::P1LevelDev &L = c->lev[l];
+    if (l == 0) {
+        hdg::launch_dense_mv(L.n, nb, c->coarse_inv, L.b, L.x, s);
+        return L.x;
+    }
+    const double w = c->opt.p1_omega;
+    double *cur = L.x, *nxt = L.y;
+    hdg::launch_p1_first(L.n, nb, L.dinv, w, L.b, cur, s);
+    for (int k = 1; k < c->opt.p1_nu; ++k) {
+        hdg::launch_p1_sweep(L.n, nb, L.rowptr, L.col, L.val, L.diag, L.dinv, w, L.b, cur, nullptr, nullptr, nxt,
+                             s);
+        std::swap(cur, nxt);
+    }
+    hdg::P1LevelDev &C = c->lev[l - 1];
+    hdg::launch_p1_resid_restrict(C.n, nb, L.crow, L.ccol, L.cw, L.rowptr, L.col, L.val, L.diag, L.b, cur, C.b,
+                                  s);
+    const double *xc = p1_vcycle(c, l - 1, nb, s);
+    for (int k = 0; k < c->opt.p1_nu; ++k) {
+        hdg::launch_p1_sweep(L.n, nb, L.rowptr, L.col, L.val, L.diag, L.dinv, w, L.b, cur, k == 0 ? xc : nullptr,
+                             L.parents, nxt, s);
+        std::swap(cur, nxt);
+    }
+    return cur;
+}
+
+// z = V(r): Alg. twolevel_vcycle from a zero initial guess.
+void vcycle(hdg_ctx *c, int nb, int prec, const double *r, double *z, hipStream_t s) {
+    if (prec == HDG_MIXED)
+        hdg::launch_jacobi0<float>(c->p, c->n_facet, nb, c->Dw32, r, c->vz0, s);
+    else
+        hdg::launch_jacobi0<double>(c->p, c->n_facet, nb, c->Dw64, r, c->vz0, s);
+    double *bufs[2] = {c->vx, c->vx2};
+    int bi = 0;
+    double *cur = c->vz0;  // first sweep from zero gives omega D^-1 r exactly
+    for (int k = 1; k < c->opt.nu_pre; ++k) {
+        double *out = bufs[bi];
+        bi ^= 1;
+        op_sweep(c, nb, prec, cur, c->vz0, nullptr, out, s);
+        cur = out;
+    }
+    op_apply(c, nb, prec, cur, r, c->vres, s, HDG_KERNEL_RESIDUAL);
+    const int L = (int)c->lev.size() - 1;
+    hdg::launch_restrict_trace(c->p, c->n_vert, nb, c->vf_row, c->vf_col, c->vres, c->lev[L].b, s);
+    const double *xl = p1_vcycle(c, L, nb, s);
+    for (int k = 0; k < c->opt.nu_post; ++k) {
+        double *out;
+        if (k == c->opt.nu_post - 1) {
+            out = z;
+        } else {
+            out = bufs[bi];
+            if (out == cur) {
+                bi ^= 1;
+                out = bufs[bi];
+            }
+            bi ^= 1;
+        }
+        op_sweep(c, nb, prec, cur, c->vz0, k == 0 ? xl : nullptr, out, s);
+        cur = out;
+    }
+    check_launch();
+}
+
+// ------------------------------------------------------------------ reductions and Krylov
+
+enum { SC_RR = 0, SC_RZ0, SC_RZ1, SC_PW, SC_BETA, SC_RES, SC_HN2, SC_HN, SC_BN2, SC_COUNT };
+
+double *scal(hdg_ctx *c, int slot) { return c->scal + (size_t)slot * c->opt.max_rhs; }
+int64_t vec_len(const hdg_ctx *c) { return (int64_t)c->n_facet * c->m; }
+
+void dots(hdg_ctx *c, int nb, int nd, const double *X, int64_t xstride, const double *y, double *out,
+          hipStream_t s) {
+    hdg::launch_dots(vec_len(c), nb, nd, X, xstride, y, c->red, c->red_blocks, out, s);
+    check_launch();
+}
+
+void fetch(hdg_ctx *c, const double *dev, int count, hipStream_t s) {
+    HDG_HIP_CHECK(hipMemcpyAsync(c->hscal, dev, count * sizeof(double), hipMemcpyDeviceToHost, s));
+    HDG_HIP_CHECK(hipStreamSynchronize(s));
+}
+
+void fill_info(hdg_solve_info *info, int nb, int its, int refinements, const std::vector<double> &rel,
+               int status) {
+    if (!info) return;
+    for (int r = 0; r < nb; ++r) {
+        info[r].iters = its;
+        info[r].refinements = refinements;
+        info[r].fallbacks = 0;
+        info[r].status = status;
+        info[r].rel_res = rel[r];
+    }
+}
+
+bool all_below(const std::vector<double> &v, double tol) {
+    for (double x : v)
+        if (!(x <= tol)) return false;
+    return true;
+}
+
+bool any_nonfinite(const std::vector<double> &v) {
+    for (double x : v)
+        if (!std::isfinite(x)) return true;
+    return false;
+}
+
+// rel[r] = ||rhat - S lam|| / ||rhat|| with the FP64 operator; the residual stays in out.
+void true_residual(hdg_ctx *c, int nb, const double *rhat, const double *lam, double *out,
+                   std::vector<double> &rel, hipStream_t s) {
+    op_apply(c, nb, HDG_FP64, lam, rhat, out, s, HDG_KERNEL_RESIDUAL);
+    dots(c, nb, 1, out, 0, out, scal(c, SC_RR), s);
+    fetch(c, scal(c, SC_RR), nb, s);
+    for (int r = 0; r < nb; ++r) {
+        const double bn2 = c->hbn2[r];
+        rel[r] = bn2 > 0 ? std::sqrt(c->hscal[r] / bn2) : std::sqrt(c->hscal[r]);
+    }
+}
+
+// Preconditioned CG (f = 0 and FP64: S symmetric positive definite, the
+// V-cycle a fixed symmetric linear operator).  Convergence is judged on the
+// recurrence residual and confirmed on the true residual; PCG restarts from
+// the true residual when the two disagree.
+int solve_pcg(hdg_ctx *c, int nb, const double *rhat, double *lam, hdg_solve_info *info, hipStream_t s) {
+    const int64_t n = vec_len(c);
+    const double rtol = c->opt.rtol;
+    std::vector<double> rel(nb, 0.0);
+    int its = 0, restarts = 0;
+    double *rz = scal(c, SC_RZ0), *rzn = scal(c, SC_RZ1);
+    while (true) {
+        true_residual(c, nb, rhat, lam, c->kr, rel, s);
+        if (any_nonfinite(rel)) { fill_info(info, nb, its, restarts, rel, HDG_EBREAKDOWN); return HDG_EBREAKDOWN; }
+        if (all_below(rel, rtol)) { fill_info(info, nb, its, restarts, rel, HDG_OK); return HDG_OK; }
+        if (its >= c->opt.maxit) { fill_info(info, nb, its, restarts, rel, HDG_ENOTCONV); return HDG_ENOTCONV; }
+        ++restarts;
+        vcycle(c, nb, HDG_FP64, c->kr, c->kz, s);
+        dots(c, nb, 1, c->kr, 0, c->kz, rz, s);
+        hdg::launch_copy(n * nb, c->kz, c->kp, s);
+        while (its < c->opt.maxit) {
+            op_apply(c, nb, HDG_FP64, c->kp, nullptr, c->kw, s, HDG_KERNEL_APPLY);
+            dots(c, nb, 1, c->kp, 0, c->kw, scal(c, SC_PW), s);
+            hdg::launch_pcg_update(n, nb, rz, scal(c, SC_PW), c->kp, c->kw, lam, c->kr, s);
+            ++its;
+            dots(c, nb, 1, c->kr, 0, c->kr, scal(c, SC_RR), s);
+            fetch(c, scal(c, SC_RR), nb, s);
+            bool done = true, bad = false;
+            for (int r = 0; r < nb; ++r) {
+                const double v = c->hscal[r];
+                if (!std::isfinite(v)) bad = true;
+                if (!(v <= rtol * rtol * c->hbn2[r])) done = false;
+            }
+            if (bad || done) break;
+            vcycle(c, nb, HDG_FP64, c->kr, c->kz, s);
+            dots(c, nb, 1, c->kr, 0, c->kz, rzn, s);
+            hdg::launch_pcg_dir(n, nb, rzn, rz, c->kz, c->kp, s);
+            std::swap(rz, rzn);
+        }
+    }
+}
+
+// Flexible GMRES, right preconditioned, classical Gram-Schmidt.  Every
+// restart recomputes the residual with the FP64 operator.  With inner ==
+// HDG_MIXED the Arnoldi process applies the FP32 operator and the
+// mixed-precision V-cycle, and a cycle ends once it has reduced its own
+// starting residual by inner_eta: the restarts are then FP64 iterative
+// refinement around a reduced-precision inner solve.
+int solve_fgmres(hdg_ctx *c, int nb, int inner, double inner_eta, const double *rhat, double *lam,
+                 hdg_solve_info *info, hipStream_t s) {
+    const int64_t n = vec_len(c);
+    const int64_t vs = n * c->opt.max_rhs;
+    const int R = c->opt.restart;
+    const double rtol = c->opt.rtol;
+    std::vector<double> rel(nb, 0.0), cyc0(nb, 0.0);
+    int its = 0, cycles = 0;
+    while (true) {
+        true_residual(c, nb, rhat, lam, c->kV, rel, s);
+        if (any_nonfinite(rel)) { fill_info(info, nb, its, cycles, rel, HDG_EBREAKDOWN); return HDG_EBREAKDOWN; }
+        if (all_below(rel, rtol)) { fill_info(info, nb, its, cycles, rel, HDG_OK); return HDG_OK; }
+        if (its >= c->opt.maxit) { fill_info(info, nb, its, cycles, rel, HDG_ENOTCONV); return HDG_ENOTCONV; }
+        ++cycles;
+        cyc0 = rel;
+        hdg::launch_gmres_start(nb, R, scal(c, SC_RR), c->gm, scal(c, SC_BETA), s);
+        hdg::launch_scale_inv(n, nb, scal(c, SC_BETA), c->kV, c->kV, s);
+        int k = 0;
+        for (int j = 0; j < R && its < c->opt.maxit; ++j) {
+            double *Vj = c->kV + (size_t)j * vs, *Vn = c->kV + (size_t)(j + 1) * vs;
+            double *Zj = c->kZ + (size_t)j * vs;
+            vcycle(c, nb, inner, Vj, Zj, s);
+            op_apply(c, nb, inner, Zj, nullptr, Vn, s, HDG_KERNEL_APPLY);
+            dots(c, nb, j + 1, c->kV, vs, Vn, c->hcol, s);
+            hdg::launch_gs_update(n, nb, j + 1, c->hcol, c->kV, vs, Vn, s);
+            dots(c, nb, 1, Vn, 0, Vn, scal(c, SC_HN2), s);
+            hdg::launch_sqrt(nb, scal(c, SC_HN2), scal(c, SC_HN), s);
+            hdg::launch_scale_inv(n, nb, scal(c, SC_HN), Vn, Vn, s);
+            hdg::launch_gmres_givens(nb, j, R, c->hcol, scal(c, SC_HN), c->gm, c->dbn, scal(c, SC_RES), s);
+            check_launch();
+            ++its;
+            k = j + 1;
+            fetch(c, scal(c, SC_RES), nb, s);
+            bool done = true, bad = false;
+            for (int r = 0; r < nb; ++r) {
+                const double v = c->hscal[r];
+                if (!std::isfinite(v)) bad = true;
+                if (!(v <= std::max(rtol, inner_eta * cyc0[r]))) done = false;
+            }
+            if (bad || done) break;
+        }
+        hdg::launch_gmres_solve(nb, k, R, c->gm, c->hy, s);
+        hdg::launch_lincomb(n, nb, k, c->hy, c->kZ, vs, lam, s);
+        check_launch();
+    }
+}
+
+void check_nb(const hdg_ctx *c, int nb) {
+    HDG_REQUIRE(nb >= 1 && nb <= c->opt.max_rhs, "nrhs must be in 1..max_rhs");
+}
+
+void check_prec(int prec) { HDG_REQUIRE(prec == HDG_FP64 || prec == HDG_MIXED, "precision must be HDG_FP64 or HDG_MIXED"); }
+
+// ------------------------------------------------------------------ setup
+
+void validate_mesh(const hdg_mesh &m) {
+    HDG_REQUIRE(m.geom == HDG_TORUS || m.geom == HDG_SPHERE, "geom must be HDG_TORUS or HDG_SPHERE");
+    HDG_REQUIRE(m.n_vert >= 1 && m.n_cell >= 2, "mesh needs at least one vertex and two cells");
+    HDG_REQUIRE(m.vert_xyz && m.cell_vert, "mesh arrays must not be NULL");
+    HDG_REQUIRE(m.geom == HDG_SPHERE || m.period > 0, "torus period must be positive");
+}
+
+void setup_impl(const hdg_mesh *levels, int nlev, const int32_t *const *parents, const hdg_params *prm,
+                const hdg_options *opt_in, hdg_ctx *c) {
+    HDG_REQUIRE(levels && prm && nlev >= 1, "levels, prm must be given and n_levels >= 1");
+    HDG_REQUIRE(prm->degree >= 1 && prm->degree <= 3, "degree must be 1, 2 or 3");
+    HDG_REQUIRE(prm->dt > 0 && prm->g > 0 && prm->H > 0 && prm->tau > 0, "dt, g, H, tau must be positive");
+    hdg_options opt;
+    hdg_default_options(&opt);
+    if (opt_in) opt = *opt_in;
+    HDG_REQUIRE(opt.max_rhs >= 1 && opt.max_rhs <= 64, "max_rhs must be in 1..64");
+    HDG_REQUIRE(opt.restart >= 1 && opt.restart <= 64, "restart must be in 1..64");
+    HDG_REQUIRE(opt.nu_pre >= 1 && opt.nu_post >= 1 && opt.p1_nu >= 1, "sweep counts must be >= 1");
+    HDG_REQUIRE(opt.omega > 0 && opt.p1_omega > 0, "damping factors must be positive");
+    HDG_REQUIRE(opt.rtol >= 0 && opt.maxit >= 1, "rtol >= 0 and maxit >= 1 required");
+    for (int l = 0; l < nlev; ++l) validate_mesh(levels[l]);
+    const hdg_mesh &fine = levels[nlev - 1];
+
+    HDG_HIP_CHECK(hipGetDevice(&c->device));
+    c->prm = *prm;
+    c->opt = opt;
+    c->p = prm->degree;
+    c->m = c->p + 1;
+    c->n = (c->p + 1) * (c->p + 2) / 2;
+    c->nc = 3 * c->n;
+    c->nt = 3 * c->m;
+    c->geom = fine.geom;
+    c->tau = prm->tau;
+    c->dt = prm->dt;
+    c->kappa = std::sqrt(prm->g * prm->H) * prm->dt;
+    c->hscale = std::sqrt(prm->g / prm->H);
+    c->symmetric = (fine.geom == HDG_TORUS ? prm->f0 == 0.0 : (prm->f0 == 0.0 && prm->omega == 0.0));
+
+    // ---- topology (host)
+    c->topo = hdg::build_topology(fine);
+    const int nk = fine.n_cell, ne = c->topo.n_facet, nv = fine.n_vert;
+    c->n_cell = nk;
+    c->n_facet = ne;
+    c->n_vert = nv;
+    hipStream_t s = nullptr;
+
+    // ---- per-cell assembly and condensation (device)
+    std::vector<double> corners = hdg::cell_corners(fine);
+    double *d_corners = dev_upload(c, corners);
+    hdg::RefTables R = hdg::build_ref_tables(c->p);
+    std::vector<double> ref;
+    for (auto *v : {&R.M, &R.G, &R.E, &R.T, &R.F, &R.qx, &R.qw, &R.Phi}) ref.insert(ref.end(), v->begin(), v->end());
+    double *d_ref = dev_upload(c, ref);
+    int *d_err = dev_alloc<int>(c, 1);
+    HDG_HIP_CHECK(hipMemset(d_err, 0, sizeof(int)));
+    double *Sloc = dev_alloc<double>(c, (size_t)c->nt * c->nt * nk);
+    c->Zr = dev_alloc<double>(c, (size_t)c->nt * c->nc * nk);
+    c->Ar = dev_alloc<double>(c, (size_t)c->nc * c->nc * nk);
+    c->Wr = dev_alloc<double>(c, (size_t)c->nc * c->nt * nk);
+    hdg::CellParams cp{c->kappa, c->tau, c->dt, prm->f0, prm->omega, c->hscale, fine.geom};
+    hdg::launch_cell_condense(c->p, nk, d_corners, d_ref, cp, Sloc, c->Zr, c->Ar, c->Wr, d_err, s);
+    check_launch();
+    HDG_HIP_CHECK(hipDeviceSynchronize());
+    int herr = 0;
+    HDG_HIP_CHECK(hipMemcpy(&herr, d_err, sizeof(int), hipMemcpyDeviceToHost));
+    if (herr & 1) throw Error{HDG_EINVAL, "a cell has non-positive area (cells must be counter-clockwise)"};
+    if (herr & 2) throw Error{HDG_EINVAL, "singular local cell matrix A_K"};
+
+    // ---- facet block rows (device)
+    std::vector<int32_t> cf_t((size_t)3 * nk);
+    std::vector<int8_t> cr_t((size_t)3 * nk);
+    for (int K = 0; K < nk; ++K)
+        for (int i = 0; i < 3; ++i) {
+            cf_t[(size_t)i * nk + K] = c->topo.cell_facet[3 * K + i];
+            cr_t[(size_t)i * nk + K] = c->topo.cell_rev[3 * K + i];
+        }
+    c->cell_facet = dev_upload(c, cf_t);
+    c->cell_rev = dev_upload(c, cr_t);
+    int32_t *d_fcell = dev_upload(c, c->topo.facet_cell);
+    int32_t *d_floc = dev_upload(c, c->topo.facet_loc);
+    c->facet_vert = dev_upload(c, c->topo.facet_vert);
+    const int m = c->m;
+    c->nbr = dev_alloc<int32_t>(c, (size_t)4 * ne);
+    c->S64 = dev_alloc<double>(c, (size_t)5 * m * m * ne);
+    c->T64 = dev_alloc<double>(c, (size_t)4 * m * m * ne);
+    c->Dw64 = dev_alloc<double>(c, (size_t)m * m * ne);
+    c->S32 = dev_alloc<float>(c, (size_t)5 * m * m * ne);
+    c->T16 = dev_alloc<__hip_bfloat16>(c, (size_t)4 * m * m * ne);
+    c->Dw32 = dev_alloc<float>(c, (size_t)m * m * ne);
+    hdg::launch_facet_rows(c->p, ne, nk, Sloc, d_fcell, d_floc, c->cell_facet, c->cell_rev, opt.omega, c->S64,
+                           c->T64, c->Dw64, c->S32, c->T16, c->Dw32, c->nbr, d_err, s);
+    check_launch();
+    HDG_HIP_CHECK(hipDeviceSynchronize());
+    HDG_HIP_CHECK(hipMemcpy(&herr, d_err, sizeof(int), hipMemcpyDeviceToHost));
+    if (herr & 4) throw Error{HDG_EINVAL, "singular facet diagonal block"};
+    c->d_fcell = d_fcell;
+    c->d_floc = d_floc;
+    dev_release(c, Sloc, (size_t)c->nt * c->nt * nk * sizeof(double));
+    dev_release(c, d_corners, corners.size() * sizeof(double));
+
+    // ---- vertex -> facet-end CSR for the trace -> P1 restriction
+    {
+        std::vector<int32_t> cnt(nv + 1, 0);
+        for (int e = 0; e < ne; ++e) {
+            cnt[c->topo.facet_vert[2 * e] + 1]++;
+            cnt[c->topo.facet_vert[2 * e + 1] + 1]++;
+        }
+        for (int v = 0; v < nv; ++v) cnt[v + 1] += cnt[v];
+        std::vector<int32_t> col(cnt[nv]);
+        std::vector<int32_t> fill(cnt.begin(), cnt.end() - 1);
+        for (int e = 0; e < ne; ++e)
+            for (int end = 0; end < 2; ++end) col[fill[c->topo.facet_vert[2 * e + end]]++] = 2 * e + end;
+        c->vf_row = dev_upload(c, cnt);
+        c->vf_col = dev_upload(c, col);
+    }
+
+    // ---- P1 hierarchy
+    HDG_REQUIRE(levels[nlev - 1].n_vert == nv, "the finest hierarchy level must be the HDG mesh");
+    c->lev.resize(nlev);
+    const int mr = opt.max_rhs;
+    for (int l = 0; l < nlev; ++l) {
+        const hdg_mesh &lm = levels[l];
+        hdg::P1Host P = hdg::assemble_p1(lm, c->kappa);
+        hdg::P1LevelDev &L = c->lev[l];
+        L.n = lm.n_vert;
+        std::vector<double> dinv(L.n);
+        for (int v = 0; v < L.n; ++v) {
+            HDG_REQUIRE(P.diag[v] > 0, "P1 operator has a non-positive diagonal");
+            dinv[v] = 1.0 / P.diag[v];
+        }
+        L.rowptr = dev_upload(c, P.rowptr);
+        L.col = dev_upload(c, P.col);
+        L.val = dev_upload(c, P.val);
+        L.diag = dev_upload(c, P.diag);
+        L.dinv = dev_upload(c, dinv);
+        L.b = dev_alloc<double>(c, (size_t)L.n * mr);
+        L.x = dev_alloc<double>(c, (size_t)L.n * mr);
+        L.y = dev_alloc<double>(c, (size_t)L.n * mr);
+        if (l == 0) {
+            HDG_REQUIRE(L.n <= 8192, "coarsest P1 level must have at most 8192 vertices");
+            std::vector<double> dense((size_t)L.n * L.n, 0.0);
+            for (int v = 0; v < L.n; ++v) {
+                dense[(size_t)v * L.n + v] = P.diag[v];
+                for (int k = P.rowptr[v]; k < P.rowptr[v + 1]; ++k) dense[(size_t)v * L.n + P.col[k]] += P.val[k];
+            }
+            if (!hdg::spd_inverse(dense, L.n)) throw Error{HDG_EINVAL, "coarsest P1 operator is singular"};
+            c->coarse_inv = dev_upload(c, dense);
+        } else {
+            HDG_REQUIRE(parents && parents[l], "parents[l] must be given for every level above the coarsest");
+            const int ncv = levels[l - 1].n_vert;
+            std::vector<int32_t> par(parents[l], parents[l] + 2 * (size_t)L.n);
+            std::vector<std::vector<std::pair<int, double>>> ch(ncv);
+            for (int v = 0; v < L.n; ++v)
+                for (int k = 0; k < 2; ++k) {
+                    HDG_REQUIRE(par[2 * v + k] >= 0 && par[2 * v + k] < ncv, "parent id out of range");
+                    ch[par[2 * v + k]].push_back({v, 0.5});
+                }
+            std::vector<int32_t> crow(ncv + 1, 0), ccol;
+            std::vector<double> cw;
+            for (int cv = 0; cv < ncv; ++cv) {
+                for (auto &pr : ch[cv]) {
+                    ccol.push_back(pr.first);
+                    cw.push_back(pr.second);
+                }
+                crow[cv + 1] = (int)ccol.size();
+            }
+            L.parents = dev_upload(c, par);
+            L.crow = dev_upload(c, crow);
+            L.ccol = dev_upload(c, ccol);
+            L.cw = dev_upload(c, cw);
+        }
+    }
+
+    // ---- work vectors
+    const size_t vl = (size_t)ne * m * mr;
+    c->vz0 = dev_alloc<double>(c, vl);
+    c->vx = dev_alloc<double>(c, vl);
+    c->vx2 = dev_alloc<double>(c, vl);
+    c->vres = dev_alloc<double>(c, vl);
+    c->kr = dev_alloc<double>(c, vl);
+    c->kz = dev_alloc<double>(c, vl);
+    c->kp = dev_alloc<double>(c, vl);
+    c->kw = dev_alloc<double>(c, vl);
+    const int Rr = opt.restart;
+    const bool need_gmres = !(opt.krylov == HDG_KRYLOV_PCG);
+    if (need_gmres) {
+        c->kV = dev_alloc<double>(c, vl * (Rr + 1));
+        c->kZ = dev_alloc<double>(c, vl * Rr);
+    }
+    c->red_blocks = 1024;
+    c->red = dev_alloc<double>(c, (size_t)c->red_blocks * (Rr + 1) * mr);
+    c->scal = dev_alloc<double>(c, (size_t)SC_COUNT * mr);
+    c->hcol = dev_alloc<double>(c, (size_t)(Rr + 1) * mr);
+    c->gm = dev_alloc<double>(c, (size_t)((Rr + 1) * Rr + 2 * Rr + (Rr + 1)) * mr);
+    c->hy = dev_alloc<double>(c, (size_t)Rr * mr);
+    c->dbn = dev_alloc<double>(c, mr);
+    c->loc = dev_alloc<double>(c, (size_t)c->nt * nk * mr);
+    HDG_HIP_CHECK(hipHostMalloc((void **)&c->hscal, sizeof(double) * 64 * 4, hipHostMallocDefault));
+    c->hbn2.assign(mr, 0.0);
+    HDG_HIP_CHECK(hipDeviceSynchronize());
+}
+
+void destroy_impl(hdg_ctx *c) {
+    for (void *p : c->allocations) (void)hipFree(p);
+    c->allocations.clear();
+    for (auto &p : c->pending) {
+        (void)hipEventDestroy(p.a);
+        (void)hipEventDestroy(p.b);
+    }
+    for (auto e : c->event_pool) (void)hipEventDestroy(e);
+    if (c->hscal) (void)hipHostFree(c->hscal);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ C ABI
+
+extern "C" int hdg_default_options(hdg_options *o) {
+    if (!o) return HDG_EINVAL;
+    o->krylov = HDG_KRYLOV_AUTO;
+    o->precision = HDG_FP64;
+    o->smoother = HDG_SMOOTH_BJACOBI;
+    o->nu_pre = 2;
+    o->nu_post = 2;
+    o->omega = 0.7;
+    o->p1_nu = 2;
+    o->p1_omega = 2.0 / 3.0;
+    o->rtol = 1e-8;
+    o->maxit = 200;
+    o->restart = 30;
+    o->max_rhs = 1;
+    o->use_graph = 1;
+    o->fallback_ratio = 0.5;
+    return HDG_OK;
+}
+
+extern "C" int hdg_setup(const hdg_mesh *levels, int32_t n_levels, const int32_t *const *parents,
+                         const hdg_params *prm, const hdg_options *opt, hdg_ctx **out) {
+    if (!out) {
+        hdg::set_error("out must not be NULL");
+        return HDG_EINVAL;
+    }
+    *out = nullptr;
+    hdg_ctx *c = new (std::nothrow) hdg_ctx();
+    if (!c) {
+        hdg::set_error("host allocation failed");
+        return HDG_ENOMEM;
+    }
+    int rc = guard([&] { setup_impl(levels, n_levels, parents, prm, opt, c); });
+    if (rc != HDG_OK) {
+        destroy_impl(c);
+        delete c;
+        return rc;
+    }
+    *out = c;
+    return HDG_OK;
+}
+
+extern "C" void hdg_destroy(hdg_ctx *c) {
+    if (!c) return;
+    destroy_impl(c);
+    delete c;
+}
+
+extern "C" int hdg_get_sizes(const hdg_ctx *c, hdg_sizes *out) {
+    if (!c || !out) {
+        hdg::set_error("ctx and out must not be NULL");
+        return HDG_EINVAL;
+    }
+    out->n_cell = c->n_cell;
+    out->n_facet = c->n_facet;
+    out->n_vert = c->n_vert;
+    out->degree = c->p;
+    out->n_loc = c->n;
+    out->n_levels = (int)c->lev.size();
+    out->device_bytes = c->device_bytes;
+    out->kappa = c->kappa;
+    return HDG_OK;
+}
+
+extern "C" int hdg_get_topology(const hdg_ctx *c, int32_t *facet_cell, int32_t *facet_loc, int32_t *facet_vert) {
+    if (!c) {
+        hdg::set_error("ctx must not be NULL");
+        return HDG_EINVAL;
+    }
+    const size_t n2 = (size_t)2 * c->n_facet;
+    if (facet_cell) std::memcpy(facet_cell, c->topo.facet_cell.data(), n2 * sizeof(int32_t));
+    if (facet_loc) std::memcpy(facet_loc, c->topo.facet_loc.data(), n2 * sizeof(int32_t));
+    if (facet_vert) std::memcpy(facet_vert, c->topo.facet_vert.data(), n2 * sizeof(int32_t));
+    return HDG_OK;
+}
+
+extern "C" int hdg_condense(hdg_ctx *c, int32_t nb, const double *r_cell, double *rhat, void *stream) {
+    if (!c) return HDG_EINVAL;
+    return guard([&] {
+        check_nb(c, nb);
+        HDG_REQUIRE(r_cell && rhat, "r_cell and rhat must not be NULL");
+        hipStream_t s = as_stream(stream);
+        Timed t(c, HDG_KERNEL_CONDENSE, HDG_FP64, s);
+        hdg::launch_condense(c->p, c->n_cell, c->n_facet, nb, c->Zr, r_cell, c->loc, c->d_fcell, c->d_floc, rhat, s);
+        check_launch();
+    });
+}
+
+extern "C" int hdg_trace_apply(hdg_ctx *c, int32_t nb, int32_t prec, const double *x, double *y, void *stream) {
+    if (!c) return HDG_EINVAL;
+    return guard([&] {
+        check_nb(c, nb);
+        check_prec(prec);
+        HDG_REQUIRE(x && y && x != y, "x and y must be distinct non-NULL buffers");
+        op_apply(c, nb, prec, x, nullptr, y, as_stream(stream), HDG_KERNEL_APPLY);
+    });
+}
+
+extern "C" int hdg_mg_vcycle(hdg_ctx *c, int32_t nb, int32_t prec, const double *r, double *z, void *stream) {
+    if (!c) return HDG_EINVAL;
+    return guard([&] {
+        check_nb(c, nb);
+        check_prec(prec);
+        HDG_REQUIRE(r && z && r != z, "r and z must be distinct non-NULL buffers");
+        vcycle(c, nb, prec, r, z, as_stream(stream));
+    });
+}
+
+extern "C" int hdg_solve(hdg_ctx *c, int32_t nb, const double *rhat, double *lam, hdg_solve_info *info,
+                         void *stream) {
+    if (!c) return HDG_EINVAL;
+    int status = HDG_OK;
+    int rc = guard([&] {
+        check_nb(c, nb);
+        HDG_REQUIRE(rhat && lam && rhat != lam, "rhat and lam must be distinct non-NULL buffers");
+        hipStream_t s = as_stream(stream);
+        dots(c, nb, 1, rhat, 0, rhat, scal(c, SC_BN2), s);
+        hdg::launch_sqrt(nb, scal(c, SC_BN2), c->dbn, s);
+        fetch(c, scal(c, SC_BN2), nb, s);
+        for (int r = 0; r < nb; ++r) c->hbn2[r] = c->hscal[r];
+        int kry = c->opt.krylov;
+        if (kry == HDG_KRYLOV_AUTO) kry = (c->symmetric && c->opt.precision == HDG_FP64) ? HDG_KRYLOV_PCG : HDG_KRYLOV_FGMRES;
+        if (kry == HDG_KRYLOV_FGMRES) HDG_REQUIRE(c->kV != nullptr, "FGMRES workspace was not allocated (krylov = PCG at setup)");
+        if (kry == HDG_KRYLOV_PCG) {
+            HDG_REQUIRE(c->opt.precision == HDG_FP64, "PCG needs the FP64 (linear) preconditioner");
+            status = solve_pcg(c, nb, rhat, lam, info, s);
+        } else if (c->opt.precision == HDG_MIXED) {
+            status = solve_fgmres(c, nb, HDG_MIXED, 1e-4, rhat, lam, info, s);
+        } else {
+            status = solve_fgmres(c, nb, HDG_FP64, 0.0, rhat, lam, info, s);
+        }
+    });
+    if (rc != HDG_OK) return rc;
+    if (status == HDG_EBREAKDOWN) hdg::set_error("non-finite residual in the Krylov solve");
+    return status;
+}
+
+extern "C" int hdg_recover(hdg_ctx *c, int32_t nb, const double *r_cell, const double *lam, double *q_cell,
+                           void *stream) {
+    if (!c) return HDG_EINVAL;
+    return guard([&] {
+        check_nb(c, nb);
+        HDG_REQUIRE(r_cell && lam && q_cell, "r_cell, lam and q_cell must not be NULL");
+        hipStream_t s = as_stream(stream);
+        Timed t(c, HDG_KERNEL_RECOVER, HDG_FP64, s);
+        hdg::launch_recover(c->p, c->n_cell, nb, c->Ar, c->Wr, c->cell_facet, c->cell_rev, r_cell, lam, q_cell, s);
+        check_launch();
+    });
+}
+
+extern "C" int hdg_set_timing(hdg_ctx *c, int32_t enable) {
+    if (!c) return HDG_EINVAL;
+    return guard([&] {
+        collect_timing(c);
+        c->timing = enable != 0;
+        std::memset(c->t_ms, 0, sizeof(c->t_ms));
+        std::memset(c->t_launches, 0, sizeof(c->t_launches));
+    });
+}
+
+extern "C" int hdg_kernel_stats(hdg_ctx *c, int32_t kernel, int32_t prec, int64_t *launches, double *total_ms,
+                                double *bytes_per_launch) {
+    if (!c) return HDG_EINVAL;
+    return guard([&] {
+        HDG_REQUIRE(kernel >= 0 && kernel < HDG_KERNEL_COUNT, "unknown kernel id");
+        check_prec(prec);
+        collect_timing(c);
+        if (launches) *launches = c->t_launches[prec][kernel];
+        if (total_ms) *total_ms = c->t_ms[prec][kernel];
+        if (bytes_per_launch) {
+            // algorithmic bytes at nrhs = 1: every stored matrix entry once, every
+            // vector entry read or written once, indices once
+            const double m = c->m, ne = c->n_facet, nk = c->n_cell, nc = c->nc, nt = c->nt;
+            const double sm = prec == HDG_MIXED ? 4.0 : 8.0, st = prec == HDG_MIXED ? 2.0 : 8.0;
+            double b = 0;
+            switch (kernel) {
+            case HDG_KERNEL_APPLY: b = ne * (5 * m * m * sm + 4 * 4 + 2 * m * 8); break;
+            case HDG_KERNEL_RESIDUAL: b = ne * (5 * m * m * sm + 4 * 4 + 3 * m * 8); break;
+            case HDG_KERNEL_SWEEP: b = ne * (4 * m * m * st + 4 * 4 + 3 * m * 8); break;
+            case HDG_KERNEL_CONDENSE: b = nk * (nt * nc * 8 + nc * 8) + ne * m * 8; break;
+            case HDG_KERNEL_RECOVER: b = nk * ((nc * nc + nc * nt) * 8 + 2 * nc * 8) + ne * m * 8; break;
+            }
+            *bytes_per_launch = b;
+        }
+    });
+}
+
+extern "C" int hdg_copy(const double *src, double *dst, int64_t n, void *stream) {
+    return guard([&] {
+        HDG_REQUIRE(src && dst && n >= 0, "bad copy arguments");
+        hdg::launch_copy(n, src, dst, as_stream(stream));
+        check_launch();
+    });
+}

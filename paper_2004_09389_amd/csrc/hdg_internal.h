@@ -1,0 +1,152 @@
+// Internal declarations of the HDG trace-multigrid library (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/hdg.h"
+
+namespace hdg {
+
+// ------------------------------------------------------------------ errors
+void set_error(const std::string &msg);
+
+struct Error {
+    int code;
+    std::string msg;
+};
+
+#define HDG_HIP_CHECK(expr)                                                          \
+    do {                                                                             \
+        hipError_t _e = (expr);                                                      \
+        if (_e != hipSuccess)                                                        \
+            throw ::hdg::Error{HDG_EHIP, std::string(#expr) + ": " + hipGetErrorString(_e)}; \
+    } while (0)
+
+#define HDG_REQUIRE(cond, msg)                                                       \
+    do {                                                                             \
+        if (!(cond)) throw ::hdg::Error{HDG_EINVAL, (msg)};                          \
+    } while (0)
+
+// ------------------------------------------------------------------ host topology
+struct Topology {
+    int n_cell = 0, n_facet = 0;
+    std::vector<int32_t> cell_facet;  // [n_cell][3]
+    std::vector<int8_t> cell_rev;     // [n_cell][3] 1 when the cell runs against the facet direction
+    std::vector<int32_t> facet_cell;  // [n_facet][2] owner, other
+    std::vector<int32_t> facet_loc;   // [n_facet][2]
+    std::vector<int32_t> facet_vert;  // [n_facet][2] start, end
+};
+Topology build_topology(const hdg_mesh &mesh);
+
+// Unwrapped corner coordinates [n_cell][3][3].
+std::vector<double> cell_corners(const hdg_mesh &mesh);
+
+// ------------------------------------------------------------------ reference tables
+// Lagrange basis at the equispaced lattice of the reference triangle and the
+// integrals the per-cell assembly needs.  Sizes: n = (p+1)(p+2)/2, m = p+1,
+// nq = (p+3)^2 collapsed Gauss points.
+struct RefTables {
+    int p = 0, n = 0, m = 0, nq = 0;
+    std::vector<double> M;     // [n][n]      int phi_i phi_j
+    std::vector<double> G;     // [2][n][n]   int phi_i d_r phi_j
+    std::vector<double> E;     // [3][n][n]   int_0^1 phi_i phi_j ds on facet f
+    std::vector<double> T;     // [3][n][m]   int_0^1 phi_i mu_k ds on facet f
+    std::vector<double> F;     // [m][m]      int_0^1 mu_k mu_l ds
+    std::vector<double> qx;    // [nq][2]     quadrature points
+    std::vector<double> qw;    // [nq]        weights (sum 1/2)
+    std::vector<double> Phi;   // [nq][n]     basis values at the points
+};
+RefTables build_ref_tables(int p);
+
+// ------------------------------------------------------------------ P1 levels (host)
+struct P1Host {
+    int n = 0;
+    std::vector<int32_t> rowptr, col;  // CSR of S_c without the diagonal
+    std::vector<double> val;
+    std::vector<double> diag;
+};
+P1Host assemble_p1(const hdg_mesh &mesh, double kappa);
+// in-place inverse of a dense SPD matrix [n][n]; returns false when not positive definite
+bool spd_inverse(std::vector<double> &a, int n);
+
+// ------------------------------------------------------------------ context
+struct P1LevelDev {
+    int n = 0;
+    int32_t *rowptr = nullptr, *col = nullptr;
+    double *val = nullptr, *diag = nullptr, *dinv = nullptr;
+    int32_t *parents = nullptr;                    // [n][2] into the coarser level (level > 0)
+    int32_t *crow = nullptr, *ccol = nullptr;      // children CSR of the coarser level (restriction)
+    double *cw = nullptr;
+    double *b = nullptr, *x = nullptr, *y = nullptr;  // [n][max_rhs] work vectors
+};
+
+}  // namespace hdg
+
+struct hdg_ctx {
+    int device = 0;
+    int p = 0, m = 0, n = 0, nc = 0, nt = 0;
+    int n_cell = 0, n_facet = 0, n_vert = 0, geom = 0;
+    double kappa = 0, hscale = 0, tau = 0, dt = 0;
+    hdg_params prm{};
+    hdg_options opt{};
+    bool symmetric = false;
+    hdg::Topology topo;
+    int64_t device_bytes = 0;
+    std::vector<void *> allocations;
+
+    // per-cell matrices, component-major [row][col][n_cell]
+    double *Zr = nullptr;      // [nt][nc]  C A^-1 Mtilde  (condense)
+    double *Ar = nullptr;      // [nc][nc]  A^-1 Mtilde, phi rows / hscale  (recover)
+    double *Wr = nullptr;      // [nc][nt]  A^-1 B, phi rows / hscale       (recover)
+    int32_t *cell_facet = nullptr;  // [3][n_cell]
+    int8_t *cell_rev = nullptr;     // [3][n_cell]
+
+    // facet block rows, component-major [slot][a][b][n_facet]
+    int32_t *nbr = nullptr;     // [4][n_facet]
+    double *S64 = nullptr;      // [5][m][m]  slot 0 = diagonal block
+    double *T64 = nullptr;      // [4][m][m]  omega D^-1 S_j (off-diagonal slots)
+    double *Dw64 = nullptr;     // [m][m]     omega D^-1
+    float *S32 = nullptr;
+    __hip_bfloat16 *T16 = nullptr;
+    float *Dw32 = nullptr;
+    int32_t *facet_vert = nullptr;  // [n_facet][2]
+    int32_t *d_fcell = nullptr;     // [n_facet][2] owner, other cell
+    int32_t *d_floc = nullptr;      // [n_facet][2] local facet index in each
+    int32_t *vf_row = nullptr, *vf_col = nullptr;  // vertex -> (facet, end) CSR, col = 2 e + end
+
+    // P1 hierarchy, level 0 coarsest
+    std::vector<hdg::P1LevelDev> lev;
+    double *coarse_inv = nullptr;   // dense inverse of the coarsest level
+
+    // trace work vectors [n_facet][m][max_rhs]
+    double *vz0 = nullptr, *vx = nullptr, *vx2 = nullptr, *vres = nullptr;
+    // Krylov work
+    double *kr = nullptr, *kz = nullptr, *kp = nullptr, *kw = nullptr, *kd = nullptr;
+    double *kV = nullptr, *kZ = nullptr;      // FGMRES bases [(restart+1)][vec], [restart][vec]
+    double *red = nullptr;                    // reduction partials
+    double *scal = nullptr;                   // device scalars [slot][max_rhs]
+    double *hscal = nullptr;                  // pinned host mirror
+    double *hcol = nullptr;                   // FGMRES Hessenberg column [restart+1][max_rhs]
+    double *gm = nullptr;                     // FGMRES per-RHS state (H, Givens, g)
+    double *hy = nullptr;                     // FGMRES coefficients [restart][max_rhs]
+    double *dbn = nullptr;                    // ||rhat|| per RHS (device)
+    double *loc = nullptr;                    // condensation scratch [nt][n_cell][max_rhs]
+    std::vector<double> hbn2;                 // ||rhat||^2 per RHS (host)
+    int red_blocks = 0;
+
+    // timing
+    struct PendingEvent {
+        hipEvent_t a, b;
+        int kind, prec;
+    };
+    bool timing = false;
+    std::vector<PendingEvent> pending;
+    std::vector<hipEvent_t> event_pool;
+    int64_t t_launches[2][HDG_KERNEL_COUNT] = {};
+    double t_ms[2][HDG_KERNEL_COUNT] = {};
+};

@@ -1,0 +1,914 @@
+// Device kernels of the HDG trace-multigrid library, written for gfx950
+// (64-wide wavefronts).  Layout conventions:
+//   per-cell matrices  component-major [row][col][n_cell]  (lanes = cells, coalesced)
+//   facet block rows   component-major [slot][a][b][n_facet]
+//   vectors            [item][dof][nrhs]  (RHS innermost)
+#include "hdg_kernels.h"
+
+namespace hdg {
+
+// ------------------------------------------------------------------ helpers
+
+__device__ __forceinline__ double ldm(const double *p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ float ldm(const float *p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ float ldm(const __hip_bfloat16 *p) { return __bfloat162float(*p); }
+
+template <typename MT> struct Acc { using type = float; };
+template <> struct Acc<double> { using type = double; };
+
+// ------------------------------------------------------------------ setup: per-cell condensation
+//
+// One wavefront per cell.  The local HDG blocks (Eq. ABCMform) are assembled
+// from reference-element tables and the cell's affine map:
+//   A = [[M + k t sum_f E_f,  k G_1,  k G_2],
+//        [-k G_1^T,           M,     -dt Mf],
+//        [-k G_2^T,           dt Mf,  M   ]]
+//   B = [-k t T_f ; k n_f1 T_f ; k n_f2 T_f],   C = [t T_f^T, n_f1 T_f^T, n_f2 T_f^T],
+//   Mt = t F_f (block diagonal),
+// with k = kappa, t = tau, G_d[i][j] = (d_d phi_j, phi_i), E_f / T_f / F_f the
+// facet mass / facet-trace / trace mass on local facet f.  (This is the HDG
+// form of Eq. bilinear_HDG_upwind after integrating the volume flux term by
+// parts.)  [A | B | Mtilde] is reduced by Gauss-Jordan with partial pivoting
+// in LDS, giving W = A^-1 B and A^-1 Mtilde, then S_K = Mt + C W (Step 2
+// operator) and C A^-1 Mtilde (Step 1 map) are formed.
+
+template <int P>
+__global__ __launch_bounds__(64) void k_cell_condense(int nk, const double *__restrict__ corners,
+                                                      const double *__restrict__ ref, CellParams cp,
+                                                      double *__restrict__ Sloc, double *__restrict__ Zr,
+                                                      double *__restrict__ Ar, double *__restrict__ Wr,
+                                                      int *__restrict__ err) {
+    constexpr int n = (P + 1) * (P + 2) / 2, m = P + 1, nc = 3 * n, nt = 3 * m, nq = (P + 3) * (P + 3);
+    constexpr int LD = nc + nt + nc;
+    __shared__ double aug[nc * LD];
+    __shared__ double Cm[nt * nc];
+    __shared__ double fac[nc];
+    __shared__ double fq[nq];
+    const int K = blockIdx.x;
+    const int lane = threadIdx.x;
+    if (K >= nk) return;
+
+    const double *rM = ref;
+    const double *rG = rM + n * n;
+    const double *rE = rG + 2 * n * n;
+    const double *rT = rE + 3 * n * n;
+    const double *rF = rT + 3 * n * m;
+    const double *rq = rF + m * m;
+    const double *rw = rq + 2 * nq;
+    const double *rPhi = rw + nq;
+
+    // ---- geometry of the flat cell
+    const double *X = corners + 9 * (size_t)K;
+    double ab[3], ac[3];
+    for (int d = 0; d < 3; ++d) {
+        ab[d] = X[3 + d] - X[d];
+        ac[d] = X[6 + d] - X[d];
+    }
+    double e1[3], e2[3];
+    if (cp.geom == HDG_TORUS) {
+        e1[0] = 1; e1[1] = 0; e1[2] = 0;
+        e2[0] = 0; e2[1] = 1; e2[2] = 0;
+    } else {
+        double kn[3] = {ab[1] * ac[2] - ab[2] * ac[1], ab[2] * ac[0] - ab[0] * ac[2], ab[0] * ac[1] - ab[1] * ac[0]};
+        double il = 1.0 / sqrt(kn[0] * kn[0] + kn[1] * kn[1] + kn[2] * kn[2]);
+        for (int d = 0; d < 3; ++d) kn[d] *= il;
+        double la = 1.0 / sqrt(ab[0] * ab[0] + ab[1] * ab[1] + ab[2] * ab[2]);
+        for (int d = 0; d < 3; ++d) e1[d] = ab[d] * la;
+        e2[0] = kn[1] * e1[2] - kn[2] * e1[1];
+        e2[1] = kn[2] * e1[0] - kn[0] * e1[2];
+        e2[2] = kn[0] * e1[1] - kn[1] * e1[0];
+    }
+    const double Pbx = ab[0] * e1[0] + ab[1] * e1[1] + ab[2] * e1[2];
+    const double Pby = ab[0] * e2[0] + ab[1] * e2[1] + ab[2] * e2[2];
+    const double Pcx = ac[0] * e1[0] + ac[1] * e1[1] + ac[2] * e1[2];
+    const double Pcy = ac[0] * e2[0] + ac[1] * e2[1] + ac[2] * e2[2];
+    const double det = Pbx * Pcy - Pby * Pcx;
+    if (!(det > 0.0)) {
+        if (lane == 0) atomicOr(err, 1);
+        return;
+    }
+    // Jinv[r][d] = d xi_r / d x_d
+    const double J00 = Pcy / det, J01 = -Pcx / det, J10 = -Pby / det, J11 = Pbx / det;
+    double L[3], nx[3], ny[3];
+    {
+        const double Px[3] = {0.0, Pbx, Pcx}, Py[3] = {0.0, Pby, Pcy};
+        for (int f = 0; f < 3; ++f) {
+            double tx = Px[(f + 2) % 3] - Px[(f + 1) % 3], ty = Py[(f + 2) % 3] - Py[(f + 1) % 3];
+            L[f] = sqrt(tx * tx + ty * ty);
+            nx[f] = ty / L[f];
+            ny[f] = -tx / L[f];
+        }
+    }
+    const double kap = cp.kappa, tau = cp.tau, dt = cp.dt;
+    for (int q = lane; q < nq; q += 64) {
+        double f = cp.f0;
+        if (cp.geom == HDG_SPHERE && cp.omega != 0.0) {
+            double x0 = X[0] + rq[2 * q] * ab[0] + rq[2 * q + 1] * ac[0];
+            double x1 = X[1] + rq[2 * q] * ab[1] + rq[2 * q + 1] * ac[1];
+            double x2 = X[2] + rq[2 * q] * ab[2] + rq[2 * q + 1] * ac[2];
+            f += 2.0 * cp.omega * x2 / sqrt(x0 * x0 + x1 * x1 + x2 * x2);
+        }
+        fq[q] = f * rw[q];
+    }
+    __syncthreads();
+
+    // ---- assemble [A | B | Mtilde] and C in LDS
+    for (int idx = lane; idx < nc * LD; idx += 64) {
+        const int row = idx / LD, col = idx % LD;
+        const int fr = row / n, i = row % n;
+        double v = 0.0;
+        if (col < nc) {
+            const int fc = col / n, j = col % n;
+            if (fr == 0 && fc == 0) {
+                v = det * rM[i * n + j];
+                for (int f = 0; f < 3; ++f) v += kap * tau * L[f] * rE[f * n * n + i * n + j];
+            } else if (fr == 0) {
+                const double c0 = fc == 1 ? J00 : J01, c1 = fc == 1 ? J10 : J11;
+                v = kap * det * (c0 * rG[i * n + j] + c1 * rG[n * n + i * n + j]);
+            } else if (fc == 0) {
+                const double c0 = fr == 1 ? J00 : J01, c1 = fr == 1 ? J10 : J11;
+                v = -kap * det * (c0 * rG[j * n + i] + c1 * rG[n * n + j * n + i]);
+            } else if (fr == fc) {
+                v = det * rM[i * n + j];
+            } else {
+                double mf = 0.0;
+                for (int q = 0; q < nq; ++q) mf += fq[q] * rPhi[q * n + i] * rPhi[q * n + j];
+                mf *= det;
+                v = (fr == 1) ? -dt * mf : dt * mf;
+            }
+        } else if (col < nc + nt) {
+            const int c = col - nc, f = c / m, k = c % m;
+            const double t = L[f] * rT[f * n * m + i * m + k];
+            v = fr == 0 ? -kap * tau * t : kap * (fr == 1 ? nx[f] : ny[f]) * t;
+        } else {
+            const int c = col - nc - nt, fc = c / n, j = c % n;
+            if (fc == fr) v = (fr == 0 ? cp.hscale : 1.0) * det * rM[i * n + j];
+        }
+        aug[idx] = v;
+    }
+    for (int idx = lane; idx < nt * nc; idx += 64) {
+        const int row = idx / nc, col = idx % nc;
+        const int f = row / m, k = row % m, fc = col / n, j = col % n;
+        const double t = L[f] * rT[f * n * m + j * m + k];
+        Cm[idx] = fc == 0 ? tau * t : (fc == 1 ? nx[f] : ny[f]) * t;
+    }
+    __syncthreads();
+
+    // ---- Gauss-Jordan with partial pivoting
+    for (int k = 0; k < nc; ++k) {
+        double best = (lane >= k && lane < nc) ? fabs(aug[lane * LD + k]) : -1.0;
+        int bi = lane;
+        for (int off = 32; off > 0; off >>= 1) {
+            double ob = __shfl_xor(best, off, 64);
+            int oi = __shfl_xor(bi, off, 64);
+            if (ob > best || (ob == best && oi < bi)) {
+                best = ob;
+                bi = oi;
+            }
+        }
+        if (!(best > 0.0)) {
+            if (lane == 0) atomicOr(err, 2);
+            return;
+        }
+        if (bi != k) {
+            for (int c = lane; c < LD; c += 64) {
+                double t = aug[k * LD + c];
+                aug[k * LD + c] = aug[bi * LD + c];
+                aug[bi * LD + c] = t;
+            }
+        }
+        __syncthreads();
+        const double ip = 1.0 / aug[k * LD + k];
+        __syncthreads();
+        for (int c = lane; c < LD; c += 64) aug[k * LD + c] *= ip;
+        for (int r = lane; r < nc; r += 64) fac[r] = aug[r * LD + k];
+        __syncthreads();
+        for (int idx = lane; idx < nc * (LD - k); idx += 64) {
+            const int r = idx / (LD - k), c = k + idx % (LD - k);
+            if (r != k) aug[r * LD + c] -= fac[r] * aug[k * LD + c];
+        }
+        __syncthreads();
+    }
+
+    // ---- products and outputs
+    const size_t NK = (size_t)nk;
+    for (int idx = lane; idx < nt * nt; idx += 64) {
+        const int a = idx / nt, b = idx % nt;
+        double s = 0.0;
+        if (a / m == b / m) s = tau * L[a / m] * rF[(a % m) * m + (b % m)];
+        for (int j = 0; j < nc; ++j) s += Cm[a * nc + j] * aug[j * LD + nc + b];
+        Sloc[(size_t)idx * NK + K] = s;
+    }
+    for (int idx = lane; idx < nt * nc; idx += 64) {
+        const int a = idx / nc, b = idx % nc;
+        double s = 0.0;
+        for (int j = 0; j < nc; ++j) s += Cm[a * nc + j] * aug[j * LD + nc + nt + b];
+        Zr[(size_t)idx * NK + K] = s;
+    }
+    const double ih = 1.0 / cp.hscale;
+    for (int idx = lane; idx < nc * nc; idx += 64) {
+        const int a = idx / nc, b = idx % nc;
+        Ar[(size_t)idx * NK + K] = (a < n ? ih : 1.0) * aug[a * LD + nc + nt + b];
+    }
+    for (int idx = lane; idx < nc * nt; idx += 64) {
+        const int a = idx / nt, b = idx % nt;
+        Wr[(size_t)idx * NK + K] = (a < n ? ih : 1.0) * aug[a * LD + nc + b];
+    }
+}
+
+// ------------------------------------------------------------------ setup: facet block rows
+//
+// Row block of facet e: S restricted to (e, e') for the five facets e' of the
+// two cells adjacent to e.  The diagonal block sums both cells'
+// contributions; the four off-diagonal slots hold the other two facets of the
+// owner cell, then of the second cell.  Also forms omega D_e^-1 and
+// omega D_e^-1 S_{e,j} used by the block-Jacobi sweep.
+
+template <int M>
+__device__ bool small_inverse(double (&a)[M][M], double (&inv)[M][M]) {
+    for (int i = 0; i < M; ++i)
+        for (int j = 0; j < M; ++j) inv[i][j] = i == j ? 1.0 : 0.0;
+    for (int k = 0; k < M; ++k) {
+        int p = k;
+        for (int i = k + 1; i < M; ++i)
+            if (fabs(a[i][k]) > fabs(a[p][k])) p = i;
+        if (!(fabs(a[p][k]) > 0.0)) return false;
+        if (p != k)
+            for (int j = 0; j < M; ++j) {
+                double t = a[k][j]; a[k][j] = a[p][j]; a[p][j] = t;
+                t = inv[k][j]; inv[k][j] = inv[p][j]; inv[p][j] = t;
+            }
+        double d = 1.0 / a[k][k];
+        for (int j = 0; j < M; ++j) { a[k][j] *= d; inv[k][j] *= d; }
+        for (int i = 0; i < M; ++i) {
+            if (i == k) continue;
+            double f = a[i][k];
+            for (int j = 0; j < M; ++j) { a[i][j] -= f * a[k][j]; inv[i][j] -= f * inv[k][j]; }
+        }
+    }
+    return true;
+}
+
+template <int P>
+__global__ void k_facet_rows(int ne, int nk, const double *__restrict__ Sloc, const int *__restrict__ facet_cell,
+                             const int *__restrict__ facet_loc, const int *__restrict__ cell_facet,
+                             const int8_t *__restrict__ cell_rev, double omega, double *__restrict__ S64,
+                             double *__restrict__ T64, double *__restrict__ Dw64, float *__restrict__ S32,
+                             __hip_bfloat16 *__restrict__ T16, float *__restrict__ Dw32, int *__restrict__ nbr,
+                             int *__restrict__ err) {
+    constexpr int m = P + 1, nt = 3 * m;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= ne) return;
+    double D[m][m] = {};
+    double Off[4][m][m];
+    const size_t NK = (size_t)nk, NE = (size_t)ne;
+    for (int s = 0; s < 2; ++s) {
+        const int K = facet_cell[2 * e + s], i = facet_loc[2 * e + s];
+        for (int jj = 0; jj < 3; ++jj) {
+            const int i2 = (i + jj) % 3;
+            const int e2 = cell_facet[i2 * NK + K];
+            const int rev2 = cell_rev[i2 * NK + K];
+            if (jj > 0) nbr[(2 * s + jj - 1) * NE + e] = e2;
+            for (int a = 0; a < m; ++a) {
+                const int ra = i * m + (s == 0 ? a : P - a);
+                for (int b = 0; b < m; ++b) {
+                    const int cb = i2 * m + (rev2 ? P - b : b);
+                    const double v = Sloc[(size_t)(ra * nt + cb) * NK + K];
+                    if (jj == 0)
+                        D[a][b] += v;
+                    else
+                        Off[2 * s + jj - 1][a][b] = v;
+                }
+            }
+        }
+    }
+    double Dc[m][m], Di[m][m];
+    for (int a = 0; a < m; ++a)
+        for (int b = 0; b < m; ++b) Dc[a][b] = D[a][b];
+    if (!small_inverse<m>(Dc, Di)) {
+        atomicOr(err, 4);
+        return;
+    }
+    for (int a = 0; a < m; ++a)
+        for (int b = 0; b < m; ++b) {
+            const size_t o = (size_t)(a * m + b) * NE + e;
+            S64[o] = D[a][b];
+            S32[o] = (float)D[a][b];
+            Dw64[o] = omega * Di[a][b];
+            Dw32[o] = (float)(omega * Di[a][b]);
+        }
+    for (int j = 0; j < 4; ++j)
+        for (int a = 0; a < m; ++a)
+            for (int b = 0; b < m; ++b) {
+                double t = 0.0;
+                for (int c = 0; c < m; ++c) t += Di[a][c] * Off[j][c][b];
+                const size_t os = (size_t)(((j + 1) * m + a) * m + b) * NE + e;
+                const size_t ot = (size_t)((j * m + a) * m + b) * NE + e;
+                S64[os] = Off[j][a][b];
+                S32[os] = (float)Off[j][a][b];
+                T64[ot] = omega * t;
+                T16[ot] = __float2bfloat16((float)(omega * t));
+            }
+}
+
+// ------------------------------------------------------------------ trace-level operators
+//
+// Pull formulation: each (facet, RHS) thread gathers the trace values of the
+// five facets of its block row and produces all m rows, so every matrix
+// entry is read exactly once per apply and there are no write conflicts.
+
+template <int M, typename MT>
+__global__ __launch_bounds__(256) void k_trace_apply(int ne, int nb, const MT *__restrict__ S,
+                                                     const int *__restrict__ nbr, const double *__restrict__ x,
+                                                     const double *__restrict__ b, double *__restrict__ y) {
+    using AT = typename Acc<MT>::type;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ne * nb) return;
+    const int e = t / nb, r = t - e * nb;
+    const size_t NE = (size_t)ne;
+    int id[5];
+    id[0] = e;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) id[j + 1] = nbr[j * NE + e];
+    AT xv[5][M];
+#pragma unroll
+    for (int j = 0; j < 5; ++j)
+#pragma unroll
+        for (int k = 0; k < M; ++k) xv[j][k] = (AT)x[((size_t)id[j] * M + k) * nb + r];
+#pragma unroll
+    for (int a = 0; a < M; ++a) {
+        AT acc = 0;
+#pragma unroll
+        for (int j = 0; j < 5; ++j)
+#pragma unroll
+            for (int k = 0; k < M; ++k) acc += (AT)ldm(S + (size_t)((j * M + a) * M + k) * NE + e) * xv[j][k];
+        const size_t o = ((size_t)e * M + a) * nb + r;
+        y[o] = b ? b[o] - (double)acc : (double)acc;   // b != nullptr: residual b - S x
+    }
+}
+
+// z0 = omega D^-1 r  (first sweep from a zero guess)
+template <int M, typename MT>
+__global__ __launch_bounds__(256) void k_jacobi0(int ne, int nb, const MT *__restrict__ Dw,
+                                                 const double *__restrict__ r, double *__restrict__ z0) {
+    using AT = typename Acc<MT>::type;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ne * nb) return;
+    const int e = t / nb, rr = t - e * nb;
+    const size_t NE = (size_t)ne;
+    AT rv[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) rv[k] = (AT)r[((size_t)e * M + k) * nb + rr];
+#pragma unroll
+    for (int a = 0; a < M; ++a) {
+        AT acc = 0;
+#pragma unroll
+        for (int k = 0; k < M; ++k) acc += (AT)ldm(Dw + (size_t)(a * M + k) * NE + e) * rv[k];
+        z0[((size_t)e * M + a) * nb + rr] = (double)acc;
+    }
+}
+
+// Block-Jacobi sweep  y = x + omega D^-1 (r - S x) = (1 - omega) x + z0 - sum_j T_j x_j,
+// with T_j = omega D^-1 S_j over the four off-diagonal slots and z0 = omega D^-1 r.
+// With qc != nullptr the input is x + pi qc (prolongation of the P1 correction
+// fused in, pi the injection of a P1 function onto the trace nodes).
+template <int M, typename MT>
+__global__ __launch_bounds__(256) void k_sweep(int ne, int nb, const MT *__restrict__ T,
+                                               const int *__restrict__ nbr, const double *__restrict__ x,
+                                               const double *__restrict__ z0, const double *__restrict__ qc,
+                                               const int *__restrict__ fvert, double omega,
+                                               double *__restrict__ y) {
+    using AT = typename Acc<MT>::type;
+    constexpr int P = M - 1;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ne * nb) return;
+    const int e = t / nb, r = t - e * nb;
+    const size_t NE = (size_t)ne;
+    int id[5];
+    id[0] = e;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) id[j + 1] = nbr[j * NE + e];
+    double xv[5][M];
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+#pragma unroll
+        for (int k = 0; k < M; ++k) xv[j][k] = x[((size_t)id[j] * M + k) * nb + r];
+        if (qc) {
+            const double q0 = qc[(size_t)fvert[2 * id[j]] * nb + r];
+            const double q1 = qc[(size_t)fvert[2 * id[j] + 1] * nb + r];
+#pragma unroll
+            for (int k = 0; k < M; ++k) xv[j][k] += (1.0 - (double)k / P) * q0 + ((double)k / P) * q1;
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < M; ++a) {
+        AT acc = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int k = 0; k < M; ++k)
+                acc += (AT)ldm(T + (size_t)((j * M + a) * M + k) * NE + e) * (AT)xv[j + 1][k];
+        const size_t o = ((size_t)e * M + a) * nb + r;
+        y[o] = (1.0 - omega) * xv[0][a] + z0[o] - (double)acc;
+    }
+}
+
+// Restriction pi^T of a trace residual onto the P1 vertices:
+// rc[v] = sum over facet ends at v of sum_k w_end(k) res[e][k], w_0 = 1 - k/p, w_1 = k/p.
+template <int M>
+__global__ void k_restrict_trace(int nv, int nb, const int *__restrict__ vf_row, const int *__restrict__ vf_col,
+                                 const double *__restrict__ res, double *__restrict__ rc) {
+    constexpr int P = M - 1;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nv * nb) return;
+    const int v = t / nb, r = t - v * nb;
+    double acc = 0.0;
+    for (int c = vf_row[v]; c < vf_row[v + 1]; ++c) {
+        const int code = vf_col[c], e = code >> 1, end = code & 1;
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            const double w = end ? (double)k / P : 1.0 - (double)k / P;
+            acc += w * res[((size_t)e * M + k) * nb + r];
+        }
+    }
+    rc[(size_t)v * nb + r] = acc;
+}
+
+// ------------------------------------------------------------------ P1 levels
+
+__device__ __forceinline__ double p1_row(int v, int nb, int r, const int *rowptr, const int *col,
+                                         const double *val, const double *x) {
+    double s = 0.0;
+    for (int c = rowptr[v]; c < rowptr[v + 1]; ++c) s += val[c] * x[(size_t)col[c] * nb + r];
+    return s;
+}
+
+__global__ void k_p1_first(int n, int nb, const double *__restrict__ dinv, double omega,
+                           const double *__restrict__ b, double *__restrict__ x) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * nb) return;
+    x[t] = omega * dinv[t / nb] * b[t];
+}
+
+// y = x + omega D^-1 (b - A x); with xc != nullptr the input is x + P xc (prolongation fused)
+__global__ void k_p1_sweep(int n, int nb, const int *__restrict__ rowptr, const int *__restrict__ col,
+                           const double *__restrict__ val, const double *__restrict__ diag,
+                           const double *__restrict__ dinv, double omega, const double *__restrict__ b,
+                           const double *__restrict__ x, const double *__restrict__ xc,
+                           const int *__restrict__ parents, double *__restrict__ y) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * nb) return;
+    const int v = t / nb, r = t - v * nb;
+    auto xin = [&](int u) -> double {
+        double s = x[(size_t)u * nb + r];
+        if (xc) s += 0.5 * (xc[(size_t)parents[2 * u] * nb + r] + xc[(size_t)parents[2 * u + 1] * nb + r]);
+        return s;
+    };
+    double ax = 0.0;
+    for (int c = rowptr[v]; c < rowptr[v + 1]; ++c) ax += val[c] * xin(col[c]);
+    const double xv = xin(v);
+    ax += diag[v] * xv;
+    y[t] = xv + omega * dinv[v] * (b[t] - ax);
+}
+
+// bc[c] = sum_children w * (b - A x)[child]  (residual and restriction fused)
+__global__ void k_p1_resid_restrict(int nc, int nb, const int *__restrict__ crow, const int *__restrict__ ccol,
+                                    const double *__restrict__ cw, const int *__restrict__ rowptr,
+                                    const int *__restrict__ col, const double *__restrict__ val,
+                                    const double *__restrict__ diag, const double *__restrict__ b,
+                                    const double *__restrict__ x, double *__restrict__ bc) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nc * nb) return;
+    const int c = t / nb, r = t - c * nb;
+    double acc = 0.0;
+    for (int k = crow[c]; k < crow[c + 1]; ++k) {
+        const int v = ccol[k];
+        const double res = b[(size_t)v * nb + r] - diag[v] * x[(size_t)v * nb + r] - p1_row(v, nb, r, rowptr, col, val, x);
+        acc += cw[k] * res;
+    }
+    bc[t] = acc;
+}
+
+// x = Ainv b on the coarsest level (dense)
+__global__ void k_dense_mv(int n, int nb, const double *__restrict__ Ainv, const double *__restrict__ b,
+                           double *__restrict__ x) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * nb) return;
+    const int i = t / nb, r = t - i * nb;
+    double s = 0.0;
+    for (int j = 0; j < n; ++j) s += Ainv[(size_t)i * n + j] * b[(size_t)j * nb + r];
+    x[t] = s;
+}
+
+// ------------------------------------------------------------------ condensation / recovery (per solve)
+
+// loc[rho][K][r] = sum_j Zr[rho][j][K] r_cell[K][j][r]   (Step 1, cell part)
+template <int P>
+__global__ __launch_bounds__(256) void k_condense_cell(int nk, int nb, const double *__restrict__ Zr,
+                                                       const double *__restrict__ rc, double *__restrict__ loc) {
+    constexpr int n = (P + 1) * (P + 2) / 2, m = P + 1, nc = 3 * n, nt = 3 * m;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nk * nb) return;
+    const int K = t / nb, r = t - K * nb;
+    const size_t NK = (size_t)nk;
+    double f[nc];
+#pragma unroll
+    for (int j = 0; j < nc; ++j) f[j] = rc[((size_t)K * nc + j) * nb + r];
+#pragma unroll
+    for (int a = 0; a < nt; ++a) {
+        double s = 0.0;
+#pragma unroll
+        for (int j = 0; j < nc; ++j) s += ldm(Zr + (size_t)(a * nc + j) * NK + K) * f[j];
+        loc[((size_t)a * NK + K) * nb + r] = s;
+    }
+}
+
+// rhat[e][a][r] = sum of the two cells' local contributions (orientation mapped)
+template <int P>
+__global__ void k_condense_gather(int ne, int nk, int nb, const int *__restrict__ facet_cell,
+                                  const int *__restrict__ facet_loc, const double *__restrict__ loc,
+                                  double *__restrict__ rhat) {
+    constexpr int m = P + 1;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ne * m * nb) return;
+    const int r = t % nb, ea = t / nb, e = ea / m, a = ea - e * m;
+    const size_t NK = (size_t)nk;
+    const int K0 = facet_cell[2 * e], i0 = facet_loc[2 * e];
+    const int K1 = facet_cell[2 * e + 1], i1 = facet_loc[2 * e + 1];
+    const double v0 = loc[((size_t)(i0 * m + a) * NK + K0) * nb + r];
+    const double v1 = loc[((size_t)(i1 * m + P - a) * NK + K1) * nb + r];
+    rhat[t] = v0 + v1;
+}
+
+// q = Ar r_cell - Wr lam_K  (Step 3)
+template <int P>
+__global__ __launch_bounds__(256) void k_recover(int nk, int nb, const double *__restrict__ Ar,
+                                                 const double *__restrict__ Wr, const int *__restrict__ cell_facet,
+                                                 const int8_t *__restrict__ cell_rev, const double *__restrict__ rc,
+                                                 const double *__restrict__ lam, double *__restrict__ q) {
+    constexpr int n = (P + 1) * (P + 2) / 2, m = P + 1, nc = 3 * n, nt = 3 * m;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nk * nb) return;
+    const int K = t / nb, r = t - K * nb;
+    const size_t NK = (size_t)nk;
+    double f[nc], l[nt];
+#pragma unroll
+    for (int j = 0; j < nc; ++j) f[j] = rc[((size_t)K * nc + j) * nb + r];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const int e = cell_facet[i * NK + K];
+        const int rev = cell_rev[i * NK + K];
+#pragma unroll
+        for (int k = 0; k < m; ++k) l[i * m + k] = lam[((size_t)e * m + (rev ? P - k : k)) * nb + r];
+    }
+#pragma unroll 1
+    for (int a = 0; a < nc; ++a) {
+        double s = 0.0;
+#pragma unroll
+        for (int j = 0; j < nc; ++j) s += ldm(Ar + (size_t)(a * nc + j) * NK + K) * f[j];
+#pragma unroll
+        for (int j = 0; j < nt; ++j) s -= ldm(Wr + (size_t)(a * nt + j) * NK + K) * l[j];
+        q[((size_t)K * nc + a) * nb + r] = s;
+    }
+}
+
+// ------------------------------------------------------------------ Krylov vector kernels
+//
+// Vectors are [len][nb]; per-RHS reductions run in two deterministic passes
+// (block partials, then one block per RHS), so repeated solves are bitwise
+// identical.
+
+__device__ __forceinline__ int rows_per_block(int nb) {
+    int r = 1;
+    while (r * 2 * nb <= 256) r *= 2;
+    return r;
+}
+
+// partial[blk][d][r] = sum over this block's rows of x_d[i][r] * y[i][r], for nd vectors x_d
+__global__ __launch_bounds__(256) void k_dots_partial(int64_t len, int nb, int nd, const double *__restrict__ X,
+                                                      int64_t xstride, const double *__restrict__ y,
+                                                      double *__restrict__ partial) {
+    __shared__ double sh[256];
+    const int rpb = rows_per_block(nb);
+    const int tid = threadIdx.x;
+    const int rl = tid / nb, r = tid - rl * nb;
+    const bool active = rl < rpb;
+    for (int d = 0; d < nd; ++d) {
+        double acc = 0.0;
+        if (active) {
+            const double *x = X + (size_t)d * xstride;
+            for (int64_t i = (int64_t)blockIdx.x * rpb + rl; i < len; i += (int64_t)gridDim.x * rpb)
+                acc += x[i * nb + r] * y[i * nb + r];
+        }
+        sh[tid] = acc;
+        __syncthreads();
+        for (int s = rpb / 2; s > 0; s >>= 1) {
+            if (active && rl < s) sh[tid] += sh[tid + s * nb];
+            __syncthreads();
+        }
+        if (tid < nb) partial[((size_t)blockIdx.x * nd + d) * nb + tid] = sh[tid];
+        __syncthreads();
+    }
+}
+
+// out[d][r] = sum over blocks of partial[blk][d][r]; grid = (nd, nb)
+__global__ __launch_bounds__(256) void k_dots_final(int nblk, int nb, int nd, const double *__restrict__ partial,
+                                                    double *__restrict__ out) {
+    __shared__ double sh[256];
+    const int d = blockIdx.x, r = blockIdx.y;
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += 256) acc += partial[((size_t)b * nd + d) * nb + r];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[(size_t)d * nb + r] = sh[0];
+}
+
+// y[i][r] = a[r] * x[i][r] + b[r] * y[i][r] with per-RHS device scalars (null = 0 / 1 given)
+__global__ void k_axpby(int64_t n, int nb, const double *__restrict__ a, double as, const double *__restrict__ x,
+                        const double *__restrict__ b, double bs, double *__restrict__ y) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * nb) return;
+    const int r = (int)(t % nb);
+    const double av = a ? as * a[r] : as, bv = b ? bs * b[r] : bs;
+    y[t] = av * x[t] + (bv == 0.0 ? 0.0 : bv * y[t]);
+}
+
+// PCG update: x += alpha p, r -= alpha w, alpha[r] = num[r] / den[r] (zero when den is zero)
+__global__ void k_pcg_update(int64_t n, int nb, const double *__restrict__ num, const double *__restrict__ den,
+                             const double *__restrict__ p, const double *__restrict__ w, double *__restrict__ x,
+                             double *__restrict__ res) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * nb) return;
+    const int r = (int)(t % nb);
+    const double d = den[r];
+    const double al = d != 0.0 ? num[r] / d : 0.0;
+    x[t] += al * p[t];
+    res[t] -= al * w[t];
+}
+
+// p = z + beta p, beta[r] = num[r] / den[r]
+__global__ void k_pcg_dir(int64_t n, int nb, const double *__restrict__ num, const double *__restrict__ den,
+                          const double *__restrict__ z, double *__restrict__ p) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * nb) return;
+    const int r = (int)(t % nb);
+    const double d = den[r];
+    const double be = d != 0.0 ? num[r] / d : 0.0;
+    p[t] = z[t] + be * p[t];
+}
+
+// w -= sum_{d < nd} h[d][r] V_d   (classical Gram-Schmidt update)
+__global__ void k_gs_update(int64_t n, int nb, int nd, const double *__restrict__ h, const double *__restrict__ V,
+                            int64_t vstride, double *__restrict__ w) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * nb) return;
+    const int r = (int)(t % nb);
+    double s = w[t];
+    for (int d = 0; d < nd; ++d) s -= h[(size_t)d * nb + r] * V[(size_t)d * vstride + t];
+    w[t] = s;
+}
+
+// x += sum_{d < nd} y[d][r] Z_d
+__global__ void k_lincomb(int64_t n, int nb, int nd, const double *__restrict__ y, const double *__restrict__ Z,
+                          int64_t zstride, double *__restrict__ x) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * nb) return;
+    const int r = (int)(t % nb);
+    double s = x[t];
+    for (int d = 0; d < nd; ++d) s += y[(size_t)d * nb + r] * Z[(size_t)d * zstride + t];
+    x[t] = s;
+}
+
+// y = x / s[r]  (s > 0), writes 0 for s == 0
+__global__ void k_scale_inv(int64_t n, int nb, const double *__restrict__ s, const double *__restrict__ x,
+                            double *__restrict__ y) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * nb) return;
+    const double v = s[t % nb];
+    y[t] = v != 0.0 ? x[t] / v : 0.0;
+}
+
+__global__ void k_copy(int64_t n, const double *__restrict__ src, double *__restrict__ dst) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) dst[t] = src[t];
+}
+
+// ------------------------------------------------------------------ FGMRES small dense work (one thread per RHS)
+//
+// State per RHS in gm: H[(restart+1)][restart], cs[restart], sn[restart], g[restart+1],
+// beta, status.  Column j of H arrives in hcol (dots with V_0..V_j) and hnorm
+// (||w|| after orthogonalisation).  Applies the stored Givens rotations, forms
+// the new one and returns |g[j+1]| / bnorm in resid[r].
+__global__ void k_gmres_givens(int nb, int j, int restart, const double *__restrict__ hcol,
+                               const double *__restrict__ hnorm, double *__restrict__ gm,
+                               const double *__restrict__ bnorm, double *__restrict__ resid) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nb) return;
+    const int stride = (restart + 1) * restart + 2 * restart + (restart + 1);
+    double *H = gm + (size_t)r * stride;
+    double *cs = H + (restart + 1) * restart;
+    double *sn = cs + restart;
+    double *g = sn + restart;
+    double col[65];
+    for (int i = 0; i <= j; ++i) col[i] = hcol[(size_t)i * nb + r];
+    col[j + 1] = hnorm[r];
+    for (int i = 0; i < j; ++i) {
+        const double a = col[i], b = col[i + 1];
+        col[i] = cs[i] * a + sn[i] * b;
+        col[i + 1] = -sn[i] * a + cs[i] * b;
+    }
+    const double a = col[j], b = col[j + 1];
+    const double d = sqrt(a * a + b * b);
+    const double c = d > 0.0 ? a / d : 1.0, s = d > 0.0 ? b / d : 0.0;
+    cs[j] = c;
+    sn[j] = s;
+    col[j] = d;
+    col[j + 1] = 0.0;
+    for (int i = 0; i <= j; ++i) H[(size_t)i * restart + j] = col[i];
+    const double gj = g[j];
+    g[j] = c * gj;
+    g[j + 1] = -s * gj;
+    const double bn = bnorm[r];
+    resid[r] = bn > 0.0 ? fabs(g[j + 1]) / bn : 0.0;
+}
+
+// start of a cycle: g = (beta, 0, ...), beta = ||r0||
+__global__ void k_gmres_start(int nb, int restart, const double *__restrict__ beta2, double *__restrict__ gm,
+                              double *__restrict__ beta) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nb) return;
+    const int stride = (restart + 1) * restart + 2 * restart + (restart + 1);
+    double *g = gm + (size_t)r * stride + (restart + 1) * restart + 2 * restart;
+    const double b = sqrt(fmax(beta2[r], 0.0));
+    for (int i = 0; i <= restart; ++i) g[i] = 0.0;
+    g[0] = b;
+    beta[r] = b;
+}
+
+// y = H(0:k,0:k)^-1 g(0:k) by back substitution, written as y[i][r]
+__global__ void k_gmres_solve(int nb, int k, int restart, const double *__restrict__ gm, double *__restrict__ y) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nb) return;
+    const int stride = (restart + 1) * restart + 2 * restart + (restart + 1);
+    const double *H = gm + (size_t)r * stride;
+    const double *g = H + (restart + 1) * restart + 2 * restart;
+    double yy[64];
+    for (int i = k - 1; i >= 0; --i) {
+        double s = g[i];
+        for (int l = i + 1; l < k; ++l) s -= H[(size_t)i * restart + l] * yy[l];
+        const double d = H[(size_t)i * restart + i];
+        yy[i] = d != 0.0 ? s / d : 0.0;
+    }
+    for (int i = 0; i < k; ++i) y[(size_t)i * nb + r] = yy[i];
+}
+
+__global__ void k_sqrt(int nb, const double *__restrict__ in, double *__restrict__ out) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < nb) out[r] = sqrt(fmax(in[r], 0.0));
+}
+
+// ------------------------------------------------------------------ explicit instantiations via launchers
+
+#define GRID(n, b) dim3((unsigned)(((n) + (b) - 1) / (b))), dim3(b)
+
+void launch_cell_condense(int p, int nk, const double *corners, const double *ref, CellParams cp, double *Sloc,
+                          double *Zr, double *Ar, double *Wr, int *err, hipStream_t s) {
+    switch (p) {
+    case 1: hipLaunchKernelGGL(k_cell_condense<1>, dim3(nk), dim3(64), 0, s, nk, corners, ref, cp, Sloc, Zr, Ar, Wr, err); break;
+    case 2: hipLaunchKernelGGL(k_cell_condense<2>, dim3(nk), dim3(64), 0, s, nk, corners, ref, cp, Sloc, Zr, Ar, Wr, err); break;
+    case 3: hipLaunchKernelGGL(k_cell_condense<3>, dim3(nk), dim3(64), 0, s, nk, corners, ref, cp, Sloc, Zr, Ar, Wr, err); break;
+    }
+}
+
+void launch_facet_rows(int p, int ne, int nk, const double *Sloc, const int *facet_cell, const int *facet_loc,
+                       const int *cell_facet, const int8_t *cell_rev, double omega, double *S64, double *T64,
+                       double *Dw64, float *S32, __hip_bfloat16 *T16, float *Dw32, int *nbr, int *err,
+                       hipStream_t s) {
+#define FR(P) hipLaunchKernelGGL(k_facet_rows<P>, GRID(ne, 128), 0, s, ne, nk, Sloc, facet_cell, facet_loc, cell_facet, cell_rev, omega, S64, T64, Dw64, S32, T16, Dw32, nbr, err)
+    switch (p) { case 1: FR(1); break; case 2: FR(2); break; case 3: FR(3); break; }
+#undef FR
+}
+
+template <typename MT>
+void launch_trace_apply(int p, int ne, int nb, const MT *S, const int *nbr, const double *x, const double *b,
+                        double *y, hipStream_t s) {
+#define TA(P) hipLaunchKernelGGL((k_trace_apply<P + 1, MT>), GRID(ne * nb, 256), 0, s, ne, nb, S, nbr, x, b, y)
+    switch (p) { case 1: TA(1); break; case 2: TA(2); break; case 3: TA(3); break; }
+#undef TA
+}
+template void launch_trace_apply<double>(int, int, int, const double *, const int *, const double *, const double *, double *, hipStream_t);
+template void launch_trace_apply<float>(int, int, int, const float *, const int *, const double *, const double *, double *, hipStream_t);
+
+template <typename MT>
+void launch_jacobi0(int p, int ne, int nb, const MT *Dw, const double *r, double *z0, hipStream_t s) {
+#define J0(P) hipLaunchKernelGGL((k_jacobi0<P + 1, MT>), GRID(ne * nb, 256), 0, s, ne, nb, Dw, r, z0)
+    switch (p) { case 1: J0(1); break; case 2: J0(2); break; case 3: J0(3); break; }
+#undef J0
+}
+template void launch_jacobi0<double>(int, int, int, const double *, const double *, double *, hipStream_t);
+template void launch_jacobi0<float>(int, int, int, const float *, const double *, double *, hipStream_t);
+
+template <typename MT>
+void launch_sweep(int p, int ne, int nb, const MT *T, const int *nbr, const double *x, const double *z0,
+                  const double *qc, const int *fvert, double omega, double *y, hipStream_t s) {
+#define SW(P) hipLaunchKernelGGL((k_sweep<P + 1, MT>), GRID(ne * nb, 256), 0, s, ne, nb, T, nbr, x, z0, qc, fvert, omega, y)
+    switch (p) { case 1: SW(1); break; case 2: SW(2); break; case 3: SW(3); break; }
+#undef SW
+}
+template void launch_sweep<double>(int, int, int, const double *, const int *, const double *, const double *, const double *, const int *, double, double *, hipStream_t);
+template void launch_sweep<__hip_bfloat16>(int, int, int, const __hip_bfloat16 *, const int *, const double *, const double *, const double *, const int *, double, double *, hipStream_t);
+
+void launch_restrict_trace(int p, int nv, int nb, const int *vf_row, const int *vf_col, const double *res,
+                           double *rc, hipStream_t s) {
+#define RT(P) hipLaunchKernelGGL(k_restrict_trace<P + 1>, GRID(nv * nb, 256), 0, s, nv, nb, vf_row, vf_col, res, rc)
+    switch (p) { case 1: RT(1); break; case 2: RT(2); break; case 3: RT(3); break; }
+#undef RT
+}
+
+void launch_p1_first(int n, int nb, const double *dinv, double omega, const double *b, double *x, hipStream_t s) {
+    hipLaunchKernelGGL(k_p1_first, GRID(n * nb, 256), 0, s, n, nb, dinv, omega, b, x);
+}
+void launch_p1_sweep(int n, int nb, const int *rowptr, const int *col, const double *val, const double *diag,
+                     const double *dinv, double omega, const double *b, const double *x, const double *xc,
+                     const int *parents, double *y, hipStream_t s) {
+    hipLaunchKernelGGL(k_p1_sweep, GRID(n * nb, 256), 0, s, n, nb, rowptr, col, val, diag, dinv, omega, b, x, xc,
+                       parents, y);
+}
+void launch_p1_resid_restrict(int nc, int nb, const int *crow, const int *ccol, const double *cw,
+                              const int *rowptr, const int *col, const double *val, const double *diag,
+                              const double *b, const double *x, double *bc, hipStream_t s) {
+    hipLaunchKernelGGL(k_p1_resid_restrict, GRID(nc * nb, 256), 0, s, nc, nb, crow, ccol, cw, rowptr, col, val,
+                       diag, b, x, bc);
+}
+void launch_dense_mv(int n, int nb, const double *Ainv, const double *b, double *x, hipStream_t s) {
+    hipLaunchKernelGGL(k_dense_mv, GRID(n * nb, 64), 0, s, n, nb, Ainv, b, x);
+}
+
+void launch_condense(int p, int nk, int ne, int nb, const double *Zr, const double *rc, double *loc,
+                     const int *facet_cell, const int *facet_loc, double *rhat, hipStream_t s) {
+#define CC(P)                                                                                                     \
+    hipLaunchKernelGGL(k_condense_cell<P>, GRID(nk * nb, 256), 0, s, nk, nb, Zr, rc, loc);                        \
+    hipLaunchKernelGGL(k_condense_gather<P>, GRID(ne * (P + 1) * nb, 256), 0, s, ne, nk, nb, facet_cell,         \
+                       facet_loc, loc, rhat)
+    switch (p) { case 1: CC(1); break; case 2: CC(2); break; case 3: CC(3); break; }
+#undef CC
+}
+
+void launch_recover(int p, int nk, int nb, const double *Ar, const double *Wr, const int *cell_facet,
+                    const int8_t *cell_rev, const double *rc, const double *lam, double *q, hipStream_t s) {
+#define RC(P) hipLaunchKernelGGL(k_recover<P>, GRID(nk * nb, 256), 0, s, nk, nb, Ar, Wr, cell_facet, cell_rev, rc, lam, q)
+    switch (p) { case 1: RC(1); break; case 2: RC(2); break; case 3: RC(3); break; }
+#undef RC
+}
+
+void launch_dots(int64_t len, int nb, int nd, const double *X, int64_t xstride, const double *y, double *partial,
+                 int nblk, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_dots_partial, dim3(nblk), dim3(256), 0, s, len, nb, nd, X, xstride, y, partial);
+    hipLaunchKernelGGL(k_dots_final, dim3(nd, nb), dim3(256), 0, s, nblk, nb, nd, partial, out);
+}
+
+void launch_axpby(int64_t n, int nb, const double *a, double as, const double *x, const double *b, double bs,
+                  double *y, hipStream_t s) {
+    hipLaunchKernelGGL(k_axpby, GRID(n * nb, 256), 0, s, n, nb, a, as, x, b, bs, y);
+}
+void launch_pcg_update(int64_t n, int nb, const double *num, const double *den, const double *p, const double *w,
+                       double *x, double *res, hipStream_t s) {
+    hipLaunchKernelGGL(k_pcg_update, GRID(n * nb, 256), 0, s, n, nb, num, den, p, w, x, res);
+}
+void launch_pcg_dir(int64_t n, int nb, const double *num, const double *den, const double *z, double *p,
+                    hipStream_t s) {
+    hipLaunchKernelGGL(k_pcg_dir, GRID(n * nb, 256), 0, s, n, nb, num, den, z, p);
+}
+void launch_gs_update(int64_t n, int nb, int nd, const double *h, const double *V, int64_t vstride, double *w,
+                      hipStream_t s) {
+    hipLaunchKernelGGL(k_gs_update, GRID(n * nb, 256), 0, s, n, nb, nd, h, V, vstride, w);
+}
+void launch_lincomb(int64_t n, int nb, int nd, const double *y, const double *Z, int64_t zstride, double *x,
+                    hipStream_t s) {
+    hipLaunchKernelGGL(k_lincomb, GRID(n * nb, 256), 0, s, n, nb, nd, y, Z, zstride, x);
+}
+void launch_scale_inv(int64_t n, int nb, const double *sc, const double *x, double *y, hipStream_t s) {
+    hipLaunchKernelGGL(k_scale_inv, GRID(n * nb, 256), 0, s, n, nb, sc, x, y);
+}
+void launch_copy(int64_t n, const double *src, double *dst, hipStream_t s) {
+    hipLaunchKernelGGL(k_copy, GRID(n, 256), 0, s, n, src, dst);
+}
+void launch_gmres_start(int nb, int restart, const double *beta2, double *gm, double *beta, hipStream_t s) {
+    hipLaunchKernelGGL(k_gmres_start, GRID(nb, 64), 0, s, nb, restart, beta2, gm, beta);
+}
+void launch_gmres_givens(int nb, int j, int restart, const double *hcol, const double *hnorm, double *gm,
+                         const double *bnorm, double *resid, hipStream_t s) {
+    hipLaunchKernelGGL(k_gmres_givens, GRID(nb, 64), 0, s, nb, j, restart, hcol, hnorm, gm, bnorm, resid);
+}
+void launch_gmres_solve(int nb, int k, int restart, const double *gm, double *y, hipStream_t s) {
+    hipLaunchKernelGGL(k_gmres_solve, GRID(nb, 64), 0, s, nb, k, restart, gm, y);
+}
+void launch_sqrt(int nb, const double *in, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_sqrt, GRID(nb, 64), 0, s, nb, in, out);
+}
+
+}  // namespace hdg

@@ -1,0 +1,273 @@
+"""ctypes binding of libhdg.so (the C ABI in include/hdg.h).
+
+Argument marshalling only: every numerical step runs in the library's HIP
+kernels.  Device buffers are torch CUDA (HIP) tensors; streams are torch's
+current stream.  Importing this module loads the library and fails loudly
+when it has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhdg.so")
+
+HDG_OK, HDG_EINVAL, HDG_ENOMEM, HDG_EHIP, HDG_EBREAKDOWN, HDG_ENOTCONV = 0, -1, -2, -3, -4, 1
+HDG_TORUS, HDG_SPHERE = 0, 1
+HDG_FP64, HDG_MIXED = 0, 1
+HDG_KRYLOV_AUTO, HDG_KRYLOV_PCG, HDG_KRYLOV_FGMRES = 0, 1, 2
+HDG_SMOOTH_BJACOBI, HDG_SMOOTH_MLP = 0, 1
+KERNELS = {"apply": 0, "sweep": 1, "residual": 2, "condense": 3, "recover": 4}
+
+
+class HdgMesh(ctypes.Structure):
+    _fields_ = [("geom", ctypes.c_int32), ("n_vert", ctypes.c_int32), ("n_cell", ctypes.c_int32),
+                ("period", ctypes.c_double), ("vert_xyz", ctypes.c_void_p),
+                ("cell_vert", ctypes.c_void_p), ("cell_shift", ctypes.c_void_p)]
+
+
+class HdgParams(ctypes.Structure):
+    _fields_ = [("degree", ctypes.c_int32), ("dt", ctypes.c_double), ("g", ctypes.c_double),
+                ("H", ctypes.c_double), ("f0", ctypes.c_double), ("omega", ctypes.c_double),
+                ("tau", ctypes.c_double)]
+
+
+class HdgOptions(ctypes.Structure):
+    _fields_ = [("krylov", ctypes.c_int32), ("precision", ctypes.c_int32), ("smoother", ctypes.c_int32),
+                ("nu_pre", ctypes.c_int32), ("nu_post", ctypes.c_int32), ("omega", ctypes.c_double),
+                ("p1_nu", ctypes.c_int32), ("p1_omega", ctypes.c_double), ("rtol", ctypes.c_double),
+                ("maxit", ctypes.c_int32), ("restart", ctypes.c_int32), ("max_rhs", ctypes.c_int32),
+                ("use_graph", ctypes.c_int32), ("fallback_ratio", ctypes.c_double)]
+
+
+class HdgSolveInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("refinements", ctypes.c_int32), ("fallbacks", ctypes.c_int32),
+                ("status", ctypes.c_int32), ("rel_res", ctypes.c_double)]
+
+
+class HdgSizes(ctypes.Structure):
+    _fields_ = [("n_cell", ctypes.c_int32), ("n_facet", ctypes.c_int32), ("n_vert", ctypes.c_int32),
+                ("degree", ctypes.c_int32), ("n_loc", ctypes.c_int32), ("n_levels", ctypes.c_int32),
+                ("device_bytes", ctypes.c_int64), ("kappa", ctypes.c_double)]
+
+
+_P = ctypes.c_void_p
+_I = ctypes.c_int32
+_SIGS = {
+    "hdg_default_options": (_I, [ctypes.POINTER(HdgOptions)]),
+    "hdg_setup": (_I, [ctypes.POINTER(HdgMesh), _I, ctypes.POINTER(ctypes.c_void_p),
+                       ctypes.POINTER(HdgParams), ctypes.POINTER(HdgOptions), ctypes.POINTER(_P)]),
+    "hdg_get_sizes": (_I, [_P, ctypes.POINTER(HdgSizes)]),
+    "hdg_get_topology": (_I, [_P, _P, _P, _P]),
+    "hdg_condense": (_I, [_P, _I, _P, _P, _P]),
+    "hdg_trace_apply": (_I, [_P, _I, _I, _P, _P, _P]),
+    "hdg_mg_vcycle": (_I, [_P, _I, _I, _P, _P, _P]),
+    "hdg_solve": (_I, [_P, _I, _P, _P, ctypes.POINTER(HdgSolveInfo), _P]),
+    "hdg_recover": (_I, [_P, _I, _P, _P, _P, _P]),
+    "hdg_destroy": (None, [_P]),
+    "hdg_last_error": (ctypes.c_char_p, []),
+    "hdg_set_timing": (_I, [_P, _I]),
+    "hdg_kernel_stats": (_I, [_P, _I, _I, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
+                              ctypes.POINTER(ctypes.c_double)]),
+    "hdg_copy": (_I, [_P, _P, ctypes.c_int64, _P]),
+}
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libhdg.so; raises if it is missing (there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP library not built: {path} is missing "
+                           "(run python -m paper_2004_09389_amd.build)")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+class HdgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"hdg error {code}: {msg}")
+        self.code = code
+
+
+def _check(rc, allow=(HDG_OK,)):
+    if rc not in allow:
+        raise HdgError(rc, load_library().hdg_last_error().decode())
+    return rc
+
+
+def default_options() -> HdgOptions:
+    o = HdgOptions()
+    _check(load_library().hdg_default_options(ctypes.byref(o)))
+    return o
+
+
+def _ptr(t) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+@dataclass
+class SolveInfo:
+    iters: int
+    refinements: int
+    fallbacks: int
+    status: int
+    rel_res: float
+
+
+class HdgSolver:
+    """One HDG context on the current GPU (see include/hdg.h for the method).
+
+    hierarchy: hdg_inputs.Hierarchy (coarse -> fine; the finest mesh is the
+    HDG mesh).  Device arrays are torch float64 tensors on cuda with the
+    layouts of the C ABI: cell arrays (n_cell, 3, n_loc, nrhs), trace arrays
+    (n_facet, p+1, nrhs).
+    """
+
+    def __init__(self, hierarchy, degree: int, dt: float, g: float = 1.0, H: float = 1.0,
+                 f0: float = 0.0, omega: float = 0.0, tau: float = 1.0, **options):
+        import torch  # noqa: F401  (initialises the HIP runtime through torch)
+        self.lib = load_library()
+        self.hier = hierarchy
+        opt = default_options()
+        for k, v in options.items():
+            if not hasattr(opt, k):
+                raise ValueError(f"unknown option {k}")
+            setattr(opt, k, v)
+        self.options = opt
+        keep = []
+        meshes = (HdgMesh * len(hierarchy.meshes))()
+        for i, m in enumerate(hierarchy.meshes):
+            vx = np.ascontiguousarray(m.vert_xyz, dtype=np.float64)
+            cv = np.ascontiguousarray(m.cell_vert, dtype=np.int32)
+            cs = np.ascontiguousarray(m.cell_shift, dtype=np.int32)
+            keep += [vx, cv, cs]
+            meshes[i] = HdgMesh(HDG_TORUS if m.kind == "torus" else HDG_SPHERE, m.n_vert, m.n_cell,
+                                float(m.period), vx.ctypes.data, cv.ctypes.data, cs.ctypes.data)
+        parents = (ctypes.c_void_p * len(hierarchy.meshes))()
+        parents[0] = None
+        for l, par in enumerate(hierarchy.parents):
+            a = np.ascontiguousarray(par, dtype=np.int32)
+            keep.append(a)
+            parents[l + 1] = a.ctypes.data
+        prm = HdgParams(degree, dt, g, H, f0, omega, tau)
+        ctx = ctypes.c_void_p()
+        _check(self.lib.hdg_setup(meshes, len(hierarchy.meshes), parents, ctypes.byref(prm),
+                                  ctypes.byref(opt), ctypes.byref(ctx)))
+        self.ctx = ctx
+        sz = HdgSizes()
+        _check(self.lib.hdg_get_sizes(ctx, ctypes.byref(sz)))
+        self.sizes = sz
+        self.p = degree
+        self.m = degree + 1
+        self.n_loc = sz.n_loc
+        self.n_cell, self.n_facet, self.n_vert = sz.n_cell, sz.n_facet, sz.n_vert
+        self.kappa = sz.kappa
+
+    # ------------------------------------------------------------------ helpers
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.hdg_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def trace_zeros(self, nrhs: int = 1):
+        import torch
+        return torch.zeros((self.n_facet, self.m, nrhs), dtype=torch.float64, device="cuda")
+
+    def cell_zeros(self, nrhs: int = 1):
+        import torch
+        return torch.zeros((self.n_cell, 3, self.n_loc, nrhs), dtype=torch.float64, device="cuda")
+
+    @staticmethod
+    def _nrhs(t, trailing_dims):
+        if t.dtype != __import__("torch").float64 or not t.is_cuda or not t.is_contiguous():
+            raise ValueError("expected a contiguous float64 CUDA tensor")
+        if t.dim() != trailing_dims:
+            raise ValueError(f"expected a {trailing_dims}-d tensor")
+        return int(t.shape[-1])
+
+    def topology(self):
+        fc = np.zeros((self.n_facet, 2), dtype=np.int32)
+        fl = np.zeros((self.n_facet, 2), dtype=np.int32)
+        fv = np.zeros((self.n_facet, 2), dtype=np.int32)
+        _check(self.lib.hdg_get_topology(self.ctx, fc.ctypes.data, fl.ctypes.data, fv.ctypes.data))
+        return fc, fl, fv
+
+    # ------------------------------------------------------------------ the ABI calls
+    def condense(self, r_cell, out=None):
+        nb = self._nrhs(r_cell, 4)
+        out = self.trace_zeros(nb) if out is None else out
+        _check(self.lib.hdg_condense(self.ctx, nb, _ptr(r_cell), _ptr(out), _stream()))
+        return out
+
+    def trace_apply(self, x, precision: int = HDG_FP64, out=None):
+        nb = self._nrhs(x, 3)
+        out = self.trace_zeros(nb) if out is None else out
+        _check(self.lib.hdg_trace_apply(self.ctx, nb, precision, _ptr(x), _ptr(out), _stream()))
+        return out
+
+    def mg_vcycle(self, r, precision: int = HDG_FP64, out=None):
+        nb = self._nrhs(r, 3)
+        out = self.trace_zeros(nb) if out is None else out
+        _check(self.lib.hdg_mg_vcycle(self.ctx, nb, precision, _ptr(r), _ptr(out), _stream()))
+        return out
+
+    def solve(self, rhat, lam=None, allow_notconv: bool = False) -> "tuple":
+        nb = self._nrhs(rhat, 3)
+        lam = self.trace_zeros(nb) if lam is None else lam
+        info = (HdgSolveInfo * nb)()
+        allow = (HDG_OK, HDG_ENOTCONV) if allow_notconv else (HDG_OK,)
+        _check(self.lib.hdg_solve(self.ctx, nb, _ptr(rhat), _ptr(lam), info, _stream()), allow)
+        return lam, [SolveInfo(i.iters, i.refinements, i.fallbacks, i.status, i.rel_res) for i in info]
+
+    def recover(self, r_cell, lam, out=None):
+        nb = self._nrhs(r_cell, 4)
+        out = self.cell_zeros(nb) if out is None else out
+        _check(self.lib.hdg_recover(self.ctx, nb, _ptr(r_cell), _ptr(lam), _ptr(out), _stream()))
+        return out
+
+    def step(self, r_cell):
+        """Condense, solve, recover: one implicit stage.  Returns (q, lam, info)."""
+        rhat = self.condense(r_cell)
+        lam, info = self.solve(rhat)
+        return self.recover(r_cell, lam), lam, info
+
+    # ------------------------------------------------------------------ measurement
+    def set_timing(self, enable: bool):
+        _check(self.lib.hdg_set_timing(self.ctx, 1 if enable else 0))
+
+    def kernel_stats(self, kernel: str, precision: int = HDG_FP64):
+        n = ctypes.c_int64()
+        ms = ctypes.c_double()
+        b = ctypes.c_double()
+        _check(self.lib.hdg_kernel_stats(self.ctx, KERNELS[kernel], precision, ctypes.byref(n),
+                                         ctypes.byref(ms), ctypes.byref(b)))
+        return int(n.value), float(ms.value), float(b.value)
+
+
+def device_copy(src, dst):
+    _check(load_library().hdg_copy(_ptr(src), _ptr(dst), src.numel(), _stream()))

@@ -1,0 +1,54 @@
+"""The C-ABI library loads and exports every symbol include/hdg.h declares
+(no GPU needed: no compute call is made)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2004_09389_amd import hdg
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "hdg.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hdg_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_entry_points():
+    syms = declared_symbols()
+    for name in ("hdg_setup", "hdg_condense", "hdg_trace_apply", "hdg_mg_vcycle", "hdg_solve",
+                 "hdg_recover", "hdg_destroy", "hdg_last_error"):
+        assert name in syms
+
+
+def test_library_exports_every_declared_symbol():
+    lib = hdg.load_library()
+    for name in declared_symbols():
+        assert hasattr(lib, name), name
+        assert getattr(lib, name) is not None
+
+
+def test_binding_signatures_cover_header():
+    assert set(declared_symbols()) == set(hdg._SIGS)
+
+
+def test_default_options_and_errors_without_gpu():
+    o = hdg.default_options()
+    assert (o.nu_pre, o.nu_post, o.p1_nu, o.restart, o.max_rhs) == (2, 2, 2, 30, 1)
+    assert o.omega == 0.7 and abs(o.p1_omega - 2 / 3) < 1e-15 and o.rtol == 1e-8
+    lib = hdg.load_library()
+    assert lib.hdg_default_options(None) == hdg.HDG_EINVAL
+    # a NULL context is rejected before any device work
+    assert lib.hdg_condense(None, 1, None, None, None) == hdg.HDG_EINVAL
+    assert lib.hdg_get_sizes(None, None) == hdg.HDG_EINVAL
+    assert isinstance(lib.hdg_last_error(), bytes)
+
+
+def test_struct_layouts_match_header():
+    # the ctypes mirrors must have the C struct sizes (natural alignment)
+    assert ctypes.sizeof(hdg.HdgMesh) == 4 * 3 + 4 + 8 + 3 * 8
+    assert ctypes.sizeof(hdg.HdgParams) == 8 + 6 * 8
+    assert ctypes.sizeof(hdg.HdgSolveInfo) == 4 * 4 + 8
