@@ -1,0 +1,205 @@
+"""Benchmark: one implicit HDG stage of the linearised rotating shallow-water
+equations on one MI355X.
+
+Workload (default): periodic unit square, 256 x 256 squares -> 131072
+triangles, g = H = 1, f = 1, dt = 8/256 (gravity-wave Courant 8), DG degree
+p = 3 with a degree-3 scalar trace (786 432 trace unknowns), right-hand side
+a smooth random field (64 Fourier modes per field, amplitudes ~ |k|^-2).
+
+A step is one pass of the whole hot path for one batch of right-hand sides:
+condense (Step 1) -> Krylov solve of the trace system to a true relative
+residual of 1e-8 preconditioned by the non-nested multigrid V-cycle
+(Step 2) -> recovery of the cell fields (Step 3).  Inputs are resident in
+device memory before timing starts.  `value` is the mixed-precision solver's
+throughput (solves/s); the plain FP64 GPU multigrid is timed beside it.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--degree p] [--nrhs b]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E peak
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--degree", type=int, default=3)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--nrhs", type=int, default=1)
+    ap.add_argument("--coarse", type=int, default=16, help="side of the coarsest P1 level")
+    ap.add_argument("--tail-max", type=int, default=4096, help="P1 levels up to this size run in one workgroup")
+    ap.add_argument("--rtol", type=float, default=1e-8)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison leg")
+    ap.add_argument("--mixed-mode", default="mixed", choices=["mixed", "mixed_ir"],
+                    help="mixed: FP64 Krylov + reduced-precision V-cycle; mixed_ir: FP64 refinement of an FP32 inner solve")
+    ap.add_argument("--no-graph", action="store_true", help="launch every kernel eagerly (no HIP graphs)")
+    return ap.parse_args()
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(n_full, p, dt):
+    """Time the FP64 CPU oracle (direct SuperLU trace solve with its own
+    condensation and recovery) on a bounded sample: one right-hand side on
+    the same problem with a quarter of the cells (n/2 x n/2 squares), single
+    threaded; the per-solve time is scaled by the cell ratio to the full
+    workload."""
+    from threadpoolctl import threadpool_limits
+
+    import hdg_inputs as hi
+    from oracle.hdg import HdgOracle
+
+    ns = max(n_full // 2, 8)
+    with threadpool_limits(limits=1):
+        mesh = hi.torus(ns)
+        r = hi.fourier_rhs_torus(mesh, p, 100)[..., 0]
+        o = HdgOracle(mesh, p, dt, 1.0, 1.0, 1.0)
+        t0 = time.perf_counter()
+        o.solve(r)
+        t = time.perf_counter() - t0
+    scale = (n_full / ns) ** 2
+    return {"value": 1.0 / (t * scale), "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": f"one solve on the {ns}x{ns} torus (p={p}, same dt and f; "
+                      f"{2 * ns * ns} cells), {t:.2f} s, scaled x{scale:.0f} to {2 * n_full * n_full} cells"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; a multi-GPU run is not provided "
+                                   "(right-hand sides would shard across GPUs with no communication)"}))
+        sys.exit(2)
+
+    import torch
+
+    import hdg_inputs as hi
+    from paper_2004_09389_amd.hdg import HDG_FP64, HDG_MIXED, HDG_MIXED_IR, HdgSolver
+
+    torch.cuda.set_device(0)
+    p, n, nb = args.degree, args.n, args.nrhs
+    dt = 8.0 / n
+    t0 = time.perf_counter()
+    hier = hi.torus_hierarchy(n, args.coarse)
+    mesh = hier.fine
+    r = hi.fourier_rhs_torus(mesh, p, 100, nrhs=nb)
+    log(f"[bench] mesh+rhs {time.perf_counter() - t0:.1f}s cells={mesh.n_cell} p={p} nrhs={nb}")
+    rd = torch.from_numpy(r).to("cuda")
+
+    def make(prec):
+        t = time.perf_counter()
+        s = HdgSolver(hier, p, dt, 1.0, 1.0, 1.0, 0.0, 1.0, rtol=args.rtol, precision=prec, max_rhs=nb,
+                      krylov=2, maxit=200, p1_tail_max=args.tail_max, use_graph=0 if args.no_graph else 1)
+        torch.cuda.synchronize()
+        log(f"[bench] setup {'mixed' if prec else 'fp64'} {time.perf_counter() - t:.2f}s "
+            f"device={s.sizes.device_bytes / 2**30:.2f} GiB")
+        return s, time.perf_counter() - t
+
+    def run(s, steps, timing=False):
+        lam = s.trace_zeros(nb)
+        rhat = s.trace_zeros(nb)
+        q = s.cell_zeros(nb)
+        infos = []
+        if timing:
+            s.set_timing(True)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            s.condense(rd, out=rhat)
+            lam.zero_()
+            _, info = s.solve(rhat, lam)
+            s.recover(rd, lam, out=q)
+            infos.append(info)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t
+        return el, infos, lam, q
+
+    results = {}
+    mixed_prec = HDG_MIXED if args.mixed_mode == "mixed" else HDG_MIXED_IR
+    legs = [("mixed", mixed_prec)] + ([] if args.no_fp64 else [("fp64", HDG_FP64)])
+    for name, prec in legs:
+        s, tsetup = make(prec)
+        run(s, args.warmup)
+        el, infos, lam, q = run(s, args.steps, timing=(name == "mixed" and args.no_graph))
+        its = [i.iters for inf in infos for i in inf]
+        res = max(i.rel_res for inf in infos for i in inf)
+        stats = {k: s.kernel_stats(k, min(prec, HDG_MIXED)) for k in ("apply", "sweep", "residual", "condense", "recover")}
+        results[name] = dict(el=el, its=float(np.mean(its)), res=res, lam=lam.clone(), setup=tsetup,
+                             stats=stats, refinements=float(np.mean([i.refinements for inf in infos for i in inf])))
+        log(f"[bench] {name}: {args.steps} steps in {el:.3f}s ({1e3 * el / args.steps:.3f} ms/step) "
+            f"iters={np.mean(its):.1f} rel_res<={res:.2e}")
+        s.close()
+        del s
+
+    mx = results["mixed"]
+    steps = args.steps
+    value = steps * nb / mx["el"]
+    # dominant kernel by total event time during the timed mixed-precision steps
+    st = mx["stats"]
+    dom = max(st, key=lambda k: st[k][1])
+    launches, ms, bpl = st[dom]
+    avg_s = ms / max(launches, 1) / 1e3
+    achieved = bpl * nb / avg_s / 1e9 if avg_s > 0 else 0.0
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "avg_launch_us": round(avg_s * 1e6, 3), "launches": launches,
+                "bytes_per_launch": bpl * nb}
+    kern = {k: {"launches": v[0], "total_ms": round(v[1], 3),
+                "avg_us": round(1e3 * v[1] / max(v[0], 1), 3),
+                "GBps": round(v[2] * nb / (v[1] / max(v[0], 1) / 1e3) / 1e9, 1) if v[1] > 0 else None}
+            for k, v in st.items()}
+    out = {
+        "metric": "trace solves/s to 1e-8 rel residual (learned/mixed vs FP64 MG), HBM GB/s",
+        "value": round(value, 3),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * mx["el"] / steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64+f32+bf16",
+        "data": "synthetic",
+        "config": {"workload": f"torus{n}x{n}_p{p}_f1_courant8", "degree": p, "n_cell": mesh.n_cell,
+                   "n_trace_dof": int(3 * (p + 1) * mesh.n_cell // 2),
+                   "n_cell_dof": int(3 * (p + 1) * (p + 2) // 2 * mesh.n_cell), "nrhs": nb,
+                   "rtol": args.rtol, "precision": "mixed (fp32 operator, bf16 smoother, fp64 refinement)",
+                   "coarsest_p1": f"{args.coarse}x{args.coarse}", "p1_tail_max": args.tail_max},
+        "iters": mx["its"],
+        "refinements": mx["refinements"],
+        "rel_res_max": mx["res"],
+        "roofline": roofline,
+        "kernels": kern,
+    }
+    if "fp64" in results:
+        fp = results["fp64"]
+        out["fp64_baseline"] = {"value": round(steps * nb / fp["el"], 3), "unit": "solves/s",
+                                "ms_per_step": round(1e3 * fp["el"] / steps, 4), "iters": fp["its"],
+                                "rel_res_max": fp["res"]}
+        out["speedup_vs_fp64"] = round(fp["el"] / mx["el"], 3)
+        d = (mx["lam"] - fp["lam"]).norm().item() / fp["lam"].norm().item()
+        out["lam_rel_diff_vs_fp64"] = d
+    if not args.no_cpu:
+        log("[bench] cpu oracle baseline ...")
+        out["cpu_baseline"] = cpu_baseline(n, p, dt)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

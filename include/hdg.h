@@ -65,9 +65,13 @@ extern "C" {
 #define HDG_TORUS  0
 #define HDG_SPHERE 1
 
-#define HDG_FP64   0        /* everything in FP64 */
-#define HDG_MIXED  1        /* FP32 operator / BF16 smoother storage, FP32 accumulate,
-                               FP64 Krylov, true residual and coarse P1 */
+#define HDG_FP64     0      /* everything in FP64 */
+#define HDG_MIXED    1      /* FP64 Krylov with the FP64 operator; the V-cycle uses the FP32
+                               operator rows, BF16 smoother rows and FP32 block inverses with FP32
+                               accumulation; P1 coarse solve in FP64 */
+#define HDG_MIXED_IR 2      /* hdg_solve only: FP64 iterative refinement (true residual with the
+                               FP64 operator at every restart) around an inner flexible GMRES
+                               that applies the FP32 operator and the mixed V-cycle */
 
 #define HDG_KRYLOV_AUTO   0 /* PCG when the trace operator is symmetric (f = 0, FP64), else FGMRES */
 #define HDG_KRYLOV_PCG    1
@@ -100,7 +104,7 @@ typedef struct {
 
 typedef struct {
     int32_t krylov;             /* HDG_KRYLOV_* */
-    int32_t precision;          /* HDG_FP64 or HDG_MIXED (solve path) */
+    int32_t precision;          /* solve path: HDG_FP64, HDG_MIXED or HDG_MIXED_IR */
     int32_t smoother;           /* HDG_SMOOTH_BJACOBI or HDG_SMOOTH_MLP */
     int32_t nu_pre, nu_post;    /* facet block-Jacobi sweeps (default 2, 2) */
     double  omega;              /* block-Jacobi damping (default 0.7) */
@@ -110,9 +114,12 @@ typedef struct {
     int32_t maxit;              /* max Krylov iterations in total (default 200) */
     int32_t restart;            /* FGMRES restart length (default 30, max 64) */
     int32_t max_rhs;            /* largest nrhs any call will use (default 1, max 64) */
-    int32_t use_graph;          /* capture Krylov iteration blocks in HIP graphs (default 1) */
+    int32_t use_graph;          /* replay each Krylov iteration as a captured HIP graph (default 1);
+                                   off while kernel timing is enabled */
     double  fallback_ratio;     /* learned smoother: revert to block-Jacobi when the residual
                                    shrinks by less than this per iteration (default 0.5) */
+    int32_t p1_tail_max;        /* P1 levels with at most this many vertices run inside one
+                                   single-workgroup kernel (default 4096, max 4096, 0 = never) */
 } hdg_options;
 
 typedef struct {

@@ -65,6 +65,39 @@ void check_launch() {
     if (e != hipSuccess) throw Error{HDG_EHIP, std::string("kernel launch: ") + hipGetErrorString(e)};
 }
 
+// ------------------------------------------------------------------ HIP graphs
+//
+// A Krylov iteration is a fixed sequence of ~25 small launches.  It is
+// captured once per (kind, nrhs, precision, index) on a private stream and
+// replayed into the caller's stream; the pointers it bakes in are all
+// context-owned buffers, so replays stay valid for the context's lifetime.
+// Nothing captured clears memory with a memset node.
+void run_step(hdg_ctx *c, uint64_t key, hipStream_t s, const std::function<void(hipStream_t)> &body) {
+    if (!c->opt.use_graph || c->timing) {
+        body(s);
+        return;
+    }
+    auto it = c->graphs.find(key);
+    if (it == c->graphs.end()) {
+        if (!c->cap_stream) HDG_HIP_CHECK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+        // order the capture stream after work already queued on s
+        HDG_HIP_CHECK(hipStreamSynchronize(s));
+        hipGraph_t g = nullptr;
+        HDG_HIP_CHECK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+        body(c->cap_stream);
+        HDG_HIP_CHECK(hipStreamEndCapture(c->cap_stream, &g));
+        hipGraphExec_t ex = nullptr;
+        HDG_HIP_CHECK(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
+        HDG_HIP_CHECK(hipGraphDestroy(g));
+        it = c->graphs.emplace(key, ex).first;
+    }
+    HDG_HIP_CHECK(hipGraphLaunch(it->second, s));
+}
+
+uint64_t graph_key(int kind, int nb, int prec, int idx) {
+    return ((uint64_t)kind << 48) | ((uint64_t)nb << 32) | ((uint64_t)prec << 24) | (uint64_t)idx;
+}
+
 // ------------------------------------------------------------------ kernel timing
 
 hipEvent_t pool_event(hdg_ctx *c) {
@@ -137,33 +170,41 @@ void op_sweep(hdg_ctx *c, int nb, int prec, const double *x, const double *z0, c
 }
 
 // One P1 geometric-multigrid V-cycle on level l (input lev[l].b); returns the
-// buffer holding the result.  Damped Jacobi pre/post smoothing, residual and
-// restriction fused, prolongation fused into the first post-sweep, dense
-// solve on the coarsest level.
+// buffer holding the result.  Damped-Jacobi pre-smoothing (first two sweeps
+// fused), residual, restriction, recursion, prolongation fused into the first
+// post-sweep.  Levels small enough for the tail kernel are handled by it in
+// one launch, dense coarsest solve included.
 double *p1_vcycle(hdg_ctx *c, int l, int nb, hipStream_t s) {
     hdg::P1LevelDev &L = c->lev[l];
+    if (l == c->tail_top) {
+        hdg::launch_p1_tail(c->tail, nb, s);
+        return L.x;
+    }
     if (l == 0) {
         hdg::launch_dense_mv(L.n, nb, c->coarse_inv, L.b, L.x, s);
         return L.x;
     }
     const double w = c->opt.p1_omega;
-    double *cur = L.x, *nxt = L.y;
-    hdg::launch_p1_first(L.n, nb, L.dinv, w, L.b, cur, s);
-    for (int k = 1; k < c->opt.p1_nu; ++k) {
-        hdg::launch_p1_sweep(L.n, nb, L.rowptr, L.col, L.val, L.diag, L.dinv, w, L.b, cur, nullptr, nullptr, nxt,
-                             s);
-        std::swap(cur, nxt);
+    double *x = L.x, *y = L.y;
+    if (c->opt.p1_nu == 1) {
+        hdg::launch_p1_first(L.n, nb, L.dinv, w, L.b, x, s);
+    } else {
+        hdg::launch_p1_pre2(L.n, nb, L.rowptr, L.col, L.val, L.diag, L.dinv, w, L.b, x, s);
+        for (int k = 2; k < c->opt.p1_nu; ++k) {
+            hdg::launch_p1_sweep(L.n, nb, L.rowptr, L.col, L.val, L.diag, L.dinv, w, L.b, x, nullptr, nullptr, y, s);
+            std::swap(x, y);
+        }
     }
+    hdg::launch_p1_resid(L.n, nb, L.rowptr, L.col, L.val, L.diag, L.b, x, y, s);
     hdg::P1LevelDev &C = c->lev[l - 1];
-    hdg::launch_p1_resid_restrict(C.n, nb, L.crow, L.ccol, L.cw, L.rowptr, L.col, L.val, L.diag, L.b, cur, C.b,
-                                  s);
+    hdg::launch_p1_restrict(C.n, nb, L.crow, L.ccol, L.cw, y, C.b, s);
     const double *xc = p1_vcycle(c, l - 1, nb, s);
     for (int k = 0; k < c->opt.p1_nu; ++k) {
-        hdg::launch_p1_sweep(L.n, nb, L.rowptr, L.col, L.val, L.diag, L.dinv, w, L.b, cur, k == 0 ? xc : nullptr,
-                             L.parents, nxt, s);
-        std::swap(cur, nxt);
+        hdg::launch_p1_sweep(L.n, nb, L.rowptr, L.col, L.val, L.diag, L.dinv, w, L.b, x, k == 0 ? xc : nullptr,
+                             L.parents, y, s);
+        std::swap(x, y);
     }
-    return cur;
+    return x;
 }
 
 // z = V(r): Alg. twolevel_vcycle from a zero initial guess.
@@ -210,15 +251,30 @@ enum { SC_RR = 0, SC_RZ0, SC_RZ1, SC_PW, SC_BETA, SC_RES, SC_HN2, SC_HN, SC_BN2,
 double *scal(hdg_ctx *c, int slot) { return c->scal + (size_t)slot * c->opt.max_rhs; }
 int64_t vec_len(const hdg_ctx *c) { return (int64_t)c->n_facet * c->m; }
 
+// out (device, may be null) and host (host-mapped, may be null) receive the dots
 void dots(hdg_ctx *c, int nb, int nd, const double *X, int64_t xstride, const double *y, double *out,
-          hipStream_t s) {
-    hdg::launch_dots(vec_len(c), nb, nd, X, xstride, y, c->red, c->red_blocks, out, s);
+          hipStream_t s, double *host = nullptr) {
+    hdg::launch_dots(vec_len(c), nb, nd, X, xstride, y, c->red, out, host, s);
     check_launch();
 }
 
-void fetch(hdg_ctx *c, const double *dev, int count, hipStream_t s) {
-    HDG_HIP_CHECK(hipMemcpyAsync(c->hscal, dev, count * sizeof(double), hipMemcpyDeviceToHost, s));
+// Reduction results the host needs are written by the kernels straight into
+// host-mapped memory (slots of 64 doubles in c->hlag, device view c->dlag):
+// no copy kernel is queued.  mark_lag() records when slot's values are final;
+// wait_lag() blocks until then.  The Krylov loops look at iteration j's
+// residual while iteration j+1 is already queued, so the GPU does not idle.
+double *lag_dev(hdg_ctx *c, int slot) { return c->dlag + 64 * slot; }
+void mark_lag(hdg_ctx *c, int slot, hipStream_t s) { HDG_HIP_CHECK(hipEventRecord(c->lag_ev[slot], s)); }
+const double *wait_lag(hdg_ctx *c, int slot) {
+    HDG_HIP_CHECK(hipEventSynchronize(c->lag_ev[slot]));
+    return c->hlag + 64 * slot;
+}
+
+// Blocking: dots of a single pair written to host slot 2.
+const double *dots_now(hdg_ctx *c, int nb, const double *x, const double *y, double *out, hipStream_t s) {
+    dots(c, nb, 1, x, 0, y, out, s, lag_dev(c, 2));
     HDG_HIP_CHECK(hipStreamSynchronize(s));
+    return c->hlag + 64 * 2;
 }
 
 void fill_info(hdg_solve_info *info, int nb, int its, int refinements, const std::vector<double> &rel,
@@ -249,51 +305,68 @@ bool any_nonfinite(const std::vector<double> &v) {
 void true_residual(hdg_ctx *c, int nb, const double *rhat, const double *lam, double *out,
                    std::vector<double> &rel, hipStream_t s) {
     op_apply(c, nb, HDG_FP64, lam, rhat, out, s, HDG_KERNEL_RESIDUAL);
-    dots(c, nb, 1, out, 0, out, scal(c, SC_RR), s);
-    fetch(c, scal(c, SC_RR), nb, s);
+    const double *h = dots_now(c, nb, out, out, scal(c, SC_RR), s);
     for (int r = 0; r < nb; ++r) {
         const double bn2 = c->hbn2[r];
-        rel[r] = bn2 > 0 ? std::sqrt(c->hscal[r] / bn2) : std::sqrt(c->hscal[r]);
+        rel[r] = bn2 > 0 ? std::sqrt(h[r] / bn2) : std::sqrt(h[r]);
     }
 }
 
 // Preconditioned CG (f = 0 and FP64: S symmetric positive definite, the
 // V-cycle a fixed symmetric linear operator).  Convergence is judged on the
-// recurrence residual and confirmed on the true residual; PCG restarts from
-// the true residual when the two disagree.
-int solve_pcg(hdg_ctx *c, int nb, const double *rhat, double *lam, hdg_solve_info *info, hipStream_t s) {
+// recurrence residual, one iteration late, and confirmed on the true
+// residual; PCG restarts from the true residual when the two disagree.
+int solve_pcg(hdg_ctx *c, int nb, const double *rhat, double *lam_user, hdg_solve_info *info, hipStream_t s) {
     const int64_t n = vec_len(c);
     const double rtol = c->opt.rtol;
     std::vector<double> rel(nb, 0.0);
     int its = 0, restarts = 0;
-    double *rz = scal(c, SC_RZ0), *rzn = scal(c, SC_RZ1);
+    // iterate on a context-owned copy of lam so captured iterations never refer to caller memory
+    double *lam = c->klam;
+    hdg::launch_copy(n * nb, lam_user, lam, s);
+    double *rzb[2] = {scal(c, SC_RZ0), scal(c, SC_RZ1)};
+    auto finish = [&](int status) {
+        hdg::launch_copy(n * nb, lam, lam_user, s);
+        fill_info(info, nb, its, restarts, rel, status);
+        return status;
+    };
     while (true) {
         true_residual(c, nb, rhat, lam, c->kr, rel, s);
-        if (any_nonfinite(rel)) { fill_info(info, nb, its, restarts, rel, HDG_EBREAKDOWN); return HDG_EBREAKDOWN; }
-        if (all_below(rel, rtol)) { fill_info(info, nb, its, restarts, rel, HDG_OK); return HDG_OK; }
-        if (its >= c->opt.maxit) { fill_info(info, nb, its, restarts, rel, HDG_ENOTCONV); return HDG_ENOTCONV; }
+        if (any_nonfinite(rel)) return finish(HDG_EBREAKDOWN);
+        if (all_below(rel, rtol)) return finish(HDG_OK);
+        if (its >= c->opt.maxit) return finish(HDG_ENOTCONV);
         ++restarts;
         vcycle(c, nb, HDG_FP64, c->kr, c->kz, s);
-        dots(c, nb, 1, c->kr, 0, c->kz, rz, s);
+        dots(c, nb, 1, c->kr, 0, c->kz, rzb[its & 1], s);
         hdg::launch_copy(n * nb, c->kz, c->kp, s);
+        int pending = -1;
         while (its < c->opt.maxit) {
-            op_apply(c, nb, HDG_FP64, c->kp, nullptr, c->kw, s, HDG_KERNEL_APPLY);
-            dots(c, nb, 1, c->kp, 0, c->kw, scal(c, SC_PW), s);
-            hdg::launch_pcg_update(n, nb, rz, scal(c, SC_PW), c->kp, c->kw, lam, c->kr, s);
+            const int slot = its & 1;
+            // one iteration: w = S p, alpha = rz / (p.w), lam += alpha p, r -= alpha w, ||r||^2 -> slot,
+            // z = V(r), rzn = r.z, p = z + (rzn / rz) p;  rz and rzn swap roles every iteration
+            double *a = rzb[slot], *b = rzb[slot ^ 1];
+            run_step(c, graph_key(1, nb, HDG_FP64, slot), s, [&](hipStream_t st) {
+                op_apply(c, nb, HDG_FP64, c->kp, nullptr, c->kw, st, HDG_KERNEL_APPLY);
+                dots(c, nb, 1, c->kp, 0, c->kw, scal(c, SC_PW), st);
+                hdg::launch_pcg_update_norm(n, nb, a, scal(c, SC_PW), c->kp, c->kw, lam, c->kr, c->red,
+                                            lag_dev(c, slot), st);
+                vcycle(c, nb, HDG_FP64, c->kr, c->kz, st);
+                dots(c, nb, 1, c->kr, 0, c->kz, b, st);
+                hdg::launch_pcg_dir(n, nb, b, a, c->kz, c->kp, st);
+                check_launch();
+            });
+            mark_lag(c, slot, s);
             ++its;
-            dots(c, nb, 1, c->kr, 0, c->kr, scal(c, SC_RR), s);
-            fetch(c, scal(c, SC_RR), nb, s);
-            bool done = true, bad = false;
-            for (int r = 0; r < nb; ++r) {
-                const double v = c->hscal[r];
-                if (!std::isfinite(v)) bad = true;
-                if (!(v <= rtol * rtol * c->hbn2[r])) done = false;
+            if (pending >= 0) {
+                const double *h = wait_lag(c, pending);
+                bool done = true, bad = false;
+                for (int r = 0; r < nb; ++r) {
+                    if (!std::isfinite(h[r])) bad = true;
+                    if (!(h[r] <= rtol * rtol * c->hbn2[r])) done = false;
+                }
+                if (bad || done) break;
             }
-            if (bad || done) break;
-            vcycle(c, nb, HDG_FP64, c->kr, c->kz, s);
-            dots(c, nb, 1, c->kr, 0, c->kz, rzn, s);
-            hdg::launch_pcg_dir(n, nb, rzn, rz, c->kz, c->kp, s);
-            std::swap(rz, rzn);
+            pending = slot;
         }
     }
 }
@@ -303,9 +376,10 @@ int solve_pcg(hdg_ctx *c, int nb, const double *rhat, double *lam, hdg_solve_inf
 // HDG_MIXED the Arnoldi process applies the FP32 operator and the
 // mixed-precision V-cycle, and a cycle ends once it has reduced its own
 // starting residual by inner_eta: the restarts are then FP64 iterative
-// refinement around a reduced-precision inner solve.
-int solve_fgmres(hdg_ctx *c, int nb, int inner, double inner_eta, const double *rhat, double *lam,
-                 hdg_solve_info *info, hipStream_t s) {
+// refinement around a reduced-precision inner solve.  The residual estimate
+// of column j is examined while column j+1 is already queued.
+int solve_fgmres(hdg_ctx *c, int nb, int vc_prec, int op_prec, double inner_eta, const double *rhat,
+                 double *lam, hdg_solve_info *info, hipStream_t s) {
     const int64_t n = vec_len(c);
     const int64_t vs = n * c->opt.max_rhs;
     const int R = c->opt.restart;
@@ -321,29 +395,36 @@ int solve_fgmres(hdg_ctx *c, int nb, int inner, double inner_eta, const double *
         cyc0 = rel;
         hdg::launch_gmres_start(nb, R, scal(c, SC_RR), c->gm, scal(c, SC_BETA), s);
         hdg::launch_scale_inv(n, nb, scal(c, SC_BETA), c->kV, c->kV, s);
-        int k = 0;
+        int k = 0, pending = -1;
+        auto converged = [&](const double *h) {
+            for (int r = 0; r < nb; ++r) {
+                if (!std::isfinite(h[r])) return true;   // stop the cycle; the true residual reports it
+                if (!(h[r] <= std::max(rtol, inner_eta * cyc0[r]))) return false;
+            }
+            return true;
+        };
         for (int j = 0; j < R && its < c->opt.maxit; ++j) {
             double *Vj = c->kV + (size_t)j * vs, *Vn = c->kV + (size_t)(j + 1) * vs;
             double *Zj = c->kZ + (size_t)j * vs;
-            vcycle(c, nb, inner, Vj, Zj, s);
-            op_apply(c, nb, inner, Zj, nullptr, Vn, s, HDG_KERNEL_APPLY);
-            dots(c, nb, j + 1, c->kV, vs, Vn, c->hcol, s);
-            hdg::launch_gs_update(n, nb, j + 1, c->hcol, c->kV, vs, Vn, s);
-            dots(c, nb, 1, Vn, 0, Vn, scal(c, SC_HN2), s);
-            hdg::launch_sqrt(nb, scal(c, SC_HN2), scal(c, SC_HN), s);
-            hdg::launch_scale_inv(n, nb, scal(c, SC_HN), Vn, Vn, s);
-            hdg::launch_gmres_givens(nb, j, R, c->hcol, scal(c, SC_HN), c->gm, c->dbn, scal(c, SC_RES), s);
-            check_launch();
+            const int slot = j & 1;
+            run_step(c, graph_key(2, nb, vc_prec * 4 + op_prec, j), s, [&](hipStream_t st) {
+                vcycle(c, nb, vc_prec, Vj, Zj, st);
+                op_apply(c, nb, op_prec, Zj, nullptr, Vn, st, HDG_KERNEL_APPLY);
+                dots(c, nb, j + 1, c->kV, vs, Vn, c->hcol, st);
+                hdg::launch_gs_norm_givens(n, nb, j + 1, c->hcol, c->kV, vs, Vn, c->red, scal(c, SC_HN), j, R, c->gm,
+                                           c->dbn, lag_dev(c, slot), st);
+                hdg::launch_scale_inv(n, nb, scal(c, SC_HN), Vn, Vn, st);
+                check_launch();
+            });
+            mark_lag(c, slot, s);
             ++its;
             k = j + 1;
-            fetch(c, scal(c, SC_RES), nb, s);
-            bool done = true, bad = false;
-            for (int r = 0; r < nb; ++r) {
-                const double v = c->hscal[r];
-                if (!std::isfinite(v)) bad = true;
-                if (!(v <= std::max(rtol, inner_eta * cyc0[r]))) done = false;
+            if (pending >= 0 && converged(wait_lag(c, pending))) {
+                k = j;   // column j was queued speculatively; the solution uses columns 0..j-1
+                pending = -1;
+                break;
             }
-            if (bad || done) break;
+            pending = slot;
         }
         hdg::launch_gmres_solve(nb, k, R, c->gm, c->hy, s);
         hdg::launch_lincomb(n, nb, k, c->hy, c->kZ, vs, lam, s);
@@ -379,6 +460,7 @@ void setup_impl(const hdg_mesh *levels, int nlev, const int32_t *const *parents,
     HDG_REQUIRE(opt.nu_pre >= 1 && opt.nu_post >= 1 && opt.p1_nu >= 1, "sweep counts must be >= 1");
     HDG_REQUIRE(opt.omega > 0 && opt.p1_omega > 0, "damping factors must be positive");
     HDG_REQUIRE(opt.rtol >= 0 && opt.maxit >= 1, "rtol >= 0 and maxit >= 1 required");
+    HDG_REQUIRE(opt.p1_tail_max >= 0 && opt.p1_tail_max <= hdg::P1_TAIL_MAX, "p1_tail_max must be in 0..4096");
     for (int l = 0; l < nlev; ++l) validate_mesh(levels[l]);
     const hdg_mesh &fine = levels[nlev - 1];
 
@@ -532,6 +614,24 @@ void setup_impl(const hdg_mesh *levels, int nlev, const int32_t *const *parents,
         }
     }
 
+    // ---- tail of the P1 hierarchy (levels small enough for one workgroup)
+    c->tail_top = -1;
+    for (int l = 0; l < nlev && l < hdg::P1_TAIL_LEVELS; ++l)
+        if (c->lev[l].n <= opt.p1_tail_max) c->tail_top = l;
+        else break;
+    if (c->tail_top >= 0) {
+        hdg::P1Tail &T = c->tail;
+        T.top = c->tail_top;
+        T.nu = opt.p1_nu;
+        T.omega = opt.p1_omega;
+        T.Ainv = c->coarse_inv;
+        for (int l = 0; l <= c->tail_top; ++l) {
+            const hdg::P1LevelDev &L = c->lev[l];
+            T.lev[l] = hdg::P1Lev{L.n, L.rowptr, L.col, L.val, L.diag, L.dinv, L.parents, L.crow, L.ccol, L.cw,
+                                  L.b, L.x, L.y};
+        }
+    }
+
     // ---- work vectors
     const size_t vl = (size_t)ne * m * mr;
     c->vz0 = dev_alloc<double>(c, vl);
@@ -542,13 +642,14 @@ void setup_impl(const hdg_mesh *levels, int nlev, const int32_t *const *parents,
     c->kz = dev_alloc<double>(c, vl);
     c->kp = dev_alloc<double>(c, vl);
     c->kw = dev_alloc<double>(c, vl);
+    c->klam = dev_alloc<double>(c, vl);
     const int Rr = opt.restart;
     const bool need_gmres = !(opt.krylov == HDG_KRYLOV_PCG);
     if (need_gmres) {
         c->kV = dev_alloc<double>(c, vl * (Rr + 1));
         c->kZ = dev_alloc<double>(c, vl * Rr);
     }
-    c->red_blocks = 1024;
+    c->red_blocks = 2048;   // upper bound of red_grid() for any nrhs
     c->red = dev_alloc<double>(c, (size_t)c->red_blocks * (Rr + 1) * mr);
     c->scal = dev_alloc<double>(c, (size_t)SC_COUNT * mr);
     c->hcol = dev_alloc<double>(c, (size_t)(Rr + 1) * mr);
@@ -557,6 +658,10 @@ void setup_impl(const hdg_mesh *levels, int nlev, const int32_t *const *parents,
     c->dbn = dev_alloc<double>(c, mr);
     c->loc = dev_alloc<double>(c, (size_t)c->nt * nk * mr);
     HDG_HIP_CHECK(hipHostMalloc((void **)&c->hscal, sizeof(double) * 64 * 4, hipHostMallocDefault));
+    HDG_HIP_CHECK(hipHostMalloc((void **)&c->hlag, sizeof(double) * 64 * 4,
+                                hipHostMallocMapped | hipHostMallocCoherent));
+    HDG_HIP_CHECK(hipHostGetDevicePointer((void **)&c->dlag, c->hlag, 0));
+    for (int i = 0; i < 2; ++i) HDG_HIP_CHECK(hipEventCreateWithFlags(&c->lag_ev[i], hipEventDisableTiming));
     c->hbn2.assign(mr, 0.0);
     HDG_HIP_CHECK(hipDeviceSynchronize());
 }
@@ -569,7 +674,13 @@ void destroy_impl(hdg_ctx *c) {
         (void)hipEventDestroy(p.b);
     }
     for (auto e : c->event_pool) (void)hipEventDestroy(e);
+    for (auto &g : c->graphs) (void)hipGraphExecDestroy(g.second);
+    c->graphs.clear();
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->hscal) (void)hipHostFree(c->hscal);
+    if (c->hlag) (void)hipHostFree(c->hlag);
+    for (int i = 0; i < 2; ++i)
+        if (c->lag_ev[i]) (void)hipEventDestroy(c->lag_ev[i]);
 }
 
 }  // namespace
@@ -592,6 +703,7 @@ extern "C" int hdg_default_options(hdg_options *o) {
     o->max_rhs = 1;
     o->use_graph = 1;
     o->fallback_ratio = 0.5;
+    o->p1_tail_max = hdg::P1_TAIL_MAX;
     return HDG_OK;
 }
 
@@ -691,20 +803,20 @@ extern "C" int hdg_solve(hdg_ctx *c, int32_t nb, const double *rhat, double *lam
         check_nb(c, nb);
         HDG_REQUIRE(rhat && lam && rhat != lam, "rhat and lam must be distinct non-NULL buffers");
         hipStream_t s = as_stream(stream);
-        dots(c, nb, 1, rhat, 0, rhat, scal(c, SC_BN2), s);
+        const double *h = dots_now(c, nb, rhat, rhat, scal(c, SC_BN2), s);
         hdg::launch_sqrt(nb, scal(c, SC_BN2), c->dbn, s);
-        fetch(c, scal(c, SC_BN2), nb, s);
-        for (int r = 0; r < nb; ++r) c->hbn2[r] = c->hscal[r];
+        for (int r = 0; r < nb; ++r) c->hbn2[r] = h[r];
         int kry = c->opt.krylov;
         if (kry == HDG_KRYLOV_AUTO) kry = (c->symmetric && c->opt.precision == HDG_FP64) ? HDG_KRYLOV_PCG : HDG_KRYLOV_FGMRES;
+        HDG_REQUIRE(c->opt.precision >= HDG_FP64 && c->opt.precision <= HDG_MIXED_IR, "unknown solve precision");
         if (kry == HDG_KRYLOV_FGMRES) HDG_REQUIRE(c->kV != nullptr, "FGMRES workspace was not allocated (krylov = PCG at setup)");
         if (kry == HDG_KRYLOV_PCG) {
             HDG_REQUIRE(c->opt.precision == HDG_FP64, "PCG needs the FP64 (linear) preconditioner");
             status = solve_pcg(c, nb, rhat, lam, info, s);
-        } else if (c->opt.precision == HDG_MIXED) {
-            status = solve_fgmres(c, nb, HDG_MIXED, 1e-4, rhat, lam, info, s);
+        } else if (c->opt.precision == HDG_MIXED_IR) {
+            status = solve_fgmres(c, nb, HDG_MIXED, HDG_MIXED, 1e-4, rhat, lam, info, s);
         } else {
-            status = solve_fgmres(c, nb, HDG_FP64, 0.0, rhat, lam, info, s);
+            status = solve_fgmres(c, nb, c->opt.precision, HDG_FP64, 0.0, rhat, lam, info, s);
         }
     });
     if (rc != HDG_OK) return rc;

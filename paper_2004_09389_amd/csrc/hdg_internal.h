@@ -5,6 +5,7 @@
 #include <hip/hip_bf16.h>
 
 #include <cstdint>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -85,6 +86,26 @@ struct P1LevelDev {
     double *b = nullptr, *x = nullptr, *y = nullptr;  // [n][max_rhs] work vectors
 };
 
+constexpr int P1_TAIL_MAX = 4096;   // levels up to this many vertices run in the tail kernel
+constexpr int P1_TAIL_LEVELS = 8;
+
+struct P1Lev {
+    int n;
+    const int *rowptr, *col;
+    const double *val, *diag, *dinv;
+    const int *parents;                      // into level - 1
+    const int *crow, *ccol;                  // children of the level - 1 vertices
+    const double *cw;
+    double *b, *x, *y;
+};
+
+struct P1Tail {
+    int top, nu;
+    double omega;
+    const double *Ainv;                      // dense inverse of level 0
+    P1Lev lev[P1_TAIL_LEVELS];
+};
+
 }  // namespace hdg
 
 struct hdg_ctx {
@@ -122,11 +143,13 @@ struct hdg_ctx {
     // P1 hierarchy, level 0 coarsest
     std::vector<hdg::P1LevelDev> lev;
     double *coarse_inv = nullptr;   // dense inverse of the coarsest level
+    int tail_top = -1;              // levels 0..tail_top run in the single-workgroup tail kernel
+    hdg::P1Tail tail{};
 
     // trace work vectors [n_facet][m][max_rhs]
     double *vz0 = nullptr, *vx = nullptr, *vx2 = nullptr, *vres = nullptr;
     // Krylov work
-    double *kr = nullptr, *kz = nullptr, *kp = nullptr, *kw = nullptr, *kd = nullptr;
+    double *kr = nullptr, *kz = nullptr, *kp = nullptr, *kw = nullptr, *klam = nullptr;
     double *kV = nullptr, *kZ = nullptr;      // FGMRES bases [(restart+1)][vec], [restart][vec]
     double *red = nullptr;                    // reduction partials
     double *scal = nullptr;                   // device scalars [slot][max_rhs]
@@ -137,6 +160,9 @@ struct hdg_ctx {
     double *dbn = nullptr;                    // ||rhat|| per RHS (device)
     double *loc = nullptr;                    // condensation scratch [nt][n_cell][max_rhs]
     std::vector<double> hbn2;                 // ||rhat||^2 per RHS (host)
+    double *hlag = nullptr;                   // host-mapped landing slots for reduction results [4][64]
+    double *dlag = nullptr;                   // device view of hlag
+    hipEvent_t lag_ev[2] = {nullptr, nullptr};
     int red_blocks = 0;
 
     // timing
@@ -147,6 +173,10 @@ struct hdg_ctx {
     bool timing = false;
     std::vector<PendingEvent> pending;
     std::vector<hipEvent_t> event_pool;
+
+    // captured Krylov iterations
+    std::map<uint64_t, hipGraphExec_t> graphs;
+    hipStream_t cap_stream = nullptr;
     int64_t t_launches[2][HDG_KERNEL_COUNT] = {};
     double t_ms[2][HDG_KERNEL_COUNT] = {};
 };

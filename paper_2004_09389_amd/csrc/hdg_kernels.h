@@ -29,36 +29,41 @@ void launch_restrict_trace(int p, int nv, int nb, const int *vf_row, const int *
                            double *rc, hipStream_t s);
 
 void launch_p1_first(int n, int nb, const double *dinv, double omega, const double *b, double *x, hipStream_t s);
+void launch_p1_pre2(int n, int nb, const int *rowptr, const int *col, const double *val, const double *diag,
+                    const double *dinv, double omega, const double *b, double *x, hipStream_t s);
 void launch_p1_sweep(int n, int nb, const int *rowptr, const int *col, const double *val, const double *diag,
                      const double *dinv, double omega, const double *b, const double *x, const double *xc,
                      const int *parents, double *y, hipStream_t s);
-void launch_p1_resid_restrict(int nc, int nb, const int *crow, const int *ccol, const double *cw,
-                              const int *rowptr, const int *col, const double *val, const double *diag,
-                              const double *b, const double *x, double *bc, hipStream_t s);
+void launch_p1_resid(int n, int nb, const int *rowptr, const int *col, const double *val, const double *diag,
+                     const double *b, const double *x, double *y, hipStream_t s);
+void launch_p1_restrict(int nc, int nb, const int *crow, const int *ccol, const double *cw, const double *r,
+                        double *bc, hipStream_t s);
 void launch_dense_mv(int n, int nb, const double *Ainv, const double *b, double *x, hipStream_t s);
+void launch_p1_tail(const P1Tail &T, int nb, hipStream_t s);
 
 void launch_condense(int p, int nk, int ne, int nb, const double *Zr, const double *rc, double *loc,
                      const int *facet_cell, const int *facet_loc, double *rhat, hipStream_t s);
 void launch_recover(int p, int nk, int nb, const double *Ar, const double *Wr, const int *cell_facet,
                     const int8_t *cell_rev, const double *rc, const double *lam, double *q, hipStream_t s);
 
+int red_grid(int64_t len, int nb);
 void launch_dots(int64_t len, int nb, int nd, const double *X, int64_t xstride, const double *y, double *partial,
-                 int nblk, double *out, hipStream_t s);
+                 double *out, double *host, hipStream_t s);
+void launch_gs_norm_givens(int64_t len, int nb, int nd, const double *h, const double *V, int64_t vstride,
+                           double *w, double *partial, double *hn, int j, int restart, double *gm,
+                           const double *bnorm, double *resid_host, hipStream_t s);
+void launch_pcg_update_norm(int64_t len, int nb, const double *num, const double *den, const double *p,
+                            const double *w, double *x, double *res, double *partial, double *rr_host,
+                            hipStream_t s);
 void launch_axpby(int64_t n, int nb, const double *a, double as, const double *x, const double *b, double bs,
                   double *y, hipStream_t s);
-void launch_pcg_update(int64_t n, int nb, const double *num, const double *den, const double *p, const double *w,
-                       double *x, double *res, hipStream_t s);
 void launch_pcg_dir(int64_t n, int nb, const double *num, const double *den, const double *z, double *p,
                     hipStream_t s);
-void launch_gs_update(int64_t n, int nb, int nd, const double *h, const double *V, int64_t vstride, double *w,
-                      hipStream_t s);
 void launch_lincomb(int64_t n, int nb, int nd, const double *y, const double *Z, int64_t zstride, double *x,
                     hipStream_t s);
 void launch_scale_inv(int64_t n, int nb, const double *sc, const double *x, double *y, hipStream_t s);
 void launch_copy(int64_t n, const double *src, double *dst, hipStream_t s);
 void launch_gmres_start(int nb, int restart, const double *beta2, double *gm, double *beta, hipStream_t s);
-void launch_gmres_givens(int nb, int j, int restart, const double *hcol, const double *hnorm, double *gm,
-                         const double *bnorm, double *resid, hipStream_t s);
 void launch_gmres_solve(int nb, int k, int restart, const double *gm, double *y, hipStream_t s);
 void launch_sqrt(int nb, const double *in, double *out, hipStream_t s);
 

@@ -435,10 +435,17 @@ __global__ void k_restrict_trace(int nv, int nb, const int *__restrict__ vf_row,
 }
 
 // ------------------------------------------------------------------ P1 levels
+//
+// Coarse problem S_c q = r_c of the upwind case, solved by one geometric
+// multigrid V-cycle: damped Jacobi smoothing, linear-interpolation transfer
+// from the nested hierarchy's parent map, dense inverse on the coarsest
+// level.  Large levels run as one kernel per step; all levels with at most
+// P1_TAIL_MAX vertices (and the dense solve) run inside one single-workgroup
+// kernel, because at that size a launch costs more than the work.
 
-__device__ __forceinline__ double p1_row(int v, int nb, int r, const int *rowptr, const int *col,
-                                         const double *val, const double *x) {
-    double s = 0.0;
+__device__ __forceinline__ double p1_ax(int v, int nb, int r, const int *rowptr, const int *col,
+                                        const double *val, const double *diag, const double *x) {
+    double s = diag[v] * x[(size_t)v * nb + r];
     for (int c = rowptr[v]; c < rowptr[v + 1]; ++c) s += val[c] * x[(size_t)col[c] * nb + r];
     return s;
 }
@@ -450,7 +457,24 @@ __global__ void k_p1_first(int n, int nb, const double *__restrict__ dinv, doubl
     x[t] = omega * dinv[t / nb] * b[t];
 }
 
-// y = x + omega D^-1 (b - A x); with xc != nullptr the input is x + P xc (prolongation fused)
+// two sweeps from a zero guess: x1 = w D^-1 b, x2 = x1 + w D^-1 (b - A x1)
+__global__ void k_p1_pre2(int n, int nb, const int *__restrict__ rowptr, const int *__restrict__ col,
+                          const double *__restrict__ val, const double *__restrict__ diag,
+                          const double *__restrict__ dinv, double omega, const double *__restrict__ b,
+                          double *__restrict__ x) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * nb) return;
+    const int v = t / nb, r = t - v * nb;
+    double ax = diag[v] * omega * dinv[v] * b[t];
+    for (int c = rowptr[v]; c < rowptr[v + 1]; ++c) {
+        const int u = col[c];
+        ax += val[c] * omega * dinv[u] * b[(size_t)u * nb + r];
+    }
+    const double x1 = omega * dinv[v] * b[t];
+    x[t] = x1 + omega * dinv[v] * (b[t] - ax);
+}
+
+// y = x + w D^-1 (b - A x); with xc != nullptr the input is x + P xc (prolongation fused)
 __global__ void k_p1_sweep(int n, int nb, const int *__restrict__ rowptr, const int *__restrict__ col,
                            const double *__restrict__ val, const double *__restrict__ diag,
                            const double *__restrict__ dinv, double omega, const double *__restrict__ b,
@@ -471,33 +495,121 @@ __global__ void k_p1_sweep(int n, int nb, const int *__restrict__ rowptr, const 
     y[t] = xv + omega * dinv[v] * (b[t] - ax);
 }
 
-// bc[c] = sum_children w * (b - A x)[child]  (residual and restriction fused)
-__global__ void k_p1_resid_restrict(int nc, int nb, const int *__restrict__ crow, const int *__restrict__ ccol,
-                                    const double *__restrict__ cw, const int *__restrict__ rowptr,
-                                    const int *__restrict__ col, const double *__restrict__ val,
-                                    const double *__restrict__ diag, const double *__restrict__ b,
-                                    const double *__restrict__ x, double *__restrict__ bc) {
+__global__ void k_p1_resid(int n, int nb, const int *__restrict__ rowptr, const int *__restrict__ col,
+                           const double *__restrict__ val, const double *__restrict__ diag,
+                           const double *__restrict__ b, const double *__restrict__ x, double *__restrict__ y) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * nb) return;
+    const int v = t / nb, r = t - v * nb;
+    y[t] = b[t] - p1_ax(v, nb, r, rowptr, col, val, diag, x);
+}
+
+// bc[c] = sum over children of w * r[child]  (transpose of the interpolation)
+__global__ void k_p1_restrict(int nc, int nb, const int *__restrict__ crow, const int *__restrict__ ccol,
+                              const double *__restrict__ cw, const double *__restrict__ r,
+                              double *__restrict__ bc) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nc * nb) return;
-    const int c = t / nb, r = t - c * nb;
+    const int c = t / nb, rr = t - c * nb;
     double acc = 0.0;
-    for (int k = crow[c]; k < crow[c + 1]; ++k) {
-        const int v = ccol[k];
-        const double res = b[(size_t)v * nb + r] - diag[v] * x[(size_t)v * nb + r] - p1_row(v, nb, r, rowptr, col, val, x);
-        acc += cw[k] * res;
-    }
+    for (int k = crow[c]; k < crow[c + 1]; ++k) acc += cw[k] * r[(size_t)ccol[k] * nb + rr];
     bc[t] = acc;
 }
 
-// x = Ainv b on the coarsest level (dense)
+// x = Ainv b on the coarsest level when it is too large for the tail kernel:
+// one wavefront per (row, RHS), lanes stride over the row, shuffle reduction.
 __global__ void k_dense_mv(int n, int nb, const double *__restrict__ Ainv, const double *__restrict__ b,
                            double *__restrict__ x) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n * nb) return;
-    const int i = t / nb, r = t - i * nb;
+    const int w = (blockIdx.x * blockDim.x + threadIdx.x) / 64;
+    const int lane = threadIdx.x & 63;
+    if (w >= n * nb) return;
+    const int i = w / nb, r = w - i * nb;
     double s = 0.0;
-    for (int j = 0; j < n; ++j) s += Ainv[(size_t)i * n + j] * b[(size_t)j * nb + r];
-    x[t] = s;
+    for (int j = lane; j < n; j += 64) s += Ainv[(size_t)i * n + j] * b[(size_t)j * nb + r];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (lane == 0) x[w] = s;
+}
+
+// All levels 0..top of the hierarchy in one workgroup: the complete V-cycle
+// below and including level `top`, input lev[top].b, result in lev[top].x.
+__global__ __launch_bounds__(1024) void k_p1_tail(const P1Tail Targ, int nb) {
+    __shared__ double *xs[P1_TAIL_LEVELS];
+    __shared__ P1Tail T;   // level descriptors staged in LDS (runtime-indexed below)
+    const int tid = threadIdx.x, nth = blockDim.x;
+    if (tid == 0) T = Targ;
+    __syncthreads();
+    const double w = T.omega;
+    for (int l = T.top; l >= 1; --l) {
+        const P1Lev &L = T.lev[l];
+        const int N = L.n * nb;
+        double *x = L.x, *y = L.y;
+        for (int t = tid; t < N; t += nth) x[t] = w * L.dinv[t / nb] * L.b[t];
+        __syncthreads();
+        for (int k = 1; k < T.nu; ++k) {
+            for (int t = tid; t < N; t += nth) {
+                const int v = t / nb, r = t - v * nb;
+                y[t] = x[t] + w * L.dinv[v] * (L.b[t] - p1_ax(v, nb, r, L.rowptr, L.col, L.val, L.diag, x));
+            }
+            __syncthreads();
+            double *tmp = x; x = y; y = tmp;
+        }
+        for (int t = tid; t < N; t += nth) {
+            const int v = t / nb, r = t - v * nb;
+            y[t] = L.b[t] - p1_ax(v, nb, r, L.rowptr, L.col, L.val, L.diag, x);
+        }
+        __syncthreads();
+        const P1Lev &C = T.lev[l - 1];
+        for (int t = tid; t < C.n * nb; t += nth) {
+            const int c = t / nb, rr = t - c * nb;
+            double acc = 0.0;
+            for (int k = L.crow[c]; k < L.crow[c + 1]; ++k) acc += L.cw[k] * y[(size_t)L.ccol[k] * nb + rr];
+            C.b[t] = acc;
+        }
+        if (tid == 0) xs[l] = x;
+        __syncthreads();
+    }
+    {
+        const P1Lev &L0 = T.lev[0];
+        const int n0 = L0.n;
+        for (int t = tid; t < n0 * nb; t += nth) {
+            const int i = t / nb, r = t - i * nb;
+            double s = 0.0;
+            for (int j = 0; j < n0; ++j) s += T.Ainv[(size_t)i * n0 + j] * L0.b[(size_t)j * nb + r];
+            L0.x[t] = s;
+        }
+        if (tid == 0) xs[0] = L0.x;
+        __syncthreads();
+    }
+    for (int l = 1; l <= T.top; ++l) {
+        const P1Lev &L = T.lev[l];
+        const int N = L.n * nb;
+        double *x = xs[l];
+        double *y = (x == L.x) ? L.y : L.x;
+        const double *xc = xs[l - 1];
+        for (int k = 0; k < T.nu; ++k) {
+            for (int t = tid; t < N; t += nth) {
+                const int v = t / nb, r = t - v * nb;
+                auto xin = [&](int u) -> double {
+                    double s = x[(size_t)u * nb + r];
+                    if (k == 0) s += 0.5 * (xc[(size_t)L.parents[2 * u] * nb + r] + xc[(size_t)L.parents[2 * u + 1] * nb + r]);
+                    return s;
+                };
+                double ax = 0.0;
+                for (int c = L.rowptr[v]; c < L.rowptr[v + 1]; ++c) ax += L.val[c] * xin(L.col[c]);
+                const double xv = xin(v);
+                ax += L.diag[v] * xv;
+                y[t] = xv + w * L.dinv[v] * (L.b[t] - ax);
+            }
+            __syncthreads();
+            double *tmp = x; x = y; y = tmp;
+        }
+        if (tid == 0) xs[l] = x;
+        __syncthreads();
+    }
+    const P1Lev &Lt = T.lev[T.top];
+    if (T.top > 0 && xs[T.top] != Lt.x) {
+        for (int t = tid; t < Lt.n * nb; t += nth) Lt.x[t] = xs[T.top][t];
+    }
 }
 
 // ------------------------------------------------------------------ condensation / recovery (per solve)
@@ -584,47 +696,172 @@ __device__ __forceinline__ int rows_per_block(int nb) {
     return r;
 }
 
-// partial[blk][d][r] = sum over this block's rows of x_d[i][r] * y[i][r], for nd vectors x_d
-__global__ __launch_bounds__(256) void k_dots_partial(int64_t len, int nb, int nd, const double *__restrict__ X,
-                                                      int64_t xstride, const double *__restrict__ y,
-                                                      double *__restrict__ partial) {
-    __shared__ double sh[256];
-    const int rpb = rows_per_block(nb);
+// Per-RHS reductions over trace vectors run in two deterministic passes:
+// block partials (fixed row split), then one block per output summing the
+// partials in block order.  Repeated solves are bitwise identical.
+
+constexpr int RED_CHUNK = 8;   // dot products accumulated per pass over the rows
+
+// sh[k][tid] -> per-RHS block sums for k < kc in sh[k][r], r < nb
+__device__ __forceinline__ void block_rhs_sums(double (*sh)[256], int kc, int nb, int rpb) {
     const int tid = threadIdx.x;
-    const int rl = tid / nb, r = tid - rl * nb;
-    const bool active = rl < rpb;
-    for (int d = 0; d < nd; ++d) {
-        double acc = 0.0;
-        if (active) {
-            const double *x = X + (size_t)d * xstride;
-            for (int64_t i = (int64_t)blockIdx.x * rpb + rl; i < len; i += (int64_t)gridDim.x * rpb)
-                acc += x[i * nb + r] * y[i * nb + r];
-        }
-        sh[tid] = acc;
-        __syncthreads();
-        for (int s = rpb / 2; s > 0; s >>= 1) {
-            if (active && rl < s) sh[tid] += sh[tid + s * nb];
-            __syncthreads();
-        }
-        if (tid < nb) partial[((size_t)blockIdx.x * nd + d) * nb + tid] = sh[tid];
+    const int rl = tid / nb;
+    __syncthreads();
+    for (int s = rpb / 2; s > 0; s >>= 1) {
+        if (rl < s)
+            for (int k = 0; k < kc; ++k) sh[k][tid] += sh[k][tid + s * nb];
         __syncthreads();
     }
 }
 
-// out[d][r] = sum over blocks of partial[blk][d][r]; grid = (nd, nb)
-__global__ __launch_bounds__(256) void k_dots_final(int nblk, int nb, int nd, const double *__restrict__ partial,
-                                                    double *__restrict__ out) {
+// partial[blk][d][r] = this block's share of sum_i X_d[i][r] y[i][r], d < nd
+__global__ __launch_bounds__(256) void k_mdot_partial(int64_t len, int nb, int nd, const double *__restrict__ X,
+                                                      int64_t xstride, const double *__restrict__ y,
+                                                      double *__restrict__ partial) {
+    __shared__ double sh[RED_CHUNK][256];
+    const int rpb = rows_per_block(nb);
+    const int tid = threadIdx.x;
+    const int rl = tid / nb, r = tid - rl * nb;
+    for (int d0 = 0; d0 < nd; d0 += RED_CHUNK) {
+        const int kc = min(RED_CHUNK, nd - d0);
+        double acc[RED_CHUNK];
+#pragma unroll
+        for (int k = 0; k < RED_CHUNK; ++k) acc[k] = 0.0;
+        if (rl < rpb) {
+            for (int64_t i = (int64_t)blockIdx.x * rpb + rl; i < len; i += (int64_t)gridDim.x * rpb) {
+                const size_t t = (size_t)i * nb + r;
+                const double yv = y[t];
+#pragma unroll
+                for (int k = 0; k < RED_CHUNK; ++k)
+                    if (k < kc) acc[k] += X[(size_t)(d0 + k) * xstride + t] * yv;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < RED_CHUNK; ++k) sh[k][tid] = (rl < rpb) ? acc[k] : 0.0;
+        block_rhs_sums(sh, kc, nb, rpb);
+        if (tid < nb)
+            for (int k = 0; k < kc; ++k) partial[((size_t)blockIdx.x * nd + d0 + k) * nb + tid] = sh[k][tid];
+        __syncthreads();
+    }
+}
+
+__device__ __forceinline__ double block_sum_partials(const double *partial, int nblk, int nout, int o) {
     __shared__ double sh[256];
-    const int d = blockIdx.x, r = blockIdx.y;
     double acc = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += 256) acc += partial[((size_t)b * nd + d) * nb + r];
+    for (int b = threadIdx.x; b < nblk; b += 256) acc += partial[(size_t)b * nout + o];
     sh[threadIdx.x] = acc;
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {
         if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[(size_t)d * nb + r] = sh[0];
+    return sh[0];
+}
+
+// out[o] = sum over blocks, one block per output o = d * nb + r (grid nd * nb);
+// host (may be null) receives a copy in host-mapped memory.
+__global__ __launch_bounds__(256) void k_sum_final(int nblk, int nout, const double *__restrict__ partial,
+                                                   double *__restrict__ out, double *__restrict__ host) {
+    const int o = blockIdx.x;
+    const double v = block_sum_partials(partial, nblk, nout, o);
+    if (threadIdx.x == 0) {
+        if (out) out[o] = v;
+        if (host) host[o] = v;
+    }
+}
+
+__device__ void givens_column(int r, int nb, int j, int restart, const double *hcol, double hn, double *gm,
+                              const double *bnorm, double *resid) {
+    const int stride = (restart + 1) * restart + 2 * restart + (restart + 1);
+    double *H = gm + (size_t)r * stride;
+    double *cs = H + (restart + 1) * restart;
+    double *sn = cs + restart;
+    double *g = sn + restart;
+    double col[65];
+    for (int i = 0; i <= j; ++i) col[i] = hcol[(size_t)i * nb + r];
+    col[j + 1] = hn;
+    for (int i = 0; i < j; ++i) {
+        const double a = col[i], b = col[i + 1];
+        col[i] = cs[i] * a + sn[i] * b;
+        col[i + 1] = -sn[i] * a + cs[i] * b;
+    }
+    const double a = col[j], b = col[j + 1];
+    const double d = sqrt(a * a + b * b);
+    const double c = d > 0.0 ? a / d : 1.0, s = d > 0.0 ? b / d : 0.0;
+    cs[j] = c;
+    sn[j] = s;
+    col[j] = d;
+    for (int i = 0; i <= j; ++i) H[(size_t)i * restart + j] = col[i];
+    const double gj = g[j];
+    g[j] = c * gj;
+    g[j + 1] = -s * gj;
+    const double bn = bnorm[r];
+    resid[r] = bn > 0.0 ? fabs(g[j + 1]) / bn : 0.0;
+}
+
+// w -= sum_d h[d] V_d (classical Gram-Schmidt) and block partials of ||w||^2
+__global__ __launch_bounds__(256) void k_gs_update_norm(int64_t len, int nb, int nd, const double *__restrict__ h,
+                                                        const double *__restrict__ V, int64_t vstride,
+                                                        double *__restrict__ w, double *__restrict__ partial) {
+    __shared__ double sh[1][256];
+    const int rpb = rows_per_block(nb);
+    const int tid = threadIdx.x;
+    const int rl = tid / nb, r = tid - rl * nb;
+    double acc = 0.0;
+    if (rl < rpb) {
+        for (int64_t i = (int64_t)blockIdx.x * rpb + rl; i < len; i += (int64_t)gridDim.x * rpb) {
+            const size_t t = (size_t)i * nb + r;
+            double s = w[t];
+            for (int d = 0; d < nd; ++d) s -= h[(size_t)d * nb + r] * V[(size_t)d * vstride + t];
+            w[t] = s;
+            acc += s * s;
+        }
+    }
+    sh[0][tid] = (rl < rpb) ? acc : 0.0;
+    block_rhs_sums(sh, 1, nb, rpb);
+    if (tid < nb) partial[(size_t)blockIdx.x * nb + tid] = sh[0][tid];
+}
+
+// one block per RHS: ||w|| from the partials, then the Givens step of column j
+// (FGMRES); the relative residual estimate goes to host-mapped memory.
+__global__ __launch_bounds__(256) void k_norm_givens(int nblk, int nb, const double *__restrict__ partial,
+                                                     double *__restrict__ hn, int j, int restart,
+                                                     const double *__restrict__ hcol, double *__restrict__ gm,
+                                                     const double *__restrict__ bnorm, double *__restrict__ resid) {
+    const int r = blockIdx.x;
+    const double v = block_sum_partials(partial, nblk, nb, r);
+    if (threadIdx.x == 0) {
+        const double n = sqrt(fmax(v, 0.0));
+        hn[r] = n;
+        givens_column(r, nb, j, restart, hcol, n, gm, bnorm, resid);
+    }
+}
+
+// PCG update x += alpha p, r -= alpha w (alpha = num/den) and partials of ||r||^2
+__global__ __launch_bounds__(256) void k_pcg_update_norm(int64_t len, int nb, const double *__restrict__ num,
+                                                         const double *__restrict__ den,
+                                                         const double *__restrict__ p, const double *__restrict__ w,
+                                                         double *__restrict__ x, double *__restrict__ res,
+                                                         double *__restrict__ partial) {
+    __shared__ double sh[1][256];
+    const int rpb = rows_per_block(nb);
+    const int tid = threadIdx.x;
+    const int rl = tid / nb, r = tid - rl * nb;
+    double acc = 0.0;
+    if (rl < rpb) {
+        const double d = den[r];
+        const double al = d != 0.0 ? num[r] / d : 0.0;
+        for (int64_t i = (int64_t)blockIdx.x * rpb + rl; i < len; i += (int64_t)gridDim.x * rpb) {
+            const size_t t = (size_t)i * nb + r;
+            x[t] += al * p[t];
+            const double v = res[t] - al * w[t];
+            res[t] = v;
+            acc += v * v;
+        }
+    }
+    sh[0][tid] = (rl < rpb) ? acc : 0.0;
+    block_rhs_sums(sh, 1, nb, rpb);
+    if (tid < nb) partial[(size_t)blockIdx.x * nb + tid] = sh[0][tid];
 }
 
 // y[i][r] = a[r] * x[i][r] + b[r] * y[i][r] with per-RHS device scalars (null = 0 / 1 given)
@@ -637,19 +874,6 @@ __global__ void k_axpby(int64_t n, int nb, const double *__restrict__ a, double 
     y[t] = av * x[t] + (bv == 0.0 ? 0.0 : bv * y[t]);
 }
 
-// PCG update: x += alpha p, r -= alpha w, alpha[r] = num[r] / den[r] (zero when den is zero)
-__global__ void k_pcg_update(int64_t n, int nb, const double *__restrict__ num, const double *__restrict__ den,
-                             const double *__restrict__ p, const double *__restrict__ w, double *__restrict__ x,
-                             double *__restrict__ res) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n * nb) return;
-    const int r = (int)(t % nb);
-    const double d = den[r];
-    const double al = d != 0.0 ? num[r] / d : 0.0;
-    x[t] += al * p[t];
-    res[t] -= al * w[t];
-}
-
 // p = z + beta p, beta[r] = num[r] / den[r]
 __global__ void k_pcg_dir(int64_t n, int nb, const double *__restrict__ num, const double *__restrict__ den,
                           const double *__restrict__ z, double *__restrict__ p) {
@@ -659,17 +883,6 @@ __global__ void k_pcg_dir(int64_t n, int nb, const double *__restrict__ num, con
     const double d = den[r];
     const double be = d != 0.0 ? num[r] / d : 0.0;
     p[t] = z[t] + be * p[t];
-}
-
-// w -= sum_{d < nd} h[d][r] V_d   (classical Gram-Schmidt update)
-__global__ void k_gs_update(int64_t n, int nb, int nd, const double *__restrict__ h, const double *__restrict__ V,
-                            int64_t vstride, double *__restrict__ w) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n * nb) return;
-    const int r = (int)(t % nb);
-    double s = w[t];
-    for (int d = 0; d < nd; ++d) s -= h[(size_t)d * nb + r] * V[(size_t)d * vstride + t];
-    w[t] = s;
 }
 
 // x += sum_{d < nd} y[d][r] Z_d
@@ -695,45 +908,6 @@ __global__ void k_scale_inv(int64_t n, int nb, const double *__restrict__ s, con
 __global__ void k_copy(int64_t n, const double *__restrict__ src, double *__restrict__ dst) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t < n) dst[t] = src[t];
-}
-
-// ------------------------------------------------------------------ FGMRES small dense work (one thread per RHS)
-//
-// State per RHS in gm: H[(restart+1)][restart], cs[restart], sn[restart], g[restart+1],
-// beta, status.  Column j of H arrives in hcol (dots with V_0..V_j) and hnorm
-// (||w|| after orthogonalisation).  Applies the stored Givens rotations, forms
-// the new one and returns |g[j+1]| / bnorm in resid[r].
-__global__ void k_gmres_givens(int nb, int j, int restart, const double *__restrict__ hcol,
-                               const double *__restrict__ hnorm, double *__restrict__ gm,
-                               const double *__restrict__ bnorm, double *__restrict__ resid) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= nb) return;
-    const int stride = (restart + 1) * restart + 2 * restart + (restart + 1);
-    double *H = gm + (size_t)r * stride;
-    double *cs = H + (restart + 1) * restart;
-    double *sn = cs + restart;
-    double *g = sn + restart;
-    double col[65];
-    for (int i = 0; i <= j; ++i) col[i] = hcol[(size_t)i * nb + r];
-    col[j + 1] = hnorm[r];
-    for (int i = 0; i < j; ++i) {
-        const double a = col[i], b = col[i + 1];
-        col[i] = cs[i] * a + sn[i] * b;
-        col[i + 1] = -sn[i] * a + cs[i] * b;
-    }
-    const double a = col[j], b = col[j + 1];
-    const double d = sqrt(a * a + b * b);
-    const double c = d > 0.0 ? a / d : 1.0, s = d > 0.0 ? b / d : 0.0;
-    cs[j] = c;
-    sn[j] = s;
-    col[j] = d;
-    col[j + 1] = 0.0;
-    for (int i = 0; i <= j; ++i) H[(size_t)i * restart + j] = col[i];
-    const double gj = g[j];
-    g[j] = c * gj;
-    g[j + 1] = -s * gj;
-    const double bn = bnorm[r];
-    resid[r] = bn > 0.0 ? fabs(g[j + 1]) / bn : 0.0;
 }
 
 // start of a cycle: g = (beta, 0, ...), beta = ||r0||
@@ -832,20 +1006,29 @@ void launch_restrict_trace(int p, int nv, int nb, const int *vf_row, const int *
 void launch_p1_first(int n, int nb, const double *dinv, double omega, const double *b, double *x, hipStream_t s) {
     hipLaunchKernelGGL(k_p1_first, GRID(n * nb, 256), 0, s, n, nb, dinv, omega, b, x);
 }
+void launch_p1_pre2(int n, int nb, const int *rowptr, const int *col, const double *val, const double *diag,
+                    const double *dinv, double omega, const double *b, double *x, hipStream_t s) {
+    hipLaunchKernelGGL(k_p1_pre2, GRID(n * nb, 256), 0, s, n, nb, rowptr, col, val, diag, dinv, omega, b, x);
+}
 void launch_p1_sweep(int n, int nb, const int *rowptr, const int *col, const double *val, const double *diag,
                      const double *dinv, double omega, const double *b, const double *x, const double *xc,
                      const int *parents, double *y, hipStream_t s) {
     hipLaunchKernelGGL(k_p1_sweep, GRID(n * nb, 256), 0, s, n, nb, rowptr, col, val, diag, dinv, omega, b, x, xc,
                        parents, y);
 }
-void launch_p1_resid_restrict(int nc, int nb, const int *crow, const int *ccol, const double *cw,
-                              const int *rowptr, const int *col, const double *val, const double *diag,
-                              const double *b, const double *x, double *bc, hipStream_t s) {
-    hipLaunchKernelGGL(k_p1_resid_restrict, GRID(nc * nb, 256), 0, s, nc, nb, crow, ccol, cw, rowptr, col, val,
-                       diag, b, x, bc);
+void launch_p1_resid(int n, int nb, const int *rowptr, const int *col, const double *val, const double *diag,
+                     const double *b, const double *x, double *y, hipStream_t s) {
+    hipLaunchKernelGGL(k_p1_resid, GRID(n * nb, 256), 0, s, n, nb, rowptr, col, val, diag, b, x, y);
+}
+void launch_p1_restrict(int nc, int nb, const int *crow, const int *ccol, const double *cw, const double *r,
+                        double *bc, hipStream_t s) {
+    hipLaunchKernelGGL(k_p1_restrict, GRID(nc * nb, 256), 0, s, nc, nb, crow, ccol, cw, r, bc);
 }
 void launch_dense_mv(int n, int nb, const double *Ainv, const double *b, double *x, hipStream_t s) {
-    hipLaunchKernelGGL(k_dense_mv, GRID(n * nb, 64), 0, s, n, nb, Ainv, b, x);
+    hipLaunchKernelGGL(k_dense_mv, GRID((int64_t)n * nb * 64, 256), 0, s, n, nb, Ainv, b, x);
+}
+void launch_p1_tail(const P1Tail &T, int nb, hipStream_t s) {
+    hipLaunchKernelGGL(k_p1_tail, dim3(1), dim3(1024), 0, s, T, nb);
 }
 
 void launch_condense(int p, int nk, int ne, int nb, const double *Zr, const double *rc, double *loc,
@@ -865,27 +1048,44 @@ void launch_recover(int p, int nk, int nb, const double *Ar, const double *Wr, c
 #undef RC
 }
 
+int red_grid(int64_t len, int nb) {
+    // about four rows per thread; the final pass sums one partial per block
+    const int rpb = [&] { int r = 1; while (r * 2 * nb <= 256) r *= 2; return r; }();
+    int64_t blocks = (len + (int64_t)rpb * 4 - 1) / ((int64_t)rpb * 4);
+    if (blocks < 1) blocks = 1;
+    if (blocks > 2048) blocks = 2048;
+    return (int)blocks;
+}
+
 void launch_dots(int64_t len, int nb, int nd, const double *X, int64_t xstride, const double *y, double *partial,
-                 int nblk, double *out, hipStream_t s) {
-    hipLaunchKernelGGL(k_dots_partial, dim3(nblk), dim3(256), 0, s, len, nb, nd, X, xstride, y, partial);
-    hipLaunchKernelGGL(k_dots_final, dim3(nd, nb), dim3(256), 0, s, nblk, nb, nd, partial, out);
+                 double *out, double *host, hipStream_t s) {
+    const int g = red_grid(len, nb);
+    hipLaunchKernelGGL(k_mdot_partial, dim3(g), dim3(256), 0, s, len, nb, nd, X, xstride, y, partial);
+    hipLaunchKernelGGL(k_sum_final, dim3(nd * nb), dim3(256), 0, s, g, nd * nb, partial, out, host);
+}
+void launch_gs_norm_givens(int64_t len, int nb, int nd, const double *h, const double *V, int64_t vstride,
+                           double *w, double *partial, double *hn, int j, int restart, double *gm,
+                           const double *bnorm, double *resid_host, hipStream_t s) {
+    const int g = red_grid(len, nb);
+    hipLaunchKernelGGL(k_gs_update_norm, dim3(g), dim3(256), 0, s, len, nb, nd, h, V, vstride, w, partial);
+    hipLaunchKernelGGL(k_norm_givens, dim3(nb), dim3(256), 0, s, g, nb, partial, hn, j, restart, h, gm, bnorm,
+                       resid_host);
+}
+void launch_pcg_update_norm(int64_t len, int nb, const double *num, const double *den, const double *p,
+                            const double *w, double *x, double *res, double *partial, double *rr_host,
+                            hipStream_t s) {
+    const int g = red_grid(len, nb);
+    hipLaunchKernelGGL(k_pcg_update_norm, dim3(g), dim3(256), 0, s, len, nb, num, den, p, w, x, res, partial);
+    hipLaunchKernelGGL(k_sum_final, dim3(nb), dim3(256), 0, s, g, nb, partial, (double *)nullptr, rr_host);
 }
 
 void launch_axpby(int64_t n, int nb, const double *a, double as, const double *x, const double *b, double bs,
                   double *y, hipStream_t s) {
     hipLaunchKernelGGL(k_axpby, GRID(n * nb, 256), 0, s, n, nb, a, as, x, b, bs, y);
 }
-void launch_pcg_update(int64_t n, int nb, const double *num, const double *den, const double *p, const double *w,
-                       double *x, double *res, hipStream_t s) {
-    hipLaunchKernelGGL(k_pcg_update, GRID(n * nb, 256), 0, s, n, nb, num, den, p, w, x, res);
-}
 void launch_pcg_dir(int64_t n, int nb, const double *num, const double *den, const double *z, double *p,
                     hipStream_t s) {
     hipLaunchKernelGGL(k_pcg_dir, GRID(n * nb, 256), 0, s, n, nb, num, den, z, p);
-}
-void launch_gs_update(int64_t n, int nb, int nd, const double *h, const double *V, int64_t vstride, double *w,
-                      hipStream_t s) {
-    hipLaunchKernelGGL(k_gs_update, GRID(n * nb, 256), 0, s, n, nb, nd, h, V, vstride, w);
 }
 void launch_lincomb(int64_t n, int nb, int nd, const double *y, const double *Z, int64_t zstride, double *x,
                     hipStream_t s) {
@@ -899,10 +1099,6 @@ void launch_copy(int64_t n, const double *src, double *dst, hipStream_t s) {
 }
 void launch_gmres_start(int nb, int restart, const double *beta2, double *gm, double *beta, hipStream_t s) {
     hipLaunchKernelGGL(k_gmres_start, GRID(nb, 64), 0, s, nb, restart, beta2, gm, beta);
-}
-void launch_gmres_givens(int nb, int j, int restart, const double *hcol, const double *hnorm, double *gm,
-                         const double *bnorm, double *resid, hipStream_t s) {
-    hipLaunchKernelGGL(k_gmres_givens, GRID(nb, 64), 0, s, nb, j, restart, hcol, hnorm, gm, bnorm, resid);
 }
 void launch_gmres_solve(int nb, int k, int restart, const double *gm, double *y, hipStream_t s) {
     hipLaunchKernelGGL(k_gmres_solve, GRID(nb, 64), 0, s, nb, k, restart, gm, y);

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libhdg.so")
 
 HDG_OK, HDG_EINVAL, HDG_ENOMEM, HDG_EHIP, HDG_EBREAKDOWN, HDG_ENOTCONV = 0, -1, -2, -3, -4, 1
 HDG_TORUS, HDG_SPHERE = 0, 1
-HDG_FP64, HDG_MIXED = 0, 1
+HDG_FP64, HDG_MIXED, HDG_MIXED_IR = 0, 1, 2
 HDG_KRYLOV_AUTO, HDG_KRYLOV_PCG, HDG_KRYLOV_FGMRES = 0, 1, 2
 HDG_SMOOTH_BJACOBI, HDG_SMOOTH_MLP = 0, 1
 KERNELS = {"apply": 0, "sweep": 1, "residual": 2, "condense": 3, "recover": 4}
@@ -42,7 +42,8 @@ class HdgOptions(ctypes.Structure):
                 ("nu_pre", ctypes.c_int32), ("nu_post", ctypes.c_int32), ("omega", ctypes.c_double),
                 ("p1_nu", ctypes.c_int32), ("p1_omega", ctypes.c_double), ("rtol", ctypes.c_double),
                 ("maxit", ctypes.c_int32), ("restart", ctypes.c_int32), ("max_rhs", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32), ("fallback_ratio", ctypes.c_double)]
+                ("use_graph", ctypes.c_int32), ("fallback_ratio", ctypes.c_double),
+                ("p1_tail_max", ctypes.c_int32)]
 
 
 class HdgSolveInfo(ctypes.Structure):

@@ -23,6 +23,8 @@ def _cases():
         "torus16_p3_f1": (lambda: hi.torus_hierarchy(16, 4), 3, 0.5, 1.0, 1.0, 1.0, 0.0),
         "torus1_twocell_p1": (lambda: hi.torus_hierarchy(1, 1), 1, 0.5, 1.0, 1.0, 0.0, 0.0),
         "sphere_L2_p2": (lambda: hi.icosphere_hierarchy(2, HMS), 2, 1800.0, 9.81, 5960.0, 0.0, 7.292e-5),
+        # six P1 levels; only the finest (9216 vertices) is above the tail-kernel bound
+        "torus96_p1_deep": (lambda: hi.torus_hierarchy(96, 3), 1, 8.0 / 96, 1.0, 1.0, 1.0, 0.0),
     }
 
 
@@ -108,6 +110,17 @@ def test_vcycle(name):
     assert rel(z16, ref) < 3e-2
 
 
+@pytest.mark.parametrize("name", ["config1_torus8_p1", "torus96_p1_deep", "sphere_L2_p2"])
+def test_vcycle_without_tail_kernel(name):
+    """Every P1 level as separate kernels (and the dense coarsest solve as a
+    multi-block mat-vec) gives the same V-cycle as the single-workgroup tail."""
+    hier, solver, oracle, mg = setup_case(name, p1_tail_max=0)
+    r = np.random.default_rng(6).standard_normal((solver.n_facet, solver.m, 2))
+    ref = mg.vcycle(r[..., 0].ravel())
+    z = trace_np(solver.mg_vcycle(to_dev(r[..., :1].copy())))[..., 0].ravel()
+    assert rel(z, ref) < 1e-11
+
+
 @pytest.mark.parametrize("name", list(CASES))
 def test_solve_and_recover_fp64(name):
     hier, solver, oracle, _ = setup_case(name, rtol=1e-12)
@@ -149,3 +162,22 @@ def test_batched_matches_single(name):
         assert rel(lamb[..., k].ravel(), lam_ref) < 1e-10
         for fld in range(3):
             assert rel(qb[:, fld, :, k], q_ref[:, fld]) < 1e-10
+
+
+@pytest.mark.parametrize("name,prec", [("config1_torus8_p1", 0), ("torus16_p3_f1", 0), ("torus16_p3_f1", 1),
+                                       ("torus16_p3_f1", 2)])
+def test_graph_replay_matches_eager(name, prec):
+    """Captured Krylov iterations replayed several times, with eager work and
+    synchronisations between the replays, give bitwise the eager result."""
+    import torch
+    hier, sg, oracle, _ = setup_case(name, rtol=1e-10, precision=prec, use_graph=1)
+    _, se, _, _ = setup_case(name, rtol=1e-10, precision=prec, use_graph=0)
+    for seed in (51, 52, 53):
+        r = to_dev(hi.iid_rhs(hier.fine, sg.p, seed))
+        qg, lg, ig = sg.step(r)
+        junk = torch.randn(1000, device="cuda").sum()    # eager work between replays
+        torch.cuda.synchronize()
+        qe, le, ie = se.step(r)
+        torch.cuda.synchronize()
+        assert ig[0].iters == ie[0].iters and ig[0].status == 0
+        assert torch.equal(lg, le) and torch.equal(qg, qe), (seed, float(junk))
