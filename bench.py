@@ -39,8 +39,9 @@ def parse():
     ap.add_argument("--degree", type=int, default=3)
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--nrhs", type=int, default=1)
-    ap.add_argument("--coarse", type=int, default=16, help="side of the coarsest P1 level")
-    ap.add_argument("--tail-max", type=int, default=4096, help="P1 levels up to this size run in one workgroup")
+    ap.add_argument("--coarse", type=int, default=32, help="side of the coarsest P1 level")
+    ap.add_argument("--tail-max", type=int, default=0, help="P1 levels up to this size run in one workgroup")
+    ap.add_argument("--p1-nu", type=int, default=2, help="P1 Jacobi sweeps per level (pre and post)")
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison leg")
@@ -104,7 +105,8 @@ def main():
     def make(prec):
         t = time.perf_counter()
         s = HdgSolver(hier, p, dt, 1.0, 1.0, 1.0, 0.0, 1.0, rtol=args.rtol, precision=prec, max_rhs=nb,
-                      krylov=2, maxit=200, p1_tail_max=args.tail_max, use_graph=0 if args.no_graph else 1)
+                      krylov=2, maxit=200, p1_tail_max=args.tail_max, p1_nu=args.p1_nu,
+                      use_graph=0 if args.no_graph else 1)
         torch.cuda.synchronize()
         log(f"[bench] setup {'mixed' if prec else 'fp64'} {time.perf_counter() - t:.2f}s "
             f"device={s.sizes.device_bytes / 2**30:.2f} GiB")

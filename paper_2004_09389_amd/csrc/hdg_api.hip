@@ -189,30 +189,34 @@ double *p1_vcycle(hdg_ctx *c, int l, int nb, hipStream_t s) {
     if (c->opt.p1_nu == 1) {
         hdg::launch_p1_first(L.n, nb, L.dinv, w, L.b, x, s);
     } else {
-        hdg::launch_p1_pre2(L.n, nb, L.rowptr, L.col, L.val, L.diag, L.dinv, w, L.b, x, s);
+        hdg::launch_p1_pre2(L.n, L.w, nb, L.col, L.val, L.diag, L.dinv, w, L.b, x, s);
         for (int k = 2; k < c->opt.p1_nu; ++k) {
-            hdg::launch_p1_sweep(L.n, nb, L.rowptr, L.col, L.val, L.diag, L.dinv, w, L.b, x, nullptr, nullptr, y, s);
+            hdg::launch_p1_sweep(L.n, L.w, nb, L.col, L.val, L.diag, L.dinv, w, L.b, x, nullptr, nullptr, y, s);
             std::swap(x, y);
         }
     }
-    hdg::launch_p1_resid(L.n, nb, L.rowptr, L.col, L.val, L.diag, L.b, x, y, s);
+    hdg::launch_p1_resid(L.n, L.w, nb, L.col, L.val, L.diag, L.b, x, y, s);
     hdg::P1LevelDev &C = c->lev[l - 1];
     hdg::launch_p1_restrict(C.n, nb, L.crow, L.ccol, L.cw, y, C.b, s);
     const double *xc = p1_vcycle(c, l - 1, nb, s);
     for (int k = 0; k < c->opt.p1_nu; ++k) {
-        hdg::launch_p1_sweep(L.n, nb, L.rowptr, L.col, L.val, L.diag, L.dinv, w, L.b, x, k == 0 ? xc : nullptr,
+        hdg::launch_p1_sweep(L.n, L.w, nb, L.col, L.val, L.diag, L.dinv, w, L.b, x, k == 0 ? xc : nullptr,
                              L.parents, y, s);
         std::swap(x, y);
     }
     return x;
 }
 
-// z = V(r): Alg. twolevel_vcycle from a zero initial guess.
-void vcycle(hdg_ctx *c, int nb, int prec, const double *r, double *z, hipStream_t s) {
+// z = V(r): Alg. twolevel_vcycle from a zero initial guess.  With scale != null
+// the input is r / scale[rhs] and r is normalised in place on the way (the
+// FGMRES basis vector is scaled by its first reader).
+void vcycle(hdg_ctx *c, int nb, int prec, const double *r, double *z, hipStream_t s,
+            const double *scale = nullptr) {
+    double *rs = scale ? const_cast<double *>(r) : nullptr;
     if (prec == HDG_MIXED)
-        hdg::launch_jacobi0<float>(c->p, c->n_facet, nb, c->Dw32, r, c->vz0, s);
+        hdg::launch_jacobi0<float>(c->p, c->n_facet, nb, c->Dw32, r, scale, rs, c->vz0, s);
     else
-        hdg::launch_jacobi0<double>(c->p, c->n_facet, nb, c->Dw64, r, c->vz0, s);
+        hdg::launch_jacobi0<double>(c->p, c->n_facet, nb, c->Dw64, r, scale, rs, c->vz0, s);
     double *bufs[2] = {c->vx, c->vx2};
     int bi = 0;
     double *cur = c->vz0;  // first sweep from zero gives omega D^-1 r exactly
@@ -394,7 +398,6 @@ int solve_fgmres(hdg_ctx *c, int nb, int vc_prec, int op_prec, double inner_eta,
         ++cycles;
         cyc0 = rel;
         hdg::launch_gmres_start(nb, R, scal(c, SC_RR), c->gm, scal(c, SC_BETA), s);
-        hdg::launch_scale_inv(n, nb, scal(c, SC_BETA), c->kV, c->kV, s);
         int k = 0, pending = -1;
         auto converged = [&](const double *h) {
             for (int r = 0; r < nb; ++r) {
@@ -407,13 +410,15 @@ int solve_fgmres(hdg_ctx *c, int nb, int vc_prec, int op_prec, double inner_eta,
             double *Vj = c->kV + (size_t)j * vs, *Vn = c->kV + (size_t)(j + 1) * vs;
             double *Zj = c->kZ + (size_t)j * vs;
             const int slot = j & 1;
+            // V_j still carries its norm (beta for j = 0, the previous step's ||w|| after);
+            // the V-cycle's first kernel divides it out in place
+            const double *vscale = (j == 0) ? scal(c, SC_BETA) : scal(c, SC_HN);
             run_step(c, graph_key(2, nb, vc_prec * 4 + op_prec, j), s, [&](hipStream_t st) {
-                vcycle(c, nb, vc_prec, Vj, Zj, st);
+                vcycle(c, nb, vc_prec, Vj, Zj, st, vscale);
                 op_apply(c, nb, op_prec, Zj, nullptr, Vn, st, HDG_KERNEL_APPLY);
                 dots(c, nb, j + 1, c->kV, vs, Vn, c->hcol, st);
                 hdg::launch_gs_norm_givens(n, nb, j + 1, c->hcol, c->kV, vs, Vn, c->red, scal(c, SC_HN), j, R, c->gm,
                                            c->dbn, lag_dev(c, slot), st);
-                hdg::launch_scale_inv(n, nb, scal(c, SC_HN), Vn, Vn, st);
                 check_launch();
             });
             mark_lag(c, slot, s);
@@ -524,12 +529,12 @@ void setup_impl(const hdg_mesh *levels, int nlev, const int32_t *const *parents,
     c->facet_vert = dev_upload(c, c->topo.facet_vert);
     const int m = c->m;
     c->nbr = dev_alloc<int32_t>(c, (size_t)4 * ne);
-    c->S64 = dev_alloc<double>(c, (size_t)5 * m * m * ne);
-    c->T64 = dev_alloc<double>(c, (size_t)4 * m * m * ne);
-    c->Dw64 = dev_alloc<double>(c, (size_t)m * m * ne);
-    c->S32 = dev_alloc<float>(c, (size_t)5 * m * m * ne);
-    c->T16 = dev_alloc<__hip_bfloat16>(c, (size_t)4 * m * m * ne);
-    c->Dw32 = dev_alloc<float>(c, (size_t)m * m * ne);
+    c->S64 = dev_alloc<double>(c, (size_t)hdg::wide_padded(5 * m * m, 2) * ne);
+    c->T64 = dev_alloc<double>(c, (size_t)hdg::wide_padded(4 * m * m, 2) * ne);
+    c->Dw64 = dev_alloc<double>(c, (size_t)hdg::wide_padded(m * m, 2) * ne);
+    c->S32 = dev_alloc<float>(c, (size_t)hdg::wide_padded(5 * m * m, 4) * ne);
+    c->T16 = dev_alloc<__hip_bfloat16>(c, (size_t)hdg::wide_padded(4 * m * m, 8) * ne);
+    c->Dw32 = dev_alloc<float>(c, (size_t)hdg::wide_padded(m * m, 4) * ne);
     hdg::launch_facet_rows(c->p, ne, nk, Sloc, d_fcell, d_floc, c->cell_facet, c->cell_rev, opt.omega, c->S64,
                            c->T64, c->Dw64, c->S32, c->T16, c->Dw32, c->nbr, d_err, s);
     check_launch();
@@ -571,9 +576,22 @@ void setup_impl(const hdg_mesh *levels, int nlev, const int32_t *const *parents,
             HDG_REQUIRE(P.diag[v] > 0, "P1 operator has a non-positive diagonal");
             dinv[v] = 1.0 / P.diag[v];
         }
-        L.rowptr = dev_upload(c, P.rowptr);
-        L.col = dev_upload(c, P.col);
-        L.val = dev_upload(c, P.val);
+        {
+            int W = 0;
+            for (int vv = 0; vv < L.n; ++vv) W = std::max(W, P.rowptr[vv + 1] - P.rowptr[vv]);
+            std::vector<int32_t> ec((size_t)std::max(W, 1) * L.n);
+            std::vector<double> ev((size_t)std::max(W, 1) * L.n, 0.0);
+            for (int vv = 0; vv < L.n; ++vv)
+                for (int k = 0; k < W; ++k) {
+                    const int q = P.rowptr[vv] + k;
+                    const bool in = q < P.rowptr[vv + 1];
+                    ec[(size_t)k * L.n + vv] = in ? P.col[q] : vv;
+                    ev[(size_t)k * L.n + vv] = in ? P.val[q] : 0.0;
+                }
+            L.w = W;
+            L.col = dev_upload(c, ec);
+            L.val = dev_upload(c, ev);
+        }
         L.diag = dev_upload(c, P.diag);
         L.dinv = dev_upload(c, dinv);
         L.b = dev_alloc<double>(c, (size_t)L.n * mr);
@@ -627,7 +645,7 @@ void setup_impl(const hdg_mesh *levels, int nlev, const int32_t *const *parents,
         T.Ainv = c->coarse_inv;
         for (int l = 0; l <= c->tail_top; ++l) {
             const hdg::P1LevelDev &L = c->lev[l];
-            T.lev[l] = hdg::P1Lev{L.n, L.rowptr, L.col, L.val, L.diag, L.dinv, L.parents, L.crow, L.ccol, L.cw,
+            T.lev[l] = hdg::P1Lev{L.n, L.w, L.col, L.val, L.diag, L.dinv, L.parents, L.crow, L.ccol, L.cw,
                                   L.b, L.x, L.y};
         }
     }

@@ -77,8 +77,8 @@ bool spd_inverse(std::vector<double> &a, int n);
 
 // ------------------------------------------------------------------ context
 struct P1LevelDev {
-    int n = 0;
-    int32_t *rowptr = nullptr, *col = nullptr;
+    int n = 0, w = 0;                              // vertices, ELL width (max off-diagonals per row)
+    int32_t *col = nullptr;                        // ELL [w][n]
     double *val = nullptr, *diag = nullptr, *dinv = nullptr;
     int32_t *parents = nullptr;                    // [n][2] into the coarser level (level > 0)
     int32_t *crow = nullptr, *ccol = nullptr;      // children CSR of the coarser level (restriction)
@@ -90,8 +90,8 @@ constexpr int P1_TAIL_MAX = 4096;   // levels up to this many vertices run in th
 constexpr int P1_TAIL_LEVELS = 8;
 
 struct P1Lev {
-    int n;
-    const int *rowptr, *col;
+    int n, w;
+    const int *col;
     const double *val, *diag, *dinv;
     const int *parents;                      // into level - 1
     const int *crow, *ccol;                  // children of the level - 1 vertices

@@ -5,6 +5,9 @@
 
 namespace hdg {
 
+// padded component count of a facet-row matrix stored with v entries per 16 bytes
+constexpr int wide_padded(int c, int v) { return (c + v - 1) / v * v; }
+
 struct CellParams {
     double kappa, tau, dt, f0, omega, hscale;
     int geom;
@@ -21,7 +24,8 @@ template <typename MT>
 void launch_trace_apply(int p, int ne, int nb, const MT *S, const int *nbr, const double *x, const double *b,
                         double *y, hipStream_t s);
 template <typename MT>
-void launch_jacobi0(int p, int ne, int nb, const MT *Dw, const double *r, double *z0, hipStream_t s);
+void launch_jacobi0(int p, int ne, int nb, const MT *Dw, const double *r, const double *scale, double *rs,
+                    double *z0, hipStream_t s);
 template <typename MT>
 void launch_sweep(int p, int ne, int nb, const MT *T, const int *nbr, const double *x, const double *z0,
                   const double *qc, const int *fvert, double omega, double *y, hipStream_t s);
@@ -29,12 +33,12 @@ void launch_restrict_trace(int p, int nv, int nb, const int *vf_row, const int *
                            double *rc, hipStream_t s);
 
 void launch_p1_first(int n, int nb, const double *dinv, double omega, const double *b, double *x, hipStream_t s);
-void launch_p1_pre2(int n, int nb, const int *rowptr, const int *col, const double *val, const double *diag,
+void launch_p1_pre2(int n, int W, int nb, const int *col, const double *val, const double *diag,
                     const double *dinv, double omega, const double *b, double *x, hipStream_t s);
-void launch_p1_sweep(int n, int nb, const int *rowptr, const int *col, const double *val, const double *diag,
+void launch_p1_sweep(int n, int W, int nb, const int *col, const double *val, const double *diag,
                      const double *dinv, double omega, const double *b, const double *x, const double *xc,
                      const int *parents, double *y, hipStream_t s);
-void launch_p1_resid(int n, int nb, const int *rowptr, const int *col, const double *val, const double *diag,
+void launch_p1_resid(int n, int W, int nb, const int *col, const double *val, const double *diag,
                      const double *b, const double *x, double *y, hipStream_t s);
 void launch_p1_restrict(int nc, int nb, const int *crow, const int *ccol, const double *cw, const double *r,
                         double *bc, hipStream_t s);

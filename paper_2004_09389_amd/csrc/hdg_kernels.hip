@@ -16,6 +16,47 @@ __device__ __forceinline__ float ldm(const __hip_bfloat16 *p) { return __bfloat1
 template <typename MT> struct Acc { using type = float; };
 template <> struct Acc<double> { using type = double; };
 
+// Facet-row matrices are stored as [component / V][n_facet][V] with V the
+// number of entries in 16 bytes (2 FP64, 4 FP32, 8 BF16), components padded
+// with zeros to a multiple of V: a lane fetches V consecutive components of
+// its facet with one 16-byte load and a wavefront reads 1 KiB contiguously.
+__host__ __device__ constexpr int padded(int c, int v) { return (c + v - 1) / v * v; }
+__device__ __forceinline__ size_t widx(int c, int e, size_t ne, int v) {
+    return ((size_t)(c / v) * ne + e) * v + (c % v);
+}
+
+typedef double dbl2_t __attribute__((ext_vector_type(2)));
+typedef float flt4_t __attribute__((ext_vector_type(4)));
+typedef unsigned u32x4_t __attribute__((ext_vector_type(4)));
+
+template <typename MT> struct Wide;
+template <> struct Wide<double> {
+    static constexpr int V = 2;
+    __device__ static void load(const double *p, double (&o)[2]) {
+        const dbl2_t v = __builtin_nontemporal_load(reinterpret_cast<const dbl2_t *>(p));
+        o[0] = v.x; o[1] = v.y;
+    }
+};
+template <> struct Wide<float> {
+    static constexpr int V = 4;
+    __device__ static void load(const float *p, float (&o)[4]) {
+        const flt4_t v = __builtin_nontemporal_load(reinterpret_cast<const flt4_t *>(p));
+        o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+    }
+};
+template <> struct Wide<__hip_bfloat16> {
+    static constexpr int V = 8;
+    __device__ static void load(const __hip_bfloat16 *p, float (&o)[8]) {
+        const u32x4_t v = __builtin_nontemporal_load(reinterpret_cast<const u32x4_t *>(p));
+        const unsigned w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            o[2 * i] = __uint_as_float(w[i] << 16);
+            o[2 * i + 1] = __uint_as_float(w[i] & 0xffff0000u);
+        }
+    }
+};
+
 // ------------------------------------------------------------------ setup: per-cell condensation
 //
 // One wavefront per cell.  The local HDG blocks (Eq. ABCMform) are assembled
@@ -291,24 +332,37 @@ __global__ void k_facet_rows(int ne, int nk, const double *__restrict__ Sloc, co
     }
     for (int a = 0; a < m; ++a)
         for (int b = 0; b < m; ++b) {
-            const size_t o = (size_t)(a * m + b) * NE + e;
-            S64[o] = D[a][b];
-            S32[o] = (float)D[a][b];
-            Dw64[o] = omega * Di[a][b];
-            Dw32[o] = (float)(omega * Di[a][b]);
+            const int c = a * m + b;
+            S64[widx(c, e, NE, 2)] = D[a][b];
+            S32[widx(c, e, NE, 4)] = (float)D[a][b];
+            Dw64[widx(c, e, NE, 2)] = omega * Di[a][b];
+            Dw32[widx(c, e, NE, 4)] = (float)(omega * Di[a][b]);
         }
     for (int j = 0; j < 4; ++j)
         for (int a = 0; a < m; ++a)
             for (int b = 0; b < m; ++b) {
                 double t = 0.0;
                 for (int c = 0; c < m; ++c) t += Di[a][c] * Off[j][c][b];
-                const size_t os = (size_t)(((j + 1) * m + a) * m + b) * NE + e;
-                const size_t ot = (size_t)((j * m + a) * m + b) * NE + e;
-                S64[os] = Off[j][a][b];
-                S32[os] = (float)Off[j][a][b];
-                T64[ot] = omega * t;
-                T16[ot] = __float2bfloat16((float)(omega * t));
+                const int cs = ((j + 1) * m + a) * m + b;
+                const int ct = (j * m + a) * m + b;
+                S64[widx(cs, e, NE, 2)] = Off[j][a][b];
+                S32[widx(cs, e, NE, 4)] = (float)Off[j][a][b];
+                T64[widx(ct, e, NE, 2)] = omega * t;
+                T16[widx(ct, e, NE, 8)] = __float2bfloat16((float)(omega * t));
             }
+    // zero the padding up to a whole 16-byte group
+    for (int c = 5 * m * m; c < padded(5 * m * m, 4); ++c) {
+        if (c < padded(5 * m * m, 2)) S64[widx(c, e, NE, 2)] = 0.0;
+        S32[widx(c, e, NE, 4)] = 0.f;
+    }
+    for (int c = m * m; c < padded(m * m, 4); ++c) {
+        if (c < padded(m * m, 2)) Dw64[widx(c, e, NE, 2)] = 0.0;
+        Dw32[widx(c, e, NE, 4)] = 0.f;
+    }
+    for (int c = 4 * m * m; c < padded(4 * m * m, 8); ++c) {
+        if (c < padded(4 * m * m, 2)) T64[widx(c, e, NE, 2)] = 0.0;
+        T16[widx(c, e, NE, 8)] = __float2bfloat16(0.f);
+    }
 }
 
 // ------------------------------------------------------------------ trace-level operators
@@ -322,6 +376,7 @@ __global__ __launch_bounds__(256) void k_trace_apply(int ne, int nb, const MT *_
                                                      const int *__restrict__ nbr, const double *__restrict__ x,
                                                      const double *__restrict__ b, double *__restrict__ y) {
     using AT = typename Acc<MT>::type;
+    constexpr int V = Wide<MT>::V, C = 5 * M * M, G = padded(C, V) / V;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= ne * nb) return;
     const int e = t / nb, r = t - e * nb;
@@ -335,37 +390,65 @@ __global__ __launch_bounds__(256) void k_trace_apply(int ne, int nb, const MT *_
     for (int j = 0; j < 5; ++j)
 #pragma unroll
         for (int k = 0; k < M; ++k) xv[j][k] = (AT)x[((size_t)id[j] * M + k) * nb + r];
+    AT acc[M];
+#pragma unroll
+    for (int a = 0; a < M; ++a) acc[a] = 0;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        AT w[V];
+        Wide<MT>::load(S + ((size_t)g * NE + e) * V, w);
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const int c = g * V + v;
+            if (c < C) {
+                const int j = c / (M * M), a = (c / M) % M, k = c % M;
+                acc[a] += w[v] * xv[j][k];
+            }
+        }
+    }
 #pragma unroll
     for (int a = 0; a < M; ++a) {
-        AT acc = 0;
-#pragma unroll
-        for (int j = 0; j < 5; ++j)
-#pragma unroll
-            for (int k = 0; k < M; ++k) acc += (AT)ldm(S + (size_t)((j * M + a) * M + k) * NE + e) * xv[j][k];
         const size_t o = ((size_t)e * M + a) * nb + r;
-        y[o] = b ? b[o] - (double)acc : (double)acc;   // b != nullptr: residual b - S x
+        y[o] = b ? b[o] - (double)acc[a] : (double)acc[a];   // b != nullptr: residual b - S x
     }
 }
 
-// z0 = omega D^-1 r  (first sweep from a zero guess)
+// z0 = omega D^-1 r  (first sweep from a zero guess).  With scale != nullptr
+// the input is r / scale[rhs], and the scaled input is also written to rs
+// (normalisation of a Krylov basis vector fused into its first use).
 template <int M, typename MT>
 __global__ __launch_bounds__(256) void k_jacobi0(int ne, int nb, const MT *__restrict__ Dw,
-                                                 const double *__restrict__ r, double *__restrict__ z0) {
+                                                 const double *__restrict__ r, const double *__restrict__ scale,
+                                                 double *__restrict__ rs, double *__restrict__ z0) {
     using AT = typename Acc<MT>::type;
+    constexpr int V = Wide<MT>::V, C = M * M, G = padded(C, V) / V;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= ne * nb) return;
     const int e = t / nb, rr = t - e * nb;
     const size_t NE = (size_t)ne;
-    AT rv[M];
+    double rv[M];
+    const double sc = scale ? (scale[rr] != 0.0 ? 1.0 / scale[rr] : 0.0) : 1.0;
 #pragma unroll
-    for (int k = 0; k < M; ++k) rv[k] = (AT)r[((size_t)e * M + k) * nb + rr];
-#pragma unroll
-    for (int a = 0; a < M; ++a) {
-        AT acc = 0;
-#pragma unroll
-        for (int k = 0; k < M; ++k) acc += (AT)ldm(Dw + (size_t)(a * M + k) * NE + e) * rv[k];
-        z0[((size_t)e * M + a) * nb + rr] = (double)acc;
+    for (int k = 0; k < M; ++k) {
+        const size_t o = ((size_t)e * M + k) * nb + rr;
+        rv[k] = r[o] * sc;
+        if (scale) rs[o] = rv[k];
     }
+    AT acc[M];
+#pragma unroll
+    for (int a = 0; a < M; ++a) acc[a] = 0;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        AT w[V];
+        Wide<MT>::load(Dw + ((size_t)g * NE + e) * V, w);
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const int c = g * V + v;
+            if (c < C) acc[c / M] += w[v] * (AT)rv[c % M];
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < M; ++a) z0[((size_t)e * M + a) * nb + rr] = (double)acc[a];
 }
 
 // Block-Jacobi sweep  y = x + omega D^-1 (r - S x) = (1 - omega) x + z0 - sum_j T_j x_j,
@@ -380,6 +463,7 @@ __global__ __launch_bounds__(256) void k_sweep(int ne, int nb, const MT *__restr
                                                double *__restrict__ y) {
     using AT = typename Acc<MT>::type;
     constexpr int P = M - 1;
+    constexpr int V = Wide<MT>::V, C = 4 * M * M, G = padded(C, V) / V;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= ne * nb) return;
     const int e = t / nb, r = t - e * nb;
@@ -400,16 +484,26 @@ __global__ __launch_bounds__(256) void k_sweep(int ne, int nb, const MT *__restr
             for (int k = 0; k < M; ++k) xv[j][k] += (1.0 - (double)k / P) * q0 + ((double)k / P) * q1;
         }
     }
+    AT acc[M];
+#pragma unroll
+    for (int a = 0; a < M; ++a) acc[a] = 0;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        AT w[V];
+        Wide<MT>::load(T + ((size_t)g * NE + e) * V, w);
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const int c = g * V + v;
+            if (c < C) {
+                const int j = c / (M * M), a = (c / M) % M, k = c % M;
+                acc[a] += w[v] * (AT)xv[j + 1][k];
+            }
+        }
+    }
 #pragma unroll
     for (int a = 0; a < M; ++a) {
-        AT acc = 0;
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-#pragma unroll
-            for (int k = 0; k < M; ++k)
-                acc += (AT)ldm(T + (size_t)((j * M + a) * M + k) * NE + e) * (AT)xv[j + 1][k];
         const size_t o = ((size_t)e * M + a) * nb + r;
-        y[o] = (1.0 - omega) * xv[0][a] + z0[o] - (double)acc;
+        y[o] = (1.0 - omega) * xv[0][a] + z0[o] - (double)acc[a];
     }
 }
 
@@ -443,10 +537,13 @@ __global__ void k_restrict_trace(int nv, int nb, const int *__restrict__ vf_row,
 // P1_TAIL_MAX vertices (and the dense solve) run inside one single-workgroup
 // kernel, because at that size a launch costs more than the work.
 
-__device__ __forceinline__ double p1_ax(int v, int nb, int r, const int *rowptr, const int *col,
-                                        const double *val, const double *diag, const double *x) {
+// Level matrices are stored off-diagonal in ELL form, [W][n] column-major
+// (padding entries point at the row itself with value 0), so the neighbour
+// indices of a row are independent coalesced loads.
+__device__ __forceinline__ double p1_ax(int v, int n, int W, int nb, int r, const int *ell_col,
+                                        const double *ell_val, const double *diag, const double *x) {
     double s = diag[v] * x[(size_t)v * nb + r];
-    for (int c = rowptr[v]; c < rowptr[v + 1]; ++c) s += val[c] * x[(size_t)col[c] * nb + r];
+    for (int k = 0; k < W; ++k) s += ell_val[(size_t)k * n + v] * x[(size_t)ell_col[(size_t)k * n + v] * nb + r];
     return s;
 }
 
@@ -458,27 +555,25 @@ __global__ void k_p1_first(int n, int nb, const double *__restrict__ dinv, doubl
 }
 
 // two sweeps from a zero guess: x1 = w D^-1 b, x2 = x1 + w D^-1 (b - A x1)
-__global__ void k_p1_pre2(int n, int nb, const int *__restrict__ rowptr, const int *__restrict__ col,
-                          const double *__restrict__ val, const double *__restrict__ diag,
-                          const double *__restrict__ dinv, double omega, const double *__restrict__ b,
-                          double *__restrict__ x) {
+__global__ void k_p1_pre2(int n, int W, int nb, const int *__restrict__ ell_col, const double *__restrict__ ell_val,
+                          const double *__restrict__ diag, const double *__restrict__ dinv, double omega,
+                          const double *__restrict__ b, double *__restrict__ x) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n * nb) return;
     const int v = t / nb, r = t - v * nb;
     double ax = diag[v] * omega * dinv[v] * b[t];
-    for (int c = rowptr[v]; c < rowptr[v + 1]; ++c) {
-        const int u = col[c];
-        ax += val[c] * omega * dinv[u] * b[(size_t)u * nb + r];
+    for (int k = 0; k < W; ++k) {
+        const int u = ell_col[(size_t)k * n + v];
+        ax += ell_val[(size_t)k * n + v] * omega * dinv[u] * b[(size_t)u * nb + r];
     }
     const double x1 = omega * dinv[v] * b[t];
     x[t] = x1 + omega * dinv[v] * (b[t] - ax);
 }
 
 // y = x + w D^-1 (b - A x); with xc != nullptr the input is x + P xc (prolongation fused)
-__global__ void k_p1_sweep(int n, int nb, const int *__restrict__ rowptr, const int *__restrict__ col,
-                           const double *__restrict__ val, const double *__restrict__ diag,
-                           const double *__restrict__ dinv, double omega, const double *__restrict__ b,
-                           const double *__restrict__ x, const double *__restrict__ xc,
+__global__ void k_p1_sweep(int n, int W, int nb, const int *__restrict__ ell_col, const double *__restrict__ ell_val,
+                           const double *__restrict__ diag, const double *__restrict__ dinv, double omega,
+                           const double *__restrict__ b, const double *__restrict__ x, const double *__restrict__ xc,
                            const int *__restrict__ parents, double *__restrict__ y) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n * nb) return;
@@ -489,19 +584,19 @@ __global__ void k_p1_sweep(int n, int nb, const int *__restrict__ rowptr, const 
         return s;
     };
     double ax = 0.0;
-    for (int c = rowptr[v]; c < rowptr[v + 1]; ++c) ax += val[c] * xin(col[c]);
+    for (int k = 0; k < W; ++k) ax += ell_val[(size_t)k * n + v] * xin(ell_col[(size_t)k * n + v]);
     const double xv = xin(v);
     ax += diag[v] * xv;
     y[t] = xv + omega * dinv[v] * (b[t] - ax);
 }
 
-__global__ void k_p1_resid(int n, int nb, const int *__restrict__ rowptr, const int *__restrict__ col,
-                           const double *__restrict__ val, const double *__restrict__ diag,
-                           const double *__restrict__ b, const double *__restrict__ x, double *__restrict__ y) {
+__global__ void k_p1_resid(int n, int W, int nb, const int *__restrict__ ell_col, const double *__restrict__ ell_val,
+                           const double *__restrict__ diag, const double *__restrict__ b, const double *__restrict__ x,
+                           double *__restrict__ y) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n * nb) return;
     const int v = t / nb, r = t - v * nb;
-    y[t] = b[t] - p1_ax(v, nb, r, rowptr, col, val, diag, x);
+    y[t] = b[t] - p1_ax(v, n, W, nb, r, ell_col, ell_val, diag, x);
 }
 
 // bc[c] = sum over children of w * r[child]  (transpose of the interpolation)
@@ -548,14 +643,14 @@ __global__ __launch_bounds__(1024) void k_p1_tail(const P1Tail Targ, int nb) {
         for (int k = 1; k < T.nu; ++k) {
             for (int t = tid; t < N; t += nth) {
                 const int v = t / nb, r = t - v * nb;
-                y[t] = x[t] + w * L.dinv[v] * (L.b[t] - p1_ax(v, nb, r, L.rowptr, L.col, L.val, L.diag, x));
+                y[t] = x[t] + w * L.dinv[v] * (L.b[t] - p1_ax(v, L.n, L.w, nb, r, L.col, L.val, L.diag, x));
             }
             __syncthreads();
             double *tmp = x; x = y; y = tmp;
         }
         for (int t = tid; t < N; t += nth) {
             const int v = t / nb, r = t - v * nb;
-            y[t] = L.b[t] - p1_ax(v, nb, r, L.rowptr, L.col, L.val, L.diag, x);
+            y[t] = L.b[t] - p1_ax(v, L.n, L.w, nb, r, L.col, L.val, L.diag, x);
         }
         __syncthreads();
         const P1Lev &C = T.lev[l - 1];
@@ -595,7 +690,7 @@ __global__ __launch_bounds__(1024) void k_p1_tail(const P1Tail Targ, int nb) {
                     return s;
                 };
                 double ax = 0.0;
-                for (int c = L.rowptr[v]; c < L.rowptr[v + 1]; ++c) ax += L.val[c] * xin(L.col[c]);
+                for (int k = 0; k < L.w; ++k) ax += L.val[(size_t)k * L.n + v] * xin(L.col[(size_t)k * L.n + v]);
                 const double xv = xin(v);
                 ax += L.diag[v] * xv;
                 y[t] = xv + w * L.dinv[v] * (L.b[t] - ax);
@@ -978,13 +1073,16 @@ template void launch_trace_apply<double>(int, int, int, const double *, const in
 template void launch_trace_apply<float>(int, int, int, const float *, const int *, const double *, const double *, double *, hipStream_t);
 
 template <typename MT>
-void launch_jacobi0(int p, int ne, int nb, const MT *Dw, const double *r, double *z0, hipStream_t s) {
-#define J0(P) hipLaunchKernelGGL((k_jacobi0<P + 1, MT>), GRID(ne * nb, 256), 0, s, ne, nb, Dw, r, z0)
+void launch_jacobi0(int p, int ne, int nb, const MT *Dw, const double *r, const double *scale, double *rs,
+                    double *z0, hipStream_t s) {
+#define J0(P) hipLaunchKernelGGL((k_jacobi0<P + 1, MT>), GRID(ne * nb, 256), 0, s, ne, nb, Dw, r, scale, rs, z0)
     switch (p) { case 1: J0(1); break; case 2: J0(2); break; case 3: J0(3); break; }
 #undef J0
 }
-template void launch_jacobi0<double>(int, int, int, const double *, const double *, double *, hipStream_t);
-template void launch_jacobi0<float>(int, int, int, const float *, const double *, double *, hipStream_t);
+template void launch_jacobi0<double>(int, int, int, const double *, const double *, const double *, double *,
+                                     double *, hipStream_t);
+template void launch_jacobi0<float>(int, int, int, const float *, const double *, const double *, double *,
+                                    double *, hipStream_t);
 
 template <typename MT>
 void launch_sweep(int p, int ne, int nb, const MT *T, const int *nbr, const double *x, const double *z0,
@@ -1006,19 +1104,19 @@ void launch_restrict_trace(int p, int nv, int nb, const int *vf_row, const int *
 void launch_p1_first(int n, int nb, const double *dinv, double omega, const double *b, double *x, hipStream_t s) {
     hipLaunchKernelGGL(k_p1_first, GRID(n * nb, 256), 0, s, n, nb, dinv, omega, b, x);
 }
-void launch_p1_pre2(int n, int nb, const int *rowptr, const int *col, const double *val, const double *diag,
+void launch_p1_pre2(int n, int W, int nb, const int *col, const double *val, const double *diag,
                     const double *dinv, double omega, const double *b, double *x, hipStream_t s) {
-    hipLaunchKernelGGL(k_p1_pre2, GRID(n * nb, 256), 0, s, n, nb, rowptr, col, val, diag, dinv, omega, b, x);
+    hipLaunchKernelGGL(k_p1_pre2, GRID(n * nb, 256), 0, s, n, W, nb, col, val, diag, dinv, omega, b, x);
 }
-void launch_p1_sweep(int n, int nb, const int *rowptr, const int *col, const double *val, const double *diag,
+void launch_p1_sweep(int n, int W, int nb, const int *col, const double *val, const double *diag,
                      const double *dinv, double omega, const double *b, const double *x, const double *xc,
                      const int *parents, double *y, hipStream_t s) {
-    hipLaunchKernelGGL(k_p1_sweep, GRID(n * nb, 256), 0, s, n, nb, rowptr, col, val, diag, dinv, omega, b, x, xc,
+    hipLaunchKernelGGL(k_p1_sweep, GRID(n * nb, 256), 0, s, n, W, nb, col, val, diag, dinv, omega, b, x, xc,
                        parents, y);
 }
-void launch_p1_resid(int n, int nb, const int *rowptr, const int *col, const double *val, const double *diag,
+void launch_p1_resid(int n, int W, int nb, const int *col, const double *val, const double *diag,
                      const double *b, const double *x, double *y, hipStream_t s) {
-    hipLaunchKernelGGL(k_p1_resid, GRID(n * nb, 256), 0, s, n, nb, rowptr, col, val, diag, b, x, y);
+    hipLaunchKernelGGL(k_p1_resid, GRID(n * nb, 256), 0, s, n, W, nb, col, val, diag, b, x, y);
 }
 void launch_p1_restrict(int nc, int nb, const int *crow, const int *ccol, const double *cw, const double *r,
                         double *bc, hipStream_t s) {
