@@ -29,6 +29,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E peak
+TIMING_REPEAT = 8       # back-to-back launches per event pair in the instrumented pass
 
 
 def parse():
@@ -48,11 +49,31 @@ def parse():
     ap.add_argument("--mixed-mode", default="mixed", choices=["mixed", "mixed_ir"],
                     help="mixed: FP64 Krylov + reduced-precision V-cycle; mixed_ir: FP64 refinement of an FP32 inner solve")
     ap.add_argument("--no-graph", action="store_true", help="launch every kernel eagerly (no HIP graphs)")
+    ap.add_argument("--batch", type=int, default=16, help="also time a batch of this many right-hand sides")
+    ap.add_argument("--pmc-run", action="store_true",
+                    help="short run for hardware counters: mixed leg only, plus a reference copy kernel")
     return ap.parse_args()
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def measured_traffic(kernel_label):
+    """HBM bytes per launch of `kernel_label` from the committed rocprofv3 counter
+    summaries (FETCH_SIZE, WRITE_SIZE scaled by a reference copy), or None when
+    no summary covers it or the kernel source changed since the counters were taken."""
+    import glob
+    import hashlib
+    src = os.path.join(ROOT, "paper_2004_09389_amd", "csrc", "hdg_kernels.hip")
+    cur = hashlib.sha1(open(src, "rb").read()).hexdigest()[:12]
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "hbm_traffic_*.md"))):
+        for line in open(path):
+            f = line.split()
+            if len(f) == 5 and f[0] == "traffic_bytes_per_launch" and f[1] == kernel_label and f[3] == "kernels_sha1":
+                if f[4] == cur:
+                    return float(f[2]), os.path.relpath(path, ROOT)
+    return None
 
 
 def cpu_baseline(n_full, p, dt):
@@ -82,6 +103,8 @@ def cpu_baseline(n_full, p, dt):
 
 def main():
     args = parse()
+    if args.pmc_run:
+        args.no_fp64, args.no_cpu, args.batch = True, True, 0
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; a multi-GPU run is not provided "
                                    "(right-hand sides would shard across GPUs with no communication)"}))
@@ -102,9 +125,10 @@ def main():
     log(f"[bench] mesh+rhs {time.perf_counter() - t0:.1f}s cells={mesh.n_cell} p={p} nrhs={nb}")
     rd = torch.from_numpy(r).to("cuda")
 
-    def make(prec):
+    def make(prec, nb_override=None):
         t = time.perf_counter()
-        s = HdgSolver(hier, p, dt, 1.0, 1.0, 1.0, 0.0, 1.0, rtol=args.rtol, precision=prec, max_rhs=nb,
+        s = HdgSolver(hier, p, dt, 1.0, 1.0, 1.0, 0.0, 1.0, rtol=args.rtol, precision=prec,
+                      max_rhs=nb_override or nb,
                       krylov=2, maxit=200, p1_tail_max=args.tail_max, p1_nu=args.p1_nu,
                       use_graph=0 if args.no_graph else 1)
         torch.cuda.synchronize()
@@ -112,20 +136,22 @@ def main():
             f"device={s.sizes.device_bytes / 2**30:.2f} GiB")
         return s, time.perf_counter() - t
 
-    def run(s, steps, timing=False):
-        lam = s.trace_zeros(nb)
-        rhat = s.trace_zeros(nb)
-        q = s.cell_zeros(nb)
+    def run(s, steps, timing=0, rhs=None, nbb=None):
+        rhs = rd if rhs is None else rhs
+        nbb = nb if nbb is None else nbb
+        lam = s.trace_zeros(nbb)
+        rhat = s.trace_zeros(nbb)
+        q = s.cell_zeros(nbb)
         infos = []
         if timing:
-            s.set_timing(True)
+            s.set_timing(timing)
         torch.cuda.synchronize()
         t = time.perf_counter()
         for _ in range(steps):
-            s.condense(rd, out=rhat)
+            s.condense(rhs, out=rhat)
             lam.zero_()
             _, info = s.solve(rhat, lam)
-            s.recover(rd, lam, out=q)
+            s.recover(rhs, lam, out=q)
             infos.append(info)
         torch.cuda.synchronize()
         el = time.perf_counter() - t
@@ -134,37 +160,74 @@ def main():
     results = {}
     mixed_prec = HDG_MIXED if args.mixed_mode == "mixed" else HDG_MIXED_IR
     legs = [("mixed", mixed_prec)] + ([] if args.no_fp64 else [("fp64", HDG_FP64)])
+    classes = ("apply", "sweep", "residual", "condense", "recover")
     for name, prec in legs:
         s, tsetup = make(prec)
         run(s, args.warmup)
-        el, infos, lam, q = run(s, args.steps, timing=(name == "mixed" and args.no_graph))
+        el, infos, lam, q = run(s, args.steps)
         its = [i.iters for inf in infos for i in inf]
         res = max(i.rel_res for inf in infos for i in inf)
-        stats = {k: s.kernel_stats(k, min(prec, HDG_MIXED)) for k in ("apply", "sweep", "residual", "condense", "recover")}
-        results[name] = dict(el=el, its=float(np.mean(its)), res=res, lam=lam.clone(), setup=tsetup,
-                             stats=stats, refinements=float(np.mean([i.refinements for inf in infos for i in inf])))
+        rec = dict(el=el, its=float(np.mean(its)), res=res, lam=lam.clone(), setup=tsetup,
+                   refinements=float(np.mean([i.refinements for inf in infos for i in inf])))
+        if name == "mixed":
+            # instrumented pass: the same steps again, every launch of the
+            # instrumented kernel classes bracketed by HIP events on its stream
+            run(s, args.steps, timing=TIMING_REPEAT)
+            rec["stats"] = {(k, pr): s.kernel_stats(k, pr) for k in classes for pr in (HDG_FP64, HDG_MIXED)}
+            s.set_timing(False)
+        if args.batch > 1 and not args.pmc_run:
+            sb, _ = make(prec, nb_override=args.batch)
+            rb = torch.from_numpy(hi.fourier_rhs_torus(mesh, p, 200, nrhs=args.batch)).to("cuda")
+            run(sb, args.warmup, rhs=rb, nbb=args.batch)
+            elb, infb, _, _ = run(sb, args.steps, rhs=rb, nbb=args.batch)
+            rec["batched"] = {"nrhs": args.batch, "value": round(args.steps * args.batch / elb, 3),
+                              "ms_per_step": round(1e3 * elb / args.steps, 4),
+                              "iters": float(np.mean([i.iters for inf in infb for i in inf])),
+                              "rel_res_max": max(i.rel_res for inf in infb for i in inf)}
+            sb.close()
+            del sb
+        results[name] = rec
         log(f"[bench] {name}: {args.steps} steps in {el:.3f}s ({1e3 * el / args.steps:.3f} ms/step) "
-            f"iters={np.mean(its):.1f} rel_res<={res:.2e}")
+            f"iters={np.mean(its):.1f} rel_res<={res:.2e}"
+            + (f" | batch {args.batch}: {rec['batched']['value']:.1f} solves/s" if "batched" in rec else ""))
         s.close()
         del s
+
+    if args.pmc_run:
+        # reference copy of known size for scaling the profiler's byte counters
+        n_copy = 32 * 1024 * 1024
+        src = torch.ones(n_copy, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        from paper_2004_09389_amd.hdg import device_copy
+        for _ in range(3):
+            device_copy(src, dst)
+        torch.cuda.synchronize()
+        log(f"[bench] reference copy: {n_copy * 8} bytes read, {n_copy * 8} bytes written per launch")
+        return
 
     mx = results["mixed"]
     steps = args.steps
     value = steps * nb / mx["el"]
-    # dominant kernel by total event time during the timed mixed-precision steps
+    # dominant kernel: largest total event time in the instrumented pass
     st = mx["stats"]
     dom = max(st, key=lambda k: st[k][1])
     launches, ms, bpl = st[dom]
     avg_s = ms / max(launches, 1) / 1e3
     achieved = bpl * nb / avg_s / 1e9 if avg_s > 0 else 0.0
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "avg_launch_us": round(avg_s * 1e6, 3), "launches": launches,
-                "bytes_per_launch": bpl * nb}
-    kern = {k: {"launches": v[0], "total_ms": round(v[1], 3),
-                "avg_us": round(1e3 * v[1] / max(v[0], 1), 3),
-                "GBps": round(v[2] * nb / (v[1] / max(v[0], 1) / 1e3) / 1e9, 1) if v[1] > 0 else None}
-            for k, v in st.items()}
+    pname = {HDG_FP64: "fp64", HDG_MIXED: "mixed"}
+    label = f"{dom[0]}[{pname[dom[1]]}]"
+    tr = measured_traffic(label) if (n == 256 and p == 3 and nb == 1) else None
+    roofline = {"bound": "hbm", "kernel": label, "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": tr[0] if tr else None, "traffic_source": tr[1] if tr else None,
+                "avg_launch_us": round(avg_s * 1e6, 3), "launches": launches, "bytes_per_launch": bpl * nb,
+                "timing": f"HIP events on the launch stream around every launch of the kernel in an "
+                          f"instrumented eager pass of the same steps right after the timed (graph-replayed) "
+                          f"pass; each instrumented launch issued {TIMING_REPEAT}x back to back per event pair"}
+    kern = {f"{k}[{pname[pr]}]": {"launches": v[0], "total_ms": round(v[1], 3),
+                                  "avg_us": round(1e3 * v[1] / max(v[0], 1), 3),
+                                  "GBps": round(v[2] * nb / (v[1] / max(v[0], 1) / 1e3) / 1e9, 1) if v[1] > 0 else None}
+            for (k, pr), v in st.items() if v[0] > 0}
     out = {
         "metric": "trace solves/s to 1e-8 rel residual (learned/mixed vs FP64 MG), HBM GB/s",
         "value": round(value, 3),
@@ -181,19 +244,26 @@ def main():
         "config": {"workload": f"torus{n}x{n}_p{p}_f1_courant8", "degree": p, "n_cell": mesh.n_cell,
                    "n_trace_dof": int(3 * (p + 1) * mesh.n_cell // 2),
                    "n_cell_dof": int(3 * (p + 1) * (p + 2) // 2 * mesh.n_cell), "nrhs": nb,
-                   "rtol": args.rtol, "precision": "mixed (fp32 operator, bf16 smoother, fp64 refinement)",
-                   "coarsest_p1": f"{args.coarse}x{args.coarse}", "p1_tail_max": args.tail_max},
+                   "rtol": args.rtol, "precision": args.mixed_mode,
+                   "coarsest_p1": f"{args.coarse}x{args.coarse}", "p1_tail_max": args.tail_max,
+                   "hip_graphs": not args.no_graph},
         "iters": mx["its"],
         "refinements": mx["refinements"],
         "rel_res_max": mx["res"],
+        "dof_per_s": {"trace": round(value * 3 * (p + 1) * mesh.n_cell / 2, 1),
+                      "cell": round(value * 3 * (p + 1) * (p + 2) / 2 * mesh.n_cell, 1)},
         "roofline": roofline,
         "kernels": kern,
     }
+    if "batched" in mx:
+        out["batched"] = mx["batched"]
     if "fp64" in results:
         fp = results["fp64"]
         out["fp64_baseline"] = {"value": round(steps * nb / fp["el"], 3), "unit": "solves/s",
                                 "ms_per_step": round(1e3 * fp["el"] / steps, 4), "iters": fp["its"],
                                 "rel_res_max": fp["res"]}
+        if "batched" in fp:
+            out["fp64_baseline"]["batched"] = fp["batched"]
         out["speedup_vs_fp64"] = round(fp["el"] / mx["el"], 3)
         d = (mx["lam"] - fp["lam"]).norm().item() / fp["lam"].norm().item()
         out["lam_rel_diff_vs_fp64"] = d

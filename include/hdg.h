@@ -198,11 +198,17 @@ const char *hdg_last_error(void);
 
 /* ------------------------------------------------------------------ measurement helpers */
 
-/* Per-kernel-class timing with HIP events on the launch stream.  When enabled,
- * every launch of the instrumented kernels is bracketed by events;
- * hdg_kernel_stats returns, for kernel class id, the launch count and the sum
- * of the event-measured durations (ms) since the last reset, and the number
- * of algorithmic bytes one launch moves per RHS at nrhs = 1.  Synchronous. */
+/* Per-kernel-class timing with HIP events on the launch stream.
+ * hdg_set_timing(ctx, R): R = 0 switches timing off; R >= 1 brackets every
+ * launch of the instrumented kernel classes with a pair of events, issuing
+ * the (idempotent) launch R times back to back in between and counting the
+ * elapsed time divided by R (R > 1 spreads the cost of the event records).
+ * While timing is on, Krylov iterations run eagerly (no graph replay).
+ * hdg_kernel_stats returns, for kernel class id and precision, the launch
+ * count and the summed per-launch duration (ms) since the last
+ * hdg_set_timing call, and the algorithmic bytes one launch moves at
+ * nrhs = 1 (every stored matrix entry once, every vector entry read or
+ * written once, indices once).  Both calls synchronise. */
 #define HDG_KERNEL_APPLY    0   /* y = S x  (facet block rows) */
 #define HDG_KERNEL_SWEEP    1   /* block-Jacobi sweep with the off-diagonal rows */
 #define HDG_KERNEL_RESIDUAL 2   /* r - S x */

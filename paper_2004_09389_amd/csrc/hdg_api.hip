@@ -112,6 +112,10 @@ hipEvent_t pool_event(hdg_ctx *c) {
 }
 
 // Brackets one launch with events on its own stream when timing is enabled.
+// The instrumented launches are idempotent (their outputs never alias their
+// inputs), so with a repeat count R the launch is issued R times back to back
+// between the two events and the duration is divided by R: the per-launch
+// cost of recording the events is spread over R launches.
 struct Timed {
     hdg_ctx *c;
     int kind, prec;
@@ -122,6 +126,7 @@ struct Timed {
         a = pool_event(c);
         HDG_HIP_CHECK(hipEventRecord(a, s));
     }
+    int repeats() const { return a ? c->timing_repeat : 1; }
     ~Timed() {
         if (!a) return;
         hipEvent_t b = pool_event(c);
@@ -136,7 +141,7 @@ void collect_timing(hdg_ctx *c) {
     for (auto &p : c->pending) {
         float ms = 0.f;
         HDG_HIP_CHECK(hipEventElapsedTime(&ms, p.a, p.b));
-        c->t_ms[p.prec][p.kind] += ms;
+        c->t_ms[p.prec][p.kind] += ms / c->timing_repeat;
         c->t_launches[p.prec][p.kind] += 1;
         c->event_pool.push_back(p.a);
         c->event_pool.push_back(p.b);
@@ -150,22 +155,26 @@ void collect_timing(hdg_ctx *c) {
 void op_apply(hdg_ctx *c, int nb, int prec, const double *x, const double *b, double *y, hipStream_t s,
               int kind) {
     Timed t(c, kind, prec, s);
-    if (prec == HDG_MIXED)
-        hdg::launch_trace_apply<float>(c->p, c->n_facet, nb, c->S32, c->nbr, x, b, y, s);
-    else
-        hdg::launch_trace_apply<double>(c->p, c->n_facet, nb, c->S64, c->nbr, x, b, y, s);
+    for (int rep = 0; rep < t.repeats(); ++rep) {
+        if (prec == HDG_MIXED)
+            hdg::launch_trace_apply<float>(c->p, c->n_facet, nb, c->S32, c->nbr, x, b, y, s);
+        else
+            hdg::launch_trace_apply<double>(c->p, c->n_facet, nb, c->S64, c->nbr, x, b, y, s);
+    }
     check_launch();
 }
 
 void op_sweep(hdg_ctx *c, int nb, int prec, const double *x, const double *z0, const double *qc, double *y,
               hipStream_t s) {
     Timed t(c, HDG_KERNEL_SWEEP, prec, s);
-    if (prec == HDG_MIXED)
-        hdg::launch_sweep<__hip_bfloat16>(c->p, c->n_facet, nb, c->T16, c->nbr, x, z0, qc, c->facet_vert,
-                                          c->opt.omega, y, s);
-    else
-        hdg::launch_sweep<double>(c->p, c->n_facet, nb, c->T64, c->nbr, x, z0, qc, c->facet_vert, c->opt.omega,
-                                  y, s);
+    for (int rep = 0; rep < t.repeats(); ++rep) {
+        if (prec == HDG_MIXED)
+            hdg::launch_sweep<__hip_bfloat16>(c->p, c->n_facet, nb, c->T16, c->nbr, x, z0, qc, c->facet_vert,
+                                              c->opt.omega, y, s);
+        else
+            hdg::launch_sweep<double>(c->p, c->n_facet, nb, c->T64, c->nbr, x, z0, qc, c->facet_vert,
+                                      c->opt.omega, y, s);
+    }
     check_launch();
 }
 
@@ -788,7 +797,9 @@ extern "C" int hdg_condense(hdg_ctx *c, int32_t nb, const double *r_cell, double
         HDG_REQUIRE(r_cell && rhat, "r_cell and rhat must not be NULL");
         hipStream_t s = as_stream(stream);
         Timed t(c, HDG_KERNEL_CONDENSE, HDG_FP64, s);
-        hdg::launch_condense(c->p, c->n_cell, c->n_facet, nb, c->Zr, r_cell, c->loc, c->d_fcell, c->d_floc, rhat, s);
+        for (int rep = 0; rep < t.repeats(); ++rep)
+            hdg::launch_condense(c->p, c->n_cell, c->n_facet, nb, c->Zr, r_cell, c->loc, c->d_fcell, c->d_floc, rhat,
+                                 s);
         check_launch();
     });
 }
@@ -850,7 +861,9 @@ extern "C" int hdg_recover(hdg_ctx *c, int32_t nb, const double *r_cell, const d
         HDG_REQUIRE(r_cell && lam && q_cell, "r_cell, lam and q_cell must not be NULL");
         hipStream_t s = as_stream(stream);
         Timed t(c, HDG_KERNEL_RECOVER, HDG_FP64, s);
-        hdg::launch_recover(c->p, c->n_cell, nb, c->Ar, c->Wr, c->cell_facet, c->cell_rev, r_cell, lam, q_cell, s);
+        for (int rep = 0; rep < t.repeats(); ++rep)
+            hdg::launch_recover(c->p, c->n_cell, nb, c->Ar, c->Wr, c->cell_facet, c->cell_rev, r_cell, lam, q_cell,
+                                s);
         check_launch();
     });
 }
@@ -858,8 +871,10 @@ extern "C" int hdg_recover(hdg_ctx *c, int32_t nb, const double *r_cell, const d
 extern "C" int hdg_set_timing(hdg_ctx *c, int32_t enable) {
     if (!c) return HDG_EINVAL;
     return guard([&] {
+        HDG_REQUIRE(enable >= 0 && enable <= 64, "timing repeat count must be in 0..64");
         collect_timing(c);
         c->timing = enable != 0;
+        c->timing_repeat = enable > 0 ? enable : 1;
         std::memset(c->t_ms, 0, sizeof(c->t_ms));
         std::memset(c->t_launches, 0, sizeof(c->t_launches));
     });

@@ -171,6 +171,7 @@ struct hdg_ctx {
         int kind, prec;
     };
     bool timing = false;
+    int timing_repeat = 1;
     std::vector<PendingEvent> pending;
     std::vector<hipEvent_t> event_pool;
 

@@ -258,8 +258,10 @@ class HdgSolver:
         return self.recover(r_cell, lam), lam, info
 
     # ------------------------------------------------------------------ measurement
-    def set_timing(self, enable: bool):
-        _check(self.lib.hdg_set_timing(self.ctx, 1 if enable else 0))
+    def set_timing(self, repeat: int):
+        """repeat = 0: off; repeat >= 1: event-time the instrumented kernels,
+        each launch issued `repeat` times per event pair."""
+        _check(self.lib.hdg_set_timing(self.ctx, int(repeat)))
 
     def kernel_stats(self, kernel: str, precision: int = HDG_FP64):
         n = ctypes.c_int64()
