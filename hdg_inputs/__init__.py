@@ -7,9 +7,9 @@ arithmetic: no quadrature, no basis, no operator, no topology beyond the
 cell->vertex lists that define a mesh.
 """
 from .mesh import Mesh, Hierarchy, torus, torus_hierarchy, icosphere, icosphere_hierarchy
-from .rhs import n_loc, ref_nodes, iid_rhs, fourier_rhs_torus, smooth_rhs_sphere, cell_frames
+from .rhs import n_loc, ref_nodes, iid_rhs, fourier_rhs_torus, smooth_rhs_sphere, cell_frames, mlp_init, iid_trace
 
 __all__ = [
     "Mesh", "Hierarchy", "torus", "torus_hierarchy", "icosphere", "icosphere_hierarchy",
-    "n_loc", "ref_nodes", "iid_rhs", "fourier_rhs_torus", "smooth_rhs_sphere", "cell_frames",
+    "n_loc", "ref_nodes", "iid_rhs", "fourier_rhs_torus", "smooth_rhs_sphere", "cell_frames", "mlp_init", "iid_trace",
 ]

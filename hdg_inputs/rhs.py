@@ -112,3 +112,19 @@ def smooth_rhs_sphere(mesh: Mesh, p: int, seed: int, nrhs: int = 1,
         out[:, 1, :, r] = u1 * (u_scale / umax)
         out[:, 2, :, r] = u2 * (u_scale / umax)
     return out
+
+
+def iid_trace(n_facet: int, p: int, seed: int, nrhs: int = 1) -> np.ndarray:
+    """iid N(0,1) trace vector (n_facet, p+1, nrhs): a random initial error."""
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((n_facet, p + 1, nrhs))
+
+
+def mlp_init(m: int, hidden: int = 64, seed: int = 0):
+    """Initial weights of the learned smoother, drawn from PCG64(seed): first
+    layer He-normal (std sqrt(2 / fan_in)), last layer zero.  (hidden, 5m) and
+    (m, hidden), float64."""
+    rng = np.random.default_rng(seed)
+    W1 = rng.standard_normal((hidden, 5 * m)) * np.sqrt(2.0 / (5 * m))
+    W2 = np.zeros((m, hidden))
+    return W1, W2

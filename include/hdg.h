@@ -196,6 +196,49 @@ int hdg_recover(hdg_ctx *ctx, int32_t nrhs, const double *r_cell, const double *
 void hdg_destroy(hdg_ctx *ctx);
 const char *hdg_last_error(void);
 
+/* ------------------------------------------------------------------ learned smoother
+ *
+ * An extension beyond the paper (whose conclusion names better smoothers as
+ * future work): a small network replaces the block-Jacobi sweep of the
+ * V-cycle.  For facet e the patch is e and the four other facets of its two
+ * cells (the facets of e's block row of S); the features are the
+ * block-Jacobi corrections u = omega D^-1 r on the patch, each slot in the
+ * counter-clockwise direction of the cell it is taken from (slot 0 in e's own
+ * direction), 5(p+1) values, normalised by their RMS s.  Network: h =
+ * ReLU(W1 z), 64 hidden units, y = W2 h, p+1 outputs, no biases; a smoothing
+ * step is x <- x + u_e + s y_e.  Inference and training run in BF16 on the
+ * matrix cores with FP32 accumulation; FP32 master weights, Adam
+ * (beta 0.9, 0.999, eps 1e-8).  The weights start at zero, where the
+ * learned step is the block-Jacobi step.  Selected by opt.smoother =
+ * HDG_SMOOTH_MLP in hdg_setup (FGMRES only; hdg_solve reverts to block-Jacobi
+ * for the rest of a solve, counting info.fallbacks, once the relative
+ * residual falls by less than a factor fallback_ratio over one iteration).
+ *
+ * Weight layout (host, row-major FP32): W1 [64][5(p+1)], W2 [p+1][64]. */
+int hdg_mlp_set_weights(hdg_ctx *ctx, const float *W1, const float *W2);   /* resets Adam; synchronous */
+int hdg_mlp_get_weights(hdg_ctx *ctx, float *W1, float *W2);               /* either may be NULL; synchronous */
+
+/* Training pair for the trace error e (device [n_facet][p+1][nrhs]):
+ * u = omega D^-1 S e (the features' source) and the target
+ * t = e - pi x_c - u, x_c = coarse_its stationary P1 multigrid V-cycles on
+ * S_c x_c = pi^T S e from zero (what the coarse correction leaves of e,
+ * minus the block-Jacobi step).  u, t: device, same layout; synchronous. */
+int hdg_mlp_make_data(hdg_ctx *ctx, int32_t nrhs, const double *e, double *u, double *t,
+                      int32_t coarse_its, void *stream);
+
+/* Loss mean over (facet, rhs) of sum_o (y_o - t_o / s)^2 and its gradient
+ * (host outputs, layouts as the weights; any may be NULL).  Synchronous. */
+int hdg_mlp_loss_grad(hdg_ctx *ctx, int32_t nrhs, const double *u, const double *t, double *loss,
+                      float *dW1, float *dW2, void *stream);
+
+/* Train in place: starting from the error e0 (device), for each of `cycles`
+ * errors (e0, then e <- e - V(S e) with the block-Jacobi V-cycle in FP64)
+ * build the training pair and take `epochs` Adam steps with learning rate lr
+ * on it.  loss_hist (host, may be NULL) receives the loss before every step,
+ * cycles * epochs <= 4096 values.  Synchronous. */
+int hdg_mlp_train(hdg_ctx *ctx, int32_t nrhs, const double *e0, int32_t cycles, int32_t coarse_its,
+                  int32_t epochs, double lr, double *loss_hist, void *stream);
+
 /* ------------------------------------------------------------------ measurement helpers */
 
 /* Per-kernel-class timing with HIP events on the launch stream.

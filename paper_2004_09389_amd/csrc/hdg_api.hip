@@ -219,8 +219,8 @@ double *p1_vcycle(hdg_ctx *c, int l, int nb, hipStream_t s) {
 // z = V(r): Alg. twolevel_vcycle from a zero initial guess.  With scale != null
 // the input is r / scale[rhs] and r is normalised in place on the way (the
 // FGMRES basis vector is scaled by its first reader).
-void vcycle(hdg_ctx *c, int nb, int prec, const double *r, double *z, hipStream_t s,
-            const double *scale = nullptr) {
+void vcycle_bj(hdg_ctx *c, int nb, int prec, const double *r, double *z, hipStream_t s,
+               const double *scale = nullptr) {
     double *rs = scale ? const_cast<double *>(r) : nullptr;
     if (prec == HDG_MIXED)
         hdg::launch_jacobi0<float>(c->p, c->n_facet, nb, c->Dw32, r, scale, rs, c->vz0, s);
@@ -255,6 +255,52 @@ void vcycle(hdg_ctx *c, int nb, int prec, const double *r, double *z, hipStream_
         cur = out;
     }
     check_launch();
+}
+
+void jacobi0(hdg_ctx *c, int nb, int prec, const double *r, const double *scale, double *rs, double *z0,
+             hipStream_t s) {
+    if (prec == HDG_MIXED)
+        hdg::launch_jacobi0<float>(c->p, c->n_facet, nb, c->Dw32, r, scale, rs, z0, s);
+    else
+        hdg::launch_jacobi0<double>(c->p, c->n_facet, nb, c->Dw64, r, scale, rs, z0, s);
+}
+
+// The same V-cycle with the learned smoother: every smoothing step is the
+// block-Jacobi sweep y = x + omega D^-1 (r - S x) followed by the network,
+// x <- y + s MLP(patch of u = y - x); prolongation x += pi x_P1 before
+// post-smoothing.  The first step from zero is y = z0 = omega D^-1 r.
+void vcycle_mlp(hdg_ctx *c, int nb, int prec, const double *r, double *z, hipStream_t s,
+                const double *scale = nullptr) {
+    double *rs = scale ? const_cast<double *>(r) : nullptr;
+    const short *W1b = c->mlp_wb, *W2b = c->mlp_wb + c->mlp_n1;
+    jacobi0(c, nb, prec, r, scale, rs, c->vz0, s);
+    // buffers: x alternates between vx and vx2; the sweep output goes to vres
+    double *x = c->vx, *other = c->vx2;
+    hdg::launch_mlp_smooth(c->p, c->n_facet, nb, c->vz0, nullptr, c->nbr, c->prev, W1b, W2b, x, s);
+    auto step = [&](double *out) {
+        op_sweep(c, nb, prec, x, c->vz0, nullptr, c->vres, s);
+        hdg::launch_mlp_smooth(c->p, c->n_facet, nb, c->vres, x, c->nbr, c->prev, W1b, W2b, out, s);
+        if (out != z) {
+            other = x;
+            x = out;
+        }
+    };
+    for (int k = 1; k < c->opt.nu_pre; ++k) step(other);
+    op_apply(c, nb, prec, x, r, c->vres, s, HDG_KERNEL_RESIDUAL);
+    const int L = (int)c->lev.size() - 1;
+    hdg::launch_restrict_trace(c->p, c->n_vert, nb, c->vf_row, c->vf_col, c->vres, c->lev[L].b, s);
+    const double *xl = p1_vcycle(c, L, nb, s);
+    hdg::launch_prolong_trace(c->p, c->n_facet, nb, c->facet_vert, xl, x, s);
+    for (int k = 0; k < c->opt.nu_post; ++k) step(k == c->opt.nu_post - 1 ? z : other);
+    check_launch();
+}
+
+void vcycle(hdg_ctx *c, int nb, int prec, const double *r, double *z, hipStream_t s,
+            const double *scale = nullptr) {
+    if (c->use_mlp_now)
+        vcycle_mlp(c, nb, prec, r, z, s, scale);
+    else
+        vcycle_bj(c, nb, prec, r, z, s, scale);
 }
 
 // ------------------------------------------------------------------ reductions and Krylov
@@ -397,15 +443,22 @@ int solve_fgmres(hdg_ctx *c, int nb, int vc_prec, int op_prec, double inner_eta,
     const int64_t vs = n * c->opt.max_rhs;
     const int R = c->opt.restart;
     const double rtol = c->opt.rtol;
-    std::vector<double> rel(nb, 0.0), cyc0(nb, 0.0);
-    int its = 0, cycles = 0;
+    std::vector<double> rel(nb, 0.0), cyc0(nb, 0.0), prev_res(nb, 0.0);
+    int its = 0, cycles = 0, fallbacks = 0;
+    auto done_info = [&](int status) {
+        fill_info(info, nb, its, cycles, rel, status);
+        if (info)
+            for (int r = 0; r < nb; ++r) info[r].fallbacks = fallbacks;
+        return status;
+    };
     while (true) {
         true_residual(c, nb, rhat, lam, c->kV, rel, s);
-        if (any_nonfinite(rel)) { fill_info(info, nb, its, cycles, rel, HDG_EBREAKDOWN); return HDG_EBREAKDOWN; }
-        if (all_below(rel, rtol)) { fill_info(info, nb, its, cycles, rel, HDG_OK); return HDG_OK; }
-        if (its >= c->opt.maxit) { fill_info(info, nb, its, cycles, rel, HDG_ENOTCONV); return HDG_ENOTCONV; }
+        if (any_nonfinite(rel)) return done_info(HDG_EBREAKDOWN);
+        if (all_below(rel, rtol)) return done_info(HDG_OK);
+        if (its >= c->opt.maxit) return done_info(HDG_ENOTCONV);
         ++cycles;
         cyc0 = rel;
+        prev_res = rel;
         hdg::launch_gmres_start(nb, R, scal(c, SC_RR), c->gm, scal(c, SC_BETA), s);
         int k = 0, pending = -1;
         auto converged = [&](const double *h) {
@@ -422,7 +475,7 @@ int solve_fgmres(hdg_ctx *c, int nb, int vc_prec, int op_prec, double inner_eta,
             // V_j still carries its norm (beta for j = 0, the previous step's ||w|| after);
             // the V-cycle's first kernel divides it out in place
             const double *vscale = (j == 0) ? scal(c, SC_BETA) : scal(c, SC_HN);
-            run_step(c, graph_key(2, nb, vc_prec * 4 + op_prec, j), s, [&](hipStream_t st) {
+            run_step(c, graph_key(2 + (c->use_mlp_now ? 1 : 0), nb, vc_prec * 4 + op_prec, j), s, [&](hipStream_t st) {
                 vcycle(c, nb, vc_prec, Vj, Zj, st, vscale);
                 op_apply(c, nb, op_prec, Zj, nullptr, Vn, st, HDG_KERNEL_APPLY);
                 dots(c, nb, j + 1, c->kV, vs, Vn, c->hcol, st);
@@ -433,10 +486,24 @@ int solve_fgmres(hdg_ctx *c, int nb, int vc_prec, int op_prec, double inner_eta,
             mark_lag(c, slot, s);
             ++its;
             k = j + 1;
-            if (pending >= 0 && converged(wait_lag(c, pending))) {
-                k = j;   // column j was queued speculatively; the solution uses columns 0..j-1
-                pending = -1;
-                break;
+            if (pending >= 0) {
+                const double *h = wait_lag(c, pending);
+                if (converged(h)) {
+                    k = j;   // column j was queued speculatively; the solution uses columns 0..j-1
+                    pending = -1;
+                    break;
+                }
+                // learned smoother judged by the residual reduction per iteration; block-Jacobi
+                // takes over for the rest of the solve when it is too weak
+                if (c->use_mlp_now) {
+                    for (int r = 0; r < nb; ++r)
+                        if (prev_res[r] > 0 && h[r] > c->opt.fallback_ratio * prev_res[r]) {
+                            c->use_mlp_now = false;
+                            ++fallbacks;
+                            break;
+                        }
+                }
+                for (int r = 0; r < nb; ++r) prev_res[r] = h[r];
             }
             pending = slot;
         }
@@ -538,6 +605,7 @@ void setup_impl(const hdg_mesh *levels, int nlev, const int32_t *const *parents,
     c->facet_vert = dev_upload(c, c->topo.facet_vert);
     const int m = c->m;
     c->nbr = dev_alloc<int32_t>(c, (size_t)4 * ne);
+    c->prev = dev_alloc<int8_t>(c, (size_t)4 * ne);
     c->S64 = dev_alloc<double>(c, (size_t)hdg::wide_padded(5 * m * m, 2) * ne);
     c->T64 = dev_alloc<double>(c, (size_t)hdg::wide_padded(4 * m * m, 2) * ne);
     c->Dw64 = dev_alloc<double>(c, (size_t)hdg::wide_padded(m * m, 2) * ne);
@@ -545,7 +613,7 @@ void setup_impl(const hdg_mesh *levels, int nlev, const int32_t *const *parents,
     c->T16 = dev_alloc<__hip_bfloat16>(c, (size_t)hdg::wide_padded(4 * m * m, 8) * ne);
     c->Dw32 = dev_alloc<float>(c, (size_t)hdg::wide_padded(m * m, 4) * ne);
     hdg::launch_facet_rows(c->p, ne, nk, Sloc, d_fcell, d_floc, c->cell_facet, c->cell_rev, opt.omega, c->S64,
-                           c->T64, c->Dw64, c->S32, c->T16, c->Dw32, c->nbr, d_err, s);
+                           c->T64, c->Dw64, c->S32, c->T16, c->Dw32, c->nbr, c->prev, d_err, s);
     check_launch();
     HDG_HIP_CHECK(hipDeviceSynchronize());
     HDG_HIP_CHECK(hipMemcpy(&herr, d_err, sizeof(int), hipMemcpyDeviceToHost));
@@ -684,6 +752,28 @@ void setup_impl(const hdg_mesh *levels, int nlev, const int32_t *const *parents,
     c->hy = dev_alloc<double>(c, (size_t)Rr * mr);
     c->dbn = dev_alloc<double>(c, mr);
     c->loc = dev_alloc<double>(c, (size_t)c->nt * nk * mr);
+    // learned smoother (zero weights until set: the untrained smoother is block-Jacobi)
+    c->mlp_n1 = 64 * hdg::mlp_k1p(c->p);
+    c->mlp_n2 = 16 * 64;
+    {
+        const size_t nw = c->mlp_n1 + c->mlp_n2;
+        c->mlp_w = dev_alloc<float>(c, nw);
+        c->mlp_m1 = dev_alloc<float>(c, nw);
+        c->mlp_m2 = dev_alloc<float>(c, nw);
+        c->mlp_g = dev_alloc<float>(c, nw);
+        c->mlp_wb = dev_alloc<short>(c, nw);
+        HDG_HIP_CHECK(hipMemset(c->mlp_w, 0, nw * sizeof(float)));
+        HDG_HIP_CHECK(hipMemset(c->mlp_m1, 0, nw * sizeof(float)));
+        HDG_HIP_CHECK(hipMemset(c->mlp_m2, 0, nw * sizeof(float)));
+        HDG_HIP_CHECK(hipMemset(c->mlp_wb, 0, nw * sizeof(short)));
+        const int nwv = hdg::mlp_grad_waves(ne, mr);
+        c->mlp_pdW1 = dev_alloc<float>(c, (size_t)nwv * c->mlp_n1);
+        c->mlp_pdW2 = dev_alloc<float>(c, (size_t)nwv * c->mlp_n2);
+        c->mlp_ploss = dev_alloc<float>(c, (size_t)nwv);
+        c->mlp_loss = dev_alloc<double>(c, 4096);
+        c->p1_keep = dev_alloc<double>(c, (size_t)nv * mr);
+        c->p1_acc = dev_alloc<double>(c, (size_t)nv * mr);
+    }
     HDG_HIP_CHECK(hipHostMalloc((void **)&c->hscal, sizeof(double) * 64 * 4, hipHostMallocDefault));
     HDG_HIP_CHECK(hipHostMalloc((void **)&c->hlag, sizeof(double) * 64 * 4,
                                 hipHostMallocMapped | hipHostMallocCoherent));
@@ -820,6 +910,7 @@ extern "C" int hdg_mg_vcycle(hdg_ctx *c, int32_t nb, int32_t prec, const double 
         check_nb(c, nb);
         check_prec(prec);
         HDG_REQUIRE(r && z && r != z, "r and z must be distinct non-NULL buffers");
+        c->use_mlp_now = c->opt.smoother == HDG_SMOOTH_MLP;
         vcycle(c, nb, prec, r, z, as_stream(stream));
     });
 }
@@ -835,8 +926,11 @@ extern "C" int hdg_solve(hdg_ctx *c, int32_t nb, const double *rhat, double *lam
         const double *h = dots_now(c, nb, rhat, rhat, scal(c, SC_BN2), s);
         hdg::launch_sqrt(nb, scal(c, SC_BN2), c->dbn, s);
         for (int r = 0; r < nb; ++r) c->hbn2[r] = h[r];
+        c->use_mlp_now = c->opt.smoother == HDG_SMOOTH_MLP;
         int kry = c->opt.krylov;
-        if (kry == HDG_KRYLOV_AUTO) kry = (c->symmetric && c->opt.precision == HDG_FP64) ? HDG_KRYLOV_PCG : HDG_KRYLOV_FGMRES;
+        if (kry == HDG_KRYLOV_AUTO)
+            kry = (c->symmetric && c->opt.precision == HDG_FP64 && !c->use_mlp_now) ? HDG_KRYLOV_PCG : HDG_KRYLOV_FGMRES;
+        HDG_REQUIRE(!(kry == HDG_KRYLOV_PCG && c->use_mlp_now), "the learned smoother is nonlinear: use FGMRES");
         HDG_REQUIRE(c->opt.precision >= HDG_FP64 && c->opt.precision <= HDG_MIXED_IR, "unknown solve precision");
         if (kry == HDG_KRYLOV_FGMRES) HDG_REQUIRE(c->kV != nullptr, "FGMRES workspace was not allocated (krylov = PCG at setup)");
         if (kry == HDG_KRYLOV_PCG) {
@@ -865,6 +959,187 @@ extern "C" int hdg_recover(hdg_ctx *c, int32_t nb, const double *r_cell, const d
             hdg::launch_recover(c->p, c->n_cell, nb, c->Ar, c->Wr, c->cell_facet, c->cell_rev, r_cell, lam, q_cell,
                                 s);
         check_launch();
+    });
+}
+
+// ------------------------------------------------------------------ learned smoother
+
+namespace {
+
+void mlp_data_buffers(hdg_ctx *c) {
+    if (c->mlp_E) return;
+    const size_t vl = (size_t)vec_len(c) * c->opt.max_rhs;
+    c->mlp_E = dev_alloc<double>(c, vl);
+    c->mlp_R = dev_alloc<double>(c, vl);
+    c->mlp_U = dev_alloc<double>(c, vl);
+    c->mlp_T = dev_alloc<double>(c, vl);
+}
+
+// Training pair for the error e: r = S e, u = omega D^-1 r, and the target
+// t = e - pi x_c - u, x_c = coarse_its stationary P1 V-cycles on
+// S_c x_c = pi^T r from zero (the part of e the coarse correction leaves,
+// minus the block-Jacobi step).  FP64 throughout.
+void mlp_pair(hdg_ctx *c, int nb, int coarse_its, const double *e, double *r, double *u, double *t, hipStream_t s) {
+    const int L = (int)c->lev.size() - 1;
+    hdg::P1LevelDev &F = c->lev[L];
+    const int64_t nv = (int64_t)F.n * nb;
+    op_apply(c, nb, HDG_FP64, e, nullptr, r, s, HDG_KERNEL_APPLY);
+    jacobi0(c, nb, HDG_FP64, r, nullptr, nullptr, u, s);
+    hdg::launch_restrict_trace(c->p, c->n_vert, nb, c->vf_row, c->vf_col, r, c->p1_keep, s);
+    for (int k = 0; k < coarse_its; ++k) {
+        if (k == 0)
+            hdg::launch_copy(nv, c->p1_keep, F.b, s);
+        else
+            hdg::launch_p1_resid(F.n, F.w, nb, F.col, F.val, F.diag, c->p1_keep, c->p1_acc, F.b, s);
+        const double *xl = p1_vcycle(c, L, nb, s);
+        hdg::launch_lin3(nv, 1.0, xl, k == 0 ? 0.0 : 1.0, k == 0 ? nullptr : c->p1_acc, 0.0, nullptr, c->p1_acc, s);
+    }
+    const int64_t n = vec_len(c) * nb;
+    hdg::launch_lin3(n, 1.0, e, -1.0, u, 0.0, nullptr, t, s);
+    if (coarse_its > 0) {
+        hdg::launch_lin3(nv, -1.0, c->p1_acc, 0.0, nullptr, 0.0, nullptr, c->p1_acc, s);
+        hdg::launch_prolong_trace(c->p, c->n_facet, nb, c->facet_vert, c->p1_acc, t, s);
+    }
+    check_launch();
+}
+
+void mlp_grad(hdg_ctx *c, int nb, const double *u, const double *t, double *loss, hipStream_t s) {
+    hdg::launch_mlp_grad(c->p, c->n_facet, nb, u, t, c->nbr, c->prev, c->mlp_wb, c->mlp_wb + c->mlp_n1, c->mlp_pdW1,
+                         c->mlp_pdW2, c->mlp_ploss, c->mlp_g, loss, s);
+    check_launch();
+}
+
+// padded device layout [W1: 64 x K1P | W2: 16 x 64] <-> dense (64 x 5m), (m x 64)
+void mlp_pack(const hdg_ctx *c, const float *W1, const float *W2, std::vector<float> &buf) {
+    const int m = c->p + 1, k1 = 5 * m, k1p = c->mlp_n1 / 64;
+    buf.assign((size_t)c->mlp_n1 + c->mlp_n2, 0.f);
+    for (int h = 0; h < 64; ++h)
+        for (int k = 0; k < k1; ++k) buf[(size_t)h * k1p + k] = W1[(size_t)h * k1 + k];
+    for (int o = 0; o < m; ++o)
+        for (int h = 0; h < 64; ++h) buf[(size_t)c->mlp_n1 + o * 64 + h] = W2[(size_t)o * 64 + h];
+}
+
+void mlp_unpack(const hdg_ctx *c, const std::vector<float> &buf, float scale, float *W1, float *W2) {
+    const int m = c->p + 1, k1 = 5 * m, k1p = c->mlp_n1 / 64;
+    if (W1)
+        for (int h = 0; h < 64; ++h)
+            for (int k = 0; k < k1; ++k) W1[(size_t)h * k1 + k] = scale * buf[(size_t)h * k1p + k];
+    if (W2)
+        for (int o = 0; o < m; ++o)
+            for (int h = 0; h < 64; ++h) W2[(size_t)o * 64 + h] = scale * buf[(size_t)c->mlp_n1 + o * 64 + h];
+}
+
+}  // namespace
+
+extern "C" int hdg_mlp_set_weights(hdg_ctx *c, const float *W1, const float *W2) {
+    if (!c) return HDG_EINVAL;
+    return guard([&] {
+        HDG_REQUIRE(W1 && W2, "W1 and W2 must not be NULL");
+        const int m = c->p + 1;
+        for (size_t i = 0; i < (size_t)64 * 5 * m; ++i) HDG_REQUIRE(std::isfinite(W1[i]), "W1 has a non-finite entry");
+        for (size_t i = 0; i < (size_t)m * 64; ++i) HDG_REQUIRE(std::isfinite(W2[i]), "W2 has a non-finite entry");
+        std::vector<float> buf;
+        mlp_pack(c, W1, W2, buf);
+        const size_t nw = buf.size();
+        HDG_HIP_CHECK(hipDeviceSynchronize());
+        HDG_HIP_CHECK(hipMemcpy(c->mlp_w, buf.data(), nw * sizeof(float), hipMemcpyHostToDevice));
+        HDG_HIP_CHECK(hipMemset(c->mlp_m1, 0, nw * sizeof(float)));
+        HDG_HIP_CHECK(hipMemset(c->mlp_m2, 0, nw * sizeof(float)));
+        hdg::launch_to_bf16((int)nw, c->mlp_w, c->mlp_wb, nullptr);
+        check_launch();
+        HDG_HIP_CHECK(hipDeviceSynchronize());
+        c->mlp_step = 0;
+        c->mlp_ready = true;
+    });
+}
+
+extern "C" int hdg_mlp_get_weights(hdg_ctx *c, float *W1, float *W2) {
+    if (!c) return HDG_EINVAL;
+    return guard([&] {
+        std::vector<float> buf((size_t)c->mlp_n1 + c->mlp_n2);
+        HDG_HIP_CHECK(hipDeviceSynchronize());
+        HDG_HIP_CHECK(hipMemcpy(buf.data(), c->mlp_w, buf.size() * sizeof(float), hipMemcpyDeviceToHost));
+        mlp_unpack(c, buf, 1.f, W1, W2);
+    });
+}
+
+extern "C" int hdg_mlp_make_data(hdg_ctx *c, int32_t nb, const double *e, double *u, double *t, int32_t coarse_its,
+                                 void *stream) {
+    if (!c) return HDG_EINVAL;
+    return guard([&] {
+        check_nb(c, nb);
+        HDG_REQUIRE(e && u && t && e != u && e != t && u != t, "e, u and t must be distinct non-NULL buffers");
+        HDG_REQUIRE(coarse_its >= 0 && coarse_its <= 64, "coarse_its must be in 0..64");
+        hipStream_t s = as_stream(stream);
+        mlp_data_buffers(c);
+        mlp_pair(c, nb, coarse_its, e, c->mlp_R, u, t, s);
+        HDG_HIP_CHECK(hipStreamSynchronize(s));
+    });
+}
+
+extern "C" int hdg_mlp_loss_grad(hdg_ctx *c, int32_t nb, const double *u, const double *t, double *loss, float *dW1,
+                                 float *dW2, void *stream) {
+    if (!c) return HDG_EINVAL;
+    return guard([&] {
+        check_nb(c, nb);
+        HDG_REQUIRE(u && t, "u and t must not be NULL");
+        hipStream_t s = as_stream(stream);
+        mlp_grad(c, nb, u, t, c->mlp_loss, s);
+        HDG_HIP_CHECK(hipStreamSynchronize(s));
+        const double n = (double)c->n_facet * nb;
+        std::vector<float> buf((size_t)c->mlp_n1 + c->mlp_n2);
+        HDG_HIP_CHECK(hipMemcpy(buf.data(), c->mlp_g, buf.size() * sizeof(float), hipMemcpyDeviceToHost));
+        mlp_unpack(c, buf, (float)(1.0 / n), dW1, dW2);
+        if (loss) {
+            double l = 0;
+            HDG_HIP_CHECK(hipMemcpy(&l, c->mlp_loss, sizeof(double), hipMemcpyDeviceToHost));
+            *loss = l / n;
+        }
+    });
+}
+
+extern "C" int hdg_mlp_train(hdg_ctx *c, int32_t nb, const double *e0, int32_t cycles, int32_t coarse_its,
+                             int32_t epochs, double lr, double *loss_hist, void *stream) {
+    if (!c) return HDG_EINVAL;
+    return guard([&] {
+        check_nb(c, nb);
+        HDG_REQUIRE(e0, "e0 must not be NULL");
+        HDG_REQUIRE(cycles >= 1 && epochs >= 1 && (int64_t)cycles * epochs <= 4096,
+                    "need cycles, epochs >= 1 and cycles * epochs <= 4096");
+        HDG_REQUIRE(coarse_its >= 0 && coarse_its <= 64, "coarse_its must be in 0..64");
+        HDG_REQUIRE(lr > 0 && std::isfinite(lr), "lr must be positive");
+        hipStream_t s = as_stream(stream);
+        mlp_data_buffers(c);
+        const int64_t n = vec_len(c) * nb;
+        const float gscale = (float)(1.0 / ((double)c->n_facet * nb));
+        const bool keep = c->use_mlp_now;
+        c->use_mlp_now = false;   // the data come from the block-Jacobi cycle
+        hdg::launch_copy(n, e0, c->mlp_E, s);
+        int idx = 0;
+        for (int k = 0; k < cycles; ++k) {
+            mlp_pair(c, nb, coarse_its, c->mlp_E, c->mlp_R, c->mlp_U, c->mlp_T, s);
+            for (int ep = 0; ep < epochs; ++ep, ++idx) {
+                mlp_grad(c, nb, c->mlp_U, c->mlp_T, c->mlp_loss + idx, s);
+                ++c->mlp_step;
+                hdg::launch_adam(c->p, c->mlp_g, gscale, c->mlp_w, c->mlp_m1, c->mlp_m2, (float)lr, c->mlp_step,
+                                 c->mlp_wb, s);
+                check_launch();
+            }
+            if (k + 1 < cycles) {
+                // next error: e <- e - V(S e) with the plain block-Jacobi cycle (r = S e is in mlp_R)
+                vcycle_bj(c, nb, HDG_FP64, c->mlp_R, c->mlp_U, s);
+                hdg::launch_lin3(n, 1.0, c->mlp_E, -1.0, c->mlp_U, 0.0, nullptr, c->mlp_E, s);
+                check_launch();
+            }
+        }
+        c->use_mlp_now = keep;
+        c->mlp_ready = true;
+        HDG_HIP_CHECK(hipStreamSynchronize(s));
+        if (loss_hist) {
+            std::vector<double> l(idx);
+            HDG_HIP_CHECK(hipMemcpy(l.data(), c->mlp_loss, idx * sizeof(double), hipMemcpyDeviceToHost));
+            for (int i = 0; i < idx; ++i) loss_hist[i] = l[i] * gscale;
+        }
     });
 }
 

@@ -129,6 +129,7 @@ struct hdg_ctx {
 
     // facet block rows, component-major [slot][a][b][n_facet]
     int32_t *nbr = nullptr;     // [4][n_facet]
+    int8_t *prev = nullptr;     // [4][n_facet] learned-smoother patch orientation flags
     double *S64 = nullptr;      // [5][m][m]  slot 0 = diagonal block
     double *T64 = nullptr;      // [4][m][m]  omega D^-1 S_j (off-diagonal slots)
     double *Dw64 = nullptr;     // [m][m]     omega D^-1
@@ -164,6 +165,18 @@ struct hdg_ctx {
     double *dlag = nullptr;                   // device view of hlag
     hipEvent_t lag_ev[2] = {nullptr, nullptr};
     int red_blocks = 0;
+
+    // learned smoother: weights [W1 (64 x K1P) | W2 (16 x 64)], FP32 master + Adam moments, BF16 copy
+    int mlp_n1 = 0, mlp_n2 = 0, mlp_step = 0;
+    bool mlp_ready = false;
+    float *mlp_w = nullptr, *mlp_m1 = nullptr, *mlp_m2 = nullptr, *mlp_g = nullptr;
+    short *mlp_wb = nullptr;
+    float *mlp_pdW1 = nullptr, *mlp_pdW2 = nullptr, *mlp_ploss = nullptr;
+    double *mlp_loss = nullptr;           // device, one value per training step of an epoch
+    double *mlp_E = nullptr, *mlp_R = nullptr;   // training: current error and S e (allocated on first use)
+    double *mlp_U = nullptr, *mlp_T = nullptr;   // training: features source u and targets t
+    double *p1_keep = nullptr, *p1_acc = nullptr;  // finest-P1 vectors for the training targets
+    bool use_mlp_now = false;             // smoother of the current V-cycles (fallback clears it)
 
     // timing
     struct PendingEvent {

@@ -5,6 +5,17 @@
 
 namespace hdg {
 
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.
+// The trace and cell kernels remap the block index so that every XCD streams
+// one contiguous range of facets (cells): the neighbour gathers of a facet row
+// then hit the L2 that already holds them.  Launchers pad the grid to a
+// multiple of 8 blocks; threads past the end return.
+constexpr int N_XCD = 8;
+__device__ __forceinline__ int xcd_block() {
+    const int per = gridDim.x / N_XCD;
+    return (blockIdx.x % N_XCD) * per + blockIdx.x / N_XCD;
+}
+
 // padded component count of a facet-row matrix stored with v entries per 16 bytes
 constexpr int wide_padded(int c, int v) { return (c + v - 1) / v * v; }
 
@@ -17,8 +28,8 @@ void launch_cell_condense(int p, int nk, const double *corners, const double *re
                           double *Zr, double *Ar, double *Wr, int *err, hipStream_t s);
 void launch_facet_rows(int p, int ne, int nk, const double *Sloc, const int *facet_cell, const int *facet_loc,
                        const int *cell_facet, const int8_t *cell_rev, double omega, double *S64, double *T64,
-                       double *Dw64, float *S32, __hip_bfloat16 *T16, float *Dw32, int *nbr, int *err,
-                       hipStream_t s);
+                       double *Dw64, float *S32, __hip_bfloat16 *T16, float *Dw32, int *nbr, int8_t *prev,
+                       int *err, hipStream_t s);
 
 template <typename MT>
 void launch_trace_apply(int p, int ne, int nb, const MT *S, const int *nbr, const double *x, const double *b,
@@ -70,5 +81,20 @@ void launch_copy(int64_t n, const double *src, double *dst, hipStream_t s);
 void launch_gmres_start(int nb, int restart, const double *beta2, double *gm, double *beta, hipStream_t s);
 void launch_gmres_solve(int nb, int k, int restart, const double *gm, double *y, hipStream_t s);
 void launch_sqrt(int nb, const double *in, double *out, hipStream_t s);
+
+// learned smoother (hdg_mlp.hip)
+int mlp_k1p(int p);
+int mlp_grad_waves(int ne, int nb);
+void launch_mlp_smooth(int p, int ne, int nb, const double *u, const double *xi, const int *nbr, const int8_t *prev,
+                       const short *W1b, const short *W2b, double *xo, hipStream_t s);
+void launch_mlp_grad(int p, int ne, int nb, const double *u, const double *t, const int *nbr, const int8_t *prev,
+                     const short *W1b, const short *W2b, float *pdW1, float *pdW2, float *ploss, float *g,
+                     double *loss, hipStream_t s);
+void launch_adam(int p, const float *g, float gscale, float *w, float *m1, float *m2, float lr, int step,
+                 short *wb, hipStream_t s);
+void launch_to_bf16(int n, const float *w, short *wb, hipStream_t s);
+void launch_prolong_trace(int p, int ne, int nb, const int *fvert, const double *qc, double *x, hipStream_t s);
+void launch_lin3(int64_t n, double a, const double *x, double b, const double *y, double c, const double *z,
+                 double *out, hipStream_t s);
 
 }  // namespace hdg

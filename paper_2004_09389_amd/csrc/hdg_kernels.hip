@@ -25,6 +25,7 @@ __device__ __forceinline__ size_t widx(int c, int e, size_t ne, int v) {
     return ((size_t)(c / v) * ne + e) * v + (c % v);
 }
 
+
 typedef double dbl2_t __attribute__((ext_vector_type(2)));
 typedef float flt4_t __attribute__((ext_vector_type(4)));
 typedef unsigned u32x4_t __attribute__((ext_vector_type(4)));
@@ -296,7 +297,7 @@ __global__ void k_facet_rows(int ne, int nk, const double *__restrict__ Sloc, co
                              const int8_t *__restrict__ cell_rev, double omega, double *__restrict__ S64,
                              double *__restrict__ T64, double *__restrict__ Dw64, float *__restrict__ S32,
                              __hip_bfloat16 *__restrict__ T16, float *__restrict__ Dw32, int *__restrict__ nbr,
-                             int *__restrict__ err) {
+                             int8_t *__restrict__ prev, int *__restrict__ err) {
     constexpr int m = P + 1, nt = 3 * m;
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= ne) return;
@@ -309,7 +310,11 @@ __global__ void k_facet_rows(int ne, int nk, const double *__restrict__ Sloc, co
             const int i2 = (i + jj) % 3;
             const int e2 = cell_facet[i2 * NK + K];
             const int rev2 = cell_rev[i2 * NK + K];
-            if (jj > 0) nbr[(2 * s + jj - 1) * NE + e] = e2;
+            if (jj > 0) {
+                nbr[(2 * s + jj - 1) * NE + e] = e2;
+                // learned-smoother patch: list this slot's nodes counter-clockwise around cell K
+                prev[(2 * s + jj - 1) * NE + e] = (int8_t)rev2;
+            }
             for (int a = 0; a < m; ++a) {
                 const int ra = i * m + (s == 0 ? a : P - a);
                 for (int b = 0; b < m; ++b) {
@@ -377,7 +382,7 @@ __global__ __launch_bounds__(256) void k_trace_apply(int ne, int nb, const MT *_
                                                      const double *__restrict__ b, double *__restrict__ y) {
     using AT = typename Acc<MT>::type;
     constexpr int V = Wide<MT>::V, C = 5 * M * M, G = padded(C, V) / V;
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int t = xcd_block() * blockDim.x + threadIdx.x;
     if (t >= ne * nb) return;
     const int e = t / nb, r = t - e * nb;
     const size_t NE = (size_t)ne;
@@ -422,7 +427,7 @@ __global__ __launch_bounds__(256) void k_jacobi0(int ne, int nb, const MT *__res
                                                  double *__restrict__ rs, double *__restrict__ z0) {
     using AT = typename Acc<MT>::type;
     constexpr int V = Wide<MT>::V, C = M * M, G = padded(C, V) / V;
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int t = xcd_block() * blockDim.x + threadIdx.x;
     if (t >= ne * nb) return;
     const int e = t / nb, rr = t - e * nb;
     const size_t NE = (size_t)ne;
@@ -464,7 +469,7 @@ __global__ __launch_bounds__(256) void k_sweep(int ne, int nb, const MT *__restr
     using AT = typename Acc<MT>::type;
     constexpr int P = M - 1;
     constexpr int V = Wide<MT>::V, C = 4 * M * M, G = padded(C, V) / V;
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int t = xcd_block() * blockDim.x + threadIdx.x;
     if (t >= ne * nb) return;
     const int e = t / nb, r = t - e * nb;
     const size_t NE = (size_t)ne;
@@ -513,7 +518,7 @@ template <int M>
 __global__ void k_restrict_trace(int nv, int nb, const int *__restrict__ vf_row, const int *__restrict__ vf_col,
                                  const double *__restrict__ res, double *__restrict__ rc) {
     constexpr int P = M - 1;
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int t = xcd_block() * blockDim.x + threadIdx.x;
     if (t >= nv * nb) return;
     const int v = t / nb, r = t - v * nb;
     double acc = 0.0;
@@ -714,7 +719,7 @@ template <int P>
 __global__ __launch_bounds__(256) void k_condense_cell(int nk, int nb, const double *__restrict__ Zr,
                                                        const double *__restrict__ rc, double *__restrict__ loc) {
     constexpr int n = (P + 1) * (P + 2) / 2, m = P + 1, nc = 3 * n, nt = 3 * m;
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int t = xcd_block() * blockDim.x + threadIdx.x;
     if (t >= nk * nb) return;
     const int K = t / nb, r = t - K * nb;
     const size_t NK = (size_t)nk;
@@ -736,7 +741,7 @@ __global__ void k_condense_gather(int ne, int nk, int nb, const int *__restrict_
                                   const int *__restrict__ facet_loc, const double *__restrict__ loc,
                                   double *__restrict__ rhat) {
     constexpr int m = P + 1;
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int t = xcd_block() * blockDim.x + threadIdx.x;
     if (t >= ne * m * nb) return;
     const int r = t % nb, ea = t / nb, e = ea / m, a = ea - e * m;
     const size_t NK = (size_t)nk;
@@ -754,7 +759,7 @@ __global__ __launch_bounds__(256) void k_recover(int nk, int nb, const double *_
                                                  const int8_t *__restrict__ cell_rev, const double *__restrict__ rc,
                                                  const double *__restrict__ lam, double *__restrict__ q) {
     constexpr int n = (P + 1) * (P + 2) / 2, m = P + 1, nc = 3 * n, nt = 3 * m;
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int t = xcd_block() * blockDim.x + threadIdx.x;
     if (t >= nk * nb) return;
     const int K = t / nb, r = t - K * nb;
     const size_t NK = (size_t)nk;
@@ -1043,6 +1048,8 @@ __global__ void k_sqrt(int nb, const double *__restrict__ in, double *__restrict
 // ------------------------------------------------------------------ explicit instantiations via launchers
 
 #define GRID(n, b) dim3((unsigned)(((n) + (b) - 1) / (b))), dim3(b)
+// grid padded to a multiple of N_XCD blocks, for kernels indexed through xcd_block()
+#define GRID8(n, b) dim3((unsigned)((((n) + (b) - 1) / (b) + N_XCD - 1) / N_XCD * N_XCD)), dim3(b)
 
 void launch_cell_condense(int p, int nk, const double *corners, const double *ref, CellParams cp, double *Sloc,
                           double *Zr, double *Ar, double *Wr, int *err, hipStream_t s) {
@@ -1055,9 +1062,9 @@ void launch_cell_condense(int p, int nk, const double *corners, const double *re
 
 void launch_facet_rows(int p, int ne, int nk, const double *Sloc, const int *facet_cell, const int *facet_loc,
                        const int *cell_facet, const int8_t *cell_rev, double omega, double *S64, double *T64,
-                       double *Dw64, float *S32, __hip_bfloat16 *T16, float *Dw32, int *nbr, int *err,
-                       hipStream_t s) {
-#define FR(P) hipLaunchKernelGGL(k_facet_rows<P>, GRID(ne, 128), 0, s, ne, nk, Sloc, facet_cell, facet_loc, cell_facet, cell_rev, omega, S64, T64, Dw64, S32, T16, Dw32, nbr, err)
+                       double *Dw64, float *S32, __hip_bfloat16 *T16, float *Dw32, int *nbr, int8_t *prev,
+                       int *err, hipStream_t s) {
+#define FR(P) hipLaunchKernelGGL(k_facet_rows<P>, GRID(ne, 128), 0, s, ne, nk, Sloc, facet_cell, facet_loc, cell_facet, cell_rev, omega, S64, T64, Dw64, S32, T16, Dw32, nbr, prev, err)
     switch (p) { case 1: FR(1); break; case 2: FR(2); break; case 3: FR(3); break; }
 #undef FR
 }
@@ -1065,7 +1072,7 @@ void launch_facet_rows(int p, int ne, int nk, const double *Sloc, const int *fac
 template <typename MT>
 void launch_trace_apply(int p, int ne, int nb, const MT *S, const int *nbr, const double *x, const double *b,
                         double *y, hipStream_t s) {
-#define TA(P) hipLaunchKernelGGL((k_trace_apply<P + 1, MT>), GRID(ne * nb, 256), 0, s, ne, nb, S, nbr, x, b, y)
+#define TA(P) hipLaunchKernelGGL((k_trace_apply<P + 1, MT>), GRID8(ne * nb, 256), 0, s, ne, nb, S, nbr, x, b, y)
     switch (p) { case 1: TA(1); break; case 2: TA(2); break; case 3: TA(3); break; }
 #undef TA
 }
@@ -1075,7 +1082,7 @@ template void launch_trace_apply<float>(int, int, int, const float *, const int 
 template <typename MT>
 void launch_jacobi0(int p, int ne, int nb, const MT *Dw, const double *r, const double *scale, double *rs,
                     double *z0, hipStream_t s) {
-#define J0(P) hipLaunchKernelGGL((k_jacobi0<P + 1, MT>), GRID(ne * nb, 256), 0, s, ne, nb, Dw, r, scale, rs, z0)
+#define J0(P) hipLaunchKernelGGL((k_jacobi0<P + 1, MT>), GRID8(ne * nb, 256), 0, s, ne, nb, Dw, r, scale, rs, z0)
     switch (p) { case 1: J0(1); break; case 2: J0(2); break; case 3: J0(3); break; }
 #undef J0
 }
@@ -1087,7 +1094,7 @@ template void launch_jacobi0<float>(int, int, int, const float *, const double *
 template <typename MT>
 void launch_sweep(int p, int ne, int nb, const MT *T, const int *nbr, const double *x, const double *z0,
                   const double *qc, const int *fvert, double omega, double *y, hipStream_t s) {
-#define SW(P) hipLaunchKernelGGL((k_sweep<P + 1, MT>), GRID(ne * nb, 256), 0, s, ne, nb, T, nbr, x, z0, qc, fvert, omega, y)
+#define SW(P) hipLaunchKernelGGL((k_sweep<P + 1, MT>), GRID8(ne * nb, 256), 0, s, ne, nb, T, nbr, x, z0, qc, fvert, omega, y)
     switch (p) { case 1: SW(1); break; case 2: SW(2); break; case 3: SW(3); break; }
 #undef SW
 }
@@ -1096,7 +1103,7 @@ template void launch_sweep<__hip_bfloat16>(int, int, int, const __hip_bfloat16 *
 
 void launch_restrict_trace(int p, int nv, int nb, const int *vf_row, const int *vf_col, const double *res,
                            double *rc, hipStream_t s) {
-#define RT(P) hipLaunchKernelGGL(k_restrict_trace<P + 1>, GRID(nv * nb, 256), 0, s, nv, nb, vf_row, vf_col, res, rc)
+#define RT(P) hipLaunchKernelGGL(k_restrict_trace<P + 1>, GRID8(nv * nb, 256), 0, s, nv, nb, vf_row, vf_col, res, rc)
     switch (p) { case 1: RT(1); break; case 2: RT(2); break; case 3: RT(3); break; }
 #undef RT
 }
@@ -1132,8 +1139,8 @@ void launch_p1_tail(const P1Tail &T, int nb, hipStream_t s) {
 void launch_condense(int p, int nk, int ne, int nb, const double *Zr, const double *rc, double *loc,
                      const int *facet_cell, const int *facet_loc, double *rhat, hipStream_t s) {
 #define CC(P)                                                                                                     \
-    hipLaunchKernelGGL(k_condense_cell<P>, GRID(nk * nb, 256), 0, s, nk, nb, Zr, rc, loc);                        \
-    hipLaunchKernelGGL(k_condense_gather<P>, GRID(ne * (P + 1) * nb, 256), 0, s, ne, nk, nb, facet_cell,         \
+    hipLaunchKernelGGL(k_condense_cell<P>, GRID8(nk * nb, 256), 0, s, nk, nb, Zr, rc, loc);                        \
+    hipLaunchKernelGGL(k_condense_gather<P>, GRID8(ne * (P + 1) * nb, 256), 0, s, ne, nk, nb, facet_cell,         \
                        facet_loc, loc, rhat)
     switch (p) { case 1: CC(1); break; case 2: CC(2); break; case 3: CC(3); break; }
 #undef CC
@@ -1141,7 +1148,7 @@ void launch_condense(int p, int nk, int ne, int nb, const double *Zr, const doub
 
 void launch_recover(int p, int nk, int nb, const double *Ar, const double *Wr, const int *cell_facet,
                     const int8_t *cell_rev, const double *rc, const double *lam, double *q, hipStream_t s) {
-#define RC(P) hipLaunchKernelGGL(k_recover<P>, GRID(nk * nb, 256), 0, s, nk, nb, Ar, Wr, cell_facet, cell_rev, rc, lam, q)
+#define RC(P) hipLaunchKernelGGL(k_recover<P>, GRID8(nk * nb, 256), 0, s, nk, nb, Ar, Wr, cell_facet, cell_rev, rc, lam, q)
     switch (p) { case 1: RC(1); break; case 2: RC(2); break; case 3: RC(3); break; }
 #undef RC
 }

@@ -1,0 +1,387 @@
+// Learned facet-patch smoother: BF16 MFMA inference and training kernels.
+//
+// Per (facet e, right-hand side r) sample: features are the block-Jacobi
+// corrections u = omega D^-1 r of the five facets of e's block row (slot 0 in
+// e's direction, slots 1-4 counter-clockwise around the cell they come from),
+// normalised by their RMS s; h = ReLU(W1 z) with 64 hidden units, y = W2 h;
+// the smoother adds u_e + s y to the iterate.
+//
+// A wavefront handles 16 samples per tile with v_mfma_f32_16x16x16_bf16
+// (lane l holds A[l%16][4(l/16)+v], B[4(l/16)+v][l%16], D[4(l/16)+v][l%16]).
+// The first layer is computed transposed, H^T = W1 Z^T, so its accumulators
+// are already in the B-operand layout the second layer Y^T = W2 H^T needs;
+// in the backward pass dH^T = W2^T dY^T reuses the D layout of Y^T the same
+// way.  Only the two weight-gradient products go through 16x16 LDS transposes.
+#include "hdg_kernels.h"
+
+namespace hdg {
+
+typedef short s4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ short bf_bits(float x) {
+    return (short)__bfloat16_as_ushort(__float2bfloat16(x));
+}
+__device__ __forceinline__ float bf_float(short b) { return __uint_as_float(((unsigned)(unsigned short)b) << 16); }
+
+__device__ __forceinline__ f4_t mfma16(s4_t a, s4_t b, f4_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+template <int M>
+struct MlpTile {
+    static constexpr int K1 = 5 * M;
+    static constexpr int KT = (K1 + 15) / 16;
+    s4_t zb[KT];      // normalised features, B layout of the first layer
+    f4_t pre[4];      // first-layer pre-activations, D layout
+    s4_t hb[4];       // ReLU(pre) in bf16 = B layout of the second layer
+    f4_t y;           // second-layer output, D layout (lanes 0-15 hold o = v)
+    float s;          // RMS of the sample's features
+    int e, r;
+    bool valid;
+};
+
+// Forward pass of one tile of 16 samples (samp0 .. samp0 + 15).  The
+// block-Jacobi corrections are u = y - xi (xi == nullptr: u = y).
+template <int M>
+__device__ void mlp_forward(MlpTile<M> &T, int samp0, int nsamp, int ne, int nb, const double *__restrict__ y,
+                            const double *__restrict__ xi, const int *__restrict__ nbr,
+                            const int8_t *__restrict__ prev, const short *__restrict__ W1b,
+                            const short *__restrict__ W2b) {
+    constexpr int K1 = MlpTile<M>::K1, KT = MlpTile<M>::KT, K1P = KT * 16;
+    const int lane = threadIdx.x & 63;
+    const int col = lane & 15, grp = lane >> 4;
+    const int samp = samp0 + col;
+    T.valid = samp < nsamp;
+    T.e = T.valid ? samp / nb : 0;
+    T.r = T.valid ? samp - T.e * nb : 0;
+    const size_t NE = (size_t)ne;
+    float val[KT][4];
+    float ss = 0.f;
+#pragma unroll
+    for (int kt = 0; kt < KT; ++kt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int f = 16 * kt + 4 * grp + v;
+            float x = 0.f;
+            if (T.valid && f < K1) {
+                const int slot = f / M, node = f % M;
+                int id = T.e, nd = node;
+                if (slot > 0) {
+                    id = nbr[(size_t)(slot - 1) * NE + T.e];
+                    if (prev[(size_t)(slot - 1) * NE + T.e]) nd = M - 1 - node;
+                }
+                const size_t o = ((size_t)id * M + nd) * nb + T.r;
+                x = (float)(xi ? y[o] - xi[o] : y[o]);
+            }
+            val[kt][v] = x;
+            ss += x * x;
+        }
+    ss += __shfl_xor(ss, 16, 64);
+    ss += __shfl_xor(ss, 32, 64);
+    T.s = sqrtf(ss / (float)K1);
+    const float inv = T.s > 0.f ? 1.f / T.s : 0.f;
+#pragma unroll
+    for (int kt = 0; kt < KT; ++kt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) T.zb[kt][v] = bf_bits(val[kt][v] * inv);
+    // layer 1 (transposed): H^T[16 mt + i][sample] = sum_k W1[16 mt + i][k] z[sample][k]
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+        f4_t acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kt = 0; kt < KT; ++kt) {
+            const s4_t a = *reinterpret_cast<const s4_t *>(W1b + (size_t)(16 * mt + col) * K1P + 16 * kt + 4 * grp);
+            acc = mfma16(a, T.zb[kt], acc);
+        }
+        T.pre[mt] = acc;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) T.hb[mt][v] = bf_bits(fmaxf(acc[v], 0.f));
+    }
+    // layer 2 (transposed): Y^T[o][sample] = sum_h W2[o][h] H^T[h][sample]
+    f4_t out = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+        const s4_t a = *reinterpret_cast<const s4_t *>(W2b + (size_t)col * 64 + 16 * mt + 4 * grp);
+        out = mfma16(a, T.hb[mt], out);
+    }
+    T.y = out;
+}
+
+// Learned smoothing step.  y = xi + u is the block-Jacobi sweep of the
+// iterate xi (xi == nullptr: zero iterate, y = u); xo = y + s MLP(u-patch).
+template <int M>
+__global__ __launch_bounds__(256) void k_mlp_smooth(int ne, int nb, const double *__restrict__ y,
+                                                    const double *__restrict__ xi, const int *__restrict__ nbr,
+                                                    const int8_t *__restrict__ prev, const short *__restrict__ W1b,
+                                                    const short *__restrict__ W2b, double *__restrict__ xo) {
+    const int nsamp = ne * nb;
+    const int wave = (xcd_block() * blockDim.x + threadIdx.x) >> 6;
+    const int samp0 = wave * 16;
+    if (samp0 >= nsamp) return;   // whole wavefront leaves together
+    MlpTile<M> T;
+    mlp_forward<M>(T, samp0, nsamp, ne, nb, y, xi, nbr, prev, W1b, W2b);
+    const int lane = threadIdx.x & 63;
+    if (lane < 16 && T.valid) {
+#pragma unroll
+        for (int o = 0; o < M; ++o) {
+            const size_t idx = ((size_t)T.e * M + o) * nb + T.r;
+            xo[idx] = y[idx] + (double)(T.s * T.y[o]);
+        }
+    }
+}
+
+// Loss and weight gradients over all (facet, rhs) samples of one data set.
+// Targets t are normalised per sample by s.  Every block runs the same
+// number of tile iterations (tiles past the end contribute nothing) so the
+// block barriers around the LDS transposes are uniform.  Per-wave partial
+// sums: dW1 [64][K1P], dW2 [16][64] (unscaled: d = 2 (y - t/s)), loss.
+template <int M>
+__global__ __launch_bounds__(256) void k_mlp_grad(int ne, int nb, const double *__restrict__ u,
+                                                  const double *__restrict__ t, const int *__restrict__ nbr,
+                                                  const int8_t *__restrict__ prev, const short *__restrict__ W1b,
+                                                  const short *__restrict__ W2b, int iters,
+                                                  float *__restrict__ pdW1, float *__restrict__ pdW2,
+                                                  float *__restrict__ ploss) {
+    constexpr int KT = MlpTile<M>::KT, K1P = KT * 16;
+    __shared__ unsigned short lds[4][4 + KT + 1 + 4][256];
+    const int nsamp = ne * nb;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int col = lane & 15, grp = lane >> 4;
+    const int wid = blockIdx.x * 4 + w;
+    const int nwaves = gridDim.x * 4;
+    unsigned short(*Tdh)[256] = &lds[w][0];
+    unsigned short(*Tz)[256] = &lds[w][4];
+    unsigned short *Tdy = lds[w][4 + KT];
+    unsigned short(*Th)[256] = &lds[w][4 + KT + 1];
+
+    f4_t g1[4][KT], g2[4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+        g2[mt] = f4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kt = 0; kt < KT; ++kt) g1[mt][kt] = f4_t{0.f, 0.f, 0.f, 0.f};
+    }
+    float lsum = 0.f;
+
+    for (int it = 0; it < iters; ++it) {
+        const int tile = wid + it * nwaves;
+        MlpTile<M> T;
+        mlp_forward<M>(T, tile * 16, nsamp, ne, nb, u, nullptr, nbr, prev, W1b, W2b);
+        // d = 2 (y - t/s) on the M valid outputs (lanes 0-15 hold o = v)
+        s4_t dyb;
+        {
+            const float inv = T.s > 0.f ? 1.f / T.s : 0.f;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                float d = 0.f;
+                if (grp == 0 && v < M && T.valid) {
+                    const float tau = (float)t[((size_t)T.e * M + v) * nb + T.r] * inv;
+                    const float diff = T.y[v] - tau;
+                    lsum += diff * diff;
+                    d = 2.f * diff;
+                }
+                dyb[v] = bf_bits(d);
+            }
+        }
+        // dH^T = W2^T dY^T, masked by ReLU'
+        s4_t dhb[4];
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            s4_t a;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) a[v] = W2b[(size_t)(4 * grp + v) * 64 + 16 * mt + col];
+            const f4_t dh = mfma16(a, dyb, f4_t{0.f, 0.f, 0.f, 0.f});
+#pragma unroll
+            for (int v = 0; v < 4; ++v) dhb[mt][v] = bf_bits(T.pre[mt][v] > 0.f ? dh[v] : 0.f);
+        }
+        // stage D-layout tiles (row = 4 grp + v, column = sample) for the transposes
+        __syncthreads();
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int o = (4 * grp + v) * 16 + col;
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) {
+                Tdh[mt][o] = (unsigned short)dhb[mt][v];
+                Th[mt][o] = (unsigned short)T.hb[mt][v];
+            }
+#pragma unroll
+            for (int kt = 0; kt < KT; ++kt) Tz[kt][o] = (unsigned short)T.zb[kt][v];
+            Tdy[o] = (unsigned short)dyb[v];
+        }
+        __syncthreads();
+        // read back as [row = lane % 16][sample = 4 grp + v]
+        const int ib = col * 16 + 4 * grp;
+        s4_t dyA;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) dyA[v] = (short)Tdy[ib + v];
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            s4_t dhA, hB;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                dhA[v] = (short)Tdh[mt][ib + v];
+                hB[v] = (short)Th[mt][ib + v];
+            }
+            // dW2[o][16 mt + h] += sum_s dY^T[o][s] H[s][h]
+            g2[mt] = mfma16(dyA, hB, g2[mt]);
+#pragma unroll
+            for (int kt = 0; kt < KT; ++kt) {
+                s4_t zB;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) zB[v] = (short)Tz[kt][ib + v];
+                // dW1[16 mt + h][16 kt + k] += sum_s dH^T[h][s] Z[s][k]
+                g1[mt][kt] = mfma16(dhA, zB, g1[mt][kt]);
+            }
+        }
+    }
+    // per-wave partials
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+#pragma unroll
+            for (int kt = 0; kt < KT; ++kt)
+                pdW1[(size_t)wid * 64 * K1P + (size_t)(16 * mt + 4 * grp + v) * K1P + 16 * kt + col] = g1[mt][kt][v];
+            pdW2[(size_t)wid * 16 * 64 + (size_t)(4 * grp + v) * 64 + 16 * mt + col] = g2[mt][v];
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) lsum += __shfl_xor(lsum, off, 64);
+    if (lane == 0) ploss[wid] = lsum;
+}
+
+// Sum of the per-wave partials in wave order: g[i] for i < n1 + n2 (+ loss).
+__global__ void k_mlp_reduce(int nwaves, int n1, int n2, const float *__restrict__ p1, const float *__restrict__ p2,
+                             const float *__restrict__ pl, float *__restrict__ g, double *__restrict__ loss) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n1) {
+        float s = 0.f;
+        for (int w = 0; w < nwaves; ++w) s += p1[(size_t)w * n1 + i];
+        g[i] = s;
+    } else if (i < n1 + n2) {
+        float s = 0.f;
+        for (int w = 0; w < nwaves; ++w) s += p2[(size_t)w * n2 + (i - n1)];
+        g[i] = s;
+    } else if (i == n1 + n2) {
+        double s = 0.0;
+        for (int w = 0; w < nwaves; ++w) s += pl[w];
+        loss[0] = s;
+    }
+}
+
+// Adam on the FP32 master weights [W1 (64 x K1P) | W2 (16 x 64)] with the
+// gradient g scaled by gscale; entries outside the real (64 x 5m, m x 64)
+// blocks stay zero.  Refreshes the BF16 copies.
+__global__ void k_adam(int n1, int n2, int k1, int k1p, int m, const float *__restrict__ g, float gscale,
+                       float *__restrict__ w, float *__restrict__ m1, float *__restrict__ m2, float lr, float b1,
+                       float b2, float eps, float c1, float c2, short *__restrict__ wb) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n1 + n2) return;
+    bool live;
+    if (i < n1) live = (i % k1p) < k1;
+    else live = ((i - n1) / 64) < m;
+    if (live) {
+        const float gi = g[i] * gscale;
+        const float a = b1 * m1[i] + (1.f - b1) * gi;
+        const float b = b2 * m2[i] + (1.f - b2) * gi * gi;
+        m1[i] = a;
+        m2[i] = b;
+        w[i] -= lr * (a / c1) / (sqrtf(b / c2) + eps);
+    } else {
+        w[i] = 0.f;
+    }
+    wb[i] = bf_bits(w[i]);
+}
+
+__global__ void k_to_bf16(int n, const float *__restrict__ w, short *__restrict__ wb) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) wb[i] = bf_bits(w[i]);
+}
+
+// x[e][k] += (1 - k/p) qc[v0] + (k/p) qc[v1]  (prolongation pi of a P1 vector)
+template <int M>
+__global__ void k_prolong_trace(int ne, int nb, const int *__restrict__ fvert, const double *__restrict__ qc,
+                                double *__restrict__ x) {
+    constexpr int P = M - 1;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ne * nb) return;
+    const int e = t / nb, r = t - e * nb;
+    const double q0 = qc[(size_t)fvert[2 * e] * nb + r], q1 = qc[(size_t)fvert[2 * e + 1] * nb + r];
+#pragma unroll
+    for (int k = 0; k < M; ++k) x[((size_t)e * M + k) * nb + r] += (1.0 - (double)k / P) * q0 + ((double)k / P) * q1;
+}
+
+// out = a x + b y + c z (elementwise)
+__global__ void k_lin3(int64_t n, double a, const double *__restrict__ x, double b, const double *__restrict__ y,
+                       double c, const double *__restrict__ z, double *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    out[i] = a * x[i] + (y ? b * y[i] : 0.0) + (z ? c * z[i] : 0.0);
+}
+
+#define GRIDL(n, b) dim3((unsigned)(((n) + (b) - 1) / (b))), dim3(b)
+
+void launch_mlp_smooth(int p, int ne, int nb, const double *y, const double *xi, const int *nbr, const int8_t *prev,
+                       const short *W1b, const short *W2b, double *xo, hipStream_t s) {
+    const int64_t waves = ((int64_t)ne * nb + 15) / 16;
+    const int64_t blocks = (waves + 3) / 4;
+    const dim3 grid((unsigned)(((blocks + 7) / 8) * 8)), block(256);   // multiple of 8 for the XCD remap
+    switch (p) {
+    case 1: hipLaunchKernelGGL(k_mlp_smooth<2>, grid, block, 0, s, ne, nb, y, xi, nbr, prev, W1b, W2b, xo); break;
+    case 2: hipLaunchKernelGGL(k_mlp_smooth<3>, grid, block, 0, s, ne, nb, y, xi, nbr, prev, W1b, W2b, xo); break;
+    case 3: hipLaunchKernelGGL(k_mlp_smooth<4>, grid, block, 0, s, ne, nb, y, xi, nbr, prev, W1b, W2b, xo); break;
+    }
+}
+
+int mlp_k1p(int p) { return ((5 * (p + 1) + 15) / 16) * 16; }
+
+int mlp_grad_waves(int ne, int nb) {
+    const int64_t tiles = ((int64_t)ne * nb + 15) / 16;
+    int64_t blocks = (tiles + 3) / 4;
+    if (blocks > 256) blocks = 256;
+    return (int)blocks * 4;
+}
+
+void launch_mlp_grad(int p, int ne, int nb, const double *u, const double *t, const int *nbr, const int8_t *prev,
+                     const short *W1b, const short *W2b, float *pdW1, float *pdW2, float *ploss, float *g,
+                     double *loss, hipStream_t s) {
+    const int nw = mlp_grad_waves(ne, nb);
+    const int64_t tiles = ((int64_t)ne * nb + 15) / 16;
+    const int iters = (int)((tiles + nw - 1) / nw);
+    const dim3 grid(nw / 4), block(256);
+    switch (p) {
+    case 1: hipLaunchKernelGGL(k_mlp_grad<2>, grid, block, 0, s, ne, nb, u, t, nbr, prev, W1b, W2b, iters, pdW1, pdW2, ploss); break;
+    case 2: hipLaunchKernelGGL(k_mlp_grad<3>, grid, block, 0, s, ne, nb, u, t, nbr, prev, W1b, W2b, iters, pdW1, pdW2, ploss); break;
+    case 3: hipLaunchKernelGGL(k_mlp_grad<4>, grid, block, 0, s, ne, nb, u, t, nbr, prev, W1b, W2b, iters, pdW1, pdW2, ploss); break;
+    }
+    const int n1 = 64 * mlp_k1p(p), n2 = 16 * 64;
+    hipLaunchKernelGGL(k_mlp_reduce, GRIDL(n1 + n2 + 1, 256), 0, s, nw, n1, n2, pdW1, pdW2, ploss, g, loss);
+}
+
+void launch_adam(int p, const float *g, float gscale, float *w, float *m1, float *m2, float lr, int step,
+                 short *wb, hipStream_t s) {
+    const int k1p = mlp_k1p(p), n1 = 64 * k1p, n2 = 16 * 64;
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
+    hipLaunchKernelGGL(k_adam, GRIDL(n1 + n2, 256), 0, s, n1, n2, 5 * (p + 1), k1p, p + 1, g, gscale, w, m1, m2, lr,
+                       b1, b2, 1e-8f, c1, c2, wb);
+}
+
+void launch_to_bf16(int n, const float *w, short *wb, hipStream_t s) {
+    hipLaunchKernelGGL(k_to_bf16, GRIDL(n, 256), 0, s, n, w, wb);
+}
+
+void launch_prolong_trace(int p, int ne, int nb, const int *fvert, const double *qc, double *x, hipStream_t s) {
+    switch (p) {
+    case 1: hipLaunchKernelGGL(k_prolong_trace<2>, GRIDL(ne * nb, 256), 0, s, ne, nb, fvert, qc, x); break;
+    case 2: hipLaunchKernelGGL(k_prolong_trace<3>, GRIDL(ne * nb, 256), 0, s, ne, nb, fvert, qc, x); break;
+    case 3: hipLaunchKernelGGL(k_prolong_trace<4>, GRIDL(ne * nb, 256), 0, s, ne, nb, fvert, qc, x); break;
+    }
+}
+
+void launch_lin3(int64_t n, double a, const double *x, double b, const double *y, double c, const double *z,
+                 double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_lin3, GRIDL(n, 256), 0, s, n, a, x, b, y, c, z, out);
+}
+
+}  // namespace hdg

@@ -76,6 +76,11 @@ _SIGS = {
     "hdg_kernel_stats": (_I, [_P, _I, _I, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
                               ctypes.POINTER(ctypes.c_double)]),
     "hdg_copy": (_I, [_P, _P, ctypes.c_int64, _P]),
+    "hdg_mlp_set_weights": (_I, [_P, _P, _P]),
+    "hdg_mlp_get_weights": (_I, [_P, _P, _P]),
+    "hdg_mlp_make_data": (_I, [_P, _I, _P, _P, _P, _I, _P]),
+    "hdg_mlp_loss_grad": (_I, [_P, _I, _P, _P, ctypes.POINTER(ctypes.c_double), _P, _P, _P]),
+    "hdg_mlp_train": (_I, [_P, _I, _P, _I, _I, _I, ctypes.c_double, _P, _P]),
 }
 
 _lib = None
@@ -256,6 +261,45 @@ class HdgSolver:
         rhat = self.condense(r_cell)
         lam, info = self.solve(rhat)
         return self.recover(r_cell, lam), lam, info
+
+    # ------------------------------------------------------------------ learned smoother
+    def mlp_set_weights(self, W1, W2):
+        """W1 (64, 5(p+1)), W2 (p+1, 64); stored as FP32 (Adam state reset)."""
+        W1 = np.ascontiguousarray(W1, dtype=np.float32)
+        W2 = np.ascontiguousarray(W2, dtype=np.float32)
+        if W1.shape != (64, 5 * self.m) or W2.shape != (self.m, 64):
+            raise ValueError("W1 must be (64, 5(p+1)) and W2 (p+1, 64)")
+        _check(self.lib.hdg_mlp_set_weights(self.ctx, W1.ctypes.data, W2.ctypes.data))
+
+    def mlp_get_weights(self):
+        W1 = np.zeros((64, 5 * self.m), dtype=np.float32)
+        W2 = np.zeros((self.m, 64), dtype=np.float32)
+        _check(self.lib.hdg_mlp_get_weights(self.ctx, W1.ctypes.data, W2.ctypes.data))
+        return W1, W2
+
+    def mlp_make_data(self, e, coarse_its: int = 1):
+        """Training pair (u, t) for the trace error e."""
+        nb = self._nrhs(e, 3)
+        u, t = self.trace_zeros(nb), self.trace_zeros(nb)
+        _check(self.lib.hdg_mlp_make_data(self.ctx, nb, _ptr(e), _ptr(u), _ptr(t), int(coarse_its), _stream()))
+        return u, t
+
+    def mlp_loss_grad(self, u, t):
+        nb = self._nrhs(u, 3)
+        loss = ctypes.c_double()
+        dW1 = np.zeros((64, 5 * self.m), dtype=np.float32)
+        dW2 = np.zeros((self.m, 64), dtype=np.float32)
+        _check(self.lib.hdg_mlp_loss_grad(self.ctx, nb, _ptr(u), _ptr(t), ctypes.byref(loss), dW1.ctypes.data,
+                                          dW2.ctypes.data, _stream()))
+        return float(loss.value), dW1, dW2
+
+    def mlp_train(self, e0, cycles: int, coarse_its: int = 1, epochs: int = 1, lr: float = 1e-3):
+        """Adam training in place from the error e0; returns the loss before every step."""
+        nb = self._nrhs(e0, 3)
+        hist = np.zeros(cycles * epochs)
+        _check(self.lib.hdg_mlp_train(self.ctx, nb, _ptr(e0), int(cycles), int(coarse_its), int(epochs),
+                                      float(lr), hist.ctypes.data, _stream()))
+        return hist
 
     # ------------------------------------------------------------------ measurement
     def set_timing(self, repeat: int):
