@@ -50,6 +50,12 @@ def parse():
                     help="mixed: FP64 Krylov + reduced-precision V-cycle; mixed_ir: FP64 refinement of an FP32 inner solve")
     ap.add_argument("--no-graph", action="store_true", help="launch every kernel eagerly (no HIP graphs)")
     ap.add_argument("--batch", type=int, default=16, help="also time a batch of this many right-hand sides")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-smoother leg")
+    ap.add_argument("--train-batches", type=int, default=32, help="learned smoother: batches of random errors")
+    ap.add_argument("--train-epochs", type=int, default=8, help="learned smoother: Adam steps per batch")
+    ap.add_argument("--learned-nu", type=int, default=1, help="learned smoother: sweeps before and after the coarse solve")
+    ap.add_argument("--headline", default="learned", choices=["learned", "mixed"],
+                    help="which reduced-precision solver `value` reports")
     ap.add_argument("--pmc-run", action="store_true",
                     help="short run for hardware counters: mixed leg only, plus a reference copy kernel")
     return ap.parse_args()
@@ -105,6 +111,9 @@ def main():
     args = parse()
     if args.pmc_run:
         args.no_fp64, args.no_cpu, args.batch = True, True, 0
+        args.no_learned, args.headline = True, "mixed"
+    if args.no_learned:
+        args.headline = "mixed"
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; a multi-GPU run is not provided "
                                    "(right-hand sides would shard across GPUs with no communication)"}))
@@ -113,7 +122,9 @@ def main():
     import torch
 
     import hdg_inputs as hi
-    from paper_2004_09389_amd.hdg import HDG_FP64, HDG_MIXED, HDG_MIXED_IR, HdgSolver
+    from paper_2004_09389_amd.hdg import (HDG_FP64, HDG_MIXED, HDG_MIXED_IR, HDG_SMOOTH_BJACOBI, HDG_SMOOTH_MLP,
+                                          HdgSolver)
+    from paper_2004_09389_amd.learned import train
 
     torch.cuda.set_device(0)
     p, n, nb = args.degree, args.n, args.nrhs
@@ -125,15 +136,35 @@ def main():
     log(f"[bench] mesh+rhs {time.perf_counter() - t0:.1f}s cells={mesh.n_cell} p={p} nrhs={nb}")
     rd = torch.from_numpy(r).to("cuda")
 
-    def make(prec, nb_override=None):
+    trained = {}
+
+    def make(prec, nb_override=None, learned=False):
         t = time.perf_counter()
         s = HdgSolver(hier, p, dt, 1.0, 1.0, 1.0, 0.0, 1.0, rtol=args.rtol, precision=prec,
-                      max_rhs=nb_override or nb,
+                      max_rhs=nb_override or nb, smoother=HDG_SMOOTH_MLP if learned else HDG_SMOOTH_BJACOBI,
+                      **({"nu_pre": args.learned_nu, "nu_post": args.learned_nu} if learned else {}),
                       krylov=2, maxit=200, p1_tail_max=args.tail_max, p1_nu=args.p1_nu,
                       use_graph=0 if args.no_graph else 1)
         torch.cuda.synchronize()
-        log(f"[bench] setup {'mixed' if prec else 'fp64'} {time.perf_counter() - t:.2f}s "
-            f"device={s.sizes.device_bytes / 2**30:.2f} GiB")
+        log(f"[bench] setup {'mixed' if prec else 'fp64'}{' learned' if learned else ''} "
+            f"{time.perf_counter() - t:.2f}s device={s.sizes.device_bytes / 2**30:.2f} GiB")
+        if learned:
+            if "W" not in trained:
+                # train once on random initial errors (seeds 1000+); not part of a step
+                W1, _ = hi.mlp_init(p + 1, 64, 0)
+                s.mlp_set_weights(W1.astype(np.float32), np.zeros((p + 1, 64), np.float32))
+                hist, tt = train(s, batches=args.train_batches, epochs=args.train_epochs, lr=3e-3)
+                trained["W"] = s.mlp_get_weights()
+                trained["info"] = {"seconds": round(tt, 3), "adam_steps": int(len(hist)),
+                                   "errors_per_batch": int(s.options.max_rhs), "batches": args.train_batches,
+                                   "loss_first": round(float(hist[0]), 4), "loss_last": round(float(hist[-1]), 4),
+                                   "seeds": f"1000-{1000 + args.train_batches - 1}",
+                                   "nu_pre_post": args.learned_nu}
+                log(f"[bench] trained the smoother in {tt:.2f}s: loss {hist[0]:.4f} -> {hist[-1]:.4f}")
+            else:
+                s.mlp_set_weights(*trained["W"])
+            tuned = s.autotune(nb_override or nb)
+            log(f"[bench] autotune: {tuned}")
         return s, time.perf_counter() - t
 
     def run(s, steps, timing=0, rhs=None, nbb=None):
@@ -159,24 +190,26 @@ def main():
 
     results = {}
     mixed_prec = HDG_MIXED if args.mixed_mode == "mixed" else HDG_MIXED_IR
-    legs = [("mixed", mixed_prec)] + ([] if args.no_fp64 else [("fp64", HDG_FP64)])
-    classes = ("apply", "sweep", "residual", "condense", "recover")
+    legs = [("mixed", mixed_prec)] + ([] if args.no_learned else [("learned", mixed_prec)]) \
+        + ([] if args.no_fp64 else [("fp64", HDG_FP64)])
+    classes = ("apply", "sweep", "residual", "condense", "recover", "mlp")
     for name, prec in legs:
-        s, tsetup = make(prec)
+        s, tsetup = make(prec, learned=name == "learned")
         run(s, args.warmup)
         el, infos, lam, q = run(s, args.steps)
         its = [i.iters for inf in infos for i in inf]
         res = max(i.rel_res for inf in infos for i in inf)
         rec = dict(el=el, its=float(np.mean(its)), res=res, lam=lam.clone(), setup=tsetup,
-                   refinements=float(np.mean([i.refinements for inf in infos for i in inf])))
-        if name == "mixed":
+                   refinements=float(np.mean([i.refinements for inf in infos for i in inf])),
+                   fallbacks=int(sum(i.fallbacks for inf in infos for i in inf)))
+        if name == args.headline:
             # instrumented pass: the same steps again, every launch of the
             # instrumented kernel classes bracketed by HIP events on its stream
             run(s, args.steps, timing=TIMING_REPEAT)
             rec["stats"] = {(k, pr): s.kernel_stats(k, pr) for k in classes for pr in (HDG_FP64, HDG_MIXED)}
             s.set_timing(False)
         if args.batch > 1 and not args.pmc_run:
-            sb, _ = make(prec, nb_override=args.batch)
+            sb, _ = make(prec, nb_override=args.batch, learned=name == "learned")
             rb = torch.from_numpy(hi.fourier_rhs_torus(mesh, p, 200, nrhs=args.batch)).to("cuda")
             run(sb, args.warmup, rhs=rb, nbb=args.batch)
             elb, infb, _, _ = run(sb, args.steps, rhs=rb, nbb=args.batch)
@@ -205,7 +238,7 @@ def main():
         log(f"[bench] reference copy: {n_copy * 8} bytes read, {n_copy * 8} bytes written per launch")
         return
 
-    mx = results["mixed"]
+    mx = results[args.headline]
     steps = args.steps
     value = steps * nb / mx["el"]
     # dominant kernel: largest total event time in the instrumented pass
@@ -247,7 +280,9 @@ def main():
                    "rtol": args.rtol, "precision": args.mixed_mode,
                    "coarsest_p1": f"{args.coarse}x{args.coarse}", "p1_tail_max": args.tail_max,
                    "hip_graphs": not args.no_graph},
+        "smoother": "learned" if args.headline == "learned" else "block-jacobi",
         "iters": mx["its"],
+        "fallbacks": mx["fallbacks"],
         "refinements": mx["refinements"],
         "rel_res_max": mx["res"],
         "dof_per_s": {"trace": round(value * 3 * (p + 1) * mesh.n_cell / 2, 1),
@@ -257,6 +292,15 @@ def main():
     }
     if "batched" in mx:
         out["batched"] = mx["batched"]
+    for other in ("mixed", "learned"):
+        if other != args.headline and other in results:
+            o = results[other]
+            out[f"{other}_leg"] = {"value": round(steps * nb / o["el"], 3), "unit": "solves/s",
+                                   "ms_per_step": round(1e3 * o["el"] / steps, 4), "iters": o["its"],
+                                   "rel_res_max": o["res"], "fallbacks": o["fallbacks"],
+                                   **({"batched": o["batched"]} if "batched" in o else {})}
+    if "learned" in results:
+        out["training"] = trained["info"]
     if "fp64" in results:
         fp = results["fp64"]
         out["fp64_baseline"] = {"value": round(steps * nb / fp["el"], 3), "unit": "solves/s",

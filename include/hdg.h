@@ -116,8 +116,10 @@ typedef struct {
     int32_t max_rhs;            /* largest nrhs any call will use (default 1, max 64) */
     int32_t use_graph;          /* replay each Krylov iteration as a captured HIP graph (default 1);
                                    off while kernel timing is enabled */
-    double  fallback_ratio;     /* learned smoother: revert to block-Jacobi when the residual
-                                   shrinks by less than this per iteration (default 0.5) */
+    double  fallback_ratio;     /* learned smoother: revert to block-Jacobi when the relative
+                                   residual shrinks by less than this factor per iteration, as a
+                                   geometric mean over the current restart cycle, checked from
+                                   its second iteration on (default 0.5) */
     int32_t p1_tail_max;        /* P1 levels with at most this many vertices run inside one
                                    single-workgroup kernel (default 4096, max 4096, 0 = never) */
 } hdg_options;
@@ -211,8 +213,8 @@ const char *hdg_last_error(void);
  * (beta 0.9, 0.999, eps 1e-8).  The weights start at zero, where the
  * learned step is the block-Jacobi step.  Selected by opt.smoother =
  * HDG_SMOOTH_MLP in hdg_setup (FGMRES only; hdg_solve reverts to block-Jacobi
- * for the rest of a solve, counting info.fallbacks, once the relative
- * residual falls by less than a factor fallback_ratio over one iteration).
+ * for the rest of a solve, counting info.fallbacks, once the mean residual
+ * reduction per iteration is weaker than fallback_ratio, see hdg_options).
  *
  * Weight layout (host, row-major FP32): W1 [64][5(p+1)], W2 [p+1][64]. */
 int hdg_mlp_set_weights(hdg_ctx *ctx, const float *W1, const float *W2);   /* resets Adam; synchronous */
@@ -239,6 +241,19 @@ int hdg_mlp_loss_grad(hdg_ctx *ctx, int32_t nrhs, const double *u, const double 
 int hdg_mlp_train(hdg_ctx *ctx, int32_t nrhs, const double *e0, int32_t cycles, int32_t coarse_its,
                   int32_t epochs, double lr, double *loss_hist, void *stream);
 
+/* ------------------------------------------------------------------ launch tuning
+ * Launch shapes that do not change results.  hdg_autotune times each
+ * candidate on the context's own mesh at nrhs right-hand sides (HIP events,
+ * a few launches each, on the stream) and keeps the fastest; hdg_set_tuning
+ * imposes values.  Both drop the captured graphs.  Synchronous. */
+typedef struct {
+    int32_t mlp_samples_per_lane; /* samples (facet, rhs) each lane gathers in the learned
+                                     smoothing kernel: 1 or 2 (default 1) */
+} hdg_tuning;
+int hdg_get_tuning(const hdg_ctx *ctx, hdg_tuning *out);
+int hdg_set_tuning(hdg_ctx *ctx, const hdg_tuning *tuning);
+int hdg_autotune(hdg_ctx *ctx, int32_t nrhs, hdg_tuning *chosen, void *stream);
+
 /* ------------------------------------------------------------------ measurement helpers */
 
 /* Per-kernel-class timing with HIP events on the launch stream.
@@ -257,7 +272,8 @@ int hdg_mlp_train(hdg_ctx *ctx, int32_t nrhs, const double *e0, int32_t cycles, 
 #define HDG_KERNEL_RESIDUAL 2   /* r - S x */
 #define HDG_KERNEL_CONDENSE 3
 #define HDG_KERNEL_RECOVER  4
-#define HDG_KERNEL_COUNT    5
+#define HDG_KERNEL_MLP      5   /* learned smoothing step after a sweep (patch gather + network) */
+#define HDG_KERNEL_COUNT    6
 int hdg_set_timing(hdg_ctx *ctx, int32_t enable);
 int hdg_kernel_stats(hdg_ctx *ctx, int32_t kernel, int32_t precision, int64_t *launches,
                      double *total_ms, double *bytes_per_launch);

@@ -94,6 +94,11 @@ void run_step(hdg_ctx *c, uint64_t key, hipStream_t s, const std::function<void(
     HDG_HIP_CHECK(hipGraphLaunch(it->second, s));
 }
 
+void drop_graphs(hdg_ctx *c) {
+    for (auto &g : c->graphs) (void)hipGraphExecDestroy(g.second);
+    c->graphs.clear();
+}
+
 uint64_t graph_key(int kind, int nb, int prec, int idx) {
     return ((uint64_t)kind << 48) | ((uint64_t)nb << 32) | ((uint64_t)prec << 24) | (uint64_t)idx;
 }
@@ -276,10 +281,14 @@ void vcycle_mlp(hdg_ctx *c, int nb, int prec, const double *r, double *z, hipStr
     jacobi0(c, nb, prec, r, scale, rs, c->vz0, s);
     // buffers: x alternates between vx and vx2; the sweep output goes to vres
     double *x = c->vx, *other = c->vx2;
-    hdg::launch_mlp_smooth(c->p, c->n_facet, nb, c->vz0, nullptr, c->nbr, c->prev, W1b, W2b, x, s);
+    hdg::launch_mlp_smooth(c->p, c->n_facet, nb, c->mlp_spl, c->vz0, nullptr, c->nbr, c->prev, W1b, W2b, x, s);
     auto step = [&](double *out) {
         op_sweep(c, nb, prec, x, c->vz0, nullptr, c->vres, s);
-        hdg::launch_mlp_smooth(c->p, c->n_facet, nb, c->vres, x, c->nbr, c->prev, W1b, W2b, out, s);
+        {
+            Timed t(c, HDG_KERNEL_MLP, prec, s);
+            for (int rep = 0; rep < t.repeats(); ++rep)
+                hdg::launch_mlp_smooth(c->p, c->n_facet, nb, c->mlp_spl, c->vres, x, c->nbr, c->prev, W1b, W2b, out, s);
+        }
         if (out != z) {
             other = x;
             x = out;
@@ -443,7 +452,7 @@ int solve_fgmres(hdg_ctx *c, int nb, int vc_prec, int op_prec, double inner_eta,
     const int64_t vs = n * c->opt.max_rhs;
     const int R = c->opt.restart;
     const double rtol = c->opt.rtol;
-    std::vector<double> rel(nb, 0.0), cyc0(nb, 0.0), prev_res(nb, 0.0);
+    std::vector<double> rel(nb, 0.0), cyc0(nb, 0.0);
     int its = 0, cycles = 0, fallbacks = 0;
     auto done_info = [&](int status) {
         fill_info(info, nb, its, cycles, rel, status);
@@ -458,7 +467,6 @@ int solve_fgmres(hdg_ctx *c, int nb, int vc_prec, int op_prec, double inner_eta,
         if (its >= c->opt.maxit) return done_info(HDG_ENOTCONV);
         ++cycles;
         cyc0 = rel;
-        prev_res = rel;
         hdg::launch_gmres_start(nb, R, scal(c, SC_RR), c->gm, scal(c, SC_BETA), s);
         int k = 0, pending = -1;
         auto converged = [&](const double *h) {
@@ -493,17 +501,17 @@ int solve_fgmres(hdg_ctx *c, int nb, int vc_prec, int op_prec, double inner_eta,
                     pending = -1;
                     break;
                 }
-                // learned smoother judged by the residual reduction per iteration; block-Jacobi
+                // learned smoother judged by the mean residual reduction per iteration over
+                // this restart cycle (h holds the estimate after j iterations); block-Jacobi
                 // takes over for the rest of the solve when it is too weak
-                if (c->use_mlp_now) {
+                if (c->use_mlp_now && j >= 2) {
                     for (int r = 0; r < nb; ++r)
-                        if (prev_res[r] > 0 && h[r] > c->opt.fallback_ratio * prev_res[r]) {
+                        if (cyc0[r] > 0 && std::pow(h[r] / cyc0[r], 1.0 / j) > c->opt.fallback_ratio) {
                             c->use_mlp_now = false;
                             ++fallbacks;
                             break;
                         }
                 }
-                for (int r = 0; r < nb; ++r) prev_res[r] = h[r];
             }
             pending = slot;
         }
@@ -791,8 +799,7 @@ void destroy_impl(hdg_ctx *c) {
         (void)hipEventDestroy(p.b);
     }
     for (auto e : c->event_pool) (void)hipEventDestroy(e);
-    for (auto &g : c->graphs) (void)hipGraphExecDestroy(g.second);
-    c->graphs.clear();
+    drop_graphs(c);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->hscal) (void)hipHostFree(c->hscal);
     if (c->hlag) (void)hipHostFree(c->hlag);
@@ -1009,12 +1016,13 @@ void mlp_grad(hdg_ctx *c, int nb, const double *u, const double *t, double *loss
     check_launch();
 }
 
-// padded device layout [W1: 64 x K1P | W2: 16 x 64] <-> dense (64 x 5m), (m x 64)
+// packed device layout [W1: 64 x K1P | W2: 16 x 64] <-> dense (64 x 5m), (m x 64);
+// dense W1 column slot * m + node sits at packed column 4 slot + node
 void mlp_pack(const hdg_ctx *c, const float *W1, const float *W2, std::vector<float> &buf) {
     const int m = c->p + 1, k1 = 5 * m, k1p = c->mlp_n1 / 64;
     buf.assign((size_t)c->mlp_n1 + c->mlp_n2, 0.f);
     for (int h = 0; h < 64; ++h)
-        for (int k = 0; k < k1; ++k) buf[(size_t)h * k1p + k] = W1[(size_t)h * k1 + k];
+        for (int k = 0; k < k1; ++k) buf[(size_t)h * k1p + 4 * (k / m) + k % m] = W1[(size_t)h * k1 + k];
     for (int o = 0; o < m; ++o)
         for (int h = 0; h < 64; ++h) buf[(size_t)c->mlp_n1 + o * 64 + h] = W2[(size_t)o * 64 + h];
 }
@@ -1023,7 +1031,7 @@ void mlp_unpack(const hdg_ctx *c, const std::vector<float> &buf, float scale, fl
     const int m = c->p + 1, k1 = 5 * m, k1p = c->mlp_n1 / 64;
     if (W1)
         for (int h = 0; h < 64; ++h)
-            for (int k = 0; k < k1; ++k) W1[(size_t)h * k1 + k] = scale * buf[(size_t)h * k1p + k];
+            for (int k = 0; k < k1; ++k) W1[(size_t)h * k1 + k] = scale * buf[(size_t)h * k1p + 4 * (k / m) + k % m];
     if (W2)
         for (int o = 0; o < m; ++o)
             for (int h = 0; h < 64; ++h) W2[(size_t)o * 64 + h] = scale * buf[(size_t)c->mlp_n1 + o * 64 + h];
@@ -1143,6 +1151,81 @@ extern "C" int hdg_mlp_train(hdg_ctx *c, int32_t nb, const double *e0, int32_t c
     });
 }
 
+// ------------------------------------------------------------------ launch tuning
+
+namespace {
+
+void check_tuning(const hdg_tuning &t) {
+    const int v = t.mlp_samples_per_lane;
+    HDG_REQUIRE(v == 1 || v == 2, "mlp_samples_per_lane must be 1 or 2");
+}
+
+// mean duration (ms) of `reps` launches of fn, after one untimed launch
+template <typename F>
+double time_launches(hipStream_t s, int reps, F &&fn) {
+    hipEvent_t a, b;
+    HDG_HIP_CHECK(hipEventCreate(&a));
+    HDG_HIP_CHECK(hipEventCreate(&b));
+    fn();
+    HDG_HIP_CHECK(hipEventRecord(a, s));
+    for (int i = 0; i < reps; ++i) fn();
+    HDG_HIP_CHECK(hipEventRecord(b, s));
+    HDG_HIP_CHECK(hipEventSynchronize(b));
+    float ms = 0.f;
+    HDG_HIP_CHECK(hipEventElapsedTime(&ms, a, b));
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    check_launch();
+    return ms / reps;
+}
+
+}  // namespace
+
+extern "C" int hdg_get_tuning(const hdg_ctx *c, hdg_tuning *out) {
+    if (!c || !out) return HDG_EINVAL;
+    out->mlp_samples_per_lane = c->mlp_spl;
+    return HDG_OK;
+}
+
+extern "C" int hdg_set_tuning(hdg_ctx *c, const hdg_tuning *t) {
+    if (!c) return HDG_EINVAL;
+    return guard([&] {
+        HDG_REQUIRE(t, "tuning must not be NULL");
+        check_tuning(*t);
+        HDG_HIP_CHECK(hipDeviceSynchronize());
+        drop_graphs(c);
+        c->mlp_spl = t->mlp_samples_per_lane;
+    });
+}
+
+extern "C" int hdg_autotune(hdg_ctx *c, int32_t nb, hdg_tuning *chosen, void *stream) {
+    if (!c) return HDG_EINVAL;
+    return guard([&] {
+        check_nb(c, nb);
+        hipStream_t s = as_stream(stream);
+        HDG_HIP_CHECK(hipDeviceSynchronize());
+        drop_graphs(c);
+        const size_t bytes = sizeof(double) * (size_t)vec_len(c) * nb;
+        HDG_HIP_CHECK(hipMemsetAsync(c->vres, 0, bytes, s));
+        HDG_HIP_CHECK(hipMemsetAsync(c->vx, 0, bytes, s));
+        const short *W1b = c->mlp_wb, *W2b = c->mlp_wb + c->mlp_n1;
+        double best = 1e300;
+        int best_tpw = c->mlp_spl;
+        for (int tpw : {1, 2}) {
+            const double ms = time_launches(s, 10, [&] {
+                hdg::launch_mlp_smooth(c->p, c->n_facet, nb, tpw, c->vres, c->vx, c->nbr, c->prev, W1b, W2b, c->vx2,
+                                       s);
+            });
+            if (ms < best) {
+                best = ms;
+                best_tpw = tpw;
+            }
+        }
+        c->mlp_spl = best_tpw;
+        if (chosen) chosen->mlp_samples_per_lane = best_tpw;
+    });
+}
+
 extern "C" int hdg_set_timing(hdg_ctx *c, int32_t enable) {
     if (!c) return HDG_EINVAL;
     return guard([&] {
@@ -1176,6 +1259,7 @@ extern "C" int hdg_kernel_stats(hdg_ctx *c, int32_t kernel, int32_t prec, int64_
             case HDG_KERNEL_SWEEP: b = ne * (4 * m * m * st + 4 * 4 + 3 * m * 8); break;
             case HDG_KERNEL_CONDENSE: b = nk * (nt * nc * 8 + nc * 8) + ne * m * 8; break;
             case HDG_KERNEL_RECOVER: b = nk * ((nc * nc + nc * nt) * 8 + 2 * nc * 8) + ne * m * 8; break;
+            case HDG_KERNEL_MLP: b = ne * (3 * m * 8 + 4 * 4 + 4); break;
             }
             *bytes_per_launch = b;
         }

@@ -168,6 +168,7 @@ struct hdg_ctx {
 
     // learned smoother: weights [W1 (64 x K1P) | W2 (16 x 64)], FP32 master + Adam moments, BF16 copy
     int mlp_n1 = 0, mlp_n2 = 0, mlp_step = 0;
+    int mlp_spl = 1;                      // samples per lane in the learned smoothing kernel
     bool mlp_ready = false;
     float *mlp_w = nullptr, *mlp_m1 = nullptr, *mlp_m2 = nullptr, *mlp_g = nullptr;
     short *mlp_wb = nullptr;

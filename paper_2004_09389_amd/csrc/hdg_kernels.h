@@ -85,8 +85,8 @@ void launch_sqrt(int nb, const double *in, double *out, hipStream_t s);
 // learned smoother (hdg_mlp.hip)
 int mlp_k1p(int p);
 int mlp_grad_waves(int ne, int nb);
-void launch_mlp_smooth(int p, int ne, int nb, const double *u, const double *xi, const int *nbr, const int8_t *prev,
-                       const short *W1b, const short *W2b, double *xo, hipStream_t s);
+void launch_mlp_smooth(int p, int ne, int nb, int tpw, const double *y, const double *xi, const int *nbr,
+                       const int8_t *prev, const short *W1b, const short *W2b, double *xo, hipStream_t s);
 void launch_mlp_grad(int p, int ne, int nb, const double *u, const double *t, const int *nbr, const int8_t *prev,
                      const short *W1b, const short *W2b, float *pdW1, float *pdW2, float *ploss, float *g,
                      double *loss, hipStream_t s);

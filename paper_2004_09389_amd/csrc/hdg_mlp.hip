@@ -18,6 +18,7 @@ namespace hdg {
 
 typedef short s4_t __attribute__((ext_vector_type(4)));
 typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef double dbl2_t __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ short bf_bits(float x) {
     return (short)__bfloat16_as_ushort(__float2bfloat16(x));
@@ -28,11 +29,34 @@ __device__ __forceinline__ f4_t mfma16(s4_t a, s4_t b, f4_t c) {
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
 
+// Feature k-index layout: slot s (0..4) occupies k = 4 s .. 4 s + 3, node
+// j < M at k = 4 s + j (k-indices with j >= M and k >= 20 are zero), so a
+// first-layer B operand lane (k = 16 kt + 4 grp + v) reads the nodes of one
+// slot, s = 4 kt + grp.  The packed first-layer weights are [64][32] in this
+// layout; K1 = 5 M real features enter the RMS.
+constexpr int MLP_K1P = 32;
+
+struct MlpWeights {
+    s4_t a1[4][2];   // W1 A operands, [hidden tile][k tile]
+    s4_t a2[4];      // W2 A operands, [hidden tile]
+};
+
+__device__ __forceinline__ void mlp_load_weights(MlpWeights &W, const short *__restrict__ W1b,
+                                                 const short *__restrict__ W2b) {
+    const int lane = threadIdx.x & 63, col = lane & 15, grp = lane >> 4;
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+#pragma unroll
+        for (int kt = 0; kt < 2; ++kt)
+            W.a1[mt][kt] = *reinterpret_cast<const s4_t *>(W1b + (16 * mt + col) * MLP_K1P + 16 * kt + 4 * grp);
+        W.a2[mt] = *reinterpret_cast<const s4_t *>(W2b + col * 64 + 16 * mt + 4 * grp);
+    }
+}
+
 template <int M>
 struct MlpTile {
-    static constexpr int K1 = 5 * M;
-    static constexpr int KT = (K1 + 15) / 16;
-    s4_t zb[KT];      // normalised features, B layout of the first layer
+    static_assert(M >= 2 && M <= 4, "one slot must fit one 4-wide k group");
+    s4_t zb[2];       // normalised features, B layout of the first layer
     f4_t pre[4];      // first-layer pre-activations, D layout
     s4_t hb[4];       // ReLU(pre) in bf16 = B layout of the second layer
     f4_t y;           // second-layer output, D layout (lanes 0-15 hold o = v)
@@ -44,11 +68,9 @@ struct MlpTile {
 // Forward pass of one tile of 16 samples (samp0 .. samp0 + 15).  The
 // block-Jacobi corrections are u = y - xi (xi == nullptr: u = y).
 template <int M>
-__device__ void mlp_forward(MlpTile<M> &T, int samp0, int nsamp, int ne, int nb, const double *__restrict__ y,
-                            const double *__restrict__ xi, const int *__restrict__ nbr,
-                            const int8_t *__restrict__ prev, const short *__restrict__ W1b,
-                            const short *__restrict__ W2b) {
-    constexpr int K1 = MlpTile<M>::K1, KT = MlpTile<M>::KT, K1P = KT * 16;
+__device__ void mlp_forward(MlpTile<M> &T, const MlpWeights &W, int samp0, int nsamp, int ne, int nb,
+                            const double *__restrict__ y, const double *__restrict__ xi,
+                            const int *__restrict__ nbr, const int8_t *__restrict__ prev) {
     const int lane = threadIdx.x & 63;
     const int col = lane & 15, grp = lane >> 4;
     const int samp = samp0 + col;
@@ -56,44 +78,48 @@ __device__ void mlp_forward(MlpTile<M> &T, int samp0, int nsamp, int ne, int nb,
     T.e = T.valid ? samp / nb : 0;
     T.r = T.valid ? samp - T.e * nb : 0;
     const size_t NE = (size_t)ne;
-    float val[KT][4];
+    float val[2][4];
     float ss = 0.f;
 #pragma unroll
-    for (int kt = 0; kt < KT; ++kt)
+    for (int kt = 0; kt < 2; ++kt) {
+        const int slot = 4 * kt + grp;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int f = 16 * kt + 4 * grp + v;
-            float x = 0.f;
-            if (T.valid && f < K1) {
-                const int slot = f / M, node = f % M;
-                int id = T.e, nd = node;
-                if (slot > 0) {
-                    id = nbr[(size_t)(slot - 1) * NE + T.e];
-                    if (prev[(size_t)(slot - 1) * NE + T.e]) nd = M - 1 - node;
-                }
-                const size_t o = ((size_t)id * M + nd) * nb + T.r;
-                x = (float)(xi ? y[o] - xi[o] : y[o]);
+        for (int v = 0; v < 4; ++v) val[kt][v] = 0.f;
+        if (T.valid && slot < 5) {
+            int id = T.e;
+            bool rv = false;
+            if (slot > 0) {
+                id = nbr[(size_t)(slot - 1) * NE + T.e];
+                rv = prev[(size_t)(slot - 1) * NE + T.e] != 0;
             }
-            val[kt][v] = x;
-            ss += x * x;
+            const size_t base = (size_t)id * M * nb + T.r;
+            double d[M];
+#pragma unroll
+            for (int j = 0; j < M; ++j) {
+                const size_t o = base + (size_t)j * nb;
+                d[j] = xi ? y[o] - xi[o] : y[o];
+            }
+#pragma unroll
+            for (int j = 0; j < M; ++j) {
+                val[kt][j] = (float)(rv ? d[M - 1 - j] : d[j]);
+                ss += val[kt][j] * val[kt][j];
+            }
         }
+    }
     ss += __shfl_xor(ss, 16, 64);
     ss += __shfl_xor(ss, 32, 64);
-    T.s = sqrtf(ss / (float)K1);
+    T.s = sqrtf(ss / (float)(5 * M));
     const float inv = T.s > 0.f ? 1.f / T.s : 0.f;
 #pragma unroll
-    for (int kt = 0; kt < KT; ++kt)
+    for (int kt = 0; kt < 2; ++kt)
 #pragma unroll
         for (int v = 0; v < 4; ++v) T.zb[kt][v] = bf_bits(val[kt][v] * inv);
     // layer 1 (transposed): H^T[16 mt + i][sample] = sum_k W1[16 mt + i][k] z[sample][k]
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt) {
         f4_t acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int kt = 0; kt < KT; ++kt) {
-            const s4_t a = *reinterpret_cast<const s4_t *>(W1b + (size_t)(16 * mt + col) * K1P + 16 * kt + 4 * grp);
-            acc = mfma16(a, T.zb[kt], acc);
-        }
+        acc = mfma16(W.a1[mt][0], T.zb[0], acc);
+        acc = mfma16(W.a1[mt][1], T.zb[1], acc);
         T.pre[mt] = acc;
 #pragma unroll
         for (int v = 0; v < 4; ++v) T.hb[mt][v] = bf_bits(fmaxf(acc[v], 0.f));
@@ -101,32 +127,159 @@ __device__ void mlp_forward(MlpTile<M> &T, int samp0, int nsamp, int ne, int nb,
     // layer 2 (transposed): Y^T[o][sample] = sum_h W2[o][h] H^T[h][sample]
     f4_t out = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt) {
-        const s4_t a = *reinterpret_cast<const s4_t *>(W2b + (size_t)col * 64 + 16 * mt + 4 * grp);
-        out = mfma16(a, T.hb[mt], out);
-    }
+    for (int mt = 0; mt < 4; ++mt) out = mfma16(W.a2[mt], T.hb[mt], out);
     T.y = out;
 }
 
 // Learned smoothing step.  y = xi + u is the block-Jacobi sweep of the
 // iterate xi (xi == nullptr: zero iterate, y = u); xo = y + s MLP(u-patch).
-template <int M>
+//
+// Each lane gathers the patches of SPL samples itself (16-byte loads at
+// nrhs = 1), normalises them and stages the BF16 features in LDS as
+// [sample][k]; the wavefront then runs the 64 SPL / 16 tiles through the
+// matrix cores with the weights held in registers, parks the outputs in the
+// same LDS rows and every lane finishes its own samples.  Only wave-local LDS traffic, so
+// no block barrier is needed beyond the wave's own ordering.
+constexpr int MLP_ZROW = 40;   // LDS row stride of a sample's features (shorts): 80 B
+// Loads the M trace values of facet id for right-hand side r: contiguous
+// (16-byte loads where aligned) when NB1, strided by nb otherwise.
+template <int M, bool NB1>
+__device__ __forceinline__ void load_facet(const double *__restrict__ v, size_t base, int nb, double (&d)[M]) {
+    if constexpr (NB1 && M % 2 == 0) {
+#pragma unroll
+        for (int j = 0; j < M; j += 2) {
+            const dbl2_t a = *reinterpret_cast<const dbl2_t *>(v + base + j);
+            d[j] = a.x;
+            d[j + 1] = a.y;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < M; ++j) d[j] = v[base + (size_t)(NB1 ? j : j * nb)];
+    }
+}
+
+template <int M, int SPL, bool HAS_X, bool NB1>
 __global__ __launch_bounds__(256) void k_mlp_smooth(int ne, int nb, const double *__restrict__ y,
                                                     const double *__restrict__ xi, const int *__restrict__ nbr,
                                                     const int8_t *__restrict__ prev, const short *__restrict__ W1b,
                                                     const short *__restrict__ W2b, double *__restrict__ xo) {
+    constexpr int WS = 64 * SPL;   // samples per wavefront
+    __shared__ short zs[4][WS * MLP_ZROW];
     const int nsamp = ne * nb;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int wave = (xcd_block() * blockDim.x + threadIdx.x) >> 6;
-    const int samp0 = wave * 16;
-    if (samp0 >= nsamp) return;   // whole wavefront leaves together
-    MlpTile<M> T;
-    mlp_forward<M>(T, samp0, nsamp, ne, nb, y, xi, nbr, prev, W1b, W2b);
-    const int lane = threadIdx.x & 63;
-    if (lane < 16 && T.valid) {
+    const int wbase = wave * WS;
+    if (wbase >= nsamp) return;   // whole wavefront leaves together
+    short *Z = zs[w];
+    const size_t NE = (size_t)ne;
+    float sc[SPL];
+    double ye[SPL][M];
+    // gather, normalise, stage
 #pragma unroll
-        for (int o = 0; o < M; ++o) {
-            const size_t idx = ((size_t)T.e * M + o) * nb + T.r;
-            xo[idx] = y[idx] + (double)(T.s * T.y[o]);
+    for (int q = 0; q < SPL; ++q) {
+        const int ls = q * 64 + lane, samp = wbase + ls;
+        float u[5][M];
+        float ss = 0.f;
+        if (samp < nsamp) {
+            const int e = NB1 ? samp : samp / nb, r = NB1 ? 0 : samp - e * nb;
+            int id[5];
+            bool rv[5];
+            id[0] = e;
+            rv[0] = false;
+#pragma unroll
+            for (int k = 1; k < 5; ++k) {
+                id[k] = nbr[(size_t)(k - 1) * NE + e];
+                rv[k] = prev[(size_t)(k - 1) * NE + e] != 0;
+            }
+            double dy[5][M], dx[5][M];
+#pragma unroll
+            for (int k = 0; k < 5; ++k) {
+                const size_t base = (size_t)id[k] * M * (NB1 ? 1 : nb) + r;
+                load_facet<M, NB1>(y, base, nb, dy[k]);
+                if constexpr (HAS_X) load_facet<M, NB1>(xi, base, nb, dx[k]);
+            }
+#pragma unroll
+            for (int j = 0; j < M; ++j) ye[q][j] = dy[0][j];
+#pragma unroll
+            for (int k = 0; k < 5; ++k)
+#pragma unroll
+                for (int j = 0; j < M; ++j) {
+                    const int jj = rv[k] ? M - 1 - j : j;
+                    const double dv = HAS_X ? dy[k][jj] - dx[k][jj] : dy[k][jj];
+                    u[k][j] = (float)dv;
+                    ss += u[k][j] * u[k][j];
+                }
+        } else {
+#pragma unroll
+            for (int k = 0; k < 5; ++k)
+#pragma unroll
+                for (int j = 0; j < M; ++j) u[k][j] = 0.f;
+#pragma unroll
+            for (int j = 0; j < M; ++j) ye[q][j] = 0.0;
+        }
+        const float s = sqrtf(ss / (float)(5 * M));
+        const float inv = s > 0.f ? 1.f / s : 0.f;
+        sc[q] = s;
+        short *row = Z + ls * MLP_ZROW;
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            s4_t v;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) v[j] = j < M ? bf_bits(u[k][j] * inv) : (short)0;
+            *reinterpret_cast<s4_t *>(row + 4 * k) = v;
+        }
+        const s4_t zero = {0, 0, 0, 0};
+#pragma unroll
+        for (int k = 5; k < 8; ++k) *reinterpret_cast<s4_t *>(row + 4 * k) = zero;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // network on the matrix cores
+    MlpWeights W;
+    mlp_load_weights(W, W1b, W2b);
+    const int col = lane & 15, grp = lane >> 4;
+#pragma unroll
+    for (int t = 0; t < WS / 16; ++t) {
+        const short *zr = Z + (t * 16 + col) * MLP_ZROW + 4 * grp;
+        const s4_t z0 = *reinterpret_cast<const s4_t *>(zr);
+        const s4_t z1 = *reinterpret_cast<const s4_t *>(zr + 16);
+        s4_t hb[4];
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            f4_t acc = {0.f, 0.f, 0.f, 0.f};
+            acc = mfma16(W.a1[mt][0], z0, acc);
+            acc = mfma16(W.a1[mt][1], z1, acc);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) hb[mt][v] = bf_bits(fmaxf(acc[v], 0.f));
+        }
+        f4_t out = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) out = mfma16(W.a2[mt], hb[mt], out);
+        // the outputs overwrite the first 16 bytes of the sample's own feature row, which
+        // this tile has already read
+        if (grp == 0) *reinterpret_cast<f4_t *>(Z + (t * 16 + col) * MLP_ZROW) = out;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // finish own samples: xo = y + s out
+#pragma unroll
+    for (int q = 0; q < SPL; ++q) {
+        const int ls = q * 64 + lane, samp = wbase + ls;
+        if (samp >= nsamp) continue;
+        const f4_t out = *reinterpret_cast<const f4_t *>(Z + ls * MLP_ZROW);
+        double res[M];
+#pragma unroll
+        for (int o = 0; o < M; ++o) res[o] = ye[q][o] + (double)(sc[q] * out[o]);
+        if constexpr (NB1 && M % 2 == 0) {
+#pragma unroll
+            for (int o = 0; o < M; o += 2)
+                *reinterpret_cast<dbl2_t *>(xo + (size_t)samp * M + o) = dbl2_t{res[o], res[o + 1]};
+        } else {
+            const int e = NB1 ? samp : samp / nb, r = NB1 ? 0 : samp - e * nb;
+#pragma unroll
+            for (int o = 0; o < M; ++o) xo[((size_t)e * M + o) * (NB1 ? 1 : nb) + r] = res[o];
         }
     }
 }
@@ -143,7 +296,7 @@ __global__ __launch_bounds__(256) void k_mlp_grad(int ne, int nb, const double *
                                                   const short *__restrict__ W2b, int iters,
                                                   float *__restrict__ pdW1, float *__restrict__ pdW2,
                                                   float *__restrict__ ploss) {
-    constexpr int KT = MlpTile<M>::KT, K1P = KT * 16;
+    constexpr int KT = 2, K1P = MLP_K1P;
     __shared__ unsigned short lds[4][4 + KT + 1 + 4][256];
     const int nsamp = ne * nb;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -163,11 +316,13 @@ __global__ __launch_bounds__(256) void k_mlp_grad(int ne, int nb, const double *
         for (int kt = 0; kt < KT; ++kt) g1[mt][kt] = f4_t{0.f, 0.f, 0.f, 0.f};
     }
     float lsum = 0.f;
+    MlpWeights W;
+    mlp_load_weights(W, W1b, W2b);
 
     for (int it = 0; it < iters; ++it) {
         const int tile = wid + it * nwaves;
         MlpTile<M> T;
-        mlp_forward<M>(T, tile * 16, nsamp, ne, nb, u, nullptr, nbr, prev, W1b, W2b);
+        mlp_forward<M>(T, W, tile * 16, nsamp, ne, nb, u, nullptr, nbr, prev);
         // d = 2 (y - t/s) on the M valid outputs (lanes 0-15 hold o = v)
         s4_t dyb;
         {
@@ -272,14 +427,18 @@ __global__ void k_mlp_reduce(int nwaves, int n1, int n2, const float *__restrict
 // Adam on the FP32 master weights [W1 (64 x K1P) | W2 (16 x 64)] with the
 // gradient g scaled by gscale; entries outside the real (64 x 5m, m x 64)
 // blocks stay zero.  Refreshes the BF16 copies.
-__global__ void k_adam(int n1, int n2, int k1, int k1p, int m, const float *__restrict__ g, float gscale,
+__global__ void k_adam(int n1, int n2, int k1p, int m, const float *__restrict__ g, float gscale,
                        float *__restrict__ w, float *__restrict__ m1, float *__restrict__ m2, float lr, float b1,
                        float b2, float eps, float c1, float c2, short *__restrict__ wb) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n1 + n2) return;
     bool live;
-    if (i < n1) live = (i % k1p) < k1;
-    else live = ((i - n1) / 64) < m;
+    if (i < n1) {
+        const int k = i % k1p;   // slot-aligned feature layout: k = 4 slot + node
+        live = k < 20 && (k & 3) < m;
+    } else {
+        live = ((i - n1) / 64) < m;
+    }
     if (live) {
         const float gi = g[i] * gscale;
         const float a = b1 * m1[i] + (1.f - b1) * gi;
@@ -321,19 +480,35 @@ __global__ void k_lin3(int64_t n, double a, const double *__restrict__ x, double
 
 #define GRIDL(n, b) dim3((unsigned)(((n) + (b) - 1) / (b))), dim3(b)
 
-void launch_mlp_smooth(int p, int ne, int nb, const double *y, const double *xi, const int *nbr, const int8_t *prev,
-                       const short *W1b, const short *W2b, double *xo, hipStream_t s) {
-    const int64_t waves = ((int64_t)ne * nb + 15) / 16;
+void launch_mlp_smooth(int p, int ne, int nb, int spl, const double *y, const double *xi, const int *nbr,
+                       const int8_t *prev, const short *W1b, const short *W2b, double *xo, hipStream_t s) {
+    spl = spl >= 2 ? 2 : 1;
+    const int64_t waves = ((int64_t)ne * nb + 64 * spl - 1) / (64 * spl);
     const int64_t blocks = (waves + 3) / 4;
     const dim3 grid((unsigned)(((blocks + 7) / 8) * 8)), block(256);   // multiple of 8 for the XCD remap
-    switch (p) {
-    case 1: hipLaunchKernelGGL(k_mlp_smooth<2>, grid, block, 0, s, ne, nb, y, xi, nbr, prev, W1b, W2b, xo); break;
-    case 2: hipLaunchKernelGGL(k_mlp_smooth<3>, grid, block, 0, s, ne, nb, y, xi, nbr, prev, W1b, W2b, xo); break;
-    case 3: hipLaunchKernelGGL(k_mlp_smooth<4>, grid, block, 0, s, ne, nb, y, xi, nbr, prev, W1b, W2b, xo); break;
+    const bool hx = xi != nullptr, n1 = nb == 1;
+#define MS(M, S, X, N) hipLaunchKernelGGL((k_mlp_smooth<M, S, X, N>), grid, block, 0, s, ne, nb, y, xi, nbr, prev, W1b, W2b, xo)
+#define MS_XN(M, S)                          \
+    if (hx) {                                \
+        if (n1) MS(M, S, true, true);        \
+        else MS(M, S, true, false);          \
+    } else {                                 \
+        if (n1) MS(M, S, false, true);       \
+        else MS(M, S, false, false);         \
     }
+#define MS_P(S)                              \
+    switch (p) {                             \
+    case 1: MS_XN(2, S) break;               \
+    case 2: MS_XN(3, S) break;               \
+    case 3: MS_XN(4, S) break;               \
+    }
+    if (spl == 1) { MS_P(1) } else { MS_P(2) }
+#undef MS_P
+#undef MS_XN
+#undef MS
 }
 
-int mlp_k1p(int p) { return ((5 * (p + 1) + 15) / 16) * 16; }
+int mlp_k1p(int) { return MLP_K1P; }
 
 int mlp_grad_waves(int ne, int nb) {
     const int64_t tiles = ((int64_t)ne * nb + 15) / 16;
@@ -363,7 +538,7 @@ void launch_adam(int p, const float *g, float gscale, float *w, float *m1, float
     const int k1p = mlp_k1p(p), n1 = 64 * k1p, n2 = 16 * 64;
     const float b1 = 0.9f, b2 = 0.999f;
     const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
-    hipLaunchKernelGGL(k_adam, GRIDL(n1 + n2, 256), 0, s, n1, n2, 5 * (p + 1), k1p, p + 1, g, gscale, w, m1, m2, lr,
+    hipLaunchKernelGGL(k_adam, GRIDL(n1 + n2, 256), 0, s, n1, n2, k1p, p + 1, g, gscale, w, m1, m2, lr,
                        b1, b2, 1e-8f, c1, c2, wb);
 }
 

@@ -22,7 +22,7 @@ HDG_TORUS, HDG_SPHERE = 0, 1
 HDG_FP64, HDG_MIXED, HDG_MIXED_IR = 0, 1, 2
 HDG_KRYLOV_AUTO, HDG_KRYLOV_PCG, HDG_KRYLOV_FGMRES = 0, 1, 2
 HDG_SMOOTH_BJACOBI, HDG_SMOOTH_MLP = 0, 1
-KERNELS = {"apply": 0, "sweep": 1, "residual": 2, "condense": 3, "recover": 4}
+KERNELS = {"apply": 0, "sweep": 1, "residual": 2, "condense": 3, "recover": 4, "mlp": 5}
 
 
 class HdgMesh(ctypes.Structure):
@@ -57,6 +57,10 @@ class HdgSizes(ctypes.Structure):
                 ("device_bytes", ctypes.c_int64), ("kappa", ctypes.c_double)]
 
 
+class HdgTuning(ctypes.Structure):
+    _fields_ = [("mlp_samples_per_lane", ctypes.c_int32)]
+
+
 _P = ctypes.c_void_p
 _I = ctypes.c_int32
 _SIGS = {
@@ -76,6 +80,9 @@ _SIGS = {
     "hdg_kernel_stats": (_I, [_P, _I, _I, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
                               ctypes.POINTER(ctypes.c_double)]),
     "hdg_copy": (_I, [_P, _P, ctypes.c_int64, _P]),
+    "hdg_get_tuning": (_I, [_P, ctypes.POINTER(HdgTuning)]),
+    "hdg_set_tuning": (_I, [_P, ctypes.POINTER(HdgTuning)]),
+    "hdg_autotune": (_I, [_P, _I, ctypes.POINTER(HdgTuning), _P]),
     "hdg_mlp_set_weights": (_I, [_P, _P, _P]),
     "hdg_mlp_get_weights": (_I, [_P, _P, _P]),
     "hdg_mlp_make_data": (_I, [_P, _I, _P, _P, _P, _I, _P]),
@@ -300,6 +307,24 @@ class HdgSolver:
         _check(self.lib.hdg_mlp_train(self.ctx, nb, _ptr(e0), int(cycles), int(coarse_its), int(epochs),
                                       float(lr), hist.ctypes.data, _stream()))
         return hist
+
+    # ------------------------------------------------------------------ launch tuning
+    def get_tuning(self) -> dict:
+        t = HdgTuning()
+        _check(self.lib.hdg_get_tuning(self.ctx, ctypes.byref(t)))
+        return {"mlp_samples_per_lane": t.mlp_samples_per_lane}
+
+    def set_tuning(self, **kw):
+        t = HdgTuning()
+        _check(self.lib.hdg_get_tuning(self.ctx, ctypes.byref(t)))
+        for k, v in kw.items():
+            setattr(t, k, int(v))
+        _check(self.lib.hdg_set_tuning(self.ctx, ctypes.byref(t)))
+
+    def autotune(self, nrhs: int = 1) -> dict:
+        t = HdgTuning()
+        _check(self.lib.hdg_autotune(self.ctx, int(nrhs), ctypes.byref(t), _stream()))
+        return {"mlp_samples_per_lane": t.mlp_samples_per_lane}
 
     # ------------------------------------------------------------------ measurement
     def set_timing(self, repeat: int):

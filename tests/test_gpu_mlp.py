@@ -239,3 +239,20 @@ def test_fallback_threshold_forces_block_jacobi():
     assert info.fallbacks == 1 and info.status == 0
     assert abs(info.iters - plain.iters) <= 2
     assert rel(lam, ref) < 1e-8
+
+
+def test_tuning_does_not_change_results():
+    """Samples per lane change the launch shape only: bitwise-equal V-cycles."""
+    hier, solver, oracle, mg = setup("torus12_p2_coriolis")
+    W1, W2 = weights(solver.m, 12, scale=0.1)
+    solver.mlp_set_weights(W1, W2)
+    r = to_dev(np.random.default_rng(13).standard_normal((solver.n_facet, solver.m, 1)))
+    outs = []
+    for tpw in (1, 2, 1):
+        solver.set_tuning(mlp_samples_per_lane=tpw)
+        outs.append(host(solver.mg_vcycle(r)))
+    chosen = solver.autotune(1)
+    assert chosen["mlp_samples_per_lane"] in (1, 2) and solver.get_tuning() == chosen
+    outs.append(host(solver.mg_vcycle(r)))
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
