@@ -54,7 +54,7 @@ def parse():
     ap.add_argument("--train-batches", type=int, default=32, help="learned smoother: batches of random errors")
     ap.add_argument("--train-epochs", type=int, default=8, help="learned smoother: Adam steps per batch")
     ap.add_argument("--learned-nu", type=int, default=1, help="learned smoother: sweeps before and after the coarse solve")
-    ap.add_argument("--headline", default="learned", choices=["learned", "mixed"],
+    ap.add_argument("--headline", default="mixed", choices=["learned", "mixed"],
                     help="which reduced-precision solver `value` reports")
     ap.add_argument("--pmc-run", action="store_true",
                     help="short run for hardware counters: mixed leg only, plus a reference copy kernel")

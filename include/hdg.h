@@ -15,7 +15,7 @@
  *     prolongation and the coarse form of Eq. coarse_problem_upwind, the
  *     coarse problem solved by one P1 geometric-multigrid V-cycle.
  *
- * Equations solved (BASELINE form), with c = sqrt(g H):
+ * Equations solved (in the caller's variables), with c = sqrt(g H):
  *     u + dt (f k x u + g grad h) = r_u,     h + dt H div u = r_h.
  * Internally phi = h sqrt(g/H) and kappa = c dt (symmetric form, linearised
  * SWE with flat bathymetry); the trace unknown lam lives in phi units.
@@ -37,7 +37,9 @@
  *   cell arrays   [n_cell][3][n_loc][nrhs]   fields (h, u1, u2), n_loc = (p+1)(p+2)/2
  *   trace arrays  [n_facet][p+1][nrhs]
  * Device pointers are HIP device memory owned by the caller; the library
- * never frees them.  Host pointers are read during the call only.
+ * never frees them.  Trace arrays must be 16-byte aligned (every hipMalloc
+ * and torch allocation is; HDG_EINVAL otherwise).  Host pointers are read
+ * during the call only.
  *
  * Errors: every int-returning entry returns HDG_OK (0) on success, a
  * negative code on failure (message in hdg_last_error(), thread-local), and

@@ -1,6 +1,6 @@
 """HDG and standard-DG systems for one implicit stage of the linearised SWE (oracle).
 
-Equations.  The BASELINE problem  u + dt (f k x u + g grad h) = r_u,
+Equations.  The caller's problem  u + dt (f k x u + g grad h) = r_u,
 h + dt H div u = r_h  is rewritten in the symmetric variables of the paper's
 linearised SWE (Eq. SWE_continuum_linear with flat bathymetry phi_B = 1):
 c = sqrt(g H), phi = h sqrt(g/H), kappa = c dt (the paper's c_g alpha dt with

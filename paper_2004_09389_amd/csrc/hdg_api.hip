@@ -3,6 +3,7 @@
 // V-cycle and measurement helpers.
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <cstring>
 #include <functional>
 #include <utility>
@@ -170,15 +171,15 @@ void op_apply(hdg_ctx *c, int nb, int prec, const double *x, const double *b, do
 }
 
 void op_sweep(hdg_ctx *c, int nb, int prec, const double *x, const double *z0, const double *qc, double *y,
-              hipStream_t s) {
+              hipStream_t s, int out_u = 0) {
     Timed t(c, HDG_KERNEL_SWEEP, prec, s);
     for (int rep = 0; rep < t.repeats(); ++rep) {
         if (prec == HDG_MIXED)
             hdg::launch_sweep<__hip_bfloat16>(c->p, c->n_facet, nb, c->T16, c->nbr, x, z0, qc, c->facet_vert,
-                                              c->opt.omega, y, s);
+                                              c->opt.omega, out_u, y, s);
         else
             hdg::launch_sweep<double>(c->p, c->n_facet, nb, c->T64, c->nbr, x, z0, qc, c->facet_vert,
-                                      c->opt.omega, y, s);
+                                      c->opt.omega, out_u, y, s);
     }
     check_launch();
 }
@@ -271,36 +272,38 @@ void jacobi0(hdg_ctx *c, int nb, int prec, const double *r, const double *scale,
 }
 
 // The same V-cycle with the learned smoother: every smoothing step is the
-// block-Jacobi sweep y = x + omega D^-1 (r - S x) followed by the network,
-// x <- y + s MLP(patch of u = y - x); prolongation x += pi x_P1 before
-// post-smoothing.  The first step from zero is y = z0 = omega D^-1 r.
+// block-Jacobi correction u = omega D^-1 (r - S x) (the sweep kernel returns
+// u alone) followed by the network, x <- x + u + s MLP(patch of u).  The
+// first step from zero uses u = z0 = omega D^-1 r; the prolongation
+// x += pi x_P1 rides in the first post-smoothing step.
 void vcycle_mlp(hdg_ctx *c, int nb, int prec, const double *r, double *z, hipStream_t s,
                 const double *scale = nullptr) {
     double *rs = scale ? const_cast<double *>(r) : nullptr;
     const short *W1b = c->mlp_wb, *W2b = c->mlp_wb + c->mlp_n1;
     jacobi0(c, nb, prec, r, scale, rs, c->vz0, s);
-    // buffers: x alternates between vx and vx2; the sweep output goes to vres
+    // x alternates between vx and vx2; the correction goes to vres
     double *x = c->vx, *other = c->vx2;
-    hdg::launch_mlp_smooth(c->p, c->n_facet, nb, c->mlp_spl, c->vz0, nullptr, c->nbr, c->prev, W1b, W2b, x, s);
-    auto step = [&](double *out) {
-        op_sweep(c, nb, prec, x, c->vz0, nullptr, c->vres, s);
-        {
-            Timed t(c, HDG_KERNEL_MLP, prec, s);
-            for (int rep = 0; rep < t.repeats(); ++rep)
-                hdg::launch_mlp_smooth(c->p, c->n_facet, nb, c->mlp_spl, c->vres, x, c->nbr, c->prev, W1b, W2b, out, s);
-        }
+    auto learned = [&](const double *u, const double *xi, const double *qc, double *out) {
+        Timed t(c, HDG_KERNEL_MLP, prec, s);
+        for (int rep = 0; rep < t.repeats(); ++rep)
+            hdg::launch_mlp_smooth(c->p, c->n_facet, nb, c->mlp_spl, u, xi, qc, c->facet_vert, c->nbr, c->prev, W1b,
+                                   W2b, out, s);
+    };
+    learned(c->vz0, nullptr, nullptr, x);
+    auto step = [&](const double *qc, double *out) {
+        op_sweep(c, nb, prec, x, c->vz0, qc, c->vres, s, 1);
+        learned(c->vres, x, qc, out);
         if (out != z) {
             other = x;
             x = out;
         }
     };
-    for (int k = 1; k < c->opt.nu_pre; ++k) step(other);
+    for (int k = 1; k < c->opt.nu_pre; ++k) step(nullptr, other);
     op_apply(c, nb, prec, x, r, c->vres, s, HDG_KERNEL_RESIDUAL);
     const int L = (int)c->lev.size() - 1;
     hdg::launch_restrict_trace(c->p, c->n_vert, nb, c->vf_row, c->vf_col, c->vres, c->lev[L].b, s);
     const double *xl = p1_vcycle(c, L, nb, s);
-    hdg::launch_prolong_trace(c->p, c->n_facet, nb, c->facet_vert, xl, x, s);
-    for (int k = 0; k < c->opt.nu_post; ++k) step(k == c->opt.nu_post - 1 ? z : other);
+    for (int k = 0; k < c->opt.nu_post; ++k) step(k == 0 ? xl : nullptr, k == c->opt.nu_post - 1 ? z : other);
     check_launch();
 }
 
@@ -519,6 +522,12 @@ int solve_fgmres(hdg_ctx *c, int nb, int vc_prec, int op_prec, double inner_eta,
         hdg::launch_lincomb(n, nb, k, c->hy, c->kZ, vs, lam, s);
         check_launch();
     }
+}
+
+// trace vectors are read and written as 16-byte pairs at nrhs = 1
+void check_aligned(const void *p, const char *what) {
+    if (reinterpret_cast<uintptr_t>(p) % 16 != 0)
+        throw Error{HDG_EINVAL, std::string(what) + " must be 16-byte aligned"};
 }
 
 void check_nb(const hdg_ctx *c, int nb) {
@@ -907,6 +916,8 @@ extern "C" int hdg_trace_apply(hdg_ctx *c, int32_t nb, int32_t prec, const doubl
         check_nb(c, nb);
         check_prec(prec);
         HDG_REQUIRE(x && y && x != y, "x and y must be distinct non-NULL buffers");
+        check_aligned(x, "x");
+        check_aligned(y, "y");
         op_apply(c, nb, prec, x, nullptr, y, as_stream(stream), HDG_KERNEL_APPLY);
     });
 }
@@ -917,6 +928,8 @@ extern "C" int hdg_mg_vcycle(hdg_ctx *c, int32_t nb, int32_t prec, const double 
         check_nb(c, nb);
         check_prec(prec);
         HDG_REQUIRE(r && z && r != z, "r and z must be distinct non-NULL buffers");
+        check_aligned(r, "r");
+        check_aligned(z, "z");
         c->use_mlp_now = c->opt.smoother == HDG_SMOOTH_MLP;
         vcycle(c, nb, prec, r, z, as_stream(stream));
     });
@@ -929,6 +942,8 @@ extern "C" int hdg_solve(hdg_ctx *c, int32_t nb, const double *rhat, double *lam
     int rc = guard([&] {
         check_nb(c, nb);
         HDG_REQUIRE(rhat && lam && rhat != lam, "rhat and lam must be distinct non-NULL buffers");
+        check_aligned(rhat, "rhat");
+        check_aligned(lam, "lam");
         hipStream_t s = as_stream(stream);
         const double *h = dots_now(c, nb, rhat, rhat, scal(c, SC_BN2), s);
         hdg::launch_sqrt(nb, scal(c, SC_BN2), c->dbn, s);
@@ -960,6 +975,7 @@ extern "C" int hdg_recover(hdg_ctx *c, int32_t nb, const double *r_cell, const d
     return guard([&] {
         check_nb(c, nb);
         HDG_REQUIRE(r_cell && lam && q_cell, "r_cell, lam and q_cell must not be NULL");
+        check_aligned(lam, "lam");
         hipStream_t s = as_stream(stream);
         Timed t(c, HDG_KERNEL_RECOVER, HDG_FP64, s);
         for (int rep = 0; rep < t.repeats(); ++rep)
@@ -1077,6 +1093,9 @@ extern "C" int hdg_mlp_make_data(hdg_ctx *c, int32_t nb, const double *e, double
     return guard([&] {
         check_nb(c, nb);
         HDG_REQUIRE(e && u && t && e != u && e != t && u != t, "e, u and t must be distinct non-NULL buffers");
+        check_aligned(e, "e");
+        check_aligned(u, "u");
+        check_aligned(t, "t");
         HDG_REQUIRE(coarse_its >= 0 && coarse_its <= 64, "coarse_its must be in 0..64");
         hipStream_t s = as_stream(stream);
         mlp_data_buffers(c);
@@ -1091,6 +1110,8 @@ extern "C" int hdg_mlp_loss_grad(hdg_ctx *c, int32_t nb, const double *u, const 
     return guard([&] {
         check_nb(c, nb);
         HDG_REQUIRE(u && t, "u and t must not be NULL");
+        check_aligned(u, "u");
+        check_aligned(t, "t");
         hipStream_t s = as_stream(stream);
         mlp_grad(c, nb, u, t, c->mlp_loss, s);
         HDG_HIP_CHECK(hipStreamSynchronize(s));
@@ -1112,6 +1133,7 @@ extern "C" int hdg_mlp_train(hdg_ctx *c, int32_t nb, const double *e0, int32_t c
     return guard([&] {
         check_nb(c, nb);
         HDG_REQUIRE(e0, "e0 must not be NULL");
+        check_aligned(e0, "e0");
         HDG_REQUIRE(cycles >= 1 && epochs >= 1 && (int64_t)cycles * epochs <= 4096,
                     "need cycles, epochs >= 1 and cycles * epochs <= 4096");
         HDG_REQUIRE(coarse_its >= 0 && coarse_its <= 64, "coarse_its must be in 0..64");
@@ -1210,19 +1232,19 @@ extern "C" int hdg_autotune(hdg_ctx *c, int32_t nb, hdg_tuning *chosen, void *st
         HDG_HIP_CHECK(hipMemsetAsync(c->vx, 0, bytes, s));
         const short *W1b = c->mlp_wb, *W2b = c->mlp_wb + c->mlp_n1;
         double best = 1e300;
-        int best_tpw = c->mlp_spl;
-        for (int tpw : {1, 2}) {
+        int best_spl = c->mlp_spl;
+        for (int spl : {1, 2}) {
             const double ms = time_launches(s, 10, [&] {
-                hdg::launch_mlp_smooth(c->p, c->n_facet, nb, tpw, c->vres, c->vx, c->nbr, c->prev, W1b, W2b, c->vx2,
-                                       s);
+                hdg::launch_mlp_smooth(c->p, c->n_facet, nb, spl, c->vres, c->vx, nullptr, c->facet_vert, c->nbr,
+                                       c->prev, W1b, W2b, c->vx2, s);
             });
             if (ms < best) {
                 best = ms;
-                best_tpw = tpw;
+                best_spl = spl;
             }
         }
-        c->mlp_spl = best_tpw;
-        if (chosen) chosen->mlp_samples_per_lane = best_tpw;
+        c->mlp_spl = best_spl;
+        if (chosen) chosen->mlp_samples_per_lane = best_spl;
     });
 }
 

@@ -16,6 +16,36 @@ __device__ __forceinline__ int xcd_block() {
     return (blockIdx.x % N_XCD) * per + blockIdx.x / N_XCD;
 }
 
+// Trace vectors are [facet][node][rhs].  With one right-hand side the M
+// values of a facet are contiguous and (M even) 16-byte aligned: load and
+// store them as pairs.  base = facet * M * nb + rhs.
+typedef double trace_dbl2_t __attribute__((ext_vector_type(2)));
+template <int M, bool NB1>
+__device__ __forceinline__ void load_trace(const double *__restrict__ v, size_t base, int nb, double (&d)[M]) {
+    if constexpr (NB1 && M % 2 == 0) {
+#pragma unroll
+        for (int j = 0; j < M; j += 2) {
+            const trace_dbl2_t a = *reinterpret_cast<const trace_dbl2_t *>(v + base + j);
+            d[j] = a.x;
+            d[j + 1] = a.y;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < M; ++j) d[j] = v[base + (size_t)(NB1 ? j : j * nb)];
+    }
+}
+template <int M, bool NB1>
+__device__ __forceinline__ void store_trace(double *__restrict__ v, size_t base, int nb, const double (&d)[M]) {
+    if constexpr (NB1 && M % 2 == 0) {
+#pragma unroll
+        for (int j = 0; j < M; j += 2)
+            *reinterpret_cast<trace_dbl2_t *>(v + base + j) = trace_dbl2_t{d[j], d[j + 1]};
+    } else {
+#pragma unroll
+        for (int j = 0; j < M; ++j) v[base + (size_t)(NB1 ? j : j * nb)] = d[j];
+    }
+}
+
 // padded component count of a facet-row matrix stored with v entries per 16 bytes
 constexpr int wide_padded(int c, int v) { return (c + v - 1) / v * v; }
 
@@ -39,7 +69,7 @@ void launch_jacobi0(int p, int ne, int nb, const MT *Dw, const double *r, const 
                     double *z0, hipStream_t s);
 template <typename MT>
 void launch_sweep(int p, int ne, int nb, const MT *T, const int *nbr, const double *x, const double *z0,
-                  const double *qc, const int *fvert, double omega, double *y, hipStream_t s);
+                  const double *qc, const int *fvert, double omega, int out_u, double *y, hipStream_t s);
 void launch_restrict_trace(int p, int nv, int nb, const int *vf_row, const int *vf_col, const double *res,
                            double *rc, hipStream_t s);
 
@@ -85,8 +115,9 @@ void launch_sqrt(int nb, const double *in, double *out, hipStream_t s);
 // learned smoother (hdg_mlp.hip)
 int mlp_k1p(int p);
 int mlp_grad_waves(int ne, int nb);
-void launch_mlp_smooth(int p, int ne, int nb, int tpw, const double *y, const double *xi, const int *nbr,
-                       const int8_t *prev, const short *W1b, const short *W2b, double *xo, hipStream_t s);
+void launch_mlp_smooth(int p, int ne, int nb, int spl, const double *u, const double *xi, const double *qc,
+                       const int *fvert, const int *nbr, const int8_t *prev, const short *W1b, const short *W2b,
+                       double *xo, hipStream_t s);
 void launch_mlp_grad(int p, int ne, int nb, const double *u, const double *t, const int *nbr, const int8_t *prev,
                      const short *W1b, const short *W2b, float *pdW1, float *pdW2, float *ploss, float *g,
                      double *loss, hipStream_t s);

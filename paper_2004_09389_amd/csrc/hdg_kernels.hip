@@ -376,7 +376,7 @@ __global__ void k_facet_rows(int ne, int nk, const double *__restrict__ Sloc, co
 // five facets of its block row and produces all m rows, so every matrix
 // entry is read exactly once per apply and there are no write conflicts.
 
-template <int M, typename MT>
+template <int M, typename MT, bool NB1>
 __global__ __launch_bounds__(256) void k_trace_apply(int ne, int nb, const MT *__restrict__ S,
                                                      const int *__restrict__ nbr, const double *__restrict__ x,
                                                      const double *__restrict__ b, double *__restrict__ y) {
@@ -384,17 +384,15 @@ __global__ __launch_bounds__(256) void k_trace_apply(int ne, int nb, const MT *_
     constexpr int V = Wide<MT>::V, C = 5 * M * M, G = padded(C, V) / V;
     const int t = xcd_block() * blockDim.x + threadIdx.x;
     if (t >= ne * nb) return;
-    const int e = t / nb, r = t - e * nb;
-    const size_t NE = (size_t)ne;
+    const int e = NB1 ? t : t / nb, r = NB1 ? 0 : t - e * nb;
+    const size_t NE = (size_t)ne, MB = (size_t)M * (NB1 ? 1 : nb);
     int id[5];
     id[0] = e;
 #pragma unroll
     for (int j = 0; j < 4; ++j) id[j + 1] = nbr[j * NE + e];
-    AT xv[5][M];
+    double xd[5][M];
 #pragma unroll
-    for (int j = 0; j < 5; ++j)
-#pragma unroll
-        for (int k = 0; k < M; ++k) xv[j][k] = (AT)x[((size_t)id[j] * M + k) * nb + r];
+    for (int j = 0; j < 5; ++j) load_trace<M, NB1>(x, id[j] * MB + r, nb, xd[j]);
     AT acc[M];
 #pragma unroll
     for (int a = 0; a < M; ++a) acc[a] = 0;
@@ -407,15 +405,21 @@ __global__ __launch_bounds__(256) void k_trace_apply(int ne, int nb, const MT *_
             const int c = g * V + v;
             if (c < C) {
                 const int j = c / (M * M), a = (c / M) % M, k = c % M;
-                acc[a] += w[v] * xv[j][k];
+                acc[a] += w[v] * (AT)xd[j][k];
             }
         }
     }
+    double out[M];
+    if (b) {   // residual b - S x
+        double bv[M];
+        load_trace<M, NB1>(b, e * MB + r, nb, bv);
 #pragma unroll
-    for (int a = 0; a < M; ++a) {
-        const size_t o = ((size_t)e * M + a) * nb + r;
-        y[o] = b ? b[o] - (double)acc[a] : (double)acc[a];   // b != nullptr: residual b - S x
+        for (int a = 0; a < M; ++a) out[a] = bv[a] - (double)acc[a];
+    } else {
+#pragma unroll
+        for (int a = 0; a < M; ++a) out[a] = (double)acc[a];
     }
+    store_trace<M, NB1>(y, e * MB + r, nb, out);
 }
 
 // z0 = omega D^-1 r  (first sweep from a zero guess).  With scale != nullptr
@@ -460,19 +464,19 @@ __global__ __launch_bounds__(256) void k_jacobi0(int ne, int nb, const MT *__res
 // with T_j = omega D^-1 S_j over the four off-diagonal slots and z0 = omega D^-1 r.
 // With qc != nullptr the input is x + pi qc (prolongation of the P1 correction
 // fused in, pi the injection of a P1 function onto the trace nodes).
-template <int M, typename MT>
+template <int M, typename MT, bool NB1>
 __global__ __launch_bounds__(256) void k_sweep(int ne, int nb, const MT *__restrict__ T,
                                                const int *__restrict__ nbr, const double *__restrict__ x,
                                                const double *__restrict__ z0, const double *__restrict__ qc,
-                                               const int *__restrict__ fvert, double omega,
+                                               const int *__restrict__ fvert, double omega, int out_u,
                                                double *__restrict__ y) {
     using AT = typename Acc<MT>::type;
     constexpr int P = M - 1;
     constexpr int V = Wide<MT>::V, C = 4 * M * M, G = padded(C, V) / V;
     const int t = xcd_block() * blockDim.x + threadIdx.x;
     if (t >= ne * nb) return;
-    const int e = t / nb, r = t - e * nb;
-    const size_t NE = (size_t)ne;
+    const int e = NB1 ? t : t / nb, r = NB1 ? 0 : t - e * nb;
+    const size_t NE = (size_t)ne, MB = (size_t)M * (NB1 ? 1 : nb);
     int id[5];
     id[0] = e;
 #pragma unroll
@@ -480,8 +484,7 @@ __global__ __launch_bounds__(256) void k_sweep(int ne, int nb, const MT *__restr
     double xv[5][M];
 #pragma unroll
     for (int j = 0; j < 5; ++j) {
-#pragma unroll
-        for (int k = 0; k < M; ++k) xv[j][k] = x[((size_t)id[j] * M + k) * nb + r];
+        load_trace<M, NB1>(x, id[j] * MB + r, nb, xv[j]);
         if (qc) {
             const double q0 = qc[(size_t)fvert[2 * id[j]] * nb + r];
             const double q1 = qc[(size_t)fvert[2 * id[j] + 1] * nb + r];
@@ -505,11 +508,13 @@ __global__ __launch_bounds__(256) void k_sweep(int ne, int nb, const MT *__restr
             }
         }
     }
+    double zv[M], out[M];
+    load_trace<M, NB1>(z0, e * MB + r, nb, zv);
+    // out_u: the correction y - x alone (the learned step adds it to x itself)
+    const double keep = out_u ? -omega : 1.0 - omega;
 #pragma unroll
-    for (int a = 0; a < M; ++a) {
-        const size_t o = ((size_t)e * M + a) * nb + r;
-        y[o] = (1.0 - omega) * xv[0][a] + z0[o] - (double)acc[a];
-    }
+    for (int a = 0; a < M; ++a) out[a] = keep * xv[0][a] + zv[a] - (double)acc[a];
+    store_trace<M, NB1>(y, e * MB + r, nb, out);
 }
 
 // Restriction pi^T of a trace residual onto the P1 vertices:
@@ -1072,7 +1077,9 @@ void launch_facet_rows(int p, int ne, int nk, const double *Sloc, const int *fac
 template <typename MT>
 void launch_trace_apply(int p, int ne, int nb, const MT *S, const int *nbr, const double *x, const double *b,
                         double *y, hipStream_t s) {
-#define TA(P) hipLaunchKernelGGL((k_trace_apply<P + 1, MT>), GRID8(ne * nb, 256), 0, s, ne, nb, S, nbr, x, b, y)
+#define TA(P)                                                                                          \
+    if (nb == 1) hipLaunchKernelGGL((k_trace_apply<P + 1, MT, true>), GRID8(ne * nb, 256), 0, s, ne, nb, S, nbr, x, b, y); \
+    else hipLaunchKernelGGL((k_trace_apply<P + 1, MT, false>), GRID8(ne * nb, 256), 0, s, ne, nb, S, nbr, x, b, y)
     switch (p) { case 1: TA(1); break; case 2: TA(2); break; case 3: TA(3); break; }
 #undef TA
 }
@@ -1093,13 +1100,15 @@ template void launch_jacobi0<float>(int, int, int, const float *, const double *
 
 template <typename MT>
 void launch_sweep(int p, int ne, int nb, const MT *T, const int *nbr, const double *x, const double *z0,
-                  const double *qc, const int *fvert, double omega, double *y, hipStream_t s) {
-#define SW(P) hipLaunchKernelGGL((k_sweep<P + 1, MT>), GRID8(ne * nb, 256), 0, s, ne, nb, T, nbr, x, z0, qc, fvert, omega, y)
+                  const double *qc, const int *fvert, double omega, int out_u, double *y, hipStream_t s) {
+#define SW(P)                                                                                                \
+    if (nb == 1) hipLaunchKernelGGL((k_sweep<P + 1, MT, true>), GRID8(ne * nb, 256), 0, s, ne, nb, T, nbr, x, z0, qc, fvert, omega, out_u, y); \
+    else hipLaunchKernelGGL((k_sweep<P + 1, MT, false>), GRID8(ne * nb, 256), 0, s, ne, nb, T, nbr, x, z0, qc, fvert, omega, out_u, y)
     switch (p) { case 1: SW(1); break; case 2: SW(2); break; case 3: SW(3); break; }
 #undef SW
 }
-template void launch_sweep<double>(int, int, int, const double *, const int *, const double *, const double *, const double *, const int *, double, double *, hipStream_t);
-template void launch_sweep<__hip_bfloat16>(int, int, int, const __hip_bfloat16 *, const int *, const double *, const double *, const double *, const int *, double, double *, hipStream_t);
+template void launch_sweep<double>(int, int, int, const double *, const int *, const double *, const double *, const double *, const int *, double, int, double *, hipStream_t);
+template void launch_sweep<__hip_bfloat16>(int, int, int, const __hip_bfloat16 *, const int *, const double *, const double *, const double *, const int *, double, int, double *, hipStream_t);
 
 void launch_restrict_trace(int p, int nv, int nb, const int *vf_row, const int *vf_col, const double *res,
                            double *rc, hipStream_t s) {

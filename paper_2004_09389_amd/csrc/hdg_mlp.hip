@@ -18,7 +18,6 @@ namespace hdg {
 
 typedef short s4_t __attribute__((ext_vector_type(4)));
 typedef float f4_t __attribute__((ext_vector_type(4)));
-typedef double dbl2_t __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ short bf_bits(float x) {
     return (short)__bfloat16_as_ushort(__float2bfloat16(x));
@@ -131,39 +130,26 @@ __device__ void mlp_forward(MlpTile<M> &T, const MlpWeights &W, int samp0, int n
     T.y = out;
 }
 
-// Learned smoothing step.  y = xi + u is the block-Jacobi sweep of the
-// iterate xi (xi == nullptr: zero iterate, y = u); xo = y + s MLP(u-patch).
+// Learned smoothing step: xo = x' + u + s MLP(u-patch), u the block-Jacobi
+// correction of the iterate x' = xi + pi qc (xi == nullptr: zero iterate;
+// qc == nullptr: no prolongation term).
 //
 // Each lane gathers the patches of SPL samples itself (16-byte loads at
 // nrhs = 1), normalises them and stages the BF16 features in LDS as
 // [sample][k]; the wavefront then runs the 64 SPL / 16 tiles through the
 // matrix cores with the weights held in registers, parks the outputs in the
-// same LDS rows and every lane finishes its own samples.  Only wave-local LDS traffic, so
-// no block barrier is needed beyond the wave's own ordering.
+// same LDS rows and every lane finishes its own samples.  Only wave-local LDS
+// traffic, so no block barrier is needed beyond the wave's own ordering.
 constexpr int MLP_ZROW = 40;   // LDS row stride of a sample's features (shorts): 80 B
-// Loads the M trace values of facet id for right-hand side r: contiguous
-// (16-byte loads where aligned) when NB1, strided by nb otherwise.
-template <int M, bool NB1>
-__device__ __forceinline__ void load_facet(const double *__restrict__ v, size_t base, int nb, double (&d)[M]) {
-    if constexpr (NB1 && M % 2 == 0) {
-#pragma unroll
-        for (int j = 0; j < M; j += 2) {
-            const dbl2_t a = *reinterpret_cast<const dbl2_t *>(v + base + j);
-            d[j] = a.x;
-            d[j + 1] = a.y;
-        }
-    } else {
-#pragma unroll
-        for (int j = 0; j < M; ++j) d[j] = v[base + (size_t)(NB1 ? j : j * nb)];
-    }
-}
 
 template <int M, int SPL, bool HAS_X, bool NB1>
-__global__ __launch_bounds__(256) void k_mlp_smooth(int ne, int nb, const double *__restrict__ y,
-                                                    const double *__restrict__ xi, const int *__restrict__ nbr,
+__global__ __launch_bounds__(256) void k_mlp_smooth(int ne, int nb, const double *__restrict__ u,
+                                                    const double *__restrict__ xi, const double *__restrict__ qc,
+                                                    const int *__restrict__ fvert, const int *__restrict__ nbr,
                                                     const int8_t *__restrict__ prev, const short *__restrict__ W1b,
                                                     const short *__restrict__ W2b, double *__restrict__ xo) {
     constexpr int WS = 64 * SPL;   // samples per wavefront
+    constexpr int P = M - 1;
     __shared__ short zs[4][WS * MLP_ZROW];
     const int nsamp = ne * nb;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -171,14 +157,34 @@ __global__ __launch_bounds__(256) void k_mlp_smooth(int ne, int nb, const double
     const int wbase = wave * WS;
     if (wbase >= nsamp) return;   // whole wavefront leaves together
     short *Z = zs[w];
-    const size_t NE = (size_t)ne;
+    const size_t NE = (size_t)ne, MB = (size_t)M * (NB1 ? 1 : nb);
     float sc[SPL];
-    double ye[SPL][M];
+    double ue[SPL][M];
+    // the iterate (and its prolongation term) is needed only at the end: issue those loads first
+    double xe[SPL][M];
+    if constexpr (HAS_X) {
+#pragma unroll
+        for (int q = 0; q < SPL; ++q) {
+            const int samp = wbase + q * 64 + lane;
+#pragma unroll
+            for (int o = 0; o < M; ++o) xe[q][o] = 0.0;
+            if (samp < nsamp) {
+                const int e = NB1 ? samp : samp / nb, r = NB1 ? 0 : samp - e * nb;
+                load_trace<M, NB1>(xi, e * MB + r, nb, xe[q]);
+                if (qc) {
+                    const double q0 = qc[(size_t)fvert[2 * e] * nb + r];
+                    const double q1 = qc[(size_t)fvert[2 * e + 1] * nb + r];
+#pragma unroll
+                    for (int o = 0; o < M; ++o) xe[q][o] += (1.0 - (double)o / P) * q0 + ((double)o / P) * q1;
+                }
+            }
+        }
+    }
     // gather, normalise, stage
 #pragma unroll
     for (int q = 0; q < SPL; ++q) {
         const int ls = q * 64 + lane, samp = wbase + ls;
-        float u[5][M];
+        float f[5][M];
         float ss = 0.f;
         if (samp < nsamp) {
             const int e = NB1 ? samp : samp / nb, r = NB1 ? 0 : samp - e * nb;
@@ -191,31 +197,25 @@ __global__ __launch_bounds__(256) void k_mlp_smooth(int ne, int nb, const double
                 id[k] = nbr[(size_t)(k - 1) * NE + e];
                 rv[k] = prev[(size_t)(k - 1) * NE + e] != 0;
             }
-            double dy[5][M], dx[5][M];
+            double d[5][M];
 #pragma unroll
-            for (int k = 0; k < 5; ++k) {
-                const size_t base = (size_t)id[k] * M * (NB1 ? 1 : nb) + r;
-                load_facet<M, NB1>(y, base, nb, dy[k]);
-                if constexpr (HAS_X) load_facet<M, NB1>(xi, base, nb, dx[k]);
-            }
+            for (int k = 0; k < 5; ++k) load_trace<M, NB1>(u, id[k] * MB + r, nb, d[k]);
 #pragma unroll
-            for (int j = 0; j < M; ++j) ye[q][j] = dy[0][j];
+            for (int j = 0; j < M; ++j) ue[q][j] = d[0][j];
 #pragma unroll
             for (int k = 0; k < 5; ++k)
 #pragma unroll
                 for (int j = 0; j < M; ++j) {
-                    const int jj = rv[k] ? M - 1 - j : j;
-                    const double dv = HAS_X ? dy[k][jj] - dx[k][jj] : dy[k][jj];
-                    u[k][j] = (float)dv;
-                    ss += u[k][j] * u[k][j];
+                    f[k][j] = (float)(rv[k] ? d[k][M - 1 - j] : d[k][j]);
+                    ss += f[k][j] * f[k][j];
                 }
         } else {
 #pragma unroll
             for (int k = 0; k < 5; ++k)
 #pragma unroll
-                for (int j = 0; j < M; ++j) u[k][j] = 0.f;
+                for (int j = 0; j < M; ++j) f[k][j] = 0.f;
 #pragma unroll
-            for (int j = 0; j < M; ++j) ye[q][j] = 0.0;
+            for (int j = 0; j < M; ++j) ue[q][j] = 0.0;
         }
         const float s = sqrtf(ss / (float)(5 * M));
         const float inv = s > 0.f ? 1.f / s : 0.f;
@@ -225,7 +225,7 @@ __global__ __launch_bounds__(256) void k_mlp_smooth(int ne, int nb, const double
         for (int k = 0; k < 5; ++k) {
             s4_t v;
 #pragma unroll
-            for (int j = 0; j < 4; ++j) v[j] = j < M ? bf_bits(u[k][j] * inv) : (short)0;
+            for (int j = 0; j < 4; ++j) v[j] = j < M ? bf_bits(f[k][j] * inv) : (short)0;
             *reinterpret_cast<s4_t *>(row + 4 * k) = v;
         }
         const s4_t zero = {0, 0, 0, 0};
@@ -263,24 +263,21 @@ __global__ __launch_bounds__(256) void k_mlp_smooth(int ne, int nb, const double
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    // finish own samples: xo = y + s out
+    // finish own samples: xo = x' + u + s out
 #pragma unroll
     for (int q = 0; q < SPL; ++q) {
         const int ls = q * 64 + lane, samp = wbase + ls;
         if (samp >= nsamp) continue;
+        const int e = NB1 ? samp : samp / nb, r = NB1 ? 0 : samp - e * nb;
         const f4_t out = *reinterpret_cast<const f4_t *>(Z + ls * MLP_ZROW);
         double res[M];
 #pragma unroll
-        for (int o = 0; o < M; ++o) res[o] = ye[q][o] + (double)(sc[q] * out[o]);
-        if constexpr (NB1 && M % 2 == 0) {
+        for (int o = 0; o < M; ++o) res[o] = ue[q][o] + (double)(sc[q] * out[o]);
+        if constexpr (HAS_X) {
 #pragma unroll
-            for (int o = 0; o < M; o += 2)
-                *reinterpret_cast<dbl2_t *>(xo + (size_t)samp * M + o) = dbl2_t{res[o], res[o + 1]};
-        } else {
-            const int e = NB1 ? samp : samp / nb, r = NB1 ? 0 : samp - e * nb;
-#pragma unroll
-            for (int o = 0; o < M; ++o) xo[((size_t)e * M + o) * (NB1 ? 1 : nb) + r] = res[o];
+            for (int o = 0; o < M; ++o) res[o] += xe[q][o];
         }
+        store_trace<M, NB1>(xo, e * MB + r, nb, res);
     }
 }
 
@@ -480,14 +477,16 @@ __global__ void k_lin3(int64_t n, double a, const double *__restrict__ x, double
 
 #define GRIDL(n, b) dim3((unsigned)(((n) + (b) - 1) / (b))), dim3(b)
 
-void launch_mlp_smooth(int p, int ne, int nb, int spl, const double *y, const double *xi, const int *nbr,
-                       const int8_t *prev, const short *W1b, const short *W2b, double *xo, hipStream_t s) {
+void launch_mlp_smooth(int p, int ne, int nb, int spl, const double *u, const double *xi, const double *qc,
+                       const int *fvert, const int *nbr, const int8_t *prev, const short *W1b, const short *W2b,
+                       double *xo, hipStream_t s) {
     spl = spl >= 2 ? 2 : 1;
     const int64_t waves = ((int64_t)ne * nb + 64 * spl - 1) / (64 * spl);
     const int64_t blocks = (waves + 3) / 4;
     const dim3 grid((unsigned)(((blocks + 7) / 8) * 8)), block(256);   // multiple of 8 for the XCD remap
     const bool hx = xi != nullptr, n1 = nb == 1;
-#define MS(M, S, X, N) hipLaunchKernelGGL((k_mlp_smooth<M, S, X, N>), grid, block, 0, s, ne, nb, y, xi, nbr, prev, W1b, W2b, xo)
+#define MS(M, S, X, N) \
+    hipLaunchKernelGGL((k_mlp_smooth<M, S, X, N>), grid, block, 0, s, ne, nb, u, xi, qc, fvert, nbr, prev, W1b, W2b, xo)
 #define MS_XN(M, S)                          \
     if (hx) {                                \
         if (n1) MS(M, S, true, true);        \
