@@ -246,20 +246,20 @@ def main():
     dom = max(st, key=lambda k: st[k][1])
     launches, ms, bpl = st[dom]
     avg_s = ms / max(launches, 1) / 1e3
-    achieved = bpl * nb / avg_s / 1e9 if avg_s > 0 else 0.0
+    achieved = bpl / avg_s / 1e9 if avg_s > 0 else 0.0
     pname = {HDG_FP64: "fp64", HDG_MIXED: "mixed"}
     label = f"{dom[0]}[{pname[dom[1]]}]"
     tr = measured_traffic(label) if (n == 256 and p == 3 and nb == 1) else None
     roofline = {"bound": "hbm", "kernel": label, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": tr[0] if tr else None, "traffic_source": tr[1] if tr else None,
-                "avg_launch_us": round(avg_s * 1e6, 3), "launches": launches, "bytes_per_launch": bpl * nb,
+                "avg_launch_us": round(avg_s * 1e6, 3), "launches": launches, "bytes_per_launch": bpl,
                 "timing": f"HIP events on the launch stream around every launch of the kernel in an "
                           f"instrumented eager pass of the same steps right after the timed (graph-replayed) "
                           f"pass; each instrumented launch issued {TIMING_REPEAT}x back to back per event pair"}
     kern = {f"{k}[{pname[pr]}]": {"launches": v[0], "total_ms": round(v[1], 3),
                                   "avg_us": round(1e3 * v[1] / max(v[0], 1), 3),
-                                  "GBps": round(v[2] * nb / (v[1] / max(v[0], 1) / 1e3) / 1e9, 1) if v[1] > 0 else None}
+                                  "GBps": round(v[2] / (v[1] / max(v[0], 1) / 1e3) / 1e9, 1) if v[1] > 0 else None}
             for (k, pr), v in st.items() if v[0] > 0}
     out = {
         "metric": "trace solves/s to 1e-8 rel residual (learned/mixed vs FP64 MG), HBM GB/s",

@@ -251,6 +251,9 @@ int hdg_mlp_train(hdg_ctx *ctx, int32_t nrhs, const double *e0, int32_t cycles, 
 typedef struct {
     int32_t mlp_samples_per_lane; /* samples (facet, rhs) each lane gathers in the learned
                                      smoothing kernel: 1 or 2 (default 1) */
+    int32_t rhs_block;          /* facet-row kernels (apply, residual, sweep) at nrhs = 4, 8, ..., 64:
+                                   1 = one thread per (facet, rhs); 4 = four right-hand sides per
+                                   thread with the block's rows staged in LDS (default 4) */
 } hdg_tuning;
 int hdg_get_tuning(const hdg_ctx *ctx, hdg_tuning *out);
 int hdg_set_tuning(hdg_ctx *ctx, const hdg_tuning *tuning);
@@ -266,9 +269,9 @@ int hdg_autotune(hdg_ctx *ctx, int32_t nrhs, hdg_tuning *chosen, void *stream);
  * While timing is on, Krylov iterations run eagerly (no graph replay).
  * hdg_kernel_stats returns, for kernel class id and precision, the launch
  * count and the summed per-launch duration (ms) since the last
- * hdg_set_timing call, and the algorithmic bytes one launch moves at
- * nrhs = 1 (every stored matrix entry once, every vector entry read or
- * written once, indices once).  Both calls synchronise. */
+ * hdg_set_timing call, and the algorithmic bytes one launch moves at the
+ * nrhs of the timed launches (every stored matrix entry once, every vector
+ * entry read or written once, indices once).  Both calls synchronise. */
 #define HDG_KERNEL_APPLY    0   /* y = S x  (facet block rows) */
 #define HDG_KERNEL_SWEEP    1   /* block-Jacobi sweep with the off-diagonal rows */
 #define HDG_KERNEL_RESIDUAL 2   /* r - S x */

@@ -127,8 +127,9 @@ struct Timed {
     int kind, prec;
     hipStream_t s;
     hipEvent_t a = nullptr;
-    Timed(hdg_ctx *c_, int kind_, int prec_, hipStream_t s_) : c(c_), kind(kind_), prec(prec_), s(s_) {
+    Timed(hdg_ctx *c_, int kind_, int prec_, hipStream_t s_, int nb) : c(c_), kind(kind_), prec(prec_), s(s_) {
         if (!c->timing) return;
+        c->t_nb[prec][kind] = nb;
         a = pool_event(c);
         HDG_HIP_CHECK(hipEventRecord(a, s));
     }
@@ -160,26 +161,26 @@ void collect_timing(hdg_ctx *c) {
 // y = S x (b == nullptr) or y = b - S x
 void op_apply(hdg_ctx *c, int nb, int prec, const double *x, const double *b, double *y, hipStream_t s,
               int kind) {
-    Timed t(c, kind, prec, s);
+    Timed t(c, kind, prec, s, nb);
     for (int rep = 0; rep < t.repeats(); ++rep) {
         if (prec == HDG_MIXED)
-            hdg::launch_trace_apply<float>(c->p, c->n_facet, nb, c->S32, c->nbr, x, b, y, s);
+            hdg::launch_trace_apply<float>(c->p, c->n_facet, nb, c->S32, c->nbr, x, b, y, s, c->rhs_block);
         else
-            hdg::launch_trace_apply<double>(c->p, c->n_facet, nb, c->S64, c->nbr, x, b, y, s);
+            hdg::launch_trace_apply<double>(c->p, c->n_facet, nb, c->S64, c->nbr, x, b, y, s, c->rhs_block);
     }
     check_launch();
 }
 
 void op_sweep(hdg_ctx *c, int nb, int prec, const double *x, const double *z0, const double *qc, double *y,
               hipStream_t s, int out_u = 0) {
-    Timed t(c, HDG_KERNEL_SWEEP, prec, s);
+    Timed t(c, HDG_KERNEL_SWEEP, prec, s, nb);
     for (int rep = 0; rep < t.repeats(); ++rep) {
         if (prec == HDG_MIXED)
             hdg::launch_sweep<__hip_bfloat16>(c->p, c->n_facet, nb, c->T16, c->nbr, x, z0, qc, c->facet_vert,
-                                              c->opt.omega, out_u, y, s);
+                                              c->opt.omega, out_u, y, s, c->rhs_block);
         else
             hdg::launch_sweep<double>(c->p, c->n_facet, nb, c->T64, c->nbr, x, z0, qc, c->facet_vert,
-                                      c->opt.omega, out_u, y, s);
+                                      c->opt.omega, out_u, y, s, c->rhs_block);
     }
     check_launch();
 }
@@ -284,7 +285,7 @@ void vcycle_mlp(hdg_ctx *c, int nb, int prec, const double *r, double *z, hipStr
     // x alternates between vx and vx2; the correction goes to vres
     double *x = c->vx, *other = c->vx2;
     auto learned = [&](const double *u, const double *xi, const double *qc, double *out) {
-        Timed t(c, HDG_KERNEL_MLP, prec, s);
+        Timed t(c, HDG_KERNEL_MLP, prec, s, nb);
         for (int rep = 0; rep < t.repeats(); ++rep)
             hdg::launch_mlp_smooth(c->p, c->n_facet, nb, c->mlp_spl, u, xi, qc, c->facet_vert, c->nbr, c->prev, W1b,
                                    W2b, out, s);
@@ -902,7 +903,7 @@ extern "C" int hdg_condense(hdg_ctx *c, int32_t nb, const double *r_cell, double
         check_nb(c, nb);
         HDG_REQUIRE(r_cell && rhat, "r_cell and rhat must not be NULL");
         hipStream_t s = as_stream(stream);
-        Timed t(c, HDG_KERNEL_CONDENSE, HDG_FP64, s);
+        Timed t(c, HDG_KERNEL_CONDENSE, HDG_FP64, s, nb);
         for (int rep = 0; rep < t.repeats(); ++rep)
             hdg::launch_condense(c->p, c->n_cell, c->n_facet, nb, c->Zr, r_cell, c->loc, c->d_fcell, c->d_floc, rhat,
                                  s);
@@ -977,7 +978,7 @@ extern "C" int hdg_recover(hdg_ctx *c, int32_t nb, const double *r_cell, const d
         HDG_REQUIRE(r_cell && lam && q_cell, "r_cell, lam and q_cell must not be NULL");
         check_aligned(lam, "lam");
         hipStream_t s = as_stream(stream);
-        Timed t(c, HDG_KERNEL_RECOVER, HDG_FP64, s);
+        Timed t(c, HDG_KERNEL_RECOVER, HDG_FP64, s, nb);
         for (int rep = 0; rep < t.repeats(); ++rep)
             hdg::launch_recover(c->p, c->n_cell, nb, c->Ar, c->Wr, c->cell_facet, c->cell_rev, r_cell, lam, q_cell,
                                 s);
@@ -1180,6 +1181,7 @@ namespace {
 void check_tuning(const hdg_tuning &t) {
     const int v = t.mlp_samples_per_lane;
     HDG_REQUIRE(v == 1 || v == 2, "mlp_samples_per_lane must be 1 or 2");
+    HDG_REQUIRE(t.rhs_block == 1 || t.rhs_block == 4, "rhs_block must be 1 or 4");
 }
 
 // mean duration (ms) of `reps` launches of fn, after one untimed launch
@@ -1206,6 +1208,7 @@ double time_launches(hipStream_t s, int reps, F &&fn) {
 extern "C" int hdg_get_tuning(const hdg_ctx *c, hdg_tuning *out) {
     if (!c || !out) return HDG_EINVAL;
     out->mlp_samples_per_lane = c->mlp_spl;
+    out->rhs_block = c->rhs_block;
     return HDG_OK;
 }
 
@@ -1217,6 +1220,7 @@ extern "C" int hdg_set_tuning(hdg_ctx *c, const hdg_tuning *t) {
         HDG_HIP_CHECK(hipDeviceSynchronize());
         drop_graphs(c);
         c->mlp_spl = t->mlp_samples_per_lane;
+        c->rhs_block = t->rhs_block;
     });
 }
 
@@ -1244,7 +1248,26 @@ extern "C" int hdg_autotune(hdg_ctx *c, int32_t nb, hdg_tuning *chosen, void *st
             }
         }
         c->mlp_spl = best_spl;
-        if (chosen) chosen->mlp_samples_per_lane = best_spl;
+        // facet-row kernels: one thread per (facet, rhs) or RHS-blocked with LDS-staged rows
+        HDG_HIP_CHECK(hipMemsetAsync(c->vx2, 0, bytes, s));
+        best = 1e300;
+        int best_rb = 1;
+        for (int rb : {1, 4}) {
+            c->rhs_block = rb;
+            const double ms = time_launches(s, 10, [&] {
+                op_apply(c, nb, HDG_FP64, c->vx, nullptr, c->vx2, s, HDG_KERNEL_APPLY);
+                op_sweep(c, nb, HDG_MIXED, c->vx, c->vres, nullptr, c->vx2, s);
+            });
+            if (ms < best) {
+                best = ms;
+                best_rb = rb;
+            }
+        }
+        c->rhs_block = best_rb;
+        if (chosen) {
+            chosen->mlp_samples_per_lane = best_spl;
+            chosen->rhs_block = best_rb;
+        }
     });
 }
 
@@ -1270,18 +1293,19 @@ extern "C" int hdg_kernel_stats(hdg_ctx *c, int32_t kernel, int32_t prec, int64_
         if (launches) *launches = c->t_launches[prec][kernel];
         if (total_ms) *total_ms = c->t_ms[prec][kernel];
         if (bytes_per_launch) {
-            // algorithmic bytes at nrhs = 1: every stored matrix entry once, every
-            // vector entry read or written once, indices once
+            // algorithmic bytes at the nrhs of the timed launches: every stored matrix entry
+            // once, every vector entry read or written once, indices once
             const double m = c->m, ne = c->n_facet, nk = c->n_cell, nc = c->nc, nt = c->nt;
+            const double nb = std::max(1, c->t_nb[prec][kernel]);
             const double sm = prec == HDG_MIXED ? 4.0 : 8.0, st = prec == HDG_MIXED ? 2.0 : 8.0;
             double b = 0;
             switch (kernel) {
-            case HDG_KERNEL_APPLY: b = ne * (5 * m * m * sm + 4 * 4 + 2 * m * 8); break;
-            case HDG_KERNEL_RESIDUAL: b = ne * (5 * m * m * sm + 4 * 4 + 3 * m * 8); break;
-            case HDG_KERNEL_SWEEP: b = ne * (4 * m * m * st + 4 * 4 + 3 * m * 8); break;
-            case HDG_KERNEL_CONDENSE: b = nk * (nt * nc * 8 + nc * 8) + ne * m * 8; break;
-            case HDG_KERNEL_RECOVER: b = nk * ((nc * nc + nc * nt) * 8 + 2 * nc * 8) + ne * m * 8; break;
-            case HDG_KERNEL_MLP: b = ne * (3 * m * 8 + 4 * 4 + 4); break;
+            case HDG_KERNEL_APPLY: b = ne * (5 * m * m * sm + 4 * 4) + nb * ne * 2 * m * 8; break;
+            case HDG_KERNEL_RESIDUAL: b = ne * (5 * m * m * sm + 4 * 4) + nb * ne * 3 * m * 8; break;
+            case HDG_KERNEL_SWEEP: b = ne * (4 * m * m * st + 4 * 4) + nb * ne * 3 * m * 8; break;
+            case HDG_KERNEL_CONDENSE: b = nk * nt * nc * 8 + nb * (nk * nc * 8 + ne * m * 8); break;
+            case HDG_KERNEL_RECOVER: b = nk * (nc * nc + nc * nt) * 8 + nb * (nk * 2 * nc * 8 + ne * m * 8); break;
+            case HDG_KERNEL_MLP: b = ne * (4 * 4 + 4) + nb * ne * 3 * m * 8; break;
             }
             *bytes_per_launch = b;
         }

@@ -169,6 +169,7 @@ struct hdg_ctx {
     // learned smoother: weights [W1 (64 x K1P) | W2 (16 x 64)], FP32 master + Adam moments, BF16 copy
     int mlp_n1 = 0, mlp_n2 = 0, mlp_step = 0;
     int mlp_spl = 1;                      // samples per lane in the learned smoothing kernel
+    int rhs_block = 4;                    // facet-row kernels: RHS per thread when nrhs allows (1 or 4)
     bool mlp_ready = false;
     float *mlp_w = nullptr, *mlp_m1 = nullptr, *mlp_m2 = nullptr, *mlp_g = nullptr;
     short *mlp_wb = nullptr;
@@ -193,5 +194,6 @@ struct hdg_ctx {
     std::map<uint64_t, hipGraphExec_t> graphs;
     hipStream_t cap_stream = nullptr;
     int64_t t_launches[2][HDG_KERNEL_COUNT] = {};
+    int t_nb[2][HDG_KERNEL_COUNT] = {};   // nrhs of the last timed launch per class
     double t_ms[2][HDG_KERNEL_COUNT] = {};
 };

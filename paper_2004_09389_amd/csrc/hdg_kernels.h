@@ -46,6 +46,16 @@ __device__ __forceinline__ void store_trace(double *__restrict__ v, size_t base,
     }
 }
 
+// Value at trace node k of the linear interpolant of q0 (start vertex) and
+// q1 (end vertex): the injection pi of a P1 function.  The rounding is fixed
+// here (one product, one fused multiply-add) so that every kernel applying
+// pi produces identical bits.
+template <int P>
+__device__ __forceinline__ double p1_node(int k, double q0, double q1) {
+    const double t = (double)k / P;
+    return __builtin_fma(t, q1, (1.0 - t) * q0);
+}
+
 // padded component count of a facet-row matrix stored with v entries per 16 bytes
 constexpr int wide_padded(int c, int v) { return (c + v - 1) / v * v; }
 
@@ -63,13 +73,13 @@ void launch_facet_rows(int p, int ne, int nk, const double *Sloc, const int *fac
 
 template <typename MT>
 void launch_trace_apply(int p, int ne, int nb, const MT *S, const int *nbr, const double *x, const double *b,
-                        double *y, hipStream_t s);
+                        double *y, hipStream_t s, int rhs_block = 1);
 template <typename MT>
 void launch_jacobi0(int p, int ne, int nb, const MT *Dw, const double *r, const double *scale, double *rs,
                     double *z0, hipStream_t s);
 template <typename MT>
 void launch_sweep(int p, int ne, int nb, const MT *T, const int *nbr, const double *x, const double *z0,
-                  const double *qc, const int *fvert, double omega, int out_u, double *y, hipStream_t s);
+                  const double *qc, const int *fvert, double omega, int out_u, double *y, hipStream_t s, int rhs_block = 1);
 void launch_restrict_trace(int p, int nv, int nb, const int *vf_row, const int *vf_col, const double *res,
                            double *rc, hipStream_t s);
 

@@ -3,6 +3,8 @@
 //   per-cell matrices  component-major [row][col][n_cell]  (lanes = cells, coalesced)
 //   facet block rows   component-major [slot][a][b][n_facet]
 //   vectors            [item][dof][nrhs]  (RHS innermost)
+#include <type_traits>
+
 #include "hdg_kernels.h"
 
 namespace hdg {
@@ -489,7 +491,7 @@ __global__ __launch_bounds__(256) void k_sweep(int ne, int nb, const MT *__restr
             const double q0 = qc[(size_t)fvert[2 * id[j]] * nb + r];
             const double q1 = qc[(size_t)fvert[2 * id[j] + 1] * nb + r];
 #pragma unroll
-            for (int k = 0; k < M; ++k) xv[j][k] += (1.0 - (double)k / P) * q0 + ((double)k / P) * q1;
+            for (int k = 0; k < M; ++k) xv[j][k] += p1_node<P>(k, q0, q1);
         }
     }
     AT acc[M];
@@ -1054,6 +1056,184 @@ __global__ void k_sqrt(int nb, const double *__restrict__ in, double *__restrict
 
 #define GRID(n, b) dim3((unsigned)(((n) + (b) - 1) / (b))), dim3(b)
 // grid padded to a multiple of N_XCD blocks, for kernels indexed through xcd_block()
+
+// ------------------------------------------------------------------ RHS-blocked facet-row kernels
+//
+// With many right-hand sides the per-(facet, rhs) kernels above re-read the
+// facet's matrix row once per right-hand side.  These variants give each
+// thread RB = 4 consecutive right-hand sides of one facet (two 16-byte loads
+// per facet node) and stage the rows of the block's 64 facets in LDS with
+// coalesced 16-byte loads, so every row leaves L2 once per block.
+// Block = 64 facets x (nb / RB) threads; nb / RB must be a power of two <= 16.
+constexpr int RB_FACETS = 64;
+
+template <typename MT>
+__device__ __forceinline__ float lds_entry_f(const MT *p) { return (float)*p; }
+template <>
+__device__ __forceinline__ float lds_entry_f<__hip_bfloat16>(const __hip_bfloat16 *p) {
+    return __uint_as_float(((unsigned)*reinterpret_cast<const unsigned short *>(p)) << 16);
+}
+template <typename MT>
+__device__ __forceinline__ typename Acc<MT>::type lds_entry(const MT *p) {
+    if constexpr (std::is_same<MT, double>::value) return *p;
+    else return lds_entry_f<MT>(p);
+}
+
+// stage the G 16-byte groups of the rows of facets f0 .. f0 + 63 as [g][64][V]
+template <typename MT, int G>
+__device__ __forceinline__ void stage_rows(MT *sm, const MT *__restrict__ S, int f0, int ne) {
+    constexpr int V = Wide<MT>::V;
+    const size_t NE = (size_t)ne;
+    for (int i = threadIdx.x; i < G * RB_FACETS; i += blockDim.x) {
+        const int g = i / RB_FACETS, el = i - g * RB_FACETS, e = f0 + el;
+        u32x4_t v = {0u, 0u, 0u, 0u};
+        if (e < ne) v = *reinterpret_cast<const u32x4_t *>(S + ((size_t)g * NE + e) * V);
+        *reinterpret_cast<u32x4_t *>(sm + (size_t)i * V) = v;
+    }
+}
+
+template <int RB>
+__device__ __forceinline__ void load_rb(const double *__restrict__ p, double (&d)[RB]) {
+#pragma unroll
+    for (int q = 0; q < RB; q += 2) {
+        const dbl2_t a = *reinterpret_cast<const dbl2_t *>(p + q);
+        d[q] = a.x;
+        d[q + 1] = a.y;
+    }
+}
+template <int RB>
+__device__ __forceinline__ void store_rb(double *__restrict__ p, const double (&d)[RB]) {
+#pragma unroll
+    for (int q = 0; q < RB; q += 2) *reinterpret_cast<dbl2_t *>(p + q) = dbl2_t{d[q], d[q + 1]};
+}
+
+// y = S x or y = b - S x
+template <int M, typename MT, int RB>
+__global__ __launch_bounds__(1024) void k_trace_apply_rb(int ne, int nb, const MT *__restrict__ S,
+                                                         const int *__restrict__ nbr, const double *__restrict__ x,
+                                                         const double *__restrict__ b, double *__restrict__ y) {
+    using AT = typename Acc<MT>::type;
+    constexpr int V = Wide<MT>::V, C = 5 * M * M, G = padded(C, V) / V;
+    __shared__ __attribute__((aligned(16))) MT sm[G * RB_FACETS * V];
+    const int f0 = xcd_block() * RB_FACETS;
+    stage_rows<MT, G>(sm, S, f0, ne);
+    __syncthreads();
+    const int tpf = nb / RB;
+    const int el = threadIdx.x / tpf, r0 = (threadIdx.x - el * tpf) * RB, e = f0 + el;
+    if (e >= ne) return;
+    const size_t NE = (size_t)ne;
+    AT acc[M][RB];
+#pragma unroll
+    for (int a = 0; a < M; ++a)
+#pragma unroll
+        for (int q = 0; q < RB; ++q) acc[a][q] = 0;
+#pragma unroll 1
+    for (int j = 0; j < 5; ++j) {   // one neighbour's values in flight at a time keeps the registers in bounds
+        const int id = j == 0 ? e : nbr[(size_t)(j - 1) * NE + e];
+        double xv[M][RB];
+#pragma unroll
+        for (int k = 0; k < M; ++k) load_rb<RB>(x + ((size_t)id * M + k) * nb + r0, xv[k]);
+#pragma unroll
+        for (int a = 0; a < M; ++a)
+#pragma unroll
+            for (int k = 0; k < M; ++k) {
+                const int c = (j * M + a) * M + k;
+                const AT w = lds_entry<MT>(sm + ((size_t)(c / V) * RB_FACETS + el) * V + c % V);
+#pragma unroll
+                for (int q = 0; q < RB; ++q) acc[a][q] += w * (AT)xv[k][q];
+            }
+    }
+#pragma unroll
+    for (int a = 0; a < M; ++a) {
+        const size_t o = ((size_t)e * M + a) * nb + r0;
+        double out[RB];
+        if (b) {
+            double bv[RB];
+            load_rb<RB>(b + o, bv);
+#pragma unroll
+            for (int q = 0; q < RB; ++q) out[q] = bv[q] - (double)acc[a][q];
+        } else {
+#pragma unroll
+            for (int q = 0; q < RB; ++q) out[q] = (double)acc[a][q];
+        }
+        store_rb<RB>(y + o, out);
+    }
+}
+
+// y = keep x' + z0 - sum_j T_j x'_j, x' = x + pi qc (qc may be null); keep = 1 - omega, or -omega
+// when only the correction is wanted (out_u)
+template <int M, typename MT, int RB>
+__global__ __launch_bounds__(1024) void k_sweep_rb(int ne, int nb, const MT *__restrict__ T,
+                                                   const int *__restrict__ nbr, const double *__restrict__ x,
+                                                   const double *__restrict__ z0, const double *__restrict__ qc,
+                                                   const int *__restrict__ fvert, double omega, int out_u,
+                                                   double *__restrict__ y) {
+    using AT = typename Acc<MT>::type;
+    constexpr int P = M - 1;
+    constexpr int V = Wide<MT>::V, C = 4 * M * M, G = padded(C, V) / V;
+    __shared__ __attribute__((aligned(16))) MT sm[G * RB_FACETS * V];
+    const int f0 = xcd_block() * RB_FACETS;
+    stage_rows<MT, G>(sm, T, f0, ne);
+    __syncthreads();
+    const int tpf = nb / RB;
+    const int el = threadIdx.x / tpf, r0 = (threadIdx.x - el * tpf) * RB, e = f0 + el;
+    if (e >= ne) return;
+    const size_t NE = (size_t)ne;
+    auto iterate = [&](int id, double (&xv)[M][RB]) {
+#pragma unroll
+        for (int k = 0; k < M; ++k) load_rb<RB>(x + ((size_t)id * M + k) * nb + r0, xv[k]);
+        if (qc) {
+            double q0[RB], q1[RB];
+            load_rb<RB>(qc + (size_t)fvert[2 * id] * nb + r0, q0);
+            load_rb<RB>(qc + (size_t)fvert[2 * id + 1] * nb + r0, q1);
+#pragma unroll
+            for (int k = 0; k < M; ++k)
+#pragma unroll
+                for (int q = 0; q < RB; ++q) xv[k][q] += p1_node<P>(k, q0[q], q1[q]);
+        }
+    };
+    AT acc[M][RB];
+#pragma unroll
+    for (int a = 0; a < M; ++a)
+#pragma unroll
+        for (int q = 0; q < RB; ++q) acc[a][q] = 0;
+#pragma unroll 1
+    for (int j = 0; j < 4; ++j) {   // one neighbour's values in flight at a time keeps the registers in bounds
+        double xv[M][RB];
+        iterate(nbr[(size_t)j * NE + e], xv);
+#pragma unroll
+        for (int a = 0; a < M; ++a)
+#pragma unroll
+            for (int k = 0; k < M; ++k) {
+                const int c = (j * M + a) * M + k;
+                const AT w = lds_entry<MT>(sm + ((size_t)(c / V) * RB_FACETS + el) * V + c % V);
+#pragma unroll
+                for (int q = 0; q < RB; ++q) acc[a][q] += w * (AT)xv[k][q];
+            }
+    }
+    double xe[M][RB];
+    iterate(e, xe);
+    const double keep = out_u ? -omega : 1.0 - omega;
+#pragma unroll
+    for (int a = 0; a < M; ++a) {
+        const size_t o = ((size_t)e * M + a) * nb + r0;
+        double zv[RB], out[RB];
+        load_rb<RB>(z0 + o, zv);
+#pragma unroll
+        for (int q = 0; q < RB; ++q) out[q] = keep * xe[a][q] + zv[q] - (double)acc[a][q];
+        store_rb<RB>(y + o, out);
+    }
+}
+
+// RHS-blocked launch applies when nb / 4 is a power of two <= 16
+bool rhs_blocked(int nb, int rhs_block) {
+    if (rhs_block != 4 || nb < 4 || nb % 4 != 0) return false;
+    const int t = nb / 4;
+    return t <= 16 && (t & (t - 1)) == 0;
+}
+
+#define GRID_RB(ne, nb) dim3((unsigned)((((ne) + RB_FACETS - 1) / RB_FACETS + N_XCD - 1) / N_XCD * N_XCD)), dim3(RB_FACETS * ((nb) / 4))
+
 #define GRID8(n, b) dim3((unsigned)((((n) + (b) - 1) / (b) + N_XCD - 1) / N_XCD * N_XCD)), dim3(b)
 
 void launch_cell_condense(int p, int nk, const double *corners, const double *ref, CellParams cp, double *Sloc,
@@ -1076,15 +1256,21 @@ void launch_facet_rows(int p, int ne, int nk, const double *Sloc, const int *fac
 
 template <typename MT>
 void launch_trace_apply(int p, int ne, int nb, const MT *S, const int *nbr, const double *x, const double *b,
-                        double *y, hipStream_t s) {
+                        double *y, hipStream_t s, int rhs_block) {
+    if (rhs_blocked(nb, rhs_block)) {
+#define TAB(P) hipLaunchKernelGGL((k_trace_apply_rb<P + 1, MT, 4>), GRID_RB(ne, nb), 0, s, ne, nb, S, nbr, x, b, y)
+        switch (p) { case 1: TAB(1); break; case 2: TAB(2); break; case 3: TAB(3); break; }
+#undef TAB
+        return;
+    }
 #define TA(P)                                                                                          \
     if (nb == 1) hipLaunchKernelGGL((k_trace_apply<P + 1, MT, true>), GRID8(ne * nb, 256), 0, s, ne, nb, S, nbr, x, b, y); \
     else hipLaunchKernelGGL((k_trace_apply<P + 1, MT, false>), GRID8(ne * nb, 256), 0, s, ne, nb, S, nbr, x, b, y)
     switch (p) { case 1: TA(1); break; case 2: TA(2); break; case 3: TA(3); break; }
 #undef TA
 }
-template void launch_trace_apply<double>(int, int, int, const double *, const int *, const double *, const double *, double *, hipStream_t);
-template void launch_trace_apply<float>(int, int, int, const float *, const int *, const double *, const double *, double *, hipStream_t);
+template void launch_trace_apply<double>(int, int, int, const double *, const int *, const double *, const double *, double *, hipStream_t, int);
+template void launch_trace_apply<float>(int, int, int, const float *, const int *, const double *, const double *, double *, hipStream_t, int);
 
 template <typename MT>
 void launch_jacobi0(int p, int ne, int nb, const MT *Dw, const double *r, const double *scale, double *rs,
@@ -1100,15 +1286,22 @@ template void launch_jacobi0<float>(int, int, int, const float *, const double *
 
 template <typename MT>
 void launch_sweep(int p, int ne, int nb, const MT *T, const int *nbr, const double *x, const double *z0,
-                  const double *qc, const int *fvert, double omega, int out_u, double *y, hipStream_t s) {
+                  const double *qc, const int *fvert, double omega, int out_u, double *y, hipStream_t s,
+                  int rhs_block) {
+    if (rhs_blocked(nb, rhs_block)) {
+#define SWB(P) hipLaunchKernelGGL((k_sweep_rb<P + 1, MT, 4>), GRID_RB(ne, nb), 0, s, ne, nb, T, nbr, x, z0, qc, fvert, omega, out_u, y)
+        switch (p) { case 1: SWB(1); break; case 2: SWB(2); break; case 3: SWB(3); break; }
+#undef SWB
+        return;
+    }
 #define SW(P)                                                                                                \
     if (nb == 1) hipLaunchKernelGGL((k_sweep<P + 1, MT, true>), GRID8(ne * nb, 256), 0, s, ne, nb, T, nbr, x, z0, qc, fvert, omega, out_u, y); \
     else hipLaunchKernelGGL((k_sweep<P + 1, MT, false>), GRID8(ne * nb, 256), 0, s, ne, nb, T, nbr, x, z0, qc, fvert, omega, out_u, y)
     switch (p) { case 1: SW(1); break; case 2: SW(2); break; case 3: SW(3); break; }
 #undef SW
 }
-template void launch_sweep<double>(int, int, int, const double *, const int *, const double *, const double *, const double *, const int *, double, int, double *, hipStream_t);
-template void launch_sweep<__hip_bfloat16>(int, int, int, const __hip_bfloat16 *, const int *, const double *, const double *, const double *, const int *, double, int, double *, hipStream_t);
+template void launch_sweep<double>(int, int, int, const double *, const int *, const double *, const double *, const double *, const int *, double, int, double *, hipStream_t, int);
+template void launch_sweep<__hip_bfloat16>(int, int, int, const __hip_bfloat16 *, const int *, const double *, const double *, const double *, const int *, double, int, double *, hipStream_t, int);
 
 void launch_restrict_trace(int p, int nv, int nb, const int *vf_row, const int *vf_col, const double *res,
                            double *rc, hipStream_t s) {

@@ -175,7 +175,7 @@ __global__ __launch_bounds__(256) void k_mlp_smooth(int ne, int nb, const double
                     const double q0 = qc[(size_t)fvert[2 * e] * nb + r];
                     const double q1 = qc[(size_t)fvert[2 * e + 1] * nb + r];
 #pragma unroll
-                    for (int o = 0; o < M; ++o) xe[q][o] += (1.0 - (double)o / P) * q0 + ((double)o / P) * q1;
+                    for (int o = 0; o < M; ++o) xe[q][o] += p1_node<P>(o, q0, q1);
                 }
             }
         }
@@ -402,22 +402,30 @@ __global__ __launch_bounds__(256) void k_mlp_grad(int ne, int nb, const double *
     if (lane == 0) ploss[wid] = lsum;
 }
 
-// Sum of the per-wave partials in wave order: g[i] for i < n1 + n2 (+ loss).
-__global__ void k_mlp_reduce(int nwaves, int n1, int n2, const float *__restrict__ p1, const float *__restrict__ p2,
-                             const float *__restrict__ pl, float *__restrict__ g, double *__restrict__ loss) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+// Sum of the per-wave partials: g[i] for i < n1 + n2, and the loss (index
+// n1 + n2).  A block reduces 64 consecutive entries with 16 thread rows, each
+// row summing every 16th wave (coalesced over the 64 entries), then the 16
+// row sums in a fixed order.
+__global__ __launch_bounds__(1024) void k_mlp_reduce(int nwaves, int n1, int n2, const float *__restrict__ p1,
+                                                     const float *__restrict__ p2, const float *__restrict__ pl,
+                                                     float *__restrict__ g, double *__restrict__ loss) {
+    __shared__ double part[16][64];
+    const int i = blockIdx.x * 64 + threadIdx.x, row = threadIdx.y;
+    double sum = 0.0;
     if (i < n1) {
-        float s = 0.f;
-        for (int w = 0; w < nwaves; ++w) s += p1[(size_t)w * n1 + i];
-        g[i] = s;
+        for (int w = row; w < nwaves; w += 16) sum += p1[(size_t)w * n1 + i];
     } else if (i < n1 + n2) {
-        float s = 0.f;
-        for (int w = 0; w < nwaves; ++w) s += p2[(size_t)w * n2 + (i - n1)];
-        g[i] = s;
+        for (int w = row; w < nwaves; w += 16) sum += p2[(size_t)w * n2 + (i - n1)];
     } else if (i == n1 + n2) {
-        double s = 0.0;
-        for (int w = 0; w < nwaves; ++w) s += pl[w];
-        loss[0] = s;
+        for (int w = row; w < nwaves; w += 16) sum += pl[w];
+    }
+    part[row][threadIdx.x] = sum;
+    __syncthreads();
+    if (row == 0) {
+        double t = 0.0;
+        for (int r = 0; r < 16; ++r) t += part[r][threadIdx.x];
+        if (i < n1 + n2) g[i] = (float)t;
+        else if (i == n1 + n2) loss[0] = t;
     }
 }
 
@@ -464,7 +472,7 @@ __global__ void k_prolong_trace(int ne, int nb, const int *__restrict__ fvert, c
     const int e = t / nb, r = t - e * nb;
     const double q0 = qc[(size_t)fvert[2 * e] * nb + r], q1 = qc[(size_t)fvert[2 * e + 1] * nb + r];
 #pragma unroll
-    for (int k = 0; k < M; ++k) x[((size_t)e * M + k) * nb + r] += (1.0 - (double)k / P) * q0 + ((double)k / P) * q1;
+    for (int k = 0; k < M; ++k) x[((size_t)e * M + k) * nb + r] += p1_node<P>(k, q0, q1);
 }
 
 // out = a x + b y + c z (elementwise)
@@ -529,7 +537,8 @@ void launch_mlp_grad(int p, int ne, int nb, const double *u, const double *t, co
     case 3: hipLaunchKernelGGL(k_mlp_grad<4>, grid, block, 0, s, ne, nb, u, t, nbr, prev, W1b, W2b, iters, pdW1, pdW2, ploss); break;
     }
     const int n1 = 64 * mlp_k1p(p), n2 = 16 * 64;
-    hipLaunchKernelGGL(k_mlp_reduce, GRIDL(n1 + n2 + 1, 256), 0, s, nw, n1, n2, pdW1, pdW2, ploss, g, loss);
+    hipLaunchKernelGGL(k_mlp_reduce, dim3((unsigned)((n1 + n2 + 1 + 63) / 64)), dim3(64, 16), 0, s, nw, n1, n2, pdW1,
+                       pdW2, ploss, g, loss);
 }
 
 void launch_adam(int p, const float *g, float gscale, float *w, float *m1, float *m2, float lr, int step,

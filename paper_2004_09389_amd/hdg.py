@@ -58,7 +58,7 @@ class HdgSizes(ctypes.Structure):
 
 
 class HdgTuning(ctypes.Structure):
-    _fields_ = [("mlp_samples_per_lane", ctypes.c_int32)]
+    _fields_ = [("mlp_samples_per_lane", ctypes.c_int32), ("rhs_block", ctypes.c_int32)]
 
 
 _P = ctypes.c_void_p
@@ -312,7 +312,7 @@ class HdgSolver:
     def get_tuning(self) -> dict:
         t = HdgTuning()
         _check(self.lib.hdg_get_tuning(self.ctx, ctypes.byref(t)))
-        return {"mlp_samples_per_lane": t.mlp_samples_per_lane}
+        return {"mlp_samples_per_lane": t.mlp_samples_per_lane, "rhs_block": t.rhs_block}
 
     def set_tuning(self, **kw):
         t = HdgTuning()
@@ -324,7 +324,7 @@ class HdgSolver:
     def autotune(self, nrhs: int = 1) -> dict:
         t = HdgTuning()
         _check(self.lib.hdg_autotune(self.ctx, int(nrhs), ctypes.byref(t), _stream()))
-        return {"mlp_samples_per_lane": t.mlp_samples_per_lane}
+        return {"mlp_samples_per_lane": t.mlp_samples_per_lane, "rhs_block": t.rhs_block}
 
     # ------------------------------------------------------------------ measurement
     def set_timing(self, repeat: int):
