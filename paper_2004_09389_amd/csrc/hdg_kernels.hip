@@ -625,16 +625,35 @@ __global__ void k_p1_restrict(int nc, int nb, const int *__restrict__ crow, cons
 
 // x = Ainv b on the coarsest level when it is too large for the tail kernel:
 // one wavefront per (row, RHS), lanes stride over the row, shuffle reduction.
+// x = Ainv b on the coarsest level: one wavefront per (row, chunk of up to CH
+// right-hand sides), lanes striding the row; each matrix row is read once per
+// chunk and a lane reads the chunk's values of b[j] contiguously.
+template <int CH>
 __global__ void k_dense_mv(int n, int nb, const double *__restrict__ Ainv, const double *__restrict__ b,
                            double *__restrict__ x) {
+    const int nch = (nb + CH - 1) / CH;
     const int w = (blockIdx.x * blockDim.x + threadIdx.x) / 64;
     const int lane = threadIdx.x & 63;
-    if (w >= n * nb) return;
-    const int i = w / nb, r = w - i * nb;
-    double s = 0.0;
-    for (int j = lane; j < n; j += 64) s += Ainv[(size_t)i * n + j] * b[(size_t)j * nb + r];
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-    if (lane == 0) x[w] = s;
+    if (w >= n * nch) return;
+    const int i = w / nch, r0 = (w - i * nch) * CH;
+    const int cnt = min(CH, nb - r0);
+    double s[CH];
+#pragma unroll
+    for (int q = 0; q < CH; ++q) s[q] = 0.0;
+    for (int j = lane; j < n; j += 64) {
+        const double a = Ainv[(size_t)i * n + j];
+        const double *bj = b + (size_t)j * nb + r0;
+#pragma unroll
+        for (int q = 0; q < CH; ++q)
+            if (q < cnt) s[q] += a * bj[q];
+    }
+#pragma unroll
+    for (int q = 0; q < CH; ++q)
+        for (int off = 32; off > 0; off >>= 1) s[q] += __shfl_xor(s[q], off, 64);
+    if (lane == 0)
+#pragma unroll
+        for (int q = 0; q < CH; ++q)
+            if (q < cnt) x[(size_t)i * nb + r0 + q] = s[q];
 }
 
 // All levels 0..top of the hierarchy in one workgroup: the complete V-cycle
@@ -1332,7 +1351,10 @@ void launch_p1_restrict(int nc, int nb, const int *crow, const int *ccol, const 
     hipLaunchKernelGGL(k_p1_restrict, GRID(nc * nb, 256), 0, s, nc, nb, crow, ccol, cw, r, bc);
 }
 void launch_dense_mv(int n, int nb, const double *Ainv, const double *b, double *x, hipStream_t s) {
-    hipLaunchKernelGGL(k_dense_mv, GRID((int64_t)n * nb * 64, 256), 0, s, n, nb, Ainv, b, x);
+    if (nb == 1)
+        hipLaunchKernelGGL(k_dense_mv<1>, GRID((int64_t)n * 64, 256), 0, s, n, nb, Ainv, b, x);
+    else
+        hipLaunchKernelGGL(k_dense_mv<8>, GRID((int64_t)n * ((nb + 7) / 8) * 64, 256), 0, s, n, nb, Ainv, b, x);
 }
 void launch_p1_tail(const P1Tail &T, int nb, hipStream_t s) {
     hipLaunchKernelGGL(k_p1_tail, dim3(1), dim3(1024), 0, s, T, nb);

@@ -204,3 +204,24 @@ def test_rhs_blocked_rows_bitwise(name, nb):
     for k in (0, nb - 1):
         assert rel(outs[4][0][..., k].ravel(), oracle.apply(x[..., k].ravel())) < 1e-12
         assert rel(outs[4][2][..., k].ravel(), mg.vcycle(x[..., k].ravel())) < 1e-11
+
+
+@pytest.mark.parametrize("name", ["config1_torus8_p1", "torus12_p2_coriolis", "torus16_p3_f1", "sphere_L2_p2"])
+def test_batched_cell_kernels_bitwise(name):
+    """Condense and recover with 8 right-hand sides equal the one-column calls
+    bit for bit and the oracle to 1e-12."""
+    hier, s, oracle, _ = setup_case(name, max_rhs=16)
+    nb = 8
+    r = hi.iid_rhs(hier.fine, s.p, 70, nrhs=nb)
+    lam = np.random.default_rng(71).standard_normal((s.n_facet, s.m, nb))
+    rhat_b = trace_np(s.condense(to_dev(r)))
+    q_b = trace_np(s.recover(to_dev(r), to_dev(lam)))
+    for k in (0, 3, nb - 1):
+        rk = np.ascontiguousarray(r[..., k:k + 1])
+        lk = np.ascontiguousarray(lam[..., k:k + 1])
+        assert np.array_equal(trace_np(s.condense(to_dev(rk)))[..., 0], rhat_b[..., k])
+        assert np.array_equal(trace_np(s.recover(to_dev(rk), to_dev(lk)))[..., 0], q_b[..., k])
+        assert rel(rhat_b[..., k].ravel(), oracle.rhat(r[..., k])) < 1e-12
+        q_ref = oracle.recover(r[..., k], lam[..., k].ravel())
+        for fld in range(3):
+            assert rel(q_b[:, fld, :, k], q_ref[:, fld]) < 1e-12
