@@ -1,0 +1,109 @@
+"""Edge cases of the C ABI on the GPU: argument errors caught on the host
+before any launch, zero right-hand sides (alone and inside a batch), the
+largest batch (64 right-hand sides) and the smallest mesh."""
+import numpy as np
+import pytest
+
+import hdg_inputs as hi
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def to_dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def make(n=6, p=2, **opts):
+    from paper_2004_09389_amd.hdg import HdgSolver
+    return HdgSolver(hi.torus_hierarchy(n, n // 2 if n > 2 else 1), p, 0.4, 1.0, 1.0, 0.5, 0.0, **opts)
+
+
+def test_argument_errors_are_reported():
+    import torch
+    from paper_2004_09389_amd.hdg import HDG_EINVAL, HdgError, HdgSolver
+    with pytest.raises(HdgError) as e:
+        HdgSolver(hi.torus_hierarchy(4, 2), 4, 0.4)
+    assert e.value.code == HDG_EINVAL and "degree" in str(e.value)
+    with pytest.raises(HdgError):
+        HdgSolver(hi.torus_hierarchy(4, 2), 2, -1.0)
+    s = make(max_rhs=2)
+    x = s.trace_zeros(3)
+    with pytest.raises(HdgError) as e:
+        s.trace_apply(x)                       # nrhs above max_rhs
+    assert "max_rhs" in str(e.value)
+    # a trace buffer that is not 16-byte aligned
+    flat = torch.zeros(s.n_facet * s.m + 1, dtype=torch.float64, device="cuda")
+    mis = flat[1:].view(s.n_facet, s.m, 1)
+    with pytest.raises(HdgError) as e:
+        s.trace_apply(mis)
+    assert "aligned" in str(e.value)
+    with pytest.raises(HdgError):
+        s.set_tuning(rhs_block=3)
+    with pytest.raises(HdgError):
+        s.set_tuning(mlp_samples_per_lane=5)
+    # the context still works after the rejected calls
+    y = host(s.trace_apply(to_dev(np.ones((s.n_facet, s.m, 1)))))
+    assert np.all(np.isfinite(y))
+
+
+def test_zero_right_hand_sides():
+    """A zero right-hand side converges at once to lam = 0, alone and as one
+    column of a batch whose other columns iterate."""
+    from oracle.hdg import HdgOracle
+    s = make(max_rhs=3, krylov=2, rtol=1e-11)
+    lam, info = s.solve(s.trace_zeros(1))
+    assert info[0].iters == 0 and info[0].status == 0 and np.all(host(lam) == 0)
+    hier = hi.torus_hierarchy(6, 3)
+    o = HdgOracle(hier.fine, 2, 0.4, 1.0, 1.0, 0.5, 0.0)
+    r = hi.iid_rhs(hier.fine, 2, 5, nrhs=3)
+    r[..., 1] = 0.0
+    rhat = s.condense(to_dev(r))
+    lam, info = s.solve(rhat)
+    lam = host(lam)
+    assert np.all(lam[..., 1] == 0) and all(i.status == 0 for i in info)
+    for k in (0, 2):
+        assert rel(lam[..., k].ravel(), o.solve(r[..., k])[1]) < 1e-8
+
+
+def test_largest_batch():
+    """64 right-hand sides (the maximum) through condense, solve and recover;
+    every column against the oracle."""
+    from oracle.hdg import HdgOracle
+    hier = hi.torus_hierarchy(6, 3)
+    s = make(max_rhs=64, rtol=1e-11)
+    o = HdgOracle(hier.fine, 2, 0.4, 1.0, 1.0, 0.5, 0.0)
+    r = hi.iid_rhs(hier.fine, 2, 9, nrhs=64)
+    q, lam, info = s.step(to_dev(r))
+    q, lam = host(q), host(lam)
+    assert all(i.status == 0 for i in info)
+    for k in (0, 17, 63):
+        q_ref, lam_ref = o.solve(r[..., k])
+        assert rel(lam[..., k].ravel(), lam_ref) < 1e-9
+        for fld in range(3):
+            assert rel(q[:, fld, :, k], q_ref[:, fld]) < 1e-9
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_two_cell_mesh_every_degree(p):
+    """The smallest periodic mesh (one square, two cells, three facets)."""
+    from oracle.hdg import HdgOracle
+    from paper_2004_09389_amd.hdg import HdgSolver
+    hier = hi.torus_hierarchy(1, 1)
+    s = HdgSolver(hier, p, 0.7, 1.0, 1.0, 0.3, 0.0, rtol=1e-12)
+    o = HdgOracle(hier.fine, p, 0.7, 1.0, 1.0, 0.3, 0.0)
+    r = hi.iid_rhs(hier.fine, p, 13)
+    q, lam, info = s.step(to_dev(r))
+    q_ref, lam_ref = o.solve(r[..., 0])
+    assert info[0].status == 0
+    assert rel(host(lam)[..., 0].ravel(), lam_ref) < 1e-10
+    for fld in range(3):
+        assert rel(host(q)[:, fld, :, 0], q_ref[:, fld]) < 1e-10
