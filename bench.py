@@ -53,7 +53,7 @@ def parse():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-smoother leg")
     ap.add_argument("--train-batches", type=int, default=32, help="learned smoother: batches of random errors")
     ap.add_argument("--train-epochs", type=int, default=8, help="learned smoother: Adam steps per batch")
-    ap.add_argument("--learned-nu", type=int, default=1, help="learned smoother: sweeps before and after the coarse solve")
+    ap.add_argument("--learned-nu", type=int, default=2, help="learned smoother: sweeps before and after the coarse solve")
     ap.add_argument("--headline", default="mixed", choices=["learned", "mixed"],
                     help="which reduced-precision solver `value` reports")
     ap.add_argument("--pmc-run", action="store_true",
@@ -87,7 +87,7 @@ def cpu_baseline(n_full, p, dt):
     condensation and recovery) on a bounded sample: one right-hand side on
     the same problem with a quarter of the cells (n/2 x n/2 squares), single
     threaded; the per-solve time is scaled by the cell ratio to the full
-    workload."""
+    workload.  Also returns the oracle's solution of the sample."""
     from threadpoolctl import threadpool_limits
 
     import hdg_inputs as hi
@@ -99,12 +99,43 @@ def cpu_baseline(n_full, p, dt):
         r = hi.fourier_rhs_torus(mesh, p, 100)[..., 0]
         o = HdgOracle(mesh, p, dt, 1.0, 1.0, 1.0)
         t0 = time.perf_counter()
-        o.solve(r)
+        q_ref, lam_ref = o.solve(r)
         t = time.perf_counter() - t0
     scale = (n_full / ns) ** 2
-    return {"value": 1.0 / (t * scale), "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": f"one solve on the {ns}x{ns} torus (p={p}, same dt and f; "
-                      f"{2 * ns * ns} cells), {t:.2f} s, scaled x{scale:.0f} to {2 * n_full * n_full} cells"}
+    out = {"value": 1.0 / (t * scale), "unit": "solves/s", "cores": 1, "kind": "oracle",
+           "sample": f"one solve on the {ns}x{ns} torus (p={p}, same dt and f; "
+                     f"{2 * ns * ns} cells), {t:.2f} s, scaled x{scale:.0f} to {2 * n_full * n_full} cells"}
+    return out, (ns, r, q_ref, lam_ref)
+
+
+def errors_vs_oracle(sample, p, dt, rtol, coarse, learned_weights):
+    """Per-field relative L2 errors (h, u1, u2 and the trace) of the GPU
+    solvers against the oracle's direct solution of the CPU sample."""
+    import torch
+
+    import hdg_inputs as hi
+    from paper_2004_09389_amd.hdg import HDG_FP64, HDG_MIXED, HDG_SMOOTH_BJACOBI, HDG_SMOOTH_MLP, HdgSolver
+
+    ns, r, q_ref, lam_ref = sample
+    hier = hi.torus_hierarchy(ns, min(coarse, ns))
+    rd = torch.from_numpy(np.ascontiguousarray(r[..., None])).to("cuda")
+    out = {}
+    legs = [("fp64", HDG_FP64, HDG_SMOOTH_BJACOBI), ("mixed", HDG_MIXED, HDG_SMOOTH_BJACOBI)]
+    if learned_weights is not None:
+        legs.append(("learned", HDG_MIXED, HDG_SMOOTH_MLP))
+    for name, prec, sm in legs:
+        s = HdgSolver(hier, p, dt, 1.0, 1.0, 1.0, 0.0, 1.0, rtol=rtol, precision=prec, krylov=2, smoother=sm)
+        if sm == HDG_SMOOTH_MLP:
+            s.mlp_set_weights(*learned_weights)
+        q, lam, info = s.step(rd)
+        q, lam = q.cpu().numpy()[..., 0], lam.cpu().numpy()[..., 0].ravel()
+        e = {f: float(np.linalg.norm(q[:, i] - q_ref[:, i]) / np.linalg.norm(q_ref[:, i]))
+             for i, f in enumerate(("h", "u1", "u2"))}
+        e["trace"] = float(np.linalg.norm(lam - lam_ref) / np.linalg.norm(lam_ref))
+        e["iters"] = info[0].iters
+        out[name] = e
+        s.close()
+    return out
 
 
 def main():
@@ -199,9 +230,16 @@ def main():
         el, infos, lam, q = run(s, args.steps)
         its = [i.iters for inf in infos for i in inf]
         res = max(i.rel_res for inf in infos for i in inf)
-        rec = dict(el=el, its=float(np.mean(its)), res=res, lam=lam.clone(), setup=tsetup,
+        rec = dict(el=el, its=float(np.mean(its)), res=res, lam=lam.clone(), q=q.clone(), setup=tsetup,
                    refinements=float(np.mean([i.refinements for inf in infos for i in inf])),
                    fallbacks=int(sum(i.fallbacks for inf in infos for i in inf)))
+        if name == "mixed":
+            # error of each reduced-precision stage against its FP64 counterpart (same context)
+            xb = s.condense(rd)
+            a64, a32 = s.trace_apply(xb, HDG_FP64), s.trace_apply(xb, HDG_MIXED)
+            v64, v32 = s.mg_vcycle(xb, HDG_FP64), s.mg_vcycle(xb, HDG_MIXED)
+            rec["stages"] = {"trace_apply_fp32_rows": ((a32 - a64).norm() / a64.norm()).item(),
+                             "vcycle_mixed": ((v32 - v64).norm() / v64.norm()).item()}
         if name == args.headline:
             # instrumented pass: the same steps again, every launch of the
             # instrumented kernel classes bracketed by HIP events on its stream
@@ -283,6 +321,7 @@ def main():
         "smoother": "learned" if args.headline == "learned" else "block-jacobi",
         "iters": mx["its"],
         "fallbacks": mx["fallbacks"],
+        "setup_s": round(mx["setup"], 3),
         "refinements": mx["refinements"],
         "rel_res_max": mx["res"],
         "dof_per_s": {"trace": round(value * 3 * (p + 1) * mesh.n_cell / 2, 1),
@@ -311,9 +350,22 @@ def main():
         out["speedup_vs_fp64"] = round(fp["el"] / mx["el"], 3)
         d = (mx["lam"] - fp["lam"]).norm().item() / fp["lam"].norm().item()
         out["lam_rel_diff_vs_fp64"] = d
+        if "stages" in results.get("mixed", {}):
+            mq, fq = results["mixed"]["q"], fp["q"]
+            out["precision_report"] = {
+                **results["mixed"]["stages"],
+                "solution_trace_mixed": ((results["mixed"]["lam"] - fp["lam"]).norm() / fp["lam"].norm()).item(),
+                **{f"solution_{f}_mixed": ((mq[:, i] - fq[:, i]).norm() / fq[:, i].norm()).item()
+                   for i, f in enumerate(("h", "u1", "u2"))},
+                "note": "relative L2 differences of the mixed path against the FP64 path at each stage: "
+                        "FP32 operator rows, the mixed V-cycle (FP32 rows, BF16 smoother rows, FP32 block "
+                        "inverses) and the end-to-end solution at rtol; condense and recover are FP64 in both"}
     if not args.no_cpu:
         log("[bench] cpu oracle baseline ...")
-        out["cpu_baseline"] = cpu_baseline(n, p, dt)
+        out["cpu_baseline"], sample = cpu_baseline(n, p, dt)
+        out["error_vs_oracle"] = {
+            "sample": f"{sample[0]}x{sample[0]} torus, p={p}, same dt and f, right-hand side seed 100, rtol {args.rtol}",
+            **errors_vs_oracle(sample, p, dt, args.rtol, args.coarse, trained.get("W"))}
     print(json.dumps(out), flush=True)
 
 

@@ -1,8 +1,8 @@
 """GPU parity at the full workload sizes, in the launch configuration the
 benchmark uses, against the FP64 oracle built on the same mesh.
 
-* 256 x 256 periodic square (131072 cells), p = 3, f = 1, Courant 8
-  (786 432 trace unknowns), coarsest P1 level 32 x 32, tail kernel off,
+* 256 x 256 periodic square (131072 cells), p = 1, 2, 3, f = 1, Courant 8
+  (up to 786 432 trace unknowns), coarsest P1 level 32 x 32, tail kernel off,
   FGMRES: every entry of rhat, S x, the V-cycle and the recovered fields is
   compared with the oracle; solves are certified by the oracle's own true
   residual.
@@ -30,10 +30,10 @@ pytestmark = pytest.mark.gpu
 HMS = 6.371e6
 
 
-def _torus256():
+def _torus256(p):
     hier = hi.torus_hierarchy(256, 32)
-    return hier, dict(degree=3, dt=8.0 / 256, g=1.0, H=1.0, f0=1.0, omega=0.0), \
-        lambda nb, seed: hi.fourier_rhs_torus(hier.fine, 3, seed, nrhs=nb)
+    return hier, dict(degree=p, dt=8.0 / 256, g=1.0, H=1.0, f0=1.0, omega=0.0), \
+        lambda nb, seed: hi.fourier_rhs_torus(hier.fine, p, seed, nrhs=nb)
 
 
 def _sphere(level, p, dt):
@@ -50,7 +50,9 @@ def _sphere(level, p, dt):
 
 
 CONFIGS = {
-    "torus256_p3": (_torus256, 1),
+    "torus256_p1": (lambda: _torus256(1), 1),
+    "torus256_p2": (lambda: _torus256(2), 1),
+    "torus256_p3": (lambda: _torus256(3), 1),
     "sphere_L6_p2": (lambda: _sphere(6, 2, 1800.0), 16),
     "sphere_L7_p3": (lambda: _sphere(7, 3, 3600.0), 32),
 }
