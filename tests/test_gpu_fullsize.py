@@ -144,20 +144,39 @@ def test_solve_full_size_certified(name, precision):
 
 
 def test_learned_solve_full_size_certified():
-    """The learned smoother (trained on the GPU on random initial errors) in the
-    mixed solver on the 256 x 256 p = 3 workload, certified by the oracle."""
-    from paper_2004_09389_amd.hdg import HDG_MIXED, HDG_SMOOTH_MLP
+    """The learned smoother (trained on the GPU on random initial errors of the
+    256 x 256 p = 3 torus) in the mixed solver, certified by the oracle; the
+    same flat-trained weights then run on the level-7 sphere (p = 3), where
+    the iteration counts against block-Jacobi show the generalisation gap."""
+    from paper_2004_09389_amd.hdg import HDG_MIXED, HDG_SMOOTH_BJACOBI, HDG_SMOOTH_MLP
     from paper_2004_09389_amd.learned import train
     hier, phys, rall, nb, o, mg = problem("torus256_p3")
     s = solver("torus256_p3", precision=HDG_MIXED, smoother=HDG_SMOOTH_MLP, rtol=1e-8)
     W1, _ = hi.mlp_init(4, 64, 0)
     s.mlp_set_weights(W1.astype(np.float32), np.zeros((4, 64), np.float32))
-    hist, _ = train(s, batches=8, epochs=8, lr=3e-3)
+    hist, _ = train(s, batches=32, epochs=8, lr=3e-3)
     assert hist[-1] < hist[0]
+    weights = s.mlp_get_weights()
     r = hi.fourier_rhs_torus(hier.fine, 3, 300)
     lam, info = s.solve(s.condense(to_dev(r)))
     rh = o.rhat(r[..., 0])
     res = np.linalg.norm(rh - o.apply(host(lam)[..., 0].ravel())) / np.linalg.norm(rh)
-    print(f"[fullsize] learned: {info[0]} oracle residual {res:.3e}")
+    print(f"[fullsize] learned torus: {info[0]} oracle residual {res:.3e}")
     assert info[0].status == 0 and res <= 1e-8 * (1 + 1e-3)
     s.close()
+    # flat-trained weights on the sphere
+    hier5, phys5, r5, nb5, o5, _ = problem("sphere_L7_p3")
+    its = {}
+    for name, sm in (("block-jacobi", HDG_SMOOTH_BJACOBI), ("learned", HDG_SMOOTH_MLP)):
+        s5 = solver("sphere_L7_p3", precision=HDG_MIXED, smoother=sm, rtol=1e-8)
+        if sm == HDG_SMOOTH_MLP:
+            s5.mlp_set_weights(*weights)
+        lam5, info5 = s5.solve(s5.condense(to_dev(r5)))
+        lam5 = host(lam5)
+        for k in (0, nb5 - 1):
+            rh5 = o5.rhat(r5[..., k])
+            res5 = np.linalg.norm(rh5 - o5.apply(lam5[..., k].ravel())) / np.linalg.norm(rh5)
+            assert info5[k].status == 0 and res5 <= 1e-8 * (1 + 1e-3)
+        its[name] = (float(np.mean([i.iters for i in info5])), sum(i.fallbacks for i in info5))
+        s5.close()
+    print(f"[fullsize] sphere L7 p3, 32 right-hand sides, mean iterations (fallbacks): {its}")

@@ -256,3 +256,32 @@ def test_tuning_does_not_change_results():
     outs.append(host(solver.mg_vcycle(r)))
     for o in outs[1:]:
         assert np.array_equal(o, outs[0])
+
+
+def test_config1_training_and_gain():
+    """Config 1 (8 x 8 torus, p = 1, f = 0, Courant 4): train on random initial
+    errors, then compare FGMRES iterations to 1e-10 with block-Jacobi on
+    unseen iid right-hand sides (seeds 2000-2009).  The learned cycle must
+    converge on every seed and cost no more than one extra iteration on
+    average; the counts are printed."""
+    from paper_2004_09389_amd.hdg import HDG_SMOOTH_BJACOBI, HdgSolver
+    from paper_2004_09389_amd.learned import train
+    hier = hi.torus_hierarchy(8, 4)
+    learned = HdgSolver(hier, 1, 0.5, rtol=1e-10, max_rhs=8, smoother=1)
+    plain = HdgSolver(hier, 1, 0.5, rtol=1e-10, max_rhs=8, smoother=HDG_SMOOTH_BJACOBI, krylov=2)
+    W1, _ = hi.mlp_init(2, 64, 0)
+    learned.mlp_set_weights(W1.astype(np.float32), np.zeros((2, 64), np.float32))
+    hist, _ = train(learned, batches=32, epochs=8, lr=3e-3)
+    its = []
+    for sd in range(2000, 2010):
+        r = to_dev(hi.iid_rhs(hier.fine, 1, sd))
+        row = []
+        for s in (plain, learned):
+            lam, info = s.solve(s.condense(r))
+            assert info[0].status == 0
+            row.append(info[0].iters)
+        its.append(row)
+    its = np.array(its)
+    print(f"config 1 loss {hist[0]:.3f} -> {hist[-1]:.3f}; iterations (block-Jacobi, learned): {its.tolist()}")
+    assert hist[-1] < hist[0]
+    assert its[:, 1].mean() <= its[:, 0].mean() + 1
