@@ -75,12 +75,16 @@ extern "C" {
                                FP64 operator at every restart) around an inner flexible GMRES
                                that applies the FP32 operator and the mixed V-cycle */
 
-#define HDG_KRYLOV_AUTO   0 /* PCG when the trace operator is symmetric (f = 0, FP64), else FGMRES */
+#define HDG_KRYLOV_AUTO   0 /* PCG when the trace operator and the V-cycle are symmetric (f = 0, FP64,
+                               nu_pre = nu_post, a linear smoother), else FGMRES */
 #define HDG_KRYLOV_PCG    1
 #define HDG_KRYLOV_FGMRES 2
 
-#define HDG_SMOOTH_BJACOBI 0
-#define HDG_SMOOTH_MLP     1
+#define HDG_SMOOTH_BJACOBI   0 /* damped facet block-Jacobi sweeps */
+#define HDG_SMOOTH_MLP       1 /* learned smoother (see below) */
+#define HDG_SMOOTH_CHEBYSHEV 2 /* Chebyshev iteration of degree nu_pre / nu_post preconditioned by facet
+                                  block-Jacobi on [0.1, 1.1] lambda_max(D^-1 S), lambda_max from 20
+                                  power steps at setup (the smoother of the paper's solver settings) */
 
 /* ------------------------------------------------------------------ types */
 typedef struct hdg_ctx hdg_ctx;
@@ -107,8 +111,9 @@ typedef struct {
 typedef struct {
     int32_t krylov;             /* HDG_KRYLOV_* */
     int32_t precision;          /* solve path: HDG_FP64, HDG_MIXED or HDG_MIXED_IR */
-    int32_t smoother;           /* HDG_SMOOTH_BJACOBI or HDG_SMOOTH_MLP */
-    int32_t nu_pre, nu_post;    /* facet block-Jacobi sweeps (default 2, 2) */
+    int32_t smoother;           /* HDG_SMOOTH_BJACOBI, HDG_SMOOTH_MLP or HDG_SMOOTH_CHEBYSHEV */
+    int32_t nu_pre, nu_post;    /* smoothing sweeps (Chebyshev degree) before / after the coarse
+                                   correction (default 2, 2) */
     double  omega;              /* block-Jacobi damping (default 0.7) */
     int32_t p1_nu;              /* P1 damped-Jacobi sweeps per level, pre and post (default 2) */
     double  p1_omega;           /* P1 Jacobi damping (default 2/3) */
@@ -138,6 +143,7 @@ typedef struct {
     int32_t n_cell, n_facet, n_vert, degree, n_loc, n_levels;
     int64_t device_bytes;       /* device memory held by the context */
     double  kappa;              /* c dt */
+    double  lambda_max;         /* eigenvalue estimate of D^-1 S (Chebyshev smoother), else 0 */
 } hdg_sizes;
 
 /* ------------------------------------------------------------------ entry points */

@@ -16,7 +16,14 @@
   dense solve on the coarsest level).
 * Two-level V-cycle (Alg. twolevel_vcycle): presmooth, residual, restrict,
   coarse solve, prolong, postsmooth; the smoother is damped facet-block
-  Jacobi (the block-Jacobi smoother named as future work in the conclusion).
+  Jacobi (the block-Jacobi smoother named as future work in the conclusion)
+  or, as in the paper's solver settings, Chebyshev iteration of degree nu
+  preconditioned by facet-block Jacobi.
+* Chebyshev interval: [0.1, 1.1] times an estimate of the largest eigenvalue
+  of D^-1 S (the PETSc default transform of an eigenvalue estimate, which the
+  paper's runs inherit).  The estimate is 20 power iterations from the fixed
+  start vector v_i = (((i * 2654435761) mod 2^32) / 2^32) - 1/2 (i the global
+  trace index): v <- D^-1 S v / ||D^-1 S v||, estimate = ||D^-1 S v||.
 
 Parity unpinned for the multigrid iteration itself: no printed reference
 exists for this smoother; the tests pin only that it is a convergent linear
@@ -120,7 +127,7 @@ class TraceMultigrid:
     """Non-nested two-level V-cycle on the trace space (Alg. twolevel_vcycle)."""
 
     def __init__(self, hdg, hier, omega=None, nu_pre=2, nu_post=2, p1_omega=2.0 / 3.0, p1_nu=2,
-                 exact_coarse=False):
+                 exact_coarse=False, smoother="jacobi"):
         if hier.fine.n_vert != hdg.mesh.n_vert or hier.fine.n_cell != hdg.mesh.n_cell:
             raise ValueError("hierarchy's finest mesh must be the HDG mesh")
         self.S = hdg.S
@@ -138,11 +145,19 @@ class TraceMultigrid:
             self._lu = spla.splu(self.Sc.tocsc())
         self.omega = omega if omega is not None else default_omega()
         self.nu_pre, self.nu_post = nu_pre, nu_post
+        if smoother not in ("jacobi", "chebyshev"):
+            raise ValueError("smoother must be 'jacobi' or 'chebyshev'")
+        self.smoother = smoother
+        if smoother == "chebyshev":
+            self.lambda_max = power_estimate(self.S, self.block_jacobi)
+            self.cheb_interval = (0.1 * self.lambda_max, 1.1 * self.lambda_max)
 
     def block_jacobi(self, r):
         return np.einsum("eab,eb->ea", self.Dinv, r.reshape(self.ne, self.m)).ravel()
 
     def smooth(self, b, x, nu):
+        if self.smoother == "chebyshev":
+            return chebyshev(self.S, self.block_jacobi, b, x, nu, *self.cheb_interval)
         for _ in range(nu):
             x = x + self.omega * self.block_jacobi(b - self.S @ x)
         return x
@@ -155,6 +170,42 @@ class TraceMultigrid:
         res = b - self.S @ x
         x = x + self.pi @ self.coarse_solve(self.pi.T @ res)
         return self.smooth(b, x, self.nu_post)
+
+
+def power_start(n):
+    """Fixed start vector of the eigenvalue estimate: v_i = frac(i * 2654435761 / 2^32) - 1/2."""
+    i = np.arange(n, dtype=np.uint64)
+    return ((i * np.uint64(2654435761)) % np.uint64(2 ** 32)).astype(np.float64) / 2.0 ** 32 - 0.5
+
+
+def power_estimate(S, prec, iters=20):
+    """Largest eigenvalue estimate of prec(S .): 20 normalised power steps."""
+    v = power_start(S.shape[0])
+    v = v / np.linalg.norm(v)
+    lam = 0.0
+    for _ in range(iters):
+        w = prec(S @ v)
+        lam = np.linalg.norm(w)
+        v = w / lam
+    return lam
+
+
+def chebyshev(S, prec, b, x, k, a, bnd):
+    """k steps of Chebyshev iteration for S x = b preconditioned by prec on the
+    interval [a, bnd] (the textbook three-term form: theta the centre, delta
+    the half width, sigma = theta / delta)."""
+    theta, delta = 0.5 * (bnd + a), 0.5 * (bnd - a)
+    sigma = theta / delta
+    rho = 1.0 / sigma
+    d = prec(b - S @ x) / theta
+    for step in range(k):
+        x = x + d
+        if step == k - 1:
+            break
+        rho_new = 1.0 / (2.0 * sigma - rho)
+        d = rho_new * rho * d + (2.0 * rho_new / delta) * prec(b - S @ x)
+        rho = rho_new
+    return x
 
 
 def default_omega():

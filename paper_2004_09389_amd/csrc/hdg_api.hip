@@ -171,16 +171,19 @@ void op_apply(hdg_ctx *c, int nb, int prec, const double *x, const double *b, do
     check_launch();
 }
 
+// damped block-Jacobi sweep y = x' + omega D^-1 (r - S x')
+hdg::SweepCoef bj_coef(const hdg_ctx *c) { return {1.0 - c->opt.omega, 1.0, 1.0, 0.0, nullptr, nullptr}; }
+
 void op_sweep(hdg_ctx *c, int nb, int prec, const double *x, const double *z0, const double *qc, double *y,
-              hipStream_t s, int out_u = 0) {
+              hipStream_t s, const hdg::SweepCoef &cf) {
     Timed t(c, HDG_KERNEL_SWEEP, prec, s, nb);
     for (int rep = 0; rep < t.repeats(); ++rep) {
         if (prec == HDG_MIXED)
-            hdg::launch_sweep<__hip_bfloat16>(c->p, c->n_facet, nb, c->T16, c->nbr, x, z0, qc, c->facet_vert,
-                                              c->opt.omega, out_u, y, s, c->rhs_block);
+            hdg::launch_sweep<__hip_bfloat16>(c->p, c->n_facet, nb, c->T16, c->nbr, x, z0, qc, c->facet_vert, cf, y,
+                                              s, c->rhs_block);
         else
-            hdg::launch_sweep<double>(c->p, c->n_facet, nb, c->T64, c->nbr, x, z0, qc, c->facet_vert,
-                                      c->opt.omega, out_u, y, s, c->rhs_block);
+            hdg::launch_sweep<double>(c->p, c->n_facet, nb, c->T64, c->nbr, x, z0, qc, c->facet_vert, cf, y, s,
+                                      c->rhs_block);
     }
     check_launch();
 }
@@ -239,7 +242,7 @@ void vcycle_bj(hdg_ctx *c, int nb, int prec, const double *r, double *z, hipStre
     for (int k = 1; k < c->opt.nu_pre; ++k) {
         double *out = bufs[bi];
         bi ^= 1;
-        op_sweep(c, nb, prec, cur, c->vz0, nullptr, out, s);
+        op_sweep(c, nb, prec, cur, c->vz0, nullptr, out, s, bj_coef(c));
         cur = out;
     }
     op_apply(c, nb, prec, cur, r, c->vres, s, HDG_KERNEL_RESIDUAL);
@@ -258,7 +261,7 @@ void vcycle_bj(hdg_ctx *c, int nb, int prec, const double *r, double *z, hipStre
             }
             bi ^= 1;
         }
-        op_sweep(c, nb, prec, cur, c->vz0, k == 0 ? xl : nullptr, out, s);
+        op_sweep(c, nb, prec, cur, c->vz0, k == 0 ? xl : nullptr, out, s, bj_coef(c));
         cur = out;
     }
     check_launch();
@@ -292,7 +295,8 @@ void vcycle_mlp(hdg_ctx *c, int nb, int prec, const double *r, double *z, hipStr
     };
     learned(c->vz0, nullptr, nullptr, x);
     auto step = [&](const double *qc, double *out) {
-        op_sweep(c, nb, prec, x, c->vz0, qc, c->vres, s, 1);
+        const hdg::SweepCoef only_u{-c->opt.omega, 1.0, 1.0, 0.0, nullptr, nullptr};   // the correction alone
+        op_sweep(c, nb, prec, x, c->vz0, qc, c->vres, s, only_u);
         learned(c->vres, x, qc, out);
         if (out != z) {
             other = x;
@@ -308,10 +312,80 @@ void vcycle_mlp(hdg_ctx *c, int nb, int prec, const double *r, double *z, hipStr
     check_launch();
 }
 
+// The V-cycle with Chebyshev smoothing of degree nu (pre and post), block-
+// Jacobi preconditioned, on the interval [0.1, 1.1] lambda_max(D^-1 S):
+// x_1 = x_0 + D^-1 (r - S x_0) / theta, then
+// x_{k+1} = x_k + c1 (x_k - x_{k-1}) + c2 D^-1 (r - S x_k),
+// c1 = rho_k rho_{k-1}, c2 = 2 rho_k / delta, rho_k = 1 / (2 sigma - rho_{k-1}),
+// rho_0 = 1 / sigma, sigma = theta / delta.  Every step is one generalised
+// sweep.  From a zero iterate x_1 = z0 / (theta omega) is never stored: the
+// next sweep reads z0 with the factor folded into its coefficients.
+void vcycle_cheb(hdg_ctx *c, int nb, int prec, const double *r, double *z, hipStream_t s,
+                 const double *scale = nullptr) {
+    double *rs = scale ? const_cast<double *>(r) : nullptr;
+    jacobi0(c, nb, prec, r, scale, rs, c->vz0, s);
+    const double w = c->opt.omega, lo = 0.1 * c->cheb_lmax, hi = 1.1 * c->cheb_lmax;
+    const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
+    struct Ref {
+        const double *p;
+        double sc;
+        const double *qc;
+    };
+    auto spare = [&](const Ref &x, const Ref &xp) -> double * {
+        // overwrite the previous iterate in place when it is a work buffer (each thread reads
+        // it at its own facet only), else take the work buffer x does not occupy
+        if (xp.p == c->vx || xp.p == c->vx2) return const_cast<double *>(xp.p);
+        return x.p == c->vx ? c->vx2 : c->vx;
+    };
+    // pre-smoothing from zero
+    Ref x{c->vz0, 1.0 / (theta * w), nullptr}, xp{nullptr, 0.0, nullptr};
+    double rho = 1.0 / sigma;
+    for (int k = 1; k < c->opt.nu_pre; ++k) {
+        const double rn = 1.0 / (2.0 * sigma - rho), c1 = rn * rho, c2 = 2.0 * rn / delta;
+        const hdg::SweepCoef cf{(1.0 + c1 - c2) * x.sc, c2 / w, c2 / w * x.sc, xp.p ? -c1 * xp.sc : 0.0, xp.p,
+                                nullptr};
+        double *out = spare(x, xp);
+        op_sweep(c, nb, prec, x.p, c->vz0, nullptr, out, s, cf);
+        xp = x;
+        x = Ref{out, 1.0, nullptr};
+        rho = rn;
+    }
+    const int64_t n = (int64_t)c->n_facet * c->m * nb;
+    if (x.sc != 1.0) {
+        hdg::launch_lin3(n, x.sc, x.p, 0.0, nullptr, 0.0, nullptr, c->vx, s);
+        x = Ref{c->vx, 1.0, nullptr};
+    }
+    op_apply(c, nb, prec, x.p, r, c->vres, s, HDG_KERNEL_RESIDUAL);
+    const int L = (int)c->lev.size() - 1;
+    hdg::launch_restrict_trace(c->p, c->n_vert, nb, c->vf_row, c->vf_col, c->vres, c->lev[L].b, s);
+    const double *xl = p1_vcycle(c, L, nb, s);
+    // post-smoothing from x + pi x_P1 (the prolongation rides in the sweeps)
+    x.qc = xl;
+    xp = Ref{nullptr, 0.0, nullptr};
+    rho = 1.0 / sigma;
+    for (int k = 0; k < c->opt.nu_post; ++k) {
+        hdg::SweepCoef cf;
+        if (k == 0) {
+            cf = {1.0 - 1.0 / theta, 1.0 / (theta * w), 1.0 / (theta * w), 0.0, nullptr, nullptr};
+        } else {
+            const double rn = 1.0 / (2.0 * sigma - rho), c1 = rn * rho, c2 = 2.0 * rn / delta;
+            cf = {1.0 + c1 - c2, c2 / w, c2 / w, -c1, xp.p, xp.qc};
+            rho = rn;
+        }
+        double *out = (k == c->opt.nu_post - 1) ? z : spare(x, xp);
+        op_sweep(c, nb, prec, x.p, c->vz0, x.qc, out, s, cf);
+        xp = x;
+        x = Ref{out, 1.0, nullptr};
+    }
+    check_launch();
+}
+
 void vcycle(hdg_ctx *c, int nb, int prec, const double *r, double *z, hipStream_t s,
             const double *scale = nullptr) {
     if (c->use_mlp_now)
         vcycle_mlp(c, nb, prec, r, z, s, scale);
+    else if (c->opt.smoother == HDG_SMOOTH_CHEBYSHEV)
+        vcycle_cheb(c, nb, prec, r, z, s, scale);
     else
         vcycle_bj(c, nb, prec, r, z, s, scale);
 }
@@ -546,6 +620,36 @@ void validate_mesh(const hdg_mesh &m) {
     HDG_REQUIRE(m.geom == HDG_SPHERE || m.period > 0, "torus period must be positive");
 }
 
+// Largest eigenvalue of D^-1 S for the Chebyshev interval: 20 power steps
+// v <- D^-1 S v / ||D^-1 S v|| (FP64) from the fixed start vector
+// v_i = frac(i * 2654435761 / 2^32) - 1/2, estimate ||D^-1 S v||.
+void estimate_lambda_max(hdg_ctx *c) {
+    const int64_t n = vec_len(c);
+    std::vector<double> v(n);
+    double nrm = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        const uint64_t h = ((uint64_t)i * 2654435761ull) % 4294967296ull;
+        v[i] = (double)h / 4294967296.0 - 0.5;
+        nrm += v[i] * v[i];
+    }
+    nrm = std::sqrt(nrm);
+    for (auto &x : v) x /= nrm;
+    hipStream_t s = nullptr;
+    HDG_HIP_CHECK(hipMemcpy(c->vx, v.data(), n * sizeof(double), hipMemcpyHostToDevice));
+    double lam = 0.0;
+    for (int it = 0; it < 20; ++it) {
+        op_apply(c, 1, HDG_FP64, c->vx, nullptr, c->vres, s, HDG_KERNEL_APPLY);
+        jacobi0(c, 1, HDG_FP64, c->vres, nullptr, nullptr, c->vx2, s);   // omega D^-1 S v
+        const double *h = dots_now(c, 1, c->vx2, c->vx2, scal(c, SC_RR), s);
+        lam = std::sqrt(h[0]) / c->opt.omega;
+        HDG_REQUIRE(std::isfinite(lam) && lam > 0, "eigenvalue estimate of D^-1 S failed");
+        hdg::launch_lin3(n, 1.0 / (lam * c->opt.omega), c->vx2, 0.0, nullptr, 0.0, nullptr, c->vx, s);
+        check_launch();
+    }
+    HDG_HIP_CHECK(hipStreamSynchronize(s));
+    c->cheb_lmax = lam;
+}
+
 void setup_impl(const hdg_mesh *levels, int nlev, const int32_t *const *parents, const hdg_params *prm,
                 const hdg_options *opt_in, hdg_ctx *c) {
     HDG_REQUIRE(levels && prm && nlev >= 1, "levels, prm must be given and n_levels >= 1");
@@ -560,6 +664,8 @@ void setup_impl(const hdg_mesh *levels, int nlev, const int32_t *const *parents,
     HDG_REQUIRE(opt.omega > 0 && opt.p1_omega > 0, "damping factors must be positive");
     HDG_REQUIRE(opt.rtol >= 0 && opt.maxit >= 1, "rtol >= 0 and maxit >= 1 required");
     HDG_REQUIRE(opt.p1_tail_max >= 0 && opt.p1_tail_max <= hdg::P1_TAIL_MAX, "p1_tail_max must be in 0..4096");
+    HDG_REQUIRE(opt.smoother >= HDG_SMOOTH_BJACOBI && opt.smoother <= HDG_SMOOTH_CHEBYSHEV, "unknown smoother");
+    HDG_REQUIRE(opt.krylov >= HDG_KRYLOV_AUTO && opt.krylov <= HDG_KRYLOV_FGMRES, "unknown krylov method");
     for (int l = 0; l < nlev; ++l) validate_mesh(levels[l]);
     const hdg_mesh &fine = levels[nlev - 1];
 
@@ -799,6 +905,7 @@ void setup_impl(const hdg_mesh *levels, int nlev, const int32_t *const *parents,
     for (int i = 0; i < 2; ++i) HDG_HIP_CHECK(hipEventCreateWithFlags(&c->lag_ev[i], hipEventDisableTiming));
     c->hbn2.assign(mr, 0.0);
     HDG_HIP_CHECK(hipDeviceSynchronize());
+    if (c->opt.smoother == HDG_SMOOTH_CHEBYSHEV) estimate_lambda_max(c);
 }
 
 void destroy_impl(hdg_ctx *c) {
@@ -882,6 +989,7 @@ extern "C" int hdg_get_sizes(const hdg_ctx *c, hdg_sizes *out) {
     out->n_levels = (int)c->lev.size();
     out->device_bytes = c->device_bytes;
     out->kappa = c->kappa;
+    out->lambda_max = c->cheb_lmax;
     return HDG_OK;
 }
 
@@ -952,7 +1060,8 @@ extern "C" int hdg_solve(hdg_ctx *c, int32_t nb, const double *rhat, double *lam
         c->use_mlp_now = c->opt.smoother == HDG_SMOOTH_MLP;
         int kry = c->opt.krylov;
         if (kry == HDG_KRYLOV_AUTO)
-            kry = (c->symmetric && c->opt.precision == HDG_FP64 && !c->use_mlp_now) ? HDG_KRYLOV_PCG : HDG_KRYLOV_FGMRES;
+            kry = (c->symmetric && c->opt.precision == HDG_FP64 && !c->use_mlp_now &&
+                   c->opt.nu_pre == c->opt.nu_post) ? HDG_KRYLOV_PCG : HDG_KRYLOV_FGMRES;
         HDG_REQUIRE(!(kry == HDG_KRYLOV_PCG && c->use_mlp_now), "the learned smoother is nonlinear: use FGMRES");
         HDG_REQUIRE(c->opt.precision >= HDG_FP64 && c->opt.precision <= HDG_MIXED_IR, "unknown solve precision");
         if (kry == HDG_KRYLOV_FGMRES) HDG_REQUIRE(c->kV != nullptr, "FGMRES workspace was not allocated (krylov = PCG at setup)");
@@ -1256,7 +1365,7 @@ extern "C" int hdg_autotune(hdg_ctx *c, int32_t nb, hdg_tuning *chosen, void *st
             c->rhs_block = rb;
             const double ms = time_launches(s, 10, [&] {
                 op_apply(c, nb, HDG_FP64, c->vx, nullptr, c->vx2, s, HDG_KERNEL_APPLY);
-                op_sweep(c, nb, HDG_MIXED, c->vx, c->vres, nullptr, c->vx2, s);
+                op_sweep(c, nb, HDG_MIXED, c->vx, c->vres, nullptr, c->vx2, s, bj_coef(c));
             });
             if (ms < best) {
                 best = ms;

@@ -116,6 +116,7 @@ struct hdg_ctx {
     hdg_params prm{};
     hdg_options opt{};
     bool symmetric = false;
+    double cheb_lmax = 0.0;               // eigenvalue estimate of D^-1 S (Chebyshev smoother)
     hdg::Topology topo;
     int64_t device_bytes = 0;
     std::vector<void *> allocations;

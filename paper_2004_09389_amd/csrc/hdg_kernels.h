@@ -56,6 +56,22 @@ __device__ __forceinline__ double p1_node(int k, double q0, double q1) {
     return __builtin_fma(t, q1, (1.0 - t) * q0);
 }
 
+// Coefficients of the generalised smoothing sweep
+//   y = a0 x' + a1 z0 - a3 T x' + a2 xprev'
+// with x' = x + pi qc (prolongation term optional), xprev' = xprev + pi qcprev
+// (own facet only, optional), z0 = omega D^-1 r, T x the stored off-diagonal
+// rows omega D^-1 S_j x_j.  Damped block-Jacobi: (1 - omega, 1, 1, 0);
+// the correction alone: (-omega, 1, 1, 0); Chebyshev steps: see vcycle_cheb.
+struct SweepCoef {
+    double a0, a1, a3, a2;
+    const double *xprev, *qcprev;
+};
+// the sweep's output combination with its rounding fixed (every launch shape
+// produces the same bits)
+__device__ __forceinline__ double sweep_combine(const SweepCoef &cf, double x, double z, double acc) {
+    return __builtin_fma(-cf.a3, acc, __builtin_fma(cf.a0, x, cf.a1 * z));
+}
+
 // padded component count of a facet-row matrix stored with v entries per 16 bytes
 constexpr int wide_padded(int c, int v) { return (c + v - 1) / v * v; }
 
@@ -79,7 +95,7 @@ void launch_jacobi0(int p, int ne, int nb, const MT *Dw, const double *r, const 
                     double *z0, hipStream_t s);
 template <typename MT>
 void launch_sweep(int p, int ne, int nb, const MT *T, const int *nbr, const double *x, const double *z0,
-                  const double *qc, const int *fvert, double omega, int out_u, double *y, hipStream_t s, int rhs_block = 1);
+                  const double *qc, const int *fvert, SweepCoef cf, double *y, hipStream_t s, int rhs_block = 1);
 void launch_restrict_trace(int p, int nv, int nb, const int *vf_row, const int *vf_col, const double *res,
                            double *rc, hipStream_t s);
 

@@ -470,7 +470,7 @@ template <int M, typename MT, bool NB1>
 __global__ __launch_bounds__(256) void k_sweep(int ne, int nb, const MT *__restrict__ T,
                                                const int *__restrict__ nbr, const double *__restrict__ x,
                                                const double *__restrict__ z0, const double *__restrict__ qc,
-                                               const int *__restrict__ fvert, double omega, int out_u,
+                                               const int *__restrict__ fvert, SweepCoef cf,
                                                double *__restrict__ y) {
     using AT = typename Acc<MT>::type;
     constexpr int P = M - 1;
@@ -512,10 +512,19 @@ __global__ __launch_bounds__(256) void k_sweep(int ne, int nb, const MT *__restr
     }
     double zv[M], out[M];
     load_trace<M, NB1>(z0, e * MB + r, nb, zv);
-    // out_u: the correction y - x alone (the learned step adds it to x itself)
-    const double keep = out_u ? -omega : 1.0 - omega;
 #pragma unroll
-    for (int a = 0; a < M; ++a) out[a] = keep * xv[0][a] + zv[a] - (double)acc[a];
+    for (int a = 0; a < M; ++a) out[a] = sweep_combine(cf, xv[0][a], zv[a], (double)acc[a]);
+    if (cf.xprev) {
+        double pv[M];
+        load_trace<M, NB1>(cf.xprev, e * MB + r, nb, pv);
+        if (cf.qcprev) {
+            const double q0 = cf.qcprev[(size_t)fvert[2 * e] * nb + r], q1 = cf.qcprev[(size_t)fvert[2 * e + 1] * nb + r];
+#pragma unroll
+            for (int a = 0; a < M; ++a) pv[a] += p1_node<P>(a, q0, q1);
+        }
+#pragma unroll
+        for (int a = 0; a < M; ++a) out[a] = __builtin_fma(cf.a2, pv[a], out[a]);
+    }
     store_trace<M, NB1>(y, e * MB + r, nb, out);
 }
 
@@ -1179,13 +1188,12 @@ __global__ __launch_bounds__(1024) void k_trace_apply_rb(int ne, int nb, const M
     }
 }
 
-// y = keep x' + z0 - sum_j T_j x'_j, x' = x + pi qc (qc may be null); keep = 1 - omega, or -omega
-// when only the correction is wanted (out_u)
+// the generalised sweep y = a0 x' + a1 z0 - a3 sum_j T_j x'_j + a2 xprev' (SweepCoef)
 template <int M, typename MT, int RB>
 __global__ __launch_bounds__(1024) void k_sweep_rb(int ne, int nb, const MT *__restrict__ T,
                                                    const int *__restrict__ nbr, const double *__restrict__ x,
                                                    const double *__restrict__ z0, const double *__restrict__ qc,
-                                                   const int *__restrict__ fvert, double omega, int out_u,
+                                                   const int *__restrict__ fvert, SweepCoef cf,
                                                    double *__restrict__ y) {
     using AT = typename Acc<MT>::type;
     constexpr int P = M - 1;
@@ -1232,14 +1240,27 @@ __global__ __launch_bounds__(1024) void k_sweep_rb(int ne, int nb, const MT *__r
     }
     double xe[M][RB];
     iterate(e, xe);
-    const double keep = out_u ? -omega : 1.0 - omega;
+    double q0[RB], q1[RB];
+    if (cf.xprev && cf.qcprev) {
+        load_rb<RB>(cf.qcprev + (size_t)fvert[2 * e] * nb + r0, q0);
+        load_rb<RB>(cf.qcprev + (size_t)fvert[2 * e + 1] * nb + r0, q1);
+    }
 #pragma unroll
     for (int a = 0; a < M; ++a) {
         const size_t o = ((size_t)e * M + a) * nb + r0;
         double zv[RB], out[RB];
         load_rb<RB>(z0 + o, zv);
 #pragma unroll
-        for (int q = 0; q < RB; ++q) out[q] = keep * xe[a][q] + zv[q] - (double)acc[a][q];
+        for (int q = 0; q < RB; ++q) out[q] = sweep_combine(cf, xe[a][q], zv[q], (double)acc[a][q]);
+        if (cf.xprev) {
+            double pv[RB];
+            load_rb<RB>(cf.xprev + o, pv);
+            if (cf.qcprev)
+#pragma unroll
+                for (int q = 0; q < RB; ++q) pv[q] += p1_node<P>(a, q0[q], q1[q]);
+#pragma unroll
+            for (int q = 0; q < RB; ++q) out[q] = __builtin_fma(cf.a2, pv[q], out[q]);
+        }
         store_rb<RB>(y + o, out);
     }
 }
@@ -1305,22 +1326,22 @@ template void launch_jacobi0<float>(int, int, int, const float *, const double *
 
 template <typename MT>
 void launch_sweep(int p, int ne, int nb, const MT *T, const int *nbr, const double *x, const double *z0,
-                  const double *qc, const int *fvert, double omega, int out_u, double *y, hipStream_t s,
+                  const double *qc, const int *fvert, SweepCoef cf, double *y, hipStream_t s,
                   int rhs_block) {
     if (rhs_blocked(nb, rhs_block)) {
-#define SWB(P) hipLaunchKernelGGL((k_sweep_rb<P + 1, MT, 4>), GRID_RB(ne, nb), 0, s, ne, nb, T, nbr, x, z0, qc, fvert, omega, out_u, y)
+#define SWB(P) hipLaunchKernelGGL((k_sweep_rb<P + 1, MT, 4>), GRID_RB(ne, nb), 0, s, ne, nb, T, nbr, x, z0, qc, fvert, cf, y)
         switch (p) { case 1: SWB(1); break; case 2: SWB(2); break; case 3: SWB(3); break; }
 #undef SWB
         return;
     }
 #define SW(P)                                                                                                \
-    if (nb == 1) hipLaunchKernelGGL((k_sweep<P + 1, MT, true>), GRID8(ne * nb, 256), 0, s, ne, nb, T, nbr, x, z0, qc, fvert, omega, out_u, y); \
-    else hipLaunchKernelGGL((k_sweep<P + 1, MT, false>), GRID8(ne * nb, 256), 0, s, ne, nb, T, nbr, x, z0, qc, fvert, omega, out_u, y)
+    if (nb == 1) hipLaunchKernelGGL((k_sweep<P + 1, MT, true>), GRID8(ne * nb, 256), 0, s, ne, nb, T, nbr, x, z0, qc, fvert, cf, y); \
+    else hipLaunchKernelGGL((k_sweep<P + 1, MT, false>), GRID8(ne * nb, 256), 0, s, ne, nb, T, nbr, x, z0, qc, fvert, cf, y)
     switch (p) { case 1: SW(1); break; case 2: SW(2); break; case 3: SW(3); break; }
 #undef SW
 }
-template void launch_sweep<double>(int, int, int, const double *, const int *, const double *, const double *, const double *, const int *, double, int, double *, hipStream_t, int);
-template void launch_sweep<__hip_bfloat16>(int, int, int, const __hip_bfloat16 *, const int *, const double *, const double *, const double *, const int *, double, int, double *, hipStream_t, int);
+template void launch_sweep<double>(int, int, int, const double *, const int *, const double *, const double *, const double *, const int *, SweepCoef, double *, hipStream_t, int);
+template void launch_sweep<__hip_bfloat16>(int, int, int, const __hip_bfloat16 *, const int *, const double *, const double *, const double *, const int *, SweepCoef, double *, hipStream_t, int);
 
 void launch_restrict_trace(int p, int nv, int nb, const int *vf_row, const int *vf_col, const double *res,
                            double *rc, hipStream_t s) {

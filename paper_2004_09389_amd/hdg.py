@@ -21,7 +21,7 @@ HDG_OK, HDG_EINVAL, HDG_ENOMEM, HDG_EHIP, HDG_EBREAKDOWN, HDG_ENOTCONV = 0, -1, 
 HDG_TORUS, HDG_SPHERE = 0, 1
 HDG_FP64, HDG_MIXED, HDG_MIXED_IR = 0, 1, 2
 HDG_KRYLOV_AUTO, HDG_KRYLOV_PCG, HDG_KRYLOV_FGMRES = 0, 1, 2
-HDG_SMOOTH_BJACOBI, HDG_SMOOTH_MLP = 0, 1
+HDG_SMOOTH_BJACOBI, HDG_SMOOTH_MLP, HDG_SMOOTH_CHEBYSHEV = 0, 1, 2
 KERNELS = {"apply": 0, "sweep": 1, "residual": 2, "condense": 3, "recover": 4, "mlp": 5}
 
 
@@ -54,7 +54,7 @@ class HdgSolveInfo(ctypes.Structure):
 class HdgSizes(ctypes.Structure):
     _fields_ = [("n_cell", ctypes.c_int32), ("n_facet", ctypes.c_int32), ("n_vert", ctypes.c_int32),
                 ("degree", ctypes.c_int32), ("n_loc", ctypes.c_int32), ("n_levels", ctypes.c_int32),
-                ("device_bytes", ctypes.c_int64), ("kappa", ctypes.c_double)]
+                ("device_bytes", ctypes.c_int64), ("kappa", ctypes.c_double), ("lambda_max", ctypes.c_double)]
 
 
 class HdgTuning(ctypes.Structure):

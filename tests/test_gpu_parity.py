@@ -225,3 +225,51 @@ def test_batched_cell_kernels_bitwise(name):
         q_ref = oracle.recover(r[..., k], lam[..., k].ravel())
         for fld in range(3):
             assert rel(q_b[:, fld, :, k], q_ref[:, fld]) < 1e-12
+
+
+CHEB_CASES = ["config1_torus8_p1", "torus12_p2_coriolis", "torus16_p3_f1", "sphere_L2_p2"]
+
+
+@pytest.mark.parametrize("name", CHEB_CASES)
+@pytest.mark.parametrize("nu", [(2, 2), (1, 1), (3, 2), (1, 3)])
+def test_chebyshev_vcycle(name, nu):
+    """Chebyshev smoothing: the eigenvalue estimate and the V-cycle against the
+    oracle's textbook Chebyshev iteration (FP64 1e-11, mixed 3e-2)."""
+    from oracle.p1 import TraceMultigrid
+    from paper_2004_09389_amd.hdg import HDG_MIXED, HDG_SMOOTH_CHEBYSHEV
+    hier, s, oracle, _ = setup_case(name, smoother=HDG_SMOOTH_CHEBYSHEV, nu_pre=nu[0], nu_post=nu[1])
+    mg = TraceMultigrid(oracle, hier, smoother="chebyshev", nu_pre=nu[0], nu_post=nu[1])
+    assert abs(s.sizes.lambda_max - mg.lambda_max) <= 1e-10 * mg.lambda_max
+    r = np.random.default_rng(8).standard_normal((s.n_facet, s.m, 1))
+    ref = mg.vcycle(r[..., 0].ravel())
+    assert rel(trace_np(s.mg_vcycle(to_dev(r)))[..., 0].ravel(), ref) < 1e-11
+    assert rel(trace_np(s.mg_vcycle(to_dev(r), HDG_MIXED))[..., 0].ravel(), ref) < 3e-2
+
+
+@pytest.mark.parametrize("name", ["torus12_p2_coriolis", "torus16_p3_f1"])
+def test_chebyshev_rhs_blocked_bitwise(name):
+    from paper_2004_09389_amd.hdg import HDG_MIXED, HDG_SMOOTH_CHEBYSHEV
+    hier, s, oracle, _ = setup_case(name, smoother=HDG_SMOOTH_CHEBYSHEV, max_rhs=8, nu_pre=3, nu_post=3)
+    x = to_dev(np.random.default_rng(9).standard_normal((s.n_facet, s.m, 8)))
+    outs = []
+    for rb in (1, 4):
+        s.set_tuning(rhs_block=rb)
+        outs.append([trace_np(s.mg_vcycle(x)), trace_np(s.mg_vcycle(x, HDG_MIXED))])
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("name,prec", [("config1_torus8_p1", 0), ("torus16_p3_f1", 0), ("torus16_p3_f1", 1),
+                                       ("sphere_L2_p2", 1)])
+def test_chebyshev_solve(name, prec):
+    """Solves with the Chebyshev smoother (PCG when symmetric, else FGMRES)."""
+    from paper_2004_09389_amd.hdg import HDG_SMOOTH_CHEBYSHEV
+    hier, s, oracle, _ = setup_case(name, smoother=HDG_SMOOTH_CHEBYSHEV, precision=prec, rtol=1e-12)
+    r = hi.iid_rhs(hier.fine, s.p, 23)
+    q, lam, info = s.step(to_dev(r))
+    q_ref, lam_ref = oracle.solve(r[..., 0])
+    print(name, prec, info[0])
+    assert info[0].status == 0
+    assert rel(trace_np(lam)[..., 0].ravel(), lam_ref) < 1e-9
+    for fld in range(3):
+        assert rel(trace_np(q)[:, fld, :, 0], q_ref[:, fld]) < 1e-9

@@ -321,3 +321,52 @@ def test_vcycle_symmetric_and_convergent():
             d = z + rz / rz0 * d
         its.append(k + 1)
     assert max(its) <= 16 and max(its) - min(its) <= 3, its
+
+
+def test_chebyshev_smoother_polynomial():
+    """Chebyshev smoothing of degree k from x = 0 leaves the error P_k(A) e with
+    P_k(t) = T_k((theta - t)/delta) / T_k(theta/delta) (A = D^-1 S): checked on
+    every eigenvector of A for a small symmetric problem (f = 0)."""
+    import hdg_inputs as hi
+    from oracle.hdg import HdgOracle
+    from oracle.p1 import TraceMultigrid, chebyshev
+    hier = hi.torus_hierarchy(4, 2)
+    hdg = HdgOracle(hier.fine, 1, 0.3)
+    tmg = TraceMultigrid(hdg, hier, smoother="chebyshev")
+    S = hdg.S.toarray()
+    Dinv = np.zeros_like(S)
+    for k in range(tmg.ne):
+        sl = slice(k * tmg.m, (k + 1) * tmg.m)
+        Dinv[sl, sl] = tmg.Dinv[k]
+    lam, V = np.linalg.eig(Dinv @ S)
+    lam, V = lam.real, V.real
+    a, b = tmg.cheb_interval
+    theta, delta = (a + b) / 2, (b - a) / 2
+    for k in (1, 2, 3):
+        Tk = lambda t: np.cos(k * np.arccos(t)) if abs(t) <= 1 else np.cosh(k * np.arccosh(abs(t))) * np.sign(t) ** k
+        for i in range(0, len(lam), 5):
+            e = V[:, i]
+            x = chebyshev(hdg.S, tmg.block_jacobi, hdg.S @ e, np.zeros_like(e), k, a, b)
+            expect = Tk((theta - lam[i]) / delta) / Tk(theta / delta)
+            assert np.abs((e - x) - expect * e).max() < 1e-9 * np.abs(e).max()
+
+
+def test_power_estimate_of_largest_eigenvalue():
+    """20 power steps estimate the spectral radius of D^-1 S from below within
+    5 % (the top of the spectrum is clustered near 2), so that 1.1 times the
+    estimate covers the spectrum."""
+    import hdg_inputs as hi
+    from oracle.hdg import HdgOracle
+    from oracle.p1 import TraceMultigrid
+    for n, p, f0 in ((4, 1, 0.0), (6, 2, 0.5)):
+        hier = hi.torus_hierarchy(n, 2 if n % 2 == 0 else 1)
+        hdg = HdgOracle(hier.fine, p, 0.4, f0=f0)
+        tmg = TraceMultigrid(hdg, hier, smoother="chebyshev")
+        S = hdg.S.toarray()
+        Dinv = np.zeros_like(S)
+        for k in range(tmg.ne):
+            sl = slice(k * tmg.m, (k + 1) * tmg.m)
+            Dinv[sl, sl] = tmg.Dinv[k]
+        rho = np.abs(np.linalg.eigvals(Dinv @ S)).max()
+        assert 0.95 * rho <= tmg.lambda_max <= rho * (1 + 1e-9)
+        assert tmg.cheb_interval[1] >= rho
