@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--no-graph", action="store_true", help="launch every kernel eagerly (no HIP graphs)")
     ap.add_argument("--batch", type=int, default=16, help="also time a batch of this many right-hand sides")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-smoother leg")
+    ap.add_argument("--smoother", default="jacobi", choices=["jacobi", "chebyshev"],
+                    help="smoother of the mixed and FP64 legs (damped block-Jacobi or Chebyshev over block-Jacobi)")
     ap.add_argument("--train-batches", type=int, default=32, help="learned smoother: batches of random errors")
     ap.add_argument("--train-epochs", type=int, default=8, help="learned smoother: Adam steps per batch")
     ap.add_argument("--learned-nu", type=int, default=2, help="learned smoother: sweeps before and after the coarse solve")
@@ -153,8 +155,8 @@ def main():
     import torch
 
     import hdg_inputs as hi
-    from paper_2004_09389_amd.hdg import (HDG_FP64, HDG_MIXED, HDG_MIXED_IR, HDG_SMOOTH_BJACOBI, HDG_SMOOTH_MLP,
-                                          HdgSolver)
+    from paper_2004_09389_amd.hdg import (HDG_FP64, HDG_MIXED, HDG_MIXED_IR, HDG_SMOOTH_BJACOBI,
+                                          HDG_SMOOTH_CHEBYSHEV, HDG_SMOOTH_MLP, HdgSolver)
     from paper_2004_09389_amd.learned import train
 
     torch.cuda.set_device(0)
@@ -172,7 +174,9 @@ def main():
     def make(prec, nb_override=None, learned=False):
         t = time.perf_counter()
         s = HdgSolver(hier, p, dt, 1.0, 1.0, 1.0, 0.0, 1.0, rtol=args.rtol, precision=prec,
-                      max_rhs=nb_override or nb, smoother=HDG_SMOOTH_MLP if learned else HDG_SMOOTH_BJACOBI,
+                      max_rhs=nb_override or nb,
+                      smoother=HDG_SMOOTH_MLP if learned else (HDG_SMOOTH_CHEBYSHEV if args.smoother == "chebyshev"
+                                                               else HDG_SMOOTH_BJACOBI),
                       **({"nu_pre": args.learned_nu, "nu_post": args.learned_nu} if learned else {}),
                       krylov=2, maxit=200, p1_tail_max=args.tail_max, p1_nu=args.p1_nu,
                       use_graph=0 if args.no_graph else 1)
@@ -318,7 +322,7 @@ def main():
                    "rtol": args.rtol, "precision": args.mixed_mode,
                    "coarsest_p1": f"{args.coarse}x{args.coarse}", "p1_tail_max": args.tail_max,
                    "hip_graphs": not args.no_graph},
-        "smoother": "learned" if args.headline == "learned" else "block-jacobi",
+        "smoother": "learned" if args.headline == "learned" else args.smoother,
         "iters": mx["its"],
         "fallbacks": mx["fallbacks"],
         "setup_s": round(mx["setup"], 3),
