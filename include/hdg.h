@@ -129,6 +129,10 @@ typedef struct {
                                    its second iteration on (default 0.5) */
     int32_t p1_tail_max;        /* P1 levels with at most this many vertices run inside one
                                    single-workgroup kernel (default 4096, max 4096, 0 = never) */
+    int32_t p1_galerkin;        /* 0: the rediscretised coarse form (1/kappa)(M_1 + kappa^2 K_1) on
+                                   every P1 level (default); 1: the Galerkin form S_c = pi^T S pi on
+                                   the finest P1 level (the footnoted alternative of the non-nested
+                                   multigrid section) and P^T A P below it */
 } hdg_options;
 
 typedef struct {

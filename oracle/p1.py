@@ -13,7 +13,9 @@
 * The coarse problem is solved approximately by one geometric-multigrid
   V-cycle over a nested P1 hierarchy (rediscretised S_c on every level,
   linear-interpolation transfer from the mesh's parent map, damped Jacobi,
-  dense solve on the coarsest level).
+  dense solve on the coarsest level).  Variant (galerkin=True): the Galerkin
+  form S_c = pi^T S pi of the section's footnote on the finest P1 level and
+  P^T A P below it.
 * Two-level V-cycle (Alg. twolevel_vcycle): presmooth, residual, restrict,
   coarse solve, prolong, postsmooth; the smoother is damped facet-block
   Jacobi (the block-Jacobi smoother named as future work in the conclusion)
@@ -88,9 +90,16 @@ def transfer(parents, n_coarse):
 class P1Multigrid:
     """One V-cycle of geometric multigrid for S_c on a nested P1 hierarchy."""
 
-    def __init__(self, hier, kappa, omega=2.0 / 3.0, nu=2):
-        self.A = [coarse_operator(m, kappa) for m in hier.meshes]
+    def __init__(self, hier, kappa, omega=2.0 / 3.0, nu=2, fine_operator=None):
         self.P = [transfer(par, hier.meshes[l].n_vert) for l, par in enumerate(hier.parents)]
+        if fine_operator is None:
+            self.A = [coarse_operator(m, kappa) for m in hier.meshes]
+        else:
+            # Galerkin hierarchy: the given finest operator, then A_{l-1} = P^T A_l P
+            A = [sp.csr_matrix(fine_operator)]
+            for P in reversed(self.P):
+                A.insert(0, (P.T @ A[0] @ P).tocsr())
+            self.A = A
         self.Dinv = [1.0 / a.diagonal() for a in self.A]
         self.omega, self.nu = omega, nu
         self.coarse_inv = np.linalg.inv(self.A[0].toarray())
@@ -127,7 +136,7 @@ class TraceMultigrid:
     """Non-nested two-level V-cycle on the trace space (Alg. twolevel_vcycle)."""
 
     def __init__(self, hdg, hier, omega=None, nu_pre=2, nu_post=2, p1_omega=2.0 / 3.0, p1_nu=2,
-                 exact_coarse=False, smoother="jacobi"):
+                 exact_coarse=False, smoother="jacobi", galerkin=False):
         if hier.fine.n_vert != hdg.mesh.n_vert or hier.fine.n_cell != hdg.mesh.n_cell:
             raise ValueError("hierarchy's finest mesh must be the HDG mesh")
         self.S = hdg.S
@@ -137,7 +146,12 @@ class TraceMultigrid:
         self.Dinv = np.linalg.inv(self.D)
         self.m, self.ne = m, ne
         self.pi = injection(hdg.topo, hdg.p, hdg.mesh.n_vert)
-        self.mg = P1Multigrid(hier, hdg.kappa, p1_omega, p1_nu)
+        if galerkin:
+            # the coarse form footnoted in the non-nested multigrid section: S_c(q, v) = S(pi q, pi v)
+            Sc = (self.pi.T @ self.S @ self.pi).tocsr()
+            self.mg = P1Multigrid(hier, hdg.kappa, p1_omega, p1_nu, fine_operator=Sc)
+        else:
+            self.mg = P1Multigrid(hier, hdg.kappa, p1_omega, p1_nu)
         self.Sc = self.mg.A[-1]
         self.exact_coarse = exact_coarse
         if exact_coarse:

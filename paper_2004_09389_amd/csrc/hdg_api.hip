@@ -665,6 +665,7 @@ void setup_impl(const hdg_mesh *levels, int nlev, const int32_t *const *parents,
     HDG_REQUIRE(opt.rtol >= 0 && opt.maxit >= 1, "rtol >= 0 and maxit >= 1 required");
     HDG_REQUIRE(opt.p1_tail_max >= 0 && opt.p1_tail_max <= hdg::P1_TAIL_MAX, "p1_tail_max must be in 0..4096");
     HDG_REQUIRE(opt.smoother >= HDG_SMOOTH_BJACOBI && opt.smoother <= HDG_SMOOTH_CHEBYSHEV, "unknown smoother");
+    HDG_REQUIRE(opt.p1_galerkin == 0 || opt.p1_galerkin == 1, "p1_galerkin must be 0 or 1");
     HDG_REQUIRE(opt.krylov >= HDG_KRYLOV_AUTO && opt.krylov <= HDG_KRYLOV_FGMRES, "unknown krylov method");
     for (int l = 0; l < nlev; ++l) validate_mesh(levels[l]);
     const hdg_mesh &fine = levels[nlev - 1];
@@ -767,9 +768,24 @@ void setup_impl(const hdg_mesh *levels, int nlev, const int32_t *const *parents,
     HDG_REQUIRE(levels[nlev - 1].n_vert == nv, "the finest hierarchy level must be the HDG mesh");
     c->lev.resize(nlev);
     const int mr = opt.max_rhs;
+    std::vector<hdg::P1Host> galerkin;
+    if (opt.p1_galerkin) {
+        // S_c = pi^T S pi on the finest level, P^T A P below it (built on the host from the FP64 rows)
+        std::vector<double> rows((size_t)hdg::wide_padded(5 * m * m, 2) * ne);
+        std::vector<int32_t> nbr_h((size_t)4 * ne);
+        HDG_HIP_CHECK(hipDeviceSynchronize());
+        HDG_HIP_CHECK(hipMemcpy(rows.data(), c->S64, rows.size() * sizeof(double), hipMemcpyDeviceToHost));
+        HDG_HIP_CHECK(hipMemcpy(nbr_h.data(), c->nbr, nbr_h.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+        galerkin.resize(nlev);
+        galerkin[nlev - 1] = hdg::galerkin_from_rows(ne, m, nv, rows, nbr_h, c->topo.facet_vert);
+        for (int l = nlev - 1; l > 0; --l) {
+            HDG_REQUIRE(parents && parents[l], "parents[l] must be given for every level above the coarsest");
+            galerkin[l - 1] = hdg::galerkin_coarsen(galerkin[l], parents[l], levels[l - 1].n_vert);
+        }
+    }
     for (int l = 0; l < nlev; ++l) {
         const hdg_mesh &lm = levels[l];
-        hdg::P1Host P = hdg::assemble_p1(lm, c->kappa);
+        hdg::P1Host P = opt.p1_galerkin ? galerkin[l] : hdg::assemble_p1(lm, c->kappa);
         hdg::P1LevelDev &L = c->lev[l];
         L.n = lm.n_vert;
         std::vector<double> dinv(L.n);
@@ -805,7 +821,7 @@ void setup_impl(const hdg_mesh *levels, int nlev, const int32_t *const *parents,
                 dense[(size_t)v * L.n + v] = P.diag[v];
                 for (int k = P.rowptr[v]; k < P.rowptr[v + 1]; ++k) dense[(size_t)v * L.n + P.col[k]] += P.val[k];
             }
-            if (!hdg::spd_inverse(dense, L.n)) throw Error{HDG_EINVAL, "coarsest P1 operator is singular"};
+            if (!hdg::spd_inverse(dense, L.n)) throw Error{HDG_EINVAL, "coarsest P1 operator is singular"};   // pivoted inverse
             c->coarse_inv = dev_upload(c, dense);
         } else {
             HDG_REQUIRE(parents && parents[l], "parents[l] must be given for every level above the coarsest");
@@ -933,6 +949,7 @@ extern "C" int hdg_default_options(hdg_options *o) {
     o->krylov = HDG_KRYLOV_AUTO;
     o->precision = HDG_FP64;
     o->smoother = HDG_SMOOTH_BJACOBI;
+    o->p1_galerkin = 0;
     o->nu_pre = 2;
     o->nu_post = 2;
     o->omega = 0.7;

@@ -334,6 +334,79 @@ P1Host assemble_p1(const hdg_mesh &mesh, double kappa) {
     return P;
 }
 
+// Galerkin coarse form on the finest P1 level, S_c = pi^T S pi (the coarse form
+// footnoted in the non-nested multigrid section), from the facet rows of S:
+// rows [component / 2][n_facet][2] with component (j m + a) m + k for block j
+// (0 = the facet itself, 1..4 = nbr[j - 1]); pi puts (1 - k/p, k/p) of the
+// facet's (start, end) vertex values on trace node k.
+P1Host galerkin_from_rows(int ne, int m, int nv, const std::vector<double> &rows, const std::vector<int32_t> &nbr,
+                          const std::vector<int32_t> &facet_vert) {
+    const int p = m - 1;
+    std::vector<std::map<int, double>> A(nv);
+    for (int e = 0; e < ne; ++e) {
+        int id[5] = {e, nbr[e], nbr[(size_t)ne + e], nbr[2 * (size_t)ne + e], nbr[3 * (size_t)ne + e]};
+        const int rv[2] = {facet_vert[2 * e], facet_vert[2 * e + 1]};
+        for (int j = 0; j < 5; ++j) {
+            const int cv[2] = {facet_vert[2 * id[j]], facet_vert[2 * id[j] + 1]};
+            for (int a = 0; a < m; ++a)
+                for (int k = 0; k < m; ++k) {
+                    const int comp = (j * m + a) * m + k;
+                    const double sv = rows[((size_t)(comp / 2) * ne + e) * 2 + comp % 2];
+                    const double wa[2] = {1.0 - (double)a / p, (double)a / p};
+                    const double wk[2] = {1.0 - (double)k / p, (double)k / p};
+                    for (int x = 0; x < 2; ++x)
+                        for (int y = 0; y < 2; ++y) A[rv[x]][cv[y]] += wa[x] * sv * wk[y];
+                }
+        }
+    }
+    P1Host P;
+    P.n = nv;
+    P.rowptr.assign(nv + 1, 0);
+    P.diag.assign(nv, 0.0);
+    for (int v = 0; v < nv; ++v) {
+        for (auto &kv : A[v]) {
+            if (kv.first == v) {
+                P.diag[v] = kv.second;
+            } else {
+                P.col.push_back(kv.first);
+                P.val.push_back(kv.second);
+            }
+        }
+        P.rowptr[v + 1] = (int)P.col.size();
+    }
+    return P;
+}
+
+// A_c = P^T A P with P the linear interpolation of the parent map (fine vertex v
+// takes half of each of its two parents; an inherited vertex lists one parent twice)
+P1Host galerkin_coarsen(const P1Host &F, const int32_t *parents, int nc) {
+    std::vector<std::map<int, double>> A(nc);
+    auto add_row = [&](int v, int w, double a) {
+        for (int x = 0; x < 2; ++x)
+            for (int y = 0; y < 2; ++y) A[parents[2 * v + x]][parents[2 * w + y]] += 0.25 * a;
+    };
+    for (int v = 0; v < F.n; ++v) {
+        add_row(v, v, F.diag[v]);
+        for (int q = F.rowptr[v]; q < F.rowptr[v + 1]; ++q) add_row(v, F.col[q], F.val[q]);
+    }
+    P1Host P;
+    P.n = nc;
+    P.rowptr.assign(nc + 1, 0);
+    P.diag.assign(nc, 0.0);
+    for (int v = 0; v < nc; ++v) {
+        for (auto &kv : A[v]) {
+            if (kv.first == v) {
+                P.diag[v] = kv.second;
+            } else {
+                P.col.push_back(kv.first);
+                P.val.push_back(kv.second);
+            }
+        }
+        P.rowptr[v + 1] = (int)P.col.size();
+    }
+    return P;
+}
+
 bool spd_inverse(std::vector<double> &a, int n) {
     for (int i = 0; i < n; ++i)
         if (!(a[(size_t)i * n + i] > 0.0)) return false;

@@ -72,6 +72,9 @@ struct P1Host {
     std::vector<double> diag;
 };
 P1Host assemble_p1(const hdg_mesh &mesh, double kappa);
+P1Host galerkin_from_rows(int ne, int m, int nv, const std::vector<double> &rows, const std::vector<int32_t> &nbr,
+                          const std::vector<int32_t> &facet_vert);
+P1Host galerkin_coarsen(const P1Host &fine, const int32_t *parents, int nc);
 // in-place inverse of a dense SPD matrix [n][n]; returns false when not positive definite
 bool spd_inverse(std::vector<double> &a, int n);
 

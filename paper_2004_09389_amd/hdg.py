@@ -43,7 +43,7 @@ class HdgOptions(ctypes.Structure):
                 ("p1_nu", ctypes.c_int32), ("p1_omega", ctypes.c_double), ("rtol", ctypes.c_double),
                 ("maxit", ctypes.c_int32), ("restart", ctypes.c_int32), ("max_rhs", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("fallback_ratio", ctypes.c_double),
-                ("p1_tail_max", ctypes.c_int32)]
+                ("p1_tail_max", ctypes.c_int32), ("p1_galerkin", ctypes.c_int32)]
 
 
 class HdgSolveInfo(ctypes.Structure):

@@ -273,3 +273,23 @@ def test_chebyshev_solve(name, prec):
     assert rel(trace_np(lam)[..., 0].ravel(), lam_ref) < 1e-9
     for fld in range(3):
         assert rel(trace_np(q)[:, fld, :, 0], q_ref[:, fld]) < 1e-9
+
+
+@pytest.mark.parametrize("name", ["config1_torus8_p1", "torus12_p2_coriolis", "torus16_p3_f1", "sphere_L2_p2",
+                                  "torus96_p1_deep"])
+def test_galerkin_coarse_form(name):
+    """Galerkin P1 hierarchy (S_c = pi^T S pi, then P^T A P) against the oracle's:
+    V-cycle to 1e-11 (tail kernel on and off), solve to the oracle's direct solution."""
+    from oracle.p1 import TraceMultigrid
+    hier, s, oracle, _ = setup_case(name, p1_galerkin=1, rtol=1e-12)
+    _, s0, _, _ = setup_case(name, p1_galerkin=1, p1_tail_max=0)
+    mg = TraceMultigrid(oracle, hier, galerkin=True)
+    r = np.random.default_rng(12).standard_normal((s.n_facet, s.m, 1))
+    ref = mg.vcycle(r[..., 0].ravel())
+    assert rel(trace_np(s.mg_vcycle(to_dev(r)))[..., 0].ravel(), ref) < 1e-11
+    assert rel(trace_np(s0.mg_vcycle(to_dev(r)))[..., 0].ravel(), ref) < 1e-11
+    rr = hi.iid_rhs(hier.fine, s.p, 24)
+    q, lam, info = s.step(to_dev(rr))
+    print(name, "galerkin", info[0])
+    assert info[0].status == 0
+    assert rel(trace_np(lam)[..., 0].ravel(), oracle.solve(rr[..., 0])[1]) < 1e-9

@@ -370,3 +370,28 @@ def test_power_estimate_of_largest_eigenvalue():
         rho = np.abs(np.linalg.eigvals(Dinv @ S)).max()
         assert 0.95 * rho <= tmg.lambda_max <= rho * (1 + 1e-9)
         assert tmg.cheb_interval[1] >= rho
+
+
+def test_galerkin_coarse_correction_is_a_projection():
+    """With the Galerkin coarse form and an exact coarse solve, the coarse
+    correction E = I - pi S_c^-1 pi^T S is idempotent (E^2 = E) and kills the
+    range of pi; S_c is symmetric positive definite for f = 0."""
+    import hdg_inputs as hi
+    from oracle.hdg import HdgOracle
+    from oracle.p1 import TraceMultigrid
+    for f0 in (0.0, 0.8):
+        hier = hi.torus_hierarchy(4, 2)
+        hdg = HdgOracle(hier.fine, 2, 0.3, f0=f0)
+        tmg = TraceMultigrid(hdg, hier, galerkin=True)
+        S, Pi, Sc = hdg.S.toarray(), tmg.pi.toarray(), tmg.Sc.toarray()
+        E = np.eye(S.shape[0]) - Pi @ np.linalg.solve(Sc, Pi.T @ S)
+        assert np.abs(E @ E - E).max() < 1e-10
+        assert np.abs(E @ Pi).max() < 1e-10
+        if f0 == 0.0:
+            assert np.abs(Sc - Sc.T).max() < 1e-12 * np.abs(Sc).max()
+            np.linalg.cholesky(Sc)
+        # coarser levels are Galerkin products of the finer ones
+        mg = tmg.mg
+        for l in range(1, len(mg.A)):
+            P = mg.P[l - 1].toarray()
+            assert np.abs(mg.A[l - 1].toarray() - P.T @ mg.A[l].toarray() @ P).max() < 1e-12 * np.abs(mg.A[l].toarray()).max()
