@@ -703,7 +703,7 @@ void setup_impl(const hdg_mesh *levels, int nlev, const int32_t *const *parents,
     int *d_err = dev_alloc<int>(c, 1);
     HDG_HIP_CHECK(hipMemset(d_err, 0, sizeof(int)));
     double *Sloc = dev_alloc<double>(c, (size_t)c->nt * c->nt * nk);
-    c->Zr = dev_alloc<double>(c, (size_t)c->nt * c->nc * nk);
+    c->Zr = dev_alloc<double>(c, (size_t)c->nt * hdg::cell_zw(c->p) * nk);
     c->Ar = dev_alloc<double>(c, (size_t)c->nc * c->nc * nk);
     c->Wr = dev_alloc<double>(c, (size_t)c->nc * c->nt * nk);
     hdg::CellParams cp{c->kappa, c->tau, c->dt, prm->f0, prm->omega, c->hscale, fine.geom};

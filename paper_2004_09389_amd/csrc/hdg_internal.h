@@ -125,7 +125,7 @@ struct hdg_ctx {
     std::vector<void *> allocations;
 
     // per-cell matrices, component-major [row][col][n_cell]
-    double *Zr = nullptr;      // [nt][nc]  C A^-1 Mtilde  (condense)
+    double *Zr = nullptr;      // [nt][nc, padded even]  C A^-1 Mtilde  (condense), 16-byte pairs
     double *Ar = nullptr;      // [nc][nc]  A^-1 Mtilde, phi rows / hscale  (recover)
     double *Wr = nullptr;      // [nc][nt]  A^-1 B, phi rows / hscale       (recover)
     int32_t *cell_facet = nullptr;  // [3][n_cell]

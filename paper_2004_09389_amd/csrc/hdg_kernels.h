@@ -72,6 +72,11 @@ __device__ __forceinline__ double sweep_combine(const SweepCoef &cf, double x, d
     return __builtin_fma(-cf.a3, acc, __builtin_fma(cf.a0, x, cf.a1 * z));
 }
 
+// The condensation rows Zr (C A^-1 Mtilde, length nc per trace row) are stored
+// in 16-byte pairs [entry / 2][n_cell][2], rows padded to an even length.
+// (The recovery matrices stay one entry per lane: measured faster there.)
+constexpr int cell_zw(int p) { return ((3 * (p + 1) * (p + 2) / 2) + 1) / 2 * 2; }
+
 // padded component count of a facet-row matrix stored with v entries per 16 bytes
 constexpr int wide_padded(int c, int v) { return (c + v - 1) / v * v; }
 

@@ -243,11 +243,14 @@ __global__ __launch_bounds__(64) void k_cell_condense(int nk, const double *__re
         for (int j = 0; j < nc; ++j) s += Cm[a * nc + j] * aug[j * LD + nc + b];
         Sloc[(size_t)idx * NK + K] = s;
     }
-    for (int idx = lane; idx < nt * nc; idx += 64) {
-        const int a = idx / nc, b = idx % nc;
+    // Zr = C A^-1 Mtilde, rows padded to ZW (zeros), stored as 16-byte pairs
+    constexpr int ZW = cell_zw(P);
+    for (int idx = lane; idx < nt * ZW; idx += 64) {
+        const int a = idx / ZW, b = idx % ZW;
         double s = 0.0;
-        for (int j = 0; j < nc; ++j) s += Cm[a * nc + j] * aug[j * LD + nc + nt + b];
-        Zr[(size_t)idx * NK + K] = s;
+        if (b < nc)
+            for (int j = 0; j < nc; ++j) s += Cm[a * nc + j] * aug[j * LD + nc + nt + b];
+        Zr[((size_t)(idx / 2) * NK + K) * 2 + idx % 2] = s;
     }
     const double ih = 1.0 / cp.hscale;
     for (int idx = lane; idx < nc * nc; idx += 64) {
@@ -753,19 +756,24 @@ __global__ __launch_bounds__(1024) void k_p1_tail(const P1Tail Targ, int nb) {
 template <int P>
 __global__ __launch_bounds__(256) void k_condense_cell(int nk, int nb, const double *__restrict__ Zr,
                                                        const double *__restrict__ rc, double *__restrict__ loc) {
-    constexpr int n = (P + 1) * (P + 2) / 2, m = P + 1, nc = 3 * n, nt = 3 * m;
+    constexpr int n = (P + 1) * (P + 2) / 2, m = P + 1, nc = 3 * n, nt = 3 * m, ZW = cell_zw(P);
     const int t = xcd_block() * blockDim.x + threadIdx.x;
     if (t >= nk * nb) return;
     const int K = t / nb, r = t - K * nb;
     const size_t NK = (size_t)nk;
-    double f[nc];
+    double f[ZW];
 #pragma unroll
-    for (int j = 0; j < nc; ++j) f[j] = rc[((size_t)K * nc + j) * nb + r];
+    for (int j = 0; j < ZW; ++j) f[j] = j < nc ? rc[((size_t)K * nc + j) * nb + r] : 0.0;
 #pragma unroll
     for (int a = 0; a < nt; ++a) {
         double s = 0.0;
 #pragma unroll
-        for (int j = 0; j < nc; ++j) s += ldm(Zr + (size_t)(a * nc + j) * NK + K) * f[j];
+        for (int jp = 0; jp < ZW / 2; ++jp) {
+            double w[2];
+            Wide<double>::load(Zr + ((size_t)(a * ZW / 2 + jp) * NK + K) * 2, w);
+            s += w[0] * f[2 * jp];
+            if (2 * jp + 1 < nc) s += w[1] * f[2 * jp + 1];
+        }
         loc[((size_t)a * NK + K) * nb + r] = s;
     }
 }
