@@ -827,6 +827,54 @@ __global__ __launch_bounds__(256) void k_recover(int nk, int nb, const double *_
     }
 }
 
+// Recovery with one right-hand side: the block's 128 cells read their inputs
+// and write their outputs through LDS, so the global traffic of r_cell and q
+// (nc consecutive values per cell) is coalesced; same arithmetic order as
+// k_recover.
+constexpr int RECOVER_TILE = 128;
+template <int P>
+__global__ __launch_bounds__(RECOVER_TILE) void k_recover_n1(int nk, const double *__restrict__ Ar,
+                                                            const double *__restrict__ Wr,
+                                                            const int *__restrict__ cell_facet,
+                                                            const int8_t *__restrict__ cell_rev,
+                                                            const double *__restrict__ rc,
+                                                            const double *__restrict__ lam, double *__restrict__ q) {
+    constexpr int n = (P + 1) * (P + 2) / 2, m = P + 1, nc = 3 * n, nt = 3 * m;
+    __shared__ double buf[RECOVER_TILE * nc];
+    const int K0 = xcd_block() * RECOVER_TILE, tid = threadIdx.x, K = K0 + tid;
+    const int cnt = min(RECOVER_TILE, nk - K0);   // may be <= 0 in the padding blocks
+    const size_t NK = (size_t)nk;
+    for (int i = tid; i < cnt * nc; i += RECOVER_TILE) buf[i] = rc[(size_t)K0 * nc + i];
+    __syncthreads();
+    double f[nc], l[nt];
+    const bool live = tid < cnt;
+#pragma unroll
+    for (int j = 0; j < nc; ++j) f[j] = live ? buf[tid * nc + j] : 0.0;
+    if (live) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const int e = cell_facet[i * NK + K];
+            const int rev = cell_rev[i * NK + K];
+#pragma unroll
+            for (int k = 0; k < m; ++k) l[i * m + k] = lam[(size_t)e * m + (rev ? P - k : k)];
+        }
+    }
+    __syncthreads();
+    if (live) {
+#pragma unroll 1
+        for (int a = 0; a < nc; ++a) {
+            double s = 0.0;
+#pragma unroll
+            for (int j = 0; j < nc; ++j) s += ldm(Ar + (size_t)(a * nc + j) * NK + K) * f[j];
+#pragma unroll
+            for (int j = 0; j < nt; ++j) s -= ldm(Wr + (size_t)(a * nt + j) * NK + K) * l[j];
+            buf[tid * nc + a] = s;
+        }
+    }
+    __syncthreads();
+    for (int i = tid; i < cnt * nc; i += RECOVER_TILE) q[(size_t)K0 * nc + i] = buf[i];
+}
+
 // ------------------------------------------------------------------ Krylov vector kernels
 //
 // Vectors are [len][nb]; per-RHS reductions run in two deterministic passes
@@ -1401,7 +1449,12 @@ void launch_condense(int p, int nk, int ne, int nb, const double *Zr, const doub
 
 void launch_recover(int p, int nk, int nb, const double *Ar, const double *Wr, const int *cell_facet,
                     const int8_t *cell_rev, const double *rc, const double *lam, double *q, hipStream_t s) {
-#define RC(P) hipLaunchKernelGGL(k_recover<P>, GRID8(nk * nb, 256), 0, s, nk, nb, Ar, Wr, cell_facet, cell_rev, rc, lam, q)
+#define RC(P)                                                                                                  \
+    if (nb == 1)                                                                                               \
+        hipLaunchKernelGGL(k_recover_n1<P>, GRID8(nk, RECOVER_TILE), 0, s, nk, Ar, Wr, cell_facet, cell_rev, rc, \
+                           lam, q);                                                                            \
+    else                                                                                                       \
+        hipLaunchKernelGGL(k_recover<P>, GRID8(nk * nb, 256), 0, s, nk, nb, Ar, Wr, cell_facet, cell_rev, rc, lam, q)
     switch (p) { case 1: RC(1); break; case 2: RC(2); break; case 3: RC(3); break; }
 #undef RC
 }
