@@ -753,6 +753,8 @@ __global__ __launch_bounds__(1024) void k_p1_tail(const P1Tail Targ, int nb) {
 // ------------------------------------------------------------------ condensation / recovery (per solve)
 
 // loc[rho][K][r] = sum_j Zr[rho][j][K] r_cell[K][j][r]   (Step 1, cell part)
+constexpr int RECOVER_TILE = 128;   // cells per block of the one-right-hand-side cell kernels
+
 template <int P>
 __global__ __launch_bounds__(256) void k_condense_cell(int nk, int nb, const double *__restrict__ Zr,
                                                        const double *__restrict__ rc, double *__restrict__ loc) {
@@ -775,6 +777,37 @@ __global__ __launch_bounds__(256) void k_condense_cell(int nk, int nb, const dou
             if (2 * jp + 1 < nc) s += w[1] * f[2 * jp + 1];
         }
         loc[((size_t)a * NK + K) * nb + r] = s;
+    }
+}
+
+// Condensation at one right-hand side: the block's cells read their inputs
+// through LDS (coalesced global loads); same arithmetic order as k_condense_cell.
+template <int P>
+__global__ __launch_bounds__(RECOVER_TILE) void k_condense_cell_n1(int nk, const double *__restrict__ Zr,
+                                                                  const double *__restrict__ rc,
+                                                                  double *__restrict__ loc) {
+    constexpr int n = (P + 1) * (P + 2) / 2, m = P + 1, nc = 3 * n, nt = 3 * m, ZW = cell_zw(P);
+    __shared__ double buf[RECOVER_TILE * nc];
+    const int K0 = xcd_block() * RECOVER_TILE, tid = threadIdx.x, K = K0 + tid;
+    const int cnt = min(RECOVER_TILE, nk - K0);
+    const size_t NK = (size_t)nk;
+    for (int i = tid; i < cnt * nc; i += RECOVER_TILE) buf[i] = rc[(size_t)K0 * nc + i];
+    __syncthreads();
+    if (tid >= cnt) return;
+    double f[ZW];
+#pragma unroll
+    for (int j = 0; j < ZW; ++j) f[j] = j < nc ? buf[tid * nc + j] : 0.0;
+#pragma unroll
+    for (int a = 0; a < nt; ++a) {
+        double s = 0.0;
+#pragma unroll
+        for (int jp = 0; jp < ZW / 2; ++jp) {
+            double w[2];
+            Wide<double>::load(Zr + ((size_t)(a * ZW / 2 + jp) * NK + K) * 2, w);
+            s += w[0] * f[2 * jp];
+            if (2 * jp + 1 < nc) s += w[1] * f[2 * jp + 1];
+        }
+        loc[(size_t)a * NK + K] = s;
     }
 }
 
@@ -827,11 +860,10 @@ __global__ __launch_bounds__(256) void k_recover(int nk, int nb, const double *_
     }
 }
 
-// Recovery with one right-hand side: the block's 128 cells read their inputs
+// Recovery with one right-hand side: the block's cells read their inputs
 // and write their outputs through LDS, so the global traffic of r_cell and q
 // (nc consecutive values per cell) is coalesced; same arithmetic order as
 // k_recover.
-constexpr int RECOVER_TILE = 128;
 template <int P>
 __global__ __launch_bounds__(RECOVER_TILE) void k_recover_n1(int nk, const double *__restrict__ Ar,
                                                             const double *__restrict__ Wr,
@@ -1440,7 +1472,10 @@ void launch_p1_tail(const P1Tail &T, int nb, hipStream_t s) {
 void launch_condense(int p, int nk, int ne, int nb, const double *Zr, const double *rc, double *loc,
                      const int *facet_cell, const int *facet_loc, double *rhat, hipStream_t s) {
 #define CC(P)                                                                                                     \
-    hipLaunchKernelGGL(k_condense_cell<P>, GRID8(nk * nb, 256), 0, s, nk, nb, Zr, rc, loc);                        \
+    if (nb == 1)                                                                                                  \
+        hipLaunchKernelGGL(k_condense_cell_n1<P>, GRID8(nk, RECOVER_TILE), 0, s, nk, Zr, rc, loc);                \
+    else                                                                                                          \
+        hipLaunchKernelGGL(k_condense_cell<P>, GRID8(nk * nb, 256), 0, s, nk, nb, Zr, rc, loc);                    \
     hipLaunchKernelGGL(k_condense_gather<P>, GRID8(ne * (P + 1) * nb, 256), 0, s, ne, nk, nb, facet_cell,         \
                        facet_loc, loc, rhat)
     switch (p) { case 1: CC(1); break; case 2: CC(2); break; case 3: CC(3); break; }
