@@ -1200,7 +1200,6 @@ extern "C" int hdg_mlp_set_weights(hdg_ctx *c, const float *W1, const float *W2)
         check_launch();
         HDG_HIP_CHECK(hipDeviceSynchronize());
         c->mlp_step = 0;
-        c->mlp_ready = true;
     });
 }
 
@@ -1290,7 +1289,6 @@ extern "C" int hdg_mlp_train(hdg_ctx *c, int32_t nb, const double *e0, int32_t c
             }
         }
         c->use_mlp_now = keep;
-        c->mlp_ready = true;
         HDG_HIP_CHECK(hipStreamSynchronize(s));
         if (loss_hist) {
             std::vector<double> l(idx);

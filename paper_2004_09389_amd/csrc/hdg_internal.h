@@ -174,7 +174,6 @@ struct hdg_ctx {
     int mlp_n1 = 0, mlp_n2 = 0, mlp_step = 0;
     int mlp_spl = 1;                      // samples per lane in the learned smoothing kernel
     int rhs_block = 4;                    // facet-row kernels: RHS per thread when nrhs allows (1 or 4)
-    bool mlp_ready = false;
     float *mlp_w = nullptr, *mlp_m1 = nullptr, *mlp_m2 = nullptr, *mlp_g = nullptr;
     short *mlp_wb = nullptr;
     float *mlp_pdW1 = nullptr, *mlp_pdW2 = nullptr, *mlp_ploss = nullptr;

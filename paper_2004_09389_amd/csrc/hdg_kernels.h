@@ -131,13 +131,10 @@ void launch_gs_norm_givens(int64_t len, int nb, int nd, const double *h, const d
 void launch_pcg_update_norm(int64_t len, int nb, const double *num, const double *den, const double *p,
                             const double *w, double *x, double *res, double *partial, double *rr_host,
                             hipStream_t s);
-void launch_axpby(int64_t n, int nb, const double *a, double as, const double *x, const double *b, double bs,
-                  double *y, hipStream_t s);
 void launch_pcg_dir(int64_t n, int nb, const double *num, const double *den, const double *z, double *p,
                     hipStream_t s);
 void launch_lincomb(int64_t n, int nb, int nd, const double *y, const double *Z, int64_t zstride, double *x,
                     hipStream_t s);
-void launch_scale_inv(int64_t n, int nb, const double *sc, const double *x, double *y, hipStream_t s);
 void launch_copy(int64_t n, const double *src, double *dst, hipStream_t s);
 void launch_gmres_start(int nb, int restart, const double *beta2, double *gm, double *beta, hipStream_t s);
 void launch_gmres_solve(int nb, int k, int restart, const double *gm, double *y, hipStream_t s);

@@ -1087,15 +1087,6 @@ __global__ __launch_bounds__(256) void k_pcg_update_norm(int64_t len, int nb, co
     if (tid < nb) partial[(size_t)blockIdx.x * nb + tid] = sh[0][tid];
 }
 
-// y[i][r] = a[r] * x[i][r] + b[r] * y[i][r] with per-RHS device scalars (null = 0 / 1 given)
-__global__ void k_axpby(int64_t n, int nb, const double *__restrict__ a, double as, const double *__restrict__ x,
-                        const double *__restrict__ b, double bs, double *__restrict__ y) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n * nb) return;
-    const int r = (int)(t % nb);
-    const double av = a ? as * a[r] : as, bv = b ? bs * b[r] : bs;
-    y[t] = av * x[t] + (bv == 0.0 ? 0.0 : bv * y[t]);
-}
 
 // p = z + beta p, beta[r] = num[r] / den[r]
 __global__ void k_pcg_dir(int64_t n, int nb, const double *__restrict__ num, const double *__restrict__ den,
@@ -1119,14 +1110,6 @@ __global__ void k_lincomb(int64_t n, int nb, int nd, const double *__restrict__ 
     x[t] = s;
 }
 
-// y = x / s[r]  (s > 0), writes 0 for s == 0
-__global__ void k_scale_inv(int64_t n, int nb, const double *__restrict__ s, const double *__restrict__ x,
-                            double *__restrict__ y) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n * nb) return;
-    const double v = s[t % nb];
-    y[t] = v != 0.0 ? x[t] / v : 0.0;
-}
 
 __global__ void k_copy(int64_t n, const double *__restrict__ src, double *__restrict__ dst) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1525,10 +1508,6 @@ void launch_pcg_update_norm(int64_t len, int nb, const double *num, const double
     hipLaunchKernelGGL(k_sum_final, dim3(nb), dim3(256), 0, s, g, nb, partial, (double *)nullptr, rr_host);
 }
 
-void launch_axpby(int64_t n, int nb, const double *a, double as, const double *x, const double *b, double bs,
-                  double *y, hipStream_t s) {
-    hipLaunchKernelGGL(k_axpby, GRID(n * nb, 256), 0, s, n, nb, a, as, x, b, bs, y);
-}
 void launch_pcg_dir(int64_t n, int nb, const double *num, const double *den, const double *z, double *p,
                     hipStream_t s) {
     hipLaunchKernelGGL(k_pcg_dir, GRID(n * nb, 256), 0, s, n, nb, num, den, z, p);
@@ -1536,9 +1515,6 @@ void launch_pcg_dir(int64_t n, int nb, const double *num, const double *den, con
 void launch_lincomb(int64_t n, int nb, int nd, const double *y, const double *Z, int64_t zstride, double *x,
                     hipStream_t s) {
     hipLaunchKernelGGL(k_lincomb, GRID(n * nb, 256), 0, s, n, nb, nd, y, Z, zstride, x);
-}
-void launch_scale_inv(int64_t n, int nb, const double *sc, const double *x, double *y, hipStream_t s) {
-    hipLaunchKernelGGL(k_scale_inv, GRID(n * nb, 256), 0, s, n, nb, sc, x, y);
 }
 void launch_copy(int64_t n, const double *src, double *dst, hipStream_t s) {
     hipLaunchKernelGGL(k_copy, GRID(n, 256), 0, s, n, src, dst);
