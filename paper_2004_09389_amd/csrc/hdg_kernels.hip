@@ -3,6 +3,7 @@
 //   per-cell matrices  component-major [row][col][n_cell]  (lanes = cells, coalesced)
 //   facet block rows   component-major [slot][a][b][n_facet]
 //   vectors            [item][dof][nrhs]  (RHS innermost)
+#include <algorithm>
 #include <type_traits>
 
 #include "hdg_kernels.h"
@@ -907,6 +908,98 @@ __global__ __launch_bounds__(RECOVER_TILE) void k_recover_n1(int nk, const doubl
     for (int i = tid; i < cnt * nc; i += RECOVER_TILE) q[(size_t)K0 * nc + i] = buf[i];
 }
 
+// Batched cell kernels (nrhs >= 2): a block holds CB cells x nrhs threads
+// (right-hand side fastest) and streams the cells' matrix rows through LDS in
+// chunks of CELL_ROWS rows, loaded once per block with coalesced reads; every
+// thread keeps its right-hand side's inputs in registers.  Same arithmetic
+// order as the one-thread-per-(cell, rhs) kernels.
+constexpr int CELL_ROWS = 6;
+inline int cell_block_cells(int nb) { return std::max(1, std::min(32, 256 / nb)); }
+
+template <int P>
+__global__ __launch_bounds__(256) void k_recover_b(int nk, int nb, int cb, const double *__restrict__ Ar,
+                                                   const double *__restrict__ Wr, const int *__restrict__ cell_facet,
+                                                   const int8_t *__restrict__ cell_rev, const double *__restrict__ rc,
+                                                   const double *__restrict__ lam, double *__restrict__ q) {
+    constexpr int n = (P + 1) * (P + 2) / 2, m = P + 1, nc = 3 * n, nt = 3 * m, RL = nc + nt;
+    extern __shared__ double sm[];   // [row][entry][cell], CELL_ROWS * RL * cb doubles
+    const int K0 = xcd_block() * cb, tid = threadIdx.x;
+    const int cl = tid / nb, r = tid - cl * nb, K = K0 + cl;
+    const bool live = cl < cb && K < nk;
+    const size_t NK = (size_t)nk;
+    double f[nc], l[nt];
+    if (live) {
+#pragma unroll
+        for (int j = 0; j < nc; ++j) f[j] = rc[((size_t)K * nc + j) * nb + r];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const int e = cell_facet[i * NK + K];
+            const int rev = cell_rev[i * NK + K];
+#pragma unroll
+            for (int k = 0; k < m; ++k) l[i * m + k] = lam[((size_t)e * m + (rev ? P - k : k)) * nb + r];
+        }
+    }
+    for (int a0 = 0; a0 < nc; a0 += CELL_ROWS) {
+        const int rows = min(CELL_ROWS, nc - a0);
+        __syncthreads();
+        for (int i = tid; i < rows * RL * cb; i += blockDim.x) {
+            const int c = i % cb, jr = i / cb, row = jr / RL, j = jr - row * RL, Kc = K0 + c;
+            double v = 0.0;
+            if (Kc < nk) {
+                const int a = a0 + row;
+                v = j < nc ? ldm(Ar + (size_t)(a * nc + j) * NK + Kc) : ldm(Wr + (size_t)(a * nt + j - nc) * NK + Kc);
+            }
+            sm[(row * RL + j) * cb + c] = v;
+        }
+        __syncthreads();
+        if (live) {
+            for (int row = 0; row < rows; ++row) {
+                double s = 0.0;
+#pragma unroll
+                for (int j = 0; j < nc; ++j) s += sm[(row * RL + j) * cb + cl] * f[j];
+#pragma unroll
+                for (int j = 0; j < nt; ++j) s -= sm[(row * RL + nc + j) * cb + cl] * l[j];
+                q[((size_t)K * nc + a0 + row) * nb + r] = s;
+            }
+        }
+    }
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void k_condense_cell_b(int nk, int nb, int cb, const double *__restrict__ Zr,
+                                                         const double *__restrict__ rc, double *__restrict__ loc) {
+    constexpr int n = (P + 1) * (P + 2) / 2, m = P + 1, nc = 3 * n, nt = 3 * m, ZW = cell_zw(P);
+    extern __shared__ double sm[];   // [row][entry][cell], CELL_ROWS * ZW * cb doubles
+    const int K0 = xcd_block() * cb, tid = threadIdx.x;
+    const int cl = tid / nb, r = tid - cl * nb, K = K0 + cl;
+    const bool live = cl < cb && K < nk;
+    const size_t NK = (size_t)nk;
+    double f[ZW];
+#pragma unroll
+    for (int j = 0; j < ZW; ++j) f[j] = (live && j < nc) ? rc[((size_t)K * nc + j) * nb + r] : 0.0;
+    for (int a0 = 0; a0 < nt; a0 += CELL_ROWS) {
+        const int rows = min(CELL_ROWS, nt - a0);
+        __syncthreads();
+        for (int i = tid; i < rows * ZW * cb; i += blockDim.x) {
+            const int c = i % cb, jr = i / cb, row = jr / ZW, j = jr - row * ZW, Kc = K0 + c;
+            const int idx = (a0 + row) * ZW + j;   // pair layout [idx / 2][NK][2]
+            sm[(row * ZW + j) * cb + c] = Kc < nk ? Zr[((size_t)(idx / 2) * NK + Kc) * 2 + idx % 2] : 0.0;
+        }
+        __syncthreads();
+        if (live) {
+            for (int row = 0; row < rows; ++row) {
+                double s = 0.0;
+#pragma unroll
+                for (int jp = 0; jp < ZW / 2; ++jp) {
+                    s += sm[(row * ZW + 2 * jp) * cb + cl] * f[2 * jp];
+                    if (2 * jp + 1 < nc) s += sm[(row * ZW + 2 * jp + 1) * cb + cl] * f[2 * jp + 1];
+                }
+                loc[((size_t)(a0 + row) * NK + K) * nb + r] = s;
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------------ Krylov vector kernels
 //
 // Vectors are [len][nb]; per-RHS reductions run in two deterministic passes
@@ -1458,7 +1551,9 @@ void launch_condense(int p, int nk, int ne, int nb, const double *Zr, const doub
     if (nb == 1)                                                                                                  \
         hipLaunchKernelGGL(k_condense_cell_n1<P>, GRID8(nk, RECOVER_TILE), 0, s, nk, Zr, rc, loc);                \
     else                                                                                                          \
-        hipLaunchKernelGGL(k_condense_cell<P>, GRID8(nk * nb, 256), 0, s, nk, nb, Zr, rc, loc);                    \
+        hipLaunchKernelGGL(k_condense_cell_b<P>, GRID8((int64_t)nk * nb, cell_block_cells(nb) * nb),               \
+                           sizeof(double) * CELL_ROWS * cell_zw(P) * cell_block_cells(nb), s, nk, nb,              \
+                           cell_block_cells(nb), Zr, rc, loc);                                                    \
     hipLaunchKernelGGL(k_condense_gather<P>, GRID8(ne * (P + 1) * nb, 256), 0, s, ne, nk, nb, facet_cell,         \
                        facet_loc, loc, rhat)
     switch (p) { case 1: CC(1); break; case 2: CC(2); break; case 3: CC(3); break; }
@@ -1472,7 +1567,9 @@ void launch_recover(int p, int nk, int nb, const double *Ar, const double *Wr, c
         hipLaunchKernelGGL(k_recover_n1<P>, GRID8(nk, RECOVER_TILE), 0, s, nk, Ar, Wr, cell_facet, cell_rev, rc, \
                            lam, q);                                                                            \
     else                                                                                                       \
-        hipLaunchKernelGGL(k_recover<P>, GRID8(nk * nb, 256), 0, s, nk, nb, Ar, Wr, cell_facet, cell_rev, rc, lam, q)
+        hipLaunchKernelGGL(k_recover_b<P>, GRID8((int64_t)nk * nb, cell_block_cells(nb) * nb),                 \
+                           sizeof(double) * CELL_ROWS * (3 * (P + 1) * (P + 2) / 2 + 3 * (P + 1)) * cell_block_cells(nb), \
+                           s, nk, nb, cell_block_cells(nb), Ar, Wr, cell_facet, cell_rev, rc, lam, q)
     switch (p) { case 1: RC(1); break; case 2: RC(2); break; case 3: RC(3); break; }
 #undef RC
 }
