@@ -107,3 +107,23 @@ def test_two_cell_mesh_every_degree(p):
     assert rel(host(lam)[..., 0].ravel(), lam_ref) < 1e-10
     for fld in range(3):
         assert rel(host(q)[:, fld, :, 0], q_ref[:, fld]) < 1e-10
+
+
+def test_not_converged_and_breakdown_are_reported():
+    """maxit reached: HDG_ENOTCONV with the info filled; a non-finite
+    right-hand side: HDG_EBREAKDOWN, the context still usable afterwards."""
+    import torch
+    from paper_2004_09389_amd.hdg import HDG_EBREAKDOWN, HDG_ENOTCONV, HdgError
+    hier = hi.torus_hierarchy(6, 3)
+    s = make(maxit=2, rtol=1e-12, krylov=2)
+    r = to_dev(hi.iid_rhs(hier.fine, 2, 3))
+    rhat = s.condense(r)
+    lam, info = s.solve(rhat, allow_notconv=True)
+    assert info[0].status == HDG_ENOTCONV and info[0].iters == 2 and info[0].rel_res > 1e-12
+    bad = rhat.clone()
+    bad[0, 0, 0] = float("nan")
+    with pytest.raises(HdgError) as e:
+        s.solve(bad)
+    assert e.value.code == HDG_EBREAKDOWN
+    lam, info = s.solve(rhat, allow_notconv=True)
+    assert info[0].status == HDG_ENOTCONV and np.all(np.isfinite(host(lam)))
