@@ -53,7 +53,7 @@ def features(u, ids, rev):
     ne, m = u.shape
     f = u[ids]                                  # (ne, 5, m)
     f = np.where(rev[:, :, None], f[:, :, ::-1], f)
-    return f.reshape(ne, 5 * m)
+    return f.reshape(ne, ids.shape[1] * m)
 
 
 def forward(W1, W2, feats):
