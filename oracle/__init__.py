@@ -15,7 +15,11 @@ What it computes (paper section / equation):
   schur_system, reconstruct_solution);
 * the non-nested two-level V-cycle (Alg. twolevel_vcycle) with the P1 coarse
   space, injection prolongation and coarse form (Eq. coarse_problem_upwind);
-* the learned-smoother MLP forward / backward in fp64.
+* the learned-smoother MLP forward / backward in fp64;
+* the Lax-Friedrichs flux (Eq. bilinear_HDG_lax): standard DG and HDG with
+  a vector trace, the lowest-order Raviart-Thomas coarse space with the
+  L2-projection prolongation and the grad-div coarse form
+  (Eq. coarse_problem_LF), and its geometric multigrid (module lf).
 
 Functions without an independent pin say "parity unpinned" in their
 docstring.
