@@ -13,12 +13,19 @@
  *   - Krylov on the trace system preconditioned by the non-nested two-level
  *     V-cycle (Alg. twolevel_vcycle) with the P1 coarse space, injection
  *     prolongation and the coarse form of Eq. coarse_problem_upwind, the
- *     coarse problem solved by one P1 geometric-multigrid V-cycle.
+ *     coarse problem solved by one P1 geometric-multigrid V-cycle;
+ *   - alternatively (prm.flux = HDG_FLUX_LF, torus only) the Lax-Friedrichs
+ *     flux with a vector trace (Eq. bilinear_HDG_lax), the lowest-order
+ *     Raviart-Thomas coarse space, the L2-projection prolongation of the
+ *     cells' average and the grad-div coarse form of Eq. coarse_problem_LF,
+ *     solved by one geometric-multigrid V-cycle over the nested RT0 spaces
+ *     with vertex-patch smoothing.
  *
  * Equations solved (in the caller's variables), with c = sqrt(g H):
  *     u + dt (f k x u + g grad h) = r_u,     h + dt H div u = r_h.
  * Internally phi = h sqrt(g/H) and kappa = c dt (symmetric form, linearised
- * SWE with flat bathymetry); the trace unknown lam lives in phi units.
+ * SWE with flat bathymetry); the upwind trace unknown lam lives in phi
+ * units, the Lax-Friedrichs trace is the velocity uhat.
  *
  * Discretisation conventions (shared with any independent checker):
  *   - DG basis: Lagrange at the equispaced lattice (i/p, j/p), i+j <= p, of
@@ -30,12 +37,16 @@
  *     fixes its direction; trace node k is at parameter k/p along it;
  *   - velocity components: x, y on the torus; on the sphere the flat cell's
  *     frame e1 = (b-a)/|b-a|, e2 = k x e1, k the unit cell normal;
+ *   - Lax-Friedrichs trace: per facet the x components at the p+1 nodes,
+ *     then the y components (facet_dofs = 2(p+1));
+ *   - RT0 coarse unknown of a facet: the flux of the field through it along
+ *     the owner cell's outward normal;
  *   - Coriolis f = f0 (torus) or f0 + 2 Omega z/|x| (sphere), integrated with
  *     the collapsed Gauss-Legendre rule of (p+3)^2 points.
  *
  * Array layouts (all row-major, RHS index innermost):
  *   cell arrays   [n_cell][3][n_loc][nrhs]   fields (h, u1, u2), n_loc = (p+1)(p+2)/2
- *   trace arrays  [n_facet][p+1][nrhs]
+ *   trace arrays  [n_facet][facet_dofs][nrhs]   facet_dofs = p+1 (upwind) or 2(p+1) (LF)
  * Device pointers are HIP device memory owned by the caller; the library
  * never frees them.  Trace arrays must be 16-byte aligned (every hipMalloc
  * and torch allocation is; HDG_EINVAL otherwise).  Host pointers are read
@@ -67,6 +78,9 @@ extern "C" {
 #define HDG_TORUS  0
 #define HDG_SPHERE 1
 
+#define HDG_FLUX_UPWIND 0   /* scalar trace, P1 coarse space (Eq. bilinear_HDG_upwind) */
+#define HDG_FLUX_LF     1   /* vector trace, RT0 coarse space (Eq. bilinear_HDG_lax); torus only */
+
 #define HDG_FP64     0      /* everything in FP64 */
 #define HDG_MIXED    1      /* FP64 Krylov with the FP64 operator; the V-cycle uses the FP32
                                operator rows, BF16 smoother rows and FP32 block inverses with FP32
@@ -81,7 +95,7 @@ extern "C" {
 #define HDG_KRYLOV_FGMRES 2
 
 #define HDG_SMOOTH_BJACOBI   0 /* damped facet block-Jacobi sweeps */
-#define HDG_SMOOTH_MLP       1 /* learned smoother (see below) */
+#define HDG_SMOOTH_MLP       1 /* learned smoother (see below; upwind flux only) */
 #define HDG_SMOOTH_CHEBYSHEV 2 /* Chebyshev iteration of degree nu_pre / nu_post preconditioned by facet
                                   block-Jacobi on [0.1, 1.1] lambda_max(D^-1 S), lambda_max from 20
                                   power steps at setup (the smoother of the paper's solver settings) */
@@ -105,7 +119,8 @@ typedef struct {
     int32_t degree;             /* p in 1..3: DG degree, also the trace degree */
     double dt, g, H;            /* time step, gravity, mean depth (g, H > 0, dt > 0) */
     double f0, omega;           /* Coriolis: f0 + 2 omega z/|x| on the sphere, f0 on the torus */
-    double tau;                 /* HDG stabilisation (> 0); 1 is the paper's upwind flux */
+    double tau;                 /* HDG stabilisation (> 0); 1 is the paper's flux (either kind) */
+    int32_t flux;               /* HDG_FLUX_UPWIND (0) or HDG_FLUX_LF */
 } hdg_params;
 
 typedef struct {
@@ -129,10 +144,13 @@ typedef struct {
                                    its second iteration on (default 0.5) */
     int32_t p1_tail_max;        /* P1 levels with at most this many vertices run inside one
                                    single-workgroup kernel (default 4096, max 4096, 0 = never) */
-    int32_t p1_galerkin;        /* 0: the rediscretised coarse form (1/kappa)(M_1 + kappa^2 K_1) on
+    int32_t p1_galerkin;        /* (upwind flux only) 0: the rediscretised coarse form (1/kappa)(M_1 + kappa^2 K_1) on
                                    every P1 level (default); 1: the Galerkin form S_c = pi^T S pi on
                                    the finest P1 level (the footnoted alternative of the non-nested
                                    multigrid section) and P^T A P below it */
+    int32_t rt_nu;              /* LF flux: vertex-patch smoothing steps per RT0 level, pre and post
+                                   (default 1) */
+    double  rt_omega;           /* LF flux: damping of the additive vertex-patch smoother (default 0.5) */
 } hdg_options;
 
 typedef struct {
@@ -145,6 +163,8 @@ typedef struct {
 
 typedef struct {
     int32_t n_cell, n_facet, n_vert, degree, n_loc, n_levels;
+    int32_t facet_dofs;         /* trace unknowns per facet: p+1 (upwind) or 2(p+1) (LF) */
+    int32_t flux;               /* HDG_FLUX_UPWIND or HDG_FLUX_LF */
     int64_t device_bytes;       /* device memory held by the context */
     double  kappa;              /* c dt */
     double  lambda_max;         /* eigenvalue estimate of D^-1 S (Chebyshev smoother), else 0 */
@@ -156,9 +176,12 @@ typedef struct {
 int hdg_default_options(hdg_options *opt);
 
 /* hdg_setup: build a context on the current HIP device.
- *   levels[0..n_levels-1]: P1 multigrid hierarchy, coarse to fine; levels[n_levels-1]
- *     is the HDG mesh itself (n_levels >= 1).  Each level must be the uniform
- *     refinement of the previous one.
+ *   levels[0..n_levels-1]: multigrid hierarchy (P1, or RT0 for the LF flux), coarse to
+ *     fine; levels[n_levels-1] is the HDG mesh itself (n_levels >= 1).  Each level must
+ *     be the uniform refinement of the previous one.  LF flux: the RT0 hierarchy uses
+ *     the finest level and every coarser level whose cells are determined by their
+ *     three vertex ids (at least 16 vertices); the coarsest of them (at most 8192
+ *     facets) is solved with a dense inverse.
  *   parents[l] for l = 1..n_levels-1: (host) [levels[l].n_vert][2] vertex ids in
  *     level l-1 between which vertex v of level l lies (equal ids for an
  *     inherited vertex); parents[0] is ignored (may be NULL).
@@ -181,23 +204,29 @@ int hdg_get_topology(const hdg_ctx *ctx, int32_t *facet_cell, int32_t *facet_loc
 
 /* Step 1 (Eq. schur_system right-hand side): rhat = sum_K R_K^T C_K A_K^-1 (r, v)_K.
  * r_cell: (device) [n_cell][3][n_loc][nrhs] DG coefficients of (r_h, r_u);
- * rhat:   (device) [n_facet][p+1][nrhs].  1 <= nrhs <= max_rhs. */
+ * rhat:   (device) [n_facet][facet_dofs][nrhs].  1 <= nrhs <= max_rhs. */
 int hdg_condense(hdg_ctx *ctx, int32_t nrhs, const double *r_cell, double *rhat, void *stream);
 
 /* y = S x, matrix-free over facet block rows (Eq. schur_system operator).
  * precision HDG_FP64 uses the FP64 rows, HDG_MIXED the FP32 rows with FP32 accumulation.
- * x, y: (device) [n_facet][p+1][nrhs], must not alias. */
+ * x, y: (device) [n_facet][facet_dofs][nrhs], must not alias. */
 int hdg_trace_apply(hdg_ctx *ctx, int32_t nrhs, int32_t precision, const double *x, double *y, void *stream);
 
 /* z = V(r): one non-nested V-cycle (Alg. twolevel_vcycle) from a zero initial guess:
  * nu_pre block-Jacobi sweeps, residual, restriction pi^T, one P1 GMG V-cycle on
  * S_c = (1/kappa)(M_1 + kappa^2 K_1) (Eq. coarse_problem_upwind), prolongation pi,
  * nu_post sweeps.  precision selects the storage of the trace-level matrices.
- * r, z: (device) [n_facet][p+1][nrhs], must not alias. */
+ * LF flux: the coarse problem is S_c = (1/kappa)(M_RT + kappa^2 D_RT) on RT0
+ * (Eq. coarse_problem_LF), pi^T / pi the transpose / the nodal average of the two
+ * cells' RT0 fields on each facet, solved by one RT0 GMG V-cycle: rt_nu additive
+ * vertex-patch steps (damping rt_omega) before and after the correction from the
+ * next coarser level (exact flux transfer between the nested levels), dense
+ * inverse on the coarsest level.
+ * r, z: (device) [n_facet][facet_dofs][nrhs], must not alias. */
 int hdg_mg_vcycle(hdg_ctx *ctx, int32_t nrhs, int32_t precision, const double *r, double *z, void *stream);
 
 /* Step 2: solve S lam = rhat to ||rhat - S lam|| <= rtol ||rhat|| per RHS.
- * lam is the initial guess on entry (device, [n_facet][p+1][nrhs]) and the
+ * lam is the initial guess on entry (device, [n_facet][facet_dofs][nrhs]) and the
  * solution on exit.  info: (host) [nrhs], may be NULL.  Synchronises the stream. */
 int hdg_solve(hdg_ctx *ctx, int32_t nrhs, const double *rhat, double *lam,
               hdg_solve_info *info, void *stream);

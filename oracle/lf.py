@@ -445,7 +445,7 @@ class LfTraceMultigrid:
     coarse space, pi = L2 projection of {{u_c}}."""
 
     def __init__(self, hdg: HdgLfOracle, hier, omega=0.7, nu_pre=2, nu_post=2, rt_omega=0.5, rt_nu=1,
-                 exact_coarse=False):
+                 exact_coarse=False, smoother="jacobi"):
         if hier.fine.n_vert != hdg.mesh.n_vert or hier.fine.n_cell != hdg.mesh.n_cell:
             raise ValueError("hierarchy's finest mesh must be the HDG mesh")
         self.S = hdg.S
@@ -466,11 +466,22 @@ class LfTraceMultigrid:
         if exact_coarse:
             self._lu = spla.splu(self.Sc.tocsc())
         self.omega, self.nu_pre, self.nu_post = omega, nu_pre, nu_post
+        if smoother not in ("jacobi", "chebyshev"):
+            raise ValueError("smoother must be 'jacobi' or 'chebyshev'")
+        self.smoother = smoother
+        if smoother == "chebyshev":
+            # the same Chebyshev smoother as the upwind case (interval [0.1, 1.1] lambda_max)
+            from .p1 import power_estimate
+            self.lambda_max = power_estimate(self.S, self.block_jacobi)
+            self.cheb_interval = (0.1 * self.lambda_max, 1.1 * self.lambda_max)
 
     def block_jacobi(self, r):
         return np.einsum("eab,eb->ea", self.Dinv, r.reshape(self.ne, self.mt)).ravel()
 
     def smooth(self, b, x, nu):
+        if self.smoother == "chebyshev":
+            from .p1 import chebyshev
+            return chebyshev(self.S, self.block_jacobi, b, x, nu, *self.cheb_interval)
         for _ in range(nu):
             x = x + self.omega * self.block_jacobi(b - self.S @ x)
         return x

@@ -13,7 +13,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libhdg.so")
-SOURCES = ["csrc/hdg_host.cpp", "csrc/hdg_kernels.hip", "csrc/hdg_mlp.hip", "csrc/hdg_api.hip"]
+SOURCES = ["csrc/hdg_host.cpp", "csrc/hdg_rt0_host.cpp", "csrc/hdg_kernels.hip", "csrc/hdg_mlp.hip",
+           "csrc/hdg_rt0.hip", "csrc/hdg_api.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -9,6 +9,7 @@
 #include <utility>
 
 #include "hdg_kernels.h"
+#include "hdg_rt0.h"
 
 using hdg::Error;
 
@@ -164,9 +165,9 @@ void op_apply(hdg_ctx *c, int nb, int prec, const double *x, const double *b, do
     Timed t(c, kind, prec, s, nb);
     for (int rep = 0; rep < t.repeats(); ++rep) {
         if (prec == HDG_MIXED)
-            hdg::launch_trace_apply<float>(c->p, c->n_facet, nb, c->S32, c->nbr, x, b, y, s, c->rhs_block);
+            hdg::launch_trace_apply<float>(c->m, c->n_facet, nb, c->S32, c->nbr, x, b, y, s, c->rhs_block);
         else
-            hdg::launch_trace_apply<double>(c->p, c->n_facet, nb, c->S64, c->nbr, x, b, y, s, c->rhs_block);
+            hdg::launch_trace_apply<double>(c->m, c->n_facet, nb, c->S64, c->nbr, x, b, y, s, c->rhs_block);
     }
     check_launch();
 }
@@ -179,10 +180,10 @@ void op_sweep(hdg_ctx *c, int nb, int prec, const double *x, const double *z0, c
     Timed t(c, HDG_KERNEL_SWEEP, prec, s, nb);
     for (int rep = 0; rep < t.repeats(); ++rep) {
         if (prec == HDG_MIXED)
-            hdg::launch_sweep<__hip_bfloat16>(c->p, c->n_facet, nb, c->T16, c->nbr, x, z0, qc, c->facet_vert, cf, y,
+            hdg::launch_sweep<__hip_bfloat16>(c->m, c->n_facet, nb, c->T16, c->nbr, x, z0, qc, c->facet_vert, cf, y,
                                               s, c->rhs_block);
         else
-            hdg::launch_sweep<double>(c->p, c->n_facet, nb, c->T64, c->nbr, x, z0, qc, c->facet_vert, cf, y, s,
+            hdg::launch_sweep<double>(c->m, c->n_facet, nb, c->T64, c->nbr, x, z0, qc, c->facet_vert, cf, y, s,
                                       c->rhs_block);
     }
     check_launch();
@@ -226,6 +227,42 @@ double *p1_vcycle(hdg_ctx *c, int l, int nb, hipStream_t s) {
     return x;
 }
 
+// One RT0 geometric-multigrid V-cycle on level l (input rt[l].b, Lax-Friedrichs
+// coarse problem); returns the buffer holding the result.  rt_nu additive
+// vertex-patch steps from zero, residual, restriction P^T, recursion,
+// prolongation x += P x_c, rt_nu patch steps; dense inverse on level 0.
+double *rt_vcycle(hdg_ctx *c, int l, int nb, hipStream_t s) {
+    hdg::Rt0LevelDev &L = c->rt[l];
+    if (l == 0) {
+        hdg::launch_dense_mv(L.ne, nb, c->rt_coarse_inv, L.b, L.x, s);
+        return L.x;
+    }
+    const double w = c->opt.rt_omega;
+    double *x = L.x;
+    for (int k = 0; k < c->opt.rt_nu; ++k) {
+        hdg::launch_rt_patch(L, nb, L.b, k == 0 ? nullptr : x, c->rt_corr, s);
+        hdg::launch_rt_update(L, nb, w, c->rt_corr, k == 0 ? nullptr : x, x, s);
+    }
+    hdg::launch_rt_resid(L, nb, L.b, x, L.y, s);
+    hdg::Rt0LevelDev &C = c->rt[l - 1];
+    hdg::launch_rt_restrict(L, C.ne, nb, L.y, C.b, s);
+    const double *xc = rt_vcycle(c, l - 1, nb, s);
+    hdg::launch_rt_prolong(L, nb, xc, x, s);
+    for (int k = 0; k < c->opt.rt_nu; ++k) {
+        hdg::launch_rt_patch(L, nb, L.b, x, c->rt_corr, s);
+        hdg::launch_rt_update(L, nb, w, c->rt_corr, x, x, s);
+    }
+    return x;
+}
+
+// Lax-Friedrichs coarse correction: out = cur + pi V_RT(pi^T res)
+void lf_coarse(hdg_ctx *c, int nb, const double *res, const double *cur, double *out, hipStream_t s) {
+    const int L = (int)c->rt.size() - 1;
+    hdg::launch_lf_restrict(c->m, c->n_facet, nb, c->lf_pw, c->lf_rrow, c->lf_rcol, res, c->rt[L].b, s);
+    const double *xr = rt_vcycle(c, L, nb, s);
+    hdg::launch_lf_prolong(c->m, c->n_facet, nb, c->lf_pw, c->nbr, xr, cur, out, s);
+}
+
 // z = V(r): Alg. twolevel_vcycle from a zero initial guess.  With scale != null
 // the input is r / scale[rhs] and r is normalised in place on the way (the
 // FGMRES basis vector is scaled by its first reader).
@@ -233,9 +270,9 @@ void vcycle_bj(hdg_ctx *c, int nb, int prec, const double *r, double *z, hipStre
                const double *scale = nullptr) {
     double *rs = scale ? const_cast<double *>(r) : nullptr;
     if (prec == HDG_MIXED)
-        hdg::launch_jacobi0<float>(c->p, c->n_facet, nb, c->Dw32, r, scale, rs, c->vz0, s);
+        hdg::launch_jacobi0<float>(c->m, c->n_facet, nb, c->Dw32, r, scale, rs, c->vz0, s);
     else
-        hdg::launch_jacobi0<double>(c->p, c->n_facet, nb, c->Dw64, r, scale, rs, c->vz0, s);
+        hdg::launch_jacobi0<double>(c->m, c->n_facet, nb, c->Dw64, r, scale, rs, c->vz0, s);
     double *bufs[2] = {c->vx, c->vx2};
     int bi = 0;
     double *cur = c->vz0;  // first sweep from zero gives omega D^-1 r exactly
@@ -246,9 +283,16 @@ void vcycle_bj(hdg_ctx *c, int nb, int prec, const double *r, double *z, hipStre
         cur = out;
     }
     op_apply(c, nb, prec, cur, r, c->vres, s, HDG_KERNEL_RESIDUAL);
-    const int L = (int)c->lev.size() - 1;
-    hdg::launch_restrict_trace(c->p, c->n_vert, nb, c->vf_row, c->vf_col, c->vres, c->lev[L].b, s);
-    const double *xl = p1_vcycle(c, L, nb, s);
+    const double *xl = nullptr;   // P1 correction, prolonged inside the first post-sweep (upwind)
+    if (c->flux == HDG_FLUX_LF) {
+        double *out = cur == c->vx ? c->vx2 : c->vx;
+        lf_coarse(c, nb, c->vres, cur, out, s);
+        cur = out;
+    } else {
+        const int L = (int)c->lev.size() - 1;
+        hdg::launch_restrict_trace(c->p, c->n_vert, nb, c->vf_row, c->vf_col, c->vres, c->lev[L].b, s);
+        xl = p1_vcycle(c, L, nb, s);
+    }
     for (int k = 0; k < c->opt.nu_post; ++k) {
         double *out;
         if (k == c->opt.nu_post - 1) {
@@ -270,9 +314,9 @@ void vcycle_bj(hdg_ctx *c, int nb, int prec, const double *r, double *z, hipStre
 void jacobi0(hdg_ctx *c, int nb, int prec, const double *r, const double *scale, double *rs, double *z0,
              hipStream_t s) {
     if (prec == HDG_MIXED)
-        hdg::launch_jacobi0<float>(c->p, c->n_facet, nb, c->Dw32, r, scale, rs, z0, s);
+        hdg::launch_jacobi0<float>(c->m, c->n_facet, nb, c->Dw32, r, scale, rs, z0, s);
     else
-        hdg::launch_jacobi0<double>(c->p, c->n_facet, nb, c->Dw64, r, scale, rs, z0, s);
+        hdg::launch_jacobi0<double>(c->m, c->n_facet, nb, c->Dw64, r, scale, rs, z0, s);
 }
 
 // The same V-cycle with the learned smoother: every smoothing step is the
@@ -356,11 +400,17 @@ void vcycle_cheb(hdg_ctx *c, int nb, int prec, const double *r, double *z, hipSt
         x = Ref{c->vx, 1.0, nullptr};
     }
     op_apply(c, nb, prec, x.p, r, c->vres, s, HDG_KERNEL_RESIDUAL);
-    const int L = (int)c->lev.size() - 1;
-    hdg::launch_restrict_trace(c->p, c->n_vert, nb, c->vf_row, c->vf_col, c->vres, c->lev[L].b, s);
-    const double *xl = p1_vcycle(c, L, nb, s);
-    // post-smoothing from x + pi x_P1 (the prolongation rides in the sweeps)
-    x.qc = xl;
+    if (c->flux == HDG_FLUX_LF) {
+        // post-smoothing from x + pi x_RT, formed in a work buffer
+        double *out = x.p == c->vx ? c->vx2 : c->vx;
+        lf_coarse(c, nb, c->vres, x.p, out, s);
+        x = Ref{out, 1.0, nullptr};
+    } else {
+        // post-smoothing from x + pi x_P1 (the prolongation rides in the sweeps)
+        const int L = (int)c->lev.size() - 1;
+        hdg::launch_restrict_trace(c->p, c->n_vert, nb, c->vf_row, c->vf_col, c->vres, c->lev[L].b, s);
+        x.qc = p1_vcycle(c, L, nb, s);
+    }
     xp = Ref{nullptr, 0.0, nullptr};
     rho = 1.0 / sigma;
     for (int k = 0; k < c->opt.nu_post; ++k) {
@@ -669,12 +719,22 @@ void setup_impl(const hdg_mesh *levels, int nlev, const int32_t *const *parents,
     HDG_REQUIRE(opt.krylov >= HDG_KRYLOV_AUTO && opt.krylov <= HDG_KRYLOV_FGMRES, "unknown krylov method");
     for (int l = 0; l < nlev; ++l) validate_mesh(levels[l]);
     const hdg_mesh &fine = levels[nlev - 1];
+    HDG_REQUIRE(prm->flux == HDG_FLUX_UPWIND || prm->flux == HDG_FLUX_LF, "flux must be HDG_FLUX_UPWIND or HDG_FLUX_LF");
+    const bool lf = prm->flux == HDG_FLUX_LF;
+    if (lf) {
+        HDG_REQUIRE(fine.geom == HDG_TORUS, "the Lax-Friedrichs flux is built on the torus only");
+        HDG_REQUIRE(opt.smoother != HDG_SMOOTH_MLP, "the learned smoother is built for the upwind flux only");
+        HDG_REQUIRE(opt.p1_galerkin == 0, "p1_galerkin applies to the upwind flux only");
+        HDG_REQUIRE(opt.rt_nu >= 1 && opt.rt_omega > 0, "rt_nu >= 1 and rt_omega > 0 required");
+    }
 
     HDG_HIP_CHECK(hipGetDevice(&c->device));
     c->prm = *prm;
     c->opt = opt;
     c->p = prm->degree;
-    c->m = c->p + 1;
+    c->flux = prm->flux;
+    c->nu = lf ? 2 : 1;
+    c->m = c->nu * (c->p + 1);
     c->n = (c->p + 1) * (c->p + 2) / 2;
     c->nc = 3 * c->n;
     c->nt = 3 * c->m;
@@ -707,7 +767,7 @@ void setup_impl(const hdg_mesh *levels, int nlev, const int32_t *const *parents,
     c->Ar = dev_alloc<double>(c, (size_t)c->nc * c->nc * nk);
     c->Wr = dev_alloc<double>(c, (size_t)c->nc * c->nt * nk);
     hdg::CellParams cp{c->kappa, c->tau, c->dt, prm->f0, prm->omega, c->hscale, fine.geom};
-    hdg::launch_cell_condense(c->p, nk, d_corners, d_ref, cp, Sloc, c->Zr, c->Ar, c->Wr, d_err, s);
+    hdg::launch_cell_condense(c->p, c->nu, nk, d_corners, d_ref, cp, Sloc, c->Zr, c->Ar, c->Wr, d_err, s);
     check_launch();
     HDG_HIP_CHECK(hipDeviceSynchronize());
     int herr = 0;
@@ -737,7 +797,7 @@ void setup_impl(const hdg_mesh *levels, int nlev, const int32_t *const *parents,
     c->S32 = dev_alloc<float>(c, (size_t)hdg::wide_padded(5 * m * m, 4) * ne);
     c->T16 = dev_alloc<__hip_bfloat16>(c, (size_t)hdg::wide_padded(4 * m * m, 8) * ne);
     c->Dw32 = dev_alloc<float>(c, (size_t)hdg::wide_padded(m * m, 4) * ne);
-    hdg::launch_facet_rows(c->p, ne, nk, Sloc, d_fcell, d_floc, c->cell_facet, c->cell_rev, opt.omega, c->S64,
+    hdg::launch_facet_rows(c->p, c->nu, ne, nk, Sloc, d_fcell, d_floc, c->cell_facet, c->cell_rev, opt.omega, c->S64,
                            c->T64, c->Dw64, c->S32, c->T16, c->Dw32, c->nbr, c->prev, d_err, s);
     check_launch();
     HDG_HIP_CHECK(hipDeviceSynchronize());
@@ -749,7 +809,7 @@ void setup_impl(const hdg_mesh *levels, int nlev, const int32_t *const *parents,
     dev_release(c, d_corners, corners.size() * sizeof(double));
 
     // ---- vertex -> facet-end CSR for the trace -> P1 restriction
-    {
+    if (!lf) {
         std::vector<int32_t> cnt(nv + 1, 0);
         for (int e = 0; e < ne; ++e) {
             cnt[c->topo.facet_vert[2 * e] + 1]++;
@@ -764,10 +824,69 @@ void setup_impl(const hdg_mesh *levels, int nlev, const int32_t *const *parents,
         c->vf_col = dev_upload(c, col);
     }
 
-    // ---- P1 hierarchy
     HDG_REQUIRE(levels[nlev - 1].n_vert == nv, "the finest hierarchy level must be the HDG mesh");
-    c->lev.resize(nlev);
     const int mr = opt.max_rhs;
+    if (lf) {
+        // ---- RT0 hierarchy: the finest level and every coarser one whose cells are fixed by their vertices
+        int first = nlev - 1;
+        while (first > 0 && levels[first - 1].n_vert >= 16 && hdg::cells_unique_by_vertices(levels[first - 1]))
+            --first;
+        const int nrt = nlev - first;
+        std::vector<hdg::Rt0Host> H(nrt);
+        for (int l = 0; l < nrt; ++l) H[l] = hdg::build_rt0_level(levels[first + l], c->kappa, l > 0);
+        for (int l = 1; l < nrt; ++l) {
+            HDG_REQUIRE(parents && parents[first + l], "parents[l] must be given for every level above the coarsest");
+            hdg::rt0_transfer(levels[first + l], H[l], levels[first + l - 1], H[l - 1], parents[first + l]);
+        }
+        HDG_REQUIRE(H[0].ne <= 8192, "coarsest RT0 level must have at most 8192 facets");
+        std::vector<double> dense = hdg::rt0_dense(H[0]);
+        if (!hdg::spd_inverse(dense, H[0].ne)) throw Error{HDG_EINVAL, "coarsest RT0 operator is singular"};
+        c->rt_coarse_inv = dev_upload(c, dense);
+        c->rt.resize(nrt);
+        int max_nv = 1;
+        for (int l = 0; l < nrt; ++l) {
+            const hdg::Rt0Host &h = H[l];
+            hdg::Rt0LevelDev &L = c->rt[l];
+            L.ne = h.ne;
+            L.nv = h.nv;
+            L.nbr = dev_upload(c, h.nbr);
+            L.val = dev_upload(c, h.val);
+            if (l > 0) {
+                L.pf = dev_upload(c, h.pf);
+                L.pinv = dev_upload(c, h.pinv);
+                L.fs = dev_upload(c, h.fs);
+                L.pc = dev_upload(c, h.pc);
+                L.pw = dev_upload(c, h.pw);
+                L.crow = dev_upload(c, h.crow);
+                L.ccol = dev_upload(c, h.ccol);
+                L.cw = dev_upload(c, h.cw);
+                max_nv = std::max(max_nv, h.nv);
+            }
+            L.b = dev_alloc<double>(c, (size_t)h.ne * mr);
+            L.x = dev_alloc<double>(c, (size_t)h.ne * mr);
+            L.y = dev_alloc<double>(c, (size_t)h.ne * mr);
+        }
+        c->rt_corr = dev_alloc<double>(c, (size_t)max_nv * hdg::RT_PV * mr);
+        // prolongation onto the trace and the CSR of its transpose (code 8 e + slot)
+        const hdg::Rt0Host &F = H[nrt - 1];
+        c->lf_pw = dev_upload(c, hdg::lf_prolongation_weights(fine, c->topo, c->p));
+        std::vector<std::vector<int32_t>> users(ne);
+        for (int e = 0; e < ne; ++e)
+            for (int slot = 0; slot < 5; ++slot) {
+                const int id = slot == 0 ? e : F.nbr[(size_t)(slot - 1) * ne + e];
+                users[id].push_back(8 * e + slot);
+            }
+        std::vector<int32_t> rrow(ne + 1, 0), rcol;
+        for (int e = 0; e < ne; ++e) {
+            rcol.insert(rcol.end(), users[e].begin(), users[e].end());
+            rrow[e + 1] = (int32_t)rcol.size();
+        }
+        c->lf_rrow = dev_upload(c, rrow);
+        c->lf_rcol = dev_upload(c, rcol);
+    }
+
+    // ---- P1 hierarchy (upwind flux)
+    c->lev.resize(lf ? 0 : nlev);
     std::vector<hdg::P1Host> galerkin;
     if (opt.p1_galerkin) {
         // S_c = pi^T S pi on the finest level, P^T A P below it (built on the host from the FP64 rows)
@@ -783,7 +902,7 @@ void setup_impl(const hdg_mesh *levels, int nlev, const int32_t *const *parents,
             galerkin[l - 1] = hdg::galerkin_coarsen(galerkin[l], parents[l], levels[l - 1].n_vert);
         }
     }
-    for (int l = 0; l < nlev; ++l) {
+    for (int l = 0; l < (int)c->lev.size(); ++l) {
         const hdg_mesh &lm = levels[l];
         hdg::P1Host P = opt.p1_galerkin ? galerkin[l] : hdg::assemble_p1(lm, c->kappa);
         hdg::P1LevelDev &L = c->lev[l];
@@ -851,7 +970,7 @@ void setup_impl(const hdg_mesh *levels, int nlev, const int32_t *const *parents,
 
     // ---- tail of the P1 hierarchy (levels small enough for one workgroup)
     c->tail_top = -1;
-    for (int l = 0; l < nlev && l < hdg::P1_TAIL_LEVELS; ++l)
+    for (int l = 0; l < (int)c->lev.size() && l < hdg::P1_TAIL_LEVELS; ++l)
         if (c->lev[l].n <= opt.p1_tail_max) c->tail_top = l;
         else break;
     if (c->tail_top >= 0) {
@@ -962,6 +1081,8 @@ extern "C" int hdg_default_options(hdg_options *o) {
     o->use_graph = 1;
     o->fallback_ratio = 0.5;
     o->p1_tail_max = hdg::P1_TAIL_MAX;
+    o->rt_nu = 1;
+    o->rt_omega = 0.5;
     return HDG_OK;
 }
 
@@ -1003,7 +1124,9 @@ extern "C" int hdg_get_sizes(const hdg_ctx *c, hdg_sizes *out) {
     out->n_vert = c->n_vert;
     out->degree = c->p;
     out->n_loc = c->n;
-    out->n_levels = (int)c->lev.size();
+    out->n_levels = (int)(c->flux == HDG_FLUX_LF ? c->rt.size() : c->lev.size());
+    out->facet_dofs = c->m;
+    out->flux = c->flux;
     out->device_bytes = c->device_bytes;
     out->kappa = c->kappa;
     out->lambda_max = c->cheb_lmax;
@@ -1030,7 +1153,7 @@ extern "C" int hdg_condense(hdg_ctx *c, int32_t nb, const double *r_cell, double
         hipStream_t s = as_stream(stream);
         Timed t(c, HDG_KERNEL_CONDENSE, HDG_FP64, s, nb);
         for (int rep = 0; rep < t.repeats(); ++rep)
-            hdg::launch_condense(c->p, c->n_cell, c->n_facet, nb, c->Zr, r_cell, c->loc, c->d_fcell, c->d_floc, rhat,
+            hdg::launch_condense(c->p, c->nu, c->n_cell, c->n_facet, nb, c->Zr, r_cell, c->loc, c->d_fcell, c->d_floc, rhat,
                                  s);
         check_launch();
     });
@@ -1106,7 +1229,7 @@ extern "C" int hdg_recover(hdg_ctx *c, int32_t nb, const double *r_cell, const d
         hipStream_t s = as_stream(stream);
         Timed t(c, HDG_KERNEL_RECOVER, HDG_FP64, s, nb);
         for (int rep = 0; rep < t.repeats(); ++rep)
-            hdg::launch_recover(c->p, c->n_cell, nb, c->Ar, c->Wr, c->cell_facet, c->cell_rev, r_cell, lam, q_cell,
+            hdg::launch_recover(c->p, c->nu, c->n_cell, nb, c->Ar, c->Wr, c->cell_facet, c->cell_rev, r_cell, lam, q_cell,
                                 s);
         check_launch();
     });
@@ -1185,6 +1308,7 @@ void mlp_unpack(const hdg_ctx *c, const std::vector<float> &buf, float scale, fl
 extern "C" int hdg_mlp_set_weights(hdg_ctx *c, const float *W1, const float *W2) {
     if (!c) return HDG_EINVAL;
     return guard([&] {
+        HDG_REQUIRE(c->flux == HDG_FLUX_UPWIND, "the learned smoother is built for the upwind flux only");
         HDG_REQUIRE(W1 && W2, "W1 and W2 must not be NULL");
         const int m = c->p + 1;
         for (size_t i = 0; i < (size_t)64 * 5 * m; ++i) HDG_REQUIRE(std::isfinite(W1[i]), "W1 has a non-finite entry");
@@ -1206,6 +1330,7 @@ extern "C" int hdg_mlp_set_weights(hdg_ctx *c, const float *W1, const float *W2)
 extern "C" int hdg_mlp_get_weights(hdg_ctx *c, float *W1, float *W2) {
     if (!c) return HDG_EINVAL;
     return guard([&] {
+        HDG_REQUIRE(c->flux == HDG_FLUX_UPWIND, "the learned smoother is built for the upwind flux only");
         std::vector<float> buf((size_t)c->mlp_n1 + c->mlp_n2);
         HDG_HIP_CHECK(hipDeviceSynchronize());
         HDG_HIP_CHECK(hipMemcpy(buf.data(), c->mlp_w, buf.size() * sizeof(float), hipMemcpyDeviceToHost));
@@ -1217,6 +1342,7 @@ extern "C" int hdg_mlp_make_data(hdg_ctx *c, int32_t nb, const double *e, double
                                  void *stream) {
     if (!c) return HDG_EINVAL;
     return guard([&] {
+        HDG_REQUIRE(c->flux == HDG_FLUX_UPWIND, "the learned smoother is built for the upwind flux only");
         check_nb(c, nb);
         HDG_REQUIRE(e && u && t && e != u && e != t && u != t, "e, u and t must be distinct non-NULL buffers");
         check_aligned(e, "e");
@@ -1234,6 +1360,7 @@ extern "C" int hdg_mlp_loss_grad(hdg_ctx *c, int32_t nb, const double *u, const 
                                  float *dW2, void *stream) {
     if (!c) return HDG_EINVAL;
     return guard([&] {
+        HDG_REQUIRE(c->flux == HDG_FLUX_UPWIND, "the learned smoother is built for the upwind flux only");
         check_nb(c, nb);
         HDG_REQUIRE(u && t, "u and t must not be NULL");
         check_aligned(u, "u");
@@ -1257,6 +1384,7 @@ extern "C" int hdg_mlp_train(hdg_ctx *c, int32_t nb, const double *e0, int32_t c
                              int32_t epochs, double lr, double *loss_hist, void *stream) {
     if (!c) return HDG_EINVAL;
     return guard([&] {
+        HDG_REQUIRE(c->flux == HDG_FLUX_UPWIND, "the learned smoother is built for the upwind flux only");
         check_nb(c, nb);
         HDG_REQUIRE(e0, "e0 must not be NULL");
         check_aligned(e0, "e0");
@@ -1362,6 +1490,7 @@ extern "C" int hdg_autotune(hdg_ctx *c, int32_t nb, hdg_tuning *chosen, void *st
         double best = 1e300;
         int best_spl = c->mlp_spl;
         for (int spl : {1, 2}) {
+            if (c->flux != HDG_FLUX_UPWIND) break;   // no learned smoother to tune
             const double ms = time_launches(s, 10, [&] {
                 hdg::launch_mlp_smooth(c->p, c->n_facet, nb, spl, c->vres, c->vx, nullptr, c->facet_vert, c->nbr,
                                        c->prev, W1b, W2b, c->vx2, s);

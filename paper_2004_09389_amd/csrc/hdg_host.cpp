@@ -148,7 +148,7 @@ static void gauss_legendre01(int n, std::vector<double> &x, std::vector<double> 
     }
 }
 
-static bool invert_dense(std::vector<double> &a, int n) {
+bool invert_dense(std::vector<double> &a, int n) {
     // Gauss-Jordan with partial pivoting, in place
     std::vector<int> piv(n);
     std::vector<double> inv((size_t)n * n, 0.0);

@@ -77,6 +77,36 @@ P1Host galerkin_from_rows(int ne, int m, int nv, const std::vector<double> &rows
 P1Host galerkin_coarsen(const P1Host &fine, const int32_t *parents, int nc);
 // in-place inverse of a dense SPD matrix [n][n]; returns false when not positive definite
 bool spd_inverse(std::vector<double> &a, int n);
+// in-place inverse of a dense matrix [n][n] (Gauss-Jordan, partial pivoting); false when singular
+bool invert_dense(std::vector<double> &a, int n);
+
+// ------------------------------------------------------------------ RT0 levels (host), Lax-Friedrichs flux
+constexpr int RT_PV = 8;   // most facets around one vertex (vertex-patch size)
+
+struct Rt0Host {
+    int ne = 0, nv = 0;
+    Topology topo;
+    std::vector<int32_t> nbr;     // [4][ne] other facets of the owner, then of the second cell
+    std::vector<double> val;      // [5][ne] S_c row of each facet: diagonal, then the nbr slots
+    std::vector<int32_t> pf;      // [RT_PV][nv] facets touching each vertex, -1 padded
+    std::vector<double> pinv;     // [RT_PV * RT_PV][nv] inverse of the patch block (zero padded)
+    std::vector<int32_t> fs;      // [2][ne] patch slot v * RT_PV + j of the facet's two ends
+    std::vector<int32_t> pc;      // [3][ne] coarse facets of the next coarser level feeding this facet
+    std::vector<double> pw;       // [3][ne] their weights (exact flux transfer)
+    std::vector<int32_t> crow, ccol;   // transpose of (pc, pw) over the coarser level's facets
+    std::vector<double> cw;
+};
+// S_c = (1/kappa)(M_RT + kappa^2 D_RT) on the torus mesh, patches and their inverses
+Rt0Host build_rt0_level(const hdg_mesh &mesh, double kappa, bool patches);
+// true when every cell of the mesh is determined by its three vertex ids
+bool cells_unique_by_vertices(const hdg_mesh &mesh);
+// inclusion RT0(coarse) -> RT0(fine) of a uniform refinement (fills fine.pc / pw / crow / ccol / cw)
+void rt0_transfer(const hdg_mesh &fine_mesh, Rt0Host &fine, const hdg_mesh &coarse_mesh, const Rt0Host &coarse,
+                  const int32_t *parents);
+// dense S_c of a level [ne][ne]
+std::vector<double> rt0_dense(const Rt0Host &L);
+// pi: RT0 fluxes -> LF trace nodes, weights [5][2m][ne] over the facet-row patch (facet, then nbr slots)
+std::vector<double> lf_prolongation_weights(const hdg_mesh &mesh, const Topology &topo, int p);
 
 // ------------------------------------------------------------------ context
 struct P1LevelDev {
@@ -109,11 +139,26 @@ struct P1Tail {
     P1Lev lev[P1_TAIL_LEVELS];
 };
 
+// RT0 level on the device (Lax-Friedrichs coarse space), arrays as in Rt0Host
+struct Rt0LevelDev {
+    int ne = 0, nv = 0;
+    int32_t *nbr = nullptr;
+    double *val = nullptr;
+    int32_t *pf = nullptr, *fs = nullptr;
+    double *pinv = nullptr;
+    int32_t *pc = nullptr;          // transfer from the next coarser level (null on the coarsest)
+    double *pw = nullptr;
+    int32_t *crow = nullptr, *ccol = nullptr;
+    double *cw = nullptr;
+    double *b = nullptr, *x = nullptr, *y = nullptr;   // [ne][max_rhs]
+};
+
 }  // namespace hdg
 
 struct hdg_ctx {
     int device = 0;
-    int p = 0, m = 0, n = 0, nc = 0, nt = 0;
+    int p = 0, m = 0, n = 0, nc = 0, nt = 0;   // m: trace unknowns per facet (nu (p + 1))
+    int nu = 1, flux = HDG_FLUX_UPWIND;        // trace components per node
     int n_cell = 0, n_facet = 0, n_vert = 0, geom = 0;
     double kappa = 0, hscale = 0, tau = 0, dt = 0;
     hdg_params prm{};
@@ -150,6 +195,14 @@ struct hdg_ctx {
     double *coarse_inv = nullptr;   // dense inverse of the coarsest level
     int tail_top = -1;              // levels 0..tail_top run in the single-workgroup tail kernel
     hdg::P1Tail tail{};
+
+    // Lax-Friedrichs coarse space: RT0 levels (level 0 coarsest), dense inverse of level 0,
+    // prolongation weights onto the trace [5][m][n_facet] and the CSR of its transpose
+    std::vector<hdg::Rt0LevelDev> rt;
+    double *rt_coarse_inv = nullptr;
+    double *rt_corr = nullptr;                  // vertex-patch corrections [n_vert][RT_PV][max_rhs]
+    double *lf_pw = nullptr;
+    int32_t *lf_rrow = nullptr, *lf_rcol = nullptr;
 
     // trace work vectors [n_facet][m][max_rhs]
     double *vz0 = nullptr, *vx = nullptr, *vx2 = nullptr, *vres = nullptr;

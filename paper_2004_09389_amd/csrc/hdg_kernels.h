@@ -85,21 +85,23 @@ struct CellParams {
     int geom;
 };
 
-void launch_cell_condense(int p, int nk, const double *corners, const double *ref, CellParams cp, double *Sloc,
-                          double *Zr, double *Ar, double *Wr, int *err, hipStream_t s);
-void launch_facet_rows(int p, int ne, int nk, const double *Sloc, const int *facet_cell, const int *facet_loc,
-                       const int *cell_facet, const int8_t *cell_rev, double omega, double *S64, double *T64,
-                       double *Dw64, float *S32, __hip_bfloat16 *T16, float *Dw32, int *nbr, int8_t *prev,
-                       int *err, hipStream_t s);
+// nu: trace components per node (1 upwind, 2 Lax-Friedrichs)
+void launch_cell_condense(int p, int nu, int nk, const double *corners, const double *ref, CellParams cp,
+                          double *Sloc, double *Zr, double *Ar, double *Wr, int *err, hipStream_t s);
+void launch_facet_rows(int p, int nu, int ne, int nk, const double *Sloc, const int *facet_cell,
+                       const int *facet_loc, const int *cell_facet, const int8_t *cell_rev, double omega,
+                       double *S64, double *T64, double *Dw64, float *S32, __hip_bfloat16 *T16, float *Dw32,
+                       int *nbr, int8_t *prev, int *err, hipStream_t s);
 
+// facet-row kernels: M = trace unknowns per facet (2, 3, 4, 6 or 8)
 template <typename MT>
-void launch_trace_apply(int p, int ne, int nb, const MT *S, const int *nbr, const double *x, const double *b,
+void launch_trace_apply(int M, int ne, int nb, const MT *S, const int *nbr, const double *x, const double *b,
                         double *y, hipStream_t s, int rhs_block = 1);
 template <typename MT>
-void launch_jacobi0(int p, int ne, int nb, const MT *Dw, const double *r, const double *scale, double *rs,
+void launch_jacobi0(int M, int ne, int nb, const MT *Dw, const double *r, const double *scale, double *rs,
                     double *z0, hipStream_t s);
 template <typename MT>
-void launch_sweep(int p, int ne, int nb, const MT *T, const int *nbr, const double *x, const double *z0,
+void launch_sweep(int M, int ne, int nb, const MT *T, const int *nbr, const double *x, const double *z0,
                   const double *qc, const int *fvert, SweepCoef cf, double *y, hipStream_t s, int rhs_block = 1);
 void launch_restrict_trace(int p, int nv, int nb, const int *vf_row, const int *vf_col, const double *res,
                            double *rc, hipStream_t s);
@@ -117,9 +119,9 @@ void launch_p1_restrict(int nc, int nb, const int *crow, const int *ccol, const 
 void launch_dense_mv(int n, int nb, const double *Ainv, const double *b, double *x, hipStream_t s);
 void launch_p1_tail(const P1Tail &T, int nb, hipStream_t s);
 
-void launch_condense(int p, int nk, int ne, int nb, const double *Zr, const double *rc, double *loc,
+void launch_condense(int p, int nu, int nk, int ne, int nb, const double *Zr, const double *rc, double *loc,
                      const int *facet_cell, const int *facet_loc, double *rhat, hipStream_t s);
-void launch_recover(int p, int nk, int nb, const double *Ar, const double *Wr, const int *cell_facet,
+void launch_recover(int p, int nu, int nk, int nb, const double *Ar, const double *Wr, const int *cell_facet,
                     const int8_t *cell_rev, const double *rc, const double *lam, double *q, hipStream_t s);
 
 int red_grid(int64_t len, int nb);

@@ -76,14 +76,23 @@ template <> struct Wide<__hip_bfloat16> {
 // parts.)  [A | B | Mtilde] is reduced by Gauss-Jordan with partial pivoting
 // in LDS, giving W = A^-1 B and A^-1 Mtilde, then S_K = Mt + C W (Step 2
 // operator) and C A^-1 Mtilde (Step 1 map) are formed.
+//
+// NU = 2: the Lax-Friedrichs form (Eq. bilinear_HDG_lax) with the vector
+// trace uhat, local trace unknown (f, d, k) at f*2m + d*m + k:
+//   A = [[M,                    -k G_1^T,          -k G_2^T        ],
+//        [-k G_1 + k n_f1 E_f,   M + k t sum_f E_f, -dt Mf          ],
+//        [-k G_2 + k n_f2 E_f,   dt Mf,             M + k t sum_f E_f]]
+//   (G_d^T[i][j] = (phi_j, d_d phi_i): the psi row keeps -k (u, grad psi)),
+//   B = [k n_fd T_f ; -k t T_f on component d],  C = [n_fd T_f^T, t T_f^T on
+//   component d],  Mt = t F_f per facet and component.
 
-template <int P>
+template <int P, int NU>
 __global__ __launch_bounds__(64) void k_cell_condense(int nk, const double *__restrict__ corners,
                                                       const double *__restrict__ ref, CellParams cp,
                                                       double *__restrict__ Sloc, double *__restrict__ Zr,
                                                       double *__restrict__ Ar, double *__restrict__ Wr,
                                                       int *__restrict__ err) {
-    constexpr int n = (P + 1) * (P + 2) / 2, m = P + 1, nc = 3 * n, nt = 3 * m, nq = (P + 3) * (P + 3);
+    constexpr int n = (P + 1) * (P + 2) / 2, m = P + 1, nc = 3 * n, M = NU * m, nt = 3 * M, nq = (P + 3) * (P + 3);
     constexpr int LD = nc + nt + nc;
     __shared__ double aug[nc * LD];
     __shared__ double Cm[nt * nc];
@@ -158,33 +167,58 @@ __global__ __launch_bounds__(64) void k_cell_condense(int nk, const double *__re
     __syncthreads();
 
     // ---- assemble [A | B | Mtilde] and C in LDS
+    auto mass_f = [&](int i, int j) {   // (f phi_j, phi_i)_K
+        double mf = 0.0;
+        for (int q = 0; q < nq; ++q) mf += fq[q] * rPhi[q * n + i] * rPhi[q * n + j];
+        return mf * det;
+    };
+    // (d_d phi_j, phi_i)_K / det for d = 0, 1
+    auto grad_ij = [&](int d, int i, int j) {
+        const double c0 = d == 0 ? J00 : J01, c1 = d == 0 ? J10 : J11;
+        return c0 * rG[i * n + j] + c1 * rG[n * n + i * n + j];
+    };
     for (int idx = lane; idx < nc * LD; idx += 64) {
         const int row = idx / LD, col = idx % LD;
         const int fr = row / n, i = row % n;
         double v = 0.0;
         if (col < nc) {
             const int fc = col / n, j = col % n;
-            if (fr == 0 && fc == 0) {
-                v = det * rM[i * n + j];
-                for (int f = 0; f < 3; ++f) v += kap * tau * L[f] * rE[f * n * n + i * n + j];
-            } else if (fr == 0) {
-                const double c0 = fc == 1 ? J00 : J01, c1 = fc == 1 ? J10 : J11;
-                v = kap * det * (c0 * rG[i * n + j] + c1 * rG[n * n + i * n + j]);
-            } else if (fc == 0) {
-                const double c0 = fr == 1 ? J00 : J01, c1 = fr == 1 ? J10 : J11;
-                v = -kap * det * (c0 * rG[j * n + i] + c1 * rG[n * n + j * n + i]);
-            } else if (fr == fc) {
-                v = det * rM[i * n + j];
+            if constexpr (NU == 1) {
+                if (fr == 0 && fc == 0) {
+                    v = det * rM[i * n + j];
+                    for (int f = 0; f < 3; ++f) v += kap * tau * L[f] * rE[f * n * n + i * n + j];
+                } else if (fr == 0) {
+                    v = kap * det * grad_ij(fc - 1, i, j);
+                } else if (fc == 0) {
+                    v = -kap * det * grad_ij(fr - 1, j, i);
+                } else if (fr == fc) {
+                    v = det * rM[i * n + j];
+                } else {
+                    v = (fr == 1) ? -dt * mass_f(i, j) : dt * mass_f(i, j);
+                }
             } else {
-                double mf = 0.0;
-                for (int q = 0; q < nq; ++q) mf += fq[q] * rPhi[q * n + i] * rPhi[q * n + j];
-                mf *= det;
-                v = (fr == 1) ? -dt * mf : dt * mf;
+                if (fr == 0 && fc == 0) {
+                    v = det * rM[i * n + j];
+                } else if (fr == 0) {
+                    v = -kap * det * grad_ij(fc - 1, j, i);
+                } else if (fc == 0) {
+                    v = -kap * det * grad_ij(fr - 1, j, i);
+                    for (int f = 0; f < 3; ++f)
+                        v += kap * (fr == 1 ? nx[f] : ny[f]) * L[f] * rE[f * n * n + i * n + j];
+                } else if (fr == fc) {
+                    v = det * rM[i * n + j];
+                    for (int f = 0; f < 3; ++f) v += kap * tau * L[f] * rE[f * n * n + i * n + j];
+                } else {
+                    v = (fr == 1) ? -dt * mass_f(i, j) : dt * mass_f(i, j);
+                }
             }
         } else if (col < nc + nt) {
-            const int c = col - nc, f = c / m, k = c % m;
+            const int c = col - nc, f = c / M, d = (c % M) / m, k = c % m;
             const double t = L[f] * rT[f * n * m + i * m + k];
-            v = fr == 0 ? -kap * tau * t : kap * (fr == 1 ? nx[f] : ny[f]) * t;
+            if constexpr (NU == 1)
+                v = fr == 0 ? -kap * tau * t : kap * (fr == 1 ? nx[f] : ny[f]) * t;
+            else
+                v = fr == 0 ? kap * (d == 0 ? nx[f] : ny[f]) * t : (fr == d + 1 ? -kap * tau * t : 0.0);
         } else {
             const int c = col - nc - nt, fc = c / n, j = c % n;
             if (fc == fr) v = (fr == 0 ? cp.hscale : 1.0) * det * rM[i * n + j];
@@ -193,9 +227,12 @@ __global__ __launch_bounds__(64) void k_cell_condense(int nk, const double *__re
     }
     for (int idx = lane; idx < nt * nc; idx += 64) {
         const int row = idx / nc, col = idx % nc;
-        const int f = row / m, k = row % m, fc = col / n, j = col % n;
+        const int f = row / M, d = (row % M) / m, k = row % m, fc = col / n, j = col % n;
         const double t = L[f] * rT[f * n * m + j * m + k];
-        Cm[idx] = fc == 0 ? tau * t : (fc == 1 ? nx[f] : ny[f]) * t;
+        if constexpr (NU == 1)
+            Cm[idx] = fc == 0 ? tau * t : (fc == 1 ? nx[f] : ny[f]) * t;
+        else
+            Cm[idx] = fc == 0 ? (d == 0 ? nx[f] : ny[f]) * t : (fc == d + 1 ? tau * t : 0.0);
     }
     __syncthreads();
 
@@ -240,7 +277,7 @@ __global__ __launch_bounds__(64) void k_cell_condense(int nk, const double *__re
     for (int idx = lane; idx < nt * nt; idx += 64) {
         const int a = idx / nt, b = idx % nt;
         double s = 0.0;
-        if (a / m == b / m) s = tau * L[a / m] * rF[(a % m) * m + (b % m)];
+        if (a / m == b / m) s = tau * L[a / M] * rF[(a % m) * m + (b % m)];   // same facet and component
         for (int j = 0; j < nc; ++j) s += Cm[a * nc + j] * aug[j * LD + nc + b];
         Sloc[(size_t)idx * NK + K] = s;
     }
@@ -272,6 +309,16 @@ __global__ __launch_bounds__(64) void k_cell_condense(int nk, const double *__re
 // owner cell, then of the second cell.  Also forms omega D_e^-1 and
 // omega D_e^-1 S_{e,j} used by the block-Jacobi sweep.
 
+// Local trace index of trace unknown a (0 <= a < NU m: component a / m, node
+// a % m in the facet's direction) of local facet i, for a cell that runs
+// along (rev = 0) or against (rev = 1) the facet's direction.
+template <int P, int NU>
+__device__ __forceinline__ int loc_trace(int i, int a, int rev) {
+    constexpr int m = P + 1;
+    const int k = a % m;
+    return i * NU * m + (a - k) + (rev ? P - k : k);
+}
+
 template <int M>
 __device__ bool small_inverse(double (&a)[M][M], double (&inv)[M][M]) {
     for (int i = 0; i < M; ++i)
@@ -297,81 +344,82 @@ __device__ bool small_inverse(double (&a)[M][M], double (&inv)[M][M]) {
     return true;
 }
 
-template <int P>
+template <int P, int NU>
 __global__ void k_facet_rows(int ne, int nk, const double *__restrict__ Sloc, const int *__restrict__ facet_cell,
                              const int *__restrict__ facet_loc, const int *__restrict__ cell_facet,
                              const int8_t *__restrict__ cell_rev, double omega, double *__restrict__ S64,
                              double *__restrict__ T64, double *__restrict__ Dw64, float *__restrict__ S32,
                              __hip_bfloat16 *__restrict__ T16, float *__restrict__ Dw32, int *__restrict__ nbr,
                              int8_t *__restrict__ prev, int *__restrict__ err) {
-    constexpr int m = P + 1, nt = 3 * m;
+    constexpr int m = P + 1, M = NU * m, nt = 3 * M;
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= ne) return;
-    double D[m][m] = {};
-    double Off[4][m][m];
     const size_t NK = (size_t)nk, NE = (size_t)ne;
+    // diagonal block: both cells' contributions
+    double D[M][M] = {};
     for (int s = 0; s < 2; ++s) {
         const int K = facet_cell[2 * e + s], i = facet_loc[2 * e + s];
-        for (int jj = 0; jj < 3; ++jj) {
-            const int i2 = (i + jj) % 3;
-            const int e2 = cell_facet[i2 * NK + K];
-            const int rev2 = cell_rev[i2 * NK + K];
-            if (jj > 0) {
-                nbr[(2 * s + jj - 1) * NE + e] = e2;
-                // learned-smoother patch: list this slot's nodes counter-clockwise around cell K
-                prev[(2 * s + jj - 1) * NE + e] = (int8_t)rev2;
-            }
-            for (int a = 0; a < m; ++a) {
-                const int ra = i * m + (s == 0 ? a : P - a);
-                for (int b = 0; b < m; ++b) {
-                    const int cb = i2 * m + (rev2 ? P - b : b);
-                    const double v = Sloc[(size_t)(ra * nt + cb) * NK + K];
-                    if (jj == 0)
-                        D[a][b] += v;
-                    else
-                        Off[2 * s + jj - 1][a][b] = v;
-                }
-            }
+        for (int a = 0; a < M; ++a) {
+            const int ra = loc_trace<P, NU>(i, a, s);
+            for (int b = 0; b < M; ++b) D[a][b] += Sloc[(size_t)(ra * nt + loc_trace<P, NU>(i, b, s)) * NK + K];
         }
     }
-    double Dc[m][m], Di[m][m];
-    for (int a = 0; a < m; ++a)
-        for (int b = 0; b < m; ++b) Dc[a][b] = D[a][b];
-    if (!small_inverse<m>(Dc, Di)) {
+    double Dc[M][M], Di[M][M];
+    for (int a = 0; a < M; ++a)
+        for (int b = 0; b < M; ++b) Dc[a][b] = D[a][b];
+    if (!small_inverse<M>(Dc, Di)) {
         atomicOr(err, 4);
         return;
     }
-    for (int a = 0; a < m; ++a)
-        for (int b = 0; b < m; ++b) {
-            const int c = a * m + b;
+    for (int a = 0; a < M; ++a)
+        for (int b = 0; b < M; ++b) {
+            const int c = a * M + b;
             S64[widx(c, e, NE, 2)] = D[a][b];
             S32[widx(c, e, NE, 4)] = (float)D[a][b];
             Dw64[widx(c, e, NE, 2)] = omega * Di[a][b];
             Dw32[widx(c, e, NE, 4)] = (float)(omega * Di[a][b]);
         }
-    for (int j = 0; j < 4; ++j)
-        for (int a = 0; a < m; ++a)
-            for (int b = 0; b < m; ++b) {
-                double t = 0.0;
-                for (int c = 0; c < m; ++c) t += Di[a][c] * Off[j][c][b];
-                const int cs = ((j + 1) * m + a) * m + b;
-                const int ct = (j * m + a) * m + b;
-                S64[widx(cs, e, NE, 2)] = Off[j][a][b];
-                S32[widx(cs, e, NE, 4)] = (float)Off[j][a][b];
-                T64[widx(ct, e, NE, 2)] = omega * t;
-                T16[widx(ct, e, NE, 8)] = __float2bfloat16((float)(omega * t));
+    // off-diagonal slots j = 2 s + jj - 1: the other two facets of the owner, then of the second cell
+    for (int s = 0; s < 2; ++s) {
+        const int K = facet_cell[2 * e + s], i = facet_loc[2 * e + s];
+        for (int jj = 1; jj < 3; ++jj) {
+            const int j = 2 * s + jj - 1;
+            const int i2 = (i + jj) % 3;
+            const int e2 = cell_facet[i2 * NK + K];
+            const int rev2 = cell_rev[i2 * NK + K];
+            nbr[j * NE + e] = e2;
+            // learned-smoother patch: list this slot's nodes counter-clockwise around cell K
+            prev[j * NE + e] = (int8_t)rev2;
+            double Off[M][M];
+            for (int a = 0; a < M; ++a) {
+                const int ra = loc_trace<P, NU>(i, a, s);
+                for (int b = 0; b < M; ++b)
+                    Off[a][b] = Sloc[(size_t)(ra * nt + loc_trace<P, NU>(i2, b, rev2)) * NK + K];
             }
+            for (int a = 0; a < M; ++a)
+                for (int b = 0; b < M; ++b) {
+                    double t = 0.0;
+                    for (int c = 0; c < M; ++c) t += Di[a][c] * Off[c][b];
+                    const int cs = ((j + 1) * M + a) * M + b;
+                    const int ct = (j * M + a) * M + b;
+                    S64[widx(cs, e, NE, 2)] = Off[a][b];
+                    S32[widx(cs, e, NE, 4)] = (float)Off[a][b];
+                    T64[widx(ct, e, NE, 2)] = omega * t;
+                    T16[widx(ct, e, NE, 8)] = __float2bfloat16((float)(omega * t));
+                }
+        }
+    }
     // zero the padding up to a whole 16-byte group
-    for (int c = 5 * m * m; c < padded(5 * m * m, 4); ++c) {
-        if (c < padded(5 * m * m, 2)) S64[widx(c, e, NE, 2)] = 0.0;
+    for (int c = 5 * M * M; c < padded(5 * M * M, 4); ++c) {
+        if (c < padded(5 * M * M, 2)) S64[widx(c, e, NE, 2)] = 0.0;
         S32[widx(c, e, NE, 4)] = 0.f;
     }
-    for (int c = m * m; c < padded(m * m, 4); ++c) {
-        if (c < padded(m * m, 2)) Dw64[widx(c, e, NE, 2)] = 0.0;
+    for (int c = M * M; c < padded(M * M, 4); ++c) {
+        if (c < padded(M * M, 2)) Dw64[widx(c, e, NE, 2)] = 0.0;
         Dw32[widx(c, e, NE, 4)] = 0.f;
     }
-    for (int c = 4 * m * m; c < padded(4 * m * m, 8); ++c) {
-        if (c < padded(4 * m * m, 2)) T64[widx(c, e, NE, 2)] = 0.0;
+    for (int c = 4 * M * M; c < padded(4 * M * M, 8); ++c) {
+        if (c < padded(4 * M * M, 2)) T64[widx(c, e, NE, 2)] = 0.0;
         T16[widx(c, e, NE, 8)] = __float2bfloat16(0.f);
     }
 }
@@ -756,38 +804,14 @@ __global__ __launch_bounds__(1024) void k_p1_tail(const P1Tail Targ, int nb) {
 // loc[rho][K][r] = sum_j Zr[rho][j][K] r_cell[K][j][r]   (Step 1, cell part)
 constexpr int RECOVER_TILE = 128;   // cells per block of the one-right-hand-side cell kernels
 
-template <int P>
-__global__ __launch_bounds__(256) void k_condense_cell(int nk, int nb, const double *__restrict__ Zr,
-                                                       const double *__restrict__ rc, double *__restrict__ loc) {
-    constexpr int n = (P + 1) * (P + 2) / 2, m = P + 1, nc = 3 * n, nt = 3 * m, ZW = cell_zw(P);
-    const int t = xcd_block() * blockDim.x + threadIdx.x;
-    if (t >= nk * nb) return;
-    const int K = t / nb, r = t - K * nb;
-    const size_t NK = (size_t)nk;
-    double f[ZW];
-#pragma unroll
-    for (int j = 0; j < ZW; ++j) f[j] = j < nc ? rc[((size_t)K * nc + j) * nb + r] : 0.0;
-#pragma unroll
-    for (int a = 0; a < nt; ++a) {
-        double s = 0.0;
-#pragma unroll
-        for (int jp = 0; jp < ZW / 2; ++jp) {
-            double w[2];
-            Wide<double>::load(Zr + ((size_t)(a * ZW / 2 + jp) * NK + K) * 2, w);
-            s += w[0] * f[2 * jp];
-            if (2 * jp + 1 < nc) s += w[1] * f[2 * jp + 1];
-        }
-        loc[((size_t)a * NK + K) * nb + r] = s;
-    }
-}
-
 // Condensation at one right-hand side: the block's cells read their inputs
-// through LDS (coalesced global loads); same arithmetic order as k_condense_cell.
-template <int P>
+// through LDS (coalesced global loads).  NU trace components per node (1:
+// upwind, 2: Lax-Friedrichs).
+template <int P, int NU>
 __global__ __launch_bounds__(RECOVER_TILE) void k_condense_cell_n1(int nk, const double *__restrict__ Zr,
                                                                   const double *__restrict__ rc,
                                                                   double *__restrict__ loc) {
-    constexpr int n = (P + 1) * (P + 2) / 2, m = P + 1, nc = 3 * n, nt = 3 * m, ZW = cell_zw(P);
+    constexpr int n = (P + 1) * (P + 2) / 2, m = P + 1, nc = 3 * n, nt = 3 * NU * m, ZW = cell_zw(P);
     __shared__ double buf[RECOVER_TILE * nc];
     const int K0 = xcd_block() * RECOVER_TILE, tid = threadIdx.x, K = K0 + tid;
     const int cnt = min(RECOVER_TILE, nk - K0);
@@ -813,66 +837,33 @@ __global__ __launch_bounds__(RECOVER_TILE) void k_condense_cell_n1(int nk, const
 }
 
 // rhat[e][a][r] = sum of the two cells' local contributions (orientation mapped)
-template <int P>
+template <int P, int NU>
 __global__ void k_condense_gather(int ne, int nk, int nb, const int *__restrict__ facet_cell,
                                   const int *__restrict__ facet_loc, const double *__restrict__ loc,
                                   double *__restrict__ rhat) {
-    constexpr int m = P + 1;
+    constexpr int M = NU * (P + 1);
     const int t = xcd_block() * blockDim.x + threadIdx.x;
-    if (t >= ne * m * nb) return;
-    const int r = t % nb, ea = t / nb, e = ea / m, a = ea - e * m;
+    if (t >= ne * M * nb) return;
+    const int r = t % nb, ea = t / nb, e = ea / M, a = ea - e * M;
     const size_t NK = (size_t)nk;
     const int K0 = facet_cell[2 * e], i0 = facet_loc[2 * e];
     const int K1 = facet_cell[2 * e + 1], i1 = facet_loc[2 * e + 1];
-    const double v0 = loc[((size_t)(i0 * m + a) * NK + K0) * nb + r];
-    const double v1 = loc[((size_t)(i1 * m + P - a) * NK + K1) * nb + r];
+    const double v0 = loc[((size_t)loc_trace<P, NU>(i0, a, 0) * NK + K0) * nb + r];
+    const double v1 = loc[((size_t)loc_trace<P, NU>(i1, a, 1) * NK + K1) * nb + r];
     rhat[t] = v0 + v1;
 }
 
-// q = Ar r_cell - Wr lam_K  (Step 3)
-template <int P>
-__global__ __launch_bounds__(256) void k_recover(int nk, int nb, const double *__restrict__ Ar,
-                                                 const double *__restrict__ Wr, const int *__restrict__ cell_facet,
-                                                 const int8_t *__restrict__ cell_rev, const double *__restrict__ rc,
-                                                 const double *__restrict__ lam, double *__restrict__ q) {
-    constexpr int n = (P + 1) * (P + 2) / 2, m = P + 1, nc = 3 * n, nt = 3 * m;
-    const int t = xcd_block() * blockDim.x + threadIdx.x;
-    if (t >= nk * nb) return;
-    const int K = t / nb, r = t - K * nb;
-    const size_t NK = (size_t)nk;
-    double f[nc], l[nt];
-#pragma unroll
-    for (int j = 0; j < nc; ++j) f[j] = rc[((size_t)K * nc + j) * nb + r];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        const int e = cell_facet[i * NK + K];
-        const int rev = cell_rev[i * NK + K];
-#pragma unroll
-        for (int k = 0; k < m; ++k) l[i * m + k] = lam[((size_t)e * m + (rev ? P - k : k)) * nb + r];
-    }
-#pragma unroll 1
-    for (int a = 0; a < nc; ++a) {
-        double s = 0.0;
-#pragma unroll
-        for (int j = 0; j < nc; ++j) s += ldm(Ar + (size_t)(a * nc + j) * NK + K) * f[j];
-#pragma unroll
-        for (int j = 0; j < nt; ++j) s -= ldm(Wr + (size_t)(a * nt + j) * NK + K) * l[j];
-        q[((size_t)K * nc + a) * nb + r] = s;
-    }
-}
-
-// Recovery with one right-hand side: the block's cells read their inputs
-// and write their outputs through LDS, so the global traffic of r_cell and q
-// (nc consecutive values per cell) is coalesced; same arithmetic order as
-// k_recover.
-template <int P>
+// Recovery q = Ar r_cell - Wr lam_K (Step 3) with one right-hand side: the
+// block's cells read their inputs and write their outputs through LDS, so the
+// global traffic of r_cell and q (nc consecutive values per cell) is coalesced.
+template <int P, int NU>
 __global__ __launch_bounds__(RECOVER_TILE) void k_recover_n1(int nk, const double *__restrict__ Ar,
                                                             const double *__restrict__ Wr,
                                                             const int *__restrict__ cell_facet,
                                                             const int8_t *__restrict__ cell_rev,
                                                             const double *__restrict__ rc,
                                                             const double *__restrict__ lam, double *__restrict__ q) {
-    constexpr int n = (P + 1) * (P + 2) / 2, m = P + 1, nc = 3 * n, nt = 3 * m;
+    constexpr int n = (P + 1) * (P + 2) / 2, m = P + 1, nc = 3 * n, M = NU * m, nt = 3 * M;
     __shared__ double buf[RECOVER_TILE * nc];
     const int K0 = xcd_block() * RECOVER_TILE, tid = threadIdx.x, K = K0 + tid;
     const int cnt = min(RECOVER_TILE, nk - K0);   // may be <= 0 in the padding blocks
@@ -889,7 +880,7 @@ __global__ __launch_bounds__(RECOVER_TILE) void k_recover_n1(int nk, const doubl
             const int e = cell_facet[i * NK + K];
             const int rev = cell_rev[i * NK + K];
 #pragma unroll
-            for (int k = 0; k < m; ++k) l[i * m + k] = lam[(size_t)e * m + (rev ? P - k : k)];
+            for (int a = 0; a < M; ++a) l[loc_trace<P, NU>(i, a, rev)] = lam[(size_t)e * M + a];
         }
     }
     __syncthreads();
@@ -914,14 +905,17 @@ __global__ __launch_bounds__(RECOVER_TILE) void k_recover_n1(int nk, const doubl
 // thread keeps its right-hand side's inputs in registers.  Same arithmetic
 // order as the one-thread-per-(cell, rhs) kernels.
 constexpr int CELL_ROWS = 6;
-inline int cell_block_cells(int nb) { return std::max(1, std::min(32, 256 / nb)); }
+// cells per block for row length rl: at most 256 threads and 64 KiB of staged rows
+inline int cell_block_cells(int nb, int rl) {
+    return std::max(1, std::min(std::min(32, 256 / nb), 65536 / (int)(sizeof(double) * CELL_ROWS * rl)));
+}
 
-template <int P>
+template <int P, int NU>
 __global__ __launch_bounds__(256) void k_recover_b(int nk, int nb, int cb, const double *__restrict__ Ar,
                                                    const double *__restrict__ Wr, const int *__restrict__ cell_facet,
                                                    const int8_t *__restrict__ cell_rev, const double *__restrict__ rc,
                                                    const double *__restrict__ lam, double *__restrict__ q) {
-    constexpr int n = (P + 1) * (P + 2) / 2, m = P + 1, nc = 3 * n, nt = 3 * m, RL = nc + nt;
+    constexpr int n = (P + 1) * (P + 2) / 2, m = P + 1, nc = 3 * n, M = NU * m, nt = 3 * M, RL = nc + nt;
     extern __shared__ double sm[];   // [row][entry][cell], CELL_ROWS * RL * cb doubles
     const int K0 = xcd_block() * cb, tid = threadIdx.x;
     const int cl = tid / nb, r = tid - cl * nb, K = K0 + cl;
@@ -936,7 +930,7 @@ __global__ __launch_bounds__(256) void k_recover_b(int nk, int nb, int cb, const
             const int e = cell_facet[i * NK + K];
             const int rev = cell_rev[i * NK + K];
 #pragma unroll
-            for (int k = 0; k < m; ++k) l[i * m + k] = lam[((size_t)e * m + (rev ? P - k : k)) * nb + r];
+            for (int a = 0; a < M; ++a) l[loc_trace<P, NU>(i, a, rev)] = lam[((size_t)e * M + a) * nb + r];
         }
     }
     for (int a0 = 0; a0 < nc; a0 += CELL_ROWS) {
@@ -965,10 +959,10 @@ __global__ __launch_bounds__(256) void k_recover_b(int nk, int nb, int cb, const
     }
 }
 
-template <int P>
+template <int P, int NU>
 __global__ __launch_bounds__(256) void k_condense_cell_b(int nk, int nb, int cb, const double *__restrict__ Zr,
                                                          const double *__restrict__ rc, double *__restrict__ loc) {
-    constexpr int n = (P + 1) * (P + 2) / 2, m = P + 1, nc = 3 * n, nt = 3 * m, ZW = cell_zw(P);
+    constexpr int n = (P + 1) * (P + 2) / 2, m = P + 1, nc = 3 * n, nt = 3 * NU * m, ZW = cell_zw(P);
     extern __shared__ double sm[];   // [row][entry][cell], CELL_ROWS * ZW * cb doubles
     const int K0 = xcd_block() * cb, tid = threadIdx.x;
     const int cl = tid / nb, r = tid - cl * nb, K = K0 + cl;
@@ -1440,47 +1434,56 @@ bool rhs_blocked(int nb, int rhs_block) {
 
 #define GRID8(n, b) dim3((unsigned)((((n) + (b) - 1) / (b) + N_XCD - 1) / N_XCD * N_XCD)), dim3(b)
 
-void launch_cell_condense(int p, int nk, const double *corners, const double *ref, CellParams cp, double *Sloc,
-                          double *Zr, double *Ar, double *Wr, int *err, hipStream_t s) {
-    switch (p) {
-    case 1: hipLaunchKernelGGL(k_cell_condense<1>, dim3(nk), dim3(64), 0, s, nk, corners, ref, cp, Sloc, Zr, Ar, Wr, err); break;
-    case 2: hipLaunchKernelGGL(k_cell_condense<2>, dim3(nk), dim3(64), 0, s, nk, corners, ref, cp, Sloc, Zr, Ar, Wr, err); break;
-    case 3: hipLaunchKernelGGL(k_cell_condense<3>, dim3(nk), dim3(64), 0, s, nk, corners, ref, cp, Sloc, Zr, Ar, Wr, err); break;
-    }
+void launch_cell_condense(int p, int nu, int nk, const double *corners, const double *ref, CellParams cp,
+                          double *Sloc, double *Zr, double *Ar, double *Wr, int *err, hipStream_t s) {
+#define CK(P, NU) hipLaunchKernelGGL((k_cell_condense<P, NU>), dim3(nk), dim3(64), 0, s, nk, corners, ref, cp, Sloc, Zr, Ar, Wr, err)
+    if (nu == 1) { switch (p) { case 1: CK(1, 1); break; case 2: CK(2, 1); break; case 3: CK(3, 1); break; } }
+    else { switch (p) { case 1: CK(1, 2); break; case 2: CK(2, 2); break; case 3: CK(3, 2); break; } }
+#undef CK
 }
 
-void launch_facet_rows(int p, int ne, int nk, const double *Sloc, const int *facet_cell, const int *facet_loc,
-                       const int *cell_facet, const int8_t *cell_rev, double omega, double *S64, double *T64,
-                       double *Dw64, float *S32, __hip_bfloat16 *T16, float *Dw32, int *nbr, int8_t *prev,
-                       int *err, hipStream_t s) {
-#define FR(P) hipLaunchKernelGGL(k_facet_rows<P>, GRID(ne, 128), 0, s, ne, nk, Sloc, facet_cell, facet_loc, cell_facet, cell_rev, omega, S64, T64, Dw64, S32, T16, Dw32, nbr, prev, err)
-    switch (p) { case 1: FR(1); break; case 2: FR(2); break; case 3: FR(3); break; }
+void launch_facet_rows(int p, int nu, int ne, int nk, const double *Sloc, const int *facet_cell,
+                       const int *facet_loc, const int *cell_facet, const int8_t *cell_rev, double omega,
+                       double *S64, double *T64, double *Dw64, float *S32, __hip_bfloat16 *T16, float *Dw32,
+                       int *nbr, int8_t *prev, int *err, hipStream_t s) {
+#define FR(P, NU) hipLaunchKernelGGL((k_facet_rows<P, NU>), GRID(ne, 128), 0, s, ne, nk, Sloc, facet_cell, facet_loc, cell_facet, cell_rev, omega, S64, T64, Dw64, S32, T16, Dw32, nbr, prev, err)
+    if (nu == 1) { switch (p) { case 1: FR(1, 1); break; case 2: FR(2, 1); break; case 3: FR(3, 1); break; } }
+    else { switch (p) { case 1: FR(1, 2); break; case 2: FR(2, 2); break; case 3: FR(3, 2); break; } }
 #undef FR
 }
 
+// Facet-row launchers take M, the trace unknowns per facet: p + 1 (upwind) or
+// 2 (p + 1) (Lax-Friedrichs).  The RHS-blocked forms stage 64 facets' rows in
+// LDS and are built for M <= 4.
+bool rhs_blocked_m(int M, int nb, int rhs_block) { return M <= 4 && rhs_blocked(nb, rhs_block); }
+
+#define M_SWITCH(X) \
+    switch (M) { case 2: X(2); break; case 3: X(3); break; case 4: X(4); break; case 6: X(6); break; case 8: X(8); break; }
+#define M_SWITCH_RB(X) switch (M) { case 2: X(2); break; case 3: X(3); break; case 4: X(4); break; }
+
 template <typename MT>
-void launch_trace_apply(int p, int ne, int nb, const MT *S, const int *nbr, const double *x, const double *b,
+void launch_trace_apply(int M, int ne, int nb, const MT *S, const int *nbr, const double *x, const double *b,
                         double *y, hipStream_t s, int rhs_block) {
-    if (rhs_blocked(nb, rhs_block)) {
-#define TAB(P) hipLaunchKernelGGL((k_trace_apply_rb<P + 1, MT, 4>), GRID_RB(ne, nb), 0, s, ne, nb, S, nbr, x, b, y)
-        switch (p) { case 1: TAB(1); break; case 2: TAB(2); break; case 3: TAB(3); break; }
+    if (rhs_blocked_m(M, nb, rhs_block)) {
+#define TAB(MM) hipLaunchKernelGGL((k_trace_apply_rb<MM, MT, 4>), GRID_RB(ne, nb), 0, s, ne, nb, S, nbr, x, b, y)
+        M_SWITCH_RB(TAB)
 #undef TAB
         return;
     }
-#define TA(P)                                                                                          \
-    if (nb == 1) hipLaunchKernelGGL((k_trace_apply<P + 1, MT, true>), GRID8(ne * nb, 256), 0, s, ne, nb, S, nbr, x, b, y); \
-    else hipLaunchKernelGGL((k_trace_apply<P + 1, MT, false>), GRID8(ne * nb, 256), 0, s, ne, nb, S, nbr, x, b, y)
-    switch (p) { case 1: TA(1); break; case 2: TA(2); break; case 3: TA(3); break; }
+#define TA(MM)                                                                                          \
+    if (nb == 1) hipLaunchKernelGGL((k_trace_apply<MM, MT, true>), GRID8(ne * nb, 256), 0, s, ne, nb, S, nbr, x, b, y); \
+    else hipLaunchKernelGGL((k_trace_apply<MM, MT, false>), GRID8(ne * nb, 256), 0, s, ne, nb, S, nbr, x, b, y)
+    M_SWITCH(TA)
 #undef TA
 }
 template void launch_trace_apply<double>(int, int, int, const double *, const int *, const double *, const double *, double *, hipStream_t, int);
 template void launch_trace_apply<float>(int, int, int, const float *, const int *, const double *, const double *, double *, hipStream_t, int);
 
 template <typename MT>
-void launch_jacobi0(int p, int ne, int nb, const MT *Dw, const double *r, const double *scale, double *rs,
+void launch_jacobi0(int M, int ne, int nb, const MT *Dw, const double *r, const double *scale, double *rs,
                     double *z0, hipStream_t s) {
-#define J0(P) hipLaunchKernelGGL((k_jacobi0<P + 1, MT>), GRID8(ne * nb, 256), 0, s, ne, nb, Dw, r, scale, rs, z0)
-    switch (p) { case 1: J0(1); break; case 2: J0(2); break; case 3: J0(3); break; }
+#define J0(MM) hipLaunchKernelGGL((k_jacobi0<MM, MT>), GRID8(ne * nb, 256), 0, s, ne, nb, Dw, r, scale, rs, z0)
+    M_SWITCH(J0)
 #undef J0
 }
 template void launch_jacobi0<double>(int, int, int, const double *, const double *, const double *, double *,
@@ -1488,20 +1491,21 @@ template void launch_jacobi0<double>(int, int, int, const double *, const double
 template void launch_jacobi0<float>(int, int, int, const float *, const double *, const double *, double *,
                                     double *, hipStream_t);
 
+// qc (the fused P1 prolongation) applies to the upwind trace only: M = p + 1.
 template <typename MT>
-void launch_sweep(int p, int ne, int nb, const MT *T, const int *nbr, const double *x, const double *z0,
+void launch_sweep(int M, int ne, int nb, const MT *T, const int *nbr, const double *x, const double *z0,
                   const double *qc, const int *fvert, SweepCoef cf, double *y, hipStream_t s,
                   int rhs_block) {
-    if (rhs_blocked(nb, rhs_block)) {
-#define SWB(P) hipLaunchKernelGGL((k_sweep_rb<P + 1, MT, 4>), GRID_RB(ne, nb), 0, s, ne, nb, T, nbr, x, z0, qc, fvert, cf, y)
-        switch (p) { case 1: SWB(1); break; case 2: SWB(2); break; case 3: SWB(3); break; }
+    if (rhs_blocked_m(M, nb, rhs_block)) {
+#define SWB(MM) hipLaunchKernelGGL((k_sweep_rb<MM, MT, 4>), GRID_RB(ne, nb), 0, s, ne, nb, T, nbr, x, z0, qc, fvert, cf, y)
+        M_SWITCH_RB(SWB)
 #undef SWB
         return;
     }
-#define SW(P)                                                                                                \
-    if (nb == 1) hipLaunchKernelGGL((k_sweep<P + 1, MT, true>), GRID8(ne * nb, 256), 0, s, ne, nb, T, nbr, x, z0, qc, fvert, cf, y); \
-    else hipLaunchKernelGGL((k_sweep<P + 1, MT, false>), GRID8(ne * nb, 256), 0, s, ne, nb, T, nbr, x, z0, qc, fvert, cf, y)
-    switch (p) { case 1: SW(1); break; case 2: SW(2); break; case 3: SW(3); break; }
+#define SW(MM)                                                                                                \
+    if (nb == 1) hipLaunchKernelGGL((k_sweep<MM, MT, true>), GRID8(ne * nb, 256), 0, s, ne, nb, T, nbr, x, z0, qc, fvert, cf, y); \
+    else hipLaunchKernelGGL((k_sweep<MM, MT, false>), GRID8(ne * nb, 256), 0, s, ne, nb, T, nbr, x, z0, qc, fvert, cf, y)
+    M_SWITCH(SW)
 #undef SW
 }
 template void launch_sweep<double>(int, int, int, const double *, const int *, const double *, const double *, const double *, const int *, SweepCoef, double *, hipStream_t, int);
@@ -1545,32 +1549,35 @@ void launch_p1_tail(const P1Tail &T, int nb, hipStream_t s) {
     hipLaunchKernelGGL(k_p1_tail, dim3(1), dim3(1024), 0, s, T, nb);
 }
 
-void launch_condense(int p, int nk, int ne, int nb, const double *Zr, const double *rc, double *loc,
+void launch_condense(int p, int nu, int nk, int ne, int nb, const double *Zr, const double *rc, double *loc,
                      const int *facet_cell, const int *facet_loc, double *rhat, hipStream_t s) {
-#define CC(P)                                                                                                     \
+#define CC(P, NU)                                                                                                 \
     if (nb == 1)                                                                                                  \
-        hipLaunchKernelGGL(k_condense_cell_n1<P>, GRID8(nk, RECOVER_TILE), 0, s, nk, Zr, rc, loc);                \
+        hipLaunchKernelGGL((k_condense_cell_n1<P, NU>), GRID8(nk, RECOVER_TILE), 0, s, nk, Zr, rc, loc);          \
     else                                                                                                          \
-        hipLaunchKernelGGL(k_condense_cell_b<P>, GRID8((int64_t)nk * nb, cell_block_cells(nb) * nb),               \
-                           sizeof(double) * CELL_ROWS * cell_zw(P) * cell_block_cells(nb), s, nk, nb,              \
-                           cell_block_cells(nb), Zr, rc, loc);                                                    \
-    hipLaunchKernelGGL(k_condense_gather<P>, GRID8(ne * (P + 1) * nb, 256), 0, s, ne, nk, nb, facet_cell,         \
-                       facet_loc, loc, rhat)
-    switch (p) { case 1: CC(1); break; case 2: CC(2); break; case 3: CC(3); break; }
+        hipLaunchKernelGGL((k_condense_cell_b<P, NU>), GRID8((int64_t)nk * nb, cell_block_cells(nb, cell_zw(P)) * nb), \
+                           sizeof(double) * CELL_ROWS * cell_zw(P) * cell_block_cells(nb, cell_zw(P)), s, nk, nb,  \
+                           cell_block_cells(nb, cell_zw(P)), Zr, rc, loc);                                        \
+    hipLaunchKernelGGL((k_condense_gather<P, NU>), GRID8(ne * NU * (P + 1) * nb, 256), 0, s, ne, nk, nb,          \
+                       facet_cell, facet_loc, loc, rhat)
+    if (nu == 1) { switch (p) { case 1: CC(1, 1); break; case 2: CC(2, 1); break; case 3: CC(3, 1); break; } }
+    else { switch (p) { case 1: CC(1, 2); break; case 2: CC(2, 2); break; case 3: CC(3, 2); break; } }
 #undef CC
 }
 
-void launch_recover(int p, int nk, int nb, const double *Ar, const double *Wr, const int *cell_facet,
+#define RL_REC(P, NU) (3 * (P + 1) * (P + 2) / 2 + 3 * (NU) * (P + 1))   // recovery row: A^-1 Mt and W entries
+void launch_recover(int p, int nu, int nk, int nb, const double *Ar, const double *Wr, const int *cell_facet,
                     const int8_t *cell_rev, const double *rc, const double *lam, double *q, hipStream_t s) {
-#define RC(P)                                                                                                  \
+#define RC(P, NU)                                                                                              \
     if (nb == 1)                                                                                               \
-        hipLaunchKernelGGL(k_recover_n1<P>, GRID8(nk, RECOVER_TILE), 0, s, nk, Ar, Wr, cell_facet, cell_rev, rc, \
-                           lam, q);                                                                            \
+        hipLaunchKernelGGL((k_recover_n1<P, NU>), GRID8(nk, RECOVER_TILE), 0, s, nk, Ar, Wr, cell_facet, cell_rev, \
+                           rc, lam, q);                                                                        \
     else                                                                                                       \
-        hipLaunchKernelGGL(k_recover_b<P>, GRID8((int64_t)nk * nb, cell_block_cells(nb) * nb),                 \
-                           sizeof(double) * CELL_ROWS * (3 * (P + 1) * (P + 2) / 2 + 3 * (P + 1)) * cell_block_cells(nb), \
-                           s, nk, nb, cell_block_cells(nb), Ar, Wr, cell_facet, cell_rev, rc, lam, q)
-    switch (p) { case 1: RC(1); break; case 2: RC(2); break; case 3: RC(3); break; }
+        hipLaunchKernelGGL((k_recover_b<P, NU>), GRID8((int64_t)nk * nb, cell_block_cells(nb, RL_REC(P, NU)) * nb), \
+                           sizeof(double) * CELL_ROWS * RL_REC(P, NU) * cell_block_cells(nb, RL_REC(P, NU)), s, nk, \
+                           nb, cell_block_cells(nb, RL_REC(P, NU)), Ar, Wr, cell_facet, cell_rev, rc, lam, q)
+    if (nu == 1) { switch (p) { case 1: RC(1, 1); break; case 2: RC(2, 1); break; case 3: RC(3, 1); break; } }
+    else { switch (p) { case 1: RC(1, 2); break; case 2: RC(2, 2); break; case 3: RC(3, 2); break; } }
 #undef RC
 }
 

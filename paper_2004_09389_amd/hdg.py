@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libhdg.so")
 
 HDG_OK, HDG_EINVAL, HDG_ENOMEM, HDG_EHIP, HDG_EBREAKDOWN, HDG_ENOTCONV = 0, -1, -2, -3, -4, 1
 HDG_TORUS, HDG_SPHERE = 0, 1
+HDG_FLUX_UPWIND, HDG_FLUX_LF = 0, 1
 HDG_FP64, HDG_MIXED, HDG_MIXED_IR = 0, 1, 2
 HDG_KRYLOV_AUTO, HDG_KRYLOV_PCG, HDG_KRYLOV_FGMRES = 0, 1, 2
 HDG_SMOOTH_BJACOBI, HDG_SMOOTH_MLP, HDG_SMOOTH_CHEBYSHEV = 0, 1, 2
@@ -34,7 +35,7 @@ class HdgMesh(ctypes.Structure):
 class HdgParams(ctypes.Structure):
     _fields_ = [("degree", ctypes.c_int32), ("dt", ctypes.c_double), ("g", ctypes.c_double),
                 ("H", ctypes.c_double), ("f0", ctypes.c_double), ("omega", ctypes.c_double),
-                ("tau", ctypes.c_double)]
+                ("tau", ctypes.c_double), ("flux", ctypes.c_int32)]
 
 
 class HdgOptions(ctypes.Structure):
@@ -43,7 +44,8 @@ class HdgOptions(ctypes.Structure):
                 ("p1_nu", ctypes.c_int32), ("p1_omega", ctypes.c_double), ("rtol", ctypes.c_double),
                 ("maxit", ctypes.c_int32), ("restart", ctypes.c_int32), ("max_rhs", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("fallback_ratio", ctypes.c_double),
-                ("p1_tail_max", ctypes.c_int32), ("p1_galerkin", ctypes.c_int32)]
+                ("p1_tail_max", ctypes.c_int32), ("p1_galerkin", ctypes.c_int32),
+                ("rt_nu", ctypes.c_int32), ("rt_omega", ctypes.c_double)]
 
 
 class HdgSolveInfo(ctypes.Structure):
@@ -54,7 +56,7 @@ class HdgSolveInfo(ctypes.Structure):
 class HdgSizes(ctypes.Structure):
     _fields_ = [("n_cell", ctypes.c_int32), ("n_facet", ctypes.c_int32), ("n_vert", ctypes.c_int32),
                 ("degree", ctypes.c_int32), ("n_loc", ctypes.c_int32), ("n_levels", ctypes.c_int32),
-                ("device_bytes", ctypes.c_int64), ("kappa", ctypes.c_double), ("lambda_max", ctypes.c_double)]
+                ("facet_dofs", ctypes.c_int32), ("flux", ctypes.c_int32), ("device_bytes", ctypes.c_int64), ("kappa", ctypes.c_double), ("lambda_max", ctypes.c_double)]
 
 
 class HdgTuning(ctypes.Structure):
@@ -152,11 +154,13 @@ class HdgSolver:
     hierarchy: hdg_inputs.Hierarchy (coarse -> fine; the finest mesh is the
     HDG mesh).  Device arrays are torch float64 tensors on cuda with the
     layouts of the C ABI: cell arrays (n_cell, 3, n_loc, nrhs), trace arrays
-    (n_facet, p+1, nrhs).
+    (n_facet, facet_dofs, nrhs) with facet_dofs = p+1 (upwind flux) or
+    2(p+1) (flux=HDG_FLUX_LF: x components at the nodes, then y).
     """
 
     def __init__(self, hierarchy, degree: int, dt: float, g: float = 1.0, H: float = 1.0,
-                 f0: float = 0.0, omega: float = 0.0, tau: float = 1.0, **options):
+                 f0: float = 0.0, omega: float = 0.0, tau: float = 1.0, flux: int = HDG_FLUX_UPWIND,
+                 **options):
         import torch  # noqa: F401  (initialises the HIP runtime through torch)
         self.lib = load_library()
         self.hier = hierarchy
@@ -181,7 +185,7 @@ class HdgSolver:
             a = np.ascontiguousarray(par, dtype=np.int32)
             keep.append(a)
             parents[l + 1] = a.ctypes.data
-        prm = HdgParams(degree, dt, g, H, f0, omega, tau)
+        prm = HdgParams(degree, dt, g, H, f0, omega, tau, int(flux))
         ctx = ctypes.c_void_p()
         _check(self.lib.hdg_setup(meshes, len(hierarchy.meshes), parents, ctypes.byref(prm),
                                   ctypes.byref(opt), ctypes.byref(ctx)))
@@ -190,7 +194,9 @@ class HdgSolver:
         _check(self.lib.hdg_get_sizes(ctx, ctypes.byref(sz)))
         self.sizes = sz
         self.p = degree
-        self.m = degree + 1
+        self.flux = int(flux)
+        self.m = sz.facet_dofs          # trace unknowns per facet
+        self.mp = degree + 1            # trace nodes per facet (learned-smoother weight shapes)
         self.n_loc = sz.n_loc
         self.n_cell, self.n_facet, self.n_vert = sz.n_cell, sz.n_facet, sz.n_vert
         self.kappa = sz.kappa
@@ -274,13 +280,13 @@ class HdgSolver:
         """W1 (64, 5(p+1)), W2 (p+1, 64); stored as FP32 (Adam state reset)."""
         W1 = np.ascontiguousarray(W1, dtype=np.float32)
         W2 = np.ascontiguousarray(W2, dtype=np.float32)
-        if W1.shape != (64, 5 * self.m) or W2.shape != (self.m, 64):
+        if W1.shape != (64, 5 * self.mp) or W2.shape != (self.mp, 64):
             raise ValueError("W1 must be (64, 5(p+1)) and W2 (p+1, 64)")
         _check(self.lib.hdg_mlp_set_weights(self.ctx, W1.ctypes.data, W2.ctypes.data))
 
     def mlp_get_weights(self):
-        W1 = np.zeros((64, 5 * self.m), dtype=np.float32)
-        W2 = np.zeros((self.m, 64), dtype=np.float32)
+        W1 = np.zeros((64, 5 * self.mp), dtype=np.float32)
+        W2 = np.zeros((self.mp, 64), dtype=np.float32)
         _check(self.lib.hdg_mlp_get_weights(self.ctx, W1.ctypes.data, W2.ctypes.data))
         return W1, W2
 
@@ -294,8 +300,8 @@ class HdgSolver:
     def mlp_loss_grad(self, u, t):
         nb = self._nrhs(u, 3)
         loss = ctypes.c_double()
-        dW1 = np.zeros((64, 5 * self.m), dtype=np.float32)
-        dW2 = np.zeros((self.m, 64), dtype=np.float32)
+        dW1 = np.zeros((64, 5 * self.mp), dtype=np.float32)
+        dW2 = np.zeros((self.mp, 64), dtype=np.float32)
         _check(self.lib.hdg_mlp_loss_grad(self.ctx, nb, _ptr(u), _ptr(t), ctypes.byref(loss), dW1.ctypes.data,
                                           dW2.ctypes.data, _stream()))
         return float(loss.value), dW1, dW2

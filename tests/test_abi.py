@@ -50,8 +50,35 @@ def test_default_options_and_errors_without_gpu():
 def test_struct_layouts_match_header():
     # the ctypes mirrors must have the C struct sizes (natural alignment)
     assert ctypes.sizeof(hdg.HdgMesh) == 4 * 3 + 4 + 8 + 3 * 8
-    assert ctypes.sizeof(hdg.HdgParams) == 8 + 6 * 8
+    assert ctypes.sizeof(hdg.HdgParams) == 8 + 6 * 8 + 8
     assert ctypes.sizeof(hdg.HdgSolveInfo) == 4 * 4 + 8
-    assert ctypes.sizeof(hdg.HdgOptions) == 4 * 6 + 8 + 4 + 4 + 8 + 8 + 4 * 4 + 8 + 4 + 4
+    assert ctypes.sizeof(hdg.HdgOptions) == 4 * 6 + 8 + 4 + 4 + 8 + 8 + 4 * 4 + 8 + 4 + 4 + 4 + 4 + 8
     assert ctypes.sizeof(hdg.HdgTuning) == 8
-    assert ctypes.sizeof(hdg.HdgSizes) == 6 * 4 + 8 + 2 * 8
+    assert ctypes.sizeof(hdg.HdgSizes) == 8 * 4 + 8 + 2 * 8
+
+
+def test_struct_offsets_match_c_compiler(tmp_path):
+    """Every field offset of the ctypes mirrors equals the C compiler's offsetof
+    for the structs of include/hdg.h (compiled here with gcc)."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    structs = {"hdg_mesh": hdg.HdgMesh, "hdg_params": hdg.HdgParams, "hdg_options": hdg.HdgOptions,
+               "hdg_solve_info": hdg.HdgSolveInfo, "hdg_sizes": hdg.HdgSizes, "hdg_tuning": hdg.HdgTuning}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", f'#include "{HEADER}"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)

@@ -1,0 +1,198 @@
+"""GPU parity of the Lax-Friedrichs path (vector trace, RT0 coarse space)
+against the FP64 oracle: condensation, trace operator (FP64 and FP32 rows),
+recovery, the V-cycle with block-Jacobi and Chebyshev smoothing over the RT0
+multigrid, and solves against the standard LF-DG system solved directly."""
+import numpy as np
+import pytest
+
+import hdg_inputs as hi
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def to_dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def make(n, p, n_coarse=4, dt=0.3, f0=0.5, **opts):
+    from paper_2004_09389_amd.hdg import HDG_FLUX_LF, HdgSolver
+    print(f"[lf] solver n={n} p={p} dt={dt} f0={f0} {opts}", flush=True)
+    return HdgSolver(hi.torus_hierarchy(n, n_coarse), p, dt, 1.3, 0.8, f0, 0.0, flux=HDG_FLUX_LF, **opts)
+
+
+def oracle(n, p, dt=0.3, f0=0.5):
+    from oracle.lf import HdgLfOracle
+    return HdgLfOracle(hi.torus(n), p, dt, 1.3, 0.8, f0, 0.0)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+@pytest.mark.parametrize("nb", [1, 3])
+def test_operators(p, nb):
+    from paper_2004_09389_amd.hdg import HDG_MIXED
+    n = 8
+    s = make(n, p, max_rhs=nb)
+    o = oracle(n, p)
+    assert s.m == 2 * (p + 1)
+    r = hi.iid_rhs(o.mesh, p, 21, nrhs=nb)
+    rhat = host(s.condense(to_dev(r)))
+    x = np.random.default_rng(1).standard_normal((o.topo.n_facet, s.m, nb))
+    y = host(s.trace_apply(to_dev(x)))
+    y32 = host(s.trace_apply(to_dev(x), HDG_MIXED))
+    q = host(s.recover(to_dev(r), to_dev(x)))
+    for k in range(nb):
+        assert rel(rhat[..., k].ravel(), o.rhat(r[..., k])) < 1e-12
+        ref = o.apply(x[..., k].ravel())
+        assert rel(y[..., k].ravel(), ref) < 1e-12
+        assert rel(y32[..., k].ravel(), ref) < 1e-5
+        assert rel(q[..., k], o.recover(r[..., k], x[..., k].ravel())) < 1e-12
+    s.close()
+
+
+@pytest.mark.parametrize("p", [1, 3])
+@pytest.mark.parametrize("smoother", ["jacobi", "chebyshev"])
+def test_vcycle(p, smoother):
+    """V-cycle vs the oracle's (same smoothing, pi, RT0 levels 4, 8, 16 with
+    vertex-patch smoothing and the dense 4 x 4 level)."""
+    from oracle.lf import LfTraceMultigrid
+    from paper_2004_09389_amd.hdg import HDG_MIXED, HDG_SMOOTH_BJACOBI, HDG_SMOOTH_CHEBYSHEV
+    n = 16
+    o = oracle(n, p, dt=0.5 / n * 8, f0=0.0)
+    mg = LfTraceMultigrid(o, hi.torus_hierarchy(n, 4), smoother=smoother)
+    s = make(n, p, dt=0.5 / n * 8, f0=0.0,
+             smoother=HDG_SMOOTH_CHEBYSHEV if smoother == "chebyshev" else HDG_SMOOTH_BJACOBI)
+    assert s.sizes.n_levels == 3
+    if smoother == "chebyshev":
+        assert abs(s.sizes.lambda_max - mg.lambda_max) < 1e-10 * mg.lambda_max
+    b = np.random.default_rng(7).standard_normal((o.topo.n_facet, s.m, 1))
+    ref = mg.vcycle(b[..., 0].ravel())
+    assert rel(host(s.mg_vcycle(to_dev(b)))[..., 0].ravel(), ref) < 1e-11
+    assert rel(host(s.mg_vcycle(to_dev(b), HDG_MIXED))[..., 0].ravel(), ref) < 3e-2
+    s.close()
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+@pytest.mark.parametrize("f0,precision", [(0.0, "fp64"), (0.7, "fp64"), (0.7, "mixed")])
+def test_solve_matches_dg(p, f0, precision):
+    """condense + solve + recover equals the standard LF-DG solution (direct
+    solve) and uhat = {{u}} + [[phi]]/2."""
+    from oracle.lf import DgLfOracle
+    from paper_2004_09389_amd.hdg import HDG_FP64, HDG_MIXED
+    n = 8
+    d = DgLfOracle(hi.torus(n), p, 0.3, 1.3, 0.8, f0, 0.0)
+    r = hi.iid_rhs(d.mesh, p, 31)
+    q_ref, lam_ref = d.solve(r[..., 0])
+    s = make(n, p, f0=f0, rtol=1e-12 if precision == "fp64" else 1e-11,
+             precision=HDG_FP64 if precision == "fp64" else HDG_MIXED)
+    q, lam, info = s.step(to_dev(r))
+    assert info[0].status == 0
+    tol = 1e-10 if precision == "fp64" else 1e-8
+    assert rel(host(lam)[..., 0].ravel(), lam_ref) < tol
+    for fld in range(3):
+        assert rel(host(q)[:, fld, :, 0], q_ref[:, fld]) < tol
+    print(f"p={p} f0={f0} {precision}: {info[0]}")
+    s.close()
+
+
+@pytest.mark.parametrize("n", [1, 2])
+def test_tiny_meshes_single_rt0_level(n):
+    """Meshes too small for a coarser RT0 level: the fine RT0 problem is solved
+    with its dense inverse; the solve still matches the LF-DG oracle."""
+    from oracle.lf import DgLfOracle
+    p = 2
+    d = DgLfOracle(hi.torus(n), p, 0.7, 1.3, 0.8, 0.3, 0.0)
+    r = hi.iid_rhs(d.mesh, p, 41)
+    q_ref, lam_ref = d.solve(r[..., 0])
+    s = make(n, p, n_coarse=1, dt=0.7, f0=0.3, rtol=1e-12)
+    q, lam, info = s.step(to_dev(r))
+    assert s.sizes.n_levels == 1 and info[0].status == 0
+    assert rel(host(lam)[..., 0].ravel(), lam_ref) < 1e-10
+    assert rel(host(q)[..., 0], q_ref) < 1e-10
+    s.close()
+
+
+def test_argument_errors():
+    from paper_2004_09389_amd.hdg import HDG_FLUX_LF, HDG_SMOOTH_MLP, HdgError, HdgSolver
+    with pytest.raises(HdgError) as e:
+        HdgSolver(hi.icosphere_hierarchy(1, 1.0), 1, 0.1, flux=HDG_FLUX_LF)
+    assert "torus" in str(e.value)
+    with pytest.raises(HdgError) as e:
+        HdgSolver(hi.torus_hierarchy(8, 4), 1, 0.1, flux=HDG_FLUX_LF, smoother=HDG_SMOOTH_MLP)
+    assert "upwind" in str(e.value)
+    with pytest.raises(HdgError):
+        HdgSolver(hi.torus_hierarchy(8, 4), 1, 0.1, flux=7)
+    s = make(8, 1)
+    with pytest.raises(HdgError) as e:
+        s.mlp_get_weights()
+    assert "upwind" in str(e.value)
+    s.close()
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_manufactured_solution_rate(p):
+    """A smooth periodic solution through the GPU LF path converges at a rate
+    > p + 1/2."""
+    import torch
+    from oracle.fem import volume_points
+    from oracle.lf import LfLocal
+    tp = 2 * np.pi
+    phi = lambda x, y: np.sin(tp * x) * np.cos(tp * y)
+    ux = lambda x, y: 0.5 * np.cos(tp * x) * np.sin(tp * y)
+    uy = lambda x, y: np.sin(tp * (x + y))
+    divu = lambda x, y: -0.5 * tp * np.sin(tp * x) * np.sin(tp * y) + tp * np.cos(tp * (x + y))
+    gx = lambda x, y: tp * np.cos(tp * x) * np.cos(tp * y)
+    gy = lambda x, y: -tp * np.sin(tp * x) * np.sin(tp * y)
+    errs = []
+    for n in (4, 8, 16):
+        o = LfLocal(hi.torus(n), p, 0.05, 1.0, 1.0, 0.9, 0.0)
+        kap, dt, f0 = o.kappa, o.dt, 0.9
+        Z, w = volume_points(o.geo, 2 * p + 6)
+        X = Z + o.geo.corners3[:, None, 0, :2]
+        V = o.basis.values(Z)
+        Minv = np.linalg.inv(o.M)
+        proj = lambda fn: np.einsum("cij,cj->ci", Minv, np.einsum("cq,cqi,cq->ci", w, V, fn(X[..., 0], X[..., 1])))
+        r = np.stack([proj(lambda x, y: phi(x, y) + kap * divu(x, y)),
+                      proj(lambda x, y: ux(x, y) - dt * f0 * uy(x, y) + kap * gx(x, y)),
+                      proj(lambda x, y: uy(x, y) + dt * f0 * ux(x, y) + kap * gy(x, y))], 1)
+        from paper_2004_09389_amd.hdg import HDG_FLUX_LF, HdgSolver
+        s = HdgSolver(hi.torus_hierarchy(n, 4 if n >= 4 else 1), p, 0.05, 1.0, 1.0, 0.9, 0.0, flux=HDG_FLUX_LF,
+                      rtol=1e-11)
+        q, _, info = s.step(torch.from_numpy(np.ascontiguousarray(r[..., None])).cuda())
+        assert info[0].status == 0
+        q = q.cpu().numpy()[..., 0]
+        err = 0.0
+        for fld, fn in ((0, phi), (1, ux), (2, uy)):
+            e = np.einsum("cqi,ci->cq", V, q[:, fld]) - fn(X[..., 0], X[..., 1])
+            err += np.sum(w * e ** 2)
+        errs.append(np.sqrt(err))
+        s.close()
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    print(f"LF p={p} errors {errs} rates {rates}")
+    assert rates[-1] > p + 0.5
+
+
+@pytest.mark.parametrize("p", [1, 3])
+def test_iterations_over_mesh_ladder(p):
+    """Iteration counts to 1e-8 over n = 16 ... 128 at the paper's LF Courant
+    number 2/(2p+1) stay flat (the two-level method is mesh-independent)."""
+    from paper_2004_09389_amd.hdg import HDG_MIXED, HDG_SMOOTH_CHEBYSHEV
+    its = []
+    for n in (16, 32, 64, 128):
+        s = make(n, p, dt=2.0 / (2 * p + 1) / n, f0=1.0, precision=HDG_MIXED, krylov=2,
+                 smoother=HDG_SMOOTH_CHEBYSHEV)
+        import torch
+        r = torch.from_numpy(hi.fourier_rhs_torus(hi.torus(n), p, 100)).cuda()
+        _, info = s.solve(s.condense(r))
+        assert info[0].status == 0
+        its.append(info[0].iters)
+        s.close()
+    print(f"LF p={p}: FGMRES iterations to 1e-8 over n = 16..128: {its}")
+    assert max(its) - min(its) <= 3
