@@ -58,6 +58,8 @@ def parse():
     ap.add_argument("--learned-nu", type=int, default=2, help="learned smoother: sweeps before and after the coarse solve")
     ap.add_argument("--headline", default="mixed", choices=["learned", "mixed"],
                     help="which reduced-precision solver `value` reports")
+    ap.add_argument("--no-lf", action="store_true", help="skip the Lax-Friedrichs-flux leg")
+    ap.add_argument("--lf-coarse", type=int, default=8, help="LF leg: side of the coarsest RT0 level")
     ap.add_argument("--pmc-run", action="store_true",
                     help="short run for hardware counters: mixed leg only, plus a reference copy kernel")
     return ap.parse_args()
@@ -140,11 +142,59 @@ def errors_vs_oracle(sample, p, dt, rtol, coarse, learned_weights):
     return out
 
 
+def lf_leg(args, p, n, nb, run_steps):
+    """The Lax-Friedrichs flux (vector trace, RT0 coarse space) on the same
+    torus, p and right-hand side: mixed and FP64 solvers at the paper's LF
+    Courant number 2/(2p+1) (Chebyshev(2) smoothing as in the paper's
+    settings), and the mixed solver at Courant 8 for comparison."""
+    import torch
+
+    import hdg_inputs as hi
+    from paper_2004_09389_amd.hdg import HDG_FLUX_LF, HDG_FP64, HDG_MIXED, HDG_SMOOTH_CHEBYSHEV, HdgSolver
+    hier = hi.torus_hierarchy(n, args.lf_coarse)
+    r = torch.from_numpy(hi.fourier_rhs_torus(hier.fine, p, 100, nrhs=nb)).to("cuda")
+    out = {"trace_dof": int(2 * 3 * (p + 1) * hier.fine.n_cell // 2),
+           "coarsest_rt0": f"{args.lf_coarse}x{args.lf_coarse}", "smoother": "chebyshev(2)", "f": 1.0}
+    for label, courant, precs in (("courant_paper", 2.0 / (2 * p + 1), (HDG_MIXED, HDG_FP64)),
+                                  ("courant_8", 8.0, (HDG_MIXED,))):
+        for prec in precs:
+            t = time.perf_counter()
+            s = HdgSolver(hier, p, courant / n, 1.0, 1.0, 1.0, 0.0, 1.0, flux=HDG_FLUX_LF, rtol=args.rtol,
+                          precision=prec, max_rhs=nb, smoother=HDG_SMOOTH_CHEBYSHEV, krylov=2, maxit=400,
+                          use_graph=0 if args.no_graph else 1)
+            torch.cuda.synchronize()
+            tsetup = time.perf_counter() - t
+            lam, rhat, q = s.trace_zeros(nb), s.trace_zeros(nb), s.cell_zeros(nb)
+
+            def step():
+                s.condense(r, out=rhat)
+                lam.zero_()
+                _, info = s.solve(rhat, lam)
+                s.recover(r, lam, out=q)
+                return info
+            for _ in range(max(1, args.warmup)):
+                step()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            infos = [step() for _ in range(run_steps)]
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t
+            name = f"{label}_{'mixed' if prec == HDG_MIXED else 'fp64'}"
+            out[name] = {"courant": round(courant, 4), "value": round(run_steps * nb / el, 3), "unit": "solves/s",
+                         "ms_per_step": round(1e3 * el / run_steps, 4),
+                         "iters": float(np.mean([i.iters for inf in infos for i in inf])),
+                         "rel_res_max": max(i.rel_res for inf in infos for i in inf), "setup_s": round(tsetup, 3)}
+            log(f"[bench] lf {name}: {out[name]['ms_per_step']} ms/step iters={out[name]['iters']}")
+            s.close()
+            del s
+    return out
+
+
 def main():
     args = parse()
     if args.pmc_run:
         args.no_fp64, args.no_cpu, args.batch = True, True, 0
-        args.no_learned, args.headline = True, "mixed"
+        args.no_learned, args.headline, args.no_lf = True, "mixed", True
     if args.no_learned:
         args.headline = "mixed"
     if args.gpus != 1:
@@ -268,6 +318,10 @@ def main():
         s.close()
         del s
 
+    lf_out = None
+    if not args.no_lf:
+        lf_out = lf_leg(args, p, n, nb, run_steps=min(args.steps, 10))
+
     if args.pmc_run:
         # reference copy of known size for scaling the profiler's byte counters
         n_copy = 32 * 1024 * 1024
@@ -364,6 +418,8 @@ def main():
                 "note": "relative L2 differences of the mixed path against the FP64 path at each stage: "
                         "FP32 operator rows, the mixed V-cycle (FP32 rows, BF16 smoother rows, FP32 block "
                         "inverses) and the end-to-end solution at rtol; condense and recover are FP64 in both"}
+    if lf_out is not None:
+        out["lf_leg"] = lf_out
     if not args.no_cpu:
         log("[bench] cpu oracle baseline ...")
         out["cpu_baseline"], sample = cpu_baseline(n, p, dt)

@@ -196,3 +196,62 @@ def test_iterations_over_mesh_ladder(p):
         s.close()
     print(f"LF p={p}: FGMRES iterations to 1e-8 over n = 16..128: {its}")
     assert max(its) - min(its) <= 3
+
+
+_FULL = {}
+
+
+def _full_size():
+    """256 x 256 torus, p = 3, f = 1, the paper's LF Courant number 2/7, the
+    oracle and its V-cycle over RT0 levels 8 ... 256 (built once)."""
+    if not _FULL:
+        from oracle.lf import HdgLfOracle, LfTraceMultigrid
+        print("[lf] full-size oracle", flush=True)
+        hier = hi.torus_hierarchy(256, 8)
+        o = HdgLfOracle(hier.fine, 3, (2.0 / 7.0) / 256, 1.0, 1.0, 1.0, 0.0)
+        _FULL.update(hier=hier, o=o, mg=LfTraceMultigrid(o, hier, smoother="chebyshev"),
+                     r=hi.fourier_rhs_torus(hier.fine, 3, 200, nrhs=2))
+    return _FULL
+
+
+def test_full_size_operators():
+    """Every entry of rhat, S x (FP64, FP32 rows), the recovery and the
+    Chebyshev V-cycle at the benchmark's LF size against the oracle."""
+    from paper_2004_09389_amd.hdg import HDG_FLUX_LF, HDG_MIXED, HDG_SMOOTH_CHEBYSHEV, HdgSolver
+    F = _full_size()
+    o, r = F["o"], F["r"]
+    s = HdgSolver(F["hier"], 3, (2.0 / 7.0) / 256, 1.0, 1.0, 1.0, 0.0, flux=HDG_FLUX_LF, max_rhs=2,
+                  smoother=HDG_SMOOTH_CHEBYSHEV)
+    rhat = host(s.condense(to_dev(r)))
+    for k in range(2):
+        assert rel(rhat[..., k].ravel(), o.rhat(r[..., k])) < 1e-10
+    x = np.random.default_rng(3).standard_normal((o.topo.n_facet, s.m, 1))
+    ref = o.apply(x[..., 0].ravel())
+    assert rel(host(s.trace_apply(to_dev(x)))[..., 0].ravel(), ref) < 1e-10
+    assert rel(host(s.trace_apply(to_dev(x), HDG_MIXED))[..., 0].ravel(), ref) < 1e-5
+    q = host(s.recover(to_dev(r[..., :1]), to_dev(x)))
+    assert rel(q[..., 0], o.recover(r[..., 0], x[..., 0].ravel())) < 1e-10
+    assert abs(s.sizes.lambda_max - F["mg"].lambda_max) < 1e-9 * F["mg"].lambda_max
+    vref = F["mg"].vcycle(x[..., 0].ravel())
+    assert rel(host(s.mg_vcycle(to_dev(x)))[..., 0].ravel(), vref) < 1e-10
+    s.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_full_size_solve_certified(precision):
+    """Batched solve to 1e-8 at the benchmark's LF size; the oracle recomputes
+    each column's true relative residual."""
+    from paper_2004_09389_amd.hdg import HDG_FLUX_LF, HDG_FP64, HDG_MIXED, HDG_SMOOTH_CHEBYSHEV, HdgSolver
+    F = _full_size()
+    o, r = F["o"], F["r"]
+    s = HdgSolver(F["hier"], 3, (2.0 / 7.0) / 256, 1.0, 1.0, 1.0, 0.0, flux=HDG_FLUX_LF, max_rhs=2,
+                  smoother=HDG_SMOOTH_CHEBYSHEV, krylov=2, rtol=1e-8,
+                  precision=HDG_FP64 if precision == "fp64" else HDG_MIXED)
+    lam, info = s.solve(s.condense(to_dev(r)))
+    lam = host(lam)
+    for k in range(2):
+        rh = o.rhat(r[..., k])
+        res = np.linalg.norm(rh - o.apply(lam[..., k].ravel())) / np.linalg.norm(rh)
+        assert info[k].status == 0 and res <= 1e-8 * (1 + 1e-3)
+    print(f"[lf] full size {precision}: {info}")
+    s.close()
