@@ -60,6 +60,7 @@ def parse():
                     help="which reduced-precision solver `value` reports")
     ap.add_argument("--no-lf", action="store_true", help="skip the Lax-Friedrichs-flux leg")
     ap.add_argument("--lf-coarse", type=int, default=8, help="LF leg: side of the coarsest RT0 level")
+    ap.add_argument("--lf-only", action="store_true", help="run only the Lax-Friedrichs leg (profiling)")
     ap.add_argument("--pmc-run", action="store_true",
                     help="short run for hardware counters: mixed leg only, plus a reference copy kernel")
     return ap.parse_args()
@@ -211,6 +212,9 @@ def main():
 
     torch.cuda.set_device(0)
     p, n, nb = args.degree, args.n, args.nrhs
+    if args.lf_only:
+        print(json.dumps({"lf_leg": lf_leg(args, p, n, nb, run_steps=args.steps)}), flush=True)
+        return
     dt = 8.0 / n
     t0 = time.perf_counter()
     hier = hi.torus_hierarchy(n, args.coarse)
