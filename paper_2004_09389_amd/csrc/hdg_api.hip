@@ -158,18 +158,46 @@ void collect_timing(hdg_ctx *c) {
 }
 
 // ------------------------------------------------------------------ trace-level operators
+//
+// Trace vectors are FP64 or, under the flags vcyc32 / vin32 / kv32 (see
+// hdg_ctx), FP32 in the same buffers.  vt_call runs f with a null pointer of
+// the element type selected by flag; vt2_call with two.
+template <typename F>
+void vt_call(bool f32, F &&f) {
+    if (f32)
+        f(static_cast<float *>(nullptr));
+    else
+        f(static_cast<double *>(nullptr));
+}
+template <typename F>
+void vt2_call(bool a32, bool b32, F &&f) {
+    vt_call(a32, [&](auto ta) { vt_call(b32, [&](auto tb) { f(ta, tb); }); });
+}
+template <typename VT>
+const VT *vt(const double *p) { return reinterpret_cast<const VT *>(p); }
+template <typename VT>
+VT *vt(double *p) { return reinterpret_cast<VT *>(p); }
 
-// y = S x (b == nullptr) or y = b - S x
-void op_apply(hdg_ctx *c, int nb, int prec, const double *x, const double *b, double *y, hipStream_t s,
-              int kind) {
+// y = S x (b == nullptr) or y = b - S x; x32 / y32: x, and b and y, held in FP32
+void op_apply(hdg_ctx *c, int nb, int prec, const double *x, const double *b, double *y, hipStream_t s, int kind,
+              bool x32 = false, bool y32 = false) {
     Timed t(c, kind, prec, s, nb);
-    for (int rep = 0; rep < t.repeats(); ++rep) {
-        if (prec == HDG_MIXED)
-            hdg::launch_trace_apply<float>(c->m, c->n_facet, nb, c->S32, c->nbr, x, b, y, s, c->rhs_block);
-        else
-            hdg::launch_trace_apply<double>(c->m, c->n_facet, nb, c->S64, c->nbr, x, b, y, s, c->rhs_block);
-    }
+    for (int rep = 0; rep < t.repeats(); ++rep)
+        vt2_call(x32, y32, [&](auto tx, auto ty) {
+            using XT = std::remove_pointer_t<decltype(tx)>;
+            using YT = std::remove_pointer_t<decltype(ty)>;
+            if (prec == HDG_MIXED)
+                hdg::launch_trace_apply<float, XT, YT>(c->m, c->n_facet, nb, c->S32, c->nbr, vt<XT>(x), vt<YT>(b),
+                                                       vt<YT>(y), s, c->rhs_block);
+            else
+                hdg::launch_trace_apply<double, XT, YT>(c->m, c->n_facet, nb, c->S64, c->nbr, vt<XT>(x), vt<YT>(b),
+                                                        vt<YT>(y), s, c->rhs_block);
+        });
     check_launch();
+}
+// the V-cycle's residual r - S x (work vectors)
+void op_resid_v(hdg_ctx *c, int nb, int prec, const double *x, const double *r, double *y, hipStream_t s) {
+    op_apply(c, nb, prec, x, r, y, s, HDG_KERNEL_RESIDUAL, c->vcyc32, c->vcyc32);
 }
 
 // damped block-Jacobi sweep y = x' + omega D^-1 (r - S x')
@@ -178,14 +206,16 @@ hdg::SweepCoef bj_coef(const hdg_ctx *c) { return {1.0 - c->opt.omega, 1.0, 1.0,
 void op_sweep(hdg_ctx *c, int nb, int prec, const double *x, const double *z0, const double *qc, double *y,
               hipStream_t s, const hdg::SweepCoef &cf) {
     Timed t(c, HDG_KERNEL_SWEEP, prec, s, nb);
-    for (int rep = 0; rep < t.repeats(); ++rep) {
-        if (prec == HDG_MIXED)
-            hdg::launch_sweep<__hip_bfloat16>(c->m, c->n_facet, nb, c->T16, c->nbr, x, z0, qc, c->facet_vert, cf, y,
-                                              s, c->rhs_block);
-        else
-            hdg::launch_sweep<double>(c->m, c->n_facet, nb, c->T64, c->nbr, x, z0, qc, c->facet_vert, cf, y, s,
-                                      c->rhs_block);
-    }
+    for (int rep = 0; rep < t.repeats(); ++rep)
+        vt_call(c->vcyc32, [&](auto tag) {
+            using VT = std::remove_pointer_t<decltype(tag)>;
+            if (prec == HDG_MIXED)
+                hdg::launch_sweep<__hip_bfloat16, VT>(c->m, c->n_facet, nb, c->T16, c->nbr, vt<VT>(x), vt<VT>(z0), qc,
+                                                      c->facet_vert, cf, vt<VT>(y), s, c->rhs_block);
+            else
+                hdg::launch_sweep<double, VT>(c->m, c->n_facet, nb, c->T64, c->nbr, vt<VT>(x), vt<VT>(z0), qc,
+                                              c->facet_vert, cf, vt<VT>(y), s, c->rhs_block);
+        });
     check_launch();
 }
 
@@ -227,6 +257,38 @@ double *p1_vcycle(hdg_ctx *c, int l, int nb, hipStream_t s) {
     return x;
 }
 
+// z0 = omega D^-1 r (the first sweep from zero); with scale the input is r / scale, also written to rs
+// rc (may be null): copy of the scaled input in the V-cycle's vector type
+void jacobi0(hdg_ctx *c, int nb, int prec, const double *r, const double *scale, double *rs, double *rc,
+             double *z0, hipStream_t s) {
+    vt2_call(c->vin32, c->vcyc32, [&](auto tr, auto tz) {
+        using RT = std::remove_pointer_t<decltype(tr)>;
+        using ZT = std::remove_pointer_t<decltype(tz)>;
+        if (prec == HDG_MIXED)
+            hdg::launch_jacobi0<float, RT, ZT>(c->m, c->n_facet, nb, c->Dw32, vt<RT>(r), scale, vt<RT>(rs),
+                                               vt<ZT>(rc), vt<ZT>(z0), s);
+        else
+            hdg::launch_jacobi0<double, RT, ZT>(c->m, c->n_facet, nb, c->Dw64, vt<RT>(r), scale, vt<RT>(rs),
+                                                vt<ZT>(rc), vt<ZT>(z0), s);
+    });
+}
+// first kernel of a V-cycle: z0 = omega D^-1 r; returns the right-hand side the cycle's
+// residuals use (r itself, or its copy in the V-cycle's type when the two differ)
+const double *vcycle_start(hdg_ctx *c, int nb, int prec, const double *r, const double *scale, hipStream_t s) {
+    double *rs = scale ? const_cast<double *>(r) : nullptr;
+    const bool copy = c->vcyc32 != c->vin32;
+    jacobi0(c, nb, prec, r, scale, rs, copy ? c->vrc : nullptr, c->vz0, s);
+    return copy ? c->vrc : r;
+}
+
+// pi^T of a trace residual onto the finest P1 level (upwind)
+void restrict_p1(hdg_ctx *c, int nb, const double *res, double *rc, hipStream_t s) {
+    vt_call(c->vcyc32, [&](auto tag) {
+        using VT = std::remove_pointer_t<decltype(tag)>;
+        hdg::launch_restrict_trace<VT>(c->p, c->n_vert, nb, c->vf_row, c->vf_col, vt<VT>(res), rc, s);
+    });
+}
+
 // One RT0 geometric-multigrid V-cycle on level l (input rt[l].b, Lax-Friedrichs
 // coarse problem); returns the buffer holding the result.  rt_nu additive
 // vertex-patch steps from zero, residual, restriction P^T, recursion,
@@ -258,9 +320,15 @@ double *rt_vcycle(hdg_ctx *c, int l, int nb, hipStream_t s) {
 // Lax-Friedrichs coarse correction: out = cur + pi V_RT(pi^T res)
 void lf_coarse(hdg_ctx *c, int nb, const double *res, const double *cur, double *out, hipStream_t s) {
     const int L = (int)c->rt.size() - 1;
-    hdg::launch_lf_restrict(c->m, c->n_facet, nb, c->lf_pw, c->lf_rrow, c->lf_rcol, res, c->rt[L].b, s);
+    vt_call(c->vcyc32, [&](auto tag) {
+        using VT = std::remove_pointer_t<decltype(tag)>;
+        hdg::launch_lf_restrict<VT>(c->m, c->n_facet, nb, c->lf_pw, c->lf_rrow, c->lf_rcol, vt<VT>(res), c->rt[L].b, s);
+    });
     const double *xr = rt_vcycle(c, L, nb, s);
-    hdg::launch_lf_prolong(c->m, c->n_facet, nb, c->lf_pw, c->nbr, xr, cur, out, s);
+    vt_call(c->vcyc32, [&](auto tag) {
+        using VT = std::remove_pointer_t<decltype(tag)>;
+        hdg::launch_lf_prolong<VT>(c->m, c->n_facet, nb, c->lf_pw, c->nbr, xr, vt<VT>(cur), vt<VT>(out), s);
+    });
 }
 
 // z = V(r): Alg. twolevel_vcycle from a zero initial guess.  With scale != null
@@ -268,11 +336,7 @@ void lf_coarse(hdg_ctx *c, int nb, const double *res, const double *cur, double 
 // FGMRES basis vector is scaled by its first reader).
 void vcycle_bj(hdg_ctx *c, int nb, int prec, const double *r, double *z, hipStream_t s,
                const double *scale = nullptr) {
-    double *rs = scale ? const_cast<double *>(r) : nullptr;
-    if (prec == HDG_MIXED)
-        hdg::launch_jacobi0<float>(c->m, c->n_facet, nb, c->Dw32, r, scale, rs, c->vz0, s);
-    else
-        hdg::launch_jacobi0<double>(c->m, c->n_facet, nb, c->Dw64, r, scale, rs, c->vz0, s);
+    const double *rb = vcycle_start(c, nb, prec, r, scale, s);
     double *bufs[2] = {c->vx, c->vx2};
     int bi = 0;
     double *cur = c->vz0;  // first sweep from zero gives omega D^-1 r exactly
@@ -282,7 +346,7 @@ void vcycle_bj(hdg_ctx *c, int nb, int prec, const double *r, double *z, hipStre
         op_sweep(c, nb, prec, cur, c->vz0, nullptr, out, s, bj_coef(c));
         cur = out;
     }
-    op_apply(c, nb, prec, cur, r, c->vres, s, HDG_KERNEL_RESIDUAL);
+    op_resid_v(c, nb, prec, cur, rb, c->vres, s);
     const double *xl = nullptr;   // P1 correction, prolonged inside the first post-sweep (upwind)
     if (c->flux == HDG_FLUX_LF) {
         double *out = cur == c->vx ? c->vx2 : c->vx;
@@ -290,7 +354,7 @@ void vcycle_bj(hdg_ctx *c, int nb, int prec, const double *r, double *z, hipStre
         cur = out;
     } else {
         const int L = (int)c->lev.size() - 1;
-        hdg::launch_restrict_trace(c->p, c->n_vert, nb, c->vf_row, c->vf_col, c->vres, c->lev[L].b, s);
+        restrict_p1(c, nb, c->vres, c->lev[L].b, s);
         xl = p1_vcycle(c, L, nb, s);
     }
     for (int k = 0; k < c->opt.nu_post; ++k) {
@@ -311,13 +375,6 @@ void vcycle_bj(hdg_ctx *c, int nb, int prec, const double *r, double *z, hipStre
     check_launch();
 }
 
-void jacobi0(hdg_ctx *c, int nb, int prec, const double *r, const double *scale, double *rs, double *z0,
-             hipStream_t s) {
-    if (prec == HDG_MIXED)
-        hdg::launch_jacobi0<float>(c->m, c->n_facet, nb, c->Dw32, r, scale, rs, z0, s);
-    else
-        hdg::launch_jacobi0<double>(c->m, c->n_facet, nb, c->Dw64, r, scale, rs, z0, s);
-}
 
 // The same V-cycle with the learned smoother: every smoothing step is the
 // block-Jacobi correction u = omega D^-1 (r - S x) (the sweep kernel returns
@@ -326,16 +383,18 @@ void jacobi0(hdg_ctx *c, int nb, int prec, const double *r, const double *scale,
 // x += pi x_P1 rides in the first post-smoothing step.
 void vcycle_mlp(hdg_ctx *c, int nb, int prec, const double *r, double *z, hipStream_t s,
                 const double *scale = nullptr) {
-    double *rs = scale ? const_cast<double *>(r) : nullptr;
     const short *W1b = c->mlp_wb, *W2b = c->mlp_wb + c->mlp_n1;
-    jacobi0(c, nb, prec, r, scale, rs, c->vz0, s);
+    const double *rb = vcycle_start(c, nb, prec, r, scale, s);
     // x alternates between vx and vx2; the correction goes to vres
     double *x = c->vx, *other = c->vx2;
     auto learned = [&](const double *u, const double *xi, const double *qc, double *out) {
         Timed t(c, HDG_KERNEL_MLP, prec, s, nb);
         for (int rep = 0; rep < t.repeats(); ++rep)
-            hdg::launch_mlp_smooth(c->p, c->n_facet, nb, c->mlp_spl, u, xi, qc, c->facet_vert, c->nbr, c->prev, W1b,
-                                   W2b, out, s);
+            vt_call(c->vcyc32, [&](auto tag) {
+                using VT = std::remove_pointer_t<decltype(tag)>;
+                hdg::launch_mlp_smooth<VT>(c->p, c->n_facet, nb, c->mlp_spl, vt<VT>(u), vt<VT>(xi), qc, c->facet_vert,
+                                           c->nbr, c->prev, W1b, W2b, vt<VT>(out), s);
+            });
     };
     learned(c->vz0, nullptr, nullptr, x);
     auto step = [&](const double *qc, double *out) {
@@ -348,9 +407,9 @@ void vcycle_mlp(hdg_ctx *c, int nb, int prec, const double *r, double *z, hipStr
         }
     };
     for (int k = 1; k < c->opt.nu_pre; ++k) step(nullptr, other);
-    op_apply(c, nb, prec, x, r, c->vres, s, HDG_KERNEL_RESIDUAL);
+    op_resid_v(c, nb, prec, x, rb, c->vres, s);
     const int L = (int)c->lev.size() - 1;
-    hdg::launch_restrict_trace(c->p, c->n_vert, nb, c->vf_row, c->vf_col, c->vres, c->lev[L].b, s);
+    restrict_p1(c, nb, c->vres, c->lev[L].b, s);
     const double *xl = p1_vcycle(c, L, nb, s);
     for (int k = 0; k < c->opt.nu_post; ++k) step(k == 0 ? xl : nullptr, k == c->opt.nu_post - 1 ? z : other);
     check_launch();
@@ -366,8 +425,7 @@ void vcycle_mlp(hdg_ctx *c, int nb, int prec, const double *r, double *z, hipStr
 // next sweep reads z0 with the factor folded into its coefficients.
 void vcycle_cheb(hdg_ctx *c, int nb, int prec, const double *r, double *z, hipStream_t s,
                  const double *scale = nullptr) {
-    double *rs = scale ? const_cast<double *>(r) : nullptr;
-    jacobi0(c, nb, prec, r, scale, rs, c->vz0, s);
+    const double *rb = vcycle_start(c, nb, prec, r, scale, s);
     const double w = c->opt.omega, lo = 0.1 * c->cheb_lmax, hi = 1.1 * c->cheb_lmax;
     const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
     struct Ref {
@@ -396,10 +454,13 @@ void vcycle_cheb(hdg_ctx *c, int nb, int prec, const double *r, double *z, hipSt
     }
     const int64_t n = (int64_t)c->n_facet * c->m * nb;
     if (x.sc != 1.0) {
-        hdg::launch_lin3(n, x.sc, x.p, 0.0, nullptr, 0.0, nullptr, c->vx, s);
+        vt_call(c->vcyc32, [&](auto tag) {
+            using VT = std::remove_pointer_t<decltype(tag)>;
+            hdg::launch_lin3<VT>(n, x.sc, vt<VT>(x.p), 0.0, nullptr, 0.0, nullptr, vt<VT>(c->vx), s);
+        });
         x = Ref{c->vx, 1.0, nullptr};
     }
-    op_apply(c, nb, prec, x.p, r, c->vres, s, HDG_KERNEL_RESIDUAL);
+    op_resid_v(c, nb, prec, x.p, rb, c->vres, s);
     if (c->flux == HDG_FLUX_LF) {
         // post-smoothing from x + pi x_RT, formed in a work buffer
         double *out = x.p == c->vx ? c->vx2 : c->vx;
@@ -408,7 +469,7 @@ void vcycle_cheb(hdg_ctx *c, int nb, int prec, const double *r, double *z, hipSt
     } else {
         // post-smoothing from x + pi x_P1 (the prolongation rides in the sweeps)
         const int L = (int)c->lev.size() - 1;
-        hdg::launch_restrict_trace(c->p, c->n_vert, nb, c->vf_row, c->vf_col, c->vres, c->lev[L].b, s);
+        restrict_p1(c, nb, c->vres, c->lev[L].b, s);
         x.qc = p1_vcycle(c, L, nb, s);
     }
     xp = Ref{nullptr, 0.0, nullptr};
@@ -450,7 +511,10 @@ int64_t vec_len(const hdg_ctx *c) { return (int64_t)c->n_facet * c->m; }
 // out (device, may be null) and host (host-mapped, may be null) receive the dots
 void dots(hdg_ctx *c, int nb, int nd, const double *X, int64_t xstride, const double *y, double *out,
           hipStream_t s, double *host = nullptr) {
-    hdg::launch_dots(vec_len(c), nb, nd, X, xstride, y, c->red, out, host, s);
+    vt_call(c->kv32, [&](auto tag) {
+        using VT = std::remove_pointer_t<decltype(tag)>;
+        hdg::launch_dots<VT>(vec_len(c), nb, nd, vt<VT>(X), xstride, vt<VT>(y), c->red, out, host, s);
+    });
     check_launch();
 }
 
@@ -577,24 +641,45 @@ int solve_pcg(hdg_ctx *c, int nb, const double *rhat, double *lam_user, hdg_solv
 int solve_fgmres(hdg_ctx *c, int nb, int vc_prec, int op_prec, double inner_eta, const double *rhat,
                  double *lam, hdg_solve_info *info, hipStream_t s) {
     const int64_t n = vec_len(c);
-    const int64_t vs = n * c->opt.max_rhs;
+    const int64_t vs = n * c->opt.max_rhs;   // basis slot, in doubles
     const int R = c->opt.restart;
     const double rtol = c->opt.rtol;
+    // the inner solve of HDG_MIXED_IR (FP32 operator and V-cycle) keeps its basis and the
+    // V-cycle's vectors in FP32: half the vector traffic; lam and the true residual stay FP64
+    const bool f32 = vc_prec == HDG_MIXED && op_prec == HDG_MIXED;
+    // any solve with the mixed V-cycle keeps the V-cycle's vectors and the Z basis in FP32
+    const bool z32 = vc_prec == HDG_MIXED;
+    struct Vec32Off {   // FP64 vectors again when the solve returns or throws
+        hdg_ctx *c;
+        ~Vec32Off() { c->vcyc32 = c->vin32 = c->kv32 = false; }
+    } vec32_off{c};
+    auto set32 = [&](bool on) {
+        c->vcyc32 = on && z32;
+        c->vin32 = c->kv32 = on && f32;
+    };
+    const int64_t vstride = f32 ? 2 * vs : vs;   // V basis stride in elements of its type
     std::vector<double> rel(nb, 0.0), cyc0(nb, 0.0);
     int its = 0, cycles = 0, fallbacks = 0;
     auto done_info = [&](int status) {
+        set32(false);
         fill_info(info, nb, its, cycles, rel, status);
         if (info)
             for (int r = 0; r < nb; ++r) info[r].fallbacks = fallbacks;
         return status;
     };
     while (true) {
-        true_residual(c, nb, rhat, lam, c->kV, rel, s);
+        set32(false);
+        true_residual(c, nb, rhat, lam, f32 ? c->kr : c->kV, rel, s);
+        if (f32) {
+            hdg::launch_to_f32(n * nb, c->kr, reinterpret_cast<float *>(c->kV), s);
+            check_launch();
+        }
         if (any_nonfinite(rel)) return done_info(HDG_EBREAKDOWN);
         if (all_below(rel, rtol)) return done_info(HDG_OK);
         if (its >= c->opt.maxit) return done_info(HDG_ENOTCONV);
         ++cycles;
         cyc0 = rel;
+        set32(true);
         hdg::launch_gmres_start(nb, R, scal(c, SC_RR), c->gm, scal(c, SC_BETA), s);
         int k = 0, pending = -1;
         auto converged = [&](const double *h) {
@@ -613,10 +698,13 @@ int solve_fgmres(hdg_ctx *c, int nb, int vc_prec, int op_prec, double inner_eta,
             const double *vscale = (j == 0) ? scal(c, SC_BETA) : scal(c, SC_HN);
             run_step(c, graph_key(2 + (c->use_mlp_now ? 1 : 0), nb, vc_prec * 4 + op_prec, j), s, [&](hipStream_t st) {
                 vcycle(c, nb, vc_prec, Vj, Zj, st, vscale);
-                op_apply(c, nb, op_prec, Zj, nullptr, Vn, st, HDG_KERNEL_APPLY);
-                dots(c, nb, j + 1, c->kV, vs, Vn, c->hcol, st);
-                hdg::launch_gs_norm_givens(n, nb, j + 1, c->hcol, c->kV, vs, Vn, c->red, scal(c, SC_HN), j, R, c->gm,
-                                           c->dbn, lag_dev(c, slot), st);
+                op_apply(c, nb, op_prec, Zj, nullptr, Vn, st, HDG_KERNEL_APPLY, c->vcyc32, c->kv32);
+                dots(c, nb, j + 1, c->kV, vstride, Vn, c->hcol, st);
+                vt_call(c->kv32, [&](auto tag) {
+                    using VT = std::remove_pointer_t<decltype(tag)>;
+                    hdg::launch_gs_norm_givens<VT>(n, nb, j + 1, c->hcol, vt<VT>(c->kV), vstride, vt<VT>(Vn), c->red,
+                                                   scal(c, SC_HN), j, R, c->gm, c->dbn, lag_dev(c, slot), st);
+                });
                 check_launch();
             });
             mark_lag(c, slot, s);
@@ -644,7 +732,10 @@ int solve_fgmres(hdg_ctx *c, int nb, int vc_prec, int op_prec, double inner_eta,
             pending = slot;
         }
         hdg::launch_gmres_solve(nb, k, R, c->gm, c->hy, s);
-        hdg::launch_lincomb(n, nb, k, c->hy, c->kZ, vs, lam, s);
+        vt_call(c->vcyc32, [&](auto tag) {
+            using VT = std::remove_pointer_t<decltype(tag)>;
+            hdg::launch_lincomb<VT>(n, nb, k, c->hy, vt<VT>(c->kZ), c->vcyc32 ? 2 * vs : vs, lam, s);
+        });
         check_launch();
     }
 }
@@ -689,11 +780,11 @@ void estimate_lambda_max(hdg_ctx *c) {
     double lam = 0.0;
     for (int it = 0; it < 20; ++it) {
         op_apply(c, 1, HDG_FP64, c->vx, nullptr, c->vres, s, HDG_KERNEL_APPLY);
-        jacobi0(c, 1, HDG_FP64, c->vres, nullptr, nullptr, c->vx2, s);   // omega D^-1 S v
+        jacobi0(c, 1, HDG_FP64, c->vres, nullptr, nullptr, nullptr, c->vx2, s);   // omega D^-1 S v
         const double *h = dots_now(c, 1, c->vx2, c->vx2, scal(c, SC_RR), s);
         lam = std::sqrt(h[0]) / c->opt.omega;
         HDG_REQUIRE(std::isfinite(lam) && lam > 0, "eigenvalue estimate of D^-1 S failed");
-        hdg::launch_lin3(n, 1.0 / (lam * c->opt.omega), c->vx2, 0.0, nullptr, 0.0, nullptr, c->vx, s);
+        hdg::launch_lin3<double>(n, 1.0 / (lam * c->opt.omega), c->vx2, 0.0, nullptr, 0.0, nullptr, c->vx, s);
         check_launch();
     }
     HDG_HIP_CHECK(hipStreamSynchronize(s));
@@ -992,6 +1083,7 @@ void setup_impl(const hdg_mesh *levels, int nlev, const int32_t *const *parents,
     c->vx = dev_alloc<double>(c, vl);
     c->vx2 = dev_alloc<double>(c, vl);
     c->vres = dev_alloc<double>(c, vl);
+    c->vrc = dev_alloc<double>(c, vl);
     c->kr = dev_alloc<double>(c, vl);
     c->kz = dev_alloc<double>(c, vl);
     c->kp = dev_alloc<double>(c, vl);
@@ -1257,7 +1349,7 @@ void mlp_pair(hdg_ctx *c, int nb, int coarse_its, const double *e, double *r, do
     hdg::P1LevelDev &F = c->lev[L];
     const int64_t nv = (int64_t)F.n * nb;
     op_apply(c, nb, HDG_FP64, e, nullptr, r, s, HDG_KERNEL_APPLY);
-    jacobi0(c, nb, HDG_FP64, r, nullptr, nullptr, u, s);
+    jacobi0(c, nb, HDG_FP64, r, nullptr, nullptr, nullptr, u, s);
     hdg::launch_restrict_trace(c->p, c->n_vert, nb, c->vf_row, c->vf_col, r, c->p1_keep, s);
     for (int k = 0; k < coarse_its; ++k) {
         if (k == 0)
@@ -1265,12 +1357,12 @@ void mlp_pair(hdg_ctx *c, int nb, int coarse_its, const double *e, double *r, do
         else
             hdg::launch_p1_resid(F.n, F.w, nb, F.col, F.val, F.diag, c->p1_keep, c->p1_acc, F.b, s);
         const double *xl = p1_vcycle(c, L, nb, s);
-        hdg::launch_lin3(nv, 1.0, xl, k == 0 ? 0.0 : 1.0, k == 0 ? nullptr : c->p1_acc, 0.0, nullptr, c->p1_acc, s);
+        hdg::launch_lin3<double>(nv, 1.0, xl, k == 0 ? 0.0 : 1.0, k == 0 ? nullptr : c->p1_acc, 0.0, nullptr, c->p1_acc, s);
     }
     const int64_t n = vec_len(c) * nb;
-    hdg::launch_lin3(n, 1.0, e, -1.0, u, 0.0, nullptr, t, s);
+    hdg::launch_lin3<double>(n, 1.0, e, -1.0, u, 0.0, nullptr, t, s);
     if (coarse_its > 0) {
-        hdg::launch_lin3(nv, -1.0, c->p1_acc, 0.0, nullptr, 0.0, nullptr, c->p1_acc, s);
+        hdg::launch_lin3<double>(nv, -1.0, c->p1_acc, 0.0, nullptr, 0.0, nullptr, c->p1_acc, s);
         hdg::launch_prolong_trace(c->p, c->n_facet, nb, c->facet_vert, c->p1_acc, t, s);
     }
     check_launch();
@@ -1412,7 +1504,7 @@ extern "C" int hdg_mlp_train(hdg_ctx *c, int32_t nb, const double *e0, int32_t c
             if (k + 1 < cycles) {
                 // next error: e <- e - V(S e) with the plain block-Jacobi cycle (r = S e is in mlp_R)
                 vcycle_bj(c, nb, HDG_FP64, c->mlp_R, c->mlp_U, s);
-                hdg::launch_lin3(n, 1.0, c->mlp_E, -1.0, c->mlp_U, 0.0, nullptr, c->mlp_E, s);
+                hdg::launch_lin3<double>(n, 1.0, c->mlp_E, -1.0, c->mlp_U, 0.0, nullptr, c->mlp_E, s);
                 check_launch();
             }
         }

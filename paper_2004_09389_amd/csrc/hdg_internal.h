@@ -206,6 +206,7 @@ struct hdg_ctx {
 
     // trace work vectors [n_facet][m][max_rhs]
     double *vz0 = nullptr, *vx = nullptr, *vx2 = nullptr, *vres = nullptr;
+    double *vrc = nullptr;                      // the V-cycle's input in FP32 (mixed solves)
     // Krylov work
     double *kr = nullptr, *kz = nullptr, *kp = nullptr, *kw = nullptr, *klam = nullptr;
     double *kV = nullptr, *kZ = nullptr;      // FGMRES bases [(restart+1)][vec], [restart][vec]
@@ -235,6 +236,10 @@ struct hdg_ctx {
     double *mlp_U = nullptr, *mlp_T = nullptr;   // training: features source u and targets t
     double *p1_keep = nullptr, *p1_acc = nullptr;  // finest-P1 vectors for the training targets
     bool use_mlp_now = false;             // smoother of the current V-cycles (fallback clears it)
+    // FP32 trace vectors (the same buffers, half used): vcyc32 for the V-cycle's work vectors
+    // and its output z (the FGMRES Z basis), vin32 for the V-cycle's input r, kv32 for the
+    // FGMRES V basis.  Mixed solves set vcyc32; the inner solve of HDG_MIXED_IR sets all three.
+    bool vcyc32 = false, vin32 = false, kv32 = false;
 
     // timing
     struct PendingEvent {

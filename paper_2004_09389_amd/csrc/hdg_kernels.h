@@ -1,6 +1,8 @@
 // Launch wrappers of the device kernels (see hdg_kernels.hip).
 #pragma once
 
+#include <type_traits>
+
 #include "hdg_internal.h"
 
 namespace hdg {
@@ -16,33 +18,62 @@ __device__ __forceinline__ int xcd_block() {
     return (blockIdx.x % N_XCD) * per + blockIdx.x / N_XCD;
 }
 
-// Trace vectors are [facet][node][rhs].  With one right-hand side the M
-// values of a facet are contiguous and (M even) 16-byte aligned: load and
-// store them as pairs.  base = facet * M * nb + rhs.
+// Trace vectors are [facet][node][rhs], stored as double (FP64 paths) or
+// float (the FP32 inner solve of HDG_MIXED_IR); values are converted to and
+// from double in registers.  With one right-hand side the M values of a facet
+// are contiguous: load and store them as 16-byte (or 8-byte) groups when M
+// allows.  base = facet * M * nb + rhs.
 typedef double trace_dbl2_t __attribute__((ext_vector_type(2)));
-template <int M, bool NB1>
-__device__ __forceinline__ void load_trace(const double *__restrict__ v, size_t base, int nb, double (&d)[M]) {
-    if constexpr (NB1 && M % 2 == 0) {
+typedef float trace_flt2_t __attribute__((ext_vector_type(2)));
+typedef float trace_flt4_t __attribute__((ext_vector_type(4)));
+template <int M, bool NB1, typename T>
+__device__ __forceinline__ void load_trace(const T *__restrict__ v, size_t base, int nb, double (&d)[M]) {
+    if constexpr (NB1 && std::is_same<T, double>::value && M % 2 == 0) {
 #pragma unroll
         for (int j = 0; j < M; j += 2) {
             const trace_dbl2_t a = *reinterpret_cast<const trace_dbl2_t *>(v + base + j);
             d[j] = a.x;
             d[j + 1] = a.y;
         }
+    } else if constexpr (NB1 && std::is_same<T, float>::value && M % 4 == 0) {
+#pragma unroll
+        for (int j = 0; j < M; j += 4) {
+            const trace_flt4_t a = *reinterpret_cast<const trace_flt4_t *>(v + base + j);
+            d[j] = a.x;
+            d[j + 1] = a.y;
+            d[j + 2] = a.z;
+            d[j + 3] = a.w;
+        }
+    } else if constexpr (NB1 && std::is_same<T, float>::value && M % 2 == 0) {
+#pragma unroll
+        for (int j = 0; j < M; j += 2) {
+            const trace_flt2_t a = *reinterpret_cast<const trace_flt2_t *>(v + base + j);
+            d[j] = a.x;
+            d[j + 1] = a.y;
+        }
     } else {
 #pragma unroll
-        for (int j = 0; j < M; ++j) d[j] = v[base + (size_t)(NB1 ? j : j * nb)];
+        for (int j = 0; j < M; ++j) d[j] = (double)v[base + (size_t)(NB1 ? j : j * nb)];
     }
 }
-template <int M, bool NB1>
-__device__ __forceinline__ void store_trace(double *__restrict__ v, size_t base, int nb, const double (&d)[M]) {
-    if constexpr (NB1 && M % 2 == 0) {
+template <int M, bool NB1, typename T>
+__device__ __forceinline__ void store_trace(T *__restrict__ v, size_t base, int nb, const double (&d)[M]) {
+    if constexpr (NB1 && std::is_same<T, double>::value && M % 2 == 0) {
 #pragma unroll
         for (int j = 0; j < M; j += 2)
             *reinterpret_cast<trace_dbl2_t *>(v + base + j) = trace_dbl2_t{d[j], d[j + 1]};
+    } else if constexpr (NB1 && std::is_same<T, float>::value && M % 4 == 0) {
+#pragma unroll
+        for (int j = 0; j < M; j += 4)
+            *reinterpret_cast<trace_flt4_t *>(v + base + j) =
+                trace_flt4_t{(float)d[j], (float)d[j + 1], (float)d[j + 2], (float)d[j + 3]};
+    } else if constexpr (NB1 && std::is_same<T, float>::value && M % 2 == 0) {
+#pragma unroll
+        for (int j = 0; j < M; j += 2)
+            *reinterpret_cast<trace_flt2_t *>(v + base + j) = trace_flt2_t{(float)d[j], (float)d[j + 1]};
     } else {
 #pragma unroll
-        for (int j = 0; j < M; ++j) v[base + (size_t)(NB1 ? j : j * nb)] = d[j];
+        for (int j = 0; j < M; ++j) v[base + (size_t)(NB1 ? j : j * nb)] = (T)d[j];
     }
 }
 
@@ -64,7 +95,8 @@ __device__ __forceinline__ double p1_node(int k, double q0, double q1) {
 // the correction alone: (-omega, 1, 1, 0); Chebyshev steps: see vcycle_cheb.
 struct SweepCoef {
     double a0, a1, a3, a2;
-    const double *xprev, *qcprev;
+    const void *xprev;        // trace vector of the sweep's vector type
+    const double *qcprev;
 };
 // the sweep's output combination with its rounding fixed (every launch shape
 // produces the same bits)
@@ -94,17 +126,24 @@ void launch_facet_rows(int p, int nu, int ne, int nk, const double *Sloc, const 
                        int *nbr, int8_t *prev, int *err, hipStream_t s);
 
 // facet-row kernels: M = trace unknowns per facet (2, 3, 4, 6 or 8)
-template <typename MT>
-void launch_trace_apply(int M, int ne, int nb, const MT *S, const int *nbr, const double *x, const double *b,
-                        double *y, hipStream_t s, int rhs_block = 1);
-template <typename MT>
-void launch_jacobi0(int M, int ne, int nb, const MT *Dw, const double *r, const double *scale, double *rs,
-                    double *z0, hipStream_t s);
-template <typename MT>
-void launch_sweep(int M, int ne, int nb, const MT *T, const int *nbr, const double *x, const double *z0,
-                  const double *qc, const int *fvert, SweepCoef cf, double *y, hipStream_t s, int rhs_block = 1);
-void launch_restrict_trace(int p, int nv, int nb, const int *vf_row, const int *vf_col, const double *res,
-                           double *rc, hipStream_t s);
+// VT: element type of the trace vectors (double, or float in the FP32 inner solve)
+// y = S x or y = b - S x; x may be held in another type than b and y
+template <typename MT, typename XT, typename YT>
+void launch_trace_apply(int M, int ne, int nb, const MT *S, const int *nbr, const XT *x, const YT *b, YT *y,
+                        hipStream_t s, int rhs_block = 1);
+// z0 = omega D^-1 r (r / scale, written back to rs, when scale is given); rc (may be null)
+// receives the scaled input in z0's type
+template <typename MT, typename RT, typename ZT>
+void launch_jacobi0(int M, int ne, int nb, const MT *Dw, const RT *r, const double *scale, RT *rs, ZT *rc, ZT *z0,
+                    hipStream_t s);
+template <typename MT, typename VT>
+void launch_sweep(int M, int ne, int nb, const MT *T, const int *nbr, const VT *x, const VT *z0, const double *qc,
+                  const int *fvert, SweepCoef cf, VT *y, hipStream_t s, int rhs_block = 1);
+template <typename VT>
+void launch_restrict_trace(int p, int nv, int nb, const int *vf_row, const int *vf_col, const VT *res, double *rc,
+                           hipStream_t s);
+// FP64 -> FP32 copy of a trace vector
+void launch_to_f32(int64_t n, const double *src, float *dst, hipStream_t s);
 
 void launch_p1_first(int n, int nb, const double *dinv, double omega, const double *b, double *x, hipStream_t s);
 void launch_p1_pre2(int n, int W, int nb, const int *col, const double *val, const double *diag,
@@ -125,17 +164,20 @@ void launch_recover(int p, int nu, int nk, int nb, const double *Ar, const doubl
                     const int8_t *cell_rev, const double *rc, const double *lam, double *q, hipStream_t s);
 
 int red_grid(int64_t len, int nb);
-void launch_dots(int64_t len, int nb, int nd, const double *X, int64_t xstride, const double *y, double *partial,
+template <typename VT>
+void launch_dots(int64_t len, int nb, int nd, const VT *X, int64_t xstride, const VT *y, double *partial,
                  double *out, double *host, hipStream_t s);
-void launch_gs_norm_givens(int64_t len, int nb, int nd, const double *h, const double *V, int64_t vstride,
-                           double *w, double *partial, double *hn, int j, int restart, double *gm,
-                           const double *bnorm, double *resid_host, hipStream_t s);
+template <typename VT>
+void launch_gs_norm_givens(int64_t len, int nb, int nd, const double *h, const VT *V, int64_t vstride, VT *w,
+                           double *partial, double *hn, int j, int restart, double *gm, const double *bnorm,
+                           double *resid_host, hipStream_t s);
 void launch_pcg_update_norm(int64_t len, int nb, const double *num, const double *den, const double *p,
                             const double *w, double *x, double *res, double *partial, double *rr_host,
                             hipStream_t s);
 void launch_pcg_dir(int64_t n, int nb, const double *num, const double *den, const double *z, double *p,
                     hipStream_t s);
-void launch_lincomb(int64_t n, int nb, int nd, const double *y, const double *Z, int64_t zstride, double *x,
+template <typename VT>
+void launch_lincomb(int64_t n, int nb, int nd, const double *y, const VT *Z, int64_t zstride, double *x,
                     hipStream_t s);
 void launch_copy(int64_t n, const double *src, double *dst, hipStream_t s);
 void launch_gmres_start(int nb, int restart, const double *beta2, double *gm, double *beta, hipStream_t s);
@@ -145,9 +187,10 @@ void launch_sqrt(int nb, const double *in, double *out, hipStream_t s);
 // learned smoother (hdg_mlp.hip)
 int mlp_k1p(int p);
 int mlp_grad_waves(int ne, int nb);
-void launch_mlp_smooth(int p, int ne, int nb, int spl, const double *u, const double *xi, const double *qc,
+template <typename VT>
+void launch_mlp_smooth(int p, int ne, int nb, int spl, const VT *u, const VT *xi, const double *qc,
                        const int *fvert, const int *nbr, const int8_t *prev, const short *W1b, const short *W2b,
-                       double *xo, hipStream_t s);
+                       VT *xo, hipStream_t s);
 void launch_mlp_grad(int p, int ne, int nb, const double *u, const double *t, const int *nbr, const int8_t *prev,
                      const short *W1b, const short *W2b, float *pdW1, float *pdW2, float *ploss, float *g,
                      double *loss, hipStream_t s);
@@ -155,7 +198,8 @@ void launch_adam(int p, const float *g, float gscale, float *w, float *m1, float
                  short *wb, hipStream_t s);
 void launch_to_bf16(int n, const float *w, short *wb, hipStream_t s);
 void launch_prolong_trace(int p, int ne, int nb, const int *fvert, const double *qc, double *x, hipStream_t s);
-void launch_lin3(int64_t n, double a, const double *x, double b, const double *y, double c, const double *z,
-                 double *out, hipStream_t s);
+template <typename VT>
+void launch_lin3(int64_t n, double a, const VT *x, double b, const VT *y, double c, const VT *z, VT *out,
+                 hipStream_t s);
 
 }  // namespace hdg

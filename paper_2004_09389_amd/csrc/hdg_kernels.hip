@@ -430,10 +430,10 @@ __global__ void k_facet_rows(int ne, int nk, const double *__restrict__ Sloc, co
 // five facets of its block row and produces all m rows, so every matrix
 // entry is read exactly once per apply and there are no write conflicts.
 
-template <int M, typename MT, bool NB1>
+template <int M, typename MT, typename XT, typename YT, bool NB1>
 __global__ __launch_bounds__(256) void k_trace_apply(int ne, int nb, const MT *__restrict__ S,
-                                                     const int *__restrict__ nbr, const double *__restrict__ x,
-                                                     const double *__restrict__ b, double *__restrict__ y) {
+                                                     const int *__restrict__ nbr, const XT *__restrict__ x,
+                                                     const YT *__restrict__ b, YT *__restrict__ y) {
     using AT = typename Acc<MT>::type;
     constexpr int V = Wide<MT>::V, C = 5 * M * M, G = padded(C, V) / V;
     const int t = xcd_block() * blockDim.x + threadIdx.x;
@@ -479,10 +479,11 @@ __global__ __launch_bounds__(256) void k_trace_apply(int ne, int nb, const MT *_
 // z0 = omega D^-1 r  (first sweep from a zero guess).  With scale != nullptr
 // the input is r / scale[rhs], and the scaled input is also written to rs
 // (normalisation of a Krylov basis vector fused into its first use).
-template <int M, typename MT>
+// rc (may be null): a copy of the scaled input in z0's type
+template <int M, typename MT, typename RT, typename ZT>
 __global__ __launch_bounds__(256) void k_jacobi0(int ne, int nb, const MT *__restrict__ Dw,
-                                                 const double *__restrict__ r, const double *__restrict__ scale,
-                                                 double *__restrict__ rs, double *__restrict__ z0) {
+                                                 const RT *__restrict__ r, const double *__restrict__ scale,
+                                                 RT *__restrict__ rs, ZT *__restrict__ rc, ZT *__restrict__ z0) {
     using AT = typename Acc<MT>::type;
     constexpr int V = Wide<MT>::V, C = M * M, G = padded(C, V) / V;
     const int t = xcd_block() * blockDim.x + threadIdx.x;
@@ -494,8 +495,11 @@ __global__ __launch_bounds__(256) void k_jacobi0(int ne, int nb, const MT *__res
 #pragma unroll
     for (int k = 0; k < M; ++k) {
         const size_t o = ((size_t)e * M + k) * nb + rr;
-        rv[k] = r[o] * sc;
-        if (scale) rs[o] = rv[k];
+        const RT v = (RT)((double)r[o] * sc);   // the scaled vector as stored
+        if (scale) rs[o] = v;
+        const ZT vz = (ZT)v;                    // ... and as the V-cycle reads it
+        if (rc) rc[o] = vz;
+        rv[k] = (double)vz;
     }
     AT acc[M];
 #pragma unroll
@@ -511,19 +515,19 @@ __global__ __launch_bounds__(256) void k_jacobi0(int ne, int nb, const MT *__res
         }
     }
 #pragma unroll
-    for (int a = 0; a < M; ++a) z0[((size_t)e * M + a) * nb + rr] = (double)acc[a];
+    for (int a = 0; a < M; ++a) z0[((size_t)e * M + a) * nb + rr] = (ZT)(double)acc[a];
 }
 
 // Block-Jacobi sweep  y = x + omega D^-1 (r - S x) = (1 - omega) x + z0 - sum_j T_j x_j,
 // with T_j = omega D^-1 S_j over the four off-diagonal slots and z0 = omega D^-1 r.
 // With qc != nullptr the input is x + pi qc (prolongation of the P1 correction
 // fused in, pi the injection of a P1 function onto the trace nodes).
-template <int M, typename MT, bool NB1>
+template <int M, typename MT, typename VT, bool NB1>
 __global__ __launch_bounds__(256) void k_sweep(int ne, int nb, const MT *__restrict__ T,
-                                               const int *__restrict__ nbr, const double *__restrict__ x,
-                                               const double *__restrict__ z0, const double *__restrict__ qc,
+                                               const int *__restrict__ nbr, const VT *__restrict__ x,
+                                               const VT *__restrict__ z0, const double *__restrict__ qc,
                                                const int *__restrict__ fvert, SweepCoef cf,
-                                               double *__restrict__ y) {
+                                               VT *__restrict__ y) {
     using AT = typename Acc<MT>::type;
     constexpr int P = M - 1;
     constexpr int V = Wide<MT>::V, C = 4 * M * M, G = padded(C, V) / V;
@@ -568,7 +572,7 @@ __global__ __launch_bounds__(256) void k_sweep(int ne, int nb, const MT *__restr
     for (int a = 0; a < M; ++a) out[a] = sweep_combine(cf, xv[0][a], zv[a], (double)acc[a]);
     if (cf.xprev) {
         double pv[M];
-        load_trace<M, NB1>(cf.xprev, e * MB + r, nb, pv);
+        load_trace<M, NB1>(static_cast<const VT *>(cf.xprev), e * MB + r, nb, pv);
         if (cf.qcprev) {
             const double q0 = cf.qcprev[(size_t)fvert[2 * e] * nb + r], q1 = cf.qcprev[(size_t)fvert[2 * e + 1] * nb + r];
 #pragma unroll
@@ -582,9 +586,9 @@ __global__ __launch_bounds__(256) void k_sweep(int ne, int nb, const MT *__restr
 
 // Restriction pi^T of a trace residual onto the P1 vertices:
 // rc[v] = sum over facet ends at v of sum_k w_end(k) res[e][k], w_0 = 1 - k/p, w_1 = k/p.
-template <int M>
+template <int M, typename VT>
 __global__ void k_restrict_trace(int nv, int nb, const int *__restrict__ vf_row, const int *__restrict__ vf_col,
-                                 const double *__restrict__ res, double *__restrict__ rc) {
+                                 const VT *__restrict__ res, double *__restrict__ rc) {
     constexpr int P = M - 1;
     const int t = xcd_block() * blockDim.x + threadIdx.x;
     if (t >= nv * nb) return;
@@ -595,7 +599,7 @@ __global__ void k_restrict_trace(int nv, int nb, const int *__restrict__ vf_row,
 #pragma unroll
         for (int k = 0; k < M; ++k) {
             const double w = end ? (double)k / P : 1.0 - (double)k / P;
-            acc += w * res[((size_t)e * M + k) * nb + r];
+            acc += w * (double)res[((size_t)e * M + k) * nb + r];
         }
     }
     rc[(size_t)v * nb + r] = acc;
@@ -1025,8 +1029,9 @@ __device__ __forceinline__ void block_rhs_sums(double (*sh)[256], int kc, int nb
 }
 
 // partial[blk][d][r] = this block's share of sum_i X_d[i][r] y[i][r], d < nd
-__global__ __launch_bounds__(256) void k_mdot_partial(int64_t len, int nb, int nd, const double *__restrict__ X,
-                                                      int64_t xstride, const double *__restrict__ y,
+template <typename VT>
+__global__ __launch_bounds__(256) void k_mdot_partial(int64_t len, int nb, int nd, const VT *__restrict__ X,
+                                                      int64_t xstride, const VT *__restrict__ y,
                                                       double *__restrict__ partial) {
     __shared__ double sh[RED_CHUNK][256];
     const int rpb = rows_per_block(nb);
@@ -1040,10 +1045,10 @@ __global__ __launch_bounds__(256) void k_mdot_partial(int64_t len, int nb, int n
         if (rl < rpb) {
             for (int64_t i = (int64_t)blockIdx.x * rpb + rl; i < len; i += (int64_t)gridDim.x * rpb) {
                 const size_t t = (size_t)i * nb + r;
-                const double yv = y[t];
+                const double yv = (double)y[t];
 #pragma unroll
                 for (int k = 0; k < RED_CHUNK; ++k)
-                    if (k < kc) acc[k] += X[(size_t)(d0 + k) * xstride + t] * yv;
+                    if (k < kc) acc[k] += (double)X[(size_t)(d0 + k) * xstride + t] * yv;
             }
         }
 #pragma unroll
@@ -1110,9 +1115,10 @@ __device__ void givens_column(int r, int nb, int j, int restart, const double *h
 }
 
 // w -= sum_d h[d] V_d (classical Gram-Schmidt) and block partials of ||w||^2
+template <typename VT>
 __global__ __launch_bounds__(256) void k_gs_update_norm(int64_t len, int nb, int nd, const double *__restrict__ h,
-                                                        const double *__restrict__ V, int64_t vstride,
-                                                        double *__restrict__ w, double *__restrict__ partial) {
+                                                        const VT *__restrict__ V, int64_t vstride,
+                                                        VT *__restrict__ w, double *__restrict__ partial) {
     __shared__ double sh[1][256];
     const int rpb = rows_per_block(nb);
     const int tid = threadIdx.x;
@@ -1121,10 +1127,11 @@ __global__ __launch_bounds__(256) void k_gs_update_norm(int64_t len, int nb, int
     if (rl < rpb) {
         for (int64_t i = (int64_t)blockIdx.x * rpb + rl; i < len; i += (int64_t)gridDim.x * rpb) {
             const size_t t = (size_t)i * nb + r;
-            double s = w[t];
-            for (int d = 0; d < nd; ++d) s -= h[(size_t)d * nb + r] * V[(size_t)d * vstride + t];
-            w[t] = s;
-            acc += s * s;
+            double s = (double)w[t];
+            for (int d = 0; d < nd; ++d) s -= h[(size_t)d * nb + r] * (double)V[(size_t)d * vstride + t];
+            const VT sv = (VT)s;   // the norm is that of the vector as stored
+            w[t] = sv;
+            acc += (double)sv * (double)sv;
         }
     }
     sh[0][tid] = (rl < rpb) ? acc : 0.0;
@@ -1187,13 +1194,14 @@ __global__ void k_pcg_dir(int64_t n, int nb, const double *__restrict__ num, con
 }
 
 // x += sum_{d < nd} y[d][r] Z_d
-__global__ void k_lincomb(int64_t n, int nb, int nd, const double *__restrict__ y, const double *__restrict__ Z,
+template <typename VT>
+__global__ void k_lincomb(int64_t n, int nb, int nd, const double *__restrict__ y, const VT *__restrict__ Z,
                           int64_t zstride, double *__restrict__ x) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n * nb) return;
     const int r = (int)(t % nb);
     double s = x[t];
-    for (int d = 0; d < nd; ++d) s += y[(size_t)d * nb + r] * Z[(size_t)d * zstride + t];
+    for (int d = 0; d < nd; ++d) s += y[(size_t)d * nb + r] * (double)Z[(size_t)d * zstride + t];
     x[t] = s;
 }
 
@@ -1278,26 +1286,44 @@ __device__ __forceinline__ void stage_rows(MT *sm, const MT *__restrict__ S, int
     }
 }
 
-template <int RB>
-__device__ __forceinline__ void load_rb(const double *__restrict__ p, double (&d)[RB]) {
+template <int RB, typename T>
+__device__ __forceinline__ void load_rb(const T *__restrict__ p, double (&d)[RB]) {
+    if constexpr (std::is_same<T, double>::value) {
 #pragma unroll
-    for (int q = 0; q < RB; q += 2) {
-        const dbl2_t a = *reinterpret_cast<const dbl2_t *>(p + q);
-        d[q] = a.x;
-        d[q + 1] = a.y;
+        for (int q = 0; q < RB; q += 2) {
+            const dbl2_t a = *reinterpret_cast<const dbl2_t *>(p + q);
+            d[q] = a.x;
+            d[q + 1] = a.y;
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < RB; q += 4) {
+            const trace_flt4_t a = *reinterpret_cast<const trace_flt4_t *>(p + q);
+            d[q] = a.x;
+            d[q + 1] = a.y;
+            d[q + 2] = a.z;
+            d[q + 3] = a.w;
+        }
     }
 }
-template <int RB>
-__device__ __forceinline__ void store_rb(double *__restrict__ p, const double (&d)[RB]) {
+template <int RB, typename T>
+__device__ __forceinline__ void store_rb(T *__restrict__ p, const double (&d)[RB]) {
+    if constexpr (std::is_same<T, double>::value) {
 #pragma unroll
-    for (int q = 0; q < RB; q += 2) *reinterpret_cast<dbl2_t *>(p + q) = dbl2_t{d[q], d[q + 1]};
+        for (int q = 0; q < RB; q += 2) *reinterpret_cast<dbl2_t *>(p + q) = dbl2_t{d[q], d[q + 1]};
+    } else {
+#pragma unroll
+        for (int q = 0; q < RB; q += 4)
+            *reinterpret_cast<trace_flt4_t *>(p + q) =
+                trace_flt4_t{(float)d[q], (float)d[q + 1], (float)d[q + 2], (float)d[q + 3]};
+    }
 }
 
 // y = S x or y = b - S x
-template <int M, typename MT, int RB>
+template <int M, typename MT, typename XT, typename YT, int RB>
 __global__ __launch_bounds__(1024) void k_trace_apply_rb(int ne, int nb, const MT *__restrict__ S,
-                                                         const int *__restrict__ nbr, const double *__restrict__ x,
-                                                         const double *__restrict__ b, double *__restrict__ y) {
+                                                         const int *__restrict__ nbr, const XT *__restrict__ x,
+                                                         const YT *__restrict__ b, YT *__restrict__ y) {
     using AT = typename Acc<MT>::type;
     constexpr int V = Wide<MT>::V, C = 5 * M * M, G = padded(C, V) / V;
     __shared__ __attribute__((aligned(16))) MT sm[G * RB_FACETS * V];
@@ -1347,12 +1373,12 @@ __global__ __launch_bounds__(1024) void k_trace_apply_rb(int ne, int nb, const M
 }
 
 // the generalised sweep y = a0 x' + a1 z0 - a3 sum_j T_j x'_j + a2 xprev' (SweepCoef)
-template <int M, typename MT, int RB>
+template <int M, typename MT, typename VT, int RB>
 __global__ __launch_bounds__(1024) void k_sweep_rb(int ne, int nb, const MT *__restrict__ T,
-                                                   const int *__restrict__ nbr, const double *__restrict__ x,
-                                                   const double *__restrict__ z0, const double *__restrict__ qc,
+                                                   const int *__restrict__ nbr, const VT *__restrict__ x,
+                                                   const VT *__restrict__ z0, const double *__restrict__ qc,
                                                    const int *__restrict__ fvert, SweepCoef cf,
-                                                   double *__restrict__ y) {
+                                                   VT *__restrict__ y) {
     using AT = typename Acc<MT>::type;
     constexpr int P = M - 1;
     constexpr int V = Wide<MT>::V, C = 4 * M * M, G = padded(C, V) / V;
@@ -1412,7 +1438,7 @@ __global__ __launch_bounds__(1024) void k_sweep_rb(int ne, int nb, const MT *__r
         for (int q = 0; q < RB; ++q) out[q] = sweep_combine(cf, xe[a][q], zv[q], (double)acc[a][q]);
         if (cf.xprev) {
             double pv[RB];
-            load_rb<RB>(cf.xprev + o, pv);
+            load_rb<RB>(static_cast<const VT *>(cf.xprev) + o, pv);
             if (cf.qcprev)
 #pragma unroll
                 for (int q = 0; q < RB; ++q) pv[q] += p1_node<P>(a, q0[q], q1[q]);
@@ -1461,61 +1487,89 @@ bool rhs_blocked_m(int M, int nb, int rhs_block) { return M <= 4 && rhs_blocked(
     switch (M) { case 2: X(2); break; case 3: X(3); break; case 4: X(4); break; case 6: X(6); break; case 8: X(8); break; }
 #define M_SWITCH_RB(X) switch (M) { case 2: X(2); break; case 3: X(3); break; case 4: X(4); break; }
 
-template <typename MT>
-void launch_trace_apply(int M, int ne, int nb, const MT *S, const int *nbr, const double *x, const double *b,
-                        double *y, hipStream_t s, int rhs_block) {
+template <typename MT, typename XT, typename YT>
+void launch_trace_apply(int M, int ne, int nb, const MT *S, const int *nbr, const XT *x, const YT *b, YT *y,
+                        hipStream_t s, int rhs_block) {
     if (rhs_blocked_m(M, nb, rhs_block)) {
-#define TAB(MM) hipLaunchKernelGGL((k_trace_apply_rb<MM, MT, 4>), GRID_RB(ne, nb), 0, s, ne, nb, S, nbr, x, b, y)
+#define TAB(MM) hipLaunchKernelGGL((k_trace_apply_rb<MM, MT, XT, YT, 4>), GRID_RB(ne, nb), 0, s, ne, nb, S, nbr, x, b, y)
         M_SWITCH_RB(TAB)
 #undef TAB
         return;
     }
 #define TA(MM)                                                                                          \
-    if (nb == 1) hipLaunchKernelGGL((k_trace_apply<MM, MT, true>), GRID8(ne * nb, 256), 0, s, ne, nb, S, nbr, x, b, y); \
-    else hipLaunchKernelGGL((k_trace_apply<MM, MT, false>), GRID8(ne * nb, 256), 0, s, ne, nb, S, nbr, x, b, y)
+    if (nb == 1) hipLaunchKernelGGL((k_trace_apply<MM, MT, XT, YT, true>), GRID8(ne * nb, 256), 0, s, ne, nb, S, nbr, x, b, y); \
+    else hipLaunchKernelGGL((k_trace_apply<MM, MT, XT, YT, false>), GRID8(ne * nb, 256), 0, s, ne, nb, S, nbr, x, b, y)
     M_SWITCH(TA)
 #undef TA
 }
-template void launch_trace_apply<double>(int, int, int, const double *, const int *, const double *, const double *, double *, hipStream_t, int);
-template void launch_trace_apply<float>(int, int, int, const float *, const int *, const double *, const double *, double *, hipStream_t, int);
+#define INST_TA(MT, XT, YT) \
+    template void launch_trace_apply<MT, XT, YT>(int, int, int, const MT *, const int *, const XT *, const YT *, YT *, hipStream_t, int);
+INST_TA(double, double, double)
+INST_TA(float, double, double)
+INST_TA(double, float, float)
+INST_TA(float, float, float)
+INST_TA(double, float, double)
+INST_TA(float, float, double)
+INST_TA(double, double, float)
+INST_TA(float, double, float)
+#undef INST_TA
 
-template <typename MT>
-void launch_jacobi0(int M, int ne, int nb, const MT *Dw, const double *r, const double *scale, double *rs,
-                    double *z0, hipStream_t s) {
-#define J0(MM) hipLaunchKernelGGL((k_jacobi0<MM, MT>), GRID8(ne * nb, 256), 0, s, ne, nb, Dw, r, scale, rs, z0)
+template <typename MT, typename RT, typename ZT>
+void launch_jacobi0(int M, int ne, int nb, const MT *Dw, const RT *r, const double *scale, RT *rs, ZT *rc, ZT *z0,
+                    hipStream_t s) {
+#define J0(MM) hipLaunchKernelGGL((k_jacobi0<MM, MT, RT, ZT>), GRID8(ne * nb, 256), 0, s, ne, nb, Dw, r, scale, rs, rc, z0)
     M_SWITCH(J0)
 #undef J0
 }
-template void launch_jacobi0<double>(int, int, int, const double *, const double *, const double *, double *,
-                                     double *, hipStream_t);
-template void launch_jacobi0<float>(int, int, int, const float *, const double *, const double *, double *,
-                                    double *, hipStream_t);
+#define INST_J0(MT, RT, ZT) \
+    template void launch_jacobi0<MT, RT, ZT>(int, int, int, const MT *, const RT *, const double *, RT *, ZT *, ZT *, hipStream_t);
+INST_J0(double, double, double)
+INST_J0(float, double, double)
+INST_J0(double, float, float)
+INST_J0(float, float, float)
+INST_J0(double, double, float)
+INST_J0(float, double, float)
+INST_J0(double, float, double)
+INST_J0(float, float, double)
+#undef INST_J0
 
 // qc (the fused P1 prolongation) applies to the upwind trace only: M = p + 1.
-template <typename MT>
-void launch_sweep(int M, int ne, int nb, const MT *T, const int *nbr, const double *x, const double *z0,
-                  const double *qc, const int *fvert, SweepCoef cf, double *y, hipStream_t s,
-                  int rhs_block) {
+template <typename MT, typename VT>
+void launch_sweep(int M, int ne, int nb, const MT *T, const int *nbr, const VT *x, const VT *z0, const double *qc,
+                  const int *fvert, SweepCoef cf, VT *y, hipStream_t s, int rhs_block) {
     if (rhs_blocked_m(M, nb, rhs_block)) {
-#define SWB(MM) hipLaunchKernelGGL((k_sweep_rb<MM, MT, 4>), GRID_RB(ne, nb), 0, s, ne, nb, T, nbr, x, z0, qc, fvert, cf, y)
+#define SWB(MM) hipLaunchKernelGGL((k_sweep_rb<MM, MT, VT, 4>), GRID_RB(ne, nb), 0, s, ne, nb, T, nbr, x, z0, qc, fvert, cf, y)
         M_SWITCH_RB(SWB)
 #undef SWB
         return;
     }
 #define SW(MM)                                                                                                \
-    if (nb == 1) hipLaunchKernelGGL((k_sweep<MM, MT, true>), GRID8(ne * nb, 256), 0, s, ne, nb, T, nbr, x, z0, qc, fvert, cf, y); \
-    else hipLaunchKernelGGL((k_sweep<MM, MT, false>), GRID8(ne * nb, 256), 0, s, ne, nb, T, nbr, x, z0, qc, fvert, cf, y)
+    if (nb == 1) hipLaunchKernelGGL((k_sweep<MM, MT, VT, true>), GRID8(ne * nb, 256), 0, s, ne, nb, T, nbr, x, z0, qc, fvert, cf, y); \
+    else hipLaunchKernelGGL((k_sweep<MM, MT, VT, false>), GRID8(ne * nb, 256), 0, s, ne, nb, T, nbr, x, z0, qc, fvert, cf, y)
     M_SWITCH(SW)
 #undef SW
 }
-template void launch_sweep<double>(int, int, int, const double *, const int *, const double *, const double *, const double *, const int *, SweepCoef, double *, hipStream_t, int);
-template void launch_sweep<__hip_bfloat16>(int, int, int, const __hip_bfloat16 *, const int *, const double *, const double *, const double *, const int *, SweepCoef, double *, hipStream_t, int);
+template void launch_sweep<double, double>(int, int, int, const double *, const int *, const double *, const double *, const double *, const int *, SweepCoef, double *, hipStream_t, int);
+template void launch_sweep<__hip_bfloat16, double>(int, int, int, const __hip_bfloat16 *, const int *, const double *, const double *, const double *, const int *, SweepCoef, double *, hipStream_t, int);
+template void launch_sweep<__hip_bfloat16, float>(int, int, int, const __hip_bfloat16 *, const int *, const float *, const float *, const double *, const int *, SweepCoef, float *, hipStream_t, int);
+template void launch_sweep<double, float>(int, int, int, const double *, const int *, const float *, const float *, const double *, const int *, SweepCoef, float *, hipStream_t, int);
 
-void launch_restrict_trace(int p, int nv, int nb, const int *vf_row, const int *vf_col, const double *res,
-                           double *rc, hipStream_t s) {
-#define RT(P) hipLaunchKernelGGL(k_restrict_trace<P + 1>, GRID8(nv * nb, 256), 0, s, nv, nb, vf_row, vf_col, res, rc)
+template <typename VT>
+void launch_restrict_trace(int p, int nv, int nb, const int *vf_row, const int *vf_col, const VT *res, double *rc,
+                           hipStream_t s) {
+#define RT(P) hipLaunchKernelGGL((k_restrict_trace<P + 1, VT>), GRID8(nv * nb, 256), 0, s, nv, nb, vf_row, vf_col, res, rc)
     switch (p) { case 1: RT(1); break; case 2: RT(2); break; case 3: RT(3); break; }
 #undef RT
+}
+template void launch_restrict_trace<double>(int, int, int, const int *, const int *, const double *, double *, hipStream_t);
+template void launch_restrict_trace<float>(int, int, int, const int *, const int *, const float *, double *, hipStream_t);
+
+__global__ void k_to_f32(int64_t n, const double *__restrict__ src, float *__restrict__ dst) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = (float)src[i];
+}
+void launch_to_f32(int64_t n, const double *src, float *dst, hipStream_t s) {
+    hipLaunchKernelGGL(k_to_f32, GRID(n, 256), 0, s, n, src, dst);
 }
 
 void launch_p1_first(int n, int nb, const double *dinv, double omega, const double *b, double *x, hipStream_t s) {
@@ -1590,17 +1644,19 @@ int red_grid(int64_t len, int nb) {
     return (int)blocks;
 }
 
-void launch_dots(int64_t len, int nb, int nd, const double *X, int64_t xstride, const double *y, double *partial,
+template <typename VT>
+void launch_dots(int64_t len, int nb, int nd, const VT *X, int64_t xstride, const VT *y, double *partial,
                  double *out, double *host, hipStream_t s) {
     const int g = red_grid(len, nb);
-    hipLaunchKernelGGL(k_mdot_partial, dim3(g), dim3(256), 0, s, len, nb, nd, X, xstride, y, partial);
+    hipLaunchKernelGGL(k_mdot_partial<VT>, dim3(g), dim3(256), 0, s, len, nb, nd, X, xstride, y, partial);
     hipLaunchKernelGGL(k_sum_final, dim3(nd * nb), dim3(256), 0, s, g, nd * nb, partial, out, host);
 }
-void launch_gs_norm_givens(int64_t len, int nb, int nd, const double *h, const double *V, int64_t vstride,
-                           double *w, double *partial, double *hn, int j, int restart, double *gm,
-                           const double *bnorm, double *resid_host, hipStream_t s) {
+template <typename VT>
+void launch_gs_norm_givens(int64_t len, int nb, int nd, const double *h, const VT *V, int64_t vstride, VT *w,
+                           double *partial, double *hn, int j, int restart, double *gm, const double *bnorm,
+                           double *resid_host, hipStream_t s) {
     const int g = red_grid(len, nb);
-    hipLaunchKernelGGL(k_gs_update_norm, dim3(g), dim3(256), 0, s, len, nb, nd, h, V, vstride, w, partial);
+    hipLaunchKernelGGL(k_gs_update_norm<VT>, dim3(g), dim3(256), 0, s, len, nb, nd, h, V, vstride, w, partial);
     hipLaunchKernelGGL(k_norm_givens, dim3(nb), dim3(256), 0, s, g, nb, partial, hn, j, restart, h, gm, bnorm,
                        resid_host);
 }
@@ -1616,10 +1672,25 @@ void launch_pcg_dir(int64_t n, int nb, const double *num, const double *den, con
                     hipStream_t s) {
     hipLaunchKernelGGL(k_pcg_dir, GRID(n * nb, 256), 0, s, n, nb, num, den, z, p);
 }
-void launch_lincomb(int64_t n, int nb, int nd, const double *y, const double *Z, int64_t zstride, double *x,
+template <typename VT>
+void launch_lincomb(int64_t n, int nb, int nd, const double *y, const VT *Z, int64_t zstride, double *x,
                     hipStream_t s) {
-    hipLaunchKernelGGL(k_lincomb, GRID(n * nb, 256), 0, s, n, nb, nd, y, Z, zstride, x);
+    hipLaunchKernelGGL(k_lincomb<VT>, GRID(n * nb, 256), 0, s, n, nb, nd, y, Z, zstride, x);
 }
+template void launch_dots<double>(int64_t, int, int, const double *, int64_t, const double *, double *, double *,
+                                  double *, hipStream_t);
+template void launch_dots<float>(int64_t, int, int, const float *, int64_t, const float *, double *, double *,
+                                 double *, hipStream_t);
+template void launch_gs_norm_givens<double>(int64_t, int, int, const double *, const double *, int64_t, double *,
+                                            double *, double *, int, int, double *, const double *, double *,
+                                            hipStream_t);
+template void launch_gs_norm_givens<float>(int64_t, int, int, const double *, const float *, int64_t, float *,
+                                           double *, double *, int, int, double *, const double *, double *,
+                                           hipStream_t);
+template void launch_lincomb<double>(int64_t, int, int, const double *, const double *, int64_t, double *,
+                                     hipStream_t);
+template void launch_lincomb<float>(int64_t, int, int, const double *, const float *, int64_t, double *,
+                                    hipStream_t);
 void launch_copy(int64_t n, const double *src, double *dst, hipStream_t s) {
     hipLaunchKernelGGL(k_copy, GRID(n, 256), 0, s, n, src, dst);
 }

@@ -142,12 +142,12 @@ __device__ void mlp_forward(MlpTile<M> &T, const MlpWeights &W, int samp0, int n
 // traffic, so no block barrier is needed beyond the wave's own ordering.
 constexpr int MLP_ZROW = 40;   // LDS row stride of a sample's features (shorts): 80 B
 
-template <int M, int SPL, bool HAS_X, bool NB1>
-__global__ __launch_bounds__(256) void k_mlp_smooth(int ne, int nb, const double *__restrict__ u,
-                                                    const double *__restrict__ xi, const double *__restrict__ qc,
+template <int M, int SPL, bool HAS_X, bool NB1, typename VT>
+__global__ __launch_bounds__(256) void k_mlp_smooth(int ne, int nb, const VT *__restrict__ u,
+                                                    const VT *__restrict__ xi, const double *__restrict__ qc,
                                                     const int *__restrict__ fvert, const int *__restrict__ nbr,
                                                     const int8_t *__restrict__ prev, const short *__restrict__ W1b,
-                                                    const short *__restrict__ W2b, double *__restrict__ xo) {
+                                                    const short *__restrict__ W2b, VT *__restrict__ xo) {
     constexpr int WS = 64 * SPL;   // samples per wavefront
     constexpr int P = M - 1;
     __shared__ short zs[4][WS * MLP_ZROW];
@@ -476,25 +476,27 @@ __global__ void k_prolong_trace(int ne, int nb, const int *__restrict__ fvert, c
 }
 
 // out = a x + b y + c z (elementwise)
-__global__ void k_lin3(int64_t n, double a, const double *__restrict__ x, double b, const double *__restrict__ y,
-                       double c, const double *__restrict__ z, double *__restrict__ out) {
+template <typename VT>
+__global__ void k_lin3(int64_t n, double a, const VT *__restrict__ x, double b, const VT *__restrict__ y, double c,
+                       const VT *__restrict__ z, VT *__restrict__ out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    out[i] = a * x[i] + (y ? b * y[i] : 0.0) + (z ? c * z[i] : 0.0);
+    out[i] = (VT)(a * (double)x[i] + (y ? b * (double)y[i] : 0.0) + (z ? c * (double)z[i] : 0.0));
 }
 
 #define GRIDL(n, b) dim3((unsigned)(((n) + (b) - 1) / (b))), dim3(b)
 
-void launch_mlp_smooth(int p, int ne, int nb, int spl, const double *u, const double *xi, const double *qc,
+template <typename VT>
+void launch_mlp_smooth(int p, int ne, int nb, int spl, const VT *u, const VT *xi, const double *qc,
                        const int *fvert, const int *nbr, const int8_t *prev, const short *W1b, const short *W2b,
-                       double *xo, hipStream_t s) {
+                       VT *xo, hipStream_t s) {
     spl = spl >= 2 ? 2 : 1;
     const int64_t waves = ((int64_t)ne * nb + 64 * spl - 1) / (64 * spl);
     const int64_t blocks = (waves + 3) / 4;
     const dim3 grid((unsigned)(((blocks + 7) / 8) * 8)), block(256);   // multiple of 8 for the XCD remap
     const bool hx = xi != nullptr, n1 = nb == 1;
 #define MS(M, S, X, N) \
-    hipLaunchKernelGGL((k_mlp_smooth<M, S, X, N>), grid, block, 0, s, ne, nb, u, xi, qc, fvert, nbr, prev, W1b, W2b, xo)
+    hipLaunchKernelGGL((k_mlp_smooth<M, S, X, N, VT>), grid, block, 0, s, ne, nb, u, xi, qc, fvert, nbr, prev, W1b, W2b, xo)
 #define MS_XN(M, S)                          \
     if (hx) {                                \
         if (n1) MS(M, S, true, true);        \
@@ -514,6 +516,12 @@ void launch_mlp_smooth(int p, int ne, int nb, int spl, const double *u, const do
 #undef MS_XN
 #undef MS
 }
+template void launch_mlp_smooth<double>(int, int, int, int, const double *, const double *, const double *, const int *,
+                                        const int *, const int8_t *, const short *, const short *, double *,
+                                        hipStream_t);
+template void launch_mlp_smooth<float>(int, int, int, int, const float *, const float *, const double *, const int *,
+                                       const int *, const int8_t *, const short *, const short *, float *,
+                                       hipStream_t);
 
 int mlp_k1p(int) { return MLP_K1P; }
 
@@ -562,9 +570,14 @@ void launch_prolong_trace(int p, int ne, int nb, const int *fvert, const double 
     }
 }
 
-void launch_lin3(int64_t n, double a, const double *x, double b, const double *y, double c, const double *z,
-                 double *out, hipStream_t s) {
-    hipLaunchKernelGGL(k_lin3, GRIDL(n, 256), 0, s, n, a, x, b, y, c, z, out);
+template <typename VT>
+void launch_lin3(int64_t n, double a, const VT *x, double b, const VT *y, double c, const VT *z, VT *out,
+                 hipStream_t s) {
+    hipLaunchKernelGGL(k_lin3<VT>, GRIDL(n, 256), 0, s, n, a, x, b, y, c, z, out);
 }
+template void launch_lin3<double>(int64_t, double, const double *, double, const double *, double, const double *,
+                                  double *, hipStream_t);
+template void launch_lin3<float>(int64_t, double, const float *, double, const float *, double, const float *,
+                                 float *, hipStream_t);
 
 }  // namespace hdg

@@ -6,11 +6,13 @@
 namespace hdg {
 
 // pi^T: trace residual (M = 2(p+1) unknowns per facet) -> RT0 fluxes of the finest level
-void launch_lf_restrict(int M, int ne, int nb, const double *pw, const int *rrow, const int *rcol,
-                        const double *res, double *rc, hipStream_t s);
+template <typename VT>
+void launch_lf_restrict(int M, int ne, int nb, const double *pw, const int *rrow, const int *rcol, const VT *res,
+                        double *rc, hipStream_t s);
 // out = x + pi xc (x may be null)
-void launch_lf_prolong(int M, int ne, int nb, const double *pw, const int *nbr, const double *xc, const double *x,
-                       double *out, hipStream_t s);
+template <typename VT>
+void launch_lf_prolong(int M, int ne, int nb, const double *pw, const int *nbr, const double *xc, const VT *x,
+                       VT *out, hipStream_t s);
 // RT0 level operations
 void launch_rt_patch(const Rt0LevelDev &L, int nb, const double *b, const double *x, double *corr, hipStream_t s);
 void launch_rt_update(const Rt0LevelDev &L, int nb, double omega, const double *corr, const double *xin,

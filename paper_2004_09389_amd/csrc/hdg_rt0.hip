@@ -14,10 +14,10 @@ namespace {
 
 // rc[e'] = sum over the (e, slot) pairs whose row patch holds e' of
 // sum_a pw[slot][a][e] res[e][a]   (pi^T; code = 8 e + slot)
-template <int M>
+template <int M, typename VT>
 __global__ __launch_bounds__(256) void k_lf_restrict(int ne, int nb, const double *__restrict__ pw,
                                                      const int *__restrict__ rrow, const int *__restrict__ rcol,
-                                                     const double *__restrict__ res, double *__restrict__ rc) {
+                                                     const VT *__restrict__ res, double *__restrict__ rc) {
     const int t = xcd_block() * blockDim.x + threadIdx.x;
     if (t >= ne * nb) return;
     const int ep = t / nb, r = t - ep * nb;
@@ -26,17 +26,18 @@ __global__ __launch_bounds__(256) void k_lf_restrict(int ne, int nb, const doubl
     for (int q = rrow[ep]; q < rrow[ep + 1]; ++q) {
         const int code = rcol[q], e = code >> 3, slot = code & 7;
 #pragma unroll
-        for (int a = 0; a < M; ++a) acc += pw[((size_t)slot * M + a) * NE + e] * res[((size_t)e * M + a) * nb + r];
+        for (int a = 0; a < M; ++a)
+            acc += pw[((size_t)slot * M + a) * NE + e] * (double)res[((size_t)e * M + a) * nb + r];
     }
     rc[t] = acc;
 }
 
 // out = x + pi xc  (x may be null): the average of the two cells' RT0 fields at
 // the facet's nodes, from the five fluxes of the facet's row patch
-template <int M>
+template <int M, typename VT>
 __global__ __launch_bounds__(256) void k_lf_prolong(int ne, int nb, const double *__restrict__ pw,
                                                     const int *__restrict__ nbr, const double *__restrict__ xc,
-                                                    const double *__restrict__ x, double *__restrict__ out) {
+                                                    const VT *__restrict__ x, VT *__restrict__ out) {
     const int t = xcd_block() * blockDim.x + threadIdx.x;
     if (t >= ne * nb) return;
     const int e = t / nb, r = t - e * nb;
@@ -48,10 +49,10 @@ __global__ __launch_bounds__(256) void k_lf_prolong(int ne, int nb, const double
 #pragma unroll
     for (int a = 0; a < M; ++a) {
         const size_t o = ((size_t)e * M + a) * nb + r;
-        double v = x ? x[o] : 0.0;
+        double v = x ? (double)x[o] : 0.0;
 #pragma unroll
         for (int j = 0; j < 5; ++j) v += pw[((size_t)j * M + a) * NE + e] * c[j];
-        out[o] = v;
+        out[o] = (VT)v;
     }
 }
 
@@ -143,19 +144,29 @@ __global__ __launch_bounds__(256) void k_rt_prolong(int ne, int nb, const int *_
 
 }  // namespace
 
-void launch_lf_restrict(int M, int ne, int nb, const double *pw, const int *rrow, const int *rcol,
-                        const double *res, double *rc, hipStream_t s) {
-#define LR(MM) hipLaunchKernelGGL(k_lf_restrict<MM>, GRID8(ne * nb, 256), 0, s, ne, nb, pw, rrow, rcol, res, rc)
+template <typename VT>
+void launch_lf_restrict(int M, int ne, int nb, const double *pw, const int *rrow, const int *rcol, const VT *res,
+                        double *rc, hipStream_t s) {
+#define LR(MM) hipLaunchKernelGGL((k_lf_restrict<MM, VT>), GRID8(ne * nb, 256), 0, s, ne, nb, pw, rrow, rcol, res, rc)
     switch (M) { case 4: LR(4); break; case 6: LR(6); break; case 8: LR(8); break; }
 #undef LR
 }
 
-void launch_lf_prolong(int M, int ne, int nb, const double *pw, const int *nbr, const double *xc, const double *x,
-                       double *out, hipStream_t s) {
-#define LP(MM) hipLaunchKernelGGL(k_lf_prolong<MM>, GRID8(ne * nb, 256), 0, s, ne, nb, pw, nbr, xc, x, out)
+template <typename VT>
+void launch_lf_prolong(int M, int ne, int nb, const double *pw, const int *nbr, const double *xc, const VT *x,
+                       VT *out, hipStream_t s) {
+#define LP(MM) hipLaunchKernelGGL((k_lf_prolong<MM, VT>), GRID8(ne * nb, 256), 0, s, ne, nb, pw, nbr, xc, x, out)
     switch (M) { case 4: LP(4); break; case 6: LP(6); break; case 8: LP(8); break; }
 #undef LP
 }
+template void launch_lf_restrict<double>(int, int, int, const double *, const int *, const int *, const double *,
+                                         double *, hipStream_t);
+template void launch_lf_restrict<float>(int, int, int, const double *, const int *, const int *, const float *,
+                                        double *, hipStream_t);
+template void launch_lf_prolong<double>(int, int, int, const double *, const int *, const double *, const double *,
+                                        double *, hipStream_t);
+template void launch_lf_prolong<float>(int, int, int, const double *, const int *, const double *, const float *,
+                                       float *, hipStream_t);
 
 void launch_rt_patch(const Rt0LevelDev &L, int nb, const double *b, const double *x, double *corr, hipStream_t s) {
     hipLaunchKernelGGL(k_rt_patch, GRID8(L.nv * nb, 256), 0, s, L.nv, L.ne, nb, L.pf, L.pinv, L.val, L.nbr, b, x,

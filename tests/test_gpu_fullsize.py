@@ -121,14 +121,14 @@ def test_operators_full_size(name):
 
 
 @pytest.mark.parametrize("name", list(CONFIGS))
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "mixed_ir"])
 def test_solve_full_size_certified(name, precision):
     """Batched solve to 1e-8 in the benchmark's configuration; the oracle
     recomputes every column's true relative residual."""
-    from paper_2004_09389_amd.hdg import HDG_FP64, HDG_MIXED
+    from paper_2004_09389_amd.hdg import HDG_FP64, HDG_MIXED, HDG_MIXED_IR
     hier, phys, r, nb, o, mg = problem(name)
     rtol = 1e-8
-    s = solver(name, precision=HDG_FP64 if precision == "fp64" else HDG_MIXED, rtol=rtol)
+    s = solver(name, precision={"fp64": HDG_FP64, "mixed": HDG_MIXED, "mixed_ir": HDG_MIXED_IR}[precision], rtol=rtol)
     rhat = s.condense(to_dev(r))
     lam, info = s.solve(rhat)
     lam = host(lam)

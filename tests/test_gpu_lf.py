@@ -80,18 +80,18 @@ def test_vcycle(p, smoother):
 
 
 @pytest.mark.parametrize("p", [1, 2, 3])
-@pytest.mark.parametrize("f0,precision", [(0.0, "fp64"), (0.7, "fp64"), (0.7, "mixed")])
+@pytest.mark.parametrize("f0,precision", [(0.0, "fp64"), (0.7, "fp64"), (0.7, "mixed"), (0.7, "mixed_ir")])
 def test_solve_matches_dg(p, f0, precision):
     """condense + solve + recover equals the standard LF-DG solution (direct
     solve) and uhat = {{u}} + [[phi]]/2."""
     from oracle.lf import DgLfOracle
-    from paper_2004_09389_amd.hdg import HDG_FP64, HDG_MIXED
+    from paper_2004_09389_amd.hdg import HDG_FP64, HDG_MIXED, HDG_MIXED_IR
     n = 8
     d = DgLfOracle(hi.torus(n), p, 0.3, 1.3, 0.8, f0, 0.0)
     r = hi.iid_rhs(d.mesh, p, 31)
     q_ref, lam_ref = d.solve(r[..., 0])
     s = make(n, p, f0=f0, rtol=1e-12 if precision == "fp64" else 1e-11,
-             precision=HDG_FP64 if precision == "fp64" else HDG_MIXED)
+             precision={"fp64": HDG_FP64, "mixed": HDG_MIXED, "mixed_ir": HDG_MIXED_IR}[precision], krylov=2)
     q, lam, info = s.step(to_dev(r))
     assert info[0].status == 0
     tol = 1e-10 if precision == "fp64" else 1e-8

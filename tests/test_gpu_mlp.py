@@ -216,6 +216,23 @@ def test_solve_with_learned_smoother_matches_oracle():
     assert rel(lam, ref) < 1e-9
 
 
+@pytest.mark.parametrize("nb", [1, 4])
+def test_solve_learned_mixed_ir_matches_oracle(nb):
+    """The learned smoother inside the FP32 inner solve of HDG_MIXED_IR (FP32
+    basis and V-cycle vectors, FP64 refinement): every column to 1e-8."""
+    from paper_2004_09389_amd.hdg import HDG_MIXED_IR
+    hier, solver, oracle, _ = setup("torus16_p3_f1", rtol=1e-10, precision=HDG_MIXED_IR, max_rhs=nb)
+    W1, W2 = weights(solver.m, 10, scale=0.02)
+    solver.mlp_set_weights(W1, W2)
+    r = hi.iid_rhs(hier.fine, solver.p, 35, nrhs=nb)
+    lam, info = solver.solve(solver.condense(to_dev(r)))
+    lam = host(lam)
+    for k in range(nb):
+        assert info[k].status == 0 and info[k].rel_res <= 1e-10
+        assert rel(lam[..., k].ravel(), oracle.solve(r[..., k])[1]) < 1e-8
+    print(info[0])
+
+
 def test_fallback_on_garbage_weights():
     """Weights that wreck the cycle trip the fallback; the solve still converges."""
     hier, solver, oracle, mg = setup("torus12_p2_coriolis", rtol=1e-10)

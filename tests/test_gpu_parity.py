@@ -151,6 +151,27 @@ def test_solve_mixed(name):
         assert rel(q[:, fld], q_ref[:, fld]) < 1e-8
 
 
+@pytest.mark.parametrize("name", ["config1_torus8_p1", "torus16_p3_f1", "sphere_L2_p2"])
+@pytest.mark.parametrize("nb", [1, 3, 4])
+def test_solve_mixed_ir(name, nb):
+    """HDG_MIXED_IR: FP64 refinement around an inner FGMRES whose basis and
+    V-cycle vectors are FP32 (one thread per (facet, rhs) at nb = 1, 3 and the
+    RHS-blocked kernels at nb = 4); every column against the oracle."""
+    from paper_2004_09389_amd.hdg import HDG_KRYLOV_FGMRES, HDG_MIXED_IR
+    hier, solver, oracle, _ = setup_case(name, rtol=1e-10, precision=HDG_MIXED_IR, krylov=HDG_KRYLOV_FGMRES,
+                                         max_rhs=nb)
+    r = hi.iid_rhs(hier.fine, solver.p, 33, nrhs=nb)
+    q, lam, info = solver.step(to_dev(r))
+    q, lam = trace_np(q), trace_np(lam)
+    for k in range(nb):
+        q_ref, lam_ref = oracle.solve(r[..., k])
+        assert info[k].status == 0 and info[k].rel_res <= 1e-10 and info[k].refinements >= 2
+        assert rel(lam[..., k].ravel(), lam_ref) < 1e-8
+        for fld in range(3):
+            assert rel(q[:, fld, :, k], q_ref[:, fld]) < 1e-8
+    print(f"{name} nb={nb}: {info[0]}")
+
+
 @pytest.mark.parametrize("name", ["config1_torus8_p1", "torus12_p2_coriolis"])
 def test_batched_matches_single(name):
     hier, solver, oracle, _ = setup_case(name, rtol=1e-12, max_rhs=3)
