@@ -59,8 +59,11 @@ def parse():
     ap.add_argument("--headline", default="mixed", choices=["learned", "mixed"],
                     help="which reduced-precision solver `value` reports")
     ap.add_argument("--no-lf", action="store_true", help="skip the Lax-Friedrichs-flux leg")
-    ap.add_argument("--lf-coarse", type=int, default=8, help="LF leg: side of the coarsest RT0 level")
+    ap.add_argument("--lf-coarse", type=int, default=16, help="LF leg: side of the coarsest RT0 level")
     ap.add_argument("--lf-only", action="store_true", help="run only the Lax-Friedrichs leg (profiling)")
+    ap.add_argument("--no-sphere", action="store_true", help="skip the batched level-7 sphere leg")
+    ap.add_argument("--sphere-only", action="store_true", help="run only the batched level-7 sphere leg")
+    ap.add_argument("--sphere-nrhs", type=int, default=32)
     ap.add_argument("--pmc-run", action="store_true",
                     help="short run for hardware counters: mixed leg only, plus a reference copy kernel")
     return ap.parse_args()
@@ -191,6 +194,60 @@ def lf_leg(args, p, n, nb, run_steps):
     return out
 
 
+def sphere_leg(args, weights, run_steps):
+    """Icosahedral sphere, level 7 (327 680 cells), p = 3, g = 9.81, H = 5960,
+    f = 2 Omega sin(latitude), dt = 3600 s, a batch of sphere_nrhs right-hand
+    sides per step (iid coefficients, seed 500): plain FP64 multigrid against
+    the mixed solver (block-Jacobi, and the learned smoother when weights
+    are given: trained on the flat torus, not on the sphere)."""
+    import torch
+
+    import hdg_inputs as hi
+    from paper_2004_09389_amd.hdg import HDG_FP64, HDG_MIXED, HDG_SMOOTH_BJACOBI, HDG_SMOOTH_MLP, HdgSolver
+    nb = args.sphere_nrhs
+    hier = hi.icosphere_hierarchy(7, 6.371e6, level_coarse=3)
+    r = torch.from_numpy(hi.iid_rhs(hier.fine, 3, 500, nrhs=nb)).to("cuda")
+    out = {"workload": f"icosphere_L7_p3_dt3600_b{nb}", "n_cell": hier.fine.n_cell,
+           "n_trace_dof": int(3 * 4 * hier.fine.n_cell // 2), "nrhs": nb}
+    legs = [("fp64", HDG_FP64, HDG_SMOOTH_BJACOBI), ("mixed", HDG_MIXED, HDG_SMOOTH_BJACOBI)]
+    if weights is not None:
+        legs.append(("learned", HDG_MIXED, HDG_SMOOTH_MLP))
+    for name, prec, sm in legs:
+        s = HdgSolver(hier, 3, 3600.0, 9.81, 5960.0, 0.0, 7.292e-5, 1.0, rtol=args.rtol, precision=prec,
+                      smoother=sm, max_rhs=nb, krylov=2, maxit=200, p1_tail_max=0,
+                      use_graph=0 if args.no_graph else 1)
+        if sm == HDG_SMOOTH_MLP:
+            s.mlp_set_weights(*weights)
+        tuned = s.autotune(nb)
+        lam, rhat, q = s.trace_zeros(nb), s.trace_zeros(nb), s.cell_zeros(nb)
+
+        def step():
+            s.condense(r, out=rhat)
+            lam.zero_()
+            _, info = s.solve(rhat, lam)
+            s.recover(r, lam, out=q)
+            return info
+        step()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        infos = [step() for _ in range(run_steps)]
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t
+        out[name] = {"value": round(run_steps * nb / el, 3), "unit": "solves/s",
+                     "ms_per_step": round(1e3 * el / run_steps, 3),
+                     "iters": float(np.mean([i.iters for inf in infos for i in inf])),
+                     "fallbacks": int(sum(i.fallbacks for inf in infos for i in inf)),
+                     "rel_res_max": max(i.rel_res for inf in infos for i in inf), "tuning": tuned}
+        log(f"[bench] sphere {name}: {out[name]['ms_per_step']} ms/step ({out[name]['value']} solves/s) "
+            f"iters={out[name]['iters']}")
+        s.close()
+        del s
+    for name in ("mixed", "learned"):
+        if name in out:
+            out[f"speedup_{name}_vs_fp64"] = round(out[name]["value"] / out["fp64"]["value"], 3)
+    return out
+
+
 def main():
     args = parse()
     if args.pmc_run:
@@ -212,6 +269,9 @@ def main():
 
     torch.cuda.set_device(0)
     p, n, nb = args.degree, args.n, args.nrhs
+    if args.sphere_only:
+        print(json.dumps({"sphere_leg": sphere_leg(args, None, run_steps=args.steps)}), flush=True)
+        return
     if args.lf_only:
         print(json.dumps({"lf_leg": lf_leg(args, p, n, nb, run_steps=args.steps)}), flush=True)
         return
@@ -322,6 +382,9 @@ def main():
         s.close()
         del s
 
+    sphere_out = None
+    if not args.no_sphere and not args.pmc_run:
+        sphere_out = sphere_leg(args, trained.get("W") if p == 3 else None, run_steps=min(args.steps, 5))
     lf_out = None
     if not args.no_lf:
         lf_out = lf_leg(args, p, n, nb, run_steps=min(args.steps, 10))
@@ -424,6 +487,8 @@ def main():
                         "inverses) and the end-to-end solution at rtol; condense and recover are FP64 in both"}
     if lf_out is not None:
         out["lf_leg"] = lf_out
+    if sphere_out is not None:
+        out["sphere_leg"] = sphere_out
     if not args.no_cpu:
         log("[bench] cpu oracle baseline ...")
         out["cpu_baseline"], sample = cpu_baseline(n, p, dt)
