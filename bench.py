@@ -64,6 +64,7 @@ def parse():
     ap.add_argument("--no-sphere", action="store_true", help="skip the batched level-7 sphere leg")
     ap.add_argument("--sphere-only", action="store_true", help="run only the batched level-7 sphere leg")
     ap.add_argument("--sphere-nrhs", type=int, default=32)
+    ap.add_argument("--ir-inner-rtol", type=float, default=1e-4, help="mixed_ir: reduction per inner solve")
     ap.add_argument("--pmc-run", action="store_true",
                     help="short run for hardware counters: mixed leg only, plus a reference copy kernel")
     return ap.parse_args()
@@ -198,8 +199,9 @@ def sphere_leg(args, weights, run_steps):
     """Icosahedral sphere, level 7 (327 680 cells), p = 3, g = 9.81, H = 5960,
     f = 2 Omega sin(latitude), dt = 3600 s, a batch of sphere_nrhs right-hand
     sides per step (iid coefficients, seed 500): plain FP64 multigrid against
-    the mixed solver (block-Jacobi, and the learned smoother when weights
-    are given: trained on the flat torus, not on the sphere)."""
+    the mixed solvers (HDG_MIXED; HDG_MIXED_IR with block-Jacobi, and with the
+    learned smoother when weights are given: trained on the flat torus, not
+    on the sphere)."""
     import torch
 
     import hdg_inputs as hi
@@ -209,13 +211,15 @@ def sphere_leg(args, weights, run_steps):
     r = torch.from_numpy(hi.iid_rhs(hier.fine, 3, 500, nrhs=nb)).to("cuda")
     out = {"workload": f"icosphere_L7_p3_dt3600_b{nb}", "n_cell": hier.fine.n_cell,
            "n_trace_dof": int(3 * 4 * hier.fine.n_cell // 2), "nrhs": nb}
-    legs = [("fp64", HDG_FP64, HDG_SMOOTH_BJACOBI), ("mixed", HDG_MIXED, HDG_SMOOTH_BJACOBI)]
+    from paper_2004_09389_amd.hdg import HDG_MIXED_IR
+    legs = [("fp64", HDG_FP64, HDG_SMOOTH_BJACOBI), ("mixed", HDG_MIXED, HDG_SMOOTH_BJACOBI),
+            ("mixed_ir", HDG_MIXED_IR, HDG_SMOOTH_BJACOBI)]
     if weights is not None:
-        legs.append(("learned", HDG_MIXED, HDG_SMOOTH_MLP))
+        legs.append(("learned_ir", HDG_MIXED_IR, HDG_SMOOTH_MLP))
     for name, prec, sm in legs:
         s = HdgSolver(hier, 3, 3600.0, 9.81, 5960.0, 0.0, 7.292e-5, 1.0, rtol=args.rtol, precision=prec,
                       smoother=sm, max_rhs=nb, krylov=2, maxit=200, p1_tail_max=0,
-                      use_graph=0 if args.no_graph else 1)
+                      use_graph=0 if args.no_graph else 1, ir_inner_rtol=args.ir_inner_rtol)
         if sm == HDG_SMOOTH_MLP:
             s.mlp_set_weights(*weights)
         tuned = s.autotune(nb)
@@ -242,8 +246,8 @@ def sphere_leg(args, weights, run_steps):
             f"iters={out[name]['iters']}")
         s.close()
         del s
-    for name in ("mixed", "learned"):
-        if name in out:
+    for name in ("mixed", "mixed_ir", "learned_ir"):
+        if name in out and "fp64" in out:
             out[f"speedup_{name}_vs_fp64"] = round(out[name]["value"] / out["fp64"]["value"], 3)
     return out
 
@@ -288,7 +292,7 @@ def main():
     def make(prec, nb_override=None, learned=False):
         t = time.perf_counter()
         s = HdgSolver(hier, p, dt, 1.0, 1.0, 1.0, 0.0, 1.0, rtol=args.rtol, precision=prec,
-                      max_rhs=nb_override or nb,
+                      ir_inner_rtol=args.ir_inner_rtol, max_rhs=nb_override or nb,
                       smoother=HDG_SMOOTH_MLP if learned else (HDG_SMOOTH_CHEBYSHEV if args.smoother == "chebyshev"
                                                                else HDG_SMOOTH_BJACOBI),
                       **({"nu_pre": args.learned_nu, "nu_post": args.learned_nu} if learned else {}),

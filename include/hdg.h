@@ -87,7 +87,9 @@ extern "C" {
                                accumulation; P1 coarse solve in FP64 */
 #define HDG_MIXED_IR 2      /* hdg_solve only: FP64 iterative refinement (true residual with the
                                FP64 operator at every restart) around an inner flexible GMRES
-                               that applies the FP32 operator and the mixed V-cycle */
+                               that applies the FP32 operator and the mixed V-cycle, its basis
+                               vectors held in FP32; each inner solve reduces the residual by
+                               ir_inner_rtol */
 
 #define HDG_KRYLOV_AUTO   0 /* PCG when the trace operator and the V-cycle are symmetric (f = 0, FP64,
                                nu_pre = nu_post, a linear smoother), else FGMRES */
@@ -151,6 +153,7 @@ typedef struct {
     int32_t rt_nu;              /* LF flux: vertex-patch smoothing steps per RT0 level, pre and post
                                    (default 1) */
     double  rt_omega;           /* LF flux: damping of the additive vertex-patch smoother (default 0.5) */
+    double  ir_inner_rtol;      /* HDG_MIXED_IR: relative reduction of each inner solve (default 1e-4) */
 } hdg_options;
 
 typedef struct {

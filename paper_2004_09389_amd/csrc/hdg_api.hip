@@ -804,6 +804,7 @@ void setup_impl(const hdg_mesh *levels, int nlev, const int32_t *const *parents,
     HDG_REQUIRE(opt.nu_pre >= 1 && opt.nu_post >= 1 && opt.p1_nu >= 1, "sweep counts must be >= 1");
     HDG_REQUIRE(opt.omega > 0 && opt.p1_omega > 0, "damping factors must be positive");
     HDG_REQUIRE(opt.rtol >= 0 && opt.maxit >= 1, "rtol >= 0 and maxit >= 1 required");
+    HDG_REQUIRE(opt.ir_inner_rtol > 0 && opt.ir_inner_rtol < 1, "ir_inner_rtol must be in (0, 1)");
     HDG_REQUIRE(opt.p1_tail_max >= 0 && opt.p1_tail_max <= hdg::P1_TAIL_MAX, "p1_tail_max must be in 0..4096");
     HDG_REQUIRE(opt.smoother >= HDG_SMOOTH_BJACOBI && opt.smoother <= HDG_SMOOTH_CHEBYSHEV, "unknown smoother");
     HDG_REQUIRE(opt.p1_galerkin == 0 || opt.p1_galerkin == 1, "p1_galerkin must be 0 or 1");
@@ -1175,6 +1176,7 @@ extern "C" int hdg_default_options(hdg_options *o) {
     o->p1_tail_max = hdg::P1_TAIL_MAX;
     o->rt_nu = 1;
     o->rt_omega = 0.5;
+    o->ir_inner_rtol = 1e-4;
     return HDG_OK;
 }
 
@@ -1301,7 +1303,7 @@ extern "C" int hdg_solve(hdg_ctx *c, int32_t nb, const double *rhat, double *lam
             HDG_REQUIRE(c->opt.precision == HDG_FP64, "PCG needs the FP64 (linear) preconditioner");
             status = solve_pcg(c, nb, rhat, lam, info, s);
         } else if (c->opt.precision == HDG_MIXED_IR) {
-            status = solve_fgmres(c, nb, HDG_MIXED, HDG_MIXED, 1e-4, rhat, lam, info, s);
+            status = solve_fgmres(c, nb, HDG_MIXED, HDG_MIXED, c->opt.ir_inner_rtol, rhat, lam, info, s);
         } else {
             status = solve_fgmres(c, nb, c->opt.precision, HDG_FP64, 0.0, rhat, lam, info, s);
         }

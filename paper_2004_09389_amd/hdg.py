@@ -45,7 +45,7 @@ class HdgOptions(ctypes.Structure):
                 ("maxit", ctypes.c_int32), ("restart", ctypes.c_int32), ("max_rhs", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("fallback_ratio", ctypes.c_double),
                 ("p1_tail_max", ctypes.c_int32), ("p1_galerkin", ctypes.c_int32),
-                ("rt_nu", ctypes.c_int32), ("rt_omega", ctypes.c_double)]
+                ("rt_nu", ctypes.c_int32), ("rt_omega", ctypes.c_double), ("ir_inner_rtol", ctypes.c_double)]
 
 
 class HdgSolveInfo(ctypes.Structure):
