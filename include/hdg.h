@@ -312,8 +312,10 @@ int hdg_autotune(hdg_ctx *ctx, int32_t nrhs, hdg_tuning *chosen, void *stream);
  * hdg_kernel_stats returns, for kernel class id and precision, the launch
  * count and the summed per-launch duration (ms) since the last
  * hdg_set_timing call, and the algorithmic bytes one launch moves at the
- * nrhs of the timed launches (every stored matrix entry once, every vector
- * entry read or written once, indices once).  Both calls synchronise. */
+ * nrhs and vector entry sizes of the timed launches (every stored matrix
+ * entry once, every vector entry read or written once at its stored size --
+ * 4 bytes for the FP32 vectors inside mixed solves -- indices once).  Both
+ * calls synchronise. */
 #define HDG_KERNEL_APPLY    0   /* y = S x  (facet block rows) */
 #define HDG_KERNEL_SWEEP    1   /* block-Jacobi sweep with the off-diagonal rows */
 #define HDG_KERNEL_RESIDUAL 2   /* r - S x */

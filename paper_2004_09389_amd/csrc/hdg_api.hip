@@ -128,9 +128,13 @@ struct Timed {
     int kind, prec;
     hipStream_t s;
     hipEvent_t a = nullptr;
-    Timed(hdg_ctx *c_, int kind_, int prec_, hipStream_t s_, int nb) : c(c_), kind(kind_), prec(prec_), s(s_) {
+    // sx, sy: bytes per entry of the launch's input and output trace vectors
+    Timed(hdg_ctx *c_, int kind_, int prec_, hipStream_t s_, int nb, int sx = 8, int sy = 8)
+        : c(c_), kind(kind_), prec(prec_), s(s_) {
         if (!c->timing) return;
         c->t_nb[prec][kind] = nb;
+        c->t_sx[prec][kind] = sx;
+        c->t_sy[prec][kind] = sy;
         a = pool_event(c);
         HDG_HIP_CHECK(hipEventRecord(a, s));
     }
@@ -181,7 +185,7 @@ VT *vt(double *p) { return reinterpret_cast<VT *>(p); }
 // y = S x (b == nullptr) or y = b - S x; x32 / y32: x, and b and y, held in FP32
 void op_apply(hdg_ctx *c, int nb, int prec, const double *x, const double *b, double *y, hipStream_t s, int kind,
               bool x32 = false, bool y32 = false) {
-    Timed t(c, kind, prec, s, nb);
+    Timed t(c, kind, prec, s, nb, x32 ? 4 : 8, y32 ? 4 : 8);
     for (int rep = 0; rep < t.repeats(); ++rep)
         vt2_call(x32, y32, [&](auto tx, auto ty) {
             using XT = std::remove_pointer_t<decltype(tx)>;
@@ -205,7 +209,7 @@ hdg::SweepCoef bj_coef(const hdg_ctx *c) { return {1.0 - c->opt.omega, 1.0, 1.0,
 
 void op_sweep(hdg_ctx *c, int nb, int prec, const double *x, const double *z0, const double *qc, double *y,
               hipStream_t s, const hdg::SweepCoef &cf) {
-    Timed t(c, HDG_KERNEL_SWEEP, prec, s, nb);
+    Timed t(c, HDG_KERNEL_SWEEP, prec, s, nb, c->vcyc32 ? 4 : 8, c->vcyc32 ? 4 : 8);
     for (int rep = 0; rep < t.repeats(); ++rep)
         vt_call(c->vcyc32, [&](auto tag) {
             using VT = std::remove_pointer_t<decltype(tag)>;
@@ -388,7 +392,7 @@ void vcycle_mlp(hdg_ctx *c, int nb, int prec, const double *r, double *z, hipStr
     // x alternates between vx and vx2; the correction goes to vres
     double *x = c->vx, *other = c->vx2;
     auto learned = [&](const double *u, const double *xi, const double *qc, double *out) {
-        Timed t(c, HDG_KERNEL_MLP, prec, s, nb);
+        Timed t(c, HDG_KERNEL_MLP, prec, s, nb, c->vcyc32 ? 4 : 8, c->vcyc32 ? 4 : 8);
         for (int rep = 0; rep < t.repeats(); ++rep)
             vt_call(c->vcyc32, [&](auto tag) {
                 using VT = std::remove_pointer_t<decltype(tag)>;
@@ -1645,14 +1649,17 @@ extern "C" int hdg_kernel_stats(hdg_ctx *c, int32_t kernel, int32_t prec, int64_
             const double m = c->m, ne = c->n_facet, nk = c->n_cell, nc = c->nc, nt = c->nt;
             const double nb = std::max(1, c->t_nb[prec][kernel]);
             const double sm = prec == HDG_MIXED ? 4.0 : 8.0, st = prec == HDG_MIXED ? 2.0 : 8.0;
+            // vector entry sizes of the timed launches (FP32 vectors inside mixed solves)
+            const double sx = c->t_sx[prec][kernel] ? c->t_sx[prec][kernel] : 8;
+            const double sy = c->t_sy[prec][kernel] ? c->t_sy[prec][kernel] : 8;
             double b = 0;
             switch (kernel) {
-            case HDG_KERNEL_APPLY: b = ne * (5 * m * m * sm + 4 * 4) + nb * ne * 2 * m * 8; break;
-            case HDG_KERNEL_RESIDUAL: b = ne * (5 * m * m * sm + 4 * 4) + nb * ne * 3 * m * 8; break;
-            case HDG_KERNEL_SWEEP: b = ne * (4 * m * m * st + 4 * 4) + nb * ne * 3 * m * 8; break;
+            case HDG_KERNEL_APPLY: b = ne * (5 * m * m * sm + 4 * 4) + nb * ne * m * (sx + sy); break;
+            case HDG_KERNEL_RESIDUAL: b = ne * (5 * m * m * sm + 4 * 4) + nb * ne * m * (sx + 2 * sy); break;
+            case HDG_KERNEL_SWEEP: b = ne * (4 * m * m * st + 4 * 4) + nb * ne * 3 * m * sx; break;
             case HDG_KERNEL_CONDENSE: b = nk * nt * nc * 8 + nb * (nk * nc * 8 + ne * m * 8); break;
             case HDG_KERNEL_RECOVER: b = nk * (nc * nc + nc * nt) * 8 + nb * (nk * 2 * nc * 8 + ne * m * 8); break;
-            case HDG_KERNEL_MLP: b = ne * (4 * 4 + 4) + nb * ne * 3 * m * 8; break;
+            case HDG_KERNEL_MLP: b = ne * (4 * 4 + 4) + nb * ne * 3 * m * sx; break;
             }
             *bytes_per_launch = b;
         }

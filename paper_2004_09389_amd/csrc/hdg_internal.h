@@ -256,5 +256,7 @@ struct hdg_ctx {
     hipStream_t cap_stream = nullptr;
     int64_t t_launches[2][HDG_KERNEL_COUNT] = {};
     int t_nb[2][HDG_KERNEL_COUNT] = {};   // nrhs of the last timed launch per class
+    int t_sx[2][HDG_KERNEL_COUNT] = {};   // bytes per input-vector entry of that launch (8 or 4)
+    int t_sy[2][HDG_KERNEL_COUNT] = {};   // bytes per output-vector entry
     double t_ms[2][HDG_KERNEL_COUNT] = {};
 };
