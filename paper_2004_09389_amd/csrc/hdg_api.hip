@@ -1588,7 +1588,7 @@ extern "C" int hdg_autotune(hdg_ctx *c, int32_t nb, hdg_tuning *chosen, void *st
         double best = 1e300;
         int best_spl = c->mlp_spl;
         for (int spl : {1, 2}) {
-            if (c->flux != HDG_FLUX_UPWIND) break;   // no learned smoother to tune
+            if (c->opt.smoother != HDG_SMOOTH_MLP) break;   // no learned smoother to tune
             const double ms = time_launches(s, 10, [&] {
                 hdg::launch_mlp_smooth(c->p, c->n_facet, nb, spl, c->vres, c->vx, nullptr, c->facet_vert, c->nbr,
                                        c->prev, W1b, W2b, c->vx2, s);

@@ -127,3 +127,35 @@ def test_not_converged_and_breakdown_are_reported():
     assert e.value.code == HDG_EBREAKDOWN
     lam, info = s.solve(rhat, allow_notconv=True)
     assert info[0].status == HDG_ENOTCONV and np.all(np.isfinite(host(lam)))
+
+
+def test_mixed_breakdown_leaves_the_context_in_fp64():
+    """A non-finite right-hand side in the FP32 inner solve of HDG_MIXED_IR and in
+    the mixed solve reports HDG_EBREAKDOWN; afterwards the FP64 entry points
+    (apply, V-cycle, solve) still read and write FP64 vectors."""
+    from oracle.hdg import HdgOracle
+    from paper_2004_09389_amd.hdg import HDG_EBREAKDOWN, HDG_MIXED, HDG_MIXED_IR, HdgError
+    hier = hi.torus_hierarchy(6, 3)
+    o = HdgOracle(hier.fine, 2, 0.4, 1.0, 1.0, 0.5, 0.0)
+    for prec in (HDG_MIXED_IR, HDG_MIXED):
+        s = make(precision=prec, krylov=2, rtol=1e-10)
+        r = hi.iid_rhs(hier.fine, 2, 7)
+        rhat = s.condense(to_dev(r))
+        bad = rhat.clone()
+        bad[1, 0, 0] = float("inf")
+        with pytest.raises(HdgError) as e:
+            s.solve(bad)
+        assert e.value.code == HDG_EBREAKDOWN
+        x = np.random.default_rng(2).standard_normal((s.n_facet, s.m, 1))
+        assert rel(host(s.trace_apply(to_dev(x)))[..., 0].ravel(), o.apply(x[..., 0].ravel())) < 1e-12
+        lam, info = s.solve(rhat)
+        assert info[0].status == 0
+        assert rel(host(lam)[..., 0].ravel(), o.solve(r[..., 0])[1]) < 1e-8
+        s.close()
+
+
+def test_ir_inner_rtol_is_validated():
+    from paper_2004_09389_amd.hdg import HdgError
+    with pytest.raises(HdgError) as e:
+        make(ir_inner_rtol=1.5)
+    assert "ir_inner_rtol" in str(e.value)
