@@ -84,7 +84,9 @@ extern "C" {
 #define HDG_FP64     0      /* everything in FP64 */
 #define HDG_MIXED    1      /* FP64 Krylov with the FP64 operator; the V-cycle uses the FP32
                                operator rows, BF16 smoother rows and FP32 block inverses with FP32
-                               accumulation; P1 coarse solve in FP64 */
+                               accumulation; P1 coarse solve in FP64.  Inside hdg_solve the
+                               V-cycle's work vectors and the FGMRES Z basis are FP32 (the V basis,
+                               lam and the true residual FP64); hdg_mg_vcycle keeps FP64 vectors */
 #define HDG_MIXED_IR 2      /* hdg_solve only: FP64 iterative refinement (true residual with the
                                FP64 operator at every restart) around an inner flexible GMRES
                                that applies the FP32 operator and the mixed V-cycle, its basis
