@@ -89,3 +89,30 @@ def test_iterations_flat_over_mesh_ladder(p):
         s.close()
     print(f"p={p} FGMRES iterations to 1e-8 over n = 32..256: {its}")
     assert max(its) - min(its) <= 3
+
+
+@pytest.mark.parametrize("p", [1, 3])
+def test_iterations_at_the_papers_courant_number(p):
+    """Like-for-like with the paper's iteration table for the linear problem
+    (HDG column: 8 CG iterations at p = 1, 7 at p = 3, flat in h): flat
+    bathymetry, f = 0, PCG to 1e-8, Chebyshev(2) smoothing as in the paper's
+    solver settings, and the implicit stage's kappa = c alpha dt with the
+    paper's dt = (rho gamma / (2p + 1)) h, rho gamma = 2, and alpha = 1 - 1/sqrt(2)
+    (the implicit coefficient of its ARS2(2,3,3) stepper).  The smoother's
+    preconditioner (block-Jacobi instead of SOR) and the coarse solve (GMG
+    instead of AMG) differ, so the counts are bounded, not matched."""
+    import torch
+    from paper_2004_09389_amd.hdg import HDG_KRYLOV_PCG, HDG_SMOOTH_CHEBYSHEV, HdgSolver
+    alpha = 1.0 - 1.0 / np.sqrt(2.0)
+    its = []
+    for n in (32, 64, 128, 256):
+        hier = hi.torus_hierarchy(n, min(32, n))
+        s = HdgSolver(hier, p, alpha * (2.0 / (2 * p + 1)) / n, 1.0, 1.0, 0.0, 0.0, krylov=HDG_KRYLOV_PCG,
+                      smoother=HDG_SMOOTH_CHEBYSHEV, p1_tail_max=0)
+        r = torch.from_numpy(hi.fourier_rhs_torus(hier.fine, p, 100)).cuda()
+        _, info = s.solve(s.condense(r))
+        assert info[0].status == 0
+        its.append(info[0].iters)
+        s.close()
+    print(f"p={p}: PCG iterations at the paper's Courant number over n = 32..256: {its}")
+    assert max(its) <= 9 and min(its) >= 5 and max(its) - min(its) <= 2
