@@ -295,29 +295,40 @@ void restrict_p1(hdg_ctx *c, int nb, const double *res, double *rc, hipStream_t 
 
 // One RT0 geometric-multigrid V-cycle on level l (input rt[l].b, Lax-Friedrichs
 // coarse problem); returns the buffer holding the result.  rt_nu additive
-// vertex-patch steps from zero, residual, restriction P^T, recursion,
-// prolongation x += P x_c, rt_nu patch steps; dense inverse on level 0.
-double *rt_vcycle(hdg_ctx *c, int l, int nb, hipStream_t s) {
+// vertex-patch steps from zero (a single one fused with the residual),
+// restriction P^T, recursion, prolongation x += P x_c, rt_nu patch steps.  The
+// last post-smoothing update is left pending (*pending = true): its corrections
+// stay in rt_corr and the consumer of the result (the next finer level's
+// prolongation, or pi) adds them as it reads.  Dense inverse on level 0.
+double *rt_vcycle(hdg_ctx *c, int l, int nb, hipStream_t s, bool *pending) {
     hdg::Rt0LevelDev &L = c->rt[l];
     if (l == 0) {
         hdg::launch_dense_mv(L.ne, nb, c->rt_coarse_inv, L.b, L.x, s);
+        *pending = false;
         return L.x;
     }
     const double w = c->opt.rt_omega;
     double *x = L.x;
     for (int k = 0; k < c->opt.rt_nu; ++k) {
         hdg::launch_rt_patch(L, nb, L.b, k == 0 ? nullptr : x, c->rt_corr, s);
-        hdg::launch_rt_update(L, nb, w, c->rt_corr, k == 0 ? nullptr : x, x, s);
+        if (k == 0 && c->opt.rt_nu == 1) {
+            // from zero the fused kernel reads no previous iterate, so it may write x in place
+            hdg::launch_rt_update_resid(L, nb, w, c->rt_corr, nullptr, x, L.y, s);
+        } else {
+            hdg::launch_rt_update(L, nb, w, c->rt_corr, k == 0 ? nullptr : x, x, s);
+            if (k + 1 == c->opt.rt_nu) hdg::launch_rt_resid(L, nb, L.b, x, L.y, s);
+        }
     }
-    hdg::launch_rt_resid(L, nb, L.b, x, L.y, s);
     hdg::Rt0LevelDev &C = c->rt[l - 1];
     hdg::launch_rt_restrict(L, C.ne, nb, L.y, C.b, s);
-    const double *xc = rt_vcycle(c, l - 1, nb, s);
-    hdg::launch_rt_prolong(L, nb, xc, x, s);
+    bool cpend = false;
+    const double *xc = rt_vcycle(c, l - 1, nb, s, &cpend);
+    hdg::launch_rt_prolong(L, C, nb, xc, w, cpend ? c->rt_corr : nullptr, x, s);
     for (int k = 0; k < c->opt.rt_nu; ++k) {
         hdg::launch_rt_patch(L, nb, L.b, x, c->rt_corr, s);
-        hdg::launch_rt_update(L, nb, w, c->rt_corr, x, x, s);
+        if (k + 1 < c->opt.rt_nu) hdg::launch_rt_update(L, nb, w, c->rt_corr, x, x, s);
     }
+    *pending = true;
     return x;
 }
 
@@ -328,10 +339,12 @@ void lf_coarse(hdg_ctx *c, int nb, const double *res, const double *cur, double 
         using VT = std::remove_pointer_t<decltype(tag)>;
         hdg::launch_lf_restrict<VT>(c->m, c->n_facet, nb, c->lf_pw, c->lf_rrow, c->lf_rcol, vt<VT>(res), c->rt[L].b, s);
     });
-    const double *xr = rt_vcycle(c, L, nb, s);
+    bool pend = false;
+    const double *xr = rt_vcycle(c, L, nb, s, &pend);
     vt_call(c->vcyc32, [&](auto tag) {
         using VT = std::remove_pointer_t<decltype(tag)>;
-        hdg::launch_lf_prolong<VT>(c->m, c->n_facet, nb, c->lf_pw, c->nbr, xr, vt<VT>(cur), vt<VT>(out), s);
+        hdg::launch_lf_prolong<VT>(c->m, c->n_facet, nb, c->lf_pw, c->nbr, xr, c->rt[L].fs, c->opt.rt_omega,
+                                   pend ? c->rt_corr : nullptr, vt<VT>(cur), vt<VT>(out), s);
     });
 }
 

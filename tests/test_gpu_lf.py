@@ -57,17 +57,17 @@ def test_operators(p, nb):
     s.close()
 
 
-@pytest.mark.parametrize("p", [1, 3])
+@pytest.mark.parametrize("p,rt_nu", [(1, 1), (3, 1), (3, 2)])
 @pytest.mark.parametrize("smoother", ["jacobi", "chebyshev"])
-def test_vcycle(p, smoother):
+def test_vcycle(p, rt_nu, smoother):
     """V-cycle vs the oracle's (same smoothing, pi, RT0 levels 4, 8, 16 with
-    vertex-patch smoothing and the dense 4 x 4 level)."""
+    rt_nu vertex-patch steps and the dense 4 x 4 level)."""
     from oracle.lf import LfTraceMultigrid
     from paper_2004_09389_amd.hdg import HDG_MIXED, HDG_SMOOTH_BJACOBI, HDG_SMOOTH_CHEBYSHEV
     n = 16
     o = oracle(n, p, dt=0.5 / n * 8, f0=0.0)
-    mg = LfTraceMultigrid(o, hi.torus_hierarchy(n, 4), smoother=smoother)
-    s = make(n, p, dt=0.5 / n * 8, f0=0.0,
+    mg = LfTraceMultigrid(o, hi.torus_hierarchy(n, 4), smoother=smoother, rt_nu=rt_nu)
+    s = make(n, p, dt=0.5 / n * 8, f0=0.0, rt_nu=rt_nu,
              smoother=HDG_SMOOTH_CHEBYSHEV if smoother == "chebyshev" else HDG_SMOOTH_BJACOBI)
     assert s.sizes.n_levels == 3
     if smoother == "chebyshev":
