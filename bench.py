@@ -195,10 +195,11 @@ def lf_leg(args, p, n, nb, run_steps):
     return out
 
 
-def sphere_leg(args, weights, run_steps):
-    """Icosahedral sphere, level 7 (327 680 cells), p = 3, g = 9.81, H = 5960,
-    f = 2 Omega sin(latitude), dt = 3600 s, a batch of sphere_nrhs right-hand
-    sides per step (iid coefficients, seed 500): plain FP64 multigrid against
+def sphere_leg(args, weights, run_steps, level=7, p=3, dt=3600.0, nb=None, seed=500):
+    """Icosahedral sphere of radius 6.371e6 m at the given level, g = 9.81, H = 5960,
+    f = 2 Omega sin(latitude): by default level 7 (327 680 cells), p = 3,
+    dt = 3600 s, sphere_nrhs right-hand sides per step (iid coefficients,
+    seed 500); the level-6 workload is p = 2, dt = 1800 s, 16 per step.  Plain FP64 multigrid against
     the mixed solvers (HDG_MIXED; HDG_MIXED_IR with block-Jacobi, and with the
     learned smoother when weights are given: trained on the flat torus, not
     on the sphere)."""
@@ -206,18 +207,18 @@ def sphere_leg(args, weights, run_steps):
 
     import hdg_inputs as hi
     from paper_2004_09389_amd.hdg import HDG_FP64, HDG_MIXED, HDG_SMOOTH_BJACOBI, HDG_SMOOTH_MLP, HdgSolver
-    nb = args.sphere_nrhs
-    hier = hi.icosphere_hierarchy(7, 6.371e6, level_coarse=3)
-    r = torch.from_numpy(hi.iid_rhs(hier.fine, 3, 500, nrhs=nb)).to("cuda")
-    out = {"workload": f"icosphere_L7_p3_dt3600_b{nb}", "n_cell": hier.fine.n_cell,
-           "n_trace_dof": int(3 * 4 * hier.fine.n_cell // 2), "nrhs": nb}
+    nb = nb or args.sphere_nrhs
+    hier = hi.icosphere_hierarchy(level, 6.371e6, level_coarse=3)
+    r = torch.from_numpy(hi.iid_rhs(hier.fine, p, seed, nrhs=nb)).to("cuda")
+    out = {"workload": f"icosphere_L{level}_p{p}_dt{dt:g}_b{nb}", "n_cell": hier.fine.n_cell,
+           "n_trace_dof": int(3 * (p + 1) * hier.fine.n_cell // 2), "nrhs": nb}
     from paper_2004_09389_amd.hdg import HDG_MIXED_IR
     legs = [("fp64", HDG_FP64, HDG_SMOOTH_BJACOBI), ("mixed", HDG_MIXED, HDG_SMOOTH_BJACOBI),
             ("mixed_ir", HDG_MIXED_IR, HDG_SMOOTH_BJACOBI)]
     if weights is not None:
         legs.append(("learned_ir", HDG_MIXED_IR, HDG_SMOOTH_MLP))
     for name, prec, sm in legs:
-        s = HdgSolver(hier, 3, 3600.0, 9.81, 5960.0, 0.0, 7.292e-5, 1.0, rtol=args.rtol, precision=prec,
+        s = HdgSolver(hier, p, dt, 9.81, 5960.0, 0.0, 7.292e-5, 1.0, rtol=args.rtol, precision=prec,
                       smoother=sm, max_rhs=nb, krylov=2, maxit=200, p1_tail_max=0,
                       use_graph=0 if args.no_graph else 1, ir_inner_rtol=args.ir_inner_rtol)
         if sm == HDG_SMOOTH_MLP:
@@ -242,7 +243,7 @@ def sphere_leg(args, weights, run_steps):
                      "iters": float(np.mean([i.iters for inf in infos for i in inf])),
                      "fallbacks": int(sum(i.fallbacks for inf in infos for i in inf)),
                      "rel_res_max": max(i.rel_res for inf in infos for i in inf), "tuning": tuned}
-        log(f"[bench] sphere {name}: {out[name]['ms_per_step']} ms/step ({out[name]['value']} solves/s) "
+        log(f"[bench] sphere L{level} {name}: {out[name]['ms_per_step']} ms/step ({out[name]['value']} solves/s) "
             f"iters={out[name]['iters']}")
         s.close()
         del s
@@ -386,9 +387,10 @@ def main():
         s.close()
         del s
 
-    sphere_out = None
+    sphere_out = sphere6_out = None
     if not args.no_sphere and not args.pmc_run:
         sphere_out = sphere_leg(args, trained.get("W") if p == 3 else None, run_steps=min(args.steps, 5))
+        sphere6_out = sphere_leg(args, None, run_steps=min(args.steps, 5), level=6, p=2, dt=1800.0, nb=16, seed=300)
     lf_out = None
     if not args.no_lf:
         lf_out = lf_leg(args, p, n, nb, run_steps=min(args.steps, 10))
@@ -493,6 +495,7 @@ def main():
         out["lf_leg"] = lf_out
     if sphere_out is not None:
         out["sphere_leg"] = sphere_out
+        out["sphere_l6_leg"] = sphere6_out
     if not args.no_cpu:
         log("[bench] cpu oracle baseline ...")
         out["cpu_baseline"], sample = cpu_baseline(n, p, dt)
