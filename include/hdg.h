@@ -294,7 +294,9 @@ int hdg_mlp_train(hdg_ctx *ctx, int32_t nrhs, const double *e0, int32_t cycles, 
  * imposes values.  Both drop the captured graphs.  Synchronous. */
 typedef struct {
     int32_t mlp_samples_per_lane; /* samples (facet, rhs) each lane gathers in the learned
-                                     smoothing kernel: 1 or 2 (default 1) */
+                                     smoothing kernel: 1 or 2 (default 1), or 4 = four consecutive
+                                     right-hand sides of one facet with 16-byte loads (applies when
+                                     nrhs is a multiple of 4, else 1 is used) */
     int32_t rhs_block;          /* facet-row kernels (apply, residual, sweep) at nrhs = 4, 8, ..., 64:
                                    1 = one thread per (facet, rhs); 4 = four right-hand sides per
                                    thread with the block's rows staged in LDS (default 4) */

@@ -1543,7 +1543,7 @@ namespace {
 
 void check_tuning(const hdg_tuning &t) {
     const int v = t.mlp_samples_per_lane;
-    HDG_REQUIRE(v == 1 || v == 2, "mlp_samples_per_lane must be 1 or 2");
+    HDG_REQUIRE(v == 1 || v == 2 || v == 4, "mlp_samples_per_lane must be 1, 2 or 4");
     HDG_REQUIRE(t.rhs_block == 1 || t.rhs_block == 4, "rhs_block must be 1 or 4");
 }
 
@@ -1600,8 +1600,9 @@ extern "C" int hdg_autotune(hdg_ctx *c, int32_t nb, hdg_tuning *chosen, void *st
         const short *W1b = c->mlp_wb, *W2b = c->mlp_wb + c->mlp_n1;
         double best = 1e300;
         int best_spl = c->mlp_spl;
-        for (int spl : {1, 2}) {
+        for (int spl : {1, 2, 4}) {
             if (c->opt.smoother != HDG_SMOOTH_MLP) break;   // no learned smoother to tune
+            if (spl == 4 && nb % 4 != 0) continue;           // four right-hand sides per lane
             const double ms = time_launches(s, 10, [&] {
                 hdg::launch_mlp_smooth(c->p, c->n_facet, nb, spl, c->vres, c->vx, nullptr, c->facet_vert, c->nbr,
                                        c->prev, W1b, W2b, c->vx2, s);

@@ -281,6 +281,168 @@ __global__ __launch_bounds__(256) void k_mlp_smooth(int ne, int nb, const VT *__
     }
 }
 
+// Four consecutive right-hand sides of one facet per lane (nrhs a multiple
+// of 4): the patch gathers become 16-byte (FP32) or 2 x 16-byte (FP64) loads
+// of four samples at once.  A wavefront handles 256 samples (16 tiles); the
+// per-sample arithmetic (features, RMS, network, combination) is that of
+// k_mlp_smooth, so the results are bitwise equal.  128-thread blocks keep the
+// staged features of two wavefronts (40 KiB) in LDS.
+template <typename T>
+__device__ __forceinline__ void load4(const T *__restrict__ p, double (&d)[4]) {
+    if constexpr (std::is_same<T, float>::value) {
+        const f4_t a = *reinterpret_cast<const f4_t *>(p);
+        d[0] = a[0]; d[1] = a[1]; d[2] = a[2]; d[3] = a[3];
+    } else {
+        typedef double d2_t __attribute__((ext_vector_type(2)));
+        const d2_t a = *reinterpret_cast<const d2_t *>(p), b = *reinterpret_cast<const d2_t *>(p + 2);
+        d[0] = a.x; d[1] = a.y; d[2] = b.x; d[3] = b.y;
+    }
+}
+template <typename T>
+__device__ __forceinline__ void store4(T *__restrict__ p, const double (&d)[4]) {
+    if constexpr (std::is_same<T, float>::value) {
+        *reinterpret_cast<f4_t *>(p) = f4_t{(float)d[0], (float)d[1], (float)d[2], (float)d[3]};
+    } else {
+        typedef double d2_t __attribute__((ext_vector_type(2)));
+        *reinterpret_cast<d2_t *>(p) = d2_t{d[0], d[1]};
+        *reinterpret_cast<d2_t *>(p + 2) = d2_t{d[2], d[3]};
+    }
+}
+
+template <int M, bool HAS_X, typename VT>
+__global__ __launch_bounds__(128) void k_mlp_smooth_r4(int ne, int nb, const VT *__restrict__ u,
+                                                       const VT *__restrict__ xi, const double *__restrict__ qc,
+                                                       const int *__restrict__ fvert, const int *__restrict__ nbr,
+                                                       const int8_t *__restrict__ prev, const short *__restrict__ W1b,
+                                                       const short *__restrict__ W2b, VT *__restrict__ xo) {
+    constexpr int WS = 256;   // samples per wavefront
+    constexpr int P = M - 1;
+    __shared__ short zs[2][WS * MLP_ZROW];
+    const int nsamp = ne * nb;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int wave = (xcd_block() * blockDim.x + threadIdx.x) >> 6;
+    const int wbase = wave * WS;
+    if (wbase >= nsamp) return;   // whole wavefront leaves together
+    short *Z = zs[w];
+    const size_t NE = (size_t)ne;
+    const int s0 = wbase + 4 * lane;   // the lane's four samples s0 .. s0 + 3: one facet, rhs r0 .. r0 + 3
+    const bool live = s0 < nsamp;
+    const int e = live ? s0 / nb : 0, r0 = live ? s0 - e * nb : 0;
+    float sc[4];
+    double ue[4][M], xe[4][M];
+    if constexpr (HAS_X) {
+#pragma unroll
+        for (int o = 0; o < M; ++o) {
+            double v[4] = {0.0, 0.0, 0.0, 0.0};
+            if (live) load4(xi + ((size_t)e * M + o) * nb + r0, v);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) xe[q][o] = v[q];
+        }
+        if (qc && live) {
+            double q0[4], q1[4];
+            load4(qc + (size_t)fvert[2 * e] * nb + r0, q0);
+            load4(qc + (size_t)fvert[2 * e + 1] * nb + r0, q1);
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int o = 0; o < M; ++o) xe[q][o] += p1_node<P>(o, q0[q], q1[q]);
+        }
+    }
+    // gather the patch of the four samples
+    float f[4][5][M];
+    if (live) {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            const int id = k == 0 ? e : nbr[(size_t)(k - 1) * NE + e];
+            const bool rv = k == 0 ? false : prev[(size_t)(k - 1) * NE + e] != 0;
+#pragma unroll
+            for (int j = 0; j < M; ++j) {
+                double v[4];
+                load4(u + ((size_t)id * M + j) * nb + r0, v);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    f[q][k][rv ? M - 1 - j : j] = (float)v[q];
+                    if (k == 0) ue[q][j] = v[q];
+                }
+            }
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+#pragma unroll
+            for (int k = 0; k < 5; ++k)
+#pragma unroll
+                for (int j = 0; j < M; ++j) f[q][k][j] = 0.f;
+#pragma unroll
+            for (int j = 0; j < M; ++j) ue[q][j] = 0.0;
+        }
+    }
+    // normalise and stage (same order of the RMS sum as k_mlp_smooth)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        float ss = 0.f;
+#pragma unroll
+        for (int k = 0; k < 5; ++k)
+#pragma unroll
+            for (int j = 0; j < M; ++j) ss += f[q][k][j] * f[q][k][j];
+        const float s = sqrtf(ss / (float)(5 * M));
+        const float inv = s > 0.f ? 1.f / s : 0.f;
+        sc[q] = s;
+        short *row = Z + (4 * lane + q) * MLP_ZROW;
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            s4_t v;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) v[j] = j < M ? bf_bits(f[q][k][j] * inv) : (short)0;
+            *reinterpret_cast<s4_t *>(row + 4 * k) = v;
+        }
+        const s4_t zero = {0, 0, 0, 0};
+#pragma unroll
+        for (int k = 5; k < 8; ++k) *reinterpret_cast<s4_t *>(row + 4 * k) = zero;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    MlpWeights W;
+    mlp_load_weights(W, W1b, W2b);
+    const int col = lane & 15, grp = lane >> 4;
+#pragma unroll
+    for (int t = 0; t < WS / 16; ++t) {
+        const short *zr = Z + (t * 16 + col) * MLP_ZROW + 4 * grp;
+        const s4_t z0 = *reinterpret_cast<const s4_t *>(zr);
+        const s4_t z1 = *reinterpret_cast<const s4_t *>(zr + 16);
+        s4_t hb[4];
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            f4_t acc = {0.f, 0.f, 0.f, 0.f};
+            acc = mfma16(W.a1[mt][0], z0, acc);
+            acc = mfma16(W.a1[mt][1], z1, acc);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) hb[mt][v] = bf_bits(fmaxf(acc[v], 0.f));
+        }
+        f4_t out = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) out = mfma16(W.a2[mt], hb[mt], out);
+        if (grp == 0) *reinterpret_cast<f4_t *>(Z + (t * 16 + col) * MLP_ZROW) = out;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (!live) return;
+    double res[M][4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const f4_t out = *reinterpret_cast<const f4_t *>(Z + (4 * lane + q) * MLP_ZROW);
+#pragma unroll
+        for (int o = 0; o < M; ++o) {
+            res[o][q] = ue[q][o] + (double)(sc[q] * out[o]);
+            if constexpr (HAS_X) res[o][q] += xe[q][o];
+        }
+    }
+#pragma unroll
+    for (int o = 0; o < M; ++o) store4(xo + ((size_t)e * M + o) * nb + r0, res[o]);
+}
+
 // Loss and weight gradients over all (facet, rhs) samples of one data set.
 // Targets t are normalised per sample by s.  Every block runs the same
 // number of tile iterations (tiles past the end contribute nothing) so the
@@ -490,7 +652,20 @@ template <typename VT>
 void launch_mlp_smooth(int p, int ne, int nb, int spl, const VT *u, const VT *xi, const double *qc,
                        const int *fvert, const int *nbr, const int8_t *prev, const short *W1b, const short *W2b,
                        VT *xo, hipStream_t s) {
-    spl = spl >= 2 ? 2 : 1;
+    if (spl == 4 && nb % 4 == 0) {
+        const int64_t waves = ((int64_t)ne * nb + 255) / 256;
+        const dim3 grid((unsigned)(((waves + 1) / 2 + 7) / 8 * 8)), block(128);   // multiple of 8 for the XCD remap
+#define MR(M, X) \
+    hipLaunchKernelGGL((k_mlp_smooth_r4<M, X, VT>), grid, block, 0, s, ne, nb, u, xi, qc, fvert, nbr, prev, W1b, W2b, xo)
+#define MR_X(M)                  \
+    if (xi) MR(M, true);         \
+    else MR(M, false);
+        switch (p) { case 1: MR_X(2) break; case 2: MR_X(3) break; case 3: MR_X(4) break; }
+#undef MR_X
+#undef MR
+        return;
+    }
+    spl = spl == 2 ? 2 : 1;   // 4 without a multiple of 4 right-hand sides: one sample per lane
     const int64_t waves = ((int64_t)ne * nb + 64 * spl - 1) / (64 * spl);
     const int64_t blocks = (waves + 3) / 4;
     const dim3 grid((unsigned)(((blocks + 7) / 8) * 8)), block(256);   // multiple of 8 for the XCD remap

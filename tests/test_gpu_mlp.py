@@ -275,6 +275,31 @@ def test_tuning_does_not_change_results():
         assert np.array_equal(o, outs[0])
 
 
+@pytest.mark.parametrize("nb", [4, 8])
+def test_four_rhs_per_lane_bitwise(nb):
+    """Four consecutive right-hand sides per lane in the learned smoothing kernel
+    (16-byte gathers) give the same bits as one and two samples per lane, in the
+    V-cycle (FP64 vectors) and in a mixed solve (FP32 vectors)."""
+    from paper_2004_09389_amd.hdg import HDG_MIXED
+    hier, solver, oracle, mg = setup("torus12_p2_coriolis", max_rhs=8, precision=HDG_MIXED, rtol=1e-10)
+    W1, W2 = weights(solver.m, 12, scale=0.1)
+    solver.mlp_set_weights(W1, W2)
+    r = to_dev(np.random.default_rng(17).standard_normal((solver.n_facet, solver.m, nb)))
+    rc = to_dev(hi.iid_rhs(hier.fine, solver.p, 19, nrhs=nb))
+    outs, sols = [], []
+    for tpw in (1, 2, 4):
+        solver.set_tuning(mlp_samples_per_lane=tpw)
+        outs.append(host(solver.mg_vcycle(r)))
+        lam, info = solver.solve(solver.condense(rc))
+        sols.append((host(lam), [i.iters for i in info]))
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+    for lam, its in sols[1:]:
+        assert np.array_equal(lam, sols[0][0]) and its == sols[0][1]
+    chosen = solver.autotune(nb)
+    assert chosen["mlp_samples_per_lane"] in (1, 2, 4)
+
+
 def test_config1_training_and_gain():
     """Config 1 (8 x 8 torus, p = 1, f = 0, Courant 4): train on random initial
     errors, then compare FGMRES iterations to 1e-10 with block-Jacobi on
