@@ -19,7 +19,11 @@ What it computes (paper section / equation):
 * the Lax-Friedrichs flux (Eq. bilinear_HDG_lax): standard DG and HDG with
   a vector trace, the lowest-order Raviart-Thomas coarse space with the
   L2-projection prolongation and the grad-div coarse form
-  (Eq. coarse_problem_LF), and its geometric multigrid (module lf).
+  (Eq. coarse_problem_LF), and its geometric multigrid (module lf);
+* IMEX Runge-Kutta time stepping around the implicit stage (Eqs.
+  IMEX_HDG_I, IMEX_HDG_II, theta_method) with the Theta, ARS2(2,3,2),
+  SSP2(3,2,2) and ARS3(4,4,3) tableaux, explicit Coriolis, and the Delta_2
+  error of Eq. L2_error (module imex).
 
 Functions without an independent pin say "parity unpinned" in their
 docstring.

@@ -199,7 +199,21 @@ class DgOracle(LocalOperators):
     """Standard (non-hybridised) upwind DG system, assembled and solved directly."""
 
     def matrix(self):
-        n, kap, tau, dt = self.n, self.kappa, self.tau, self.dt
+        """The implicit-stage system  M + kappa K + dt F  (CSR)."""
+        return self._assemble(1.0, self.kappa, self.dt)
+
+    def parts(self):
+        """The semi-discrete pieces in symmetric variables, each CSR:
+        mass M, the kappa-term K (volume and upwind facet terms at kappa = 1)
+        and the Coriolis term F (at dt = 1), so that the stage system is
+        M + kappa K + dt F and the time derivative is M q' = -c K q - F q."""
+        out = [self._assemble(1.0, 0.0, 0.0), self._assemble(0.0, 1.0, 0.0), self._assemble(0.0, 0.0, 1.0)]
+        for a in out:
+            a.eliminate_zeros()
+        return tuple(out)
+
+    def _assemble(self, cm, kap, dt):
+        n, tau = self.n, self.tau
         nk = self.M.shape[0]
         topo, nrm = self.topo, self.geo.fnormal
         rows, cols, vals = [], [], []
@@ -214,9 +228,9 @@ class DgOracle(LocalOperators):
 
         allc = np.arange(nk)
         # cell terms: (phi,psi) + (u,w) + dt (f k x u, w) - kappa (u, grad psi) - kappa (phi, div w)
-        add(allc, 0, allc, 0, self.M)
+        add(allc, 0, allc, 0, cm * self.M)
         for d in range(2):
-            add(allc, 1 + d, allc, 1 + d, self.M)
+            add(allc, 1 + d, allc, 1 + d, cm * self.M)
             add(allc, 0, allc, 1 + d, -kap * self.Q[d])
             add(allc, 1 + d, allc, 0, -kap * self.Q[d])
         add(allc, 1, allc, 2, -dt * self.Mf)
