@@ -244,6 +244,73 @@ int hdg_recover(hdg_ctx *ctx, int32_t nrhs, const double *r_cell, const double *
 void hdg_destroy(hdg_ctx *ctx);
 const char *hdg_last_error(void);
 
+/* ------------------------------------------------------------------ IMEX time stepping
+ *
+ * Time discretisation section (Eqs. IMEX_HDG_I, IMEX_HDG_II, theta_method):
+ * the semi-discrete linear SWE  d/dt M(q) = N_0(q) + L(q)  advanced by an
+ * additive (IMEX) Runge-Kutta method, the flux terms L implicitly through
+ * this context's HDG solve and the Coriolis source N_0(q) = -f k x u
+ * explicitly (the paper's splitting; f is a constant, an f-plane).  Stage i
+ * solves
+ *     M Q_i - at_ii dt L(Q_i) = M q_n + dt sum_{j<i} (a_ij N_0(Q_j) + at_ij L(Q_j))
+ * by condense / solve / recover (zero initial trace), and the step ends with
+ *     M q_{n+1} = M q_n + dt sum_i (b_i N_0(Q_i) + bt_i L(Q_i)).
+ * Everything runs on DG coefficients: M^-1 N_0 rotates the velocity
+ * coefficients, and dt M^-1 L(Q_j) of an implicit stage is (Q_j - R_j) / at_jj,
+ * R_j the stage's right-hand side in coefficients -- exact for the computed
+ * Q_j and its trace, whatever the solver residual.  A first stage that is
+ * explicit (Q_1 = q_n) and whose flux term is used (Theta) needs
+ * dt M^-1 L(q_n): evaluated once per call (hdg_dg_tendency) and carried to the
+ * next step from the last stage when the tableau is stiffly accurate.
+ *
+ * The context must be set up for this splitting: prm.dt = gamma dt, gamma the
+ * common value of the nonzero entries on the diagonal of at, and
+ * prm.f0 = prm.omega = 0 (HDG_EINVAL otherwise).  Any flux, mesh and
+ * precision; the stage solves use the context's options (rtol, smoother). */
+#define HDG_IMEX_THETA  0   /* Theta(theta): a = [[0,0],[1,0]], at = [[0,0],[1-theta,theta]],
+                               b = [1,0], bt = [1-theta,theta] */
+#define HDG_IMEX_ARS232 1   /* ARS2(2,3,2): gamma = 1 - 1/sqrt 2, delta = -2 sqrt(2)/3 */
+#define HDG_IMEX_SSP322 2   /* SSP2(3,2,2) */
+#define HDG_IMEX_ARS443 3   /* ARS3(4,4,3) */
+#define HDG_IMEX_MAX_STAGES 5
+typedef struct {
+    int32_t stages;             /* s, 1..HDG_IMEX_MAX_STAGES */
+    double a[5][5];             /* explicit part, strictly lower triangular */
+    double at[5][5];            /* implicit part, lower triangular */
+    double b[5], bt[5];         /* weights */
+} hdg_imex_tableau;
+typedef struct {
+    int32_t steps, solves;      /* completed steps, implicit stage solves */
+    int32_t iters_total;        /* Krylov iterations summed over solves (max over right-hand sides) */
+    int32_t iters_max;          /* most iterations of one solve */
+    int32_t status;             /* HDG_OK, or HDG_ENOTCONV when a solve stopped at maxit */
+    double rel_res_max;         /* largest final relative trace residual */
+} hdg_imex_info;
+
+/* The tableaux of the IMEX methods section (theta used by HDG_IMEX_THETA only). */
+int hdg_imex_tableau_get(int32_t method, double theta, hdg_imex_tableau *out);
+
+/* Device workspace of hdg_imex_run, in doubles: two cell arrays per stage, one
+ * more for the carried flux term and two trace arrays. */
+int hdg_imex_work_size(const hdg_ctx *ctx, const hdg_imex_tableau *tab, int32_t nrhs, int64_t *doubles);
+
+/* `steps` IMEX steps of size dt from q (device, [n_cell][3][n_loc][nrhs], (h, u1, u2)
+ * coefficients), in place.  f: the explicit Coriolis parameter.  work: device, at
+ * least hdg_imex_work_size doubles, 16-byte aligned.  info (host) may be NULL.
+ * Returns HDG_ENOTCONV (steps still completed) when a stage solve stopped at maxit.
+ * Synchronises the stream (every stage solve does). */
+int hdg_imex_run(hdg_ctx *ctx, const hdg_imex_tableau *tab, double dt, double f, int32_t nrhs, int32_t steps,
+                 double *q, double *work, hdg_imex_info *info, void *stream);
+
+/* Explicit flux evaluation  out = dt M^-1 (L(q) + N_c(q)),  N_c the context's own
+ * (implicit) Coriolis term: with lam(q) the DG trace of q -- {{phi}} + [[u]]/(2 tau)
+ * for the upwind flux, {{u}} + [[phi]]/(2 tau) for Lax-Friedrichs, the values for
+ * which the hybridised and the standard DG forms coincide -- the context's stage
+ * equations with trace lam(q) hold for q and a right-hand side r; then
+ * out = (dt / prm.dt) (q - r) (Eq. linear_hybridized; L as in Eq. L_definitions).
+ * q, out: device, [n_cell][3][n_loc][nrhs], must not alias. */
+int hdg_dg_tendency(hdg_ctx *ctx, int32_t nrhs, double dt, const double *q, double *out, void *stream);
+
 /* ------------------------------------------------------------------ learned smoother
  *
  * An extension beyond the paper (whose conclusion names better smoothers as

@@ -39,6 +39,7 @@ import scipy.sparse.linalg as spla
 
 from .fem import to_3d, volume_points
 from .hdg import DgOracle
+from .lf import DgLfOracle
 
 METHODS = ("theta", "ars232", "ssp322", "ars443")
 
@@ -82,10 +83,16 @@ def tableau(method: str, theta: float = 0.5):
 
 class LinearSwe:
     """Semi-discrete linear SWE  M q' = L q + N q  in symmetric variables, with
-    L = -c K (upwind DG flux terms) and N = -F (Coriolis source)."""
+    L = -c K (DG flux terms, upwind or Lax-Friedrichs) and N = -F (Coriolis
+    source)."""
 
-    def __init__(self, mesh, p, g=1.0, H=1.0, f=0.0, tau=1.0):
-        self.dg = DgOracle(mesh, p, dt=1.0, g=g, H=H, f0=f, tau=tau)
+    def __init__(self, mesh, p, g=1.0, H=1.0, f=0.0, tau=1.0, flux="upwind"):
+        if flux == "upwind":
+            self.dg = DgOracle(mesh, p, dt=1.0, g=g, H=H, f0=f, tau=tau)
+        elif flux == "lf":
+            self.dg = DgLfOracle(mesh, p, dt=1.0, g=g, H=H, f0=f, tau=tau)
+        else:
+            raise ValueError(f"unknown flux {flux!r}")
         self.c, self.hscale, self.n = self.dg.c, self.dg.hscale, self.dg.n
         M, K, F = self.dg.parts()
         self.M = M.tocsc()

@@ -169,7 +169,19 @@ class DgLfOracle(LfLocal):
     """Standard DG with the Lax-Friedrichs flux, assembled and solved directly."""
 
     def matrix(self):
-        n, kap, tau, dt = self.n, self.kappa, self.tau, self.dt
+        """The implicit-stage system  M + kappa K + dt F  (CSR)."""
+        return self._assemble(1.0, self.kappa, self.dt)
+
+    def parts(self):
+        """Mass M, the kappa-term K (at kappa = 1) and the Coriolis term F (at
+        dt = 1), each CSR, in symmetric variables (see DgOracle.parts)."""
+        out = [self._assemble(1.0, 0.0, 0.0), self._assemble(0.0, 1.0, 0.0), self._assemble(0.0, 0.0, 1.0)]
+        for a in out:
+            a.eliminate_zeros()
+        return tuple(out)
+
+    def _assemble(self, cm, kap, dt):
+        n, tau = self.n, self.tau
         nk = self.M.shape[0]
         topo, nrm = self.topo, self.geo.fnormal
         rows, cols, vals = [], [], []
@@ -182,9 +194,9 @@ class DgLfOracle(LfLocal):
             vals.append(blk.ravel())
 
         allc = np.arange(nk)
-        add(allc, 0, allc, 0, self.M)
+        add(allc, 0, allc, 0, cm * self.M)
         for d in range(2):
-            add(allc, 1 + d, allc, 1 + d, self.M)
+            add(allc, 1 + d, allc, 1 + d, cm * self.M)
             add(allc, 0, allc, 1 + d, -kap * self.Q[d])
             add(allc, 1 + d, allc, 0, -kap * self.Q[d])
         add(allc, 1, allc, 2, -dt * self.Mf)

@@ -915,7 +915,7 @@ void setup_impl(const hdg_mesh *levels, int nlev, const int32_t *const *parents,
     c->d_fcell = d_fcell;
     c->d_floc = d_floc;
     dev_release(c, Sloc, (size_t)c->nt * c->nt * nk * sizeof(double));
-    dev_release(c, d_corners, corners.size() * sizeof(double));
+    c->corners = d_corners;   // kept for the explicit flux evaluation (hdg_dg_tendency)
 
     // ---- vertex -> facet-end CSR for the trace -> P1 restriction
     if (!lf) {

@@ -175,6 +175,9 @@ struct hdg_ctx {
     double *Wr = nullptr;      // [nc][nt]  A^-1 B, phi rows / hscale       (recover)
     int32_t *cell_facet = nullptr;  // [3][n_cell]
     int8_t *cell_rev = nullptr;     // [3][n_cell]
+    double *corners = nullptr;      // [n_cell][3][3] unwrapped corner coordinates
+    double *dg_half = nullptr;      // explicit flux evaluation: trace shares [n_facet][2][m][max_rhs]
+    int *dg_err = nullptr;          // its singular-matrix flag
 
     // facet block rows, component-major [slot][a][b][n_facet]
     int32_t *nbr = nullptr;     // [4][n_facet]

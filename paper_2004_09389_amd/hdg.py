@@ -63,6 +63,21 @@ class HdgTuning(ctypes.Structure):
     _fields_ = [("mlp_samples_per_lane", ctypes.c_int32), ("rhs_block", ctypes.c_int32)]
 
 
+HDG_IMEX_THETA, HDG_IMEX_ARS232, HDG_IMEX_SSP322, HDG_IMEX_ARS443 = 0, 1, 2, 3
+IMEX_METHODS = {"theta": HDG_IMEX_THETA, "ars232": HDG_IMEX_ARS232, "ssp322": HDG_IMEX_SSP322,
+                "ars443": HDG_IMEX_ARS443}
+
+
+class HdgImexTableau(ctypes.Structure):
+    _fields_ = [("stages", ctypes.c_int32), ("a", (ctypes.c_double * 5) * 5), ("at", (ctypes.c_double * 5) * 5),
+                ("b", ctypes.c_double * 5), ("bt", ctypes.c_double * 5)]
+
+
+class HdgImexInfo(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int32), ("solves", ctypes.c_int32), ("iters_total", ctypes.c_int32),
+                ("iters_max", ctypes.c_int32), ("status", ctypes.c_int32), ("rel_res_max", ctypes.c_double)]
+
+
 _P = ctypes.c_void_p
 _I = ctypes.c_int32
 _SIGS = {
@@ -90,6 +105,11 @@ _SIGS = {
     "hdg_mlp_make_data": (_I, [_P, _I, _P, _P, _P, _I, _P]),
     "hdg_mlp_loss_grad": (_I, [_P, _I, _P, _P, ctypes.POINTER(ctypes.c_double), _P, _P, _P]),
     "hdg_mlp_train": (_I, [_P, _I, _P, _I, _I, _I, ctypes.c_double, _P, _P]),
+    "hdg_imex_tableau_get": (_I, [_I, ctypes.c_double, ctypes.POINTER(HdgImexTableau)]),
+    "hdg_imex_work_size": (_I, [_P, ctypes.POINTER(HdgImexTableau), _I, ctypes.POINTER(ctypes.c_int64)]),
+    "hdg_imex_run": (_I, [_P, ctypes.POINTER(HdgImexTableau), ctypes.c_double, ctypes.c_double, _I, _I, _P, _P,
+                          ctypes.POINTER(HdgImexInfo), _P]),
+    "hdg_dg_tendency": (_I, [_P, _I, ctypes.c_double, _P, _P, _P]),
 }
 
 _lib = None
@@ -275,6 +295,31 @@ class HdgSolver:
         lam, info = self.solve(rhat)
         return self.recover(r_cell, lam), lam, info
 
+    # ------------------------------------------------------------------ IMEX time stepping
+    def dg_tendency(self, q, dt: float, out=None):
+        """dt M^-1 (L(q) + N_c(q)): the explicit flux evaluation (hdg_dg_tendency)."""
+        nb = self._nrhs(q, 4)
+        out = self.cell_zeros(nb) if out is None else out
+        _check(self.lib.hdg_dg_tendency(self.ctx, nb, dt, _ptr(q), _ptr(out), _stream()))
+        return out
+
+    def imex_run(self, tableau: "HdgImexTableau", dt: float, f: float, q, steps: int, work=None,
+                 allow_notconv: bool = False):
+        """`steps` IMEX steps of size dt on q in place (hdg_imex_run); the context
+        must have been set up with dt = gamma * dt and f0 = omega = 0.
+        Returns the HdgImexInfo."""
+        import torch
+        nb = self._nrhs(q, 4)
+        if work is None:
+            n = ctypes.c_int64()
+            _check(self.lib.hdg_imex_work_size(self.ctx, ctypes.byref(tableau), nb, ctypes.byref(n)))
+            work = torch.empty(n.value, dtype=torch.float64, device="cuda")
+        info = HdgImexInfo()
+        allow = (HDG_OK, HDG_ENOTCONV) if allow_notconv else (HDG_OK,)
+        _check(self.lib.hdg_imex_run(self.ctx, ctypes.byref(tableau), dt, f, nb, steps, _ptr(q), _ptr(work),
+                                     ctypes.byref(info), _stream()), allow)
+        return info
+
     # ------------------------------------------------------------------ learned smoother
     def mlp_set_weights(self, W1, W2):
         """W1 (64, 5(p+1)), W2 (p+1, 64); stored as FP32 (Adam state reset)."""
@@ -349,3 +394,16 @@ class HdgSolver:
 
 def device_copy(src, dst):
     _check(load_library().hdg_copy(_ptr(src), _ptr(dst), src.numel(), _stream()))
+
+
+def imex_tableau(method: str, theta: float = 0.5) -> HdgImexTableau:
+    """The library's tableau of one of IMEX_METHODS (hdg_imex_tableau_get)."""
+    t = HdgImexTableau()
+    _check(load_library().hdg_imex_tableau_get(IMEX_METHODS[method], theta, ctypes.byref(t)))
+    return t
+
+
+def imex_gamma(t: HdgImexTableau) -> float:
+    """The common nonzero diagonal entry of the implicit tableau (the stage
+    operator is set up for dt_stage = gamma * dt)."""
+    return next(t.at[i][i] for i in range(t.stages) if t.at[i][i] != 0.0)

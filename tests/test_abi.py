@@ -65,7 +65,8 @@ def test_struct_offsets_match_c_compiler(tmp_path):
     if shutil.which("gcc") is None:
         pytest.skip("gcc not available")
     structs = {"hdg_mesh": hdg.HdgMesh, "hdg_params": hdg.HdgParams, "hdg_options": hdg.HdgOptions,
-               "hdg_solve_info": hdg.HdgSolveInfo, "hdg_sizes": hdg.HdgSizes, "hdg_tuning": hdg.HdgTuning}
+               "hdg_solve_info": hdg.HdgSolveInfo, "hdg_sizes": hdg.HdgSizes, "hdg_tuning": hdg.HdgTuning,
+               "hdg_imex_tableau": hdg.HdgImexTableau, "hdg_imex_info": hdg.HdgImexInfo}
     lines = ["#include <stdio.h>", "#include <stddef.h>", f'#include "{HEADER}"', "int main(void) {"]
     for cname, py in structs.items():
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
@@ -82,3 +83,33 @@ def test_struct_offsets_match_c_compiler(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(py), cname
         for fname, _ in py._fields_:
             assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
+
+
+@pytest.mark.parametrize("method", ["theta", "ars232", "ssp322", "ars443"])
+def test_library_tableaux_equal_the_oracles(method):
+    """The library's tableaux (host code, no GPU) against the oracle's, both
+    typed from the IMEX methods section; the oracle's are pinned by the order
+    conditions."""
+    import numpy as np
+    from oracle.imex import tableau
+    for theta in ((0.5, 0.55) if method == "theta" else (0.5,)):
+        t = hdg.imex_tableau(method, theta)
+        a, at, b, bt = tableau(method, theta)
+        s = len(b)
+        assert t.stages == s
+        lib_a = np.array([[t.a[i][j] for j in range(5)] for i in range(5)])
+        lib_at = np.array([[t.at[i][j] for j in range(5)] for i in range(5)])
+        assert np.abs(lib_a[:s, :s] - a).max() < 1e-15 and np.abs(lib_at[:s, :s] - at).max() < 1e-15
+        assert np.abs(np.array(t.b[:s]) - b).max() < 1e-15 and np.abs(np.array(t.bt[:s]) - bt).max() < 1e-15
+        assert not lib_a[s:].any() and not lib_at[s:].any()
+
+
+def test_imex_entry_points_reject_bad_arguments_without_gpu():
+    lib = hdg.load_library()
+    t = hdg.HdgImexTableau()
+    assert lib.hdg_imex_tableau_get(7, 0.5, ctypes.byref(t)) == hdg.HDG_EINVAL
+    assert lib.hdg_imex_tableau_get(hdg.HDG_IMEX_THETA, 0.0, ctypes.byref(t)) == hdg.HDG_EINVAL
+    n = ctypes.c_int64()
+    assert lib.hdg_imex_work_size(None, ctypes.byref(t), 1, ctypes.byref(n)) == hdg.HDG_EINVAL
+    assert lib.hdg_imex_run(None, ctypes.byref(t), 0.1, 0.0, 1, 1, None, None, None, None) == hdg.HDG_EINVAL
+    assert lib.hdg_dg_tendency(None, 1, 0.1, None, None, None) == hdg.HDG_EINVAL

@@ -122,6 +122,22 @@ def test_observed_order_against_the_matrix_exponential(method, theta, f, order):
     assert abs(rate - order) < 0.15, (errs, rate)
 
 
+@pytest.mark.parametrize("method,order", [("ars232", 2), ("ars443", 3)])
+def test_lax_friedrichs_flux_order_against_the_matrix_exponential(method, order):
+    """The same exact reference with the Lax-Friedrichs flux terms."""
+    m = hi.torus(2)
+    swe = LinearSwe(m, 1, g=1.0, H=1.0, f=1.0, flux="lf")
+    x0 = swe.to_vec(hi.iid_rhs(m, 1, seed=7))
+    xe = sl.expm(0.5 * swe.generator()) @ x0
+    errs = []
+    for k in (16, 32, 64):
+        x = x0.copy()
+        for _ in range(k):
+            x = swe.step(tableau(method), 0.5 / k, x)
+        errs.append(np.linalg.norm(x - xe) / np.linalg.norm(xe))
+    assert abs(math.log2(errs[1] / errs[2]) - order) < 0.15, errs
+
+
 @pytest.mark.parametrize("method", METHODS)
 def test_mass_is_conserved(method):
     """The flux terms are conservative and the Coriolis term does not act on
