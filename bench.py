@@ -64,6 +64,8 @@ def parse():
     ap.add_argument("--no-sphere", action="store_true", help="skip the batched level-7 sphere leg")
     ap.add_argument("--sphere-only", action="store_true", help="run only the batched level-7 sphere leg")
     ap.add_argument("--sphere-nrhs", type=int, default=32)
+    ap.add_argument("--no-imex", action="store_true", help="skip the IMEX time-stepping leg")
+    ap.add_argument("--imex-only", action="store_true", help="run only the IMEX time-stepping leg")
     ap.add_argument("--ir-inner-rtol", type=float, default=1e-4, help="mixed_ir: reduction per inner solve")
     ap.add_argument("--pmc-run", action="store_true",
                     help="short run for hardware counters: mixed leg only, plus a reference copy kernel")
@@ -253,6 +255,54 @@ def sphere_leg(args, weights, run_steps, level=7, p=3, dt=3600.0, nb=None, seed=
     return out
 
 
+def imex_leg(args, n=256, p=3, run_steps=20):
+    """IMEX time stepping of the linear SWE on the paper's stationary vortex
+    (L-Up: flat bathymetry, upwind flux; c_g = 1.89, f = 4 pi) at refinement
+    r = log2(n), degree p, the time step of the time-step-size section, every
+    tableau of the IMEX methods section, Coriolis explicit.  Per method: time
+    per step (stage right-hand sides, condense, solve, recover), solves per
+    step, Krylov iterations per solve at rtol, the paper's runtime unit
+    (seconds per step per cell unknown) and the drift of the steady state
+    ||q - q_0|| / ||q_0|| after the timed steps."""
+    import torch
+
+    import hdg_inputs as hi
+    from paper_2004_09389_amd.hdg import (HDG_MIXED, HDG_SMOOTH_BJACOBI, HDG_SMOOTH_CHEBYSHEV, HdgSolver,
+                                          imex_gamma, imex_tableau)
+    v = hi.Vortex()
+    hier = hi.torus_hierarchy(n, args.coarse)
+    dt, _ = hi.paper_time_step(n, p)
+    q0 = torch.from_numpy(hi.vortex_coefficients(hier.fine, p, v)).to("cuda")
+    n_dof = 3 * hier.fine.n_cell * (p + 1) * (p + 2) // 2
+    out = {"workload": f"vortex_torus{n}x{n}_p{p}", "dt": dt, "n_cell_dof": n_dof, "rtol": args.rtol,
+           "precision": "mixed", "steps_timed": run_steps}
+    for name, method, theta in (("theta_0.5", "theta", 0.5), ("theta_0.55", "theta", 0.55),
+                                ("ars232", "ars232", 0.5), ("ssp322", "ssp322", 0.5), ("ars443", "ars443", 0.5)):
+        tab = imex_tableau(method, theta)
+        s = HdgSolver(hier, p, imex_gamma(tab) * dt, v.c_g, v.c_g, 0.0, 0.0, 1.0, rtol=args.rtol,
+                      precision=HDG_MIXED, krylov=2, maxit=200, p1_tail_max=args.tail_max,
+                      smoother=HDG_SMOOTH_CHEBYSHEV if args.smoother == "chebyshev" else HDG_SMOOTH_BJACOBI,
+                      use_graph=0 if args.no_graph else 1)
+        q = q0.clone()
+        s.imex_run(tab, dt, v.f, q, 1)                   # warm-up (graphs, buffers)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        info = s.imex_run(tab, dt, v.f, q, run_steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t
+        drift = float(torch.linalg.norm(q - q0) / torch.linalg.norm(q0))
+        out[name] = {"ms_per_step": round(1e3 * el / run_steps, 4),
+                     "solves_per_step": info.solves / run_steps,
+                     "iters_per_solve": round(info.iters_total / max(info.solves, 1), 2),
+                     "iters_max": info.iters_max, "rel_res_max": info.rel_res_max,
+                     "s_per_step_per_unknown": el / run_steps / n_dof, "drift": drift}
+        log(f"[bench] imex {name}: {out[name]['ms_per_step']} ms/step, {out[name]['solves_per_step']} solves/step, "
+            f"{out[name]['iters_per_solve']} its/solve, drift {drift:.2e}")
+        s.close()
+        del s
+    return out
+
+
 def main():
     args = parse()
     if args.pmc_run:
@@ -279,6 +329,9 @@ def main():
         return
     if args.lf_only:
         print(json.dumps({"lf_leg": lf_leg(args, p, n, nb, run_steps=args.steps)}), flush=True)
+        return
+    if args.imex_only:
+        print(json.dumps({"imex_leg": imex_leg(args, n, p, run_steps=args.steps)}), flush=True)
         return
     dt = 8.0 / n
     t0 = time.perf_counter()
@@ -394,6 +447,9 @@ def main():
     lf_out = None
     if not args.no_lf:
         lf_out = lf_leg(args, p, n, nb, run_steps=min(args.steps, 10))
+    imex_out = None
+    if not args.no_imex and not args.pmc_run:
+        imex_out = imex_leg(args, n, p, run_steps=min(args.steps, 20))
 
     if args.pmc_run:
         # reference copy of known size for scaling the profiler's byte counters
@@ -493,6 +549,8 @@ def main():
                         "inverses) and the end-to-end solution at rtol; condense and recover are FP64 in both"}
     if lf_out is not None:
         out["lf_leg"] = lf_out
+    if imex_out is not None:
+        out["imex_leg"] = imex_out
     if sphere_out is not None:
         out["sphere_leg"] = sphere_out
         out["sphere_l6_leg"] = sphere6_out

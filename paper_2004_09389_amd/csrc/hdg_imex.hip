@@ -141,27 +141,26 @@ __global__ __launch_bounds__(64) void k_dg_tendency(int nk, int nb, double scale
                                                     const double *__restrict__ q, const double *__restrict__ half,
                                                     double *__restrict__ out, int *__restrict__ err) {
     constexpr int n = (P + 1) * (P + 2) / 2, m = P + 1, nc = 3 * n, M = NU * m, nt = 3 * M;
-    constexpr int LD = nc + TEND_MAX_RHS;
-    __shared__ double aug[nc * LD];
-    __shared__ double lam[nt * TEND_MAX_RHS];
-    __shared__ double fac[nc];
+    // LDS sized for the call's nb (tend_lds_bytes): [nc][nc + nb] | [nt][nb] | [nc]
+    extern __shared__ double tsm[];
+    const int LD = nc + nb, W = nc + nb;
+    double *aug = tsm, *lam = tsm + nc * LD, *fac = lam + nt * nb;
     const int K = blockIdx.x, lane = threadIdx.x;
     if (K >= nk) return;
     const size_t NK = (size_t)nk;
-    const int W = nc + nb;
 
     for (int idx = lane; idx < nt * nb; idx += 64) {
         const int g = idx / nb, r = idx - g * nb, i = g / M, a = g - i * M;
         const int e = cell_facet[i * NK + K], rev = cell_rev[i * NK + K];
         const double v = half[(((size_t)e * 2 + 0) * M + a) * nb + r] + half[(((size_t)e * 2 + 1) * M + a) * nb + r];
-        lam[tend_loc<P, NU>(i, a, rev) * TEND_MAX_RHS + r] = v;
+        lam[tend_loc<P, NU>(i, a, rev) * nb + r] = v;
     }
     for (int idx = lane; idx < nc * nc; idx += 64) aug[(idx / nc) * LD + idx % nc] = Ar[(size_t)idx * NK + K];
     __syncthreads();
     for (int idx = lane; idx < nc * nb; idx += 64) {
         const int a = idx / nb, r = idx - a * nb;
         double s = q[((size_t)K * nc + a) * nb + r];
-        for (int j = 0; j < nt; ++j) s += Wr[(size_t)(a * nt + j) * NK + K] * lam[j * TEND_MAX_RHS + r];
+        for (int j = 0; j < nt; ++j) s += Wr[(size_t)(a * nt + j) * NK + K] * lam[j * nb + r];
         aug[a * LD + nc + r] = s;
     }
     __syncthreads();
@@ -305,8 +304,9 @@ void dg_tendency(hdg_ctx *c, int nb, double dt, const double *q, double *out, hi
 #define HALF(P, NU)                                                                                              \
     hipLaunchKernelGGL((k_dg_half<P, NU>), dim3(grid), dim3(block), 0, s, c->n_cell, nb, c->geom, c->tau, c->hscale, \
                        c->corners, c->cell_facet, c->cell_rev, q, half)
-#define TEND(P, NU)                                                                                             \
-    hipLaunchKernelGGL((k_dg_tendency<P, NU>), dim3(c->n_cell), dim3(64), 0, s, c->n_cell, nb, scale, c->Ar, c->Wr, \
+    const size_t lds = (size_t)(c->nc * (c->nc + nb) + c->nt * nb + c->nc) * sizeof(double);
+#define TEND(P, NU)                                                                                               \
+    hipLaunchKernelGGL((k_dg_tendency<P, NU>), dim3(c->n_cell), dim3(64), lds, s, c->n_cell, nb, scale, c->Ar, c->Wr, \
                        c->cell_facet, c->cell_rev, q, half, out, err)
     if (c->nu == 1) {
         switch (c->p) {
