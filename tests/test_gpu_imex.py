@@ -165,3 +165,24 @@ def test_vortex_converges_at_the_papers_rate_through_the_gpu():
         errs.append(e)
         s.close()
     assert math.log2(errs[0] / errs[1]) >= 1.5
+
+
+@pytest.mark.parametrize("precision", ["mixed", "mixed_ir"])
+@pytest.mark.parametrize("method", ["theta", "ars443"])
+def test_imex_with_mixed_precision_stage_solves(method, precision):
+    """Stage solves in HDG_MIXED / HDG_MIXED_IR (FP64 true residual to rtol
+    1e-11): the steps agree with the oracle to 1e-8."""
+    from oracle.imex import LinearSwe, tableau
+    from paper_2004_09389_amd.hdg import HDG_MIXED, HDG_MIXED_IR, imex_gamma, imex_tableau
+    n, p, dt, f, steps = 16, 3, 0.03, 2.0, 2
+    m = hi.torus(n)
+    tab = imex_tableau(method, 0.5)
+    prec = HDG_MIXED if precision == "mixed" else HDG_MIXED_IR
+    s = solver(hi.torus_hierarchy(n, 4), p, imex_gamma(tab) * dt, precision=prec, rtol=1e-11, krylov=2)
+    q0 = hi.iid_rhs(m, p, 17)
+    q = to_dev(q0)
+    info = s.imex_run(tab, dt, f, q, steps)
+    assert info.status == 0 and info.rel_res_max <= 1e-11
+    ref = LinearSwe(m, p, g=G, H=H, f=f).run(tableau(method, 0.5), dt, steps, q0)
+    assert rel(host(q), ref) < 1e-8
+    s.close()
