@@ -23,7 +23,12 @@ What it computes (paper section / equation):
 * IMEX Runge-Kutta time stepping around the implicit stage (Eqs.
   IMEX_HDG_I, IMEX_HDG_II, theta_method) with the Theta, ARS2(2,3,2),
   SSP2(3,2,2) and ARS3(4,4,3) tableaux, explicit Coriolis, and the Delta_2
-  error of Eq. L2_error (module imex).
+  error of Eq. L2_error (module imex);
+* the non-hybridised DG solver of the native DG section: GMRES with the
+  three-step approximate Schur-complement preconditioner (Eqs.
+  native_matrix_representation, S_approx_diag), its sub-solves read as
+  cell-block Jacobi and a two-level cycle with the Galerkin P1 operator
+  (module dgschur).
 
 Functions without an independent pin say "parity unpinned" in their
 docstring.
