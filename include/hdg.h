@@ -311,6 +311,42 @@ int hdg_imex_run(hdg_ctx *ctx, const hdg_imex_tableau *tab, double dt, double f,
  * q, out: device, [n_cell][3][n_loc][nrhs], must not alias. */
 int hdg_dg_tendency(hdg_ctx *ctx, int32_t nrhs, double dt, const double *q, double *out, void *stream);
 
+/* ------------------------------------------------------------------ non-hybridised DG baseline
+ *
+ * Native DG section (Eqs. native_dg_system, native_matrix_representation,
+ * S_approx_diag): the same implicit stage solved without hybridisation, as the
+ * comparison the paper makes.  GMRES (restarted, flexible, true-residual
+ * restarts) on the standard upwind DG system  A q = R  (A: the stage matrix
+ * split by fields into [[A_pp, A_pu], [A_up, A_uu]], R the mass-weighted
+ * right-hand side), preconditioned by three steps:
+ *     V = A_uu~^-1 R_u;   Phi = S~^-1 (R_p - A_pu V);   U = A_uu~^-1 (R_u - A_up Phi),
+ *     S = A_pp - A_pu diag(A_uu)^-1 A_up.
+ * A_uu~^-1: the exact inverse of each cell's diagonal block of A_uu (in place of
+ * the paper's ILU).  S~^-1: one two-level cycle (in place of one GAMG V-cycle):
+ * Chebyshev smoothing of degree nu_pre / nu_post preconditioned by the inverse
+ * of each cell's own block of S on [0.1, 1.1] lambda_max (20 power steps at
+ * setup), and the coarse correction on conforming P1 with the Galerkin operator
+ * P^T S P (P: nodal interpolation of P1 into the DG phi space) solved by one P1
+ * multigrid V-cycle with Galerkin coarsening (p1_nu, p1_omega).  Upwind flux
+ * only; uses the context's rtol, maxit and restart.
+ *
+ * Vectors of hdg_dgs_apply / hdg_dgs_precondition are DG coefficient vectors in
+ * the symmetric variables (phi = h sqrt(g/H), u), device, [n_cell][3][n_loc][nrhs];
+ * A acts on them as the mass-weighted stage equations. */
+/* Build the baseline's operators on this context (levels / parents as for
+ * hdg_setup, the finest level the context's mesh).  Synchronous; idempotent. */
+int hdg_dgs_setup(hdg_ctx *ctx, const hdg_mesh *levels, int32_t n_levels, const int32_t *const *parents);
+/* y = A x (stage matrix of the standard DG form).  x, y must not alias. */
+int hdg_dgs_apply(hdg_ctx *ctx, int32_t nrhs, const double *x, double *y, void *stream);
+/* z = the three-step preconditioner applied to r.  r, z must not alias. */
+int hdg_dgs_precondition(hdg_ctx *ctx, int32_t nrhs, const double *r, double *z, void *stream);
+/* Solve the stage for the DG coefficients r_cell of (r_h, r_u) (as hdg_condense) and
+ * return q_cell = (h, u1, u2) (as hdg_recover); stops when ||R - A q|| <= rtol ||R||
+ * per right-hand side.  info (host) [nrhs] may be NULL.  Returns HDG_ENOTCONV at maxit.
+ * Synchronises the stream. */
+int hdg_dgs_solve(hdg_ctx *ctx, int32_t nrhs, const double *r_cell, double *q_cell, hdg_solve_info *info,
+                  void *stream);
+
 /* ------------------------------------------------------------------ learned smoother
  *
  * An extension beyond the paper (whose conclusion names better smoothers as

@@ -869,6 +869,7 @@ void setup_impl(const hdg_mesh *levels, int nlev, const int32_t *const *parents,
     std::vector<double> ref;
     for (auto *v : {&R.M, &R.G, &R.E, &R.T, &R.F, &R.qx, &R.qw, &R.Phi}) ref.insert(ref.end(), v->begin(), v->end());
     double *d_ref = dev_upload(c, ref);
+    c->ref = d_ref;
     int *d_err = dev_alloc<int>(c, 1);
     HDG_HIP_CHECK(hipMemset(d_err, 0, sizeof(int)));
     double *Sloc = dev_alloc<double>(c, (size_t)c->nt * c->nt * nk);
@@ -876,7 +877,8 @@ void setup_impl(const hdg_mesh *levels, int nlev, const int32_t *const *parents,
     c->Ar = dev_alloc<double>(c, (size_t)c->nc * c->nc * nk);
     c->Wr = dev_alloc<double>(c, (size_t)c->nc * c->nt * nk);
     hdg::CellParams cp{c->kappa, c->tau, c->dt, prm->f0, prm->omega, c->hscale, fine.geom};
-    hdg::launch_cell_condense(c->p, c->nu, nk, d_corners, d_ref, cp, Sloc, c->Zr, c->Ar, c->Wr, d_err, s);
+    hdg::launch_cell_condense(c->p, c->nu, nk, d_corners, d_ref, cp, Sloc, c->Zr, c->Ar, c->Wr, d_err, s, nullptr,
+                              nullptr);
     check_launch();
     HDG_HIP_CHECK(hipDeviceSynchronize());
     int herr = 0;
@@ -1011,70 +1013,11 @@ void setup_impl(const hdg_mesh *levels, int nlev, const int32_t *const *parents,
             galerkin[l - 1] = hdg::galerkin_coarsen(galerkin[l], parents[l], levels[l - 1].n_vert);
         }
     }
-    for (int l = 0; l < (int)c->lev.size(); ++l) {
-        const hdg_mesh &lm = levels[l];
-        hdg::P1Host P = opt.p1_galerkin ? galerkin[l] : hdg::assemble_p1(lm, c->kappa);
-        hdg::P1LevelDev &L = c->lev[l];
-        L.n = lm.n_vert;
-        std::vector<double> dinv(L.n);
-        for (int v = 0; v < L.n; ++v) {
-            HDG_REQUIRE(P.diag[v] > 0, "P1 operator has a non-positive diagonal");
-            dinv[v] = 1.0 / P.diag[v];
-        }
-        {
-            int W = 0;
-            for (int vv = 0; vv < L.n; ++vv) W = std::max(W, P.rowptr[vv + 1] - P.rowptr[vv]);
-            std::vector<int32_t> ec((size_t)std::max(W, 1) * L.n);
-            std::vector<double> ev((size_t)std::max(W, 1) * L.n, 0.0);
-            for (int vv = 0; vv < L.n; ++vv)
-                for (int k = 0; k < W; ++k) {
-                    const int q = P.rowptr[vv] + k;
-                    const bool in = q < P.rowptr[vv + 1];
-                    ec[(size_t)k * L.n + vv] = in ? P.col[q] : vv;
-                    ev[(size_t)k * L.n + vv] = in ? P.val[q] : 0.0;
-                }
-            L.w = W;
-            L.col = dev_upload(c, ec);
-            L.val = dev_upload(c, ev);
-        }
-        L.diag = dev_upload(c, P.diag);
-        L.dinv = dev_upload(c, dinv);
-        L.b = dev_alloc<double>(c, (size_t)L.n * mr);
-        L.x = dev_alloc<double>(c, (size_t)L.n * mr);
-        L.y = dev_alloc<double>(c, (size_t)L.n * mr);
-        if (l == 0) {
-            HDG_REQUIRE(L.n <= 8192, "coarsest P1 level must have at most 8192 vertices");
-            std::vector<double> dense((size_t)L.n * L.n, 0.0);
-            for (int v = 0; v < L.n; ++v) {
-                dense[(size_t)v * L.n + v] = P.diag[v];
-                for (int k = P.rowptr[v]; k < P.rowptr[v + 1]; ++k) dense[(size_t)v * L.n + P.col[k]] += P.val[k];
-            }
-            if (!hdg::spd_inverse(dense, L.n)) throw Error{HDG_EINVAL, "coarsest P1 operator is singular"};   // pivoted inverse
-            c->coarse_inv = dev_upload(c, dense);
-        } else {
-            HDG_REQUIRE(parents && parents[l], "parents[l] must be given for every level above the coarsest");
-            const int ncv = levels[l - 1].n_vert;
-            std::vector<int32_t> par(parents[l], parents[l] + 2 * (size_t)L.n);
-            std::vector<std::vector<std::pair<int, double>>> ch(ncv);
-            for (int v = 0; v < L.n; ++v)
-                for (int k = 0; k < 2; ++k) {
-                    HDG_REQUIRE(par[2 * v + k] >= 0 && par[2 * v + k] < ncv, "parent id out of range");
-                    ch[par[2 * v + k]].push_back({v, 0.5});
-                }
-            std::vector<int32_t> crow(ncv + 1, 0), ccol;
-            std::vector<double> cw;
-            for (int cv = 0; cv < ncv; ++cv) {
-                for (auto &pr : ch[cv]) {
-                    ccol.push_back(pr.first);
-                    cw.push_back(pr.second);
-                }
-                crow[cv + 1] = (int)ccol.size();
-            }
-            L.parents = dev_upload(c, par);
-            L.crow = dev_upload(c, crow);
-            L.ccol = dev_upload(c, ccol);
-            L.cw = dev_upload(c, cw);
-        }
+    if (!c->lev.empty()) {
+        std::vector<hdg::P1Host> ops(c->lev.size());
+        for (int l = 0; l < (int)c->lev.size(); ++l)
+            ops[l] = opt.p1_galerkin ? galerkin[l] : hdg::assemble_p1(levels[l], c->kappa);
+        hdg::build_p1_levels(c, levels, parents, ops, c->lev, &c->coarse_inv);
     }
 
     // ---- tail of the P1 hierarchy (levels small enough for one workgroup)
@@ -1172,6 +1115,86 @@ void destroy_impl(hdg_ctx *c) {
 }  // namespace
 
 // ------------------------------------------------------------------ C ABI
+
+// ------------------------------------------------------------------ P1 levels on the device
+//
+// Upload the P1 operators ops[l] (coarse to fine) as ELL rows with their
+// diagonal and inverse diagonal, work vectors for max_rhs right-hand sides,
+// the parent pairs and the children CSR of the linear-interpolation
+// transfer, and the dense inverse of the coarsest operator.
+void hdg::build_p1_levels(hdg_ctx *c, const hdg_mesh *levels, const int32_t *const *parents,
+                          const std::vector<hdg::P1Host> &ops, std::vector<hdg::P1LevelDev> &lev,
+                          double **coarse_inv) {
+    lev.resize(ops.size());
+    const int mr = c->opt.max_rhs;
+    for (int l = 0; l < (int)lev.size(); ++l) {
+        const hdg_mesh &lm = levels[l];
+        const hdg::P1Host &P = ops[l];
+        hdg::P1LevelDev &L = lev[l];
+        L.n = lm.n_vert;
+        std::vector<double> dinv(L.n);
+        for (int v = 0; v < L.n; ++v) {
+            HDG_REQUIRE(P.diag[v] > 0, "P1 operator has a non-positive diagonal");
+            dinv[v] = 1.0 / P.diag[v];
+        }
+        {
+            int W = 0;
+            for (int vv = 0; vv < L.n; ++vv) W = std::max(W, P.rowptr[vv + 1] - P.rowptr[vv]);
+            std::vector<int32_t> ec((size_t)std::max(W, 1) * L.n);
+            std::vector<double> ev((size_t)std::max(W, 1) * L.n, 0.0);
+            for (int vv = 0; vv < L.n; ++vv)
+                for (int k = 0; k < W; ++k) {
+                    const int q = P.rowptr[vv] + k;
+                    const bool in = q < P.rowptr[vv + 1];
+                    ec[(size_t)k * L.n + vv] = in ? P.col[q] : vv;
+                    ev[(size_t)k * L.n + vv] = in ? P.val[q] : 0.0;
+                }
+            L.w = W;
+            L.col = dev_upload(c, ec);
+            L.val = dev_upload(c, ev);
+        }
+        L.diag = dev_upload(c, P.diag);
+        L.dinv = dev_upload(c, dinv);
+        L.b = dev_alloc<double>(c, (size_t)L.n * mr);
+        L.x = dev_alloc<double>(c, (size_t)L.n * mr);
+        L.y = dev_alloc<double>(c, (size_t)L.n * mr);
+        if (l == 0) {
+            HDG_REQUIRE(L.n <= 8192, "coarsest P1 level must have at most 8192 vertices");
+            std::vector<double> dense((size_t)L.n * L.n, 0.0);
+            for (int v = 0; v < L.n; ++v) {
+                dense[(size_t)v * L.n + v] = P.diag[v];
+                for (int k = P.rowptr[v]; k < P.rowptr[v + 1]; ++k) dense[(size_t)v * L.n + P.col[k]] += P.val[k];
+            }
+            if (!hdg::spd_inverse(dense, L.n)) throw Error{HDG_EINVAL, "coarsest P1 operator is singular"};   // pivoted inverse
+            *coarse_inv = dev_upload(c, dense);
+        } else {
+            HDG_REQUIRE(parents && parents[l], "parents[l] must be given for every level above the coarsest");
+            const int ncv = levels[l - 1].n_vert;
+            std::vector<int32_t> par(parents[l], parents[l] + 2 * (size_t)L.n);
+            std::vector<std::vector<std::pair<int, double>>> ch(ncv);
+            for (int v = 0; v < L.n; ++v)
+                for (int k = 0; k < 2; ++k) {
+                    HDG_REQUIRE(par[2 * v + k] >= 0 && par[2 * v + k] < ncv, "parent id out of range");
+                    ch[par[2 * v + k]].push_back({v, 0.5});
+                }
+            std::vector<int32_t> crow(ncv + 1, 0), ccol;
+            std::vector<double> cw;
+            for (int cv = 0; cv < ncv; ++cv) {
+                for (auto &pr : ch[cv]) {
+                    ccol.push_back(pr.first);
+                    cw.push_back(pr.second);
+                }
+                crow[cv + 1] = (int)ccol.size();
+            }
+            L.parents = dev_upload(c, par);
+            L.crow = dev_upload(c, crow);
+            L.ccol = dev_upload(c, ccol);
+            L.cw = dev_upload(c, cw);
+        }
+    }
+}
+
+void *hdg::ctx_alloc(hdg_ctx *c, size_t bytes) { return dev_alloc<char>(c, bytes); }
 
 extern "C" int hdg_default_options(hdg_options *o) {
     if (!o) return HDG_EINVAL;

@@ -375,6 +375,31 @@ Plan make_plan(const hdg_imex_tableau *tab) {
 size_t even(size_t x) { return (x + 1) & ~(size_t)1; }
 
 }  // namespace
+
+void launch_dg_half(const hdg_ctx *c, int nb, double hscale, const double *q, double *half, hipStream_t s) {
+    const int64_t nth = (int64_t)c->n_cell * 3 * nb;
+    const int block = 256;
+    const unsigned grid = (unsigned)((nth + block - 1) / block);
+#define HALF(P, NU)                                                                                           \
+    hipLaunchKernelGGL((k_dg_half<P, NU>), dim3(grid), dim3(block), 0, s, c->n_cell, nb, c->geom, c->tau, hscale, \
+                       c->corners, c->cell_facet, c->cell_rev, q, half)
+    if (c->nu == 1) {
+        switch (c->p) {
+            case 1: HALF(1, 1); break;
+            case 2: HALF(2, 1); break;
+            default: HALF(3, 1); break;
+        }
+    } else {
+        switch (c->p) {
+            case 1: HALF(1, 2); break;
+            case 2: HALF(2, 2); break;
+            default: HALF(3, 2); break;
+        }
+    }
+#undef HALF
+    check_launch();
+}
+
 }  // namespace hdg
 
 using hdg::Error;

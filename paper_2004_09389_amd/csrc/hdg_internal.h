@@ -153,6 +153,15 @@ struct Rt0LevelDev {
     double *b = nullptr, *x = nullptr, *y = nullptr;   // [ne][max_rhs]
 };
 
+// upload P1 operators (coarse to fine) with transfers and the coarsest dense inverse (hdg_api.hip)
+void build_p1_levels(hdg_ctx *c, const hdg_mesh *levels, const int32_t *const *parents,
+                     const std::vector<P1Host> &ops, std::vector<P1LevelDev> &lev, double **coarse_inv);
+// device allocation owned by the context (freed by hdg_destroy)
+void *ctx_alloc(hdg_ctx *c, size_t bytes);
+// each side's share of the DG trace of the cell field q at its facet nodes (hdg_imex.hip):
+// half [n_facet][2][facet_dofs][nrhs]; phi = hscale * field 0
+void launch_dg_half(const hdg_ctx *c, int nb, double hscale, const double *q, double *half, hipStream_t s);
+
 }  // namespace hdg
 
 struct hdg_ctx {
@@ -178,6 +187,25 @@ struct hdg_ctx {
     double *corners = nullptr;      // [n_cell][3][3] unwrapped corner coordinates
     double *dg_half = nullptr;      // explicit flux evaluation: trace shares [n_facet][2][m][max_rhs]
     int *dg_err = nullptr;          // its singular-matrix flag
+    double *ref = nullptr;          // reference-element tables of the cell assembly
+
+    // non-hybridised DG baseline (hdg_dgs_setup): stage matrix as A q + B lam(q) per cell
+    bool dgs_ready = false;
+    double *dgs_A = nullptr;        // [nc][nc][n_cell]  A_K (symmetric variables)
+    double *dgs_Bn = nullptr;       // [nc][nt][n_cell]  -B_K
+    double *dgs_Auu_inv = nullptr;  // [2n][2n][n_cell] inverse of the cell's diagonal block of A_uu
+    double *dgs_Sown_inv = nullptr; // [n][n][n_cell]   inverse of the cell's own block of S
+    double *dgs_Dinv = nullptr;     // [n_cell][2n]      1 / diag(A_uu)
+    double dgs_lmax = 0.0;          // eigenvalue estimate of S_own^-1 S
+    std::vector<hdg::P1LevelDev> dgs_lev;   // Galerkin P1 hierarchy of S (level 0 coarsest)
+    double *dgs_coarse_inv = nullptr;
+    int32_t *dgs_cvert = nullptr;   // [n_cell][3] vertex ids
+    int32_t *dgs_vrow = nullptr, *dgs_vcol = nullptr;  // vertex -> 3 * cell + corner CSR
+    double *dgs_half = nullptr, *dgs_lam = nullptr;    // trace shares and trace of the apply
+    std::vector<double *> dgs_tmp;  // cell work vectors [n_cell][3][n_loc][max_rhs]
+    double *dgs_V = nullptr, *dgs_Z = nullptr;         // FGMRES bases
+    double *dgs_red = nullptr, *dgs_out = nullptr;     // reduction partials and results
+    double *dgs_coef = nullptr;                        // Krylov coefficients uploaded per step
 
     // facet block rows, component-major [slot][a][b][n_facet]
     int32_t *nbr = nullptr;     // [4][n_facet]

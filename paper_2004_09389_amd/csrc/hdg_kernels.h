@@ -118,8 +118,11 @@ struct CellParams {
 };
 
 // nu: trace components per node (1 upwind, 2 Lax-Friedrichs)
+// With Aout non-null the kernel only assembles and stores A_K ([nc][nc][nk]) and -B_K
+// ([nc][nt][nk], into Bnout), skipping the condensation.
 void launch_cell_condense(int p, int nu, int nk, const double *corners, const double *ref, CellParams cp,
-                          double *Sloc, double *Zr, double *Ar, double *Wr, int *err, hipStream_t s);
+                          double *Sloc, double *Zr, double *Ar, double *Wr, int *err, hipStream_t s,
+                          double *Aout = nullptr, double *Bnout = nullptr);
 void launch_facet_rows(int p, int nu, int ne, int nk, const double *Sloc, const int *facet_cell,
                        const int *facet_loc, const int *cell_facet, const int8_t *cell_rev, double omega,
                        double *S64, double *T64, double *Dw64, float *S32, __hip_bfloat16 *T16, float *Dw32,

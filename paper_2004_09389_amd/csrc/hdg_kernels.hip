@@ -91,7 +91,8 @@ __global__ __launch_bounds__(64) void k_cell_condense(int nk, const double *__re
                                                       const double *__restrict__ ref, CellParams cp,
                                                       double *__restrict__ Sloc, double *__restrict__ Zr,
                                                       double *__restrict__ Ar, double *__restrict__ Wr,
-                                                      int *__restrict__ err) {
+                                                      int *__restrict__ err, double *__restrict__ Aout,
+                                                      double *__restrict__ Bnout) {
     constexpr int n = (P + 1) * (P + 2) / 2, m = P + 1, nc = 3 * n, M = NU * m, nt = 3 * M, nq = (P + 3) * (P + 3);
     constexpr int LD = nc + nt + nc;
     __shared__ double aug[nc * LD];
@@ -235,6 +236,13 @@ __global__ __launch_bounds__(64) void k_cell_condense(int nk, const double *__re
             Cm[idx] = fc == 0 ? (d == 0 ? nx[f] : ny[f]) * t : (fc == d + 1 ? tau * t : 0.0);
     }
     __syncthreads();
+    if (Aout) {   // store A and -B only (the standard DG operator is A q + B lam(q))
+        const size_t NKs = (size_t)nk;
+        for (int idx = lane; idx < nc * nc; idx += 64) Aout[(size_t)idx * NKs + K] = aug[(idx / nc) * LD + idx % nc];
+        for (int idx = lane; idx < nc * nt; idx += 64)
+            Bnout[(size_t)idx * NKs + K] = -aug[(idx / nt) * LD + nc + idx % nt];
+        return;
+    }
 
     // ---- Gauss-Jordan with partial pivoting
     for (int k = 0; k < nc; ++k) {
@@ -1461,8 +1469,9 @@ bool rhs_blocked(int nb, int rhs_block) {
 #define GRID8(n, b) dim3((unsigned)((((n) + (b) - 1) / (b) + N_XCD - 1) / N_XCD * N_XCD)), dim3(b)
 
 void launch_cell_condense(int p, int nu, int nk, const double *corners, const double *ref, CellParams cp,
-                          double *Sloc, double *Zr, double *Ar, double *Wr, int *err, hipStream_t s) {
-#define CK(P, NU) hipLaunchKernelGGL((k_cell_condense<P, NU>), dim3(nk), dim3(64), 0, s, nk, corners, ref, cp, Sloc, Zr, Ar, Wr, err)
+                          double *Sloc, double *Zr, double *Ar, double *Wr, int *err, hipStream_t s, double *Aout,
+                          double *Bnout) {
+#define CK(P, NU) hipLaunchKernelGGL((k_cell_condense<P, NU>), dim3(nk), dim3(64), 0, s, nk, corners, ref, cp, Sloc, Zr, Ar, Wr, err, Aout, Bnout)
     if (nu == 1) { switch (p) { case 1: CK(1, 1); break; case 2: CK(2, 1); break; case 3: CK(3, 1); break; } }
     else { switch (p) { case 1: CK(1, 2); break; case 2: CK(2, 2); break; case 3: CK(3, 2); break; } }
 #undef CK

@@ -110,6 +110,10 @@ _SIGS = {
     "hdg_imex_run": (_I, [_P, ctypes.POINTER(HdgImexTableau), ctypes.c_double, ctypes.c_double, _I, _I, _P, _P,
                           ctypes.POINTER(HdgImexInfo), _P]),
     "hdg_dg_tendency": (_I, [_P, _I, ctypes.c_double, _P, _P, _P]),
+    "hdg_dgs_setup": (_I, [_P, ctypes.POINTER(HdgMesh), _I, ctypes.POINTER(ctypes.c_void_p)]),
+    "hdg_dgs_apply": (_I, [_P, _I, _P, _P, _P]),
+    "hdg_dgs_precondition": (_I, [_P, _I, _P, _P, _P]),
+    "hdg_dgs_solve": (_I, [_P, _I, _P, _P, ctypes.POINTER(HdgSolveInfo), _P]),
 }
 
 _lib = None
@@ -205,6 +209,7 @@ class HdgSolver:
             a = np.ascontiguousarray(par, dtype=np.int32)
             keep.append(a)
             parents[l + 1] = a.ctypes.data
+        self._meshes, self._parents, self._keep = meshes, parents, keep
         prm = HdgParams(degree, dt, g, H, f0, omega, tau, int(flux))
         ctx = ctypes.c_void_p()
         _check(self.lib.hdg_setup(meshes, len(hierarchy.meshes), parents, ctypes.byref(prm),
@@ -319,6 +324,32 @@ class HdgSolver:
         _check(self.lib.hdg_imex_run(self.ctx, ctypes.byref(tableau), dt, f, nb, steps, _ptr(q), _ptr(work),
                                      ctypes.byref(info), _stream()), allow)
         return info
+
+    # ------------------------------------------------------------------ non-hybridised DG baseline
+    def dgs_setup(self):
+        """Build the DG + approximate Schur-complement baseline on this context."""
+        _check(self.lib.hdg_dgs_setup(self.ctx, self._meshes, len(self.hier.meshes), self._parents))
+
+    def dgs_apply(self, x, out=None):
+        nb = self._nrhs(x, 4)
+        out = self.cell_zeros(nb) if out is None else out
+        _check(self.lib.hdg_dgs_apply(self.ctx, nb, _ptr(x), _ptr(out), _stream()))
+        return out
+
+    def dgs_precondition(self, r, out=None):
+        nb = self._nrhs(r, 4)
+        out = self.cell_zeros(nb) if out is None else out
+        _check(self.lib.hdg_dgs_precondition(self.ctx, nb, _ptr(r), _ptr(out), _stream()))
+        return out
+
+    def dgs_solve(self, r_cell, out=None, allow_notconv: bool = False):
+        """Solve the stage with the DG baseline; returns (q, [SolveInfo])."""
+        nb = self._nrhs(r_cell, 4)
+        out = self.cell_zeros(nb) if out is None else out
+        info = (HdgSolveInfo * nb)()
+        allow = (HDG_OK, HDG_ENOTCONV) if allow_notconv else (HDG_OK,)
+        _check(self.lib.hdg_dgs_solve(self.ctx, nb, _ptr(r_cell), _ptr(out), info, _stream()), allow)
+        return out, [SolveInfo(i.iters, i.refinements, i.fallbacks, i.status, i.rel_res) for i in info]
 
     # ------------------------------------------------------------------ learned smoother
     def mlp_set_weights(self, W1, W2):

@@ -113,3 +113,5 @@ def test_imex_entry_points_reject_bad_arguments_without_gpu():
     assert lib.hdg_imex_work_size(None, ctypes.byref(t), 1, ctypes.byref(n)) == hdg.HDG_EINVAL
     assert lib.hdg_imex_run(None, ctypes.byref(t), 0.1, 0.0, 1, 1, None, None, None, None) == hdg.HDG_EINVAL
     assert lib.hdg_dg_tendency(None, 1, 0.1, None, None, None) == hdg.HDG_EINVAL
+    assert lib.hdg_dgs_setup(None, None, 0, None) == hdg.HDG_EINVAL
+    assert lib.hdg_dgs_solve(None, 1, None, None, None, None) == hdg.HDG_EINVAL
