@@ -65,6 +65,8 @@ def parse():
     ap.add_argument("--sphere-only", action="store_true", help="run only the batched level-7 sphere leg")
     ap.add_argument("--sphere-nrhs", type=int, default=32)
     ap.add_argument("--no-imex", action="store_true", help="skip the IMEX time-stepping leg")
+    ap.add_argument("--no-dg", action="store_true", help="skip the non-hybridised DG baseline leg")
+    ap.add_argument("--dg-only", action="store_true", help="run only the non-hybridised DG baseline leg")
     ap.add_argument("--imex-only", action="store_true", help="run only the IMEX time-stepping leg")
     ap.add_argument("--ir-inner-rtol", type=float, default=1e-4, help="mixed_ir: reduction per inner solve")
     ap.add_argument("--pmc-run", action="store_true",
@@ -303,6 +305,56 @@ def imex_leg(args, n=256, p=3, run_steps=20):
     return out
 
 
+def dg_leg(args, p, n, run_steps=3):
+    """The non-hybridised DG baseline (native DG section: GMRES with the
+    approximate Schur-complement preconditioner) against the HDG solve of the
+    same stage (FP64 and mixed) on the same torus, p, right-hand side and f = 1,
+    at the paper's implicit Courant number 2/(2p+1) and at Courant 8."""
+    import torch
+
+    import hdg_inputs as hi
+    from paper_2004_09389_amd.hdg import HDG_FP64, HDG_MIXED, HdgSolver
+    hier = hi.torus_hierarchy(n, args.coarse)
+    r = torch.from_numpy(hi.fourier_rhs_torus(hier.fine, p, 100)).to("cuda")
+    out = {"workload": f"torus{n}x{n}_p{p}_f1", "n_cell_dof": int(3 * hier.fine.n_cell * (p + 1) * (p + 2) // 2),
+           "rtol": args.rtol, "note": "DG: ||R - A q|| / ||R|| on the cell system; HDG: on the trace system"}
+    for label, courant in (("courant_paper", 2.0 / (2 * p + 1)), ("courant_8", 8.0)):
+        rec = {"courant": round(courant, 4)}
+        for prec, name in ((HDG_FP64, "hdg_fp64"), (HDG_MIXED, "hdg_mixed")):
+            s = HdgSolver(hier, p, courant / n, 1.0, 1.0, 1.0, 0.0, 1.0, rtol=args.rtol, precision=prec, krylov=2,
+                          maxit=2000, p1_tail_max=args.tail_max, use_graph=0 if args.no_graph else 1)
+            if prec == HDG_FP64:
+                t = time.perf_counter()
+                s.dgs_setup()
+                torch.cuda.synchronize()
+                rec["dg_setup_s"] = round(time.perf_counter() - t, 3)
+                s.dgs_solve(r)
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                infos = [s.dgs_solve(r)[1] for _ in range(run_steps)]
+                torch.cuda.synchronize()
+                el = (time.perf_counter() - t) / run_steps
+                rec["dg_fp64"] = {"ms_per_solve": round(1e3 * el, 3), "iters": infos[-1][0].iters,
+                                  "rel_res": infos[-1][0].rel_res}
+            s.step(r)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            infos = [s.step(r)[2] for _ in range(run_steps)]
+            torch.cuda.synchronize()
+            el = (time.perf_counter() - t) / run_steps
+            rec[name] = {"ms_per_solve": round(1e3 * el, 3), "iters": infos[-1][0].iters,
+                         "rel_res": infos[-1][0].rel_res}
+            s.close()
+            del s
+        rec["speedup_hdg_fp64_vs_dg"] = round(rec["dg_fp64"]["ms_per_solve"] / rec["hdg_fp64"]["ms_per_solve"], 2)
+        rec["speedup_hdg_mixed_vs_dg"] = round(rec["dg_fp64"]["ms_per_solve"] / rec["hdg_mixed"]["ms_per_solve"], 2)
+        out[label] = rec
+        log(f"[bench] dg {label}: DG {rec['dg_fp64']['ms_per_solve']} ms ({rec['dg_fp64']['iters']} its), "
+            f"HDG fp64 {rec['hdg_fp64']['ms_per_solve']} ms ({rec['hdg_fp64']['iters']} its), "
+            f"HDG mixed {rec['hdg_mixed']['ms_per_solve']} ms")
+    return out
+
+
 def main():
     args = parse()
     if args.pmc_run:
@@ -332,6 +384,9 @@ def main():
         return
     if args.imex_only:
         print(json.dumps({"imex_leg": imex_leg(args, n, p, run_steps=args.steps)}), flush=True)
+        return
+    if args.dg_only:
+        print(json.dumps({"dg_leg": dg_leg(args, p, n, run_steps=min(args.steps, 3))}), flush=True)
         return
     dt = 8.0 / n
     t0 = time.perf_counter()
@@ -450,6 +505,9 @@ def main():
     imex_out = None
     if not args.no_imex and not args.pmc_run:
         imex_out = imex_leg(args, n, p, run_steps=min(args.steps, 20))
+    dg_out = None
+    if not args.no_dg and not args.pmc_run:
+        dg_out = dg_leg(args, p, n, run_steps=min(args.steps, 3))
 
     if args.pmc_run:
         # reference copy of known size for scaling the profiler's byte counters
@@ -551,6 +609,8 @@ def main():
         out["lf_leg"] = lf_out
     if imex_out is not None:
         out["imex_leg"] = imex_out
+    if dg_out is not None:
+        out["dg_leg"] = dg_out
     if sphere_out is not None:
         out["sphere_leg"] = sphere_out
         out["sphere_l6_leg"] = sphere6_out
