@@ -186,3 +186,39 @@ def test_imex_with_mixed_precision_stage_solves(method, precision):
     ref = LinearSwe(m, p, g=G, H=H, f=f).run(tableau(method, 0.5), dt, steps, q0)
     assert rel(host(q), ref) < 1e-8
     s.close()
+
+
+def test_imex_on_the_sphere_with_an_f_plane():
+    """Icosahedral sphere (level 2, p = 2), ARS2(2,3,2), constant explicit f in
+    every cell's frame, against the oracle."""
+    from oracle.imex import LinearSwe, tableau
+    from paper_2004_09389_amd.hdg import imex_gamma, imex_tableau
+    hier = hi.icosphere_hierarchy(2)
+    m = hier.fine
+    dt, f, steps = 0.05, 1.5, 3
+    tab = imex_tableau("ars232")
+    s = solver(hier, 2, imex_gamma(tab) * dt, g=1.0, h=1.0)
+    q0 = hi.iid_rhs(m, 2, 23)
+    q = to_dev(q0)
+    info = s.imex_run(tab, dt, f, q, steps)
+    assert info.status == 0
+    ref = LinearSwe(m, 2, g=1.0, H=1.0, f=f).run(tableau("ars232"), dt, steps, q0)
+    assert rel(host(q), ref) < 1e-9
+    s.close()
+
+
+def test_imex_lax_friedrichs_batch():
+    """Lax-Friedrichs flux, three right-hand sides, ARS3(4,4,3)."""
+    from oracle.imex import LinearSwe, tableau
+    from paper_2004_09389_amd.hdg import imex_gamma, imex_tableau
+    n, p, dt, f, nb = 8, 2, 0.04, 1.0, 3
+    m = hi.torus(n)
+    tab = imex_tableau("ars443")
+    s = solver(hi.torus_hierarchy(n, 4), p, imex_gamma(tab) * dt, "lf", max_rhs=nb)
+    q0 = hi.iid_rhs(m, p, 29, nrhs=nb)
+    q = to_dev(q0)
+    s.imex_run(tab, dt, f, q, 2)
+    swe = LinearSwe(m, p, g=G, H=H, f=f, flux="lf")
+    for k in range(nb):
+        assert rel(host(q)[..., k], swe.run(tableau("ars443"), dt, 2, q0[..., k:k + 1])[..., 0]) < 1e-9
+    s.close()
