@@ -80,3 +80,45 @@ def test_baseline_and_hdg_give_the_same_stage_solution():
     q_hdg, _, _ = s.step(r)
     assert rel(host(q_dg), host(q_hdg)) < 1e-9
     s.close()
+
+
+def _paper_iterations():
+    import os
+    rows = []
+    for line in open(os.path.join(os.path.dirname(__file__), "golden", "iterations_linear.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        rows.append([None if t == "-" else float(t) for t in line.split()])
+    return rows
+
+
+@pytest.mark.parametrize("p", [1, 3])
+def test_iterations_at_the_papers_courant_number(p):
+    """Like-for-like with the paper's iteration table for the linear problem
+    (DG column: 12-14 at p = 1, 13-15.5 at p = 3, HDG 7-8): flat bathymetry,
+    f = 0, rtol 1e-8, the implicit stage of its ARS2(2,3,2) stepper
+    (kappa = c gamma dt, dt = (2 / (2p + 1)) h, gamma = 1 - 1/sqrt 2) on the
+    32^2 ... 128^2 tori.  The sub-solves differ (cell-block inverses and a
+    Galerkin two-level cycle instead of ILU and GAMG) and the stop is on the
+    true residual, so the counts are bounded, not matched."""
+    import torch
+    from paper_2004_09389_amd.hdg import HdgSolver
+    table = _paper_iterations()
+    col = 1 if p == 1 else 3
+    lo = min(r[col] for r in table)
+    hi_ = max(r[col] for r in table)
+    gamma = 1.0 - 1.0 / np.sqrt(2.0)
+    its, hdg_its = [], []
+    for n in (32, 64, 128):
+        hier = hi.torus_hierarchy(n, min(32, n))
+        s = HdgSolver(hier, p, gamma * (2.0 / (2 * p + 1)) / n, 1.0, 1.0, 0.0, 0.0, maxit=400, p1_tail_max=0)
+        s.dgs_setup()
+        r = torch.from_numpy(hi.fourier_rhs_torus(hier.fine, p, 100)).cuda()
+        _, info = s.dgs_solve(r)
+        assert info[0].status == 0
+        its.append(info[0].iters)
+        hdg_its.append(s.step(r)[2][0].iters)
+        s.close()
+    print(f"p={p}: DG iterations {its} (paper {lo}-{hi_}), HDG {hdg_its}")
+    assert lo - 3 <= min(its) and max(its) <= hi_ + 3 and max(its) - min(its) <= 3
+    assert min(its) > max(hdg_its)
