@@ -127,6 +127,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     if not os.path.exists(path):
         raise RuntimeError(f"HIP library not built: {path} is missing "
                            "(run python -m paper_2004_09389_amd.build)")
+    # torch first: its HIP runtime is then already in the process and the
+    # library binds to the same one (loaded the other way round, torch's CUDA
+    # initialisation later finds no device)
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     for name, (res, args) in _SIGS.items():
         fn = getattr(lib, name)

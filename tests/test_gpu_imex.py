@@ -222,3 +222,32 @@ def test_imex_lax_friedrichs_batch():
     for k in range(nb):
         assert rel(host(q)[..., k], swe.run(tableau("ars443"), dt, 2, q0[..., k:k + 1])[..., 0]) < 1e-9
     s.close()
+
+
+@pytest.mark.parametrize("p", [2, 3])
+def test_vortex_rate_at_higher_degree_through_the_gpu(p):
+    """The stationary vortex at p = 2, 3 (n = 16, 32; ARS2(2,3,2), the paper's
+    time step, T = 1/2): Delta_2 drops at least as h^(p + 1/2) between the two
+    meshes and equals the oracle's on the coarser one."""
+    from oracle.imex import LinearSwe, l2_error, tableau
+    from paper_2004_09389_amd.hdg import imex_gamma, imex_tableau
+    v = hi.Vortex()
+    tab = imex_tableau("ars232")
+    errs = []
+    for n in (16, 32):
+        m = hi.torus(n)
+        dt, steps = hi.paper_time_step(n, p)
+        s = solver(hi.torus_hierarchy(n, 4), p, imex_gamma(tab) * dt, g=v.c_g, h=v.c_g, rtol=1e-10)
+        q0 = hi.vortex_coefficients(m, p, v)
+        q = to_dev(q0)
+        info = s.imex_run(tab, dt, v.f, q, steps)
+        assert info.status == 0
+        swe = LinearSwe(m, p, g=v.c_g, H=v.c_g, f=v.f)
+        e = l2_error(swe, host(q)[..., 0], lambda xy: v.state(xy))
+        if n == 16:
+            e_ref = l2_error(swe, swe.run(tableau("ars232"), dt, steps, q0)[..., 0], lambda xy: v.state(xy))
+            assert abs(e - e_ref) < 1e-6 * e_ref
+        errs.append(e)
+        s.close()
+    print(f"p={p}: Delta_2 {errs}, rate {math.log2(errs[0] / errs[1]):.2f}")
+    assert math.log2(errs[0] / errs[1]) >= p + 0.5
