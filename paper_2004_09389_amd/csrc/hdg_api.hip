@@ -1195,6 +1195,11 @@ void hdg::build_p1_levels(hdg_ctx *c, const hdg_mesh *levels, const int32_t *con
 }
 
 void *hdg::ctx_alloc(hdg_ctx *c, size_t bytes) { return dev_alloc<char>(c, bytes); }
+int hdg::guarded(const std::function<void()> &fn) { return guard(fn); }
+void hdg::check_kernel_launch() { check_launch(); }
+void hdg::check_abi(int rc) {
+    if (rc < 0) throw Error{rc, hdg_last_error()};
+}
 
 extern "C" int hdg_default_options(hdg_options *o) {
     if (!o) return HDG_EINVAL;

@@ -39,26 +39,7 @@ namespace {
 
 constexpr int DGS_MAX_RHS = 64;
 
-int guard(const std::function<void()> &fn) {
-    try {
-        fn();
-        return HDG_OK;
-    } catch (const Error &e) {
-        set_error(e.msg);
-        return e.code;
-    } catch (const std::bad_alloc &) {
-        set_error("host allocation failed");
-        return HDG_ENOMEM;
-    } catch (const std::exception &e) {
-        set_error(e.what());
-        return HDG_EINVAL;
-    }
-}
 
-void check_launch() {
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) throw Error{HDG_EHIP, std::string("kernel launch: ") + hipGetErrorString(e)};
-}
 
 inline dim3 grid_for(int64_t n, int block) { return dim3((unsigned)((n + block - 1) / block)); }
 
@@ -365,7 +346,7 @@ void lin(const Dgs &g, int f0, int f1, double a, const double *x, double b, cons
     const int64_t cnt = (int64_t)g.c->n_cell * (f1 - f0) * g.c->n * g.nb;
     hipLaunchKernelGGL(k_dgs_lin, grid_for(cnt, 256), dim3(256), 0, g.s, cnt, g.c->n, g.nb, f0, f1, a, x, b, y,
                        dinv ? g.c->dgs_Dinv : nullptr, out);
-    check_launch();
+    check_kernel_launch();
 }
 
 // y = A x, the DG stage operator (symmetric variables)
@@ -375,9 +356,9 @@ void dgs_apply(const Dgs &g, const double *x, double *y) {
     const int64_t cnt = (int64_t)c->n_facet * c->m * g.nb;
     hipLaunchKernelGGL(k_dgs_trace_sum, grid_for(cnt, 256), dim3(256), 0, g.s, cnt, c->m * g.nb, c->dgs_half,
                        c->dgs_lam);
-    check_launch();
+    check_kernel_launch();
     launch_recover(c->p, 1, c->n_cell, g.nb, c->dgs_A, c->dgs_Bn, c->cell_facet, c->cell_rev, x, c->dgs_lam, y, g.s);
-    check_launch();
+    check_kernel_launch();
 }
 
 void block_mv(const Dgs &g, bool velocity, const double *in, double *out) {
@@ -400,7 +381,7 @@ void block_mv(const Dgs &g, bool velocity, const double *in, double *out) {
         }
     }
 #undef BMV
-    check_launch();
+    check_kernel_launch();
 }
 
 // y_phi = S x_phi (x in the phi field of x; its velocity fields must be zero).
@@ -491,7 +472,7 @@ void s_cycle(const Dgs &g, const double *b, double *x) {
         case 2: RESTRICT(2); break;
         default: RESTRICT(3); break;
     }
-    check_launch();
+    check_kernel_launch();
     const double *xc = p1_cycle(c->dgs_lev, c->dgs_coarse_inv, L, g.nb, c->opt.p1_nu, c->opt.p1_omega, g.s);
     switch (c->p) {
         case 1: PROLONG(1); break;
@@ -500,7 +481,7 @@ void s_cycle(const Dgs &g, const double *b, double *x) {
     }
 #undef RESTRICT
 #undef PROLONG
-    check_launch();
+    check_kernel_launch();
     chebyshev(g, b, x, c->opt.nu_post, false);
 }
 
@@ -519,7 +500,7 @@ void precondition(const Dgs &g, const double *r, double *z) {
 
 std::vector<double> dots(const Dgs &g, int nd, const double *X, int64_t xstride, const double *y) {
     launch_dots<double>(g.len, g.nb, nd, X, xstride, y, g.c->dgs_red, g.c->dgs_out, nullptr, g.s);
-    check_launch();
+    check_kernel_launch();
     std::vector<double> h((size_t)nd * g.nb);
     HDG_HIP_CHECK(hipMemcpyAsync(h.data(), g.c->dgs_out, h.size() * sizeof(double), hipMemcpyDeviceToHost, g.s));
     HDG_HIP_CHECK(hipStreamSynchronize(g.s));
@@ -531,7 +512,7 @@ void scale_cols(const Dgs &g, const std::vector<double> &c, const double *x, dou
     for (int r = 0; r < g.nb; ++r) cc.v[r] = c[r];
     const int64_t cnt = g.len * g.nb;
     hipLaunchKernelGGL(k_dgs_scale, grid_for(cnt, 256), dim3(256), 0, g.s, cnt, g.nb, cc, x, out);
-    check_launch();
+    check_kernel_launch();
 }
 
 // x += sum_d coef[d][r] Z_d
@@ -539,7 +520,7 @@ void lincomb(const Dgs &g, int nd, const std::vector<double> &coef, const double
     HDG_HIP_CHECK(hipMemcpyAsync(g.c->dgs_coef, coef.data(), (size_t)nd * g.nb * sizeof(double),
                                  hipMemcpyHostToDevice, g.s));
     launch_lincomb<double>(g.len, g.nb, nd, g.c->dgs_coef, Z, zstride, x, g.s);
-    check_launch();
+    check_kernel_launch();
 }
 
 int restart_len(const hdg_ctx *c) { return std::max(1, std::min(c->opt.restart, 64)); }
@@ -614,7 +595,7 @@ using hdg::Error;
 
 extern "C" int hdg_dgs_setup(hdg_ctx *c, const hdg_mesh *levels, int32_t n_levels, const int32_t *const *parents) {
     if (!c) return HDG_EINVAL;
-    return hdg::guard([&] {
+    return hdg::guarded([&] {
         if (c->dgs_ready) return;
         HDG_REQUIRE(c->flux == HDG_FLUX_UPWIND, "the DG baseline is built for the upwind flux");
         HDG_REQUIRE(levels && n_levels >= 1, "levels must be given");
@@ -637,7 +618,7 @@ extern "C" int hdg_dgs_setup(hdg_ctx *c, const hdg_mesh *levels, int32_t n_level
         hdg::CellParams cp{c->kappa, c->tau, c->dt, c->prm.f0, c->prm.omega, c->hscale, c->geom};
         hdg::launch_cell_condense(c->p, 1, nk, c->corners, c->ref, cp, nullptr, nullptr, nullptr, nullptr, d_err, s,
                                   c->dgs_A, c->dgs_Bn);
-        hdg::check_launch();
+        hdg::check_kernel_launch();
 #define LOCAL(P)                                                                                                   \
     hipLaunchKernelGGL(hdg::k_dgs_local<P>, dim3(nk), dim3(64), 0, s, nk, c->geom, c->tau, c->corners, c->dgs_A, \
                        c->dgs_Bn, c->dgs_Auu_inv, c->dgs_Sown_inv, c->dgs_Dinv, d_beta, d_err)
@@ -647,7 +628,7 @@ extern "C" int hdg_dgs_setup(hdg_ctx *c, const hdg_mesh *levels, int32_t n_level
             default: LOCAL(3); break;
         }
 #undef LOCAL
-        hdg::check_launch();
+        hdg::check_kernel_launch();
         HDG_HIP_CHECK(hipDeviceSynchronize());
         int herr = 0;
         HDG_HIP_CHECK(hipMemcpy(&herr, d_err, sizeof(int), hipMemcpyDeviceToHost));
@@ -725,7 +706,7 @@ extern "C" int hdg_dgs_setup(hdg_ctx *c, const hdg_mesh *levels, int32_t n_level
 
 extern "C" int hdg_dgs_apply(hdg_ctx *c, int32_t nb, const double *x, double *y, void *stream) {
     if (!c) return HDG_EINVAL;
-    return hdg::guard([&] {
+    return hdg::guarded([&] {
         hdg::check_vec(c, nb);
         HDG_REQUIRE(x && y && x != y, "x and y must be distinct non-NULL arrays");
         hdg::Dgs g{c, nb, reinterpret_cast<hipStream_t>(stream), (int64_t)c->n_cell * c->nc};
@@ -735,7 +716,7 @@ extern "C" int hdg_dgs_apply(hdg_ctx *c, int32_t nb, const double *x, double *y,
 
 extern "C" int hdg_dgs_precondition(hdg_ctx *c, int32_t nb, const double *r, double *z, void *stream) {
     if (!c) return HDG_EINVAL;
-    return hdg::guard([&] {
+    return hdg::guarded([&] {
         hdg::check_vec(c, nb);
         HDG_REQUIRE(r && z && r != z, "r and z must be distinct non-NULL arrays");
         hdg::Dgs g{c, nb, reinterpret_cast<hipStream_t>(stream), (int64_t)c->n_cell * c->nc};
@@ -747,7 +728,7 @@ extern "C" int hdg_dgs_solve(hdg_ctx *c, int32_t nb, const double *r_cell, doubl
                              void *stream) {
     if (!c) return HDG_EINVAL;
     int status = HDG_OK;
-    const int rc = hdg::guard([&] {
+    const int rc = hdg::guarded([&] {
         hdg::check_vec(c, nb);
         HDG_REQUIRE(r_cell && q_cell && r_cell != q_cell, "r_cell and q_cell must be distinct non-NULL arrays");
         hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -760,7 +741,7 @@ extern "C" int hdg_dgs_solve(hdg_ctx *c, int32_t nb, const double *r_cell, doubl
             const int64_t cnt = len * nb;
             hipLaunchKernelGGL(hdg::k_dgs_load, hdg::grid_for(cnt, 256), dim3(256), 0, s, c->n_cell, c->n, nb,
                                c->hscale, c->dgs_A, r_cell, R);
-            hdg::check_launch();
+            hdg::check_kernel_launch();
         }
         hdg::lin(g, 0, 3, 0.0, nullptr, 0.0, nullptr, false, X);
         std::vector<double> bn = hdg::dots(g, 1, R, 0, R);

@@ -26,30 +26,8 @@ namespace {
 constexpr int TEND_MAX_RHS = 64;
 constexpr int COMBINE_MAX = 2 * HDG_IMEX_MAX_STAGES;
 
-int guard(const std::function<void()> &fn) {
-    try {
-        fn();
-        return HDG_OK;
-    } catch (const Error &e) {
-        set_error(e.msg);
-        return e.code;
-    } catch (const std::bad_alloc &) {
-        set_error("host allocation failed");
-        return HDG_ENOMEM;
-    } catch (const std::exception &e) {
-        set_error(e.what());
-        return HDG_EINVAL;
-    }
-}
 
-void check_launch() {
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) throw Error{HDG_EHIP, std::string("kernel launch: ") + hipGetErrorString(e)};
-}
 
-void check_rc(int rc) {
-    if (rc < 0) throw Error{rc, hdg_last_error()};
-}
 
 // ------------------------------------------------------------------ kernels
 
@@ -265,7 +243,7 @@ void launch_combine(const hdg_ctx *c, int nb, const Combine &t, double *out, hip
     const int block = 256;
     const int64_t grid = (npt + block - 1) / block;
     hipLaunchKernelGGL(k_imex_combine, dim3((unsigned)grid), dim3(block), 0, s, npt, stride, t, out);
-    check_launch();
+    check_kernel_launch();
 }
 
 void check_nb(const hdg_ctx *c, int nb) {
@@ -310,20 +288,20 @@ void dg_tendency(hdg_ctx *c, int nb, double dt, const double *q, double *out, hi
                        c->cell_facet, c->cell_rev, q, half, out, err)
     if (c->nu == 1) {
         switch (c->p) {
-            case 1: HALF(1, 1); check_launch(); TEND(1, 1); break;
-            case 2: HALF(2, 1); check_launch(); TEND(2, 1); break;
-            default: HALF(3, 1); check_launch(); TEND(3, 1); break;
+            case 1: HALF(1, 1); check_kernel_launch(); TEND(1, 1); break;
+            case 2: HALF(2, 1); check_kernel_launch(); TEND(2, 1); break;
+            default: HALF(3, 1); check_kernel_launch(); TEND(3, 1); break;
         }
     } else {
         switch (c->p) {
-            case 1: HALF(1, 2); check_launch(); TEND(1, 2); break;
-            case 2: HALF(2, 2); check_launch(); TEND(2, 2); break;
-            default: HALF(3, 2); check_launch(); TEND(3, 2); break;
+            case 1: HALF(1, 2); check_kernel_launch(); TEND(1, 2); break;
+            case 2: HALF(2, 2); check_kernel_launch(); TEND(2, 2); break;
+            default: HALF(3, 2); check_kernel_launch(); TEND(3, 2); break;
         }
     }
 #undef HALF
 #undef TEND
-    check_launch();
+    check_kernel_launch();
 }
 
 struct Plan {
@@ -397,7 +375,7 @@ void launch_dg_half(const hdg_ctx *c, int nb, double hscale, const double *q, do
         }
     }
 #undef HALF
-    check_launch();
+    check_kernel_launch();
 }
 
 }  // namespace hdg
@@ -405,7 +383,7 @@ void launch_dg_half(const hdg_ctx *c, int nb, double hscale, const double *q, do
 using hdg::Error;
 
 extern "C" int hdg_imex_tableau_get(int32_t method, double theta, hdg_imex_tableau *out) {
-    return hdg::guard([&] {
+    return hdg::guarded([&] {
         HDG_REQUIRE(out, "out must not be NULL");
         hdg_imex_tableau t{};
         switch (method) {
@@ -475,7 +453,7 @@ extern "C" int hdg_imex_tableau_get(int32_t method, double theta, hdg_imex_table
 
 extern "C" int hdg_imex_work_size(const hdg_ctx *c, const hdg_imex_tableau *tab, int32_t nb, int64_t *doubles) {
     if (!c) return HDG_EINVAL;
-    return hdg::guard([&] {
+    return hdg::guarded([&] {
         HDG_REQUIRE(doubles, "doubles must not be NULL");
         hdg::check_nb(c, nb);
         const hdg::Plan pl = hdg::make_plan(tab);
@@ -487,7 +465,7 @@ extern "C" int hdg_imex_work_size(const hdg_ctx *c, const hdg_imex_tableau *tab,
 
 extern "C" int hdg_dg_tendency(hdg_ctx *c, int32_t nb, double dt, const double *q, double *out, void *stream) {
     if (!c) return HDG_EINVAL;
-    return hdg::guard([&] {
+    return hdg::guarded([&] {
         hdg::check_nb(c, nb);
         HDG_REQUIRE(nb <= hdg::TEND_MAX_RHS, "nrhs must be at most 64");
         HDG_REQUIRE(q && out && q != out, "q and out must be distinct non-NULL arrays");
@@ -505,7 +483,7 @@ extern "C" int hdg_imex_run(hdg_ctx *c, const hdg_imex_tableau *tab, double dt, 
                             int32_t steps, double *q, double *work, hdg_imex_info *info, void *stream) {
     if (!c) return HDG_EINVAL;
     int status = HDG_OK;
-    const int rc = hdg::guard([&] {
+    const int rc = hdg::guarded([&] {
         hdg::check_nb(c, nb);
         const hdg::Plan pl = hdg::make_plan(tab);
         HDG_REQUIRE(q && work, "q and work must not be NULL");
@@ -574,10 +552,10 @@ extern "C" int hdg_imex_run(hdg_ctx *c, const hdg_imex_tableau *tab, double dt, 
                     stage_q[i] = R[i];
                     continue;
                 }
-                hdg::check_rc(hdg_condense(c, nb, R[i], rhat, stream));
+                hdg::check_abi(hdg_condense(c, nb, R[i], rhat, stream));
                 HDG_HIP_CHECK(hipMemsetAsync(lam, 0, (size_t)c->n_facet * c->m * nb * sizeof(double), st));
                 const int src = hdg_solve(c, nb, rhat, lam, si.data(), stream);
-                hdg::check_rc(src);
+                hdg::check_abi(src);
                 if (src == HDG_ENOTCONV) acc.status = HDG_ENOTCONV;
                 int it = 0;
                 for (int r = 0; r < nb; ++r) {
@@ -587,7 +565,7 @@ extern "C" int hdg_imex_run(hdg_ctx *c, const hdg_imex_tableau *tab, double dt, 
                 acc.solves++;
                 acc.iters_total += it;
                 acc.iters_max = std::max(acc.iters_max, it);
-                hdg::check_rc(hdg_recover(c, nb, R[i], lam, Q[i], stream));
+                hdg::check_abi(hdg_recover(c, nb, R[i], lam, Q[i], stream));
                 stage_q[i] = Q[i];
             }
             // q_{n+1} = q_n + dt sum_i b_i N_0(Q_i) + dt sum_i bt_i L(Q_i), in place

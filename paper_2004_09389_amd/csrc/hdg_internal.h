@@ -5,6 +5,7 @@
 #include <hip/hip_bf16.h>
 
 #include <cstdint>
+#include <functional>
 #include <map>
 #include <string>
 #include <vector>
@@ -152,6 +153,13 @@ struct Rt0LevelDev {
     double *cw = nullptr;
     double *b = nullptr, *x = nullptr, *y = nullptr;   // [ne][max_rhs]
 };
+
+// run fn, turning an Error (or allocation failure) into its code and hdg_last_error message
+int guarded(const std::function<void()> &fn);
+// throw HDG_EHIP when the last kernel launch failed
+void check_kernel_launch();
+// throw the code of a failed C-ABI call (negative return) with its message
+void check_abi(int rc);
 
 // upload P1 operators (coarse to fine) with transfers and the coarsest dense inverse (hdg_api.hip)
 void build_p1_levels(hdg_ctx *c, const hdg_mesh *levels, const int32_t *const *parents,
