@@ -2,8 +2,8 @@
 
 Argument marshalling only: every numerical step runs in the library's HIP
 kernels.  Device buffers are torch CUDA (HIP) tensors; streams are torch's
-current stream.  Importing this module loads the library and fails loudly
-when it has not been built.
+current stream.  The library is loaded on first use (after torch, whose HIP
+runtime it shares) and every call fails loudly when it has not been built.
 """
 from __future__ import annotations
 
