@@ -122,3 +122,24 @@ def test_iterations_at_the_papers_courant_number(p):
     print(f"p={p}: DG iterations {its} (paper {lo}-{hi_}), HDG {hdg_its}")
     assert lo - 3 <= min(its) and max(its) <= hi_ + 3 and max(its) - min(its) <= 3
     assert min(its) > max(hdg_its)
+
+
+def test_solve_is_deterministic_and_reports_non_convergence():
+    """Two solves of the same input give identical bits; a maxit too small for
+    rtol returns HDG_ENOTCONV with the final true residual in info."""
+    from paper_2004_09389_amd.hdg import HDG_ENOTCONV, HdgError, HdgSolver
+    hier = hi.torus_hierarchy(8, 4)
+    s = HdgSolver(hier, 2, 0.5, 1.3, 0.8, 1.0, 0.0, rtol=1e-10, maxit=300)
+    s.dgs_setup()
+    r = to_dev(hi.iid_rhs(hier.fine, 2, 12))
+    q1, _ = s.dgs_solve(r)
+    q2, _ = s.dgs_solve(r)
+    assert np.array_equal(host(q1), host(q2))
+    s.close()
+    s = HdgSolver(hier, 2, 0.5, 1.3, 0.8, 1.0, 0.0, rtol=1e-12, maxit=3)
+    s.dgs_setup()
+    with pytest.raises(HdgError):
+        s.dgs_solve(r)
+    q, info = s.dgs_solve(r, allow_notconv=True)
+    assert info[0].status == HDG_ENOTCONV and 1e-12 < info[0].rel_res < 1.0
+    s.close()

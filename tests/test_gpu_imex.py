@@ -251,3 +251,24 @@ def test_vortex_rate_at_higher_degree_through_the_gpu(p):
         s.close()
     print(f"p={p}: Delta_2 {errs}, rate {math.log2(errs[0] / errs[1]):.2f}")
     assert math.log2(errs[0] / errs[1]) >= p + 0.5
+
+
+def test_imex_is_deterministic_and_reports_non_convergence():
+    """Repeated runs give identical bits; a stage solve stopped at maxit makes the
+    run return HDG_ENOTCONV (steps still completed, status in info)."""
+    from paper_2004_09389_amd.hdg import HDG_ENOTCONV, HdgError, imex_gamma, imex_tableau
+    n, p, dt = 8, 2, 0.05
+    tab = imex_tableau("theta", 0.5)
+    q0 = hi.iid_rhs(hi.torus(n), p, 3)
+    s = solver(hi.torus_hierarchy(n, 4), p, imex_gamma(tab) * dt)
+    a, b = to_dev(q0), to_dev(q0)
+    s.imex_run(tab, dt, 1.0, a, 3)
+    s.imex_run(tab, dt, 1.0, b, 3)
+    assert np.array_equal(host(a), host(b))
+    s.close()
+    s = solver(hi.torus_hierarchy(n, 4), p, imex_gamma(tab) * dt, rtol=1e-14, maxit=1)
+    with pytest.raises(HdgError):
+        s.imex_run(tab, dt, 1.0, to_dev(q0), 1)
+    info = s.imex_run(tab, dt, 1.0, to_dev(q0), 2, allow_notconv=True)
+    assert info.status == HDG_ENOTCONV and info.steps == 2 and info.solves == 2
+    s.close()
