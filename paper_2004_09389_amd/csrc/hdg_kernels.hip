@@ -1023,6 +1023,8 @@ __device__ __forceinline__ int rows_per_block(int nb) {
 // partials in block order.  Repeated solves are bitwise identical.
 
 constexpr int RED_CHUNK = 8;   // dot products accumulated per pass over the rows
+constexpr int MDOT_ROWS = 4;   // rows each thread loads per step of the dot-product kernel
+constexpr int GS_ROWS = 2;     // rows each thread updates per step of the Gram-Schmidt kernel
 
 // sh[k][tid] -> per-RHS block sums for k < kc in sh[k][r], r < nb
 __device__ __forceinline__ void block_rhs_sums(double (*sh)[256], int kc, int nb, int rpb) {
@@ -1051,12 +1053,27 @@ __global__ __launch_bounds__(256) void k_mdot_partial(int64_t len, int nb, int n
 #pragma unroll
         for (int k = 0; k < RED_CHUNK; ++k) acc[k] = 0.0;
         if (rl < rpb) {
-            for (int64_t i = (int64_t)blockIdx.x * rpb + rl; i < len; i += (int64_t)gridDim.x * rpb) {
-                const size_t t = (size_t)i * nb + r;
-                const double yv = (double)y[t];
+            // MDOT_ROWS rows per pass (more loads in flight per wave)
+            const int64_t stride = (int64_t)gridDim.x * rpb;
+            for (int64_t i = (int64_t)blockIdx.x * rpb + rl; i < len; i += MDOT_ROWS * stride) {
+                size_t tt[MDOT_ROWS];
+                double yy[MDOT_ROWS];
+#pragma unroll
+                for (int u = 0; u < MDOT_ROWS; ++u) {
+                    const int64_t iu = i + u * stride;
+                    const bool ok = iu < len;
+                    tt[u] = (size_t)(ok ? iu : i) * nb + r;
+                    yy[u] = ok ? (double)y[tt[u]] : 0.0;
+                }
 #pragma unroll
                 for (int k = 0; k < RED_CHUNK; ++k)
-                    if (k < kc) acc[k] += (double)X[(size_t)(d0 + k) * xstride + t] * yv;
+                    if (k < kc) {
+                        double a[MDOT_ROWS];
+#pragma unroll
+                        for (int u = 0; u < MDOT_ROWS; ++u) a[u] = (double)X[(size_t)(d0 + k) * xstride + tt[u]];
+#pragma unroll
+                        for (int u = 0; u < MDOT_ROWS; ++u) acc[k] += a[u] * yy[u];
+                    }
             }
         }
 #pragma unroll
@@ -1133,13 +1150,31 @@ __global__ __launch_bounds__(256) void k_gs_update_norm(int64_t len, int nb, int
     const int rl = tid / nb, r = tid - rl * nb;
     double acc = 0.0;
     if (rl < rpb) {
-        for (int64_t i = (int64_t)blockIdx.x * rpb + rl; i < len; i += (int64_t)gridDim.x * rpb) {
-            const size_t t = (size_t)i * nb + r;
-            double s = (double)w[t];
-            for (int d = 0; d < nd; ++d) s -= h[(size_t)d * nb + r] * (double)V[(size_t)d * vstride + t];
-            const VT sv = (VT)s;   // the norm is that of the vector as stored
-            w[t] = sv;
-            acc += (double)sv * (double)sv;
+        // GS_ROWS rows per pass (more loads in flight per wave)
+        const int64_t stride = (int64_t)gridDim.x * rpb;
+        for (int64_t i = (int64_t)blockIdx.x * rpb + rl; i < len; i += GS_ROWS * stride) {
+            size_t tt[GS_ROWS];
+            bool ok[GS_ROWS];
+            double s[GS_ROWS];
+#pragma unroll
+            for (int u = 0; u < GS_ROWS; ++u) {
+                const int64_t iu = i + u * stride;
+                ok[u] = iu < len;
+                tt[u] = (size_t)(ok[u] ? iu : i) * nb + r;
+                s[u] = (double)w[tt[u]];
+            }
+            for (int d = 0; d < nd; ++d) {
+                const double hd = h[(size_t)d * nb + r];
+#pragma unroll
+                for (int u = 0; u < GS_ROWS; ++u) s[u] -= hd * (double)V[(size_t)d * vstride + tt[u]];
+            }
+#pragma unroll
+            for (int u = 0; u < GS_ROWS; ++u)
+                if (ok[u]) {
+                    const VT sv = (VT)s[u];   // the norm is that of the vector as stored
+                    w[tt[u]] = sv;
+                    acc += (double)sv * (double)sv;
+                }
         }
     }
     sh[0][tid] = (rl < rpb) ? acc : 0.0;
