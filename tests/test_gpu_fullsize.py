@@ -11,6 +11,10 @@ benchmark uses, against the FP64 oracle built on the same mesh.
 * icosahedral sphere level 7 (327680 cells), p = 3, dt = 3600 s, 32
   right-hand sides per batch.
 
+* IMEX stepping and the non-hybridised DG baseline on the 256 x 256 torus,
+  p = 3, through properties that hold at any size: conservation and the steady
+  vortex, and agreement of the two solvers of the same stage.
+
 Inputs of the operator-level comparisons (x, lam, r) are seeded random
 vectors; the solve checks recompute ||rhat - S lam|| with the oracle's S and
 rhat.  FP64 operators are held to the FP64 path's 1e-10: the cell-local
@@ -180,3 +184,55 @@ def test_learned_solve_full_size_certified():
         its[name] = (float(np.mean([i.iters for i in info5])), sum(i.fallbacks for i in info5))
         s5.close()
     print(f"[fullsize] sphere L7 p3, 32 right-hand sides, mean iterations (fallbacks): {its}")
+
+
+def test_dg_baseline_equals_hdg_at_full_size():
+    """256 x 256 torus, p = 3, f = 1, Courant 2/7: the non-hybridised DG baseline
+    and the HDG path solve the same stage (Eq. linear_hybridized) to 1e-10 each;
+    their solutions agree to the tolerance."""
+    import torch
+    from paper_2004_09389_amd.hdg import HdgSolver
+    hier = hi.torus_hierarchy(256, 32)
+    print("[fullsize] dg baseline 256x256 p=3", flush=True)
+    s = HdgSolver(hier, 3, (2.0 / 7.0) / 256, 1.0, 1.0, 1.0, 0.0, rtol=1e-10, maxit=400, p1_tail_max=0)
+    s.dgs_setup()
+    r = torch.from_numpy(hi.fourier_rhs_torus(hier.fine, 3, 100)).cuda()
+    q_dg, info = s.dgs_solve(r)
+    q_hdg, _, hinfo = s.step(r)
+    assert info[0].status == 0 and hinfo[0].status == 0
+    d = float(torch.linalg.norm(q_dg - q_hdg) / torch.linalg.norm(q_hdg))
+    print(f"[fullsize] dg its {info[0].iters}, hdg its {hinfo[0].iters}, rel diff {d:.2e}", flush=True)
+    assert d < 1e-8
+    s.close()
+
+
+def test_imex_conserves_mass_and_keeps_the_vortex_at_full_size():
+    """256 x 256 torus, p = 3, the stationary vortex, 10 steps of each tableau at
+    the paper's time step: the domain integral of h is unchanged (the flux terms
+    are conservative, the Coriolis term leaves h alone) and the steady state
+    drifts by less than the solver tolerance allows."""
+    import torch
+    from oracle.hdg import LocalOperators
+    from paper_2004_09389_amd.hdg import HdgSolver, imex_gamma, imex_tableau
+    v = hi.Vortex()
+    n, p = 256, 3
+    hier = hi.torus_hierarchy(n, 32)
+    dt, _ = hi.paper_time_step(n, p)
+    # integral weights of the nodal basis: the row sums of a cell's mass matrix
+    # (every cell of the torus has the same shape and area 1 / (2 n^2))
+    small = LocalOperators(hi.torus(2), p, 1.0)
+    w = small.M[0].sum(axis=1) * ((1.0 / (2 * n * n)) / (1.0 / 8.0))
+    q0 = torch.from_numpy(hi.vortex_coefficients(hier.fine, p, v)).cuda()
+    wt = torch.from_numpy(w).cuda()
+    mass = lambda q: float((q[:, 0, :, 0] * wt).sum())
+    m0 = mass(q0)
+    for method, theta in (("theta", 0.5), ("ars232", 0.5), ("ssp322", 0.5), ("ars443", 0.5)):
+        tab = imex_tableau(method, theta)
+        print(f"[fullsize] imex {method}", flush=True)
+        s = HdgSolver(hier, p, imex_gamma(tab) * dt, v.c_g, v.c_g, 0.0, 0.0, rtol=1e-10, maxit=400, p1_tail_max=0)
+        q = q0.clone()
+        info = s.imex_run(tab, dt, v.f, q, 10)
+        assert info.status == 0
+        assert abs(mass(q) - m0) < 1e-10 * float((q0[:, 0, :, 0].abs() * wt).sum())
+        assert float(torch.linalg.norm(q - q0) / torch.linalg.norm(q0)) < 1e-5
+        s.close()
