@@ -326,6 +326,30 @@ def imex_leg(args, n=256, p=3, run_steps=20):
     log(f"[bench] imex ars232 ensemble of {nb}: {out['ars232_ensemble16']['ms_per_step']} ms/step "
         f"({out['ars232_ensemble16']['member_steps_per_s']} member-steps/s)")
     s.close()
+    # the paper's whole L-Up run: refinement r = 7 (128 x 128), p = 3, to T = 1/2, with
+    # Theta(1/2) (one solve per step, as its text says) and ARS2(2,3,2) (two, as its
+    # figure caption says); wall clock of the whole run including context setup
+    n7 = 128
+    hier7 = hi.torus_hierarchy(n7, args.coarse)
+    dt7, steps7 = hi.paper_time_step(n7, p)
+    q07 = torch.from_numpy(hi.vortex_coefficients(hier7.fine, p, v)).to("cuda")
+    for name, method in (("run_r7_theta", "theta"), ("run_r7_ars232", "ars232")):
+        tab = imex_tableau(method, 0.5)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        s = HdgSolver(hier7, p, imex_gamma(tab) * dt7, v.c_g, v.c_g, 0.0, 0.0, 1.0, rtol=args.rtol,
+                      precision=HDG_MIXED, krylov=2, maxit=200, p1_tail_max=args.tail_max,
+                      use_graph=0 if args.no_graph else 1)
+        q = q07.clone()
+        info = s.imex_run(tab, dt7, v.f, q, steps7)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t
+        out[name] = {"workload": f"vortex_torus{n7}x{n7}_p{p}_T0.5", "steps": steps7, "seconds_total": round(el, 3),
+                     "ms_per_step": round(1e3 * el / steps7, 4), "solves": info.solves,
+                     "iters_per_solve": round(info.iters_total / max(info.solves, 1), 2),
+                     "drift": float(torch.linalg.norm(q - q07) / torch.linalg.norm(q07))}
+        log(f"[bench] imex {name}: {steps7} steps to T = 1/2 in {el:.3f} s ({out[name]['ms_per_step']} ms/step)")
+        s.close()
     return out
 
 
