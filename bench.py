@@ -489,16 +489,23 @@ def main():
         infos = []
         if timing:
             s.set_timing(timing)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
         torch.cuda.synchronize()
         t = time.perf_counter()
-        for _ in range(steps):
+        ev[0].record()
+        for k in range(steps):
             s.condense(rhs, out=rhat)
             lam.zero_()
             _, info = s.solve(rhat, lam)
             s.recover(rhs, lam, out=q)
+            ev[k + 1].record()
             infos.append(info)
         torch.cuda.synchronize()
         el = time.perf_counter() - t
+        step_ms = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(steps)])
+        run.last_step_ms = {"median": round(float(np.median(step_ms)), 4),
+                            "p10": round(float(np.percentile(step_ms, 10)), 4),
+                            "p90": round(float(np.percentile(step_ms, 90)), 4), "steps": int(steps)}
         return el, infos, lam, q
 
     results = {}
@@ -513,6 +520,7 @@ def main():
         its = [i.iters for inf in infos for i in inf]
         res = max(i.rel_res for inf in infos for i in inf)
         rec = dict(el=el, its=float(np.mean(its)), res=res, lam=lam.clone(), q=q.clone(), setup=tsetup,
+                   step_ms=dict(run.last_step_ms),
                    refinements=float(np.mean([i.refinements for inf in infos for i in inf])),
                    fallbacks=int(sum(i.fallbacks for inf in infos for i in inf)))
         if name == "mixed":
@@ -603,6 +611,7 @@ def main():
         "steps": steps,
         "warmup": args.warmup,
         "ms_per_step": round(1e3 * mx["el"] / steps, 4),
+        "step_ms_events": mx["step_ms"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -639,8 +648,8 @@ def main():
     if "fp64" in results:
         fp = results["fp64"]
         out["fp64_baseline"] = {"value": round(steps * nb / fp["el"], 3), "unit": "solves/s",
-                                "ms_per_step": round(1e3 * fp["el"] / steps, 4), "iters": fp["its"],
-                                "rel_res_max": fp["res"]}
+                                "ms_per_step": round(1e3 * fp["el"] / steps, 4), "step_ms_events": fp["step_ms"],
+                                "iters": fp["its"], "rel_res_max": fp["res"]}
         if "batched" in fp:
             out["fp64_baseline"]["batched"] = fp["batched"]
         out["speedup_vs_fp64"] = round(fp["el"] / mx["el"], 3)
