@@ -45,6 +45,9 @@ def parse():
     ap.add_argument("--p1-nu", type=int, default=2, help="P1 Jacobi sweeps per level (pre and post)")
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-stream", action="store_true",
+                    help="skip the measured (STREAM triad, read and copy) HBM bandwidth")
+    ap.add_argument("--stream-only", action="store_true", help="only the measured HBM bandwidth")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison leg")
     ap.add_argument("--mixed-mode", default="mixed", choices=["mixed", "mixed_ir"],
                     help="mixed: FP64 Krylov + reduced-precision V-cycle; mixed_ir: FP64 refinement of an FP32 inner solve")
@@ -95,12 +98,33 @@ def measured_traffic(kernel_label):
     return None
 
 
-def cpu_baseline(n_full, p, dt):
-    """Time the FP64 CPU oracle (direct SuperLU trace solve with its own
-    condensation and recovery) on a bounded sample: one right-hand side on
-    the same problem with a quarter of the cells (n/2 x n/2 squares), single
-    threaded; the per-solve time is scaled by the cell ratio to the full
-    workload.  Also returns the oracle's solution of the sample."""
+def host_info():
+    """The host the oracle runs on: core counts, CPU model and the BLAS pools
+    with the thread counts in force where this is called."""
+    from threadpoolctl import threadpool_info
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_count": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)), "cpu_model": model,
+            "blas": [{"api": i.get("internal_api"), "threads": i.get("num_threads")} for i in threadpool_info()]}
+
+
+def cpu_baseline(n_full, p, dt, repeats=3):
+    """Time the FP64 CPU oracle on a bounded sample: the same problem with a
+    quarter of the cells (n/2 x n/2 squares), single threaded (SuperLU is
+    sequential and BLAS is held to one thread).  Set-up (local blocks and the
+    trace matrix) and the sparse LU factorisation are timed apart from the
+    per-right-hand-side work (condensed right-hand side, the two triangular
+    solves, recovery), as the GPU's timed step excludes its own set-up.  The
+    per-solve rate is the median of `repeats` solves scaled by the cell
+    ratio to the full workload.  Also returns the oracle's solution."""
+    import scipy.sparse.linalg as spla
     from threadpoolctl import threadpool_limits
 
     import hdg_inputs as hi
@@ -110,15 +134,98 @@ def cpu_baseline(n_full, p, dt):
     with threadpool_limits(limits=1):
         mesh = hi.torus(ns)
         r = hi.fourier_rhs_torus(mesh, p, 100)[..., 0]
-        o = HdgOracle(mesh, p, dt, 1.0, 1.0, 1.0)
         t0 = time.perf_counter()
-        q_ref, lam_ref = o.solve(r)
-        t = time.perf_counter() - t0
+        o = HdgOracle(mesh, p, dt, 1.0, 1.0, 1.0)
+        t1 = time.perf_counter()
+        lu = spla.splu(o.S.tocsc())
+        t2 = time.perf_counter()
+        ts = []
+        for _ in range(repeats):
+            t3 = time.perf_counter()
+            lam_ref = lu.solve(o.rhat(r))
+            q_ref = o.recover(r, lam_ref)
+            ts.append(time.perf_counter() - t3)
+        host = host_info()
+    t = float(np.median(ts))
     scale = (n_full / ns) ** 2
     out = {"value": 1.0 / (t * scale), "unit": "solves/s", "cores": 1, "kind": "oracle",
-           "sample": f"one solve on the {ns}x{ns} torus (p={p}, same dt and f; "
-                     f"{2 * ns * ns} cells), {t:.2f} s, scaled x{scale:.0f} to {2 * n_full * n_full} cells"}
+           "sample": f"{repeats} solves on the {ns}x{ns} torus (p={p}, same dt and f; {2 * ns * ns} cells, "
+                     f"{o.n_trace} trace unknowns): median {t:.3f} s per solve after a {t2 - t1:.2f} s LU "
+                     f"factorisation, scaled x{scale:.0f} to {2 * n_full * n_full} cells",
+           "setup_s": round(t1 - t0, 3), "factor_s": round(t2 - t1, 3), "solve_s": float(f"{t:.6g}"),
+           "value_incl_factor": 1.0 / ((t + t2 - t1) * scale),
+           "host": host}
     return out, (ns, r, q_ref, lam_ref)
+
+
+def measured_bandwidth(n=1 << 28, reps=10):
+    """Measured HBM bandwidth of the device (STREAM-style, arrays of n doubles,
+    far larger than the last-level cache): the library's triad a = b + s c,
+    read-only pass and copy (16-byte loads, hdg_stream_triad, hdg_stream_read,
+    hdg_copy), and the same three as torch's element-wise kernels; each the
+    best of `reps` launches timed with HIP events on the current stream.  The
+    read-only passes are the closest to the read-dominated trace apply."""
+    import torch
+
+    from paper_2004_09389_amd.hdg import device_copy, stream_read, stream_read_blocks, stream_triad
+
+    a = torch.empty(n, dtype=torch.float64, device="cuda")
+    b = torch.rand(n, dtype=torch.float64, device="cuda")
+    c = torch.rand(n, dtype=torch.float64, device="cuda")
+    part = torch.empty(stream_read_blocks(n), dtype=torch.float64, device="cuda")
+    legs = {"triad[libhdg]": (lambda: stream_triad(b, c, 3.0, a), 3),
+            "read[libhdg]": (lambda: stream_read(b, part), 1),
+            "copy[libhdg]": (lambda: device_copy(b, a), 2),
+            "triad[torch]": (lambda: torch.add(b, c, alpha=3.0, out=a), 3),
+            "copy[torch]": (lambda: a.copy_(b), 2),
+            "read[torch.sum]": (lambda: torch.sum(b), 1)}
+    out = {}
+    for name, (fn, arrays) in legs.items():
+        fn()
+        best = None
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            ms = e0.elapsed_time(e1)
+            best = ms if best is None else min(best, ms)
+        out[name] = round(arrays * n * 8 / (best * 1e-3) / 1e9, 1)
+    del a, b, c, part
+    torch.cuda.empty_cache()
+    return out
+
+
+def apply_cache_check(s, x, reps=20, flush_doubles=1 << 27):
+    """The FP64 trace apply (hdg_trace_apply) timed two ways with the
+    library's own per-launch HIP events: warm, launches back to back, where
+    its rows (138 MB at 256^2, p = 3) can stay in the 256 MB Infinity Cache;
+    and cold, a read of a 1 GiB buffer (hdg_stream_read) before every launch,
+    outside the event pair, which evicts the L2 and the Infinity Cache so that
+    every byte of the apply comes from HBM."""
+    import torch
+
+    from paper_2004_09389_amd.hdg import HDG_FP64, stream_read, stream_read_blocks
+
+    flush = torch.ones(flush_doubles, dtype=torch.float64, device="cuda")
+    part = torch.empty(stream_read_blocks(flush_doubles), dtype=torch.float64, device="cuda")
+    y = s.trace_zeros(x.shape[-1])
+    out = {}
+    for name, repeat, pre in (("warm", TIMING_REPEAT, None), ("cold", 1, lambda: stream_read(flush, part))):
+        s.set_timing(repeat)
+        for _ in range(reps):
+            if pre is not None:
+                pre()
+            s.trace_apply(x, HDG_FP64, out=y)
+        n, ms, b = s.kernel_stats("apply", HDG_FP64)
+        us = 1e3 * ms / max(n, 1)
+        out[name] = {"avg_us": round(us, 3), "GBps": round(b / (us * 1e-6) / 1e9, 1), "launches": n}
+        out["bytes_per_launch"] = b
+    s.set_timing(0)
+    del flush, part
+    torch.cuda.empty_cache()
+    return out
 
 
 def errors_vs_oracle(sample, p, dt, rtol, coarse, learned_weights):
@@ -427,6 +534,9 @@ def main():
 
     torch.cuda.set_device(0)
     p, n, nb = args.degree, args.n, args.nrhs
+    if args.stream_only:
+        print(json.dumps({"measured_GBps": measured_bandwidth()}), flush=True)
+        return
     if args.sphere_only:
         print(json.dumps({"sphere_leg": sphere_leg(args, None, run_steps=args.steps)}), flush=True)
         return
@@ -536,6 +646,8 @@ def main():
             run(s, args.steps, timing=TIMING_REPEAT)
             rec["stats"] = {(k, pr): s.kernel_stats(k, pr) for k in classes for pr in (HDG_FP64, HDG_MIXED)}
             s.set_timing(False)
+            if not args.pmc_run:
+                rec["apply_cache"] = apply_cache_check(s, s.condense(rd))
         if args.batch > 1 and not args.pmc_run:
             sb, _ = make(prec, nb_override=args.batch, learned=name == "learned")
             rb = torch.from_numpy(hi.fourier_rhs_torus(mesh, p, 200, nrhs=args.batch)).to("cuda")
@@ -599,6 +711,12 @@ def main():
                 "timing": f"HIP events on the launch stream around every launch of the kernel in an "
                           f"instrumented eager pass of the same steps right after the timed (graph-replayed) "
                           f"pass; each instrumented launch issued {TIMING_REPEAT}x back to back per event pair"}
+    if "apply_cache" in mx:
+        roofline["apply_warm_vs_cold"] = mx["apply_cache"]
+    if not args.no_stream:
+        bw = measured_bandwidth()
+        best = max(bw.values())
+        roofline.update({"peak_measured": best, "frac_measured": round(achieved / best, 4), "measured_GBps": bw})
     kern = {f"{k}[{pname[pr]}]": {"launches": v[0], "total_ms": round(v[1], 3),
                                   "avg_us": round(1e3 * v[1] / max(v[0], 1), 3),
                                   "GBps": round(v[2] / (v[1] / max(v[0], 1) / 1e3) / 1e9, 1) if v[1] > 0 else None}

@@ -438,6 +438,23 @@ int hdg_kernel_stats(hdg_ctx *ctx, int32_t kernel, int32_t precision, int64_t *l
  * kernel whose HBM counters calibrate the profiler's byte counts. */
 int hdg_copy(const double *src, double *dst, int64_t n, void *stream);
 
+/* Bandwidth probes (measurement only, not part of a solve): the measured HBM
+ * bandwidth that the roofline reports beside the datasheet peak.  Both are
+ * asynchronous on the stream and take device arrays of doubles; a block
+ * covers a chunk of 2048 doubles with 16-byte loads.
+ *
+ * hdg_stream_triad: a[i] = b[i] + s * c[i] for 0 <= i < n (STREAM's triad).
+ *   a, b and c are 16-byte aligned; a overlaps neither b nor c (b may equal c).
+ * hdg_stream_read: partial[k] = the sum of src[2048 k ... 2048 k + 2047]
+ *   (clipped to n) for k < hdg_stream_read_blocks(n), which is ceil(n / 2048);
+ *   src is 16-byte aligned and the caller-owned partial holds at least
+ *   n_partial >= hdg_stream_read_blocks(n) doubles and does not overlap src.
+ * n = 0 launches nothing and accepts NULL pointers.  Otherwise HDG_EINVAL for
+ * NULL, misaligned or overlapping arrays, n < 0 or a short partial. */
+int hdg_stream_triad(const double *b, const double *c, double s, double *a, int64_t n, void *stream);
+int64_t hdg_stream_read_blocks(int64_t n);
+int hdg_stream_read(const double *src, int64_t n, double *partial, int64_t n_partial, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -14,7 +14,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libhdg.so")
 SOURCES = ["csrc/hdg_host.cpp", "csrc/hdg_rt0_host.cpp", "csrc/hdg_kernels.hip", "csrc/hdg_mlp.hip",
-           "csrc/hdg_rt0.hip", "csrc/hdg_imex.hip", "csrc/hdg_dgs.hip", "csrc/hdg_api.hip"]
+           "csrc/hdg_rt0.hip", "csrc/hdg_imex.hip", "csrc/hdg_dgs.hip", "csrc/hdg_stream.hip",
+           "csrc/hdg_api.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

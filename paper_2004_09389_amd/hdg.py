@@ -97,6 +97,9 @@ _SIGS = {
     "hdg_kernel_stats": (_I, [_P, _I, _I, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
                               ctypes.POINTER(ctypes.c_double)]),
     "hdg_copy": (_I, [_P, _P, ctypes.c_int64, _P]),
+    "hdg_stream_triad": (_I, [_P, _P, ctypes.c_double, _P, ctypes.c_int64, _P]),
+    "hdg_stream_read_blocks": (ctypes.c_int64, [ctypes.c_int64]),
+    "hdg_stream_read": (_I, [_P, ctypes.c_int64, _P, ctypes.c_int64, _P]),
     "hdg_get_tuning": (_I, [_P, ctypes.POINTER(HdgTuning)]),
     "hdg_set_tuning": (_I, [_P, ctypes.POINTER(HdgTuning)]),
     "hdg_autotune": (_I, [_P, _I, ctypes.POINTER(HdgTuning), _P]),
@@ -429,6 +432,31 @@ class HdgSolver:
 
 def device_copy(src, dst):
     _check(load_library().hdg_copy(_ptr(src), _ptr(dst), src.numel(), _stream()))
+
+
+def _dev_f64(*ts):
+    import torch
+    for t in ts:
+        if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+            raise ValueError("expected contiguous float64 CUDA tensors")
+
+
+def stream_triad(b, c, s, a):
+    """a = b + s c on the current stream (hdg_stream_triad); float64 CUDA tensors."""
+    _dev_f64(a, b, c)
+    if not (a.numel() == b.numel() == c.numel()):
+        raise ValueError("a, b and c must have the same length")
+    _check(load_library().hdg_stream_triad(_ptr(b), _ptr(c), float(s), _ptr(a), a.numel(), _stream()))
+
+
+def stream_read_blocks(n: int) -> int:
+    return int(load_library().hdg_stream_read_blocks(int(n)))
+
+
+def stream_read(src, partial):
+    """Per-chunk sums of src into partial on the current stream (hdg_stream_read)."""
+    _dev_f64(src, partial)
+    _check(load_library().hdg_stream_read(_ptr(src), src.numel(), _ptr(partial), partial.numel(), _stream()))
 
 
 def imex_tableau(method: str, theta: float = 0.5) -> HdgImexTableau:

@@ -115,3 +115,21 @@ def test_imex_entry_points_reject_bad_arguments_without_gpu():
     assert lib.hdg_dg_tendency(None, 1, 0.1, None, None, None) == hdg.HDG_EINVAL
     assert lib.hdg_dgs_setup(None, None, 0, None) == hdg.HDG_EINVAL
     assert lib.hdg_dgs_solve(None, 1, None, None, None, None) == hdg.HDG_EINVAL
+
+
+def test_bandwidth_probes_check_arguments_before_any_launch():
+    """Every rejected call fails its host-side check, so no pointer here is used."""
+    lib = hdg.load_library()
+    P = ctypes.c_void_p
+    assert [lib.hdg_stream_read_blocks(n) for n in (0, 1, 2048, 2049, -3)] == [0, 1, 1, 2, 0]
+    E = hdg.HDG_EINVAL
+    assert lib.hdg_stream_triad(None, None, 1.0, None, 4, None) == E
+    assert lib.hdg_stream_triad(P(4096), P(8192), 1.0, P(65536), -1, None) == E
+    assert lib.hdg_stream_triad(P(4096 + 8), P(1 << 20), 1.0, P(1 << 21), 4, None) == E  # misaligned
+    assert lib.hdg_stream_triad(P(4096), P(8192), 1.0, P(4096 + 16), 4, None) == E  # a overlaps b
+    assert lib.hdg_stream_read(None, 4, P(4096), 1, None) == E
+    assert lib.hdg_stream_read(P(4096), 4097, P(1 << 20), 2, None) == E  # partial too short
+    assert lib.hdg_stream_read(P(4096 + 8), 4, P(1 << 20), 1, None) == E  # misaligned
+    assert lib.hdg_stream_read(P(4096), 4096, P(4096 + 64), 2, None) == E  # partial overlaps src
+    assert lib.hdg_stream_triad(None, None, 1.0, None, 0, None) == hdg.HDG_OK  # empty: nothing launched
+    assert lib.hdg_stream_read(None, 0, None, 0, None) == hdg.HDG_OK
