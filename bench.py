@@ -46,7 +46,8 @@ def parse():
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-stream", action="store_true",
-                    help="skip the measured (STREAM triad, read and copy) HBM bandwidth")
+                    help="skip the measured (STREAM triad, read and copy) HBM bandwidth and the "
+                         "warm / cold timing of the FP64 apply")
     ap.add_argument("--stream-only", action="store_true", help="only the measured HBM bandwidth")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison leg")
     ap.add_argument("--mixed-mode", default="mixed", choices=["mixed", "mixed_ir"],
@@ -646,7 +647,7 @@ def main():
             run(s, args.steps, timing=TIMING_REPEAT)
             rec["stats"] = {(k, pr): s.kernel_stats(k, pr) for k in classes for pr in (HDG_FP64, HDG_MIXED)}
             s.set_timing(False)
-            if not args.pmc_run:
+            if not args.pmc_run and not args.no_stream:
                 rec["apply_cache"] = apply_cache_check(s, s.condense(rd))
         if args.batch > 1 and not args.pmc_run:
             sb, _ = make(prec, nb_override=args.batch, learned=name == "learned")

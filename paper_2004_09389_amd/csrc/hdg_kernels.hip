@@ -1319,13 +1319,23 @@ __device__ __forceinline__ typename Acc<MT>::type lds_entry(const MT *p) {
 // stage the G 16-byte groups of the rows of facets f0 .. f0 + 63 as [g][64][V]
 template <typename MT, int G>
 __device__ __forceinline__ void stage_rows(MT *sm, const MT *__restrict__ S, int f0, int ne) {
-    constexpr int V = Wide<MT>::V;
+    // four 16-byte loads per lane go out before their LDS stores
+    constexpr int V = Wide<MT>::V, W = G * RB_FACETS, U = 4;
     const size_t NE = (size_t)ne;
-    for (int i = threadIdx.x; i < G * RB_FACETS; i += blockDim.x) {
-        const int g = i / RB_FACETS, el = i - g * RB_FACETS, e = f0 + el;
-        u32x4_t v = {0u, 0u, 0u, 0u};
-        if (e < ne) v = *reinterpret_cast<const u32x4_t *>(S + ((size_t)g * NE + e) * V);
-        *reinterpret_cast<u32x4_t *>(sm + (size_t)i * V) = v;
+    const int step = blockDim.x;
+    for (int i0 = threadIdx.x; i0 < W; i0 += U * step) {
+        u32x4_t v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u * step, g = i / RB_FACETS, e = f0 + (i - g * RB_FACETS);
+            v[u] = u32x4_t{0u, 0u, 0u, 0u};
+            if (i < W && e < ne) v[u] = __builtin_nontemporal_load(reinterpret_cast<const u32x4_t *>(S + ((size_t)g * NE + e) * V));
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u * step;
+            if (i < W) *reinterpret_cast<u32x4_t *>(sm + (size_t)i * V) = v[u];
+        }
     }
 }
 
@@ -1351,18 +1361,46 @@ __device__ __forceinline__ void load_rb(const T *__restrict__ p, double (&d)[RB]
 }
 template <int RB, typename T>
 __device__ __forceinline__ void store_rb(T *__restrict__ p, const double (&d)[RB]) {
+    // streaming stores: the outputs are not read again by this launch
     if constexpr (std::is_same<T, double>::value) {
 #pragma unroll
-        for (int q = 0; q < RB; q += 2) *reinterpret_cast<dbl2_t *>(p + q) = dbl2_t{d[q], d[q + 1]};
+        for (int q = 0; q < RB; q += 2)
+            __builtin_nontemporal_store(dbl2_t{d[q], d[q + 1]}, reinterpret_cast<dbl2_t *>(p + q));
     } else {
 #pragma unroll
         for (int q = 0; q < RB; q += 4)
-            *reinterpret_cast<trace_flt4_t *>(p + q) =
-                trace_flt4_t{(float)d[q], (float)d[q + 1], (float)d[q + 2], (float)d[q + 3]};
+            __builtin_nontemporal_store(trace_flt4_t{(float)d[q], (float)d[q + 1], (float)d[q + 2], (float)d[q + 3]},
+                                        reinterpret_cast<trace_flt4_t *>(p + q));
+    }
+}
+
+// RB consecutive values in their stored type, 16 bytes per load
+template <int RB, typename T>
+__device__ __forceinline__ void load_raw(const T *__restrict__ p, T (&d)[RB]) {
+    if constexpr (std::is_same<T, double>::value) {
+#pragma unroll
+        for (int q = 0; q < RB; q += 2) {
+            const dbl2_t a = *reinterpret_cast<const dbl2_t *>(p + q);
+            d[q] = a.x;
+            d[q + 1] = a.y;
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < RB; q += 4) {
+            const trace_flt4_t a = *reinterpret_cast<const trace_flt4_t *>(p + q);
+            d[q] = a.x;
+            d[q + 1] = a.y;
+            d[q + 2] = a.z;
+            d[q + 3] = a.w;
+        }
     }
 }
 
 // y = S x or y = b - S x
+//
+// Latency: a lane requests its four neighbour ids and its own facet's values
+// before the block stages its rows, so those waits overlap the staging; each
+// neighbour then costs one wait (its values), not two (id, then values).
 template <int M, typename MT, typename XT, typename YT, int RB>
 __global__ __launch_bounds__(1024) void k_trace_apply_rb(int ne, int nb, const MT *__restrict__ S,
                                                          const int *__restrict__ nbr, const XT *__restrict__ x,
@@ -1371,23 +1409,30 @@ __global__ __launch_bounds__(1024) void k_trace_apply_rb(int ne, int nb, const M
     constexpr int V = Wide<MT>::V, C = 5 * M * M, G = padded(C, V) / V;
     __shared__ __attribute__((aligned(16))) MT sm[G * RB_FACETS * V];
     const int f0 = xcd_block() * RB_FACETS;
-    stage_rows<MT, G>(sm, S, f0, ne);
-    __syncthreads();
     const int tpf = nb / RB;
     const int el = threadIdx.x / tpf, r0 = (threadIdx.x - el * tpf) * RB, e = f0 + el;
-    if (e >= ne) return;
+    const bool live = e < ne;
     const size_t NE = (size_t)ne;
+    int id[4] = {0, 0, 0, 0};
+    XT xa[M][RB];
+    auto fetch = [&](int f, XT (&xv)[M][RB]) {
+#pragma unroll
+        for (int k = 0; k < M; ++k) load_raw<RB>(x + ((size_t)f * M + k) * nb + r0, xv[k]);
+    };
+    if (live) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) id[j] = nbr[(size_t)j * NE + e];
+        fetch(e, xa);
+    }
+    stage_rows<MT, G>(sm, S, f0, ne);
+    __syncthreads();
+    if (!live) return;
     AT acc[M][RB];
 #pragma unroll
     for (int a = 0; a < M; ++a)
 #pragma unroll
         for (int q = 0; q < RB; ++q) acc[a][q] = 0;
-#pragma unroll 1
-    for (int j = 0; j < 5; ++j) {   // one neighbour's values in flight at a time keeps the registers in bounds
-        const int id = j == 0 ? e : nbr[(size_t)(j - 1) * NE + e];
-        double xv[M][RB];
-#pragma unroll
-        for (int k = 0; k < M; ++k) load_rb<RB>(x + ((size_t)id * M + k) * nb + r0, xv[k]);
+    auto mac = [&](int j, const XT (&xv)[M][RB]) {
 #pragma unroll
         for (int a = 0; a < M; ++a)
 #pragma unroll
@@ -1397,6 +1442,13 @@ __global__ __launch_bounds__(1024) void k_trace_apply_rb(int ne, int nb, const M
 #pragma unroll
                 for (int q = 0; q < RB; ++q) acc[a][q] += w * (AT)xv[k][q];
             }
+    };
+    mac(0, xa);
+#pragma unroll 1
+    for (int j = 1; j < 5; ++j) {   // one neighbour's values in flight at a time keeps the registers in bounds
+        const int f = j == 1 ? id[0] : j == 2 ? id[1] : j == 3 ? id[2] : id[3];
+        fetch(f, xa);
+        mac(j, xa);
     }
 #pragma unroll
     for (int a = 0; a < M; ++a) {
@@ -1427,12 +1479,17 @@ __global__ __launch_bounds__(1024) void k_sweep_rb(int ne, int nb, const MT *__r
     constexpr int V = Wide<MT>::V, C = 4 * M * M, G = padded(C, V) / V;
     __shared__ __attribute__((aligned(16))) MT sm[G * RB_FACETS * V];
     const int f0 = xcd_block() * RB_FACETS;
-    stage_rows<MT, G>(sm, T, f0, ne);
-    __syncthreads();
     const int tpf = nb / RB;
     const int el = threadIdx.x / tpf, r0 = (threadIdx.x - el * tpf) * RB, e = f0 + el;
-    if (e >= ne) return;
+    const bool live = e < ne;
     const size_t NE = (size_t)ne;
+    int id[4] = {0, 0, 0, 0};   // requested before the rows are staged
+    if (live)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) id[j] = nbr[(size_t)j * NE + e];
+    stage_rows<MT, G>(sm, T, f0, ne);
+    __syncthreads();
+    if (!live) return;
     auto iterate = [&](int id, double (&xv)[M][RB]) {
 #pragma unroll
         for (int k = 0; k < M; ++k) load_rb<RB>(x + ((size_t)id * M + k) * nb + r0, xv[k]);
@@ -1454,7 +1511,7 @@ __global__ __launch_bounds__(1024) void k_sweep_rb(int ne, int nb, const MT *__r
 #pragma unroll 1
     for (int j = 0; j < 4; ++j) {   // one neighbour's values in flight at a time keeps the registers in bounds
         double xv[M][RB];
-        iterate(nbr[(size_t)j * NE + e], xv);
+        iterate(j == 0 ? id[0] : j == 1 ? id[1] : j == 2 ? id[2] : id[3], xv);
 #pragma unroll
         for (int a = 0; a < M; ++a)
 #pragma unroll
