@@ -159,6 +159,44 @@ def cpu_baseline(n_full, p, dt, repeats=3):
     return out, (ns, r, q_ref, lam_ref)
 
 
+def oracle_per_config(repeats=3):
+    """The CPU oracle's per-right-hand-side rate on the other workloads, timed
+    like cpu_baseline (one thread, factorisation apart): the 8 x 8 torus
+    (p = 1, f = 0, Courant 4) at full size, and the level-6 (p = 2) and
+    level-7 (p = 3) spheres from a level-5 sample scaled by the cell ratio."""
+    import scipy.sparse.linalg as spla
+    from threadpoolctl import threadpool_limits
+
+    import hdg_inputs as hi
+    from oracle.hdg import HdgOracle
+
+    out = {}
+    with threadpool_limits(limits=1):
+        sph5 = hi.icosphere_hierarchy(5, 6.371e6, level_coarse=3).fine
+        cases = (("torus8x8_p1_courant4", hi.torus(8), 1, (0.5, 1.0, 1.0, 0.0, 0.0), 1.0),
+                 ("icosphere_L6_p2_dt1800", sph5, 2, (1800.0, 9.81, 5960.0, 0.0, 7.292e-5), 4.0),
+                 ("icosphere_L7_p3_dt3600", sph5, 3, (3600.0, 9.81, 5960.0, 0.0, 7.292e-5), 16.0))
+        for name, mesh, p, prm, scale in cases:
+            r = hi.iid_rhs(mesh, p, 500)[..., 0]
+            t0 = time.perf_counter()
+            o = HdgOracle(mesh, p, *prm)
+            t1 = time.perf_counter()
+            lu = spla.splu(o.S.tocsc())
+            t2 = time.perf_counter()
+            ts = []
+            for _ in range(repeats):
+                t3 = time.perf_counter()
+                o.recover(r, lu.solve(o.rhat(r)))
+                ts.append(time.perf_counter() - t3)
+            t = float(np.median(ts))
+            out[name] = {"value": 1.0 / (t * scale), "unit": "solves/s", "cores": 1,
+                         "sample": ("full size" if scale == 1.0 else
+                                    f"level-5 sphere ({mesh.n_cell} cells), scaled x{scale:.0f} by cells"),
+                         "setup_s": round(t1 - t0, 3), "factor_s": round(t2 - t1, 3),
+                         "solve_s": float(f"{t:.6g}"), "trace_unknowns": int(o.n_trace)}
+    return out
+
+
 def measured_bandwidth(n=1 << 28, reps=10):
     """Measured HBM bandwidth of the device (STREAM-style, arrays of n doubles,
     far larger than the last-level cache): the library's triad a = b + s c,
@@ -796,6 +834,7 @@ def main():
     if not args.no_cpu:
         log("[bench] cpu oracle baseline ...")
         out["cpu_baseline"], sample = cpu_baseline(n, p, dt)
+        out["cpu_baseline"]["per_config"] = oracle_per_config()
         out["error_vs_oracle"] = {
             "sample": f"{sample[0]}x{sample[0]} torus, p={p}, same dt and f, right-hand side seed 100, rtol {args.rtol}",
             **errors_vs_oracle(sample, p, dt, args.rtol, args.coarse, trained.get("W"))}
