@@ -49,6 +49,8 @@ def parse():
                     help="skip the measured (STREAM triad, read and copy) HBM bandwidth and the "
                          "warm / cold timing of the FP64 apply")
     ap.add_argument("--stream-only", action="store_true", help="only the measured HBM bandwidth")
+    ap.add_argument("--no-small", action="store_true", help="skip the 8x8-torus (latency-bound) leg")
+    ap.add_argument("--small-only", action="store_true", help="only the 8x8-torus leg")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison leg")
     ap.add_argument("--mixed-mode", default="mixed", choices=["mixed", "mixed_ir"],
                     help="mixed: FP64 Krylov + reduced-precision V-cycle; mixed_ir: FP64 refinement of an FP32 inner solve")
@@ -403,6 +405,45 @@ def sphere_leg(args, weights, run_steps, level=7, p=3, dt=3600.0, nb=None, seed=
     return out
 
 
+def small_leg(args, run_steps=200):
+    """The small workload: 8 x 8 torus (128 cells), p = 1, g = H = 1, f = 0,
+    dt = 0.5 (Courant 4), iid right-hand side (seed 500), FP64 PCG with the
+    trace multigrid to 1e-10.  At 384 trace unknowns a solve is bound by
+    launch latency, so it is reported as microseconds per solve (graph replay
+    per solve), beside the oracle's rate on the same problem."""
+    import torch
+
+    import hdg_inputs as hi
+    from paper_2004_09389_amd.hdg import HDG_FP64, HDG_KRYLOV_PCG, HdgSolver
+    hier = hi.torus_hierarchy(8, 4)
+    s = HdgSolver(hier, 1, 0.5, 1.0, 1.0, 0.0, 0.0, rtol=1e-10, precision=HDG_FP64, krylov=HDG_KRYLOV_PCG,
+                  use_graph=0 if args.no_graph else 1)
+    r = torch.from_numpy(hi.iid_rhs(hier.fine, 1, 500)).to("cuda")
+    lam, rhat, q = s.trace_zeros(1), s.trace_zeros(1), s.cell_zeros(1)
+
+    def step():
+        s.condense(r, out=rhat)
+        lam.zero_()
+        _, info = s.solve(rhat, lam)
+        s.recover(r, lam, out=q)
+        return info
+    for _ in range(5):
+        step()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    infos = [step() for _ in range(run_steps)]
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t
+    s.close()
+    out = {"workload": "torus8x8_p1_f0_courant4", "n_cell": hier.fine.n_cell, "n_trace_dof": 384,
+           "rtol": 1e-10, "krylov": "pcg", "steps": run_steps, "us_per_solve": round(1e6 * el / run_steps, 2),
+           "value": round(run_steps / el, 1), "unit": "solves/s",
+           "iters": float(np.mean([i.iters for inf in infos for i in inf])),
+           "rel_res_max": max(i.rel_res for inf in infos for i in inf)}
+    log(f"[bench] small: {out['us_per_solve']} us/solve, {out['iters']} iterations")
+    return out
+
+
 def imex_leg(args, n=256, p=3, run_steps=20):
     """IMEX time stepping of the linear SWE on the paper's stationary vortex
     (L-Up: flat bathymetry, upwind flux; c_g = 1.89, f = 4 pi) at refinement
@@ -573,6 +614,9 @@ def main():
 
     torch.cuda.set_device(0)
     p, n, nb = args.degree, args.n, args.nrhs
+    if args.small_only:
+        print(json.dumps({"small_leg": small_leg(args)}), flush=True)
+        return
     if args.stream_only:
         print(json.dumps({"measured_GBps": measured_bandwidth()}), flush=True)
         return
@@ -715,6 +759,9 @@ def main():
     imex_out = None
     if not args.no_imex and not args.pmc_run:
         imex_out = imex_leg(args, n, p, run_steps=min(args.steps, 20))
+    small_out = None
+    if not args.no_small and not args.pmc_run:
+        small_out = small_leg(args)
     dg_out = None
     if not args.no_dg and not args.pmc_run:
         dg_out = dg_leg(args, p, n, run_steps=min(args.steps, 3))
@@ -828,6 +875,8 @@ def main():
         out["imex_leg"] = imex_out
     if dg_out is not None:
         out["dg_leg"] = dg_out
+    if small_out is not None:
+        out["small_leg"] = small_out
     if sphere_out is not None:
         out["sphere_leg"] = sphere_out
         out["sphere_l6_leg"] = sphere6_out
