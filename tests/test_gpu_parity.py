@@ -210,8 +210,21 @@ def test_rhs_blocked_rows_bitwise(name, nb):
     """Four right-hand sides per thread with LDS-staged rows accumulate in the
     same order as one thread per (facet, rhs): bitwise-equal apply, residual
     and V-cycles, each column matching the oracle."""
+    _rhs_blocked_bitwise(name, nb)
+
+
+@pytest.mark.parametrize("name,nb", [("torus16_p3_f1", 32), ("torus16_p3_f1", 64), ("sphere_L2_p2", 8)])
+def test_rhs_blocked_rows_bitwise_wide_blocks(name, nb):
+    """The same at 512- and 1024-thread blocks (32 and 64 right-hand sides,
+    where the row staging covers the block in one partial batch) and on a
+    sphere whose facet count leaves a ragged last block."""
+    _rhs_blocked_bitwise(name, nb)
+
+
+def _rhs_blocked_bitwise(name, nb):
     from paper_2004_09389_amd.hdg import HDG_MIXED
-    hier, s, oracle, mg = setup_case(name, max_rhs=16)
+    print(f"[rb] {name} nb={nb}", flush=True)
+    hier, s, oracle, mg = setup_case(name, max_rhs=max(16, nb))
     x = np.random.default_rng(60 + nb).standard_normal((s.n_facet, s.m, nb))
     xd = to_dev(x)
     outs = {}
