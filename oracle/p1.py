@@ -27,9 +27,12 @@
   start vector v_i = (((i * 2654435761) mod 2^32) / 2^32) - 1/2 (i the global
   trace index): v <- D^-1 S v / ||D^-1 S v||, estimate = ||D^-1 S v||.
 
-Parity unpinned for the multigrid iteration itself: no printed reference
-exists for this smoother; the tests pin only that it is a convergent linear
-preconditioner and that the coarse operator has the right scale.
+The V-cycles as linear operators are pinned to the textbook iteration
+matrices (two-level and recursive V-cycle forms built from the explicit level
+matrices), the coarse operator to its scale, the smoother blocks to the
+diagonal blocks of S.  Parity unpinned for the convergence rate the cycle
+reaches: no printed reference exists for this smoother beyond the paper's
+iteration counts, which the tests bound.
 """
 from __future__ import annotations
 

@@ -395,3 +395,60 @@ def test_galerkin_coarse_correction_is_a_projection():
         for l in range(1, len(mg.A)):
             P = mg.P[l - 1].toarray()
             assert np.abs(mg.A[l - 1].toarray() - P.T @ mg.A[l].toarray() @ P).max() < 1e-12 * np.abs(mg.A[l].toarray()).max()
+
+
+def _vcycle_by_recursion(A, P, omega, nu):
+    """Textbook V-cycle recursion on explicit dense matrices: B_0 = A_0^-1 and
+    I - B_l A_l = J_l^nu (I - P B_{l-1} P^T A_l) J_l^nu, J_l = I - omega diag(A_l)^-1 A_l."""
+    B = np.linalg.inv(A[0])
+    for l in range(1, len(A)):
+        I = np.eye(A[l].shape[0])
+        J = np.linalg.matrix_power(I - omega * (A[l] / np.diag(A[l])[:, None]), nu)
+        E = J @ (I - P[l - 1] @ B @ P[l - 1].T @ A[l]) @ J
+        B = (I - E) @ np.linalg.inv(A[l])
+    return B
+
+
+def test_p1_vcycle_is_the_textbook_recursion():
+    """The P1 multigrid V-cycle, as a matrix (its action on every unit vector),
+    equals the standard recursion of the two-grid iteration matrix built from
+    the level operators and transfers: pins the smoothing counts, the order
+    of smoothing and coarse correction, and restriction as the transpose of
+    prolongation (a dropped sweep or a sign error moves it by O(1))."""
+    from oracle.p1 import P1Multigrid
+    hier = hi.torus_hierarchy(8, 2)
+    mg = P1Multigrid(hier, 0.3, omega=2.0 / 3.0, nu=2)
+    n = hier.fine.n_vert
+    B = np.column_stack([mg.vcycle(e) for e in np.eye(n)])
+    ref = _vcycle_by_recursion([a.toarray() for a in mg.A], [p.toarray() for p in mg.P], 2.0 / 3.0, 2)
+    assert len(mg.A) == 3
+    assert np.abs(B - ref).max() < 1e-10 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("exact", [True, False])
+def test_trace_vcycle_is_the_two_level_iteration_matrix(exact):
+    """Non-nested two-level cycle (Alg. twolevel_vcycle), f != 0 so S is
+    unsymmetric: I - B S = J^nu_post (I - pi B_c pi^T S) J^nu_pre with
+    J = I - omega D^-1 S (D the facet diagonal blocks, inverted here from S
+    directly) and B_c the exact coarse inverse or the textbook P1 V-cycle."""
+    hier = hi.torus_hierarchy(4, 2)
+    o = HdgOracle(hier.fine, 1, 0.3, f0=0.5)
+    tm = TraceMultigrid(o, hier, exact_coarse=exact)
+    n, m = o.n_trace, o.m
+    B = np.column_stack([tm.vcycle(e) for e in np.eye(n)])
+    S = o.S.toarray()
+    Dinv = np.zeros_like(S)
+    for e in range(n // m):
+        sl = slice(e * m, (e + 1) * m)
+        Dinv[sl, sl] = np.linalg.inv(S[sl, sl])
+    I = np.eye(n)
+    J = I - tm.omega * Dinv @ S
+    if exact:
+        Bc = np.linalg.inv(tm.Sc.toarray())
+    else:
+        Bc = _vcycle_by_recursion([a.toarray() for a in tm.mg.A], [p.toarray() for p in tm.mg.P],
+                                  tm.mg.omega, tm.mg.nu)
+    pi = tm.pi.toarray()
+    E = np.linalg.matrix_power(J, tm.nu_post) @ (I - pi @ Bc @ pi.T @ S) @ np.linalg.matrix_power(J, tm.nu_pre)
+    ref = (I - E) @ np.linalg.inv(S)
+    assert np.abs(B - ref).max() < 1e-10 * np.abs(ref).max()
