@@ -50,9 +50,12 @@ vertex, exact patch solve, damping omega_p), whose patches contain the
 discrete-divergence-free fields that point Jacobi cannot smooth; the coarsest
 level is solved with a dense inverse.
 
-Parity unpinned for the V-cycle's iteration behaviour (no printed reference
-for this configuration); the pins fix the discretisation, the transfer and
-the coarse scale.
+The trace cycle as a linear operator is pinned to the two-level iteration
+matrix (exact RT0 coarse inverse, and the textbook RT0 V-cycle with
+vertex-patch Schwarz smoothing built from explicit matrices); the other pins
+fix the discretisation, the transfer and the coarse scale.  Parity unpinned
+for the convergence rate the cycle reaches (no printed reference for this
+configuration beyond the paper's iteration counts).
 """
 from __future__ import annotations
 

@@ -270,3 +270,55 @@ def test_lf_vcycle_symmetric_and_iteration_count():
         rz = rzn
     assert np.linalg.norm(b - h.S @ x) <= 1e-8 * np.linalg.norm(b)
     assert its <= 20
+
+
+def _schwarz_vcycle_by_recursion(meshes, A, P, omega, nu):
+    """Textbook V-cycle recursion with additive Schwarz smoothing over vertex
+    patches (the facets touching each vertex, found here from the topology):
+    J = I - omega sum_v R_v^T (R_v A R_v^T)^-1 R_v A, B_0 = A_0^-1,
+    I - B_l A_l = J^nu (I - P B_{l-1} P^T A_l) J^nu."""
+    from oracle.fem import topology
+    B = np.linalg.inv(A[0])
+    for l in range(1, len(A)):
+        n = A[l].shape[0]
+        fv = topology(meshes[l]).facet_vert
+        M = np.zeros((n, n))
+        for v in range(meshes[l].n_vert):
+            idx = np.flatnonzero((fv[:, 0] == v) | (fv[:, 1] == v))
+            M[np.ix_(idx, idx)] += np.linalg.inv(A[l][np.ix_(idx, idx)])
+        I = np.eye(n)
+        J = np.linalg.matrix_power(I - omega * M @ A[l], nu)
+        E = J @ (I - P[l - 1] @ B @ P[l - 1].T @ A[l]) @ J
+        B = (I - E) @ np.linalg.inv(A[l])
+    return B
+
+
+@pytest.mark.parametrize("exact", [True, False])
+def test_lf_vcycle_is_the_two_level_iteration_matrix(exact):
+    """The Lax-Friedrichs trace cycle (Alg. twolevel_vcycle with the RT0 coarse
+    space) as a matrix: I - B S = J^2 (I - pi B_c pi^T S) J^2 with J the damped
+    2m x 2m facet block-Jacobi sweep (blocks inverted here from S) and B_c the
+    exact RT0 inverse or the textbook two-level RT0 V-cycle with vertex-patch
+    Schwarz smoothing; f != 0."""
+    hier = hi.torus_hierarchy(8, 2)
+    o = HdgLfOracle(hier.fine, 1, 0.3, 1.0, 1.0, 0.5, 0.0)
+    tm = LfTraceMultigrid(o, hier, exact_coarse=exact)
+    n, mt = o.n_trace, o.mt
+    B = np.column_stack([tm.vcycle(e) for e in np.eye(n)])
+    S = o.S.toarray()
+    Dinv = np.zeros_like(S)
+    for e in range(n // mt):
+        sl = slice(e * mt, (e + 1) * mt)
+        Dinv[sl, sl] = np.linalg.inv(S[sl, sl])
+    I = np.eye(n)
+    J = I - tm.omega * Dinv @ S
+    if exact:
+        Bc = np.linalg.inv(tm.Sc.toarray())
+    else:
+        assert len(tm.mg.A) == 2
+        Bc = _schwarz_vcycle_by_recursion(tm.mg.meshes, [a.toarray() for a in tm.mg.A],
+                                          [p.toarray() for p in tm.mg.P], tm.mg.omega, tm.mg.nu)
+    pi = tm.pi.toarray()
+    E = np.linalg.matrix_power(J, tm.nu_post) @ (I - pi @ Bc @ pi.T @ S) @ np.linalg.matrix_power(J, tm.nu_pre)
+    ref = (I - E) @ np.linalg.inv(S)
+    assert np.abs(B - ref).max() < 1e-10 * np.abs(ref).max()
