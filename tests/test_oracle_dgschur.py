@@ -93,3 +93,29 @@ def test_preconditioner_is_linear_and_iterations_are_mesh_independent():
     x, y = rng.standard_normal((2, o.A.shape[0]))
     lhs = o.precondition(2.0 * x - 3.0 * y)
     assert np.linalg.norm(lhs - (2.0 * o.precondition(x) - 3.0 * o.precondition(y))) < 1e-12 * np.linalg.norm(lhs)
+
+
+def test_s_cycle_is_the_two_level_iteration_matrix():
+    """The Schur-complement cycle as a matrix: I - B S = C (I - P B_c P^T S) C
+    with C the Chebyshev error propagator (the smoother from x = e with b = 0;
+    its polynomial is pinned with the multigrid pins) and B_c the textbook
+    P1 V-cycle recursion on the explicit Galerkin level matrices."""
+    from oracle.p1 import chebyshev
+    o = DgApproxSchur(hi.torus_hierarchy(4, 2), 1, 0.3, 1.3, 0.8, 1.0)
+    S = o.S.toarray()
+    n = S.shape[0]
+    B = np.column_stack([o.s_cycle(e) for e in np.eye(n)])
+    a, bnd = 0.1 * o.lmax, 1.1 * o.lmax
+    C = np.column_stack([chebyshev(o.S, o.own_prec, np.zeros(n), e, o.nu, a, bnd) for e in np.eye(n)])
+    A = [m.toarray() for m in o.mg.A]
+    Pl = [m.toarray() for m in o.mg.P]
+    Bc = np.linalg.inv(A[0])
+    for l in range(1, len(A)):
+        I = np.eye(A[l].shape[0])
+        J = np.linalg.matrix_power(I - o.mg.omega * (A[l] / np.diag(A[l])[:, None]), o.mg.nu)
+        Bc = (I - J @ (I - Pl[l - 1] @ Bc @ Pl[l - 1].T @ A[l]) @ J) @ np.linalg.inv(A[l])
+    P = o.P.toarray() if sp.issparse(o.P) else np.asarray(o.P)
+    I = np.eye(n)
+    ref = (I - C @ (I - P @ Bc @ P.T @ S) @ C) @ np.linalg.inv(S)
+    assert len(A) == 2
+    assert np.abs(B - ref).max() < 1e-10 * np.abs(ref).max()
