@@ -92,21 +92,33 @@ def test_largest_batch():
             assert rel(q[:, fld, :, k], q_ref[:, fld]) < 1e-9
 
 
-@pytest.mark.parametrize("p", [1, 2, 3])
-def test_two_cell_mesh_every_degree(p):
-    """The smallest periodic mesh (one square, two cells, three facets)."""
-    from oracle.hdg import HdgOracle
-    from paper_2004_09389_amd.hdg import HdgSolver
+def _exact_cases():
+    import sys
+    import os
+    sys.path.insert(0, os.path.dirname(__file__))
+    from test_oracle_exact import CASES
+    return CASES
+
+
+@pytest.mark.parametrize("c", _exact_cases(), ids=lambda c: f"p{c['p']}-f{c['f']}-tau{c['tau']}")
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_two_cell_mesh_equals_exact_solution(c, precision):
+    """The smallest periodic mesh (one square, two cells, three facets): the
+    library's condense / solve / recover against the stage's exact solution
+    computed over Q(sqrt 2) (tests/golden/exact_torus1.txt): FP64 to 1e-10,
+    the mixed-precision path to 1e-8, every field separately."""
+    from paper_2004_09389_amd.hdg import HDG_FP64, HDG_MIXED, HdgSolver
     hier = hi.torus_hierarchy(1, 1)
-    s = HdgSolver(hier, p, 0.7, 1.0, 1.0, 0.3, 0.0, rtol=1e-12)
-    o = HdgOracle(hier.fine, p, 0.7, 1.0, 1.0, 0.3, 0.0)
-    r = hi.iid_rhs(hier.fine, p, 13)
-    q, lam, info = s.step(to_dev(r))
-    q_ref, lam_ref = o.solve(r[..., 0])
+    prec = HDG_FP64 if precision == "fp64" else HDG_MIXED
+    s = HdgSolver(hier, c["p"], float(c["dt"]), float(c["g"]), float(c["H"]), float(c["f"]), 0.0,
+                  float(c["tau"]), rtol=1e-13 if precision == "fp64" else 1e-11, precision=prec)
+    q, lam, info = s.step(to_dev(c["r"][..., None]))
     assert info[0].status == 0
-    assert rel(host(lam)[..., 0].ravel(), lam_ref) < 1e-10
+    tol = 1e-10 if precision == "fp64" else 1e-8
+    assert rel(host(lam)[..., 0].ravel(), c["lam"]) < tol
     for fld in range(3):
-        assert rel(host(q)[:, fld, :, 0], q_ref[:, fld]) < 1e-10
+        assert rel(host(q)[:, fld, :, 0], c["q"][:, fld]) < tol
+    s.close()
 
 
 def test_not_converged_and_breakdown_are_reported():

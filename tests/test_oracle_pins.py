@@ -241,13 +241,15 @@ def _mms_error(n, p, kappa_dt=0.05, f0=0.9, g=1.3, H=0.8):
     return np.sqrt(err)
 
 
-@pytest.mark.parametrize("p", [1, 2])
+@pytest.mark.parametrize("p", [1, 2, 3])
 def test_mms_convergence(p):
-    """Error decreases at least at rate p + 1/2 (accuracy section), expected
-    close to p + 1."""
-    errs = [_mms_error(n, p) for n in (4, 8, 16)]
+    """The L2 error of the manufactured solution converges at order p + 1: the
+    observed rate over n = 8, 16, 32 rises towards p + 1 and exceeds p + 0.85
+    on the last step (measured: 1.94, 2.96, 3.97 for p = 1, 2, 3); the paper's
+    accuracy section proves at least p + 1/2."""
+    errs = [_mms_error(n, p) for n in (8, 16, 32)]
     rates = [np.log2(errs[i] / errs[i + 1]) for i in range(2)]
-    assert rates[-1] > p + 0.5, (errs, rates)
+    assert rates[1] > p + 0.85 and rates[1] >= rates[0] - 0.01 and rates[1] < p + 1.2, (errs, rates)
 
 
 # ----------------------------------------------------------------- multigrid pins
