@@ -192,8 +192,9 @@ class HdgSolver:
     def __init__(self, hierarchy, degree: int, dt: float, g: float = 1.0, H: float = 1.0,
                  f0: float = 0.0, omega: float = 0.0, tau: float = 1.0, flux: int = HDG_FLUX_UPWIND,
                  **options):
-        import torch  # noqa: F401  (initialises the HIP runtime through torch)
+        import torch  # (initialises the HIP runtime through torch)
         self.lib = load_library()
+        self.device = torch.cuda.current_device()
         self.hier = hierarchy
         opt = default_options()
         for k, v in options.items():
@@ -253,13 +254,57 @@ class HdgSolver:
         import torch
         return torch.zeros((self.n_cell, 3, self.n_loc, nrhs), dtype=torch.float64, device="cuda")
 
+    # Argument checks.  The C ABI receives bare device pointers and cannot see
+    # buffer lengths, so every tensor is checked here against the context's
+    # sizes before a pointer is passed: dtype, device, contiguity and the full
+    # shape.  A mismatch raises ValueError and nothing is launched.
+    def _dev_tensor(self, t, shape, name):
+        import torch
+        if not isinstance(t, torch.Tensor):
+            raise ValueError(f"{name}: expected a torch tensor")
+        if t.dtype != torch.float64:
+            raise ValueError(f"{name}: expected float64, got {t.dtype}")
+        if not t.is_cuda:
+            raise ValueError(f"{name}: expected a CUDA tensor")
+        if getattr(self, "device", None) is not None and t.device.index != self.device:
+            raise ValueError(f"{name}: tensor is on cuda:{t.device.index}, the context on cuda:{self.device}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name}: expected a contiguous tensor")
+        if tuple(t.shape) != tuple(shape):
+            raise ValueError(f"{name}: expected shape {tuple(shape)}, got {tuple(t.shape)}")
+        return t
+
+    def _trace(self, t, name, nb=None):
+        """A trace array (n_facet, facet_dofs, nrhs); returns nrhs (taken from t unless given)."""
+        import torch
+        if nb is None:
+            if not isinstance(t, torch.Tensor) or t.dim() != 3:
+                raise ValueError(f"{name}: expected a 3-d trace tensor (n_facet, facet_dofs, nrhs)")
+            nb = int(t.shape[-1])
+        self._nb_ok(nb, name)
+        self._dev_tensor(t, (self.n_facet, self.m, nb), name)
+        return nb
+
+    def _cell(self, t, name, nb=None):
+        """A cell array (n_cell, 3, n_loc, nrhs); returns nrhs (taken from t unless given)."""
+        import torch
+        if nb is None:
+            if not isinstance(t, torch.Tensor) or t.dim() != 4:
+                raise ValueError(f"{name}: expected a 4-d cell tensor (n_cell, 3, n_loc, nrhs)")
+            nb = int(t.shape[-1])
+        self._nb_ok(nb, name)
+        self._dev_tensor(t, (self.n_cell, 3, self.n_loc, nb), name)
+        return nb
+
+    def _nb_ok(self, nb, name):
+        if not 1 <= nb <= self.options.max_rhs:
+            raise ValueError(f"{name}: nrhs = {nb} outside 1..max_rhs = {self.options.max_rhs}")
+
     @staticmethod
-    def _nrhs(t, trailing_dims):
-        if t.dtype != __import__("torch").float64 or not t.is_cuda or not t.is_contiguous():
-            raise ValueError("expected a contiguous float64 CUDA tensor")
-        if t.dim() != trailing_dims:
-            raise ValueError(f"expected a {trailing_dims}-d tensor")
-        return int(t.shape[-1])
+    def _distinct(*pairs):
+        for a, b, what in pairs:
+            if a.data_ptr() == b.data_ptr():
+                raise ValueError(f"{what} must be distinct buffers")
 
     def topology(self):
         fc = np.zeros((self.n_facet, 2), dtype=np.int32)
@@ -270,34 +315,44 @@ class HdgSolver:
 
     # ------------------------------------------------------------------ the ABI calls
     def condense(self, r_cell, out=None):
-        nb = self._nrhs(r_cell, 4)
+        nb = self._cell(r_cell, "r_cell")
         out = self.trace_zeros(nb) if out is None else out
+        self._trace(out, "out", nb)
         _check(self.lib.hdg_condense(self.ctx, nb, _ptr(r_cell), _ptr(out), _stream()))
         return out
 
     def trace_apply(self, x, precision: int = HDG_FP64, out=None):
-        nb = self._nrhs(x, 3)
+        nb = self._trace(x, "x")
         out = self.trace_zeros(nb) if out is None else out
+        self._trace(out, "out", nb)
+        self._distinct((x, out, "x and out"))
         _check(self.lib.hdg_trace_apply(self.ctx, nb, precision, _ptr(x), _ptr(out), _stream()))
         return out
 
     def mg_vcycle(self, r, precision: int = HDG_FP64, out=None):
-        nb = self._nrhs(r, 3)
+        nb = self._trace(r, "r")
         out = self.trace_zeros(nb) if out is None else out
+        self._trace(out, "out", nb)
+        self._distinct((r, out, "r and out"))
         _check(self.lib.hdg_mg_vcycle(self.ctx, nb, precision, _ptr(r), _ptr(out), _stream()))
         return out
 
     def solve(self, rhat, lam=None, allow_notconv: bool = False) -> "tuple":
-        nb = self._nrhs(rhat, 3)
+        nb = self._trace(rhat, "rhat")
         lam = self.trace_zeros(nb) if lam is None else lam
+        self._trace(lam, "lam", nb)
+        self._distinct((rhat, lam, "rhat and lam"))
         info = (HdgSolveInfo * nb)()
         allow = (HDG_OK, HDG_ENOTCONV) if allow_notconv else (HDG_OK,)
         _check(self.lib.hdg_solve(self.ctx, nb, _ptr(rhat), _ptr(lam), info, _stream()), allow)
         return lam, [SolveInfo(i.iters, i.refinements, i.fallbacks, i.status, i.rel_res) for i in info]
 
     def recover(self, r_cell, lam, out=None):
-        nb = self._nrhs(r_cell, 4)
+        nb = self._cell(r_cell, "r_cell")
+        self._trace(lam, "lam", nb)
         out = self.cell_zeros(nb) if out is None else out
+        self._cell(out, "out", nb)
+        self._distinct((r_cell, out, "r_cell and out"))
         _check(self.lib.hdg_recover(self.ctx, nb, _ptr(r_cell), _ptr(lam), _ptr(out), _stream()))
         return out
 
@@ -310,8 +365,10 @@ class HdgSolver:
     # ------------------------------------------------------------------ IMEX time stepping
     def dg_tendency(self, q, dt: float, out=None):
         """dt M^-1 (L(q) + N_c(q)): the explicit flux evaluation (hdg_dg_tendency)."""
-        nb = self._nrhs(q, 4)
+        nb = self._cell(q, "q")
         out = self.cell_zeros(nb) if out is None else out
+        self._cell(out, "out", nb)
+        self._distinct((q, out, "q and out"))
         _check(self.lib.hdg_dg_tendency(self.ctx, nb, dt, _ptr(q), _ptr(out), _stream()))
         return out
 
@@ -321,11 +378,17 @@ class HdgSolver:
         must have been set up with dt = gamma * dt and f0 = omega = 0.
         Returns the HdgImexInfo."""
         import torch
-        nb = self._nrhs(q, 4)
+        nb = self._cell(q, "q")
+        n = ctypes.c_int64()
+        _check(self.lib.hdg_imex_work_size(self.ctx, ctypes.byref(tableau), nb, ctypes.byref(n)))
         if work is None:
-            n = ctypes.c_int64()
-            _check(self.lib.hdg_imex_work_size(self.ctx, ctypes.byref(tableau), nb, ctypes.byref(n)))
             work = torch.empty(n.value, dtype=torch.float64, device="cuda")
+        if not isinstance(work, torch.Tensor) or work.dim() != 1:
+            raise ValueError("work: expected a 1-d tensor")
+        self._dev_tensor(work, (work.numel(),), "work")
+        if work.numel() < n.value:
+            raise ValueError(f"work: needs at least {n.value} doubles, got {work.numel()}")
+        self._distinct((q, work, "q and work"))
         info = HdgImexInfo()
         allow = (HDG_OK, HDG_ENOTCONV) if allow_notconv else (HDG_OK,)
         _check(self.lib.hdg_imex_run(self.ctx, ctypes.byref(tableau), dt, f, nb, steps, _ptr(q), _ptr(work),
@@ -338,21 +401,27 @@ class HdgSolver:
         _check(self.lib.hdg_dgs_setup(self.ctx, self._meshes, len(self.hier.meshes), self._parents))
 
     def dgs_apply(self, x, out=None):
-        nb = self._nrhs(x, 4)
+        nb = self._cell(x, "x")
         out = self.cell_zeros(nb) if out is None else out
+        self._cell(out, "out", nb)
+        self._distinct((x, out, "x and out"))
         _check(self.lib.hdg_dgs_apply(self.ctx, nb, _ptr(x), _ptr(out), _stream()))
         return out
 
     def dgs_precondition(self, r, out=None):
-        nb = self._nrhs(r, 4)
+        nb = self._cell(r, "r")
         out = self.cell_zeros(nb) if out is None else out
+        self._cell(out, "out", nb)
+        self._distinct((r, out, "r and out"))
         _check(self.lib.hdg_dgs_precondition(self.ctx, nb, _ptr(r), _ptr(out), _stream()))
         return out
 
     def dgs_solve(self, r_cell, out=None, allow_notconv: bool = False):
         """Solve the stage with the DG baseline; returns (q, [SolveInfo])."""
-        nb = self._nrhs(r_cell, 4)
+        nb = self._cell(r_cell, "r_cell")
         out = self.cell_zeros(nb) if out is None else out
+        self._cell(out, "out", nb)
+        self._distinct((r_cell, out, "r_cell and out"))
         info = (HdgSolveInfo * nb)()
         allow = (HDG_OK, HDG_ENOTCONV) if allow_notconv else (HDG_OK,)
         _check(self.lib.hdg_dgs_solve(self.ctx, nb, _ptr(r_cell), _ptr(out), info, _stream()), allow)
@@ -375,13 +444,14 @@ class HdgSolver:
 
     def mlp_make_data(self, e, coarse_its: int = 1):
         """Training pair (u, t) for the trace error e."""
-        nb = self._nrhs(e, 3)
+        nb = self._trace(e, "e")
         u, t = self.trace_zeros(nb), self.trace_zeros(nb)
         _check(self.lib.hdg_mlp_make_data(self.ctx, nb, _ptr(e), _ptr(u), _ptr(t), int(coarse_its), _stream()))
         return u, t
 
     def mlp_loss_grad(self, u, t):
-        nb = self._nrhs(u, 3)
+        nb = self._trace(u, "u")
+        self._trace(t, "t", nb)
         loss = ctypes.c_double()
         dW1 = np.zeros((64, 5 * self.mp), dtype=np.float32)
         dW2 = np.zeros((self.mp, 64), dtype=np.float32)
@@ -391,7 +461,7 @@ class HdgSolver:
 
     def mlp_train(self, e0, cycles: int, coarse_its: int = 1, epochs: int = 1, lr: float = 1e-3):
         """Adam training in place from the error e0; returns the loss before every step."""
-        nb = self._nrhs(e0, 3)
+        nb = self._trace(e0, "e0")
         hist = np.zeros(cycles * epochs)
         _check(self.lib.hdg_mlp_train(self.ctx, nb, _ptr(e0), int(cycles), int(coarse_its), int(epochs),
                                       float(lr), hist.ctypes.data, _stream()))
@@ -431,6 +501,9 @@ class HdgSolver:
 
 
 def device_copy(src, dst):
+    _dev_f64(src, dst)
+    if dst.numel() < src.numel() or src.data_ptr() == dst.data_ptr():
+        raise ValueError("dst must be a distinct buffer at least as long as src")
     _check(load_library().hdg_copy(_ptr(src), _ptr(dst), src.numel(), _stream()))
 
 

@@ -37,9 +37,13 @@ def test_argument_errors_are_reported():
         HdgSolver(hi.torus_hierarchy(4, 2), 2, -1.0)
     s = make(max_rhs=2)
     x = s.trace_zeros(3)
-    with pytest.raises(HdgError) as e:
-        s.trace_apply(x)                       # nrhs above max_rhs
+    with pytest.raises(ValueError) as e:
+        s.trace_apply(x)                       # nrhs above max_rhs: the binding rejects it ...
     assert "max_rhs" in str(e.value)
+    import ctypes
+    y = s.trace_zeros(3)                       # ... and so does the C ABI when called directly
+    rc = s.lib.hdg_trace_apply(s.ctx, 3, 0, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()), None)
+    assert rc == HDG_EINVAL and "max_rhs" in s.lib.hdg_last_error().decode()
     # a trace buffer that is not 16-byte aligned
     flat = torch.zeros(s.n_facet * s.m + 1, dtype=torch.float64, device="cuda")
     mis = flat[1:].view(s.n_facet, s.m, 1)
