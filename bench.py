@@ -405,42 +405,59 @@ def sphere_leg(args, weights, run_steps, level=7, p=3, dt=3600.0, nb=None, seed=
     return out
 
 
-def small_leg(args, run_steps=200):
+def small_leg(args, run_steps=200, batch=32):
     """The small workload: 8 x 8 torus (128 cells), p = 1, g = H = 1, f = 0,
     dt = 0.5 (Courant 4), iid right-hand side (seed 500), FP64 PCG with the
-    trace multigrid to 1e-10.  At 384 trace unknowns a solve is bound by
-    launch latency, so it is reported as microseconds per solve (graph replay
-    per solve), beside the oracle's rate on the same problem."""
+    trace multigrid to 1e-10.  Timed three ways: the single-launch stage solve
+    (hdg_stage_solve: Steps 1-3 in one launch, one workgroup per right-hand
+    side), the same for a batch of right-hand sides in one launch, and the
+    multi-launch path (condense, graph-replayed PCG iterations, recover) that a
+    context too large for one workgroup uses; microseconds per solve beside the
+    oracle's rate on the same problem."""
     import torch
 
     import hdg_inputs as hi
     from paper_2004_09389_amd.hdg import HDG_FP64, HDG_KRYLOV_PCG, HdgSolver
     hier = hi.torus_hierarchy(8, 4)
-    s = HdgSolver(hier, 1, 0.5, 1.0, 1.0, 0.0, 0.0, rtol=1e-10, precision=HDG_FP64, krylov=HDG_KRYLOV_PCG,
-                  use_graph=0 if args.no_graph else 1)
-    r = torch.from_numpy(hi.iid_rhs(hier.fine, 1, 500)).to("cuda")
-    lam, rhat, q = s.trace_zeros(1), s.trace_zeros(1), s.cell_zeros(1)
-
-    def step():
-        s.condense(r, out=rhat)
-        lam.zero_()
-        _, info = s.solve(rhat, lam)
-        s.recover(r, lam, out=q)
-        return info
-    for _ in range(5):
-        step()
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    infos = [step() for _ in range(run_steps)]
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t
-    s.close()
     out = {"workload": "torus8x8_p1_f0_courant4", "n_cell": hier.fine.n_cell, "n_trace_dof": 384,
-           "rtol": 1e-10, "krylov": "pcg", "steps": run_steps, "us_per_solve": round(1e6 * el / run_steps, 2),
-           "value": round(run_steps / el, 1), "unit": "solves/s",
-           "iters": float(np.mean([i.iters for inf in infos for i in inf])),
-           "rel_res_max": max(i.rel_res for inf in infos for i in inf)}
-    log(f"[bench] small: {out['us_per_solve']} us/solve, {out['iters']} iterations")
+           "rtol": 1e-10, "krylov": "pcg"}
+
+    def timed(s, nb, fn, steps):
+        for _ in range(5):
+            fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        infos = [fn() for _ in range(steps)]
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t
+        return {"nrhs": nb, "steps": steps, "us_per_solve": round(1e6 * el / (steps * nb), 2),
+                "us_per_call": round(1e6 * el / steps, 2), "value": round(steps * nb / el, 1), "unit": "solves/s",
+                "iters": float(np.mean([i.iters for inf in infos for i in inf])),
+                "rel_res_max": max(i.rel_res for inf in infos for i in inf)}
+
+    for name, nb, persistent in (("persistent", 1, 1), ("persistent_batch", batch, 1), ("multi_launch", 1, 0)):
+        s = HdgSolver(hier, 1, 0.5, 1.0, 1.0, 0.0, 0.0, rtol=1e-10, precision=HDG_FP64, krylov=HDG_KRYLOV_PCG,
+                      use_graph=0 if args.no_graph else 1, persistent=persistent, max_rhs=nb)
+        r = torch.from_numpy(hi.iid_rhs(hier.fine, 1, 500, nrhs=nb)).to("cuda")
+        lam, rhat, q = s.trace_zeros(nb), s.trace_zeros(nb), s.cell_zeros(nb)
+        if persistent:
+            assert s.sizes.persistent == 1
+
+            def step():
+                return s.stage_solve(r, lam, q)[2]
+        else:
+            def step():
+                s.condense(r, out=rhat)
+                lam.zero_()
+                _, info = s.solve(rhat, lam)
+                s.recover(r, lam, out=q)
+                return info
+        out[name] = timed(s, nb, step, run_steps if nb == 1 else max(20, run_steps // 4))
+        s.close()
+    out.update({k: out["persistent"][k] for k in ("us_per_solve", "value", "unit", "iters", "rel_res_max")})
+    log(f"[bench] small: {out['us_per_solve']} us/solve single-launch, "
+        f"{out['persistent_batch']['us_per_solve']} us/solve at {batch} per launch, "
+        f"{out['multi_launch']['us_per_solve']} us/solve multi-launch, {out['iters']} iterations")
     return out
 
 

@@ -156,6 +156,11 @@ typedef struct {
                                    (default 1) */
     double  rt_omega;           /* LF flux: damping of the additive vertex-patch smoother (default 0.5) */
     double  ir_inner_rtol;      /* HDG_MIXED_IR: relative reduction of each inner solve (default 1e-4) */
+    int32_t persistent;         /* 1 (default): when the trace system is small enough for one workgroup's
+                                   LDS (see hdg_sizes.persistent), hdg_solve and hdg_stage_solve run the
+                                   whole solve as one launch with one workgroup per right-hand side
+                                   (FP64, block-Jacobi smoother, upwind flux, restart <= 32);
+                                   0: always the multi-launch solve */
 } hdg_options;
 
 typedef struct {
@@ -173,6 +178,12 @@ typedef struct {
     int64_t device_bytes;       /* device memory held by the context */
     double  kappa;              /* c dt */
     double  lambda_max;         /* eigenvalue estimate of D^-1 S (Chebyshev smoother), else 0 */
+    int32_t persistent;         /* 1 when the context qualifies for the single-launch solve: upwind
+                                   flux, at most 8 P1 levels and the LDS footprint of one workgroup
+                                   (10 trace vectors, 3 vectors per P1 level and 12.6 KiB of Krylov
+                                   scalars) within the device's LDS per workgroup less 2 KiB
+                                   (160 KiB on gfx950): up to about 1800 trace unknowns, e.g. the
+                                   8x8 torus at p = 1..3 and the 16x16 torus at p = 1 */
 } hdg_sizes;
 
 /* ------------------------------------------------------------------ entry points */
@@ -240,6 +251,19 @@ int hdg_solve(hdg_ctx *ctx, int32_t nrhs, const double *rhat, double *lam,
  * (h, u1, u2) coefficients in q_cell (device, [n_cell][3][n_loc][nrhs]). */
 int hdg_recover(hdg_ctx *ctx, int32_t nrhs, const double *r_cell, const double *lam,
                 double *q_cell, void *stream);
+
+/* Steps 1-3 of one implicit stage (Eqs. schur_system, reconstruct_solution):
+ * condense r_cell, solve S lam = rhat from a zero initial guess to rtol, recover
+ * q_cell.  When the context qualifies (hdg_sizes.persistent, opt.persistent,
+ * FP64, block-Jacobi) the three steps run in ONE launch, one workgroup per
+ * right-hand side holding every trace and P1 vector of its solve in LDS;
+ * otherwise as hdg_condense, hdg_solve and hdg_recover.  r_cell, q_cell:
+ * (device) [n_cell][3][n_loc][nrhs]; lam: (device, output)
+ * [n_facet][facet_dofs][nrhs]; info: (host) [nrhs], may be NULL.  Returns as
+ * hdg_solve (HDG_ENOTCONV / HDG_EBREAKDOWN with lam and q_cell still written).
+ * Synchronises the stream. */
+int hdg_stage_solve(hdg_ctx *ctx, int32_t nrhs, const double *r_cell, double *lam, double *q_cell,
+                    hdg_solve_info *info, void *stream);
 
 void hdg_destroy(hdg_ctx *ctx);
 const char *hdg_last_error(void);

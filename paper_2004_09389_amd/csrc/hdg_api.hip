@@ -757,6 +757,90 @@ int solve_fgmres(hdg_ctx *c, int nb, int vc_prec, int op_prec, double inner_eta,
     }
 }
 
+// ------------------------------------------------------------------ persistent single-launch solve
+
+// Krylov method of a solve: PCG when the operator and the preconditioner are symmetric
+int krylov_kind(const hdg_ctx *c) {
+    int kry = c->opt.krylov;
+    if (kry == HDG_KRYLOV_AUTO)
+        kry = (c->symmetric && c->opt.precision == HDG_FP64 && c->opt.smoother != HDG_SMOOTH_MLP &&
+               c->opt.nu_pre == c->opt.nu_post) ? HDG_KRYLOV_PCG : HDG_KRYLOV_FGMRES;
+    return kry;
+}
+
+bool use_small(const hdg_ctx *c, int kry) {
+    return c->small_ok && c->opt.precision == HDG_FP64 && c->opt.smoother == HDG_SMOOTH_BJACOBI &&
+           (kry == HDG_KRYLOV_PCG || c->opt.restart <= hdg::SMALL_MAXR);
+}
+
+// One launch, one workgroup per right-hand side: the Krylov solve (stage: with
+// the condensation before and the recovery after it).  Fills info and returns
+// the worst status over the right-hand sides.  Synchronises the stream.
+int solve_small(hdg_ctx *c, int nb, int kry, bool stage, const double *rhat, const double *r_cell, double *lam,
+                double *q_cell, hdg_solve_info *info, hipStream_t s) {
+    hdg::SmallArgs A{};
+    A.ne = c->n_facet;
+    A.m = c->m;
+    A.nk = c->n_cell;
+    A.nb = nb;
+    A.nlev = (int)c->lev.size();
+    A.krylov = kry;
+    A.restart = c->opt.restart;
+    A.maxit = c->opt.maxit;
+    A.nu_pre = c->opt.nu_pre;
+    A.nu_post = c->opt.nu_post;
+    A.p1_nu = c->opt.p1_nu;
+    A.omega = c->opt.omega;
+    A.p1_omega = c->opt.p1_omega;
+    A.rtol = c->opt.rtol;
+    A.S = c->S64;
+    A.T = c->T64;
+    A.Dw = c->Dw64;
+    A.nbr = c->nbr;
+    A.fvert = c->facet_vert;
+    A.vf_row = c->vf_row;
+    A.vf_col = c->vf_col;
+    for (int l = 0; l < A.nlev; ++l) {
+        const hdg::P1LevelDev &L = c->lev[l];
+        A.lev[l] = hdg::P1Lev{L.n, L.w, L.col, L.val, L.diag, L.dinv, L.parents, L.crow, L.ccol, L.cw,
+                              nullptr, nullptr, nullptr};
+    }
+    A.Ainv = c->coarse_inv;
+    A.Zr = c->Zr;
+    A.Ar = c->Ar;
+    A.Wr = c->Wr;
+    A.fcell = c->d_fcell;
+    A.floc = c->d_floc;
+    A.cell_facet = c->cell_facet;
+    A.cell_rev = c->cell_rev;
+    A.r_cell = r_cell;
+    A.q_cell = q_cell;
+    A.rhat = rhat;
+    A.lam = lam;
+    A.V = c->small_V;
+    A.Z = c->small_Z;
+    A.info = c->small_info;
+    hdg::launch_solve_small(c->p, stage, A, c->small_lds, s);
+    check_launch();
+    HDG_HIP_CHECK(hipMemcpyAsync(c->small_hinfo, c->small_info, sizeof(double) * 4 * nb, hipMemcpyDeviceToHost, s));
+    HDG_HIP_CHECK(hipStreamSynchronize(s));
+    int status = HDG_OK;
+    for (int r = 0; r < nb; ++r) {
+        const double *h = c->small_hinfo + 4 * r;
+        const int st = (int)h[2];
+        if (st == HDG_EBREAKDOWN) status = HDG_EBREAKDOWN;
+        else if (st == HDG_ENOTCONV && status == HDG_OK) status = HDG_ENOTCONV;
+        if (info) {
+            info[r].iters = (int)h[0];
+            info[r].refinements = (int)h[1];
+            info[r].fallbacks = 0;
+            info[r].status = st;
+            info[r].rel_res = h[3];
+        }
+    }
+    return status;
+}
+
 // trace vectors are read and written as 16-byte pairs at nrhs = 1
 void check_aligned(const void *p, const char *what) {
     if (reinterpret_cast<uintptr_t>(p) % 16 != 0)
@@ -826,6 +910,7 @@ void setup_impl(const hdg_mesh *levels, int nlev, const int32_t *const *parents,
     HDG_REQUIRE(opt.smoother >= HDG_SMOOTH_BJACOBI && opt.smoother <= HDG_SMOOTH_CHEBYSHEV, "unknown smoother");
     HDG_REQUIRE(opt.p1_galerkin == 0 || opt.p1_galerkin == 1, "p1_galerkin must be 0 or 1");
     HDG_REQUIRE(opt.krylov >= HDG_KRYLOV_AUTO && opt.krylov <= HDG_KRYLOV_FGMRES, "unknown krylov method");
+    HDG_REQUIRE(opt.persistent == 0 || opt.persistent == 1, "persistent must be 0 or 1");
     for (int l = 0; l < nlev; ++l) validate_mesh(levels[l]);
     const hdg_mesh &fine = levels[nlev - 1];
     HDG_REQUIRE(prm->flux == HDG_FLUX_UPWIND || prm->flux == HDG_FLUX_LF, "flux must be HDG_FLUX_UPWIND or HDG_FLUX_LF");
@@ -1092,6 +1177,27 @@ void setup_impl(const hdg_mesh *levels, int nlev, const int32_t *const *parents,
     HDG_HIP_CHECK(hipHostGetDevicePointer((void **)&c->dlag, c->hlag, 0));
     for (int i = 0; i < 2; ++i) HDG_HIP_CHECK(hipEventCreateWithFlags(&c->lag_ev[i], hipEventDisableTiming));
     c->hbn2.assign(mr, 0.0);
+    c->stage_rhat = dev_alloc<double>(c, vl);
+
+    // ---- persistent single-launch solve: every trace and P1 vector of one solve in one workgroup's LDS
+    if (!lf && opt.persistent && (int)c->lev.size() <= hdg::P1_TAIL_LEVELS) {
+        std::vector<int> ln;
+        for (auto &L : c->lev) ln.push_back(L.n);
+        const size_t lds = hdg::small_lds_bytes(ne, m, ln.data(), (int)ln.size());
+        int maxlds = 0;
+        HDG_HIP_CHECK(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device));
+        // 2 KiB stay for the kernel's static LDS (level descriptors and tables)
+        const size_t limit = (size_t)std::min(maxlds, 160 * 1024) - 2048;
+        if (lds <= limit && hdg::small_prepare(c->p, lds) == hipSuccess) {
+            c->small_ok = true;
+            c->small_lds = lds;
+            const size_t v1 = (size_t)ne * m;
+            c->small_V = dev_alloc<double>(c, (size_t)mr * (hdg::SMALL_MAXR + 1) * v1);
+            c->small_Z = dev_alloc<double>(c, (size_t)mr * hdg::SMALL_MAXR * v1);
+            c->small_info = dev_alloc<double>(c, (size_t)4 * mr);
+            HDG_HIP_CHECK(hipHostMalloc((void **)&c->small_hinfo, sizeof(double) * 4 * mr, hipHostMallocDefault));
+        }
+    }
     HDG_HIP_CHECK(hipDeviceSynchronize());
     if (c->opt.smoother == HDG_SMOOTH_CHEBYSHEV) estimate_lambda_max(c);
 }
@@ -1108,6 +1214,7 @@ void destroy_impl(hdg_ctx *c) {
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->hscal) (void)hipHostFree(c->hscal);
     if (c->hlag) (void)hipHostFree(c->hlag);
+    if (c->small_hinfo) (void)hipHostFree(c->small_hinfo);
     for (int i = 0; i < 2; ++i)
         if (c->lag_ev[i]) (void)hipEventDestroy(c->lag_ev[i]);
 }
@@ -1222,6 +1329,7 @@ extern "C" int hdg_default_options(hdg_options *o) {
     o->rt_nu = 1;
     o->rt_omega = 0.5;
     o->ir_inner_rtol = 1e-4;
+    o->persistent = 1;
     return HDG_OK;
 }
 
@@ -1269,6 +1377,7 @@ extern "C" int hdg_get_sizes(const hdg_ctx *c, hdg_sizes *out) {
     out->device_bytes = c->device_bytes;
     out->kappa = c->kappa;
     out->lambda_max = c->cheb_lmax;
+    out->persistent = c->small_ok ? 1 : 0;
     return HDG_OK;
 }
 
@@ -1323,6 +1432,26 @@ extern "C" int hdg_mg_vcycle(hdg_ctx *c, int32_t nb, int32_t prec, const double 
     });
 }
 
+namespace {
+// Step 2 on the caller's stream (the argument checks are done by the callers)
+int solve_impl(hdg_ctx *c, int nb, const double *rhat, double *lam, hdg_solve_info *info, hipStream_t s) {
+    c->use_mlp_now = c->opt.smoother == HDG_SMOOTH_MLP;
+    const int kry = krylov_kind(c);
+    HDG_REQUIRE(!(kry == HDG_KRYLOV_PCG && c->use_mlp_now), "the learned smoother is nonlinear: use FGMRES");
+    HDG_REQUIRE(c->opt.precision >= HDG_FP64 && c->opt.precision <= HDG_MIXED_IR, "unknown solve precision");
+    if (kry == HDG_KRYLOV_FGMRES) HDG_REQUIRE(c->kV != nullptr, "FGMRES workspace was not allocated (krylov = PCG at setup)");
+    if (kry == HDG_KRYLOV_PCG) HDG_REQUIRE(c->opt.precision == HDG_FP64, "PCG needs the FP64 (linear) preconditioner");
+    if (use_small(c, kry)) return solve_small(c, nb, kry, false, rhat, nullptr, lam, nullptr, info, s);
+    const double *h = dots_now(c, nb, rhat, rhat, scal(c, SC_BN2), s);
+    hdg::launch_sqrt(nb, scal(c, SC_BN2), c->dbn, s);
+    for (int r = 0; r < nb; ++r) c->hbn2[r] = h[r];
+    if (kry == HDG_KRYLOV_PCG) return solve_pcg(c, nb, rhat, lam, info, s);
+    if (c->opt.precision == HDG_MIXED_IR)
+        return solve_fgmres(c, nb, HDG_MIXED, HDG_MIXED, c->opt.ir_inner_rtol, rhat, lam, info, s);
+    return solve_fgmres(c, nb, c->opt.precision, HDG_FP64, 0.0, rhat, lam, info, s);
+}
+}  // namespace
+
 extern "C" int hdg_solve(hdg_ctx *c, int32_t nb, const double *rhat, double *lam, hdg_solve_info *info,
                          void *stream) {
     if (!c) return HDG_EINVAL;
@@ -1332,26 +1461,37 @@ extern "C" int hdg_solve(hdg_ctx *c, int32_t nb, const double *rhat, double *lam
         HDG_REQUIRE(rhat && lam && rhat != lam, "rhat and lam must be distinct non-NULL buffers");
         check_aligned(rhat, "rhat");
         check_aligned(lam, "lam");
+        status = solve_impl(c, nb, rhat, lam, info, as_stream(stream));
+    });
+    if (rc != HDG_OK) return rc;
+    if (status == HDG_EBREAKDOWN) hdg::set_error("non-finite residual in the Krylov solve");
+    return status;
+}
+
+extern "C" int hdg_stage_solve(hdg_ctx *c, int32_t nb, const double *r_cell, double *lam, double *q_cell,
+                               hdg_solve_info *info, void *stream) {
+    if (!c) return HDG_EINVAL;
+    int status = HDG_OK;
+    int rc = guard([&] {
+        check_nb(c, nb);
+        HDG_REQUIRE(r_cell && lam && q_cell, "r_cell, lam and q_cell must not be NULL");
+        HDG_REQUIRE(r_cell != q_cell, "r_cell and q_cell must be distinct buffers");
+        check_aligned(lam, "lam");
         hipStream_t s = as_stream(stream);
-        const double *h = dots_now(c, nb, rhat, rhat, scal(c, SC_BN2), s);
-        hdg::launch_sqrt(nb, scal(c, SC_BN2), c->dbn, s);
-        for (int r = 0; r < nb; ++r) c->hbn2[r] = h[r];
-        c->use_mlp_now = c->opt.smoother == HDG_SMOOTH_MLP;
-        int kry = c->opt.krylov;
-        if (kry == HDG_KRYLOV_AUTO)
-            kry = (c->symmetric && c->opt.precision == HDG_FP64 && !c->use_mlp_now &&
-                   c->opt.nu_pre == c->opt.nu_post) ? HDG_KRYLOV_PCG : HDG_KRYLOV_FGMRES;
-        HDG_REQUIRE(!(kry == HDG_KRYLOV_PCG && c->use_mlp_now), "the learned smoother is nonlinear: use FGMRES");
-        HDG_REQUIRE(c->opt.precision >= HDG_FP64 && c->opt.precision <= HDG_MIXED_IR, "unknown solve precision");
-        if (kry == HDG_KRYLOV_FGMRES) HDG_REQUIRE(c->kV != nullptr, "FGMRES workspace was not allocated (krylov = PCG at setup)");
-        if (kry == HDG_KRYLOV_PCG) {
-            HDG_REQUIRE(c->opt.precision == HDG_FP64, "PCG needs the FP64 (linear) preconditioner");
-            status = solve_pcg(c, nb, rhat, lam, info, s);
-        } else if (c->opt.precision == HDG_MIXED_IR) {
-            status = solve_fgmres(c, nb, HDG_MIXED, HDG_MIXED, c->opt.ir_inner_rtol, rhat, lam, info, s);
-        } else {
-            status = solve_fgmres(c, nb, c->opt.precision, HDG_FP64, 0.0, rhat, lam, info, s);
+        const int kry = krylov_kind(c);
+        if (use_small(c, kry)) {
+            status = solve_small(c, nb, kry, true, nullptr, r_cell, lam, q_cell, info, s);
+            return;
         }
+        hdg::launch_condense(c->p, c->nu, c->n_cell, c->n_facet, nb, c->Zr, r_cell, c->loc, c->d_fcell, c->d_floc,
+                             c->stage_rhat, s);
+        check_launch();
+        HDG_HIP_CHECK(hipMemsetAsync(lam, 0, sizeof(double) * (size_t)vec_len(c) * nb, s));
+        status = solve_impl(c, nb, c->stage_rhat, lam, info, s);
+        hdg::launch_recover(c->p, c->nu, c->n_cell, nb, c->Ar, c->Wr, c->cell_facet, c->cell_rev, r_cell, lam, q_cell,
+                            s);
+        check_launch();
+        HDG_HIP_CHECK(hipStreamSynchronize(s));
     });
     if (rc != HDG_OK) return rc;
     if (status == HDG_EBREAKDOWN) hdg::set_error("non-finite residual in the Krylov solve");

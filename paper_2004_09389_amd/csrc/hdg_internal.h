@@ -263,6 +263,14 @@ struct hdg_ctx {
     hipEvent_t lag_ev[2] = {nullptr, nullptr};
     int red_blocks = 0;
 
+    // persistent single-launch solve of small systems (hdg_small.hip)
+    bool small_ok = false;                // the context qualifies (upwind flux, LDS footprint)
+    size_t small_lds = 0;                 // dynamic LDS per workgroup
+    double *small_V = nullptr, *small_Z = nullptr;   // FGMRES bases per right-hand side
+    double *small_info = nullptr;         // [max_rhs][4] device record of each solve
+    double *small_hinfo = nullptr;        // pinned host copy
+    double *stage_rhat = nullptr;         // condensed right-hand side of the multi-launch stage solve
+
     // learned smoother: weights [W1 (64 x K1P) | W2 (16 x 64)], FP32 master + Adam moments, BF16 copy
     int mlp_n1 = 0, mlp_n2 = 0, mlp_step = 0;
     int mlp_spl = 1;                      // samples per lane in the learned smoothing kernel

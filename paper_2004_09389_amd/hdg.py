@@ -45,7 +45,8 @@ class HdgOptions(ctypes.Structure):
                 ("maxit", ctypes.c_int32), ("restart", ctypes.c_int32), ("max_rhs", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("fallback_ratio", ctypes.c_double),
                 ("p1_tail_max", ctypes.c_int32), ("p1_galerkin", ctypes.c_int32),
-                ("rt_nu", ctypes.c_int32), ("rt_omega", ctypes.c_double), ("ir_inner_rtol", ctypes.c_double)]
+                ("rt_nu", ctypes.c_int32), ("rt_omega", ctypes.c_double), ("ir_inner_rtol", ctypes.c_double),
+                ("persistent", ctypes.c_int32)]
 
 
 class HdgSolveInfo(ctypes.Structure):
@@ -56,7 +57,8 @@ class HdgSolveInfo(ctypes.Structure):
 class HdgSizes(ctypes.Structure):
     _fields_ = [("n_cell", ctypes.c_int32), ("n_facet", ctypes.c_int32), ("n_vert", ctypes.c_int32),
                 ("degree", ctypes.c_int32), ("n_loc", ctypes.c_int32), ("n_levels", ctypes.c_int32),
-                ("facet_dofs", ctypes.c_int32), ("flux", ctypes.c_int32), ("device_bytes", ctypes.c_int64), ("kappa", ctypes.c_double), ("lambda_max", ctypes.c_double)]
+                ("facet_dofs", ctypes.c_int32), ("flux", ctypes.c_int32), ("device_bytes", ctypes.c_int64), ("kappa", ctypes.c_double), ("lambda_max", ctypes.c_double),
+                ("persistent", ctypes.c_int32)]
 
 
 class HdgTuning(ctypes.Structure):
@@ -91,6 +93,7 @@ _SIGS = {
     "hdg_mg_vcycle": (_I, [_P, _I, _I, _P, _P, _P]),
     "hdg_solve": (_I, [_P, _I, _P, _P, ctypes.POINTER(HdgSolveInfo), _P]),
     "hdg_recover": (_I, [_P, _I, _P, _P, _P, _P]),
+    "hdg_stage_solve": (_I, [_P, _I, _P, _P, _P, ctypes.POINTER(HdgSolveInfo), _P]),
     "hdg_destroy": (None, [_P]),
     "hdg_last_error": (ctypes.c_char_p, []),
     "hdg_set_timing": (_I, [_P, _I]),
@@ -361,6 +364,20 @@ class HdgSolver:
         rhat = self.condense(r_cell)
         lam, info = self.solve(rhat)
         return self.recover(r_cell, lam), lam, info
+
+    def stage_solve(self, r_cell, lam=None, q=None, allow_notconv: bool = False):
+        """Steps 1-3 in one call (hdg_stage_solve: one launch when the context is
+        small enough, see sizes.persistent).  Returns (q, lam, info)."""
+        nb = self._cell(r_cell, "r_cell")
+        lam = self.trace_zeros(nb) if lam is None else lam
+        q = self.cell_zeros(nb) if q is None else q
+        self._trace(lam, "lam", nb)
+        self._cell(q, "q", nb)
+        self._distinct((r_cell, q, "r_cell and q"))
+        info = (HdgSolveInfo * nb)()
+        allow = (HDG_OK, HDG_ENOTCONV) if allow_notconv else (HDG_OK,)
+        _check(self.lib.hdg_stage_solve(self.ctx, nb, _ptr(r_cell), _ptr(lam), _ptr(q), info, _stream()), allow)
+        return q, lam, [SolveInfo(i.iters, i.refinements, i.fallbacks, i.status, i.rel_res) for i in info]
 
     # ------------------------------------------------------------------ IMEX time stepping
     def dg_tendency(self, q, dt: float, out=None):

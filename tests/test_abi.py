@@ -52,9 +52,10 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(hdg.HdgMesh) == 4 * 3 + 4 + 8 + 3 * 8
     assert ctypes.sizeof(hdg.HdgParams) == 8 + 6 * 8 + 8
     assert ctypes.sizeof(hdg.HdgSolveInfo) == 4 * 4 + 8
-    assert ctypes.sizeof(hdg.HdgOptions) == 4 * 6 + 8 + 4 + 4 + 8 + 8 + 4 * 4 + 8 + 4 + 4 + 4 + 4 + 8 + 8
+    # ... + ir_inner_rtol (8) + persistent (4, padded to 8)
+    assert ctypes.sizeof(hdg.HdgOptions) == 4 * 6 + 8 + 4 + 4 + 8 + 8 + 4 * 4 + 8 + 4 + 4 + 4 + 4 + 8 + 8 + 8
     assert ctypes.sizeof(hdg.HdgTuning) == 8
-    assert ctypes.sizeof(hdg.HdgSizes) == 8 * 4 + 8 + 2 * 8
+    assert ctypes.sizeof(hdg.HdgSizes) == 8 * 4 + 8 + 2 * 8 + 8
 
 
 def test_struct_offsets_match_c_compiler(tmp_path):

@@ -105,7 +105,7 @@ def _exact_cases():
 
 
 @pytest.mark.parametrize("c", _exact_cases(), ids=lambda c: f"p{c['p']}-f{c['f']}-tau{c['tau']}")
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("precision", ["fp64", "fp64-multi-launch", "mixed"])
 def test_two_cell_mesh_equals_exact_solution(c, precision):
     """The smallest periodic mesh (one square, two cells, three facets): the
     library's condense / solve / recover against the stage's exact solution
@@ -113,12 +113,13 @@ def test_two_cell_mesh_equals_exact_solution(c, precision):
     the mixed-precision path to 1e-8, every field separately."""
     from paper_2004_09389_amd.hdg import HDG_FP64, HDG_MIXED, HdgSolver
     hier = hi.torus_hierarchy(1, 1)
-    prec = HDG_FP64 if precision == "fp64" else HDG_MIXED
+    prec = HDG_MIXED if precision == "mixed" else HDG_FP64
     s = HdgSolver(hier, c["p"], float(c["dt"]), float(c["g"]), float(c["H"]), float(c["f"]), 0.0,
-                  float(c["tau"]), rtol=1e-13 if precision == "fp64" else 1e-11, precision=prec)
+                  float(c["tau"]), rtol=1e-11 if precision == "mixed" else 1e-13, precision=prec,
+                  persistent=0 if precision == "fp64-multi-launch" else 1)
     q, lam, info = s.step(to_dev(c["r"][..., None]))
     assert info[0].status == 0
-    tol = 1e-10 if precision == "fp64" else 1e-8
+    tol = 1e-8 if precision == "mixed" else 1e-10
     assert rel(host(lam)[..., 0].ravel(), c["lam"]) < tol
     for fld in range(3):
         assert rel(host(q)[:, fld, :, 0], c["q"][:, fld]) < tol
