@@ -423,13 +423,16 @@ def small_leg(args, run_steps=200, batch=32):
            "rtol": 1e-10, "krylov": "pcg"}
 
     def timed(s, nb, fn, steps):
+        import gc
         for _ in range(5):
             fn()
         torch.cuda.synchronize()
+        gc.disable()   # a collection inside the timed loop costs tens of milliseconds
         t = time.perf_counter()
         infos = [fn() for _ in range(steps)]
         torch.cuda.synchronize()
         el = time.perf_counter() - t
+        gc.enable()
         return {"nrhs": nb, "steps": steps, "us_per_solve": round(1e6 * el / (steps * nb), 2),
                 "us_per_call": round(1e6 * el / steps, 2), "value": round(steps * nb / el, 1), "unit": "solves/s",
                 "iters": float(np.mean([i.iters for inf in infos for i in inf])),

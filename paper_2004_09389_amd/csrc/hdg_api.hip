@@ -784,6 +784,8 @@ int solve_small(hdg_ctx *c, int nb, int kry, bool stage, const double *rhat, con
     A.nk = c->n_cell;
     A.nb = nb;
     A.nlev = (int)c->lev.size();
+    A.stage_ops = c->small_stage_ops ? 1 : 0;
+    A.p1B = c->small_p1B;
     A.krylov = kry;
     A.restart = c->opt.restart;
     A.maxit = c->opt.maxit;
@@ -822,7 +824,6 @@ int solve_small(hdg_ctx *c, int nb, int kry, bool stage, const double *rhat, con
     A.info = c->small_info;
     hdg::launch_solve_small(c->p, stage, A, c->small_lds, s);
     check_launch();
-    HDG_HIP_CHECK(hipMemcpyAsync(c->small_hinfo, c->small_info, sizeof(double) * 4 * nb, hipMemcpyDeviceToHost, s));
     HDG_HIP_CHECK(hipStreamSynchronize(s));
     int status = HDG_OK;
     for (int r = 0; r < nb; ++r) {
@@ -1098,11 +1099,13 @@ void setup_impl(const hdg_mesh *levels, int nlev, const int32_t *const *parents,
             galerkin[l - 1] = hdg::galerkin_coarsen(galerkin[l], parents[l], levels[l - 1].n_vert);
         }
     }
+    std::vector<double> p1B;   // the P1 V-cycle as a matrix, for the persistent solve of small hierarchies
     if (!c->lev.empty()) {
         std::vector<hdg::P1Host> ops(c->lev.size());
         for (int l = 0; l < (int)c->lev.size(); ++l)
             ops[l] = opt.p1_galerkin ? galerkin[l] : hdg::assemble_p1(levels[l], c->kappa);
         hdg::build_p1_levels(c, levels, parents, ops, c->lev, &c->coarse_inv);
+        if (opt.persistent && nv <= hdg::SMALL_P1_DENSE) p1B = hdg::p1_vcycle_matrix(ops, parents, opt.p1_nu, opt.p1_omega);
     }
 
     // ---- tail of the P1 hierarchy (levels small enough for one workgroup)
@@ -1181,21 +1184,29 @@ void setup_impl(const hdg_mesh *levels, int nlev, const int32_t *const *parents,
 
     // ---- persistent single-launch solve: every trace and P1 vector of one solve in one workgroup's LDS
     if (!lf && opt.persistent && (int)c->lev.size() <= hdg::P1_TAIL_LEVELS) {
-        std::vector<int> ln;
-        for (auto &L : c->lev) ln.push_back(L.n);
-        const size_t lds = hdg::small_lds_bytes(ne, m, ln.data(), (int)ln.size());
+        std::vector<hdg::P1Lev> lv;
+        for (auto &L : c->lev) lv.push_back(hdg::P1Lev{L.n, L.w, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                                        nullptr, nullptr, nullptr, nullptr, nullptr});
         int maxlds = 0;
         HDG_HIP_CHECK(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device));
         // 2 KiB stay for the kernel's static LDS (level descriptors and tables)
         const size_t limit = (size_t)std::min(maxlds, 160 * 1024) - 2048;
+        const int nB = p1B.empty() ? 0 : nv;
+        const size_t with_ops = hdg::small_lds_bytes(ne, m, lv.data(), (int)lv.size(), true, nB);
+        const size_t lds =
+            with_ops <= limit ? with_ops : hdg::small_lds_bytes(ne, m, lv.data(), (int)lv.size(), false, nB);
         if (lds <= limit && hdg::small_prepare(c->p, lds) == hipSuccess) {
             c->small_ok = true;
+            c->small_stage_ops = with_ops <= limit;
             c->small_lds = lds;
+            if (nB) c->small_p1B = dev_upload(c, p1B);
             const size_t v1 = (size_t)ne * m;
             c->small_V = dev_alloc<double>(c, (size_t)mr * (hdg::SMALL_MAXR + 1) * v1);
             c->small_Z = dev_alloc<double>(c, (size_t)mr * hdg::SMALL_MAXR * v1);
-            c->small_info = dev_alloc<double>(c, (size_t)4 * mr);
-            HDG_HIP_CHECK(hipHostMalloc((void **)&c->small_hinfo, sizeof(double) * 4 * mr, hipHostMallocDefault));
+            // the kernel writes each solve's record straight into host-mapped memory
+            HDG_HIP_CHECK(hipHostMalloc((void **)&c->small_hinfo, sizeof(double) * 4 * mr,
+                                        hipHostMallocMapped | hipHostMallocCoherent));
+            HDG_HIP_CHECK(hipHostGetDevicePointer((void **)&c->small_info, c->small_hinfo, 0));
         }
     }
     HDG_HIP_CHECK(hipDeviceSynchronize());

@@ -414,3 +414,85 @@ bool spd_inverse(std::vector<double> &a, int n) {
 }
 
 }  // namespace hdg
+
+// ------------------------------------------------------------------ the P1 V-cycle as a matrix
+//
+// One P1 multigrid V-cycle (damped Jacobi with nu sweeps before and after,
+// linear-interpolation transfers from the parent pairs, exact solve on level
+// 0) is a fixed linear map b -> x on the finest level.  For a small hierarchy
+// its matrix is formed once, column by column, and the persistent solve
+// applies it as one dense product.
+namespace {
+struct P1Cycle {
+    const std::vector<hdg::P1Host> &ops;
+    const int32_t *const *parents;
+    const std::vector<double> &ainv;
+    int nu;
+    double w;
+
+    std::vector<double> ax(int l, const std::vector<double> &x) const {
+        const hdg::P1Host &A = ops[l];
+        std::vector<double> y(A.n);
+        for (int v = 0; v < A.n; ++v) {
+            double s = A.diag[v] * x[v];
+            for (int k = A.rowptr[v]; k < A.rowptr[v + 1]; ++k) s += A.val[k] * x[A.col[k]];
+            y[v] = s;
+        }
+        return y;
+    }
+    std::vector<double> cycle(int l, const std::vector<double> &b) const {
+        const hdg::P1Host &A = ops[l];
+        const int n = A.n;
+        std::vector<double> x(n, 0.0);
+        if (l == 0) {
+            for (int i = 0; i < n; ++i) {
+                double s = 0.0;
+                for (int j = 0; j < n; ++j) s += ainv[(size_t)i * n + j] * b[j];
+                x[i] = s;
+            }
+            return x;
+        }
+        for (int v = 0; v < n; ++v) x[v] = w * b[v] / A.diag[v];
+        for (int k = 1; k < nu; ++k) {
+            const std::vector<double> y = ax(l, x);
+            for (int v = 0; v < n; ++v) x[v] += w * (b[v] - y[v]) / A.diag[v];
+        }
+        std::vector<double> r = ax(l, x);
+        for (int v = 0; v < n; ++v) r[v] = b[v] - r[v];
+        const int nc = ops[l - 1].n;
+        const int32_t *par = parents[l];
+        std::vector<double> bc(nc, 0.0);
+        for (int v = 0; v < n; ++v)
+            for (int k = 0; k < 2; ++k) bc[par[2 * v + k]] += 0.5 * r[v];
+        const std::vector<double> xc = cycle(l - 1, bc);
+        for (int v = 0; v < n; ++v) x[v] += 0.5 * (xc[par[2 * v]] + xc[par[2 * v + 1]]);
+        for (int k = 0; k < nu; ++k) {
+            const std::vector<double> y = ax(l, x);
+            for (int v = 0; v < n; ++v) x[v] += w * (b[v] - y[v]) / A.diag[v];
+        }
+        return x;
+    }
+};
+}  // namespace
+
+std::vector<double> hdg::p1_vcycle_matrix(const std::vector<hdg::P1Host> &ops, const int32_t *const *parents, int nu,
+                                          double omega) {
+    const int n0 = ops[0].n;
+    std::vector<double> ainv((size_t)n0 * n0, 0.0);
+    for (int v = 0; v < n0; ++v) {
+        ainv[(size_t)v * n0 + v] = ops[0].diag[v];
+        for (int k = ops[0].rowptr[v]; k < ops[0].rowptr[v + 1]; ++k) ainv[(size_t)v * n0 + ops[0].col[k]] += ops[0].val[k];
+    }
+    if (!hdg::spd_inverse(ainv, n0)) throw hdg::Error{HDG_EINVAL, "coarsest P1 operator is singular"};
+    const P1Cycle cyc{ops, parents, ainv, nu, omega};
+    const int top = (int)ops.size() - 1, n = ops[top].n;
+    std::vector<double> B((size_t)n * n);
+    std::vector<double> e(n, 0.0);
+    for (int j = 0; j < n; ++j) {
+        e[j] = 1.0;
+        const std::vector<double> col = cyc.cycle(top, e);
+        e[j] = 0.0;
+        for (int i = 0; i < n; ++i) B[(size_t)i * n + j] = col[i];
+    }
+    return B;
+}

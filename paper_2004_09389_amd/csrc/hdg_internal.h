@@ -76,6 +76,11 @@ P1Host assemble_p1(const hdg_mesh &mesh, double kappa);
 P1Host galerkin_from_rows(int ne, int m, int nv, const std::vector<double> &rows, const std::vector<int32_t> &nbr,
                           const std::vector<int32_t> &facet_vert);
 P1Host galerkin_coarsen(const P1Host &fine, const int32_t *parents, int nc);
+// matrix [n][n] (row-major, n the finest level's size) of one P1 multigrid V-cycle over the
+// levels ops (coarse to fine) with damped Jacobi (nu sweeps, damping omega) and the parent-pair
+// transfers: the linear map the V-cycle applies to the finest level's right-hand side
+std::vector<double> p1_vcycle_matrix(const std::vector<P1Host> &ops, const int32_t *const *parents, int nu,
+                                     double omega);
 // in-place inverse of a dense SPD matrix [n][n]; returns false when not positive definite
 bool spd_inverse(std::vector<double> &a, int n);
 // in-place inverse of a dense matrix [n][n] (Gauss-Jordan, partial pivoting); false when singular
@@ -265,10 +270,12 @@ struct hdg_ctx {
 
     // persistent single-launch solve of small systems (hdg_small.hip)
     bool small_ok = false;                // the context qualifies (upwind flux, LDS footprint)
+    bool small_stage_ops = false;         // ... and its operators fit in LDS as well
+    double *small_p1B = nullptr;          // the P1 V-cycle as a dense matrix (small hierarchies), or null
     size_t small_lds = 0;                 // dynamic LDS per workgroup
     double *small_V = nullptr, *small_Z = nullptr;   // FGMRES bases per right-hand side
-    double *small_info = nullptr;         // [max_rhs][4] device record of each solve
-    double *small_hinfo = nullptr;        // pinned host copy
+    double *small_info = nullptr;         // [max_rhs][4] record of each solve: device view of small_hinfo
+    double *small_hinfo = nullptr;        // host-mapped memory the kernel writes
     double *stage_rhat = nullptr;         // condensed right-hand side of the multi-launch stage solve
 
     // learned smoother: weights [W1 (64 x K1P) | W2 (16 x 64)], FP32 master + Adam moments, BF16 copy

@@ -188,16 +188,19 @@ void launch_gmres_solve(int nb, int k, int restart, const double *gm, double *y,
 void launch_sqrt(int nb, const double *in, double *out, hipStream_t s);
 
 // persistent single-workgroup solve of small trace systems (hdg_small.hip)
-constexpr int SMALL_THREADS = 512;    // threads per workgroup (one workgroup per right-hand side)
+constexpr int SMALL_THREADS = 256;    // threads per workgroup (one workgroup per right-hand side)
 constexpr int SMALL_MAXR = 32;        // largest FGMRES restart length of the persistent solve
+constexpr int SMALL_P1_DENSE = 64;    // finest P1 levels up to this size apply the V-cycle as its matrix
 struct SmallArgs {
     int ne, m, nk, nb, nlev;
+    int stage_ops;                      // copy the operators below into LDS at the start
     int krylov, restart, maxit, nu_pre, nu_post, p1_nu;
     double omega, p1_omega, rtol;
     const double *S, *T, *Dw;           // FP64 facet rows (16-byte groups)
     const int *nbr, *fvert, *vf_row, *vf_col;
     P1Lev lev[P1_TAIL_LEVELS];          // P1 levels, 0 coarsest (work vectors unused: LDS)
     const double *Ainv;                 // dense inverse of level 0
+    const double *p1B;                  // the whole P1 V-cycle as a matrix [n][n] (finest level), or null
     // Steps 1 and 3 inside the launch (stage solve)
     const double *Zr, *Ar, *Wr;
     const int *fcell, *floc, *cell_facet;
@@ -210,8 +213,9 @@ struct SmallArgs {
     double *V, *Z;                      // FGMRES bases [nb][SMALL_MAXR + 1][n_facet m], [nb][SMALL_MAXR][...]
     double *info;                       // [nb][4]: iterations, restarts, status, final relative residual
 };
-// dynamic LDS of one workgroup for a mesh with ne facets, m unknowns per facet and the P1 level sizes
-size_t small_lds_bytes(int ne, int m, const int *level_n, int nlev);
+// dynamic LDS of one workgroup for a mesh with ne facets, m unknowns per facet and the P1 levels
+// (sizes and ELL widths), with or without the staged copies of the operators
+size_t small_lds_bytes(int ne, int m, const P1Lev *lev, int nlev, bool stage_ops, int nB);
 void launch_solve_small(int p, bool stage, const SmallArgs &A, size_t lds, hipStream_t s);
 // opt the kernels of degree p into lds bytes of dynamic LDS
 hipError_t small_prepare(int p, size_t lds);

@@ -5,20 +5,23 @@
 // Below a few thousand trace unknowns every kernel of the multi-launch solve
 // is a few waves and a solve is a chain of ~10 dependent launches per Krylov
 // iteration, so its time is launch latency.  Here the trace vectors of the
-// Krylov method and the V-cycle and the vectors of every P1 level live in LDS;
-// the operator rows (facet blocks of S, omega D^-1 S_j, omega D^-1), the P1
-// level matrices and the dense coarsest inverse are read from global memory,
-// where they stay cached after the first iteration.  A workgroup of 512
-// threads owns the facets (vertices, cells) thread-cyclically, and every phase
-// whose output is read at other items ends with a workgroup barrier.
+// Krylov method and the V-cycle and the vectors of every P1 level live in LDS,
+// and so do, when they fit, the operators themselves: the facet rows of S,
+// omega D^-1 S_j and omega D^-1, the neighbour and vertex tables, the P1 level
+// matrices and the dense coarsest inverse (otherwise they are read from global
+// memory, where they stay cached after the first iteration).  A workgroup of
+// 256 threads owns the facets (vertices, cells) thread-cyclically, and every
+// phase whose output is read at other items ends with a workgroup barrier.
 //
 // The arithmetic is the multi-launch path's: PCG (symmetric case) or flexible
 // GMRES with one classical Gram-Schmidt pass, both stopping on the FP64 true
 // relative residual; the non-nested V-cycle of Alg. twolevel_vcycle with
-// damped facet block-Jacobi sweeps, restriction pi^T, one P1 multigrid V-cycle
-// (damped Jacobi, linear-interpolation transfers, dense coarsest inverse) and
-// prolongation pi fused into the first post-sweep.  Only the order of the
-// reduction sums differs (one workgroup instead of block partials).
+// damped facet block-Jacobi sweeps (the first one from zero fused with
+// omega D^-1 r), restriction pi^T, one P1 multigrid V-cycle (damped Jacobi,
+// its first two sweeps fused, linear-interpolation transfers, dense coarsest
+// inverse) and prolongation pi fused into the first post-sweep.  Only the
+// order of the reduction sums differs (one workgroup instead of block
+// partials).
 #include "hdg_device.h"
 #include "hdg_kernels.h"
 
@@ -44,8 +47,8 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// Block-wide sum of one partial value per thread, slot i of the reduction
-// area; every thread receives the total (fixed summation order).
+// Block-wide sum of one partial value per thread; every thread receives the
+// total (fixed summation order, so every thread holds the same bits).
 __device__ __forceinline__ double block_sum(double v, double *red) {
     const double s = wave_sum(v);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
@@ -62,23 +65,61 @@ __device__ __forceinline__ void ld2(const double *p, double (&o)[2]) {
     o[1] = v.y;
 }
 
+// Operator loads.  When the operators are staged in LDS (OL) their addresses
+// are still generic pointers (published through a shared table), which would
+// compile to flat instructions; the loads below cast them to the local address
+// space, so that they compile to LDS instructions.
+typedef __attribute__((address_space(3))) const double lds_double;
+typedef __attribute__((address_space(3))) const int lds_int;
+typedef __attribute__((address_space(3))) const dbl2_t lds_double2;
+
+template <bool OL>
+__device__ __forceinline__ void opr2(const double *p, double (&o)[2]) {
+    if constexpr (OL) {
+        const dbl2_t v = *(const lds_double2 *)p;
+        o[0] = v.x;
+        o[1] = v.y;
+    } else {
+        ld2(p, o);
+    }
+}
+template <bool OL>
+__device__ __forceinline__ int opri(const int *p) {
+    if constexpr (OL) return *(const lds_int *)p;
+    else return *p;
+}
+template <bool OL>
+__device__ __forceinline__ double oprd(const double *p) {
+    if constexpr (OL) return *(const lds_double *)p;
+    else return *p;
+}
+
+// The operators as the phases read them: global memory, or the LDS copies.
+struct Ops {
+    const double *S, *T, *Dw, *Ainv, *B;
+    const int *nbr, *fvert, *vf_row, *vf_col;
+    P1Lev lev[P1_TAIL_LEVELS];
+};
+
 // y = S x  (b == nullptr) or y = b - S x over this thread's facets; x in LDS
-template <int M>
-__device__ void s_apply(const SmallArgs &A, const double *x, const double *b, double *y) {
+template <int M, bool OL>
+__device__ void s_apply(int ne, const Ops &O, const double *x, const double *b, double *y) {
     constexpr int C = 5 * M * M, G = padded(C, 2) / 2;
-    const size_t NE = (size_t)A.ne;
-    for (int e = threadIdx.x; e < A.ne; e += SMALL_THREADS) {
+    const size_t NE = (size_t)ne;
+    const double *S = O.S;
+    const int *nbr = O.nbr;
+    for (int e = threadIdx.x; e < ne; e += SMALL_THREADS) {
         int id[5];
         id[0] = e;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) id[j + 1] = A.nbr[j * NE + e];
+        for (int j = 0; j < 4; ++j) id[j + 1] = opri<OL>(nbr + j * NE + e);
         double acc[M];
 #pragma unroll
         for (int a = 0; a < M; ++a) acc[a] = 0.0;
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             double w[2];
-            ld2(A.S + ((size_t)g * NE + e) * 2, w);
+            opr2<OL>(S + ((size_t)g * NE + e) * 2, w);
 #pragma unroll
             for (int v = 0; v < 2; ++v) {
                 const int c = 2 * g + v;
@@ -93,51 +134,138 @@ __device__ void s_apply(const SmallArgs &A, const double *x, const double *b, do
     }
 }
 
-// z0 = omega D^-1 r
-template <int M>
-__device__ void s_jacobi0(const SmallArgs &A, const double *r, double *z0) {
-    constexpr int C = M * M, G = padded(C, 2) / 2;
-    const size_t NE = (size_t)A.ne;
-    for (int e = threadIdx.x; e < A.ne; e += SMALL_THREADS) {
-        double rv[M], acc[M];
-#pragma unroll
-        for (int k = 0; k < M; ++k) {
-            rv[k] = r[e * M + k];
-            acc[k] = 0.0;
-        }
-#pragma unroll
-        for (int g = 0; g < G; ++g) {
-            double w[2];
-            ld2(A.Dw + ((size_t)g * NE + e) * 2, w);
-#pragma unroll
-            for (int v = 0; v < 2; ++v) {
-                const int c = 2 * g + v;
-                if (c < C) acc[c / M] += w[v] * rv[c % M];
-            }
-        }
-#pragma unroll
-        for (int a = 0; a < M; ++a) z0[e * M + a] = acc[a];
-    }
-}
-
-// damped block-Jacobi sweep y = (1 - omega) x' + z0 - sum_j T_j x'_j, x' = x + pi qc
-template <int M>
-__device__ void s_sweep(const SmallArgs &A, const double *x, const double *z0, const double *qc, double *y) {
-    constexpr int P = M - 1, C = 4 * M * M, G = padded(C, 2) / 2;
-    const size_t NE = (size_t)A.ne;
-    const double a0 = 1.0 - A.omega;
-    for (int e = threadIdx.x; e < A.ne; e += SMALL_THREADS) {
+// PCG direction and operator in one phase: pn = z + beta po at this thread's
+// facets and w = S pn, pn at the patch facets evaluated in place (the same
+// expression, so the same bits); returns this thread's part of pn . w
+template <int M, bool OL>
+__device__ double s_apply_dir(int ne, const Ops &O, const double *z, double beta, const double *po, double *pn,
+                              double *w) {
+    constexpr int C = 5 * M * M, G = padded(C, 2) / 2;
+    const size_t NE = (size_t)ne;
+    const double *S = O.S;
+    const int *nbr = O.nbr;
+    double part = 0.0;
+    for (int e = threadIdx.x; e < ne; e += SMALL_THREADS) {
         int id[5];
         id[0] = e;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) id[j + 1] = A.nbr[j * NE + e];
+        for (int j = 0; j < 4; ++j) id[j + 1] = opri<OL>(nbr + j * NE + e);
+        double xv[5][M];
+#pragma unroll
+        for (int j = 0; j < 5; ++j)
+#pragma unroll
+            for (int k = 0; k < M; ++k) xv[j][k] = z[id[j] * M + k] + beta * po[id[j] * M + k];
+        double acc[M];
+#pragma unroll
+        for (int a = 0; a < M; ++a) acc[a] = 0.0;
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            double wv[2];
+            opr2<OL>(S + ((size_t)g * NE + e) * 2, wv);
+#pragma unroll
+            for (int v = 0; v < 2; ++v) {
+                const int c = 2 * g + v;
+                if (c < C) {
+                    const int j = c / (M * M), a = (c / M) % M, k = c % M;
+                    acc[a] += wv[v] * xv[j][k];
+                }
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < M; ++a) {
+            pn[e * M + a] = xv[0][a];
+            w[e * M + a] = acc[a];
+            part += xv[0][a] * acc[a];
+        }
+    }
+    return part;
+}
+
+// omega D_f^-1 r_f at facet f (the multi-launch first sweep's arithmetic)
+template <int M, bool OL>
+__device__ __forceinline__ void jacobi_at(const Ops &O, size_t NE, int f, const double *r, double (&z)[M]) {
+    constexpr int C = M * M, G = padded(C, 2) / 2;
+    const double *Dw = O.Dw;
+    double rv[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        rv[k] = r[f * M + k];
+        z[k] = 0.0;
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        double w[2];
+        opr2<OL>(Dw + ((size_t)g * NE + f) * 2, w);
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+            const int c = 2 * g + v;
+            if (c < C) z[c / M] += w[v] * rv[c % M];
+        }
+    }
+}
+
+// z0 = omega D^-1 r at this thread's facets and, with y != nullptr, the first
+// damped block-Jacobi sweep from zero y = (1 - omega) z0 + z0 - sum_j T_j z0_j
+// (z0 at the patch facets computed in place)
+template <int M, bool OL>
+__device__ void s_first_sweep(int ne, const Ops &O, double omega, const double *r, double *z0, double *y) {
+    constexpr int C = 4 * M * M, G = padded(C, 2) / 2;
+    const size_t NE = (size_t)ne;
+    const double *T = O.T;
+    const int *nbr = O.nbr;
+    const SweepCoef cf{1.0 - omega, 1.0, 1.0, 0.0, nullptr, nullptr};
+    for (int e = threadIdx.x; e < ne; e += SMALL_THREADS) {
+        double zv[5][M];
+        jacobi_at<M, OL>(O, NE, e, r, zv[0]);
+#pragma unroll
+        for (int a = 0; a < M; ++a) z0[e * M + a] = zv[0][a];
+        if (!y) continue;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) jacobi_at<M, OL>(O, NE, opri<OL>(nbr + j * NE + e), r, zv[j + 1]);
+        double acc[M];
+#pragma unroll
+        for (int a = 0; a < M; ++a) acc[a] = 0.0;
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            double w[2];
+            opr2<OL>(T + ((size_t)g * NE + e) * 2, w);
+#pragma unroll
+            for (int v = 0; v < 2; ++v) {
+                const int c = 2 * g + v;
+                if (c < C) {
+                    const int j = c / (M * M), a = (c / M) % M, k = c % M;
+                    acc[a] += w[v] * zv[j + 1][k];
+                }
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < M; ++a) y[e * M + a] = sweep_combine(cf, zv[0][a], zv[0][a], acc[a]);
+    }
+}
+
+// damped block-Jacobi sweep y = (1 - omega) x' + z0 - sum_j T_j x'_j, x' = x + pi qc;
+// returns this thread's part of d . y when d is given
+template <int M, bool OL>
+__device__ double s_sweep(int ne, const Ops &O, double omega, const double *x, const double *z0, const double *qc,
+                          double *y, const double *d = nullptr) {
+    double part = 0.0;
+    const double *T = O.T;
+    const int *nbr = O.nbr, *fvert = O.fvert;
+    constexpr int P = M - 1, C = 4 * M * M, G = padded(C, 2) / 2;
+    const size_t NE = (size_t)ne;
+    const SweepCoef cf{1.0 - omega, 1.0, 1.0, 0.0, nullptr, nullptr};
+    for (int e = threadIdx.x; e < ne; e += SMALL_THREADS) {
+        int id[5];
+        id[0] = e;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) id[j + 1] = opri<OL>(nbr + j * NE + e);
         double xv[5][M];
 #pragma unroll
         for (int j = 0; j < 5; ++j) {
 #pragma unroll
             for (int k = 0; k < M; ++k) xv[j][k] = x[id[j] * M + k];
             if (qc) {
-                const double q0 = qc[A.fvert[2 * id[j]]], q1 = qc[A.fvert[2 * id[j] + 1]];
+                const double q0 = qc[opri<OL>(fvert + 2 * id[j])], q1 = qc[opri<OL>(fvert + 2 * id[j] + 1)];
 #pragma unroll
                 for (int k = 0; k < M; ++k) xv[j][k] += p1_node<P>(k, q0, q1);
             }
@@ -148,7 +276,7 @@ __device__ void s_sweep(const SmallArgs &A, const double *x, const double *z0, c
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             double w[2];
-            ld2(A.T + ((size_t)g * NE + e) * 2, w);
+            opr2<OL>(T + ((size_t)g * NE + e) * 2, w);
 #pragma unroll
             for (int v = 0; v < 2; ++v) {
                 const int c = 2 * g + v;
@@ -158,54 +286,98 @@ __device__ void s_sweep(const SmallArgs &A, const double *x, const double *z0, c
                 }
             }
         }
-        const SweepCoef cf{a0, 1.0, 1.0, 0.0, nullptr, nullptr};
 #pragma unroll
-        for (int a = 0; a < M; ++a) y[e * M + a] = sweep_combine(cf, xv[0][a], z0[e * M + a], acc[a]);
+        for (int a = 0; a < M; ++a) {
+            const double v = sweep_combine(cf, xv[0][a], z0[e * M + a], acc[a]);
+            y[e * M + a] = v;
+            if (d) part += d[e * M + a] * v;
+        }
     }
+    return part;
 }
 
 // pi^T: rc[v] = sum over facet ends at v of sum_k w_end(k) res[e][k]
-template <int M>
-__device__ void s_restrict_trace(const SmallArgs &A, const P1Lev *lev, const double *res, double *rc) {
+template <int M, bool OL>
+__device__ void s_restrict_trace(int nv, const Ops &O, const double *res, double *rc) {
     constexpr int P = M - 1;
-    for (int v = threadIdx.x; v < lev[A.nlev - 1].n; v += SMALL_THREADS) {
-        double acc = 0.0;
-        for (int c = A.vf_row[v]; c < A.vf_row[v + 1]; ++c) {
-            const int code = A.vf_col[c], e = code >> 1, end = code & 1;
+    const int *vf_row = O.vf_row, *vf_col = O.vf_col;
+    for (int v = threadIdx.x; v < nv; v += SMALL_THREADS) {
+        const int c0 = opri<OL>(vf_row + v);
+        rc[v] = range_sum(opri<OL>(vf_row + v + 1) - c0, [&](int k) {
+            const int code = opri<OL>(vf_col + c0 + k), e = code >> 1, end = code & 1;
+            double acc = 0.0;
 #pragma unroll
-            for (int k = 0; k < M; ++k) {
-                const double w = end ? (double)k / P : 1.0 - (double)k / P;
-                acc += w * res[e * M + k];
+            for (int q = 0; q < M; ++q) {
+                const double w = end ? (double)q / P : 1.0 - (double)q / P;
+                acc += w * res[e * M + q];
             }
-        }
-        rc[v] = acc;
+            return acc;
+        });
     }
 }
 
-__device__ __forceinline__ double s_p1_ax(const P1Lev &L, int v, const double *x) {
-    double s = L.diag[v] * x[v];
-    for (int k = 0; k < L.w; ++k) s += L.val[(size_t)k * L.n + v] * x[L.col[(size_t)k * L.n + v]];
+// Short index ranges (ELL rows, vertex and child lists: 5-7 entries on these
+// meshes) are walked UNROLL entries at a time with the index clamped into the
+// range and the surplus terms multiplied by zero, so that all loads of a row
+// are in flight together instead of one dependent pair after the other.
+constexpr int UNROLL = 8;
+
+// sum over k in [0, cnt) of f(k); cnt >= 0
+template <typename F>
+__device__ __forceinline__ double range_sum(int cnt, F &&f) {
+    double s = 0.0;
+    for (int k0 = 0; k0 < cnt; k0 += UNROLL) {
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+            const int k = min(k0 + u, cnt - 1);
+            const double t = f(k);
+            s += k0 + u < cnt ? t : 0.0;
+        }
+    }
     return s;
 }
 
-// Level vectors of the P1 hierarchy in LDS: b, x, y of level l and the vector
-// holding the level's result (tables in LDS, runtime-indexed).
+__device__ __forceinline__ double s_p1_ax(const P1Lev &L, int v, const double *x) {
+    const double s = L.diag[v] * x[v];
+    return s + range_sum(L.w, [&](int k) { return L.val[(size_t)k * L.n + v] * x[L.col[(size_t)k * L.n + v]]; });
+}
+
+// Level vectors of the P1 hierarchy in LDS: b, x, y of level l (tables in LDS,
+// runtime-indexed).  Which of x, y holds a level's iterate follows from the
+// sweep count alone, so no pointer has to be published between the phases.
 struct P1Vecs {
-    double *b[P1_TAIL_LEVELS], *x[P1_TAIL_LEVELS], *y[P1_TAIL_LEVELS], *res[P1_TAIL_LEVELS];
+    double *b[P1_TAIL_LEVELS], *x[P1_TAIL_LEVELS], *y[P1_TAIL_LEVELS];
 };
 
 // One P1 multigrid V-cycle from the finest level's right-hand side; returns the
 // LDS vector holding the result.
-__device__ double *s_p1_vcycle(const SmallArgs &A, const P1Lev *lev, P1Vecs *pv) {
-    const int top = A.nlev - 1, tid = threadIdx.x;
-    const double w = A.p1_omega;
+__device__ double *s_p1_vcycle(int nlev, int nu, double w, const Ops &O, const P1Vecs *pv) {
+    const int top = nlev - 1, tid = threadIdx.x;
+    // after pre-smoothing the iterate is in x when the sweeps after the first
+    // fused pair are even in number; after post-smoothing in that buffer when nu is even
+    const bool pre_x = nu == 1 || (nu - 2) % 2 == 0, fin_pre = nu % 2 == 0;
+    auto pre = [&](int l) { return pre_x ? pv->x[l] : pv->y[l]; };
+    auto other = [&](int l) { return pre_x ? pv->y[l] : pv->x[l]; };
+    auto fin = [&](int l) { return l == 0 ? pv->x[0] : (fin_pre ? pre(l) : other(l)); };
     for (int l = top; l >= 1; --l) {
-        const P1Lev &L = lev[l];
+        const P1Lev &L = O.lev[l];
         double *x = pv->x[l], *y = pv->y[l];
         const double *b = pv->b[l];
-        for (int v = tid; v < L.n; v += SMALL_THREADS) x[v] = w * L.dinv[v] * b[v];
+        if (nu == 1) {
+            for (int v = tid; v < L.n; v += SMALL_THREADS) x[v] = w * L.dinv[v] * b[v];
+        } else {
+            // two sweeps from zero: x1 = w D^-1 b (evaluated where needed), x2 = x1 + w D^-1 (b - A x1)
+            for (int v = tid; v < L.n; v += SMALL_THREADS) {
+                const double x1 = w * L.dinv[v] * b[v];
+                const double ax = L.diag[v] * x1 + range_sum(L.w, [&](int k) {
+                    const int u = L.col[(size_t)k * L.n + v];
+                    return L.val[(size_t)k * L.n + v] * (w * L.dinv[u] * b[u]);
+                });
+                x[v] = x1 + w * L.dinv[v] * (b[v] - ax);
+            }
+        }
         __syncthreads();
-        for (int k = 1; k < A.p1_nu; ++k) {
+        for (int k = 2; k < nu; ++k) {
             for (int v = tid; v < L.n; v += SMALL_THREADS) y[v] = x[v] + w * L.dinv[v] * (b[v] - s_p1_ax(L, v, x));
             __syncthreads();
             double *t = x;
@@ -214,42 +386,34 @@ __device__ double *s_p1_vcycle(const SmallArgs &A, const P1Lev *lev, P1Vecs *pv)
         }
         for (int v = tid; v < L.n; v += SMALL_THREADS) y[v] = b[v] - s_p1_ax(L, v, x);
         __syncthreads();
-        const P1Lev &Cl = lev[l - 1];
+        const P1Lev &Cl = O.lev[l - 1];
         double *bc = pv->b[l - 1];
         for (int c = tid; c < Cl.n; c += SMALL_THREADS) {
-            double acc = 0.0;
-            for (int k = L.crow[c]; k < L.crow[c + 1]; ++k) acc += L.cw[k] * y[L.ccol[k]];
-            bc[c] = acc;
+            const int k0 = L.crow[c];
+            bc[c] = range_sum(L.crow[c + 1] - k0, [&](int k) { return L.cw[k0 + k] * y[L.ccol[k0 + k]]; });
         }
-        if (tid == 0) pv->res[l] = x;
         __syncthreads();
     }
     {
-        const int n0 = lev[0].n;
+        const int n0 = O.lev[0].n;
         const double *b0 = pv->b[0];
         double *x0 = pv->x[0];
-        for (int i = tid; i < n0; i += SMALL_THREADS) {
-            double s = 0.0;
-            for (int j = 0; j < n0; ++j) s += A.Ainv[(size_t)i * n0 + j] * b0[j];
-            x0[i] = s;
-        }
-        if (tid == 0) pv->res[0] = x0;
+        for (int i = tid; i < n0; i += SMALL_THREADS)
+            x0[i] = range_sum(n0, [&](int j) { return O.Ainv[(size_t)i * n0 + j] * b0[j]; });
         __syncthreads();
     }
     for (int l = 1; l <= top; ++l) {
-        const P1Lev &L = lev[l];
-        double *x = pv->res[l];
-        double *y = (x == pv->x[l]) ? pv->y[l] : pv->x[l];
-        const double *xc = pv->res[l - 1], *b = pv->b[l];
-        for (int k = 0; k < A.p1_nu; ++k) {
+        const P1Lev &L = O.lev[l];
+        double *x = pre(l), *y = other(l);
+        const double *xc = fin(l - 1), *b = pv->b[l];
+        for (int k = 0; k < nu; ++k) {
             for (int v = tid; v < L.n; v += SMALL_THREADS) {
                 auto xin = [&](int u) -> double {
                     double s = x[u];
                     if (k == 0) s += 0.5 * (xc[L.parents[2 * u]] + xc[L.parents[2 * u + 1]]);
                     return s;
                 };
-                double ax = 0.0;
-                for (int q = 0; q < L.w; ++q) ax += L.val[(size_t)q * L.n + v] * xin(L.col[(size_t)q * L.n + v]);
+                double ax = range_sum(L.w, [&](int q) { return L.val[(size_t)q * L.n + v] * xin(L.col[(size_t)q * L.n + v]); });
                 const double xv = xin(v);
                 ax += L.diag[v] * xv;
                 y[v] = xv + w * L.dinv[v] * (b[v] - ax);
@@ -259,37 +423,58 @@ __device__ double *s_p1_vcycle(const SmallArgs &A, const P1Lev *lev, P1Vecs *pv)
             x = y;
             y = t;
         }
-        if (tid == 0) pv->res[l] = x;
-        __syncthreads();
     }
-    return pv->res[top];
+    return fin(top);
 }
 
-// Shared-memory layout of one workgroup (all doubles).
+// Shared-memory layout of one workgroup (all doubles, then the staged operators).
 struct SmallLds {
-    const P1Lev *lev;   // level descriptors (copied from the kernel arguments)
-    P1Vecs *pv;         // level vectors
-    double *lam, *r, *z, *p, *w, *z0, *x, *x2, *res, *b;
+    const Ops *ops;
+    P1Vecs *pv;
+    double *lam, *r, *z, *p, *p2, *w, *z0, *x, *x2, *res, *b;
     double *red;     // [2][SMALL_MAXR + 1][SW] reduction partials
     double *hv;      // [SMALL_MAXR + 1] Gram-Schmidt coefficients
-    double *H;       // [SMALL_MAXR + 1][SMALL_MAXR] Hessenberg (column-major by column j)
+    double *H;       // Hessenberg, column j at H + j (SMALL_MAXR + 1)
     double *cs, *sn, *g, *y;
     double *scal;    // broadcast scalars
 };
 
-__device__ SmallLds carve(const SmallArgs &A, const P1Lev *lev, P1Vecs *pv, double *base) {
+constexpr size_t small_fixed_doubles() {
+    return 2 * (SMALL_MAXR + 1) * SW + (SMALL_MAXR + 1) + (SMALL_MAXR + 1) * SMALL_MAXR + 3 * SMALL_MAXR +
+           (SMALL_MAXR + 1) + 8;
+}
+
+// copy count items of src into LDS at q (16-byte aligned), advancing q; every
+// thread computes the same addresses
+template <typename T>
+__device__ const T *stage(char *&q, const T *src, size_t count) {
+    typedef unsigned u4 __attribute__((ext_vector_type(4)));
+    T *dst = reinterpret_cast<T *>(q);
+    const size_t bytes = count * sizeof(T), n16 = bytes / 16;
+    const u4 *s16 = reinterpret_cast<const u4 *>(src);   // device allocations are 256-byte aligned
+    u4 *d16 = reinterpret_cast<u4 *>(dst);
+#pragma unroll 4
+    for (size_t i = threadIdx.x; i < n16; i += SMALL_THREADS) d16[i] = s16[i];
+    const unsigned *s4 = reinterpret_cast<const unsigned *>(src);
+    unsigned *d4 = reinterpret_cast<unsigned *>(dst);
+    for (size_t i = n16 * 4 + threadIdx.x; i < bytes / 4; i += SMALL_THREADS) d4[i] = s4[i];
+    q += (bytes + 15) / 16 * 16;
+    return dst;
+}
+
+__device__ SmallLds carve(const SmallArgs &A, Ops *ops, P1Vecs *pv, double *base) {
     SmallLds L;
-    L.lev = lev;
+    L.ops = ops;
     L.pv = pv;
     const int nt = A.ne * A.m;
     double *q = base;
-    double **vec[10] = {&L.lam, &L.r, &L.z, &L.p, &L.w, &L.z0, &L.x, &L.x2, &L.res, &L.b};
-    for (int i = 0; i < 10; ++i) {
+    double **vec[11] = {&L.lam, &L.r, &L.z, &L.p, &L.p2, &L.w, &L.z0, &L.x, &L.x2, &L.res, &L.b};
+    for (int i = 0; i < 11; ++i) {
         *vec[i] = q;
         q += nt;
     }
     for (int l = 0; l < A.nlev; ++l) {
-        const int n = lev[l].n;
+        const int n = ops->lev[l].n;
         if (threadIdx.x == 0) {
             pv->b[l] = q;
             pv->x[l] = q + n;
@@ -312,33 +497,122 @@ __device__ SmallLds carve(const SmallArgs &A, const P1Lev *lev, P1Vecs *pv, doub
     L.y = q;
     q += SMALL_MAXR;
     L.scal = q;
+    q += 8;
+    if (A.stage_ops) {
+        // operators into LDS (same layouts, 16-byte aligned), after the vectors; thread 0
+        // publishes the pointers
+        char *c = reinterpret_cast<char *>(q);
+        c += (16 - (reinterpret_cast<uintptr_t>(c) & 15)) & 15;
+        const int ne = A.ne, m = A.m;
+        const double *S = stage(c, A.S, (size_t)padded(5 * m * m, 2) * ne);
+        const double *T = stage(c, A.T, (size_t)padded(4 * m * m, 2) * ne);
+        const double *Dw = stage(c, A.Dw, (size_t)padded(m * m, 2) * ne);
+        const int *nbr = stage(c, A.nbr, (size_t)4 * ne);
+        const int *fvert = stage(c, A.fvert, (size_t)2 * ne);
+        const int nv = ops->lev[A.nlev - 1].n;
+        const int *vf_row = stage(c, A.vf_row, (size_t)nv + 1);
+        const int *vf_col = stage(c, A.vf_col, (size_t)2 * ne);
+        const double *B = A.p1B ? stage(c, A.p1B, (size_t)nv * nv) : nullptr;
+        for (int l = 0; l < (A.p1B ? 0 : A.nlev); ++l) {
+            const P1Lev &G = ops->lev[l];
+            const int *col = stage(c, G.col, (size_t)G.w * G.n);
+            const double *val = stage(c, G.val, (size_t)G.w * G.n);
+            const double *diag = stage(c, G.diag, (size_t)G.n);
+            const double *dinv = stage(c, G.dinv, (size_t)G.n);
+            const int *parents = nullptr, *crow = nullptr, *ccol = nullptr;
+            const double *cw = nullptr;
+            if (l > 0) {
+                const int nc = ops->lev[l - 1].n;
+                parents = stage(c, G.parents, (size_t)2 * G.n);
+                crow = stage(c, G.crow, (size_t)nc + 1);
+                ccol = stage(c, G.ccol, (size_t)2 * G.n);
+                cw = stage(c, G.cw, (size_t)2 * G.n);
+            }
+            __syncthreads();   // every thread has read the global descriptor of level l
+            if (threadIdx.x == 0) {
+                P1Lev &D = ops->lev[l];
+                D.col = col;
+                D.val = val;
+                D.diag = diag;
+                D.dinv = dinv;
+                if (l > 0) {
+                    D.parents = parents;
+                    D.crow = crow;
+                    D.ccol = ccol;
+                    D.cw = cw;
+                }
+            }
+        }
+        const int n0 = ops->lev[0].n;
+        const double *Ainv = A.p1B ? ops->Ainv : stage(c, ops->Ainv, (size_t)n0 * n0);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            ops->B = B;
+            ops->S = S;
+            ops->T = T;
+            ops->Dw = Dw;
+            ops->Ainv = Ainv;
+            ops->nbr = nbr;
+            ops->fvert = fvert;
+            ops->vf_row = vf_row;
+            ops->vf_col = vf_col;
+        }
+    }
     return L;
 }
 
-// z = V(r) (r read at this thread's facets only; z in LDS)
-template <int M>
-__device__ void s_vcycle(const SmallArgs &A, SmallLds &L, const double *r, double *z) {
-    s_jacobi0<M>(A, r, L.z0);
-    __syncthreads();
+// z = V(r): r and z in LDS.  With d given, returns this thread's part of d . z and
+// leaves the barrier after the last sweep to the caller's reduction.
+template <int M, bool OL>
+__device__ double s_vcycle(const SmallArgs &A, SmallLds &L, const double *r, double *z, const double *d = nullptr) {
+    const Ops &O = *L.ops;
+    const int ne = A.ne, tid = threadIdx.x;
     double *bufs[2] = {L.x, L.x2};
     int bi = 0;
     double *cur = L.z0;
-    for (int k = 1; k < A.nu_pre; ++k) {
+    s_first_sweep<M, OL>(ne, O, A.omega, r, L.z0, A.nu_pre >= 2 ? L.x : nullptr);
+    __syncthreads();
+    if (A.nu_pre >= 2) {
+        cur = L.x;
+        bi = 1;
+    }
+    for (int k = 2; k < A.nu_pre; ++k) {
         double *out = bufs[bi];
         bi ^= 1;
-        s_sweep<M>(A, cur, L.z0, nullptr, out);
+        s_sweep<M, OL>(ne, O, A.omega, cur, L.z0, nullptr, out);
         __syncthreads();
         cur = out;
     }
-    s_apply<M>(A, cur, r, L.res);
+    s_apply<M, OL>(ne, O, cur, r, L.res);
     __syncthreads();
     const int top = A.nlev - 1;
-    s_restrict_trace<M>(A, L.lev, L.res, L.pv->b[top]);
+    s_restrict_trace<M, OL>(O.lev[top].n, O, L.res, L.pv->b[top]);
     __syncthreads();
-    const double *xl = s_p1_vcycle(A, L.lev, L.pv);
+    const double *xl;
+    if (O.B) {
+        // the P1 V-cycle as its matrix: four lanes per row, combined by shuffles
+        const int nv = O.lev[top].n;
+        const double *bv = L.pv->b[top], *B = O.B;
+        double *xv = L.pv->x[top];
+        for (int i0 = 0; i0 < nv; i0 += SMALL_THREADS / 4) {
+            const int i = i0 + (tid >> 2), q = tid & 3;
+            double s = 0.0;
+            if (i < nv)
+                for (int j = q; j < nv; j += 4) s += oprd<OL>(B + (size_t)i * nv + j) * bv[j];
+            s += __shfl_xor(s, 1, 64);
+            s += __shfl_xor(s, 2, 64);
+            if (i < nv && q == 0) xv[i] = s;
+        }
+        __syncthreads();
+        xl = xv;
+    } else {
+        xl = s_p1_vcycle(A.nlev, A.p1_nu, A.p1_omega, O, L.pv);
+    }
+    double part = 0.0;
     for (int k = 0; k < A.nu_post; ++k) {
+        const bool last = k == A.nu_post - 1;
         double *out;
-        if (k == A.nu_post - 1) {
+        if (last) {
             out = z;
         } else {
             out = bufs[bi];
@@ -348,25 +622,36 @@ __device__ void s_vcycle(const SmallArgs &A, SmallLds &L, const double *r, doubl
             }
             bi ^= 1;
         }
-        s_sweep<M>(A, cur, L.z0, k == 0 ? xl : nullptr, out);
-        __syncthreads();
+        part = s_sweep<M, OL>(ne, O, A.omega, cur, L.z0, k == 0 ? xl : nullptr, out, last ? d : nullptr);
+        if (!(last && d)) __syncthreads();
         cur = out;
     }
+    return part;
 }
 
-template <int P, bool STAGE>
+template <int P, bool STAGE, bool OL>
 __global__ __launch_bounds__(SMALL_THREADS) void k_solve_small(const SmallArgs A) {
     constexpr int M = P + 1, n = (P + 1) * (P + 2) / 2, nc = 3 * n, nt = 3 * M, ZW = cell_zw(P);
     extern __shared__ double lds[];
-    __shared__ P1Lev slev[P1_TAIL_LEVELS];
+    __shared__ Ops sops;
     __shared__ P1Vecs spv;
     if (threadIdx.x == 0) {
+        sops.S = A.S;
+        sops.T = A.T;
+        sops.Dw = A.Dw;
+        sops.Ainv = A.Ainv;
+        sops.B = A.p1B;
+        sops.nbr = A.nbr;
+        sops.fvert = A.fvert;
+        sops.vf_row = A.vf_row;
+        sops.vf_col = A.vf_col;
 #pragma unroll
-        for (int l = 0; l < P1_TAIL_LEVELS; ++l) slev[l] = A.lev[l];
+        for (int l = 0; l < P1_TAIL_LEVELS; ++l) sops.lev[l] = A.lev[l];
     }
     __syncthreads();
-    SmallLds L = carve(A, slev, &spv, lds);
+    SmallLds L = carve(A, &sops, &spv, lds);
     __syncthreads();
+    const Ops &O = sops;
     const int tid = threadIdx.x, rh = blockIdx.x, nb = A.nb, ne = A.ne;
     const size_t NK = (size_t)A.nk;
     double *red0 = L.red, *red1 = L.red + (SMALL_MAXR + 1) * SW;
@@ -415,7 +700,7 @@ __global__ __launch_bounds__(SMALL_THREADS) void k_solve_small(const SmallArgs A
 
     while (true) {
         // true residual r = b - S lam (FP64)
-        s_apply<M>(A, L.lam, L.b, L.r);
+        s_apply<M, OL>(ne, O, L.lam, L.b, L.r);
         part = 0.0;
         for_own<M>(ne, [&](int i) { part += L.r[i] * L.r[i]; });
         const double rr = block_sum(part, red());
@@ -431,51 +716,52 @@ __global__ __launch_bounds__(SMALL_THREADS) void k_solve_small(const SmallArgs A
         }
         ++restarts;
         if (A.krylov == HDG_KRYLOV_PCG) {
-            s_vcycle<M>(A, L, L.r, L.z);
-            part = 0.0;
-            for_own<M>(ne, [&](int i) {
-                part += L.r[i] * L.z[i];
-                L.p[i] = L.z[i];
-            });
-            double rz = block_sum(part, red());
+            // p_0 = z_0; then per iteration: p = z + beta p (fused into w = S p), alpha = rz / p.w,
+            // lam += alpha p, r -= alpha w, z = V(r), beta = r.z / rz
+            double rz = block_sum(s_vcycle<M, OL>(A, L, L.r, L.z, L.r), red());
+            double beta = 0.0;
+            double *pbuf[2] = {L.p, L.p2};
+            int pc = 0;
+            const double *po = L.z;   // first direction: z itself (beta = 0)
             while (its < A.maxit) {
-                s_apply<M>(A, L.p, nullptr, L.w);
-                part = 0.0;
-                for_own<M>(ne, [&](int i) { part += L.p[i] * L.w[i]; });
-                const double pw = block_sum(part, red());
+                double *pn = pbuf[pc];
+                const double pw = block_sum(s_apply_dir<M, OL>(ne, O, L.z, beta, po, pn, L.w), red());
                 const double alpha = rz / pw;
                 part = 0.0;
                 for_own<M>(ne, [&](int i) {
-                    L.lam[i] += alpha * L.p[i];
+                    L.lam[i] += alpha * pn[i];
                     L.r[i] -= alpha * L.w[i];
                     part += L.r[i] * L.r[i];
                 });
                 const double rrk = block_sum(part, red());
                 ++its;
                 if (!isfinite(rrk) || rrk <= rtol * rtol * bn2) break;
-                s_vcycle<M>(A, L, L.r, L.z);
-                part = 0.0;
-                for_own<M>(ne, [&](int i) { part += L.r[i] * L.z[i]; });
-                const double rzn = block_sum(part, red());
-                const double beta = rzn / rz;
+                const double rzn = block_sum(s_vcycle<M, OL>(A, L, L.r, L.z, L.r), red());
+                beta = rzn / rz;
                 rz = rzn;
-                for_own<M>(ne, [&](int i) { L.p[i] = L.z[i] + beta * L.p[i]; });
-                __syncthreads();
+                po = pn;
+                pc ^= 1;
             }
         } else {
-            // flexible GMRES(R), classical Gram-Schmidt, the basis vectors in global memory
+            // flexible GMRES(R), classical Gram-Schmidt; the basis in global memory
+            // (each thread reads back only the items it wrote), the current basis
+            // vector also in LDS (L.p) as the V-cycle's input
             const int R = A.restart;
             const double beta = sqrt(rr);
-            for_own<M>(ne, [&](int i) { Vb[i] = L.r[i] / beta; });
+            for_own<M>(ne, [&](int i) {
+                const double v = L.r[i] / beta;
+                Vb[i] = v;
+                L.p[i] = v;
+            });
             if (tid == 0) L.g[0] = beta;
+            __syncthreads();
             int k = 0;
             for (int j = 0; j < R && its < A.maxit; ++j) {
-                const double *Vj = Vb + (size_t)j * ne * M;
-                s_vcycle<M>(A, L, Vj, L.z);
+                s_vcycle<M, OL>(A, L, L.p, L.z);
                 double *Zj = Zb + (size_t)j * ne * M;
                 for_own<M>(ne, [&](int i) { Zj[i] = L.z[i]; });
-                s_apply<M>(A, L.z, nullptr, L.w);
-                // h_i = V_i . w (this thread's items were written by this thread)
+                s_apply<M, OL>(ne, O, L.z, nullptr, L.w);
+                // h_q = V_q . w for q <= j
                 double *rd = red();
                 for (int q = 0; q <= j; ++q) {
                     const double *Vq = Vb + (size_t)q * ne * M;
@@ -502,7 +788,11 @@ __global__ __launch_bounds__(SMALL_THREADS) void k_solve_small(const SmallArgs A
                 const double hn = sqrt(block_sum(part, red()));
                 double *Vn = Vb + (size_t)(j + 1) * ne * M;
                 const double inv = hn > 0 ? 1.0 / hn : 0.0;
-                for_own<M>(ne, [&](int i) { Vn[i] = L.w[i] * inv; });
+                for_own<M>(ne, [&](int i) {
+                    const double v = L.w[i] * inv;
+                    Vn[i] = v;
+                    L.p[i] = v;
+                });
                 if (tid == 0) {
                     // Givens rotations on column j of the Hessenberg matrix
                     double *Hj = L.H + (size_t)j * (SMALL_MAXR + 1);
@@ -579,40 +869,75 @@ __global__ __launch_bounds__(SMALL_THREADS) void k_solve_small(const SmallArgs A
     }
 }
 
+size_t round16(size_t b) { return (b + 15) / 16 * 16; }
+
 }  // namespace
 
-size_t small_lds_bytes(int ne, int m, const int *level_n, int nlev) {
-    size_t d = (size_t)10 * ne * m;
-    for (int l = 0; l < nlev; ++l) d += 3 * (size_t)level_n[l];
-    d += 2 * (SMALL_MAXR + 1) * SW + (SMALL_MAXR + 1) + (SMALL_MAXR + 1) * SMALL_MAXR + 3 * SMALL_MAXR +
-         (SMALL_MAXR + 1) + 8;
-    return d * sizeof(double);
+size_t small_lds_bytes(int ne, int m, const P1Lev *lev, int nlev, bool stage_ops, int nB) {
+    size_t d = (size_t)11 * ne * m;
+    for (int l = 0; l < nlev; ++l) d += 3 * (size_t)lev[l].n;
+    size_t bytes = (d + small_fixed_doubles()) * sizeof(double);
+    if (stage_ops) {
+        bytes += 16 + round16(8 * (size_t)padded(5 * m * m, 2) * ne) + round16(8 * (size_t)padded(4 * m * m, 2) * ne) +
+                 round16(8 * (size_t)padded(m * m, 2) * ne) + round16(16 * (size_t)ne) + round16(8 * (size_t)ne) +
+                 round16(4 * ((size_t)lev[nlev - 1].n + 1)) + round16(8 * (size_t)ne);
+        if (nB) {
+            bytes += round16(8 * (size_t)nB * nB);
+        } else {
+            for (int l = 0; l < nlev; ++l) {
+                const size_t n = lev[l].n, w = lev[l].w;
+                bytes += round16(4 * w * n) + round16(8 * w * n) + 2 * round16(8 * n);
+                if (l > 0)
+                    bytes += round16(8 * n) + round16(4 * ((size_t)lev[l - 1].n + 1)) + round16(8 * n) + round16(16 * n);
+            }
+            bytes += round16(8 * (size_t)lev[0].n * lev[0].n);
+        }
+    }
+    return bytes;
 }
 
-hipError_t small_prepare(int p, size_t lds) {
+template <int P, bool STAGE, bool OL>
+hipError_t prepare_one(size_t bytes) {
+    return hipFuncSetAttribute((const void *)k_solve_small<P, STAGE, OL>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)bytes);
+}
+
+template <int P>
+hipError_t prepare_p(size_t bytes) {
+    const hipError_t e[4] = {prepare_one<P, false, false>(bytes), prepare_one<P, false, true>(bytes),
+                             prepare_one<P, true, false>(bytes), prepare_one<P, true, true>(bytes)};
+    for (hipError_t x : e)
+        if (x != hipSuccess) return x;
+    return hipSuccess;
+}
+
+hipError_t small_prepare(int p, size_t bytes) {
     // dynamic LDS above the default 64 KiB needs the kernels' opt-in
-    auto set = [&](const void *f) {
-        return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    };
-    hipError_t e1 = hipSuccess, e2 = hipSuccess;
     switch (p) {
-    case 1: e1 = set((const void *)k_solve_small<1, false>); e2 = set((const void *)k_solve_small<1, true>); break;
-    case 2: e1 = set((const void *)k_solve_small<2, false>); e2 = set((const void *)k_solve_small<2, true>); break;
-    case 3: e1 = set((const void *)k_solve_small<3, false>); e2 = set((const void *)k_solve_small<3, true>); break;
+    case 1: return prepare_p<1>(bytes);
+    case 2: return prepare_p<2>(bytes);
+    case 3: return prepare_p<3>(bytes);
     default: return hipErrorInvalidValue;
     }
-    return e1 != hipSuccess ? e1 : e2;
 }
 
-void launch_solve_small(int p, bool stage, const SmallArgs &A, size_t lds, hipStream_t s) {
+template <int P>
+void launch_p(bool stage, const SmallArgs &A, size_t bytes, hipStream_t s) {
     const dim3 grid(A.nb), block(SMALL_THREADS);
-    switch (p * 2 + (stage ? 1 : 0)) {
-    case 2: k_solve_small<1, false><<<grid, block, lds, s>>>(A); break;
-    case 3: k_solve_small<1, true><<<grid, block, lds, s>>>(A); break;
-    case 4: k_solve_small<2, false><<<grid, block, lds, s>>>(A); break;
-    case 5: k_solve_small<2, true><<<grid, block, lds, s>>>(A); break;
-    case 6: k_solve_small<3, false><<<grid, block, lds, s>>>(A); break;
-    case 7: k_solve_small<3, true><<<grid, block, lds, s>>>(A); break;
+    if (stage) {
+        if (A.stage_ops) k_solve_small<P, true, true><<<grid, block, bytes, s>>>(A);
+        else k_solve_small<P, true, false><<<grid, block, bytes, s>>>(A);
+    } else {
+        if (A.stage_ops) k_solve_small<P, false, true><<<grid, block, bytes, s>>>(A);
+        else k_solve_small<P, false, false><<<grid, block, bytes, s>>>(A);
+    }
+}
+
+void launch_solve_small(int p, bool stage, const SmallArgs &A, size_t bytes, hipStream_t s) {
+    switch (p) {
+    case 1: launch_p<1>(stage, A, bytes, s); break;
+    case 2: launch_p<2>(stage, A, bytes, s); break;
+    case 3: launch_p<3>(stage, A, bytes, s); break;
     default: break;
     }
 }
