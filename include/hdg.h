@@ -223,6 +223,19 @@ int hdg_get_topology(const hdg_ctx *ctx, int32_t *facet_cell, int32_t *facet_loc
  * rhat:   (device) [n_facet][facet_dofs][nrhs].  1 <= nrhs <= max_rhs. */
 int hdg_condense(hdg_ctx *ctx, int32_t nrhs, const double *r_cell, double *rhat, void *stream);
 
+/* hdg_condense without allocation, for callers that cannot allocate device
+ * memory during the call (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same kernels and results (bit for bit)
+ * as hdg_condense, with the per-cell staging in a fixed scratch array that
+ * every GPU the library runs on holds for the life of the process (32 MiB;
+ * resolved by hdg_setup) instead of the context's buffer.  Needs
+ * 3 facet_dofs * n_cell * nrhs <= 4194304 doubles, else HDG_EINVAL (use
+ * hdg_condense).  Calls no allocating routine.  The array is shared by every
+ * call on that GPU and keeps the last call's contents (nothing in it needs to
+ * start at zero): calls that overlap on one GPU -- from two streams, threads
+ * or contexts -- race on it and must be serialised by the caller. */
+int hdg_condense_noalloc(hdg_ctx *ctx, int32_t nrhs, const double *r_cell, double *rhat, void *stream);
+
 /* y = S x, matrix-free over facet block rows (Eq. schur_system operator).
  * precision HDG_FP64 uses the FP64 rows, HDG_MIXED the FP32 rows with FP32 accumulation.
  * x, y: (device) [n_facet][facet_dofs][nrhs], must not alias. */

@@ -6,6 +6,8 @@
 #include <cstdint>
 #include <cstring>
 #include <functional>
+#include <mutex>
+#include <string>
 #include <utility>
 
 #include "hdg_kernels.h"
@@ -14,6 +16,35 @@
 using hdg::Error;
 
 namespace {
+
+// ------------------------------------------------------------------ static scratch of hdg_condense_noalloc
+//
+// The condensation stages each cell's contribution to its facets before the
+// facet gather (3 facet_dofs values per cell and right-hand side).
+// hdg_condense keeps that buffer in the context; hdg_condense_noalloc uses
+// this fixed array instead, so that the call itself allocates nothing.  Every
+// GPU the library runs on holds its own copy until the process ends.  The
+// array's name is a host-side stand-in: host code uses only the device address
+// hipGetSymbolAddress returns for it, resolved once per device by hdg_setup
+// with that device current.
+constexpr size_t NOALLOC_SCRATCH_DOUBLES = (size_t)4 << 20;   // 32 MiB
+static __device__ __align__(256) double scratch[NOALLOC_SCRATCH_DOUBLES];
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_dev[MAX_DEVICES] = {};
+
+// device address of scratch on device dev (the current device); resolved on first use
+double *scratch_on(int dev) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    HDG_REQUIRE(dev >= 0 && dev < MAX_DEVICES, "device id out of range for the static scratch");
+    if (!g_scratch_dev[dev]) {
+        void *ptr = nullptr;
+        HDG_HIP_CHECK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        HDG_REQUIRE(ptr != nullptr, "hipGetSymbolAddress returned no address for the static scratch");
+        g_scratch_dev[dev] = static_cast<double *>(ptr);
+    }
+    return g_scratch_dev[dev];
+}
 
 // ------------------------------------------------------------------ allocation helpers
 
@@ -924,6 +955,7 @@ void setup_impl(const hdg_mesh *levels, int nlev, const int32_t *const *parents,
     }
 
     HDG_HIP_CHECK(hipGetDevice(&c->device));
+    c->noalloc_scratch = scratch_on(c->device);
     c->prm = *prm;
     c->opt = opt;
     c->p = prm->degree;
@@ -1414,6 +1446,23 @@ extern "C" int hdg_condense(hdg_ctx *c, int32_t nb, const double *r_cell, double
         for (int rep = 0; rep < t.repeats(); ++rep)
             hdg::launch_condense(c->p, c->nu, c->n_cell, c->n_facet, nb, c->Zr, r_cell, c->loc, c->d_fcell, c->d_floc, rhat,
                                  s);
+        check_launch();
+    });
+}
+
+extern "C" int hdg_condense_noalloc(hdg_ctx *c, int32_t nb, const double *r_cell, double *rhat, void *stream) {
+    if (!c) return HDG_EINVAL;
+    return guard([&] {
+        check_nb(c, nb);
+        HDG_REQUIRE(r_cell && rhat, "r_cell and rhat must not be NULL");
+        const size_t need = (size_t)c->nt * c->n_cell * nb;
+        if (need > NOALLOC_SCRATCH_DOUBLES)
+            throw Error{HDG_EINVAL, "hdg_condense_noalloc needs " + std::to_string(need) +
+                                        " doubles of scratch (3 facet_dofs x n_cell x nrhs), the static scratch holds " +
+                                        std::to_string(NOALLOC_SCRATCH_DOUBLES) + ": use hdg_condense"};
+        HDG_REQUIRE(c->noalloc_scratch, "static scratch not resolved for this device");
+        hdg::launch_condense(c->p, c->nu, c->n_cell, c->n_facet, nb, c->Zr, r_cell, c->noalloc_scratch, c->d_fcell,
+                             c->d_floc, rhat, as_stream(stream));
         check_launch();
     });
 }

@@ -262,6 +262,7 @@ struct hdg_ctx {
     double *hy = nullptr;                     // FGMRES coefficients [restart][max_rhs]
     double *dbn = nullptr;                    // ||rhat|| per RHS (device)
     double *loc = nullptr;                    // condensation scratch [nt][n_cell][max_rhs]
+    double *noalloc_scratch = nullptr;        // this device's static scratch (hdg_condense_noalloc)
     std::vector<double> hbn2;                 // ||rhat||^2 per RHS (host)
     double *hlag = nullptr;                   // host-mapped landing slots for reduction results [4][64]
     double *dlag = nullptr;                   // device view of hlag

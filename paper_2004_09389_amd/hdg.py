@@ -93,6 +93,7 @@ _SIGS = {
     "hdg_mg_vcycle": (_I, [_P, _I, _I, _P, _P, _P]),
     "hdg_solve": (_I, [_P, _I, _P, _P, ctypes.POINTER(HdgSolveInfo), _P]),
     "hdg_recover": (_I, [_P, _I, _P, _P, _P, _P]),
+    "hdg_condense_noalloc": (_I, [_P, _I, _P, _P, _P]),
     "hdg_stage_solve": (_I, [_P, _I, _P, _P, _P, ctypes.POINTER(HdgSolveInfo), _P]),
     "hdg_destroy": (None, [_P]),
     "hdg_last_error": (ctypes.c_char_p, []),
@@ -322,6 +323,14 @@ class HdgSolver:
         out = self.trace_zeros(nb) if out is None else out
         self._trace(out, "out", nb)
         _check(self.lib.hdg_condense(self.ctx, nb, _ptr(r_cell), _ptr(out), _stream()))
+        return out
+
+    def condense_noalloc(self, r_cell, out):
+        """Step 1 with the library's static scratch (hdg_condense_noalloc): the
+        caller passes the output buffer; nothing is allocated."""
+        nb = self._cell(r_cell, "r_cell")
+        self._trace(out, "out", nb)
+        _check(self.lib.hdg_condense_noalloc(self.ctx, nb, _ptr(r_cell), _ptr(out), _stream()))
         return out
 
     def trace_apply(self, x, precision: int = HDG_FP64, out=None):
