@@ -1,19 +1,20 @@
-"""Benchmark: one implicit HDG stage of the linearised rotating shallow-water
+"""Benchmark: the implicit HDG stage of the linearised rotating shallow-water
 equations on one MI355X.
 
-Workload (default): periodic unit square, 256 x 256 squares -> 131072
-triangles, g = H = 1, f = 1, dt = 8/256 (gravity-wave Courant 8), DG degree
-p = 3 with a degree-3 scalar trace (786 432 trace unknowns), right-hand side
-a smooth random field (64 Fourier modes per field, amplitudes ~ |k|^-2).
+Headline workload: the icosahedral sphere at refinement level 7 (327 680
+cells), radius 6.371e6 m, g = 9.81, H = 5960, f = 2 Omega sin(latitude),
+dt = 3600 s, DG degree p = 3 with a degree-3 scalar trace (1 966 080 trace
+unknowns, 9 830 400 cell unknowns), 32 right-hand sides per step (smooth 3-D
+Fourier fields, |h| <= 100 m, |u| <= 20 m/s).  A step is one pass of the whole
+hot path for the batch: condense (Step 1) -> Krylov solve of the trace system
+to a true relative residual of 1e-8 preconditioned by the non-nested multigrid
+V-cycle (Step 2) -> recovery of the cell fields (Step 3), inputs resident in
+device memory.  `value` is the mixed-precision solver's throughput (FP64
+iterative refinement around an FP32/BF16 inner solve), in solves per second;
+the plain FP64 multigrid, the learned smoother and the other workloads are
+timed beside it.
 
-A step is one pass of the whole hot path for one batch of right-hand sides:
-condense (Step 1) -> Krylov solve of the trace system to a true relative
-residual of 1e-8 preconditioned by the non-nested multigrid V-cycle
-(Step 2) -> recovery of the cell fields (Step 3).  Inputs are resident in
-device memory before timing starts.  `value` is the mixed-precision solver's
-throughput (solves/s); the plain FP64 GPU multigrid is timed beside it.
-
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--degree p] [--nrhs b]
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
 from __future__ import annotations
 
@@ -62,14 +63,20 @@ def parse():
     ap.add_argument("--train-batches", type=int, default=32, help="learned smoother: batches of random errors")
     ap.add_argument("--train-epochs", type=int, default=8, help="learned smoother: Adam steps per batch")
     ap.add_argument("--learned-nu", type=int, default=2, help="learned smoother: sweeps before and after the coarse solve")
-    ap.add_argument("--headline", default="mixed", choices=["learned", "mixed"],
-                    help="which reduced-precision solver `value` reports")
     ap.add_argument("--no-lf", action="store_true", help="skip the Lax-Friedrichs-flux leg")
     ap.add_argument("--lf-coarse", type=int, default=16, help="LF leg: side of the coarsest RT0 level")
     ap.add_argument("--lf-only", action="store_true", help="run only the Lax-Friedrichs leg (profiling)")
-    ap.add_argument("--no-sphere", action="store_true", help="skip the batched level-7 sphere leg")
-    ap.add_argument("--sphere-only", action="store_true", help="run only the batched level-7 sphere leg")
+    ap.add_argument("--sphere-only", action="store_true", help="only the headline level-7 sphere leg")
     ap.add_argument("--sphere-nrhs", type=int, default=32)
+    ap.add_argument("--sphere-legs", default="mixed_ir,learned_ir,mixed,fp64",
+                    help="comma-separated solvers of the level-7 sphere leg")
+    ap.add_argument("--sphere-headline", default="mixed_ir", choices=["mixed_ir", "learned_ir", "mixed"],
+                    help="the reduced-precision solver whose level-7 throughput is `value`")
+    ap.add_argument("--sphere-rhs", default="fourier", choices=["fourier", "iid"],
+                    help="level-7 right-hand sides: smooth 3-D Fourier fields or iid coefficients")
+    ap.add_argument("--no-torus", action="store_true", help="skip the 256x256 torus leg")
+    ap.add_argument("--no-traj", action="store_true", help="skip the level-6 trajectory leg")
+    ap.add_argument("--no-gain", action="store_true", help="skip the learned-smoother gain leg")
     ap.add_argument("--no-imex", action="store_true", help="skip the IMEX time-stepping leg")
     ap.add_argument("--no-dg", action="store_true", help="skip the non-hybridised DG baseline leg")
     ap.add_argument("--dg-only", action="store_true", help="run only the non-hybridised DG baseline leg")
@@ -84,10 +91,11 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def measured_traffic(kernel_label):
-    """HBM bytes per launch of `kernel_label` from the committed rocprofv3 counter
-    summaries (FETCH_SIZE, WRITE_SIZE scaled by a reference copy), or None when
-    no summary covers it or the kernel source changed since the counters were taken."""
+def measured_traffic(kernel_label, workload):
+    """HBM bytes per launch of `kernel_label` on `workload` from the committed
+    rocprofv3 counter summaries (FETCH_SIZE, WRITE_SIZE scaled by a reference
+    copy), or None when no summary covers it or the kernel source changed since
+    the counters were taken."""
     import glob
     import hashlib
     src = os.path.join(ROOT, "paper_2004_09389_amd", "csrc", "hdg_kernels.hip")
@@ -95,9 +103,9 @@ def measured_traffic(kernel_label):
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "hbm_traffic_*.md"))):
         for line in open(path):
             f = line.split()
-            if len(f) == 5 and f[0] == "traffic_bytes_per_launch" and f[1] == kernel_label and f[3] == "kernels_sha1":
-                if f[4] == cur:
-                    return float(f[2]), os.path.relpath(path, ROOT)
+            if (len(f) == 7 and f[0] == "traffic_bytes_per_launch" and f[1] == kernel_label and f[3] == "workload"
+                    and f[4] == workload and f[5] == "kernels_sha1" and f[6] == cur):
+                return float(f[2]), os.path.relpath(path, ROOT)
     return None
 
 
@@ -347,61 +355,198 @@ def lf_leg(args, p, n, nb, run_steps):
     return out
 
 
-def sphere_leg(args, weights, run_steps, level=7, p=3, dt=3600.0, nb=None, seed=500):
+def _step_fn(s, r, nb):
+    lam, rhat, q = s.trace_zeros(nb), s.trace_zeros(nb), s.cell_zeros(nb)
+
+    def step():
+        s.condense(r, out=rhat)
+        lam.zero_()
+        _, info = s.solve(rhat, lam)
+        s.recover(r, lam, out=q)
+        return info
+    return step, lam, q
+
+
+def _timed(step, steps):
+    """steps calls of step() with a HIP event on the launch stream after each;
+    returns (wall seconds, infos, per-step ms summary)."""
+    import gc
+
+    import torch
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    torch.cuda.synchronize()
+    gc.disable()
+    t = time.perf_counter()
+    ev[0].record()
+    infos = []
+    for k in range(steps):
+        infos.append(step())
+        ev[k + 1].record()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t
+    gc.enable()
+    ms = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(steps)])
+    return el, infos, {"median": round(float(np.median(ms)), 4), "p10": round(float(np.percentile(ms, 10)), 4),
+                       "p90": round(float(np.percentile(ms, 90)), 4), "steps": int(steps)}
+
+
+KERNEL_CLASSES = ("apply", "sweep", "residual", "condense", "recover", "mlp")
+
+
+def sphere_leg(args, weights, run_steps, level=7, p=3, dt=3600.0, nb=None, seed=500, rhs_kind="fourier",
+               legs=None, instrument=None, warmup=1):
     """Icosahedral sphere of radius 6.371e6 m at the given level, g = 9.81, H = 5960,
     f = 2 Omega sin(latitude): by default level 7 (327 680 cells), p = 3,
-    dt = 3600 s, sphere_nrhs right-hand sides per step (iid coefficients,
-    seed 500); the level-6 workload is p = 2, dt = 1800 s, 16 per step.  Plain FP64 multigrid against
-    the mixed solvers (HDG_MIXED; HDG_MIXED_IR with block-Jacobi, and with the
-    learned smoother when weights are given: trained on the flat torus, not
-    on the sphere)."""
+    dt = 3600 s, sphere_nrhs right-hand sides per step (smooth 3-D Fourier fields,
+    seed 500, or iid coefficients).  Plain FP64 multigrid against the mixed solvers
+    (HDG_MIXED; HDG_MIXED_IR with block-Jacobi, and with the learned smoother when
+    weights are given: trained on the flat torus, not on the sphere).  Each leg
+    reports its throughput, HIP-event step times and iterations; the reduced
+    precision legs their per-field difference from the FP64 leg's solution; the
+    leg named by `instrument` also an instrumented pass (per-launch HIP events on
+    the launch stream, every instrumented launch repeated TIMING_REPEAT times per
+    event pair) for the roofline."""
     import torch
 
     import hdg_inputs as hi
-    from paper_2004_09389_amd.hdg import HDG_FP64, HDG_MIXED, HDG_SMOOTH_BJACOBI, HDG_SMOOTH_MLP, HdgSolver
+    from paper_2004_09389_amd.hdg import (HDG_FP64, HDG_MIXED, HDG_MIXED_IR, HDG_SMOOTH_BJACOBI, HDG_SMOOTH_MLP,
+                                          HdgSolver)
     nb = nb or args.sphere_nrhs
     hier = hi.icosphere_hierarchy(level, 6.371e6, level_coarse=3)
-    r = torch.from_numpy(hi.iid_rhs(hier.fine, p, seed, nrhs=nb)).to("cuda")
+    t0 = time.perf_counter()
+    if rhs_kind == "fourier":
+        rh = hi.smooth_rhs_sphere(hier.fine, p, seed, nrhs=nb, device="cuda")
+    else:
+        rh = hi.iid_rhs(hier.fine, p, seed, nrhs=nb)
+    r = torch.from_numpy(rh).to("cuda")
+    del rh
+    log(f"[bench] sphere L{level}: {rhs_kind} right-hand sides in {time.perf_counter() - t0:.1f}s")
     out = {"workload": f"icosphere_L{level}_p{p}_dt{dt:g}_b{nb}", "n_cell": hier.fine.n_cell,
-           "n_trace_dof": int(3 * (p + 1) * hier.fine.n_cell // 2), "nrhs": nb}
-    from paper_2004_09389_amd.hdg import HDG_MIXED_IR
-    legs = [("fp64", HDG_FP64, HDG_SMOOTH_BJACOBI), ("mixed", HDG_MIXED, HDG_SMOOTH_BJACOBI),
-            ("mixed_ir", HDG_MIXED_IR, HDG_SMOOTH_BJACOBI)]
-    if weights is not None:
-        legs.append(("learned_ir", HDG_MIXED_IR, HDG_SMOOTH_MLP))
-    for name, prec, sm in legs:
+           "n_trace_dof": int(3 * (p + 1) * hier.fine.n_cell // 2),
+           "n_cell_dof": int(3 * (p + 1) * (p + 2) // 2 * hier.fine.n_cell), "nrhs": nb,
+           "rhs": (f"smooth 3-D Fourier fields (64 modes per field, |k| <= 8, amplitudes ~ |k|^-2), seeds from {seed}"
+                   if rhs_kind == "fourier" else f"iid N(0,1) coefficients, seed {seed}"), "rtol": args.rtol}
+    table = {"fp64": (HDG_FP64, HDG_SMOOTH_BJACOBI), "mixed": (HDG_MIXED, HDG_SMOOTH_BJACOBI),
+             "mixed_ir": (HDG_MIXED_IR, HDG_SMOOTH_BJACOBI), "learned_ir": (HDG_MIXED_IR, HDG_SMOOTH_MLP)}
+    legs = [lg for lg in (legs or args.sphere_legs.split(",")) if lg in table]
+    if weights is None:
+        legs = [lg for lg in legs if lg != "learned_ir"]
+    sols = {}
+    for name in legs:
+        prec, sm = table[name]
+        t = time.perf_counter()
         s = HdgSolver(hier, p, dt, 9.81, 5960.0, 0.0, 7.292e-5, 1.0, rtol=args.rtol, precision=prec,
                       smoother=sm, max_rhs=nb, krylov=2, maxit=200, p1_tail_max=0,
                       use_graph=0 if args.no_graph else 1, ir_inner_rtol=args.ir_inner_rtol)
         if sm == HDG_SMOOTH_MLP:
             s.mlp_set_weights(*weights)
         tuned = s.autotune(nb)
-        lam, rhat, q = s.trace_zeros(nb), s.trace_zeros(nb), s.cell_zeros(nb)
+        torch.cuda.synchronize()
+        tsetup = time.perf_counter() - t
+        step, lam, q = _step_fn(s, r, nb)
+        for _ in range(warmup):
+            step()
+        el, infos, ev = _timed(step, run_steps)
+        rec = {"value": round(run_steps * nb / el, 3), "unit": "solves/s",
+               "ms_per_step": round(1e3 * el / run_steps, 3), "step_ms_events": ev,
+               "iters": float(np.mean([i.iters for inf in infos for i in inf])),
+               "refinements": float(np.mean([i.refinements for inf in infos for i in inf])),
+               "fallbacks": int(sum(i.fallbacks for inf in infos for i in inf)),
+               "rel_res_max": max(i.rel_res for inf in infos for i in inf), "tuning": tuned,
+               "setup_s": round(tsetup, 3)}
+        if name == instrument:
+            s.set_timing(TIMING_REPEAT)
+            step()
+            rec["stats"] = {(k, pr): s.kernel_stats(k, pr) for k in KERNEL_CLASSES for pr in (HDG_FP64, HDG_MIXED)}
+            s.set_timing(0)
+        sols[name] = (lam.clone(), q.clone())
+        out[name] = rec
+        log(f"[bench] sphere L{level} {name}: {rec['ms_per_step']} ms/step ({rec['value']} solves/s) "
+            f"iters={rec['iters']} setup={tsetup:.1f}s")
+        s.close()
+        del s, step, lam, q
+        torch.cuda.empty_cache()
+    if "fp64" in sols:
+        lf, qf = sols["fp64"]
+        for name in legs:
+            if name == "fp64":
+                continue
+            lm, qm = sols[name]
+            out[name]["diff_vs_fp64"] = {
+                "trace": ((lm - lf).norm() / lf.norm()).item(),
+                **{fld: ((qm[:, i] - qf[:, i]).norm() / qf[:, i].norm()).item() for i, fld in enumerate(("h", "u1", "u2"))}}
+            out[f"speedup_{name}_vs_fp64"] = round(out[name]["value"] / out["fp64"]["value"], 3)
+    del sols
+    torch.cuda.empty_cache()
+    return out
+
+
+def trajectory_leg(args, level=6, p=2, dt=1800.0, n_rhs=100, batch=16, seed=300):
+    """The level-6 sphere (81 920 cells), p = 2, dt = 1800 s, physics of the
+    sphere workloads: the right-hand sides are 100 consecutive states of a
+    smooth random balanced flow (|u| <= 20 m/s, h ~ 100 m, seed 300) advanced
+    by backward-Euler steps, each step one solve of this same stage through
+    the library (q_{n+1} solves the stage with right-hand side q_n, FP64,
+    rtol 1e-10).  The 100 right-hand sides are then solved in batches of 16
+    (six full batches and one with 4 right-hand sides and 12 zero columns) by
+    the FP64, mixed and mixed-with-refinement solvers."""
+    import torch
+
+    import hdg_inputs as hi
+    from paper_2004_09389_amd.hdg import HDG_FP64, HDG_MIXED, HDG_MIXED_IR, HdgSolver
+    hier = hi.icosphere_hierarchy(level, 6.371e6, level_coarse=3)
+    phys = (9.81, 5960.0, 0.0, 7.292e-5)
+    t0 = time.perf_counter()
+    q0 = hi.balanced_flow_sphere(hier.fine, p, seed, 7.292e-5, 9.81, device="cuda")
+    be = HdgSolver(hier, p, dt, *phys, rtol=1e-10, max_rhs=1, krylov=2)
+    states = [torch.from_numpy(q0[..., None]).to("cuda")]
+    its = []
+    for _ in range(n_rhs - 1):
+        qn, _, info = be.stage_solve(states[-1])
+        states.append(qn)
+        its.append(info[0].iters)
+    be.close()
+    R = torch.cat(states, dim=-1).contiguous()
+    tgen = time.perf_counter() - t0
+    out = {"workload": f"icosphere_L{level}_p{p}_dt{dt:g}_b{batch}_trajectory", "n_cell": hier.fine.n_cell,
+           "n_trace_dof": int(3 * (p + 1) * hier.fine.n_cell // 2), "n_rhs": n_rhs, "batch": batch,
+           "rtol": args.rtol,
+           "rhs": f"{n_rhs} consecutive backward-Euler states of a balanced flow (seed {seed}): "
+                  f"max |h| {R[:, 0].abs().max().item():.1f} m, generated in {tgen:.1f} s "
+                  f"({float(np.mean(its)):.1f} FP64 iterations per step at rtol 1e-10)"}
+    nbat = -(-n_rhs // batch)
+    batches = []
+    for k in range(nbat):
+        blk = R[..., k * batch:(k + 1) * batch]
+        if blk.shape[-1] < batch:
+            pad = torch.zeros(blk.shape[:-1] + (batch - blk.shape[-1],), dtype=blk.dtype, device=blk.device)
+            blk = torch.cat([blk, pad], dim=-1)
+        batches.append(blk.contiguous())
+    for name, prec in (("fp64", HDG_FP64), ("mixed", HDG_MIXED), ("mixed_ir", HDG_MIXED_IR)):
+        s = HdgSolver(hier, p, dt, *phys, 1.0, rtol=args.rtol, precision=prec, max_rhs=batch, krylov=2, maxit=200,
+                      p1_tail_max=0, use_graph=0 if args.no_graph else 1, ir_inner_rtol=args.ir_inner_rtol)
+        s.autotune(batch)
+        lam, rhat, q = s.trace_zeros(batch), s.trace_zeros(batch), s.cell_zeros(batch)
+        state = {"k": 0}
 
         def step():
-            s.condense(r, out=rhat)
+            b = batches[state["k"] % nbat]
+            state["k"] += 1
+            s.condense(b, out=rhat)
             lam.zero_()
             _, info = s.solve(rhat, lam)
-            s.recover(r, lam, out=q)
+            s.recover(b, lam, out=q)
             return info
-        step()
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        infos = [step() for _ in range(run_steps)]
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t
-        out[name] = {"value": round(run_steps * nb / el, 3), "unit": "solves/s",
-                     "ms_per_step": round(1e3 * el / run_steps, 3),
-                     "iters": float(np.mean([i.iters for inf in infos for i in inf])),
-                     "fallbacks": int(sum(i.fallbacks for inf in infos for i in inf)),
-                     "rel_res_max": max(i.rel_res for inf in infos for i in inf), "tuning": tuned}
-        log(f"[bench] sphere L{level} {name}: {out[name]['ms_per_step']} ms/step ({out[name]['value']} solves/s) "
-            f"iters={out[name]['iters']}")
+        for _ in range(nbat):
+            step()
+        el, infos, ev = _timed(step, nbat)
+        out[name] = {"value": round(n_rhs / el, 3), "unit": "solves/s", "ms_per_batch": round(1e3 * el / nbat, 3),
+                     "iters_per_batch": [int(max(i.iters for i in inf)) for inf in infos],
+                     "rel_res_max": max(i.rel_res for inf in infos for i in inf[:min(batch, n_rhs)])}
+        log(f"[bench] trajectory {name}: {out[name]['value']} solves/s, iterations {out[name]['iters_per_batch']}")
         s.close()
-        del s
-    for name in ("mixed", "mixed_ir", "learned_ir"):
-        if name in out and "fp64" in out:
-            out[f"speedup_{name}_vs_fp64"] = round(out[name]["value"] / out["fp64"]["value"], 3)
+    for name in ("mixed", "mixed_ir"):
+        out[f"speedup_{name}_vs_fp64"] = round(out[name]["value"] / out["fp64"]["value"], 3)
     return out
 
 
@@ -613,13 +758,223 @@ def dg_leg(args, p, n, run_steps=3):
     return out
 
 
+def cpu_baseline_sphere(level_full=7, level_sample=5, p=3, dt=3600.0, repeats=3):
+    """The FP64 CPU oracle on a bounded sample of the headline workload: the
+    level-5 sphere (1/16 of the level-7 cells) with the same p, dt, physics and
+    kind of right-hand side, single threaded (SuperLU is sequential and BLAS is
+    held to one thread).  Set-up (local blocks and the trace matrix) and the
+    sparse LU factorisation are timed apart from the per-right-hand-side work
+    (condensed right-hand side, the two triangular solves, recovery), as the
+    GPU's timed step excludes its own set-up; the per-solve rate is the median
+    of `repeats` solves scaled by the cell ratio (linear scaling, which flatters
+    the CPU: the LU fill grows faster than the unknowns)."""
+    import scipy.sparse.linalg as spla
+    from threadpoolctl import threadpool_limits
+
+    import hdg_inputs as hi
+    from oracle.hdg import HdgOracle
+
+    with threadpool_limits(limits=1):
+        mesh = hi.icosphere(level_sample, 6.371e6)
+        r = hi.smooth_rhs_sphere(mesh, p, 500)[..., 0]
+        t0 = time.perf_counter()
+        o = HdgOracle(mesh, p, dt, 9.81, 5960.0, 0.0, 7.292e-5)
+        t1 = time.perf_counter()
+        lu = spla.splu(o.S.tocsc())
+        t2 = time.perf_counter()
+        ts = []
+        for _ in range(repeats):
+            t3 = time.perf_counter()
+            o.recover(r, lu.solve(o.rhat(r)))
+            ts.append(time.perf_counter() - t3)
+        host = host_info()
+    t = float(np.median(ts))
+    scale = 4.0 ** (level_full - level_sample)
+    return {"value": 1.0 / (t * scale), "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": f"{repeats} solves on the level-{level_sample} sphere (p={p}, dt={dt:g} s, same physics, a "
+                      f"smooth 3-D Fourier right-hand side; {mesh.n_cell} cells, {o.n_trace} trace unknowns): median "
+                      f"{t:.3f} s per solve after a {t2 - t1:.2f} s LU factorisation, scaled x{scale:.0f} by cells "
+                      f"to the level-{level_full} sphere",
+            "setup_s": round(t1 - t0, 3), "factor_s": round(t2 - t1, 3), "solve_s": float(f"{t:.6g}"),
+            "value_incl_factor": 1.0 / ((t + t2 - t1) * scale), "host": host}
+
+
+def train_weights(args, hier, p, dt, f0, nb, seed_init=0):
+    """Train the learned smoother once on the GPU on a context of the given
+    torus (random initial errors, seeds 1000+; not part of any timed step)."""
+    import hdg_inputs as hi
+    from paper_2004_09389_amd.hdg import HDG_MIXED, HDG_SMOOTH_MLP, HdgSolver
+    from paper_2004_09389_amd.learned import train
+    s = HdgSolver(hier, p, dt, 1.0, 1.0, f0, 0.0, 1.0, precision=HDG_MIXED, smoother=HDG_SMOOTH_MLP, max_rhs=nb,
+                  krylov=2, nu_pre=args.learned_nu, nu_post=args.learned_nu)
+    W1, _ = hi.mlp_init(p + 1, 64, seed_init)
+    s.mlp_set_weights(W1.astype(np.float32), np.zeros((p + 1, 64), np.float32))
+    hist, tt = train(s, batches=args.train_batches, epochs=args.train_epochs, lr=3e-3)
+    W = s.mlp_get_weights()
+    info = {"seconds": round(tt, 3), "adam_steps": int(len(hist)), "errors_per_batch": int(nb),
+            "batches": args.train_batches, "loss_first": round(float(hist[0]), 4),
+            "loss_last": round(float(hist[-1]), 4), "seeds": f"1000-{1000 + args.train_batches - 1}",
+            "nu_pre_post": args.learned_nu, "mesh": f"torus {hier.fine.n} x {hier.fine.n}", "degree": p}
+    s.close()
+    log(f"[bench] trained the p={p} smoother in {tt:.2f}s: loss {hist[0]:.4f} -> {hist[-1]:.4f}")
+    return W, info
+
+
+def gain_leg(args, weights, seeds=range(2000, 2010)):
+    """The learned smoother against plain block-Jacobi on unseen right-hand
+    sides (seeds 2000-2009) of the 8x8 torus (p = 1, f = 0, Courant 4, iid) and
+    the 256x256 torus (p = 3, f = 1, Courant 8, Fourier fields): both with the
+    mixed-precision FGMRES and the same sweeps, to rtol 1e-8, one right-hand
+    side per solve; mean iterations and mean time per solve (HIP events)."""
+    import torch
+
+    import hdg_inputs as hi
+    from paper_2004_09389_amd.hdg import HDG_MIXED, HDG_SMOOTH_BJACOBI, HDG_SMOOTH_MLP, HdgSolver
+    out = {"rtol": 1e-8, "seeds": f"{seeds[0]}-{seeds[-1]}", "precision": "mixed"}
+    for label, n, coarse, p, dt, f0, kind in (("torus8x8_p1_f0_courant4", 8, 4, 1, 0.5, 0.0, "iid"),
+                                              ("torus256x256_p3_f1_courant8", 256, args.coarse, 3, 8.0 / 256, 1.0,
+                                               "fourier")):
+        hier = hi.torus_hierarchy(n, coarse)
+        W = weights.get(p)
+        if W is None:
+            W, _ = train_weights(args, hier, p, dt, f0, 8 if n <= 8 else 1)
+            weights[p] = W
+        rec = {}
+        for name, sm in (("block_jacobi", HDG_SMOOTH_BJACOBI), ("learned", HDG_SMOOTH_MLP)):
+            s = HdgSolver(hier, p, dt, 1.0, 1.0, f0, 0.0, 1.0, rtol=1e-8, precision=HDG_MIXED, smoother=sm, krylov=2,
+                          nu_pre=args.learned_nu, nu_post=args.learned_nu, p1_tail_max=0 if n > 8 else 4096,
+                          use_graph=0 if args.no_graph else 1)
+            if sm == HDG_SMOOTH_MLP:
+                s.mlp_set_weights(*W)
+            its, ms, falls = [], [], 0
+            for seed in seeds:
+                rr = (hi.iid_rhs(hier.fine, p, seed) if kind == "iid" else hi.fourier_rhs_torus(hier.fine, p, seed))
+                rd = torch.from_numpy(rr).to("cuda")
+                step, _, _ = _step_fn(s, rd, 1)
+                step()
+                _, infos, ev = _timed(step, 3)
+                its.append(infos[-1][0].iters)
+                falls += infos[-1][0].fallbacks
+                ms.append(ev["median"])
+            rec[name] = {"iters_mean": float(np.mean(its)), "ms_per_solve_mean": round(float(np.mean(ms)), 4),
+                         "iters": its, "fallbacks": falls}
+            s.close()
+        rec["iteration_gain"] = round(rec["block_jacobi"]["iters_mean"] - rec["learned"]["iters_mean"], 2)
+        rec["time_ratio_learned_over_bj"] = round(rec["learned"]["ms_per_solve_mean"] /
+                                                  rec["block_jacobi"]["ms_per_solve_mean"], 3)
+        out[label] = rec
+        log(f"[bench] gain {label}: iterations {rec['block_jacobi']['iters_mean']} -> {rec['learned']['iters_mean']}, "
+            f"time x{rec['time_ratio_learned_over_bj']}")
+    return out
+
+
+def torus_leg(args, trained):
+    """The 256x256 periodic torus (131 072 cells), g = H = 1, f = 1, Courant 8,
+    p = 3, smooth Fourier right-hand side, rtol 1e-8, one right-hand side per
+    step and a batch of 16: mixed precision, the learned smoother and plain FP64;
+    an instrumented pass of the mixed solver (per-kernel HIP events), the warm /
+    cold FP64 apply, and the error of every solver against the oracle's direct
+    solution of the 128x128 sample (the CPU rate of that sample is reported in
+    cpu_baseline.per_config)."""
+    import torch
+
+    import hdg_inputs as hi
+    from paper_2004_09389_amd.hdg import (HDG_FP64, HDG_MIXED, HDG_MIXED_IR, HDG_SMOOTH_BJACOBI,
+                                          HDG_SMOOTH_CHEBYSHEV, HDG_SMOOTH_MLP, HdgSolver)
+    p, n, nb = args.degree, args.n, args.nrhs
+    dt = 8.0 / n
+    hier = hi.torus_hierarchy(n, args.coarse)
+    mesh = hier.fine
+    rd = torch.from_numpy(hi.fourier_rhs_torus(mesh, p, 100, nrhs=nb)).to("cuda")
+    rb = torch.from_numpy(hi.fourier_rhs_torus(mesh, p, 200, nrhs=args.batch)).to("cuda") if args.batch > 1 else None
+    if not args.no_learned and p not in trained:
+        trained[p] = train_weights(args, hier, p, dt, 1.0, nb)
+    out = {"workload": f"torus{n}x{n}_p{p}_f1_courant8", "n_cell": mesh.n_cell,
+           "n_trace_dof": int(3 * (p + 1) * mesh.n_cell // 2), "nrhs": nb, "rtol": args.rtol,
+           "coarsest_p1": f"{args.coarse}x{args.coarse}"}
+    mixed_prec = HDG_MIXED if args.mixed_mode == "mixed" else HDG_MIXED_IR
+    legs = [("mixed", mixed_prec)] + ([] if args.no_learned else [("learned", mixed_prec)]) \
+        + ([] if args.no_fp64 else [("fp64", HDG_FP64)])
+    sols = {}
+    for name, prec in legs:
+        learned = name == "learned"
+
+        def make(nbm):
+            s = HdgSolver(hier, p, dt, 1.0, 1.0, 1.0, 0.0, 1.0, rtol=args.rtol, precision=prec,
+                          ir_inner_rtol=args.ir_inner_rtol, max_rhs=nbm,
+                          smoother=HDG_SMOOTH_MLP if learned else (HDG_SMOOTH_CHEBYSHEV if args.smoother == "chebyshev"
+                                                                   else HDG_SMOOTH_BJACOBI),
+                          **({"nu_pre": args.learned_nu, "nu_post": args.learned_nu} if learned else {}),
+                          krylov=2, maxit=200, p1_tail_max=args.tail_max, p1_nu=args.p1_nu,
+                          use_graph=0 if args.no_graph else 1)
+            if learned:
+                s.mlp_set_weights(*trained[p][0])
+                s.autotune(nbm)
+            return s
+        s = make(nb)
+        step, lam, q = _step_fn(s, rd, nb)
+        for _ in range(args.warmup):
+            step()
+        el, infos, ev = _timed(step, args.steps)
+        rec = {"value": round(args.steps * nb / el, 3), "unit": "solves/s",
+               "ms_per_step": round(1e3 * el / args.steps, 4), "step_ms_events": ev,
+               "iters": float(np.mean([i.iters for inf in infos for i in inf])),
+               "fallbacks": int(sum(i.fallbacks for inf in infos for i in inf)),
+               "rel_res_max": max(i.rel_res for inf in infos for i in inf)}
+        sols[name] = (lam.clone(), q.clone())
+        if name == "mixed":
+            xb = s.condense(rd)
+            a64, a32 = s.trace_apply(xb, HDG_FP64), s.trace_apply(xb, HDG_MIXED)
+            v64, v32 = s.mg_vcycle(xb, HDG_FP64), s.mg_vcycle(xb, HDG_MIXED)
+            rec["stages_vs_fp64"] = {"trace_apply_fp32_rows": ((a32 - a64).norm() / a64.norm()).item(),
+                                     "vcycle_mixed": ((v32 - v64).norm() / v64.norm()).item()}
+            s.set_timing(TIMING_REPEAT)
+            step()
+            st = {(k, pr): s.kernel_stats(k, pr) for k in KERNEL_CLASSES for pr in (HDG_FP64, HDG_MIXED)}
+            s.set_timing(0)
+            pname = {HDG_FP64: "fp64", HDG_MIXED: "mixed"}
+            rec["kernels"] = {f"{k}[{pname[pr]}]": {"launches": v[0], "avg_us": round(1e3 * v[1] / max(v[0], 1), 3),
+                                                   "GBps": round(v[2] / (v[1] / max(v[0], 1) / 1e3) / 1e9, 1)}
+                              for (k, pr), v in st.items() if v[0] > 0}
+            if not args.no_stream:
+                rec["apply_warm_vs_cold"] = apply_cache_check(s, xb)
+        s.close()
+        if rb is not None:
+            sb = make(args.batch)
+            stepb, _, _ = _step_fn(sb, rb, args.batch)
+            for _ in range(args.warmup):
+                stepb()
+            elb, infb, _ = _timed(stepb, args.steps)
+            rec["batched"] = {"nrhs": args.batch, "value": round(args.steps * args.batch / elb, 3),
+                              "ms_per_step": round(1e3 * elb / args.steps, 4),
+                              "iters": float(np.mean([i.iters for inf in infb for i in inf])),
+                              "rel_res_max": max(i.rel_res for inf in infb for i in inf)}
+            sb.close()
+        out[name] = rec
+        log(f"[bench] torus {name}: {rec['ms_per_step']} ms/step iters={rec['iters']}"
+            + (f" | batch {args.batch}: {rec['batched']['value']:.1f} solves/s" if "batched" in rec else ""))
+        torch.cuda.empty_cache()
+    if "fp64" in sols:
+        lf, qf = sols["fp64"]
+        for name in sols:
+            if name != "fp64":
+                lm, qm = sols[name]
+                out[name]["diff_vs_fp64"] = {"trace": ((lm - lf).norm() / lf.norm()).item(),
+                                             **{fld: ((qm[:, i] - qf[:, i]).norm() / qf[:, i].norm()).item()
+                                                for i, fld in enumerate(("h", "u1", "u2"))}}
+                out[f"speedup_{name}_vs_fp64"] = round(out[name]["value"] / out["fp64"]["value"], 3)
+    return out
+
+
 def main():
     args = parse()
+    if args.pmc_run or args.sphere_only:
+        args.no_cpu = args.no_traj = args.no_torus = args.no_gain = args.no_small = True
+        args.no_lf = args.no_imex = args.no_dg = True
     if args.pmc_run:
-        args.no_fp64, args.no_cpu, args.batch = True, True, 0
-        args.no_learned, args.headline, args.no_lf = True, "mixed", True
+        args.no_stream = True
     if args.no_learned:
-        args.headline = "mixed"
+        args.sphere_legs = ",".join(lg for lg in args.sphere_legs.split(",") if lg != "learned_ir")
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; a multi-GPU run is not provided "
                                    "(right-hand sides would shard across GPUs with no communication)"}))
@@ -628,164 +983,37 @@ def main():
     import torch
 
     import hdg_inputs as hi
-    from paper_2004_09389_amd.hdg import (HDG_FP64, HDG_MIXED, HDG_MIXED_IR, HDG_SMOOTH_BJACOBI,
-                                          HDG_SMOOTH_CHEBYSHEV, HDG_SMOOTH_MLP, HdgSolver)
-    from paper_2004_09389_amd.learned import train
+    from paper_2004_09389_amd.hdg import HDG_FP64, HDG_MIXED
 
     torch.cuda.set_device(0)
-    p, n, nb = args.degree, args.n, args.nrhs
     if args.small_only:
         print(json.dumps({"small_leg": small_leg(args)}), flush=True)
         return
     if args.stream_only:
         print(json.dumps({"measured_GBps": measured_bandwidth()}), flush=True)
         return
-    if args.sphere_only:
-        print(json.dumps({"sphere_leg": sphere_leg(args, None, run_steps=args.steps)}), flush=True)
-        return
     if args.lf_only:
-        print(json.dumps({"lf_leg": lf_leg(args, p, n, nb, run_steps=args.steps)}), flush=True)
+        print(json.dumps({"lf_leg": lf_leg(args, args.degree, args.n, args.nrhs, run_steps=args.steps)}), flush=True)
         return
     if args.imex_only:
-        print(json.dumps({"imex_leg": imex_leg(args, n, p, run_steps=args.steps)}), flush=True)
+        print(json.dumps({"imex_leg": imex_leg(args, args.n, args.degree, run_steps=args.steps)}), flush=True)
         return
     if args.dg_only:
-        print(json.dumps({"dg_leg": dg_leg(args, p, n, run_steps=min(args.steps, 3))}), flush=True)
+        print(json.dumps({"dg_leg": dg_leg(args, args.degree, args.n, run_steps=min(args.steps, 3))}), flush=True)
         return
-    dt = 8.0 / n
-    t0 = time.perf_counter()
-    hier = hi.torus_hierarchy(n, args.coarse)
-    mesh = hier.fine
-    r = hi.fourier_rhs_torus(mesh, p, 100, nrhs=nb)
-    log(f"[bench] mesh+rhs {time.perf_counter() - t0:.1f}s cells={mesh.n_cell} p={p} nrhs={nb}")
-    rd = torch.from_numpy(r).to("cuda")
 
+    # ---- the learned smoother's weights: trained once on the GPU on the 256x256 torus (config 2 mesh)
     trained = {}
+    head = args.sphere_headline
+    if not args.no_learned and "learned_ir" in args.sphere_legs.split(","):
+        hier2 = hi.torus_hierarchy(args.n, args.coarse)
+        trained[3] = train_weights(args, hier2, 3, 8.0 / args.n, 1.0, 1)
+        del hier2
 
-    def make(prec, nb_override=None, learned=False):
-        t = time.perf_counter()
-        s = HdgSolver(hier, p, dt, 1.0, 1.0, 1.0, 0.0, 1.0, rtol=args.rtol, precision=prec,
-                      ir_inner_rtol=args.ir_inner_rtol, max_rhs=nb_override or nb,
-                      smoother=HDG_SMOOTH_MLP if learned else (HDG_SMOOTH_CHEBYSHEV if args.smoother == "chebyshev"
-                                                               else HDG_SMOOTH_BJACOBI),
-                      **({"nu_pre": args.learned_nu, "nu_post": args.learned_nu} if learned else {}),
-                      krylov=2, maxit=200, p1_tail_max=args.tail_max, p1_nu=args.p1_nu,
-                      use_graph=0 if args.no_graph else 1)
-        torch.cuda.synchronize()
-        log(f"[bench] setup {'mixed' if prec else 'fp64'}{' learned' if learned else ''} "
-            f"{time.perf_counter() - t:.2f}s device={s.sizes.device_bytes / 2**30:.2f} GiB")
-        if learned:
-            if "W" not in trained:
-                # train once on random initial errors (seeds 1000+); not part of a step
-                W1, _ = hi.mlp_init(p + 1, 64, 0)
-                s.mlp_set_weights(W1.astype(np.float32), np.zeros((p + 1, 64), np.float32))
-                hist, tt = train(s, batches=args.train_batches, epochs=args.train_epochs, lr=3e-3)
-                trained["W"] = s.mlp_get_weights()
-                trained["info"] = {"seconds": round(tt, 3), "adam_steps": int(len(hist)),
-                                   "errors_per_batch": int(s.options.max_rhs), "batches": args.train_batches,
-                                   "loss_first": round(float(hist[0]), 4), "loss_last": round(float(hist[-1]), 4),
-                                   "seeds": f"1000-{1000 + args.train_batches - 1}",
-                                   "nu_pre_post": args.learned_nu}
-                log(f"[bench] trained the smoother in {tt:.2f}s: loss {hist[0]:.4f} -> {hist[-1]:.4f}")
-            else:
-                s.mlp_set_weights(*trained["W"])
-            tuned = s.autotune(nb_override or nb)
-            log(f"[bench] autotune: {tuned}")
-        return s, time.perf_counter() - t
-
-    def run(s, steps, timing=0, rhs=None, nbb=None):
-        rhs = rd if rhs is None else rhs
-        nbb = nb if nbb is None else nbb
-        lam = s.trace_zeros(nbb)
-        rhat = s.trace_zeros(nbb)
-        q = s.cell_zeros(nbb)
-        infos = []
-        if timing:
-            s.set_timing(timing)
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        ev[0].record()
-        for k in range(steps):
-            s.condense(rhs, out=rhat)
-            lam.zero_()
-            _, info = s.solve(rhat, lam)
-            s.recover(rhs, lam, out=q)
-            ev[k + 1].record()
-            infos.append(info)
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t
-        step_ms = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(steps)])
-        run.last_step_ms = {"median": round(float(np.median(step_ms)), 4),
-                            "p10": round(float(np.percentile(step_ms, 10)), 4),
-                            "p90": round(float(np.percentile(step_ms, 90)), 4), "steps": int(steps)}
-        return el, infos, lam, q
-
-    results = {}
-    mixed_prec = HDG_MIXED if args.mixed_mode == "mixed" else HDG_MIXED_IR
-    legs = [("mixed", mixed_prec)] + ([] if args.no_learned else [("learned", mixed_prec)]) \
-        + ([] if args.no_fp64 else [("fp64", HDG_FP64)])
-    classes = ("apply", "sweep", "residual", "condense", "recover", "mlp")
-    for name, prec in legs:
-        s, tsetup = make(prec, learned=name == "learned")
-        run(s, args.warmup)
-        el, infos, lam, q = run(s, args.steps)
-        its = [i.iters for inf in infos for i in inf]
-        res = max(i.rel_res for inf in infos for i in inf)
-        rec = dict(el=el, its=float(np.mean(its)), res=res, lam=lam.clone(), q=q.clone(), setup=tsetup,
-                   step_ms=dict(run.last_step_ms),
-                   refinements=float(np.mean([i.refinements for inf in infos for i in inf])),
-                   fallbacks=int(sum(i.fallbacks for inf in infos for i in inf)))
-        if name == "mixed":
-            # error of each reduced-precision stage against its FP64 counterpart (same context)
-            xb = s.condense(rd)
-            a64, a32 = s.trace_apply(xb, HDG_FP64), s.trace_apply(xb, HDG_MIXED)
-            v64, v32 = s.mg_vcycle(xb, HDG_FP64), s.mg_vcycle(xb, HDG_MIXED)
-            rec["stages"] = {"trace_apply_fp32_rows": ((a32 - a64).norm() / a64.norm()).item(),
-                             "vcycle_mixed": ((v32 - v64).norm() / v64.norm()).item()}
-        if name == args.headline:
-            # instrumented pass: the same steps again, every launch of the
-            # instrumented kernel classes bracketed by HIP events on its stream
-            run(s, args.steps, timing=TIMING_REPEAT)
-            rec["stats"] = {(k, pr): s.kernel_stats(k, pr) for k in classes for pr in (HDG_FP64, HDG_MIXED)}
-            s.set_timing(False)
-            if not args.pmc_run and not args.no_stream:
-                rec["apply_cache"] = apply_cache_check(s, s.condense(rd))
-        if args.batch > 1 and not args.pmc_run:
-            sb, _ = make(prec, nb_override=args.batch, learned=name == "learned")
-            rb = torch.from_numpy(hi.fourier_rhs_torus(mesh, p, 200, nrhs=args.batch)).to("cuda")
-            run(sb, args.warmup, rhs=rb, nbb=args.batch)
-            elb, infb, _, _ = run(sb, args.steps, rhs=rb, nbb=args.batch)
-            rec["batched"] = {"nrhs": args.batch, "value": round(args.steps * args.batch / elb, 3),
-                              "ms_per_step": round(1e3 * elb / args.steps, 4),
-                              "iters": float(np.mean([i.iters for inf in infb for i in inf])),
-                              "rel_res_max": max(i.rel_res for inf in infb for i in inf)}
-            sb.close()
-            del sb
-        results[name] = rec
-        log(f"[bench] {name}: {args.steps} steps in {el:.3f}s ({1e3 * el / args.steps:.3f} ms/step) "
-            f"iters={np.mean(its):.1f} rel_res<={res:.2e}"
-            + (f" | batch {args.batch}: {rec['batched']['value']:.1f} solves/s" if "batched" in rec else ""))
-        s.close()
-        del s
-
-    sphere_out = sphere6_out = None
-    if not args.no_sphere and not args.pmc_run:
-        sphere_out = sphere_leg(args, trained.get("W") if p == 3 else None, run_steps=min(args.steps, 5))
-        sphere6_out = sphere_leg(args, None, run_steps=min(args.steps, 5), level=6, p=2, dt=1800.0, nb=16, seed=300)
-    lf_out = None
-    if not args.no_lf:
-        lf_out = lf_leg(args, p, n, nb, run_steps=min(args.steps, 10))
-    imex_out = None
-    if not args.no_imex and not args.pmc_run:
-        imex_out = imex_leg(args, n, p, run_steps=min(args.steps, 20))
-    small_out = None
-    if not args.no_small and not args.pmc_run:
-        small_out = small_leg(args)
-    dg_out = None
-    if not args.no_dg and not args.pmc_run:
-        dg_out = dg_leg(args, p, n, run_steps=min(args.steps, 3))
-
+    # ---- headline: the level-7 sphere, p = 3, 32 right-hand sides per step
+    sph = sphere_leg(args, trained[3][0] if 3 in trained else None, run_steps=args.steps, rhs_kind=args.sphere_rhs,
+                     instrument=head, warmup=args.warmup,
+                     legs=[head] if args.pmc_run else None)
     if args.pmc_run:
         # reference copy of known size for scaling the profiler's byte counters
         n_copy = 32 * 1024 * 1024
@@ -797,116 +1025,94 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] reference copy: {n_copy * 8} bytes read, {n_copy * 8} bytes written per launch")
         return
-
-    mx = results[args.headline]
+    mx = sph[head]
+    nb = sph["nrhs"]
     steps = args.steps
-    value = steps * nb / mx["el"]
-    # dominant kernel: largest total event time in the instrumented pass
-    st = mx["stats"]
+    st = mx.pop("stats")
     dom = max(st, key=lambda k: st[k][1])
     launches, ms, bpl = st[dom]
     avg_s = ms / max(launches, 1) / 1e3
     achieved = bpl / avg_s / 1e9 if avg_s > 0 else 0.0
     pname = {HDG_FP64: "fp64", HDG_MIXED: "mixed"}
     label = f"{dom[0]}[{pname[dom[1]]}]"
-    tr = measured_traffic(label) if (n == 256 and p == 3 and nb == 1) else None
-    roofline = {"bound": "hbm", "kernel": label, "achieved": round(achieved, 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+    tr = measured_traffic(label, sph["workload"])
+    roofline = {"bound": "hbm", "kernel": label, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": tr[0] if tr else None, "traffic_source": tr[1] if tr else None,
                 "avg_launch_us": round(avg_s * 1e6, 3), "launches": launches, "bytes_per_launch": bpl,
-                "timing": f"HIP events on the launch stream around every launch of the kernel in an "
-                          f"instrumented eager pass of the same steps right after the timed (graph-replayed) "
-                          f"pass; each instrumented launch issued {TIMING_REPEAT}x back to back per event pair"}
-    if "apply_cache" in mx:
-        roofline["apply_warm_vs_cold"] = mx["apply_cache"]
+                "workload": sph["workload"],
+                "timing": f"HIP events on the launch stream around every launch of the kernel in an instrumented "
+                          f"eager pass of one step of the headline solver right after the timed (graph-replayed) "
+                          f"steps; each instrumented launch issued {TIMING_REPEAT}x back to back per event pair "
+                          f"(every launch moves more than the 256 MB Infinity Cache)"}
+    kern = {f"{k}[{pname[pr]}]": {"launches": v[0], "total_ms": round(v[1], 3),
+                                  "avg_us": round(1e3 * v[1] / max(v[0], 1), 3),
+                                  "GBps": round(v[2] / (v[1] / max(v[0], 1) / 1e3) / 1e9, 1) if v[1] > 0 else None,
+                                  "frac": round(v[2] / (v[1] / max(v[0], 1) / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
+                                  if v[1] > 0 else None}
+            for (k, pr), v in st.items() if v[0] > 0}
     if not args.no_stream:
         bw = measured_bandwidth()
         best = max(bw.values())
         roofline.update({"peak_measured": best, "frac_measured": round(achieved / best, 4), "measured_GBps": bw})
-    kern = {f"{k}[{pname[pr]}]": {"launches": v[0], "total_ms": round(v[1], 3),
-                                  "avg_us": round(1e3 * v[1] / max(v[0], 1), 3),
-                                  "GBps": round(v[2] / (v[1] / max(v[0], 1) / 1e3) / 1e9, 1) if v[1] > 0 else None}
-            for (k, pr), v in st.items() if v[0] > 0}
+    p = 3
     out = {
         "metric": "trace solves/s to 1e-8 rel residual (learned/mixed vs FP64 MG), HBM GB/s",
-        "value": round(value, 3),
+        "value": mx["value"],
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": steps,
         "warmup": args.warmup,
-        "ms_per_step": round(1e3 * mx["el"] / steps, 4),
-        "step_ms_events": mx["step_ms"],
+        "ms_per_step": mx["ms_per_step"],
+        "step_ms_events": mx["step_ms_events"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64+f32+bf16",
         "data": "synthetic",
-        "config": {"workload": f"torus{n}x{n}_p{p}_f1_courant8", "degree": p, "n_cell": mesh.n_cell,
-                   "n_trace_dof": int(3 * (p + 1) * mesh.n_cell // 2),
-                   "n_cell_dof": int(3 * (p + 1) * (p + 2) // 2 * mesh.n_cell), "nrhs": nb,
-                   "rtol": args.rtol, "precision": args.mixed_mode,
-                   "coarsest_p1": f"{args.coarse}x{args.coarse}", "p1_tail_max": args.tail_max,
-                   "hip_graphs": not args.no_graph},
-        "smoother": "learned" if args.headline == "learned" else args.smoother,
-        "iters": mx["its"],
-        "fallbacks": mx["fallbacks"],
-        "setup_s": round(mx["setup"], 3),
+        "config": {"workload": sph["workload"], "mesh": "icosahedral sphere, refinement level 7, radius 6.371e6 m",
+                   "degree": p, "n_cell": sph["n_cell"], "n_trace_dof": sph["n_trace_dof"],
+                   "n_cell_dof": sph["n_cell_dof"], "nrhs": nb, "dt": 3600.0, "g": 9.81, "H": 5960.0,
+                   "coriolis": "2 Omega sin(latitude), Omega = 7.292e-5", "rtol": args.rtol,
+                   "solver": head, "rhs": sph["rhs"], "hip_graphs": not args.no_graph},
+        "iters": mx["iters"],
         "refinements": mx["refinements"],
-        "rel_res_max": mx["res"],
-        "dof_per_s": {"trace": round(value * 3 * (p + 1) * mesh.n_cell / 2, 1),
-                      "cell": round(value * 3 * (p + 1) * (p + 2) / 2 * mesh.n_cell, 1)},
+        "rel_res_max": mx["rel_res_max"],
+        "dof_per_s": {"trace": round(mx["value"] * sph["n_trace_dof"], 1),
+                      "cell": round(mx["value"] * sph["n_cell_dof"], 1)},
         "roofline": roofline,
         "kernels": kern,
+        "sphere_leg": sph,
     }
-    if "batched" in mx:
-        out["batched"] = mx["batched"]
-    for other in ("mixed", "learned"):
-        if other != args.headline and other in results:
-            o = results[other]
-            out[f"{other}_leg"] = {"value": round(steps * nb / o["el"], 3), "unit": "solves/s",
-                                   "ms_per_step": round(1e3 * o["el"] / steps, 4), "iters": o["its"],
-                                   "rel_res_max": o["res"], "fallbacks": o["fallbacks"],
-                                   **({"batched": o["batched"]} if "batched" in o else {})}
-    if "learned" in results:
-        out["training"] = trained["info"]
-    if "fp64" in results:
-        fp = results["fp64"]
-        out["fp64_baseline"] = {"value": round(steps * nb / fp["el"], 3), "unit": "solves/s",
-                                "ms_per_step": round(1e3 * fp["el"] / steps, 4), "step_ms_events": fp["step_ms"],
-                                "iters": fp["its"], "rel_res_max": fp["res"]}
-        if "batched" in fp:
-            out["fp64_baseline"]["batched"] = fp["batched"]
-        out["speedup_vs_fp64"] = round(fp["el"] / mx["el"], 3)
-        d = (mx["lam"] - fp["lam"]).norm().item() / fp["lam"].norm().item()
-        out["lam_rel_diff_vs_fp64"] = d
-        if "stages" in results.get("mixed", {}):
-            mq, fq = results["mixed"]["q"], fp["q"]
-            out["precision_report"] = {
-                **results["mixed"]["stages"],
-                "solution_trace_mixed": ((results["mixed"]["lam"] - fp["lam"]).norm() / fp["lam"].norm()).item(),
-                **{f"solution_{f}_mixed": ((mq[:, i] - fq[:, i]).norm() / fq[:, i].norm()).item()
-                   for i, f in enumerate(("h", "u1", "u2"))},
-                "note": "relative L2 differences of the mixed path against the FP64 path at each stage: "
-                        "FP32 operator rows, the mixed V-cycle (FP32 rows, BF16 smoother rows, FP32 block "
-                        "inverses) and the end-to-end solution at rtol; condense and recover are FP64 in both"}
-    if lf_out is not None:
-        out["lf_leg"] = lf_out
-    if imex_out is not None:
-        out["imex_leg"] = imex_out
-    if dg_out is not None:
-        out["dg_leg"] = dg_out
-    if small_out is not None:
-        out["small_leg"] = small_out
-    if sphere_out is not None:
-        out["sphere_leg"] = sphere_out
-        out["sphere_l6_leg"] = sphere6_out
+    if "fp64" in sph:
+        out["fp64_baseline"] = {k: sph["fp64"][k] for k in ("value", "unit", "ms_per_step", "step_ms_events", "iters")}
+        out["speedup_vs_fp64"] = sph.get(f"speedup_{head}_vs_fp64")
+    if 3 in trained:
+        out["training"] = trained[3][1]
+    if not args.no_traj:
+        out["trajectory_leg"] = trajectory_leg(args)
+    if not args.no_torus:
+        out["torus_leg"] = torus_leg(args, trained)
+    if not args.no_gain and not args.no_learned:
+        out["gain_leg"] = gain_leg(args, {pp: w[0] for pp, w in trained.items()})
+    if not args.no_small:
+        out["small_leg"] = small_leg(args)
+    if not args.no_lf:
+        out["lf_leg"] = lf_leg(args, args.degree, args.n, args.nrhs, run_steps=min(args.steps, 10))
+    if not args.no_imex:
+        out["imex_leg"] = imex_leg(args, args.n, args.degree, run_steps=min(args.steps, 20))
+    if not args.no_dg:
+        out["dg_leg"] = dg_leg(args, args.degree, args.n, run_steps=min(args.steps, 3))
     if not args.no_cpu:
         log("[bench] cpu oracle baseline ...")
-        out["cpu_baseline"], sample = cpu_baseline(n, p, dt)
-        out["cpu_baseline"]["per_config"] = oracle_per_config()
+        out["cpu_baseline"] = cpu_baseline_sphere()
+        torus_cpu, sample = cpu_baseline(args.n, args.degree, 8.0 / args.n)
+        out["cpu_baseline"]["per_config"] = {"torus256x256_p3_courant8": torus_cpu, **oracle_per_config()}
         out["error_vs_oracle"] = {
-            "sample": f"{sample[0]}x{sample[0]} torus, p={p}, same dt and f, right-hand side seed 100, rtol {args.rtol}",
-            **errors_vs_oracle(sample, p, dt, args.rtol, args.coarse, trained.get("W"))}
+            "sample": f"{sample[0]}x{sample[0]} torus, p={args.degree}, f = 1, Courant 8, right-hand side seed 100, "
+                      f"rtol {args.rtol}",
+            **errors_vs_oracle(sample, args.degree, 8.0 / args.n, args.rtol, args.coarse,
+                               trained[3][0] if 3 in trained else None)}
     print(json.dumps(out), flush=True)
 
 

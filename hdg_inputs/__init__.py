@@ -8,11 +8,13 @@ arithmetic: no quadrature, no basis, no operator, no topology beyond the
 cell->vertex lists that define a mesh.
 """
 from .mesh import Mesh, Hierarchy, torus, torus_hierarchy, icosphere, icosphere_hierarchy
-from .rhs import n_loc, ref_nodes, iid_rhs, fourier_rhs_torus, smooth_rhs_sphere, cell_frames, mlp_init, iid_trace
+from .rhs import (n_loc, ref_nodes, iid_rhs, fourier_rhs_torus, smooth_rhs_sphere, balanced_flow_sphere, cell_frames,
+                  mlp_init, iid_trace)
 from .vortex import Vortex, vortex_coefficients, paper_time_step
 
 __all__ = [
     "Mesh", "Hierarchy", "torus", "torus_hierarchy", "icosphere", "icosphere_hierarchy",
-    "n_loc", "ref_nodes", "iid_rhs", "fourier_rhs_torus", "smooth_rhs_sphere", "cell_frames", "mlp_init", "iid_trace",
+    "n_loc", "ref_nodes", "iid_rhs", "fourier_rhs_torus", "smooth_rhs_sphere", "balanced_flow_sphere", "cell_frames",
+    "mlp_init", "iid_trace",
     "Vortex", "vortex_coefficients", "paper_time_step",
 ]

@@ -87,22 +87,56 @@ def fourier_rhs_torus(mesh: Mesh, p: int, seed: int, nrhs: int = 1,
     return out
 
 
+def _cos_sum(x, modes, scale, device=None, chunk=1 << 16):
+    """sum_m amp_m cos(scale k_m . x + phase_m) at the points x (..., d): with
+    device (a torch device) the sums are evaluated there in float64, in chunks
+    of points; the modes come from the caller's numpy generator either way."""
+    k, amp, ph = modes
+    if device is None:
+        return np.cos(scale * np.einsum("...d,md->...m", x, k) + ph) @ amp
+    import torch
+    flat = x.reshape(-1, x.shape[-1])
+    kt = torch.as_tensor(k, dtype=torch.float64, device=device)
+    at = torch.as_tensor(amp, dtype=torch.float64, device=device)
+    pt = torch.as_tensor(ph, dtype=torch.float64, device=device)
+    out = np.empty(flat.shape[0])
+    for i in range(0, flat.shape[0], chunk):
+        xt = torch.as_tensor(flat[i:i + chunk], dtype=torch.float64, device=device)
+        out[i:i + chunk] = (torch.cos(scale * (xt @ kt.T) + pt) @ at).cpu().numpy()
+    return out.reshape(x.shape[:-1])
+
+
+def _sin_grad_sum(x, modes, scale, device=None, chunk=1 << 16):
+    """Gradient of sum_m amp_m cos(scale k_m . x + phase_m): -sum_m amp_m scale k_m sin(...)."""
+    k, amp, ph = modes
+    if device is None:
+        s = np.sin(scale * np.einsum("...d,md->...m", x, k) + ph) * amp
+        return -scale * s @ k
+    import torch
+    flat = x.reshape(-1, x.shape[-1])
+    kt = torch.as_tensor(k, dtype=torch.float64, device=device)
+    at = torch.as_tensor(amp, dtype=torch.float64, device=device)
+    pt = torch.as_tensor(ph, dtype=torch.float64, device=device)
+    out = np.empty(flat.shape)
+    for i in range(0, flat.shape[0], chunk):
+        xt = torch.as_tensor(flat[i:i + chunk], dtype=torch.float64, device=device)
+        out[i:i + chunk] = (-scale * (torch.sin(scale * (xt @ kt.T) + pt) * at) @ kt).cpu().numpy()
+    return out.reshape(x.shape)
+
+
 def smooth_rhs_sphere(mesh: Mesh, p: int, seed: int, nrhs: int = 1,
                       n_modes: int = 64, kmax: int = 8,
-                      h_scale: float = 100.0, u_scale: float = 20.0) -> np.ndarray:
+                      h_scale: float = 100.0, u_scale: float = 20.0, device=None) -> np.ndarray:
     """Smooth random fields on the sphere: 3-D Fourier sums in x / radius,
     the vector one projected onto each cell's frame; height scaled to max
-    |h| = h_scale, velocity to max |u| = u_scale.  (n_cell, 3, n_loc, nrhs)."""
+    |h| = h_scale, velocity to max |u| = u_scale.  (n_cell, 3, n_loc, nrhs).
+    device: evaluate the sums with torch on that device (same modes)."""
     rng = np.random.default_rng(seed)
     x = node_coords(mesh, p) / mesh.radius
     e1, e2, _ = cell_frames(mesh)
     out = np.zeros((mesh.n_cell, 3, n_loc(p), nrhs))
     for r in range(nrhs):
-        fields = []
-        for _ in range(4):
-            k, amp, ph = _fourier_modes(rng, n_modes, kmax, 3)
-            arg = np.pi * np.einsum("cnd,md->cnm", x, k) + ph
-            fields.append(np.cos(arg) @ amp)
+        fields = [_cos_sum(x, _fourier_modes(rng, n_modes, kmax, 3), np.pi, device) for _ in range(4)]
         h = fields[0]
         vec = np.stack(fields[1:], -1)
         u1 = np.einsum("cnd,cd->cn", vec, e1)
@@ -111,6 +145,36 @@ def smooth_rhs_sphere(mesh: Mesh, p: int, seed: int, nrhs: int = 1,
         umax = np.sqrt(u1 ** 2 + u2 ** 2).max()
         out[:, 1, :, r] = u1 * (u_scale / umax)
         out[:, 2, :, r] = u2 * (u_scale / umax)
+    return out
+
+
+def balanced_flow_sphere(mesh: Mesh, p: int, seed: int, omega: float, g: float,
+                         u_max: float = 20.0, n_modes: int = 64, kmax: int = 16, device=None) -> np.ndarray:
+    """A smooth random flow in linear balance on the sphere, at the DG nodes:
+    streamfunction psi = a sum of n_modes random 3-D Fourier modes in x / radius
+    (amplitudes N(0,1) |k|^-2, uniform phases), velocity u = n x grad_s psi
+    (n the outward unit normal, grad_s the tangential gradient) scaled so that
+    max |u| = u_max, height h = f psi / g with f = 2 omega z / |x| (the linear
+    balance f n x u = -g grad h with f taken locally constant), the velocity
+    projected onto each cell's frame.  (n_cell, 3, n_loc): (h, u1, u2)."""
+    rng = np.random.default_rng(seed)
+    R = mesh.radius
+    X = node_coords(mesh, p)
+    x = X / R
+    modes = _fourier_modes(rng, n_modes, kmax, 3)
+    psi = _cos_sum(x, modes, np.pi, device)
+    grad = _sin_grad_sum(x, modes, np.pi, device) / R          # d psi / d X
+    nrm = X / np.linalg.norm(X, axis=-1, keepdims=True)
+    gs = grad - np.sum(grad * nrm, axis=-1, keepdims=True) * nrm
+    u = np.cross(nrm, gs)
+    scale = u_max / np.linalg.norm(u, axis=-1).max()
+    psi, u = psi * scale, u * scale
+    f = 2.0 * omega * nrm[..., 2]
+    e1, e2, _ = cell_frames(mesh)
+    out = np.zeros((mesh.n_cell, 3, n_loc(p)))
+    out[:, 0] = f * psi / g
+    out[:, 1] = np.einsum("cnd,cd->cn", u, e1)
+    out[:, 2] = np.einsum("cnd,cd->cn", u, e2)
     return out
 
 
