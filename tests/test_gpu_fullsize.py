@@ -5,7 +5,8 @@ benchmark uses, against the FP64 oracle built on the same mesh.
   (up to 786 432 trace unknowns), coarsest P1 level 32 x 32, tail kernel off,
   FGMRES: every entry of rhat, S x, the V-cycle and the recovered fields is
   compared with the oracle; solves are certified by the oracle's own true
-  residual.
+  residual, and at p = 1 (and p = 3 on the 128 x 128 square) compared element
+  by element with the oracle's direct solution.
 * icosahedral sphere level 6 (81920 cells), p = 2, rotating, dt = 1800 s,
   16 right-hand sides per batch.
 * icosahedral sphere level 7 (327680 cells), p = 3, dt = 3600 s, 32
@@ -40,6 +41,12 @@ def _torus256(p):
         lambda nb, seed: hi.fourier_rhs_torus(hier.fine, p, seed, nrhs=nb)
 
 
+def _torus(n, p):
+    hier = hi.torus_hierarchy(n, 32)
+    return hier, dict(degree=p, dt=8.0 / n, g=1.0, H=1.0, f0=1.0, omega=0.0), \
+        lambda nb, seed: hi.fourier_rhs_torus(hier.fine, p, seed, nrhs=nb)
+
+
 def _sphere(level, p, dt):
     hier = hi.icosphere_hierarchy(level, HMS, level_coarse=3)
 
@@ -57,6 +64,7 @@ CONFIGS = {
     "torus256_p1": (lambda: _torus256(1), 1),
     "torus256_p2": (lambda: _torus256(2), 1),
     "torus256_p3": (lambda: _torus256(3), 1),
+    "torus128_p3": (lambda: _torus(128, 3), 1),
     "sphere_L6_p2": (lambda: _sphere(6, 2, 1800.0), 16),
     "sphere_L7_p3": (lambda: _sphere(7, 3, 3600.0), 32),
 }
@@ -144,6 +152,45 @@ def test_solve_full_size_certified(name, precision):
         assert info[k].status == 0
         assert res <= rtol * (1 + 1e-3)
     print(f"[fullsize] {name} {precision}: iters {[i.iters for i in info][:4]}... worst oracle residual {worst:.3e}")
+    s.close()
+
+
+@functools.lru_cache(maxsize=None)
+def direct_solution(name, column=0):
+    """The oracle's direct solution (SuperLU on its own condensed trace system,
+    then its recovery) of one right-hand side of the configuration's batch."""
+    import time
+    _, _, r, _, o, _ = problem(name)
+    t = time.perf_counter()
+    q, lam = o.solve(r[..., column])
+    print(f"[fullsize] {name} oracle direct solve {time.perf_counter() - t:.1f}s", flush=True)
+    return q, lam
+
+
+@pytest.mark.parametrize("name,precision,rtol,tol", [
+    ("torus256_p1", "fp64", 1e-12, 1e-10),
+    ("torus256_p1", "mixed", 1e-11, 1e-8),
+    ("torus256_p1", "mixed_ir", 1e-11, 1e-8),
+    ("torus128_p3", "fp64", 1e-12, 1e-10),
+    ("torus128_p3", "mixed", 1e-11, 1e-8),
+])
+def test_solution_equals_oracle_direct_solve(name, precision, rtol, tol):
+    """Element by element against the oracle's direct (SuperLU) solution: the
+    256 x 256 torus at p = 1 (393 216 trace unknowns) and, its direct solve
+    being too slow for a test at 256 x 256, the 128 x 128 torus at p = 3
+    (196 608): FP64 to 1e-10, the mixed paths to 1e-8, every field and the
+    trace separately (the benchmark's launch configuration)."""
+    from paper_2004_09389_amd.hdg import HDG_FP64, HDG_MIXED, HDG_MIXED_IR
+    _, _, r, _, _, _ = problem(name)
+    q_ref, lam_ref = direct_solution(name)
+    s = solver(name, precision={"fp64": HDG_FP64, "mixed": HDG_MIXED, "mixed_ir": HDG_MIXED_IR}[precision], rtol=rtol,
+               max_rhs=1)
+    q, lam, info = s.step(to_dev(r[..., :1]))
+    q, lam = host(q)[..., 0], host(lam)[..., 0].ravel()
+    assert info[0].status == 0
+    errs = {"trace": rel(lam, lam_ref), **{f: rel(q[:, i], q_ref[:, i]) for i, f in enumerate(("h", "u1", "u2"))}}
+    print(f"[fullsize] {name} {precision} vs direct solve: {errs}", flush=True)
+    assert max(errs.values()) < tol, errs
     s.close()
 
 
