@@ -5,7 +5,7 @@
 #include <map>
 #include <unordered_map>
 
-#include "hdg_internal.h"
+#include "hdg_host.h"
 
 namespace hdg {
 

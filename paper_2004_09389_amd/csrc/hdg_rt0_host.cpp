@@ -13,7 +13,7 @@
 #include <cmath>
 #include <map>
 
-#include "hdg_internal.h"
+#include "hdg_host.h"
 
 namespace hdg {
 
