@@ -69,4 +69,21 @@ __device__ __forceinline__ int loc_trace(int i, int a, int rev) {
     return i * NU * m + (a - k) + (rev ? P - k : k);
 }
 
+// Sum init + f(0) + ... + f(cnt - 1) in that order, U terms at a time: the U
+// calls of a group are made first (index clamped into the list) so that their
+// loads are in flight together, then the live ones are added.  For gathers
+// whose row length is known only at run time.
+template <int U, typename F>
+__device__ __forceinline__ double acc_row(double init, int cnt, F &&f) {
+    double s = init;
+    for (int k0 = 0; k0 < cnt; k0 += U) {
+        double t[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) t[u] = f(min(k0 + u, cnt - 1));
+#pragma unroll
+        for (int u = 0; u < U; ++u) s = k0 + u < cnt ? s + t[u] : s;
+    }
+    return s;
+}
+
 }  // namespace hdg

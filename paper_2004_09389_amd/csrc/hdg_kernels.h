@@ -151,8 +151,9 @@ void launch_to_f32(int64_t n, const double *src, float *dst, hipStream_t s);
 void launch_p1_first(int n, int nb, const double *dinv, double omega, const double *b, double *x, hipStream_t s);
 void launch_p1_pre2(int n, int W, int nb, const int *col, const double *val, const double *diag,
                     const double *dinv, double omega, const double *b, double *x, hipStream_t s);
+// y = x + w D^-1 (b - A x); with xc != nullptr, x is first updated in place to x + P xc
 void launch_p1_sweep(int n, int W, int nb, const int *col, const double *val, const double *diag,
-                     const double *dinv, double omega, const double *b, const double *x, const double *xc,
+                     const double *dinv, double omega, const double *b, double *x, const double *xc,
                      const int *parents, double *y, hipStream_t s);
 void launch_p1_resid(int n, int W, int nb, const int *col, const double *val, const double *diag,
                      const double *b, const double *x, double *y, hipStream_t s);

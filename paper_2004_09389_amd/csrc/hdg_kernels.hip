@@ -534,20 +534,35 @@ __global__ __launch_bounds__(256) void k_sweep(int ne, int nb, const MT *__restr
 
 // Restriction pi^T of a trace residual onto the P1 vertices:
 // rc[v] = sum over facet ends at v of sum_k w_end(k) res[e][k], w_0 = 1 - k/p, w_1 = k/p.
+// The facet ends of a vertex (5-7 on these meshes) are taken up to eight at a
+// time with every load in flight together (index clamped into the list, the
+// surplus ends not added; the sum keeps its order).
 template <int M, typename VT>
 __global__ void k_restrict_trace(int nv, int nb, const int *__restrict__ vf_row, const int *__restrict__ vf_col,
                                  const VT *__restrict__ res, double *__restrict__ rc) {
-    constexpr int P = M - 1;
+    constexpr int P = M - 1, U = 8;
     const int t = xcd_block() * blockDim.x + threadIdx.x;
     if (t >= nv * nb) return;
     const int v = t / nb, r = t - v * nb;
+    const int c0 = vf_row[v], cnt = vf_row[v + 1] - c0;
     double acc = 0.0;
-    for (int c = vf_row[v]; c < vf_row[v + 1]; ++c) {
-        const int code = vf_col[c], e = code >> 1, end = code & 1;
+    for (int k0 = 0; k0 < cnt; k0 += U) {
+        int code[U];
+        double val[U][M];
 #pragma unroll
-        for (int k = 0; k < M; ++k) {
-            const double w = end ? (double)k / P : 1.0 - (double)k / P;
-            acc += w * (double)res[((size_t)e * M + k) * nb + r];
+        for (int u = 0; u < U; ++u) code[u] = vf_col[c0 + min(k0 + u, cnt - 1)];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int k = 0; k < M; ++k) val[u][k] = (double)res[((size_t)(code[u] >> 1) * M + k) * nb + r];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int end = code[u] & 1;
+#pragma unroll
+            for (int k = 0; k < M; ++k) {
+                const double w = end ? (double)k / P : 1.0 - (double)k / P;
+                acc = k0 + u < cnt ? acc + w * val[u][k] : acc;
+            }
         }
     }
     rc[(size_t)v * nb + r] = acc;
@@ -561,32 +576,42 @@ __global__ void k_restrict_trace(int nv, int nb, const int *__restrict__ vf_row,
 // level.  Large levels run as one kernel per step; all levels with at most
 // P1_TAIL_MAX vertices (and the dense solve) run inside one single-workgroup
 // kernel, because at that size a launch costs more than the work.
+// The per-level kernels hand each XCD one contiguous range of vertices, so the
+// neighbour rows that nearby vertices share are fetched into one L2.
 
 // Level matrices are stored off-diagonal in ELL form, [W][n] column-major
 // (padding entries point at the row itself with value 0), so the neighbour
-// indices of a row are independent coalesced loads.
+// indices of a row are independent coalesced loads.  WT > 0 fixes the width at
+// compile time (6 on the icosahedral and torus meshes), so a row's loads are
+// all issued before the first one is used; WT = 0 takes the width W at run time.
+template <int WT>
 __device__ __forceinline__ double p1_ax(int v, int n, int W, int nb, int r, const int *ell_col,
                                         const double *ell_val, const double *diag, const double *x) {
+    if (WT) W = WT;
     double s = diag[v] * x[(size_t)v * nb + r];
+#pragma unroll
     for (int k = 0; k < W; ++k) s += ell_val[(size_t)k * n + v] * x[(size_t)ell_col[(size_t)k * n + v] * nb + r];
     return s;
 }
 
 __global__ void k_p1_first(int n, int nb, const double *__restrict__ dinv, double omega,
                            const double *__restrict__ b, double *__restrict__ x) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int t = xcd_block() * blockDim.x + threadIdx.x;
     if (t >= n * nb) return;
     x[t] = omega * dinv[t / nb] * b[t];
 }
 
 // two sweeps from a zero guess: x1 = w D^-1 b, x2 = x1 + w D^-1 (b - A x1)
+template <int WT>
 __global__ void k_p1_pre2(int n, int W, int nb, const int *__restrict__ ell_col, const double *__restrict__ ell_val,
                           const double *__restrict__ diag, const double *__restrict__ dinv, double omega,
                           const double *__restrict__ b, double *__restrict__ x) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int t = xcd_block() * blockDim.x + threadIdx.x;
     if (t >= n * nb) return;
     const int v = t / nb, r = t - v * nb;
+    if (WT) W = WT;
     double ax = diag[v] * omega * dinv[v] * b[t];
+#pragma unroll
     for (int k = 0; k < W; ++k) {
         const int u = ell_col[(size_t)k * n + v];
         ax += ell_val[(size_t)k * n + v] * omega * dinv[u] * b[(size_t)u * nb + r];
@@ -595,45 +620,47 @@ __global__ void k_p1_pre2(int n, int W, int nb, const int *__restrict__ ell_col,
     x[t] = x1 + omega * dinv[v] * (b[t] - ax);
 }
 
-// y = x + w D^-1 (b - A x); with xc != nullptr the input is x + P xc (prolongation fused)
+// y = x + w D^-1 (b - A x)
+template <int WT>
 __global__ void k_p1_sweep(int n, int W, int nb, const int *__restrict__ ell_col, const double *__restrict__ ell_val,
                            const double *__restrict__ diag, const double *__restrict__ dinv, double omega,
-                           const double *__restrict__ b, const double *__restrict__ x, const double *__restrict__ xc,
-                           const int *__restrict__ parents, double *__restrict__ y) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+                           const double *__restrict__ b, const double *__restrict__ x, double *__restrict__ y) {
+    const int t = xcd_block() * blockDim.x + threadIdx.x;
     if (t >= n * nb) return;
     const int v = t / nb, r = t - v * nb;
-    auto xin = [&](int u) -> double {
-        double s = x[(size_t)u * nb + r];
-        if (xc) s += 0.5 * (xc[(size_t)parents[2 * u] * nb + r] + xc[(size_t)parents[2 * u + 1] * nb + r]);
-        return s;
-    };
-    double ax = 0.0;
-    for (int k = 0; k < W; ++k) ax += ell_val[(size_t)k * n + v] * xin(ell_col[(size_t)k * n + v]);
-    const double xv = xin(v);
-    ax += diag[v] * xv;
-    y[t] = xv + omega * dinv[v] * (b[t] - ax);
+    y[t] = x[t] + omega * dinv[v] * (b[t] - p1_ax<WT>(v, n, W, nb, r, ell_col, ell_val, diag, x));
 }
 
+// x += P xc: each vertex takes half of each of its two coarse parents (an
+// inherited vertex lists its parent twice)
+__global__ void k_p1_prolong(int n, int nb, const int *__restrict__ parents, const double *__restrict__ xc,
+                             double *__restrict__ x) {
+    const int t = xcd_block() * blockDim.x + threadIdx.x;
+    if (t >= n * nb) return;
+    const int v = t / nb, r = t - v * nb;
+    x[t] += 0.5 * (xc[(size_t)parents[2 * v] * nb + r] + xc[(size_t)parents[2 * v + 1] * nb + r]);
+}
+
+template <int WT>
 __global__ void k_p1_resid(int n, int W, int nb, const int *__restrict__ ell_col, const double *__restrict__ ell_val,
                            const double *__restrict__ diag, const double *__restrict__ b, const double *__restrict__ x,
                            double *__restrict__ y) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int t = xcd_block() * blockDim.x + threadIdx.x;
     if (t >= n * nb) return;
     const int v = t / nb, r = t - v * nb;
-    y[t] = b[t] - p1_ax(v, n, W, nb, r, ell_col, ell_val, diag, x);
+    y[t] = b[t] - p1_ax<WT>(v, n, W, nb, r, ell_col, ell_val, diag, x);
 }
 
-// bc[c] = sum over children of w * r[child]  (transpose of the interpolation)
+// bc[c] = sum over children of w * r[child]  (transpose of the interpolation); the
+// children (7 on the icosahedral hierarchy) are read eight at a time, all loads in flight
 __global__ void k_p1_restrict(int nc, int nb, const int *__restrict__ crow, const int *__restrict__ ccol,
                               const double *__restrict__ cw, const double *__restrict__ r,
                               double *__restrict__ bc) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int t = xcd_block() * blockDim.x + threadIdx.x;
     if (t >= nc * nb) return;
     const int c = t / nb, rr = t - c * nb;
-    double acc = 0.0;
-    for (int k = crow[c]; k < crow[c + 1]; ++k) acc += cw[k] * r[(size_t)ccol[k] * nb + rr];
-    bc[t] = acc;
+    const int k0 = crow[c];
+    bc[t] = acc_row<8>(0.0, crow[c + 1] - k0, [&](int k) { return cw[k0 + k] * r[(size_t)ccol[k0 + k] * nb + rr]; });
 }
 
 // x = Ainv b on the coarsest level when it is too large for the tail kernel:
@@ -687,14 +714,14 @@ __global__ __launch_bounds__(1024) void k_p1_tail(const P1Tail Targ, int nb) {
         for (int k = 1; k < T.nu; ++k) {
             for (int t = tid; t < N; t += nth) {
                 const int v = t / nb, r = t - v * nb;
-                y[t] = x[t] + w * L.dinv[v] * (L.b[t] - p1_ax(v, L.n, L.w, nb, r, L.col, L.val, L.diag, x));
+                y[t] = x[t] + w * L.dinv[v] * (L.b[t] - p1_ax<0>(v, L.n, L.w, nb, r, L.col, L.val, L.diag, x));
             }
             __syncthreads();
             double *tmp = x; x = y; y = tmp;
         }
         for (int t = tid; t < N; t += nth) {
             const int v = t / nb, r = t - v * nb;
-            y[t] = L.b[t] - p1_ax(v, L.n, L.w, nb, r, L.col, L.val, L.diag, x);
+            y[t] = L.b[t] - p1_ax<0>(v, L.n, L.w, nb, r, L.col, L.val, L.diag, x);
         }
         __syncthreads();
         const P1Lev &C = T.lev[l - 1];
@@ -1336,6 +1363,19 @@ __device__ __forceinline__ void load_raw(const T *__restrict__ p, T (&d)[RB]) {
     }
 }
 
+// RB consecutive values in their stored type, 16 bytes per store
+template <int RB, typename T>
+__device__ __forceinline__ void store_raw(T *__restrict__ p, const T (&d)[RB]) {
+    if constexpr (std::is_same<T, double>::value) {
+#pragma unroll
+        for (int q = 0; q < RB; q += 2) *reinterpret_cast<dbl2_t *>(p + q) = dbl2_t{d[q], d[q + 1]};
+    } else {
+#pragma unroll
+        for (int q = 0; q < RB; q += 4)
+            *reinterpret_cast<trace_flt4_t *>(p + q) = trace_flt4_t{d[q], d[q + 1], d[q + 2], d[q + 3]};
+    }
+}
+
 // y = S x or y = b - S x
 //
 // Latency: a lane requests its four neighbour ids and its own facet's values
@@ -1408,8 +1448,11 @@ __global__ __launch_bounds__(1024) void k_trace_apply_rb(int ne, int nb, const M
 }
 
 // the generalised sweep y = a0 x' + a1 z0 - a3 sum_j T_j x'_j + a2 xprev' (SweepCoef)
+// The FP32 sweep with bf16 rows is held to 80 registers (six waves per SIMD).
+template <typename MT, typename VT>
+constexpr int sweep_rb_waves() { return std::is_same<MT, __hip_bfloat16>::value && std::is_same<VT, float>::value ? 6 : 1; }
 template <int M, typename MT, typename VT, int RB>
-__global__ __launch_bounds__(1024) void k_sweep_rb(int ne, int nb, const MT *__restrict__ T,
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(sweep_rb_waves<MT, VT>(), 8))) void k_sweep_rb(int ne, int nb, const MT *__restrict__ T,
                                                    const int *__restrict__ nbr, const VT *__restrict__ x,
                                                    const VT *__restrict__ z0, const double *__restrict__ qc,
                                                    const int *__restrict__ fvert, SweepCoef cf,
@@ -1423,26 +1466,25 @@ __global__ __launch_bounds__(1024) void k_sweep_rb(int ne, int nb, const MT *__r
     const int el = threadIdx.x / tpf, r0 = (threadIdx.x - el * tpf) * RB, e = f0 + el;
     const bool live = e < ne;
     const size_t NE = (size_t)ne;
-    int id[4] = {0, 0, 0, 0};   // requested before the rows are staged
-    if (live)
+    // Neighbour ids (and, with a fused prolongation, their vertex ids) are
+    // requested before the rows are staged.  Neighbour values are held in the
+    // accumulation type (the same rounding as converting at the product), and
+    // the own facet's values are read node by node in the epilogue: both keep
+    // the register count, and so the number of waves in flight, up.
+    int id[4] = {0, 0, 0, 0}, iv[4][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+    if (live) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) id[j] = nbr[(size_t)j * NE + e];
+        if (qc)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                iv[j][0] = fvert[2 * id[j]];
+                iv[j][1] = fvert[2 * id[j] + 1];
+            }
+    }
     stage_rows<MT, G>(sm, T, f0, ne);
     __syncthreads();
     if (!live) return;
-    auto iterate = [&](int id, double (&xv)[M][RB]) {
-#pragma unroll
-        for (int k = 0; k < M; ++k) load_rb<RB>(x + ((size_t)id * M + k) * nb + r0, xv[k]);
-        if (qc) {
-            double q0[RB], q1[RB];
-            load_rb<RB>(qc + (size_t)fvert[2 * id] * nb + r0, q0);
-            load_rb<RB>(qc + (size_t)fvert[2 * id + 1] * nb + r0, q1);
-#pragma unroll
-            for (int k = 0; k < M; ++k)
-#pragma unroll
-                for (int q = 0; q < RB; ++q) xv[k][q] += p1_node<P>(k, q0[q], q1[q]);
-        }
-    };
     AT acc[M][RB];
 #pragma unroll
     for (int a = 0; a < M; ++a)
@@ -1450,8 +1492,27 @@ __global__ __launch_bounds__(1024) void k_sweep_rb(int ne, int nb, const MT *__r
         for (int q = 0; q < RB; ++q) acc[a][q] = 0;
 #pragma unroll 1
     for (int j = 0; j < 4; ++j) {   // one neighbour's values in flight at a time keeps the registers in bounds
-        double xv[M][RB];
-        iterate(j == 0 ? id[0] : j == 1 ? id[1] : j == 2 ? id[2] : id[3], xv);
+        const int f = j == 0 ? id[0] : j == 1 ? id[1] : j == 2 ? id[2] : id[3];
+        VT raw[M][RB];
+        AT xv[M][RB];
+#pragma unroll
+        for (int k = 0; k < M; ++k) load_raw<RB>(x + ((size_t)f * M + k) * nb + r0, raw[k]);
+        if (qc) {
+            const int v0 = j == 0 ? iv[0][0] : j == 1 ? iv[1][0] : j == 2 ? iv[2][0] : iv[3][0];
+            const int v1 = j == 0 ? iv[0][1] : j == 1 ? iv[1][1] : j == 2 ? iv[2][1] : iv[3][1];
+            double q0[RB], q1[RB];
+            load_rb<RB>(qc + (size_t)v0 * nb + r0, q0);
+            load_rb<RB>(qc + (size_t)v1 * nb + r0, q1);
+#pragma unroll
+            for (int k = 0; k < M; ++k)
+#pragma unroll
+                for (int q = 0; q < RB; ++q) xv[k][q] = (AT)((double)raw[k][q] + p1_node<P>(k, q0[q], q1[q]));
+        } else {
+#pragma unroll
+            for (int k = 0; k < M; ++k)
+#pragma unroll
+                for (int q = 0; q < RB; ++q) xv[k][q] = (AT)raw[k][q];
+        }
 #pragma unroll
         for (int a = 0; a < M; ++a)
 #pragma unroll
@@ -1459,33 +1520,96 @@ __global__ __launch_bounds__(1024) void k_sweep_rb(int ne, int nb, const MT *__r
                 const int c = (j * M + a) * M + k;
                 const AT w = lds_entry<MT>(sm + ((size_t)(c / V) * RB_FACETS + el) * V + c % V);
 #pragma unroll
-                for (int q = 0; q < RB; ++q) acc[a][q] += w * (AT)xv[k][q];
+                for (int q = 0; q < RB; ++q) acc[a][q] += w * xv[k][q];
             }
     }
-    double xe[M][RB];
-    iterate(e, xe);
-    double q0[RB], q1[RB];
+    double q0[RB], q1[RB], p0[RB], p1[RB];
+    if (qc) {
+        load_rb<RB>(qc + (size_t)fvert[2 * e] * nb + r0, q0);
+        load_rb<RB>(qc + (size_t)fvert[2 * e + 1] * nb + r0, q1);
+    }
     if (cf.xprev && cf.qcprev) {
-        load_rb<RB>(cf.qcprev + (size_t)fvert[2 * e] * nb + r0, q0);
-        load_rb<RB>(cf.qcprev + (size_t)fvert[2 * e + 1] * nb + r0, q1);
+        load_rb<RB>(cf.qcprev + (size_t)fvert[2 * e] * nb + r0, p0);
+        load_rb<RB>(cf.qcprev + (size_t)fvert[2 * e + 1] * nb + r0, p1);
     }
 #pragma unroll
     for (int a = 0; a < M; ++a) {
         const size_t o = ((size_t)e * M + a) * nb + r0;
-        double zv[RB], out[RB];
+        double xe[RB], zv[RB], out[RB];
+        load_rb<RB>(x + o, xe);
         load_rb<RB>(z0 + o, zv);
+        if (qc)
 #pragma unroll
-        for (int q = 0; q < RB; ++q) out[q] = sweep_combine(cf, xe[a][q], zv[q], (double)acc[a][q]);
+            for (int q = 0; q < RB; ++q) xe[q] += p1_node<P>(a, q0[q], q1[q]);
+#pragma unroll
+        for (int q = 0; q < RB; ++q) out[q] = sweep_combine(cf, xe[q], zv[q], (double)acc[a][q]);
         if (cf.xprev) {
             double pv[RB];
             load_rb<RB>(static_cast<const VT *>(cf.xprev) + o, pv);
             if (cf.qcprev)
 #pragma unroll
-                for (int q = 0; q < RB; ++q) pv[q] += p1_node<P>(a, q0[q], q1[q]);
+                for (int q = 0; q < RB; ++q) pv[q] += p1_node<P>(a, p0[q], p1[q]);
 #pragma unroll
             for (int q = 0; q < RB; ++q) out[q] = __builtin_fma(cf.a2, pv[q], out[q]);
         }
         store_rb<RB>(y + o, out);
+    }
+}
+
+// z0 = omega D^-1 r with RB consecutive right-hand sides per thread (16-byte
+// loads and stores of r, rs, rc and z0); the same arithmetic per entry as k_jacobi0,
+// so the two shapes give the same bits.
+template <int M, typename MT, typename RT, typename ZT, int RB>
+__global__ __launch_bounds__(256) void k_jacobi0_rb(int ne, int nb, const MT *__restrict__ Dw,
+                                                    const RT *__restrict__ r, const double *__restrict__ scale,
+                                                    RT *__restrict__ rs, ZT *__restrict__ rc, ZT *__restrict__ z0) {
+    using AT = typename Acc<MT>::type;
+    constexpr int V = Wide<MT>::V, C = M * M, G = padded(C, V) / V;
+    const int tpf = nb / RB;
+    const int t = xcd_block() * blockDim.x + threadIdx.x;
+    if (t >= ne * tpf) return;
+    const int e = t / tpf, r0 = (t - e * tpf) * RB;
+    const size_t NE = (size_t)ne;
+    double sc[RB];
+#pragma unroll
+    for (int q = 0; q < RB; ++q) sc[q] = scale ? (scale[r0 + q] != 0.0 ? 1.0 / scale[r0 + q] : 0.0) : 1.0;
+    ZT rz[M][RB];
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        const size_t o = ((size_t)e * M + k) * nb + r0;
+        RT v[RB];
+        load_raw<RB>(r + o, v);
+#pragma unroll
+        for (int q = 0; q < RB; ++q) {
+            v[q] = (RT)((double)v[q] * sc[q]);   // the scaled vector as stored
+            rz[k][q] = (ZT)v[q];                 // ... and as the V-cycle reads it
+        }
+        if (scale) store_raw<RB>(rs + o, v);
+        if (rc) store_raw<RB>(rc + o, rz[k]);
+    }
+    AT acc[M][RB];
+#pragma unroll
+    for (int a = 0; a < M; ++a)
+#pragma unroll
+        for (int q = 0; q < RB; ++q) acc[a][q] = 0;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        AT w[V];
+        Wide<MT>::load(Dw + ((size_t)g * NE + e) * V, w);
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const int c = g * V + v;
+            if (c < C)
+#pragma unroll
+                for (int q = 0; q < RB; ++q) acc[c / M][q] += w[v] * (AT)(double)rz[c % M][q];
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < M; ++a) {
+        ZT out[RB];
+#pragma unroll
+        for (int q = 0; q < RB; ++q) out[q] = (ZT)(double)acc[a][q];
+        store_raw<RB>(z0 + ((size_t)e * M + a) * nb + r0, out);
     }
 }
 
@@ -1558,6 +1682,12 @@ INST_TA(float, double, float)
 template <typename MT, typename RT, typename ZT>
 void launch_jacobi0(int M, int ne, int nb, const MT *Dw, const RT *r, const double *scale, RT *rs, ZT *rc, ZT *z0,
                     hipStream_t s) {
+    if (M <= 4 && nb % 4 == 0) {   // four right-hand sides per thread
+#define J0B(MM) hipLaunchKernelGGL((k_jacobi0_rb<MM, MT, RT, ZT, 4>), GRID8(ne * (nb / 4), 256), 0, s, ne, nb, Dw, r, scale, rs, rc, z0)
+        M_SWITCH_RB(J0B)
+#undef J0B
+        return;
+    }
 #define J0(MM) hipLaunchKernelGGL((k_jacobi0<MM, MT, RT, ZT>), GRID8(ne * nb, 256), 0, s, ne, nb, Dw, r, scale, rs, rc, z0)
     M_SWITCH(J0)
 #undef J0
@@ -1614,25 +1744,30 @@ void launch_to_f32(int64_t n, const double *src, float *dst, hipStream_t s) {
 }
 
 void launch_p1_first(int n, int nb, const double *dinv, double omega, const double *b, double *x, hipStream_t s) {
-    hipLaunchKernelGGL(k_p1_first, GRID(n * nb, 256), 0, s, n, nb, dinv, omega, b, x);
+    hipLaunchKernelGGL(k_p1_first, GRID8(n * nb, 256), 0, s, n, nb, dinv, omega, b, x);
 }
 void launch_p1_pre2(int n, int W, int nb, const int *col, const double *val, const double *diag,
                     const double *dinv, double omega, const double *b, double *x, hipStream_t s) {
-    hipLaunchKernelGGL(k_p1_pre2, GRID(n * nb, 256), 0, s, n, W, nb, col, val, diag, dinv, omega, b, x);
+    if (W == 6) hipLaunchKernelGGL(k_p1_pre2<6>, GRID8(n * nb, 256), 0, s, n, W, nb, col, val, diag, dinv, omega, b, x);
+    else hipLaunchKernelGGL(k_p1_pre2<0>, GRID8(n * nb, 256), 0, s, n, W, nb, col, val, diag, dinv, omega, b, x);
 }
 void launch_p1_sweep(int n, int W, int nb, const int *col, const double *val, const double *diag,
-                     const double *dinv, double omega, const double *b, const double *x, const double *xc,
+                     const double *dinv, double omega, const double *b, double *x, const double *xc,
                      const int *parents, double *y, hipStream_t s) {
-    hipLaunchKernelGGL(k_p1_sweep, GRID(n * nb, 256), 0, s, n, W, nb, col, val, diag, dinv, omega, b, x, xc,
-                       parents, y);
+    if (xc) hipLaunchKernelGGL(k_p1_prolong, GRID8(n * nb, 256), 0, s, n, nb, parents, xc, x);
+    if (W == 6)
+        hipLaunchKernelGGL(k_p1_sweep<6>, GRID8(n * nb, 256), 0, s, n, W, nb, col, val, diag, dinv, omega, b, x, y);
+    else
+        hipLaunchKernelGGL(k_p1_sweep<0>, GRID8(n * nb, 256), 0, s, n, W, nb, col, val, diag, dinv, omega, b, x, y);
 }
 void launch_p1_resid(int n, int W, int nb, const int *col, const double *val, const double *diag,
                      const double *b, const double *x, double *y, hipStream_t s) {
-    hipLaunchKernelGGL(k_p1_resid, GRID(n * nb, 256), 0, s, n, W, nb, col, val, diag, b, x, y);
+    if (W == 6) hipLaunchKernelGGL(k_p1_resid<6>, GRID8(n * nb, 256), 0, s, n, W, nb, col, val, diag, b, x, y);
+    else hipLaunchKernelGGL(k_p1_resid<0>, GRID8(n * nb, 256), 0, s, n, W, nb, col, val, diag, b, x, y);
 }
 void launch_p1_restrict(int nc, int nb, const int *crow, const int *ccol, const double *cw, const double *r,
                         double *bc, hipStream_t s) {
-    hipLaunchKernelGGL(k_p1_restrict, GRID(nc * nb, 256), 0, s, nc, nb, crow, ccol, cw, r, bc);
+    hipLaunchKernelGGL(k_p1_restrict, GRID8(nc * nb, 256), 0, s, nc, nb, crow, ccol, cw, r, bc);
 }
 void launch_dense_mv(int n, int nb, const double *Ainv, const double *b, double *x, hipStream_t s) {
     if (nb == 1)
