@@ -256,37 +256,38 @@ void op_sweep(hdg_ctx *c, int nb, int prec, const double *x, const double *z0, c
 
 // One P1 geometric-multigrid V-cycle on level l (input lev[l].b); returns the
 // buffer holding the result.  Damped-Jacobi pre-smoothing (first two sweeps
-// fused), residual, restriction, recursion, prolongation fused into the first
-// post-sweep.  Levels small enough for the tail kernel are handled by it in
-// one launch, dense coarsest solve included.
-double *p1_vcycle(hdg_ctx *c, int l, int nb, hipStream_t s) {
+// fused), residual, restriction, recursion, prolongation, post-smoothing.
+// Levels small enough for the tail kernel are handled by it in one launch,
+// dense coarsest solve included.  f32: the level vectors hold float values
+// (inside a V-cycle whose trace vectors are FP32, the P1 vectors are too).
+double *p1_vcycle(hdg_ctx *c, int l, int nb, hipStream_t s, bool f32) {
     hdg::P1LevelDev &L = c->lev[l];
     if (l == c->tail_top) {
-        hdg::launch_p1_tail(c->tail, nb, s);
+        hdg::launch_p1_tail(c->tail, nb, s, f32);
         return L.x;
     }
     if (l == 0) {
-        hdg::launch_dense_mv(L.n, nb, c->coarse_inv, L.b, L.x, s);
+        hdg::launch_dense_mv(L.n, nb, c->coarse_inv, L.b, L.x, s, f32);
         return L.x;
     }
     const double w = c->opt.p1_omega;
     double *x = L.x, *y = L.y;
     if (c->opt.p1_nu == 1) {
-        hdg::launch_p1_first(L.n, nb, L.dinv, w, L.b, x, s);
+        hdg::launch_p1_first(L.n, nb, L.dinv, w, L.b, x, s, f32);
     } else {
-        hdg::launch_p1_pre2(L.n, L.w, nb, L.col, L.val, L.diag, L.dinv, w, L.b, x, s);
+        hdg::launch_p1_pre2(L.n, L.w, nb, L.col, L.val, L.diag, L.dinv, w, L.b, x, s, f32);
         for (int k = 2; k < c->opt.p1_nu; ++k) {
-            hdg::launch_p1_sweep(L.n, L.w, nb, L.col, L.val, L.diag, L.dinv, w, L.b, x, nullptr, nullptr, y, s);
+            hdg::launch_p1_sweep(L.n, L.w, nb, L.col, L.val, L.diag, L.dinv, w, L.b, x, nullptr, nullptr, y, s, f32);
             std::swap(x, y);
         }
     }
-    hdg::launch_p1_resid(L.n, L.w, nb, L.col, L.val, L.diag, L.b, x, y, s);
+    hdg::launch_p1_resid(L.n, L.w, nb, L.col, L.val, L.diag, L.b, x, y, s, f32);
     hdg::P1LevelDev &C = c->lev[l - 1];
-    hdg::launch_p1_restrict(C.n, nb, L.crow, L.ccol, L.cw, y, C.b, s);
-    const double *xc = p1_vcycle(c, l - 1, nb, s);
+    hdg::launch_p1_restrict(C.n, nb, L.crow, L.ccol, L.cw, y, C.b, s, f32);
+    const double *xc = p1_vcycle(c, l - 1, nb, s, f32);
     for (int k = 0; k < c->opt.p1_nu; ++k) {
         hdg::launch_p1_sweep(L.n, L.w, nb, L.col, L.val, L.diag, L.dinv, w, L.b, x, k == 0 ? xc : nullptr,
-                             L.parents, y, s);
+                             L.parents, y, s, f32);
         std::swap(x, y);
     }
     return x;
@@ -403,7 +404,7 @@ void vcycle_bj(hdg_ctx *c, int nb, int prec, const double *r, double *z, hipStre
     } else {
         const int L = (int)c->lev.size() - 1;
         restrict_p1(c, nb, c->vres, c->lev[L].b, s);
-        xl = p1_vcycle(c, L, nb, s);
+        xl = p1_vcycle(c, L, nb, s, c->vcyc32);
     }
     for (int k = 0; k < c->opt.nu_post; ++k) {
         double *out;
@@ -458,7 +459,7 @@ void vcycle_mlp(hdg_ctx *c, int nb, int prec, const double *r, double *z, hipStr
     op_resid_v(c, nb, prec, x, rb, c->vres, s);
     const int L = (int)c->lev.size() - 1;
     restrict_p1(c, nb, c->vres, c->lev[L].b, s);
-    const double *xl = p1_vcycle(c, L, nb, s);
+    const double *xl = p1_vcycle(c, L, nb, s, c->vcyc32);
     for (int k = 0; k < c->opt.nu_post; ++k) step(k == 0 ? xl : nullptr, k == c->opt.nu_post - 1 ? z : other);
     check_launch();
 }
@@ -518,7 +519,7 @@ void vcycle_cheb(hdg_ctx *c, int nb, int prec, const double *r, double *z, hipSt
         // post-smoothing from x + pi x_P1 (the prolongation rides in the sweeps)
         const int L = (int)c->lev.size() - 1;
         restrict_p1(c, nb, c->vres, c->lev[L].b, s);
-        x.qc = p1_vcycle(c, L, nb, s);
+        x.qc = p1_vcycle(c, L, nb, s, c->vcyc32);
     }
     xp = Ref{nullptr, 0.0, nullptr};
     rho = 1.0 / sigma;
@@ -1603,7 +1604,7 @@ void mlp_pair(hdg_ctx *c, int nb, int coarse_its, const double *e, double *r, do
             hdg::launch_copy(nv, c->p1_keep, F.b, s);
         else
             hdg::launch_p1_resid(F.n, F.w, nb, F.col, F.val, F.diag, c->p1_keep, c->p1_acc, F.b, s);
-        const double *xl = p1_vcycle(c, L, nb, s);
+        const double *xl = p1_vcycle(c, L, nb, s, false);
         hdg::launch_lin3<double>(nv, 1.0, xl, k == 0 ? 0.0 : 1.0, k == 0 ? nullptr : c->p1_acc, 0.0, nullptr, c->p1_acc, s);
     }
     const int64_t n = vec_len(c) * nb;

@@ -96,7 +96,7 @@ __device__ __forceinline__ double p1_node(int k, double q0, double q1) {
 struct SweepCoef {
     double a0, a1, a3, a2;
     const void *xprev;        // trace vector of the sweep's vector type
-    const double *qcprev;
+    const void *qcprev;       // P1 vector, also of the sweep's vector type
 };
 // the sweep's output combination with its rounding fixed (every launch shape
 // produces the same bits)
@@ -139,28 +139,33 @@ void launch_trace_apply(int M, int ne, int nb, const MT *S, const int *nbr, cons
 template <typename MT, typename RT, typename ZT>
 void launch_jacobi0(int M, int ne, int nb, const MT *Dw, const RT *r, const double *scale, RT *rs, ZT *rc, ZT *z0,
                     hipStream_t s);
+// qc (a P1 vector, may be null) holds values of the sweep's vector type VT in its buffer
 template <typename MT, typename VT>
 void launch_sweep(int M, int ne, int nb, const MT *T, const int *nbr, const VT *x, const VT *z0, const double *qc,
                   const int *fvert, SweepCoef cf, VT *y, hipStream_t s, int rhs_block = 1);
+// pi^T res onto the P1 vertices; rc receives values of the residual's type VT
 template <typename VT>
 void launch_restrict_trace(int p, int nv, int nb, const int *vf_row, const int *vf_col, const VT *res, double *rc,
                            hipStream_t s);
 // FP64 -> FP32 copy of a trace vector
 void launch_to_f32(int64_t n, const double *src, float *dst, hipStream_t s);
 
-void launch_p1_first(int n, int nb, const double *dinv, double omega, const double *b, double *x, hipStream_t s);
+// P1 level kernels; f32: the level vectors (b, x, y, xc, r, bc) hold float values
+// in their double buffers (the V-cycle of a mixed-precision solve)
+void launch_p1_first(int n, int nb, const double *dinv, double omega, const double *b, double *x, hipStream_t s,
+                     bool f32 = false);
 void launch_p1_pre2(int n, int W, int nb, const int *col, const double *val, const double *diag,
-                    const double *dinv, double omega, const double *b, double *x, hipStream_t s);
+                    const double *dinv, double omega, const double *b, double *x, hipStream_t s, bool f32 = false);
 // y = x + w D^-1 (b - A x); with xc != nullptr, x is first updated in place to x + P xc
 void launch_p1_sweep(int n, int W, int nb, const int *col, const double *val, const double *diag,
                      const double *dinv, double omega, const double *b, double *x, const double *xc,
-                     const int *parents, double *y, hipStream_t s);
+                     const int *parents, double *y, hipStream_t s, bool f32 = false);
 void launch_p1_resid(int n, int W, int nb, const int *col, const double *val, const double *diag,
-                     const double *b, const double *x, double *y, hipStream_t s);
+                     const double *b, const double *x, double *y, hipStream_t s, bool f32 = false);
 void launch_p1_restrict(int nc, int nb, const int *crow, const int *ccol, const double *cw, const double *r,
-                        double *bc, hipStream_t s);
-void launch_dense_mv(int n, int nb, const double *Ainv, const double *b, double *x, hipStream_t s);
-void launch_p1_tail(const P1Tail &T, int nb, hipStream_t s);
+                        double *bc, hipStream_t s, bool f32 = false);
+void launch_dense_mv(int n, int nb, const double *Ainv, const double *b, double *x, hipStream_t s, bool f32 = false);
+void launch_p1_tail(const P1Tail &T, int nb, hipStream_t s, bool f32 = false);
 
 void launch_condense(int p, int nu, int nk, int ne, int nb, const double *Zr, const double *rc, double *loc,
                      const int *facet_cell, const int *facet_loc, double *rhat, hipStream_t s);

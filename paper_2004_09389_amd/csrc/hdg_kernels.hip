@@ -473,7 +473,7 @@ __global__ __launch_bounds__(256) void k_jacobi0(int ne, int nb, const MT *__res
 template <int M, typename MT, typename VT, bool NB1>
 __global__ __launch_bounds__(256) void k_sweep(int ne, int nb, const MT *__restrict__ T,
                                                const int *__restrict__ nbr, const VT *__restrict__ x,
-                                               const VT *__restrict__ z0, const double *__restrict__ qc,
+                                               const VT *__restrict__ z0, const VT *__restrict__ qc,
                                                const int *__restrict__ fvert, SweepCoef cf,
                                                VT *__restrict__ y) {
     using AT = typename Acc<MT>::type;
@@ -492,8 +492,8 @@ __global__ __launch_bounds__(256) void k_sweep(int ne, int nb, const MT *__restr
     for (int j = 0; j < 5; ++j) {
         load_trace<M, NB1>(x, id[j] * MB + r, nb, xv[j]);
         if (qc) {
-            const double q0 = qc[(size_t)fvert[2 * id[j]] * nb + r];
-            const double q1 = qc[(size_t)fvert[2 * id[j] + 1] * nb + r];
+            const double q0 = (double)qc[(size_t)fvert[2 * id[j]] * nb + r];
+            const double q1 = (double)qc[(size_t)fvert[2 * id[j] + 1] * nb + r];
 #pragma unroll
             for (int k = 0; k < M; ++k) xv[j][k] += p1_node<P>(k, q0, q1);
         }
@@ -522,7 +522,8 @@ __global__ __launch_bounds__(256) void k_sweep(int ne, int nb, const MT *__restr
         double pv[M];
         load_trace<M, NB1>(static_cast<const VT *>(cf.xprev), e * MB + r, nb, pv);
         if (cf.qcprev) {
-            const double q0 = cf.qcprev[(size_t)fvert[2 * e] * nb + r], q1 = cf.qcprev[(size_t)fvert[2 * e + 1] * nb + r];
+            const VT *qp = static_cast<const VT *>(cf.qcprev);
+            const double q0 = (double)qp[(size_t)fvert[2 * e] * nb + r], q1 = (double)qp[(size_t)fvert[2 * e + 1] * nb + r];
 #pragma unroll
             for (int a = 0; a < M; ++a) pv[a] += p1_node<P>(a, q0, q1);
         }
@@ -539,7 +540,7 @@ __global__ __launch_bounds__(256) void k_sweep(int ne, int nb, const MT *__restr
 // surplus ends not added; the sum keeps its order).
 template <int M, typename VT>
 __global__ void k_restrict_trace(int nv, int nb, const int *__restrict__ vf_row, const int *__restrict__ vf_col,
-                                 const VT *__restrict__ res, double *__restrict__ rc) {
+                                 const VT *__restrict__ res, VT *__restrict__ rc) {
     constexpr int P = M - 1, U = 8;
     const int t = xcd_block() * blockDim.x + threadIdx.x;
     if (t >= nv * nb) return;
@@ -565,7 +566,7 @@ __global__ void k_restrict_trace(int nv, int nb, const int *__restrict__ vf_row,
             }
         }
     }
-    rc[(size_t)v * nb + r] = acc;
+    rc[(size_t)v * nb + r] = (VT)acc;
 }
 
 // ------------------------------------------------------------------ P1 levels
@@ -584,83 +585,90 @@ __global__ void k_restrict_trace(int nv, int nb, const int *__restrict__ vf_row,
 // indices of a row are independent coalesced loads.  WT > 0 fixes the width at
 // compile time (6 on the icosahedral and torus meshes), so a row's loads are
 // all issued before the first one is used; WT = 0 takes the width W at run time.
-template <int WT>
+template <int WT, typename VT>
 __device__ __forceinline__ double p1_ax(int v, int n, int W, int nb, int r, const int *ell_col,
-                                        const double *ell_val, const double *diag, const double *x) {
+                                        const double *ell_val, const double *diag, const VT *x) {
     if (WT) W = WT;
-    double s = diag[v] * x[(size_t)v * nb + r];
+    double s = diag[v] * (double)x[(size_t)v * nb + r];
 #pragma unroll
-    for (int k = 0; k < W; ++k) s += ell_val[(size_t)k * n + v] * x[(size_t)ell_col[(size_t)k * n + v] * nb + r];
+    for (int k = 0; k < W; ++k)
+        s += ell_val[(size_t)k * n + v] * (double)x[(size_t)ell_col[(size_t)k * n + v] * nb + r];
     return s;
 }
 
+template <typename VT>
 __global__ void k_p1_first(int n, int nb, const double *__restrict__ dinv, double omega,
-                           const double *__restrict__ b, double *__restrict__ x) {
+                           const VT *__restrict__ b, VT *__restrict__ x) {
     const int t = xcd_block() * blockDim.x + threadIdx.x;
     if (t >= n * nb) return;
-    x[t] = omega * dinv[t / nb] * b[t];
+    x[t] = (VT)(omega * dinv[t / nb] * (double)b[t]);
 }
 
 // two sweeps from a zero guess: x1 = w D^-1 b, x2 = x1 + w D^-1 (b - A x1)
-template <int WT>
+template <int WT, typename VT>
 __global__ void k_p1_pre2(int n, int W, int nb, const int *__restrict__ ell_col, const double *__restrict__ ell_val,
                           const double *__restrict__ diag, const double *__restrict__ dinv, double omega,
-                          const double *__restrict__ b, double *__restrict__ x) {
+                          const VT *__restrict__ b, VT *__restrict__ x) {
     const int t = xcd_block() * blockDim.x + threadIdx.x;
     if (t >= n * nb) return;
     const int v = t / nb, r = t - v * nb;
     if (WT) W = WT;
-    double ax = diag[v] * omega * dinv[v] * b[t];
+    const double bv = (double)b[t];
+    double ax = diag[v] * omega * dinv[v] * bv;
 #pragma unroll
     for (int k = 0; k < W; ++k) {
         const int u = ell_col[(size_t)k * n + v];
-        ax += ell_val[(size_t)k * n + v] * omega * dinv[u] * b[(size_t)u * nb + r];
+        ax += ell_val[(size_t)k * n + v] * omega * dinv[u] * (double)b[(size_t)u * nb + r];
     }
-    const double x1 = omega * dinv[v] * b[t];
-    x[t] = x1 + omega * dinv[v] * (b[t] - ax);
+    const double x1 = omega * dinv[v] * bv;
+    x[t] = (VT)(x1 + omega * dinv[v] * (bv - ax));
 }
 
 // y = x + w D^-1 (b - A x)
-template <int WT>
+template <int WT, typename VT>
 __global__ void k_p1_sweep(int n, int W, int nb, const int *__restrict__ ell_col, const double *__restrict__ ell_val,
                            const double *__restrict__ diag, const double *__restrict__ dinv, double omega,
-                           const double *__restrict__ b, const double *__restrict__ x, double *__restrict__ y) {
+                           const VT *__restrict__ b, const VT *__restrict__ x, VT *__restrict__ y) {
     const int t = xcd_block() * blockDim.x + threadIdx.x;
     if (t >= n * nb) return;
     const int v = t / nb, r = t - v * nb;
-    y[t] = x[t] + omega * dinv[v] * (b[t] - p1_ax<WT>(v, n, W, nb, r, ell_col, ell_val, diag, x));
+    y[t] = (VT)((double)x[t] + omega * dinv[v] * ((double)b[t] - p1_ax<WT>(v, n, W, nb, r, ell_col, ell_val, diag, x)));
 }
 
 // x += P xc: each vertex takes half of each of its two coarse parents (an
 // inherited vertex lists its parent twice)
-__global__ void k_p1_prolong(int n, int nb, const int *__restrict__ parents, const double *__restrict__ xc,
-                             double *__restrict__ x) {
+template <typename VT>
+__global__ void k_p1_prolong(int n, int nb, const int *__restrict__ parents, const VT *__restrict__ xc,
+                             VT *__restrict__ x) {
     const int t = xcd_block() * blockDim.x + threadIdx.x;
     if (t >= n * nb) return;
     const int v = t / nb, r = t - v * nb;
-    x[t] += 0.5 * (xc[(size_t)parents[2 * v] * nb + r] + xc[(size_t)parents[2 * v + 1] * nb + r]);
+    x[t] = (VT)((double)x[t] + 0.5 * ((double)xc[(size_t)parents[2 * v] * nb + r] +
+                                     (double)xc[(size_t)parents[2 * v + 1] * nb + r]));
 }
 
-template <int WT>
+template <int WT, typename VT>
 __global__ void k_p1_resid(int n, int W, int nb, const int *__restrict__ ell_col, const double *__restrict__ ell_val,
-                           const double *__restrict__ diag, const double *__restrict__ b, const double *__restrict__ x,
-                           double *__restrict__ y) {
+                           const double *__restrict__ diag, const VT *__restrict__ b, const VT *__restrict__ x,
+                           VT *__restrict__ y) {
     const int t = xcd_block() * blockDim.x + threadIdx.x;
     if (t >= n * nb) return;
     const int v = t / nb, r = t - v * nb;
-    y[t] = b[t] - p1_ax<WT>(v, n, W, nb, r, ell_col, ell_val, diag, x);
+    y[t] = (VT)((double)b[t] - p1_ax<WT>(v, n, W, nb, r, ell_col, ell_val, diag, x));
 }
 
 // bc[c] = sum over children of w * r[child]  (transpose of the interpolation); the
 // children (7 on the icosahedral hierarchy) are read eight at a time, all loads in flight
+template <typename VT>
 __global__ void k_p1_restrict(int nc, int nb, const int *__restrict__ crow, const int *__restrict__ ccol,
-                              const double *__restrict__ cw, const double *__restrict__ r,
-                              double *__restrict__ bc) {
+                              const double *__restrict__ cw, const VT *__restrict__ r,
+                              VT *__restrict__ bc) {
     const int t = xcd_block() * blockDim.x + threadIdx.x;
     if (t >= nc * nb) return;
     const int c = t / nb, rr = t - c * nb;
     const int k0 = crow[c];
-    bc[t] = acc_row<8>(0.0, crow[c + 1] - k0, [&](int k) { return cw[k0 + k] * r[(size_t)ccol[k0 + k] * nb + rr]; });
+    bc[t] = (VT)acc_row<8>(0.0, crow[c + 1] - k0,
+                           [&](int k) { return cw[k0 + k] * (double)r[(size_t)ccol[k0 + k] * nb + rr]; });
 }
 
 // x = Ainv b on the coarsest level when it is too large for the tail kernel:
@@ -668,9 +676,9 @@ __global__ void k_p1_restrict(int nc, int nb, const int *__restrict__ crow, cons
 // x = Ainv b on the coarsest level: one wavefront per (row, chunk of up to CH
 // right-hand sides), lanes striding the row; each matrix row is read once per
 // chunk and a lane reads the chunk's values of b[j] contiguously.
-template <int CH>
-__global__ void k_dense_mv(int n, int nb, const double *__restrict__ Ainv, const double *__restrict__ b,
-                           double *__restrict__ x) {
+template <int CH, typename VT>
+__global__ void k_dense_mv(int n, int nb, const double *__restrict__ Ainv, const VT *__restrict__ b,
+                           VT *__restrict__ x) {
     const int nch = (nb + CH - 1) / CH;
     const int w = (blockIdx.x * blockDim.x + threadIdx.x) / 64;
     const int lane = threadIdx.x & 63;
@@ -682,10 +690,10 @@ __global__ void k_dense_mv(int n, int nb, const double *__restrict__ Ainv, const
     for (int q = 0; q < CH; ++q) s[q] = 0.0;
     for (int j = lane; j < n; j += 64) {
         const double a = Ainv[(size_t)i * n + j];
-        const double *bj = b + (size_t)j * nb + r0;
+        const VT *bj = b + (size_t)j * nb + r0;
 #pragma unroll
         for (int q = 0; q < CH; ++q)
-            if (q < cnt) s[q] += a * bj[q];
+            if (q < cnt) s[q] += a * (double)bj[q];
     }
 #pragma unroll
     for (int q = 0; q < CH; ++q)
@@ -693,13 +701,14 @@ __global__ void k_dense_mv(int n, int nb, const double *__restrict__ Ainv, const
     if (lane == 0)
 #pragma unroll
         for (int q = 0; q < CH; ++q)
-            if (q < cnt) x[(size_t)i * nb + r0 + q] = s[q];
+            if (q < cnt) x[(size_t)i * nb + r0 + q] = (VT)s[q];
 }
 
 // All levels 0..top of the hierarchy in one workgroup: the complete V-cycle
 // below and including level `top`, input lev[top].b, result in lev[top].x.
+template <typename VT>
 __global__ __launch_bounds__(1024) void k_p1_tail(const P1Tail Targ, int nb) {
-    __shared__ double *xs[P1_TAIL_LEVELS];
+    __shared__ VT *xs[P1_TAIL_LEVELS];
     __shared__ P1Tail T;   // level descriptors staged in LDS (runtime-indexed below)
     const int tid = threadIdx.x, nth = blockDim.x;
     if (tid == 0) T = Targ;
@@ -708,28 +717,29 @@ __global__ __launch_bounds__(1024) void k_p1_tail(const P1Tail Targ, int nb) {
     for (int l = T.top; l >= 1; --l) {
         const P1Lev &L = T.lev[l];
         const int N = L.n * nb;
-        double *x = L.x, *y = L.y;
-        for (int t = tid; t < N; t += nth) x[t] = w * L.dinv[t / nb] * L.b[t];
+        const VT *b = reinterpret_cast<const VT *>(L.b);
+        VT *x = reinterpret_cast<VT *>(L.x), *y = reinterpret_cast<VT *>(L.y);
+        for (int t = tid; t < N; t += nth) x[t] = (VT)(w * L.dinv[t / nb] * (double)b[t]);
         __syncthreads();
         for (int k = 1; k < T.nu; ++k) {
             for (int t = tid; t < N; t += nth) {
                 const int v = t / nb, r = t - v * nb;
-                y[t] = x[t] + w * L.dinv[v] * (L.b[t] - p1_ax<0>(v, L.n, L.w, nb, r, L.col, L.val, L.diag, x));
+                y[t] = (VT)((double)x[t] + w * L.dinv[v] * ((double)b[t] - p1_ax<0>(v, L.n, L.w, nb, r, L.col, L.val, L.diag, x)));
             }
             __syncthreads();
-            double *tmp = x; x = y; y = tmp;
+            VT *tmp = x; x = y; y = tmp;
         }
         for (int t = tid; t < N; t += nth) {
             const int v = t / nb, r = t - v * nb;
-            y[t] = L.b[t] - p1_ax<0>(v, L.n, L.w, nb, r, L.col, L.val, L.diag, x);
+            y[t] = (VT)((double)b[t] - p1_ax<0>(v, L.n, L.w, nb, r, L.col, L.val, L.diag, x));
         }
         __syncthreads();
         const P1Lev &C = T.lev[l - 1];
         for (int t = tid; t < C.n * nb; t += nth) {
             const int c = t / nb, rr = t - c * nb;
             double acc = 0.0;
-            for (int k = L.crow[c]; k < L.crow[c + 1]; ++k) acc += L.cw[k] * y[(size_t)L.ccol[k] * nb + rr];
-            C.b[t] = acc;
+            for (int k = L.crow[c]; k < L.crow[c + 1]; ++k) acc += L.cw[k] * (double)y[(size_t)L.ccol[k] * nb + rr];
+            reinterpret_cast<VT *>(C.b)[t] = (VT)acc;
         }
         if (tid == 0) xs[l] = x;
         __syncthreads();
@@ -740,41 +750,44 @@ __global__ __launch_bounds__(1024) void k_p1_tail(const P1Tail Targ, int nb) {
         for (int t = tid; t < n0 * nb; t += nth) {
             const int i = t / nb, r = t - i * nb;
             double s = 0.0;
-            for (int j = 0; j < n0; ++j) s += T.Ainv[(size_t)i * n0 + j] * L0.b[(size_t)j * nb + r];
-            L0.x[t] = s;
+            for (int j = 0; j < n0; ++j) s += T.Ainv[(size_t)i * n0 + j] * (double)reinterpret_cast<const VT *>(L0.b)[(size_t)j * nb + r];
+            reinterpret_cast<VT *>(L0.x)[t] = (VT)s;
         }
-        if (tid == 0) xs[0] = L0.x;
+        if (tid == 0) xs[0] = reinterpret_cast<VT *>(L0.x);
         __syncthreads();
     }
     for (int l = 1; l <= T.top; ++l) {
         const P1Lev &L = T.lev[l];
         const int N = L.n * nb;
-        double *x = xs[l];
-        double *y = (x == L.x) ? L.y : L.x;
-        const double *xc = xs[l - 1];
+        const VT *b = reinterpret_cast<const VT *>(L.b);
+        VT *x = xs[l];
+        VT *y = (x == reinterpret_cast<VT *>(L.x)) ? reinterpret_cast<VT *>(L.y) : reinterpret_cast<VT *>(L.x);
+        const VT *xc = xs[l - 1];
         for (int k = 0; k < T.nu; ++k) {
             for (int t = tid; t < N; t += nth) {
                 const int v = t / nb, r = t - v * nb;
                 auto xin = [&](int u) -> double {
-                    double s = x[(size_t)u * nb + r];
-                    if (k == 0) s += 0.5 * (xc[(size_t)L.parents[2 * u] * nb + r] + xc[(size_t)L.parents[2 * u + 1] * nb + r]);
+                    double s = (double)x[(size_t)u * nb + r];
+                    if (k == 0)
+                        s += 0.5 * ((double)xc[(size_t)L.parents[2 * u] * nb + r] +
+                                    (double)xc[(size_t)L.parents[2 * u + 1] * nb + r]);
                     return s;
                 };
                 double ax = 0.0;
                 for (int k = 0; k < L.w; ++k) ax += L.val[(size_t)k * L.n + v] * xin(L.col[(size_t)k * L.n + v]);
                 const double xv = xin(v);
                 ax += L.diag[v] * xv;
-                y[t] = xv + w * L.dinv[v] * (L.b[t] - ax);
+                y[t] = (VT)(xv + w * L.dinv[v] * ((double)b[t] - ax));
             }
             __syncthreads();
-            double *tmp = x; x = y; y = tmp;
+            VT *tmp = x; x = y; y = tmp;
         }
         if (tid == 0) xs[l] = x;
         __syncthreads();
     }
     const P1Lev &Lt = T.lev[T.top];
-    if (T.top > 0 && xs[T.top] != Lt.x) {
-        for (int t = tid; t < Lt.n * nb; t += nth) Lt.x[t] = xs[T.top][t];
+    if (T.top > 0 && xs[T.top] != reinterpret_cast<VT *>(Lt.x)) {
+        for (int t = tid; t < Lt.n * nb; t += nth) reinterpret_cast<VT *>(Lt.x)[t] = xs[T.top][t];
     }
 }
 
@@ -1454,7 +1467,7 @@ constexpr int sweep_rb_waves() { return std::is_same<MT, __hip_bfloat16>::value 
 template <int M, typename MT, typename VT, int RB>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(sweep_rb_waves<MT, VT>(), 8))) void k_sweep_rb(int ne, int nb, const MT *__restrict__ T,
                                                    const int *__restrict__ nbr, const VT *__restrict__ x,
-                                                   const VT *__restrict__ z0, const double *__restrict__ qc,
+                                                   const VT *__restrict__ z0, const VT *__restrict__ qc,
                                                    const int *__restrict__ fvert, SweepCoef cf,
                                                    VT *__restrict__ y) {
     using AT = typename Acc<MT>::type;
@@ -1529,8 +1542,9 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(sweep_rb_w
         load_rb<RB>(qc + (size_t)fvert[2 * e + 1] * nb + r0, q1);
     }
     if (cf.xprev && cf.qcprev) {
-        load_rb<RB>(cf.qcprev + (size_t)fvert[2 * e] * nb + r0, p0);
-        load_rb<RB>(cf.qcprev + (size_t)fvert[2 * e + 1] * nb + r0, p1);
+        const VT *qp = static_cast<const VT *>(cf.qcprev);
+        load_rb<RB>(qp + (size_t)fvert[2 * e] * nb + r0, p0);
+        load_rb<RB>(qp + (size_t)fvert[2 * e + 1] * nb + r0, p1);
     }
 #pragma unroll
     for (int a = 0; a < M; ++a) {
@@ -1708,15 +1722,16 @@ INST_J0(float, float, double)
 template <typename MT, typename VT>
 void launch_sweep(int M, int ne, int nb, const MT *T, const int *nbr, const VT *x, const VT *z0, const double *qc,
                   const int *fvert, SweepCoef cf, VT *y, hipStream_t s, int rhs_block) {
+    const VT *qv = reinterpret_cast<const VT *>(qc);   // P1 values in the sweep's vector type
     if (rhs_blocked_m(M, nb, rhs_block)) {
-#define SWB(MM) hipLaunchKernelGGL((k_sweep_rb<MM, MT, VT, 4>), GRID_RB(ne, nb), 0, s, ne, nb, T, nbr, x, z0, qc, fvert, cf, y)
+#define SWB(MM) hipLaunchKernelGGL((k_sweep_rb<MM, MT, VT, 4>), GRID_RB(ne, nb), 0, s, ne, nb, T, nbr, x, z0, qv, fvert, cf, y)
         M_SWITCH_RB(SWB)
 #undef SWB
         return;
     }
 #define SW(MM)                                                                                                \
-    if (nb == 1) hipLaunchKernelGGL((k_sweep<MM, MT, VT, true>), GRID8(ne * nb, 256), 0, s, ne, nb, T, nbr, x, z0, qc, fvert, cf, y); \
-    else hipLaunchKernelGGL((k_sweep<MM, MT, VT, false>), GRID8(ne * nb, 256), 0, s, ne, nb, T, nbr, x, z0, qc, fvert, cf, y)
+    if (nb == 1) hipLaunchKernelGGL((k_sweep<MM, MT, VT, true>), GRID8(ne * nb, 256), 0, s, ne, nb, T, nbr, x, z0, qv, fvert, cf, y); \
+    else hipLaunchKernelGGL((k_sweep<MM, MT, VT, false>), GRID8(ne * nb, 256), 0, s, ne, nb, T, nbr, x, z0, qv, fvert, cf, y)
     M_SWITCH(SW)
 #undef SW
 }
@@ -1728,7 +1743,8 @@ template void launch_sweep<double, float>(int, int, int, const double *, const i
 template <typename VT>
 void launch_restrict_trace(int p, int nv, int nb, const int *vf_row, const int *vf_col, const VT *res, double *rc,
                            hipStream_t s) {
-#define RT(P) hipLaunchKernelGGL((k_restrict_trace<P + 1, VT>), GRID8(nv * nb, 256), 0, s, nv, nb, vf_row, vf_col, res, rc)
+    VT *rcv = reinterpret_cast<VT *>(rc);   // the P1 vector in the residual's type
+#define RT(P) hipLaunchKernelGGL((k_restrict_trace<P + 1, VT>), GRID8(nv * nb, 256), 0, s, nv, nb, vf_row, vf_col, res, rcv)
     switch (p) { case 1: RT(1); break; case 2: RT(2); break; case 3: RT(3); break; }
 #undef RT
 }
@@ -1743,41 +1759,58 @@ void launch_to_f32(int64_t n, const double *src, float *dst, hipStream_t s) {
     hipLaunchKernelGGL(k_to_f32, GRID(n, 256), 0, s, n, src, dst);
 }
 
-void launch_p1_first(int n, int nb, const double *dinv, double omega, const double *b, double *x, hipStream_t s) {
-    hipLaunchKernelGGL(k_p1_first, GRID8(n * nb, 256), 0, s, n, nb, dinv, omega, b, x);
+// P1 launchers: the level vectors hold double values, or float values in the
+// same buffers when f32 is set (the V-cycle of a mixed-precision solve).
+template <typename VT>
+static VT *pv(double *p) { return reinterpret_cast<VT *>(p); }
+template <typename VT>
+static const VT *pv(const double *p) { return reinterpret_cast<const VT *>(p); }
+#define P1_TYPED(CALL) \
+    if (f32) { using VT = float; CALL; } else { using VT = double; CALL; }
+
+void launch_p1_first(int n, int nb, const double *dinv, double omega, const double *b, double *x, hipStream_t s,
+                     bool f32) {
+    P1_TYPED(hipLaunchKernelGGL(k_p1_first<VT>, GRID8(n * nb, 256), 0, s, n, nb, dinv, omega, pv<VT>(b), pv<VT>(x)))
 }
 void launch_p1_pre2(int n, int W, int nb, const int *col, const double *val, const double *diag,
-                    const double *dinv, double omega, const double *b, double *x, hipStream_t s) {
-    if (W == 6) hipLaunchKernelGGL(k_p1_pre2<6>, GRID8(n * nb, 256), 0, s, n, W, nb, col, val, diag, dinv, omega, b, x);
-    else hipLaunchKernelGGL(k_p1_pre2<0>, GRID8(n * nb, 256), 0, s, n, W, nb, col, val, diag, dinv, omega, b, x);
+                    const double *dinv, double omega, const double *b, double *x, hipStream_t s, bool f32) {
+    P1_TYPED(if (W == 6) hipLaunchKernelGGL((k_p1_pre2<6, VT>), GRID8(n * nb, 256), 0, s, n, W, nb, col, val, diag,
+                                             dinv, omega, pv<VT>(b), pv<VT>(x));
+             else hipLaunchKernelGGL((k_p1_pre2<0, VT>), GRID8(n * nb, 256), 0, s, n, W, nb, col, val, diag, dinv,
+                                     omega, pv<VT>(b), pv<VT>(x)))
 }
 void launch_p1_sweep(int n, int W, int nb, const int *col, const double *val, const double *diag,
                      const double *dinv, double omega, const double *b, double *x, const double *xc,
-                     const int *parents, double *y, hipStream_t s) {
-    if (xc) hipLaunchKernelGGL(k_p1_prolong, GRID8(n * nb, 256), 0, s, n, nb, parents, xc, x);
-    if (W == 6)
-        hipLaunchKernelGGL(k_p1_sweep<6>, GRID8(n * nb, 256), 0, s, n, W, nb, col, val, diag, dinv, omega, b, x, y);
-    else
-        hipLaunchKernelGGL(k_p1_sweep<0>, GRID8(n * nb, 256), 0, s, n, W, nb, col, val, diag, dinv, omega, b, x, y);
+                     const int *parents, double *y, hipStream_t s, bool f32) {
+    P1_TYPED(
+        if (xc) hipLaunchKernelGGL(k_p1_prolong<VT>, GRID8(n * nb, 256), 0, s, n, nb, parents, pv<VT>(xc), pv<VT>(x));
+        if (W == 6) hipLaunchKernelGGL((k_p1_sweep<6, VT>), GRID8(n * nb, 256), 0, s, n, W, nb, col, val, diag, dinv,
+                                       omega, pv<VT>(b), pv<VT>(x), pv<VT>(y));
+        else hipLaunchKernelGGL((k_p1_sweep<0, VT>), GRID8(n * nb, 256), 0, s, n, W, nb, col, val, diag, dinv, omega,
+                                pv<VT>(b), pv<VT>(x), pv<VT>(y)))
 }
 void launch_p1_resid(int n, int W, int nb, const int *col, const double *val, const double *diag,
-                     const double *b, const double *x, double *y, hipStream_t s) {
-    if (W == 6) hipLaunchKernelGGL(k_p1_resid<6>, GRID8(n * nb, 256), 0, s, n, W, nb, col, val, diag, b, x, y);
-    else hipLaunchKernelGGL(k_p1_resid<0>, GRID8(n * nb, 256), 0, s, n, W, nb, col, val, diag, b, x, y);
+                     const double *b, const double *x, double *y, hipStream_t s, bool f32) {
+    P1_TYPED(if (W == 6) hipLaunchKernelGGL((k_p1_resid<6, VT>), GRID8(n * nb, 256), 0, s, n, W, nb, col, val, diag,
+                                             pv<VT>(b), pv<VT>(x), pv<VT>(y));
+             else hipLaunchKernelGGL((k_p1_resid<0, VT>), GRID8(n * nb, 256), 0, s, n, W, nb, col, val, diag,
+                                     pv<VT>(b), pv<VT>(x), pv<VT>(y)))
 }
 void launch_p1_restrict(int nc, int nb, const int *crow, const int *ccol, const double *cw, const double *r,
-                        double *bc, hipStream_t s) {
-    hipLaunchKernelGGL(k_p1_restrict, GRID8(nc * nb, 256), 0, s, nc, nb, crow, ccol, cw, r, bc);
+                        double *bc, hipStream_t s, bool f32) {
+    P1_TYPED(hipLaunchKernelGGL(k_p1_restrict<VT>, GRID8(nc * nb, 256), 0, s, nc, nb, crow, ccol, cw, pv<VT>(r),
+                                pv<VT>(bc)))
 }
-void launch_dense_mv(int n, int nb, const double *Ainv, const double *b, double *x, hipStream_t s) {
-    if (nb == 1)
-        hipLaunchKernelGGL(k_dense_mv<1>, GRID((int64_t)n * 64, 256), 0, s, n, nb, Ainv, b, x);
-    else
-        hipLaunchKernelGGL(k_dense_mv<8>, GRID((int64_t)n * ((nb + 7) / 8) * 64, 256), 0, s, n, nb, Ainv, b, x);
+void launch_dense_mv(int n, int nb, const double *Ainv, const double *b, double *x, hipStream_t s, bool f32) {
+    P1_TYPED(if (nb == 1) hipLaunchKernelGGL((k_dense_mv<1, VT>), GRID((int64_t)n * 64, 256), 0, s, n, nb, Ainv,
+                                              pv<VT>(b), pv<VT>(x));
+             else hipLaunchKernelGGL((k_dense_mv<8, VT>), GRID((int64_t)n * ((nb + 7) / 8) * 64, 256), 0, s, n, nb,
+                                     Ainv, pv<VT>(b), pv<VT>(x)))
 }
-void launch_p1_tail(const P1Tail &T, int nb, hipStream_t s) {
-    hipLaunchKernelGGL(k_p1_tail, dim3(1), dim3(1024), 0, s, T, nb);
+void launch_p1_tail(const P1Tail &T, int nb, hipStream_t s, bool f32) {
+    P1_TYPED(hipLaunchKernelGGL(k_p1_tail<VT>, dim3(1), dim3(1024), 0, s, T, nb))
 }
+#undef P1_TYPED
 
 void launch_condense(int p, int nu, int nk, int ne, int nb, const double *Zr, const double *rc, double *loc,
                      const int *facet_cell, const int *facet_loc, double *rhat, hipStream_t s) {

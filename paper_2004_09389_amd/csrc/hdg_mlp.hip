@@ -144,7 +144,7 @@ constexpr int MLP_ZROW = 40;   // LDS row stride of a sample's features (shorts)
 
 template <int M, int SPL, bool HAS_X, bool NB1, typename VT>
 __global__ __launch_bounds__(256) void k_mlp_smooth(int ne, int nb, const VT *__restrict__ u,
-                                                    const VT *__restrict__ xi, const double *__restrict__ qc,
+                                                    const VT *__restrict__ xi, const VT *__restrict__ qc,
                                                     const int *__restrict__ fvert, const int *__restrict__ nbr,
                                                     const int8_t *__restrict__ prev, const short *__restrict__ W1b,
                                                     const short *__restrict__ W2b, VT *__restrict__ xo) {
@@ -172,8 +172,8 @@ __global__ __launch_bounds__(256) void k_mlp_smooth(int ne, int nb, const VT *__
                 const int e = NB1 ? samp : samp / nb, r = NB1 ? 0 : samp - e * nb;
                 load_trace<M, NB1>(xi, e * MB + r, nb, xe[q]);
                 if (qc) {
-                    const double q0 = qc[(size_t)fvert[2 * e] * nb + r];
-                    const double q1 = qc[(size_t)fvert[2 * e + 1] * nb + r];
+                    const double q0 = (double)qc[(size_t)fvert[2 * e] * nb + r];
+                    const double q1 = (double)qc[(size_t)fvert[2 * e + 1] * nb + r];
 #pragma unroll
                     for (int o = 0; o < M; ++o) xe[q][o] += p1_node<P>(o, q0, q1);
                 }
@@ -311,7 +311,7 @@ __device__ __forceinline__ void store4(T *__restrict__ p, const double (&d)[4]) 
 
 template <int M, bool HAS_X, typename VT>
 __global__ __launch_bounds__(128) void k_mlp_smooth_r4(int ne, int nb, const VT *__restrict__ u,
-                                                       const VT *__restrict__ xi, const double *__restrict__ qc,
+                                                       const VT *__restrict__ xi, const VT *__restrict__ qc,
                                                        const int *__restrict__ fvert, const int *__restrict__ nbr,
                                                        const int8_t *__restrict__ prev, const short *__restrict__ W1b,
                                                        const short *__restrict__ W2b, VT *__restrict__ xo) {
@@ -652,11 +652,12 @@ template <typename VT>
 void launch_mlp_smooth(int p, int ne, int nb, int spl, const VT *u, const VT *xi, const double *qc,
                        const int *fvert, const int *nbr, const int8_t *prev, const short *W1b, const short *W2b,
                        VT *xo, hipStream_t s) {
+    const VT *qv = reinterpret_cast<const VT *>(qc);   // P1 values in the smoother's vector type
     if (spl == 4 && nb % 4 == 0) {
         const int64_t waves = ((int64_t)ne * nb + 255) / 256;
         const dim3 grid((unsigned)(((waves + 1) / 2 + 7) / 8 * 8)), block(128);   // multiple of 8 for the XCD remap
 #define MR(M, X) \
-    hipLaunchKernelGGL((k_mlp_smooth_r4<M, X, VT>), grid, block, 0, s, ne, nb, u, xi, qc, fvert, nbr, prev, W1b, W2b, xo)
+    hipLaunchKernelGGL((k_mlp_smooth_r4<M, X, VT>), grid, block, 0, s, ne, nb, u, xi, qv, fvert, nbr, prev, W1b, W2b, xo)
 #define MR_X(M)                  \
     if (xi) MR(M, true);         \
     else MR(M, false);
@@ -671,7 +672,7 @@ void launch_mlp_smooth(int p, int ne, int nb, int spl, const VT *u, const VT *xi
     const dim3 grid((unsigned)(((blocks + 7) / 8) * 8)), block(256);   // multiple of 8 for the XCD remap
     const bool hx = xi != nullptr, n1 = nb == 1;
 #define MS(M, S, X, N) \
-    hipLaunchKernelGGL((k_mlp_smooth<M, S, X, N, VT>), grid, block, 0, s, ne, nb, u, xi, qc, fvert, nbr, prev, W1b, W2b, xo)
+    hipLaunchKernelGGL((k_mlp_smooth<M, S, X, N, VT>), grid, block, 0, s, ne, nb, u, xi, qv, fvert, nbr, prev, W1b, W2b, xo)
 #define MS_XN(M, S)                          \
     if (hx) {                                \
         if (n1) MS(M, S, true, true);        \
