@@ -458,8 +458,11 @@ int hdg_autotune(hdg_ctx *ctx, int32_t nrhs, hdg_tuning *chosen, void *stream);
  * hdg_set_timing call, and the algorithmic bytes one launch moves at the
  * nrhs and vector entry sizes of the timed launches (every stored matrix
  * entry once, every vector entry read or written once at its stored size --
- * 4 bytes for the FP32 vectors inside mixed solves -- indices once).  Both
- * calls synchronise. */
+ * 4 bytes for the FP32 vectors inside mixed solves -- indices once).  For
+ * the sweep class it is the average over the timed launches of each
+ * launch's own operands (an input that is the same vector as another counts
+ * once; the prolongation and previous-iterate terms count when present).
+ * Both calls synchronise. */
 #define HDG_KERNEL_APPLY    0   /* y = S x  (facet block rows) */
 #define HDG_KERNEL_SWEEP    1   /* block-Jacobi sweep with the off-diagonal rows */
 #define HDG_KERNEL_RESIDUAL 2   /* r - S x */

@@ -159,9 +159,11 @@ struct Timed {
     int kind, prec;
     hipStream_t s;
     hipEvent_t a = nullptr;
-    // sx, sy: bytes per entry of the launch's input and output trace vectors
-    Timed(hdg_ctx *c_, int kind_, int prec_, hipStream_t s_, int nb, int sx = 8, int sy = 8)
-        : c(c_), kind(kind_), prec(prec_), s(s_) {
+    double bytes;
+    // sx, sy: bytes per entry of the launch's input and output trace vectors; bytes
+    // (> 0): this launch's own algorithmic bytes, when they differ from the class formula
+    Timed(hdg_ctx *c_, int kind_, int prec_, hipStream_t s_, int nb, int sx = 8, int sy = 8, double bytes_ = 0.0)
+        : c(c_), kind(kind_), prec(prec_), s(s_), bytes(bytes_) {
         if (!c->timing) return;
         c->t_nb[prec][kind] = nb;
         c->t_sx[prec][kind] = sx;
@@ -174,7 +176,7 @@ struct Timed {
         if (!a) return;
         hipEvent_t b = pool_event(c);
         (void)hipEventRecord(b, s);
-        c->pending.push_back({a, b, kind, prec});
+        c->pending.push_back({a, b, kind, prec, bytes});
     }
 };
 
@@ -186,6 +188,10 @@ void collect_timing(hdg_ctx *c) {
         HDG_HIP_CHECK(hipEventElapsedTime(&ms, p.a, p.b));
         c->t_ms[p.prec][p.kind] += ms / c->timing_repeat;
         c->t_launches[p.prec][p.kind] += 1;
+        if (p.bytes > 0) {
+            c->t_bytes[p.prec][p.kind] += p.bytes;
+            c->t_blaunch[p.prec][p.kind] += 1;
+        }
         c->event_pool.push_back(p.a);
         c->event_pool.push_back(p.b);
     }
@@ -240,7 +246,17 @@ hdg::SweepCoef bj_coef(const hdg_ctx *c) { return {1.0 - c->opt.omega, 1.0, 1.0,
 
 void op_sweep(hdg_ctx *c, int nb, int prec, const double *x, const double *z0, const double *qc, double *y,
               hipStream_t s, const hdg::SweepCoef &cf) {
-    Timed t(c, HDG_KERNEL_SWEEP, prec, s, nb, c->vcyc32 ? 4 : 8, c->vcyc32 ? 4 : 8);
+    // algorithmic bytes of this launch: the rows and ids once; x (own and neighbour values),
+    // z0 (once, or not at all when it is x itself) and y; the P1 correction, the previous
+    // iterate and its P1 correction with the facets' vertex ids when present
+    const double m = c->m, ne = c->n_facet, nv = c->n_vert, sv = c->vcyc32 ? 4.0 : 8.0;
+    const double st = prec == HDG_MIXED ? 2.0 : 8.0;
+    double bytes = ne * (4 * m * m * st + 4 * 4) + nb * ne * m * sv * (x == z0 ? 2 : 3);
+    if (qc) bytes += nb * nv * sv;
+    if (cf.xprev) bytes += nb * ne * m * sv;
+    if (cf.qcprev) bytes += nb * nv * sv;
+    if (qc || cf.qcprev) bytes += ne * 2 * 4;
+    Timed t(c, HDG_KERNEL_SWEEP, prec, s, nb, c->vcyc32 ? 4 : 8, c->vcyc32 ? 4 : 8, bytes);
     for (int rep = 0; rep < t.repeats(); ++rep)
         vt_call(c->vcyc32, [&](auto tag) {
             using VT = std::remove_pointer_t<decltype(tag)>;
@@ -1874,6 +1890,8 @@ extern "C" int hdg_set_timing(hdg_ctx *c, int32_t enable) {
         c->timing_repeat = enable > 0 ? enable : 1;
         std::memset(c->t_ms, 0, sizeof(c->t_ms));
         std::memset(c->t_launches, 0, sizeof(c->t_launches));
+        std::memset(c->t_bytes, 0, sizeof(c->t_bytes));
+        std::memset(c->t_blaunch, 0, sizeof(c->t_blaunch));
     });
 }
 
@@ -1904,6 +1922,10 @@ extern "C" int hdg_kernel_stats(hdg_ctx *c, int32_t kernel, int32_t prec, int64_
             case HDG_KERNEL_RECOVER: b = nk * (nc * nc + nc * nt) * 8 + nb * (nk * 2 * nc * 8 + ne * m * 8); break;
             case HDG_KERNEL_MLP: b = ne * (4 * 4 + 4) + nb * ne * 3 * m * sx; break;
             }
+            // launches that stated their own bytes (operands that alias counted once, optional
+            // terms only when present): their average
+            const int64_t nl = c->t_launches[prec][kernel];
+            if (nl > 0 && c->t_blaunch[prec][kernel] == nl) b = c->t_bytes[prec][kernel] / (double)nl;
             *bytes_per_launch = b;
         }
     });

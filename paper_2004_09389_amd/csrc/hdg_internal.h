@@ -208,6 +208,7 @@ struct hdg_ctx {
     struct PendingEvent {
         hipEvent_t a, b;
         int kind, prec;
+        double bytes;   // the launch's own algorithmic bytes (0: use the class formula)
     };
     bool timing = false;
     int timing_repeat = 1;
@@ -222,4 +223,6 @@ struct hdg_ctx {
     int t_sx[2][HDG_KERNEL_COUNT] = {};   // bytes per input-vector entry of that launch (8 or 4)
     int t_sy[2][HDG_KERNEL_COUNT] = {};   // bytes per output-vector entry
     double t_ms[2][HDG_KERNEL_COUNT] = {};
+    double t_bytes[2][HDG_KERNEL_COUNT] = {};     // sum of the launches' own algorithmic bytes
+    int64_t t_blaunch[2][HDG_KERNEL_COUNT] = {};  // launches that stated their bytes
 };

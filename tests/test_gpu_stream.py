@@ -54,3 +54,33 @@ def test_probes_reject_misaligned_and_short_buffers():
         stream_triad(x[1:], x[1:].clone(), 1.0, torch.zeros(4096, dtype=torch.float64, device="cuda"))
     with pytest.raises(HdgError):
         stream_read(x, torch.zeros(2, dtype=torch.float64, device="cuda"))
+
+
+def test_sweep_bytes_count_each_launch_own_operands():
+    """The roofline's algorithmic bytes for the sweep class: one FP64 V-cycle
+    (block-Jacobi, 2 + 2 sweeps) makes three sweep launches -- the pre-sweep
+    whose iterate is the first sweep's output z0 itself (z0 read once), the
+    first post-sweep with the P1 correction, the last post-sweep -- and
+    hdg_kernel_stats reports their average."""
+    import torch
+
+    import hdg_inputs as hi
+    from paper_2004_09389_amd.hdg import HDG_FP64, HdgSolver
+    print("[stream] sweep byte accounting, 8x8 torus p=2 nrhs=4", flush=True)
+    h = hi.torus_hierarchy(8, 2)
+    s = HdgSolver(h, 2, 0.3, 1.0, 1.0, 0.5, 0.0, 1.0, max_rhs=4, persistent=0)
+    try:
+        nb, m, ne, nv = 4, 3, s.sizes.n_facet, s.sizes.n_vert
+        r = torch.from_numpy(hi.iid_trace(ne, 2, 5, nb)).cuda()
+        s.set_timing(1)
+        s.mg_vcycle(r, HDG_FP64)
+        torch.cuda.synchronize()
+        n, ms, b = s.kernel_stats("sweep", HDG_FP64)
+        s.set_timing(0)
+        rows = ne * (4 * m * m * 8 + 16)
+        vec = nb * ne * m * 8
+        expect = (rows + 2 * vec + rows + 3 * vec + nb * nv * 8 + ne * 8 + rows + 3 * vec) / 3
+        assert n == 3 and ms > 0
+        assert abs(b - expect) <= 1e-9 * expect, (b, expect)
+    finally:
+        s.close()
