@@ -44,6 +44,16 @@ def test_argument_errors_are_reported():
     y = s.trace_zeros(3)                       # ... and so does the C ABI when called directly
     rc = s.lib.hdg_trace_apply(s.ctx, 3, 0, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()), None)
     assert rc == HDG_EINVAL and "max_rhs" in s.lib.hdg_last_error().decode()
+    # an empty batch (nrhs = 0) is an argument error at every entry point, not a no-op launch
+    px, py = ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr())
+    assert s.lib.hdg_trace_apply(s.ctx, 0, 0, px, py, None) == HDG_EINVAL
+    assert s.lib.hdg_mg_vcycle(s.ctx, 0, 0, px, py, None) == HDG_EINVAL
+    assert s.lib.hdg_solve(s.ctx, 0, px, py, None, None) == HDG_EINVAL
+    q = s.cell_zeros(1)
+    assert s.lib.hdg_condense(s.ctx, 0, ctypes.c_void_p(q.data_ptr()), py, None) == HDG_EINVAL
+    assert s.lib.hdg_stage_solve(s.ctx, 0, ctypes.c_void_p(q.data_ptr()), py, ctypes.c_void_p(q.data_ptr()),
+                                 None, None) == HDG_EINVAL
+    assert "nrhs" in s.lib.hdg_last_error().decode()
     # a trace buffer that is not 16-byte aligned
     flat = torch.zeros(s.n_facet * s.m + 1, dtype=torch.float64, device="cuda")
     mis = flat[1:].view(s.n_facet, s.m, 1)
