@@ -310,7 +310,8 @@ double *p1_vcycle(hdg_ctx *c, int l, int nb, hipStream_t s, bool f32) {
 }
 
 // z0 = omega D^-1 r (the first sweep from zero); with scale the input is r / scale, also written to rs
-// rc (may be null): copy of the scaled input in the V-cycle's vector type
+// rc (may be null): copy of the scaled input in the V-cycle's vector type.  While c->gs_lag is set
+// (inside FGMRES) the input is first completed by the previous iteration's Gram-Schmidt step.
 void jacobi0(hdg_ctx *c, int nb, int prec, const double *r, const double *scale, double *rs, double *rc,
              double *z0, hipStream_t s) {
     vt2_call(c->vin32, c->vcyc32, [&](auto tr, auto tz) {
@@ -318,10 +319,10 @@ void jacobi0(hdg_ctx *c, int nb, int prec, const double *r, const double *scale,
         using ZT = std::remove_pointer_t<decltype(tz)>;
         if (prec == HDG_MIXED)
             hdg::launch_jacobi0<float, RT, ZT>(c->m, c->n_facet, nb, c->Dw32, vt<RT>(r), scale, vt<RT>(rs),
-                                               vt<ZT>(rc), vt<ZT>(z0), s);
+                                               vt<ZT>(rc), vt<ZT>(z0), s, c->gs_lag);
         else
             hdg::launch_jacobi0<double, RT, ZT>(c->m, c->n_facet, nb, c->Dw64, vt<RT>(r), scale, vt<RT>(rs),
-                                                vt<ZT>(rc), vt<ZT>(z0), s);
+                                                vt<ZT>(rc), vt<ZT>(z0), s, c->gs_lag);
     });
 }
 // first kernel of a V-cycle: z0 = omega D^-1 r; returns the right-hand side the cycle's
@@ -714,9 +715,12 @@ int solve_fgmres(hdg_ctx *c, int nb, int vc_prec, int op_prec, double inner_eta,
     const bool f32 = vc_prec == HDG_MIXED && op_prec == HDG_MIXED;
     // any solve with the mixed V-cycle keeps the V-cycle's vectors and the Z basis in FP32
     const bool z32 = vc_prec == HDG_MIXED;
-    struct Vec32Off {   // FP64 vectors again when the solve returns or throws
+    struct Vec32Off {   // FP64 vectors again (and no pending Gram-Schmidt step) when the solve returns or throws
         hdg_ctx *c;
-        ~Vec32Off() { c->vcyc32 = c->vin32 = c->kv32 = false; }
+        ~Vec32Off() {
+            c->vcyc32 = c->vin32 = c->kv32 = false;
+            c->gs_lag = hdg::GsLag{};
+        }
     } vec32_off{c};
     auto set32 = [&](bool on) {
         c->vcyc32 = on && z32;
@@ -758,20 +762,40 @@ int solve_fgmres(hdg_ctx *c, int nb, int vc_prec, int op_prec, double inner_eta,
             double *Vj = c->kV + (size_t)j * vs, *Vn = c->kV + (size_t)(j + 1) * vs;
             double *Zj = c->kZ + (size_t)j * vs;
             const int slot = j & 1;
-            // V_j still carries its norm (beta for j = 0, the previous step's ||w|| after);
-            // the V-cycle's first kernel divides it out in place
+            // V_j still carries its norm (beta for j = 0, the previous step's norm after);
+            // the V-cycle's first kernel divides it out in place.
+            // The FP32 inner solve of HDG_MIXED_IR makes one pass over the basis per
+            // iteration (classical Gram-Schmidt with the update and the normalisation
+            // lagged): with w = S z_j it takes the dot products with V_0..V_j and with w
+            // itself in the same pass, the norm of w - sum h_d V_d from them
+            // (||w||^2 - sum h_d^2, exact for an orthonormal basis), and leaves the update to
+            // the next V-cycle's first kernel, which reads V_{j+1} anyway and so completes
+            // and normalises it in place.  Where that norm would lose too much to rounding
+            // (the remaining part of w below 1 % of w), the explicit update pass runs
+            // instead, on the device's own decision (c->gs_explicit), and the next V-cycle
+            // skips the lagged step.  The FP64 bases, which must reach the full tolerance in
+            // one cycle, keep the explicit update and norm: there the basis' loss of
+            // orthogonality over a long cycle makes the lagged norm unreliable (measured:
+            // 30-44 iterations instead of 11-12 on some workloads).
             const double *vscale = (j == 0) ? scal(c, SC_BETA) : scal(c, SC_HN);
+            const bool one_pass = f32;
+            c->gs_lag = (j == 0 || !one_pass) ? hdg::GsLag{} : hdg::GsLag{c->kV, vstride, j, c->hcol, c->gs_explicit};
             run_step(c, graph_key(2 + (c->use_mlp_now ? 1 : 0), nb, vc_prec * 4 + op_prec, j), s, [&](hipStream_t st) {
                 vcycle(c, nb, vc_prec, Vj, Zj, st, vscale);
                 op_apply(c, nb, op_prec, Zj, nullptr, Vn, st, HDG_KERNEL_APPLY, c->vcyc32, c->kv32);
-                dots(c, nb, j + 1, c->kV, vstride, Vn, c->hcol, st);
+                dots(c, nb, one_pass ? j + 2 : j + 1, c->kV, vstride, Vn, c->hcol, st);
+                if (one_pass)
+                    hdg::launch_pyth_givens(nb, j, R, 1e-2, c->hcol, scal(c, SC_HN), c->gm, c->dbn, lag_dev(c, slot),
+                                            c->gs_explicit, st);
                 vt_call(c->kv32, [&](auto tag) {
                     using VT = std::remove_pointer_t<decltype(tag)>;
                     hdg::launch_gs_norm_givens<VT>(n, nb, j + 1, c->hcol, vt<VT>(c->kV), vstride, vt<VT>(Vn), c->red,
-                                                   scal(c, SC_HN), j, R, c->gm, c->dbn, lag_dev(c, slot), st);
+                                                   scal(c, SC_HN), j, R, c->gm, c->dbn, lag_dev(c, slot), st,
+                                                   one_pass ? c->gs_explicit : nullptr);
                 });
                 check_launch();
             });
+            c->gs_lag = hdg::GsLag{};
             mark_lag(c, slot, s);
             ++its;
             k = j + 1;
@@ -1197,6 +1221,7 @@ void setup_impl(const hdg_mesh *levels, int nlev, const int32_t *const *parents,
     c->red = dev_alloc<double>(c, (size_t)c->red_blocks * (Rr + 1) * mr);
     c->scal = dev_alloc<double>(c, (size_t)SC_COUNT * mr);
     c->hcol = dev_alloc<double>(c, (size_t)(Rr + 1) * mr);
+    c->gs_explicit = dev_alloc<int>(c, 1);
     c->gm = dev_alloc<double>(c, (size_t)((Rr + 1) * Rr + 2 * Rr + (Rr + 1)) * mr);
     c->hy = dev_alloc<double>(c, (size_t)Rr * mr);
     c->dbn = dev_alloc<double>(c, mr);

@@ -22,6 +22,17 @@ namespace hdg {
             throw ::hdg::Error{HDG_EHIP, std::string(#expr) + ": " + hipGetErrorString(_e)}; \
     } while (0)
 
+// The classical Gram-Schmidt step of a Krylov basis vector left to its first
+// reader (one pass over the basis per iteration): the vector r becomes
+// r - sum_{d < nd} h[d][rhs] V_d, V_d of r's element type, vstride elements apart.
+struct GsLag {
+    const void *V = nullptr;
+    int64_t vstride = 0;
+    int nd = 0;
+    const double *h = nullptr;   // [nd][nb]
+    const int *done = nullptr;   // (device) nonzero: the step was already made explicitly
+};
+
 // ------------------------------------------------------------------ context
 struct P1LevelDev {
     int n = 0, w = 0;                              // vertices, ELL width (max off-diagonals per row)
@@ -166,6 +177,7 @@ struct hdg_ctx {
     double *scal = nullptr;                   // device scalars [slot][max_rhs]
     double *hscal = nullptr;                  // pinned host mirror
     double *hcol = nullptr;                   // FGMRES Hessenberg column [restart+1][max_rhs]
+    int *gs_explicit = nullptr;               // (device) 1 when an iteration's Gram-Schmidt update ran explicitly
     double *gm = nullptr;                     // FGMRES per-RHS state (H, Givens, g)
     double *hy = nullptr;                     // FGMRES coefficients [restart][max_rhs]
     double *dbn = nullptr;                    // ||rhat|| per RHS (device)
@@ -203,6 +215,7 @@ struct hdg_ctx {
     // and its output z (the FGMRES Z basis), vin32 for the V-cycle's input r, kv32 for the
     // FGMRES V basis.  Mixed solves set vcyc32; the inner solve of HDG_MIXED_IR sets all three.
     bool vcyc32 = false, vin32 = false, kv32 = false;
+    hdg::GsLag gs_lag;   // Gram-Schmidt step pending on the next V-cycle's input (FGMRES)
 
     // timing
     struct PendingEvent {

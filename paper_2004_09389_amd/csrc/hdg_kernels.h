@@ -138,7 +138,7 @@ void launch_trace_apply(int M, int ne, int nb, const MT *S, const int *nbr, cons
 // receives the scaled input in z0's type
 template <typename MT, typename RT, typename ZT>
 void launch_jacobi0(int M, int ne, int nb, const MT *Dw, const RT *r, const double *scale, RT *rs, ZT *rc, ZT *z0,
-                    hipStream_t s);
+                    hipStream_t s, GsLag gs = GsLag{});
 // qc (a P1 vector, may be null) holds values of the sweep's vector type VT in its buffer
 template <typename MT, typename VT>
 void launch_sweep(int M, int ne, int nb, const MT *T, const int *nbr, const VT *x, const VT *z0, const double *qc,
@@ -176,10 +176,18 @@ int red_grid(int64_t len, int nb);
 template <typename VT>
 void launch_dots(int64_t len, int nb, int nd, const VT *X, int64_t xstride, const VT *y, double *partial,
                  double *out, double *host, hipStream_t s);
+// ||w - sum_d h_d V_d|| of an orthonormal basis from the dot products alone
+// (hcol[j + 1] holds ||w||^2: the norm is sqrt(||w||^2 - sum_{d <= j} h_d^2)), then
+// the Givens step of FGMRES column j
+// Used only when the remaining norm keeps at least `floor` of ||w||^2 for every
+// right-hand side: then *expl = 0 and the update is left to the next V-cycle's first
+// kernel (GsLag); otherwise *expl = 1 and launch_gs_norm_givens with run = expl does it.
+void launch_pyth_givens(int nb, int j, int restart, double floor, const double *hcol, double *hn, double *gm,
+                        const double *bnorm, double *resid_host, int *expl, hipStream_t s);
 template <typename VT>
 void launch_gs_norm_givens(int64_t len, int nb, int nd, const double *h, const VT *V, int64_t vstride, VT *w,
                            double *partial, double *hn, int j, int restart, double *gm, const double *bnorm,
-                           double *resid_host, hipStream_t s);
+                           double *resid_host, hipStream_t s, const int *run = nullptr);
 void launch_pcg_update_norm(int64_t len, int nb, const double *num, const double *den, const double *p,
                             const double *w, double *x, double *res, double *partial, double *rr_host,
                             hipStream_t s);

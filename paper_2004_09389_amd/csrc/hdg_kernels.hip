@@ -431,7 +431,8 @@ __global__ __launch_bounds__(256) void k_trace_apply(int ne, int nb, const MT *_
 template <int M, typename MT, typename RT, typename ZT>
 __global__ __launch_bounds__(256) void k_jacobi0(int ne, int nb, const MT *__restrict__ Dw,
                                                  const RT *__restrict__ r, const double *__restrict__ scale,
-                                                 RT *__restrict__ rs, ZT *__restrict__ rc, ZT *__restrict__ z0) {
+                                                 RT *__restrict__ rs, ZT *__restrict__ rc, ZT *__restrict__ z0,
+                                                 GsLag gs) {
     using AT = typename Acc<MT>::type;
     constexpr int V = Wide<MT>::V, C = M * M, G = padded(C, V) / V;
     const int t = xcd_block() * blockDim.x + threadIdx.x;
@@ -443,7 +444,11 @@ __global__ __launch_bounds__(256) void k_jacobi0(int ne, int nb, const MT *__res
 #pragma unroll
     for (int k = 0; k < M; ++k) {
         const size_t o = ((size_t)e * M + k) * nb + rr;
-        const RT v = (RT)((double)r[o] * sc);   // the scaled vector as stored
+        double rk = (double)r[o];
+        const int gnd = (gs.done && *gs.done) ? 0 : gs.nd;
+        for (int d = 0; d < gnd; ++d)
+            rk -= gs.h[(size_t)d * nb + rr] * (double)static_cast<const RT *>(gs.V)[(size_t)d * gs.vstride + o];
+        const RT v = (RT)(rk * sc);             // the scaled vector as stored
         if (scale) rs[o] = v;
         const ZT vz = (ZT)v;                    // ... and as the V-cycle reads it
         if (rc) rc[o] = vz;
@@ -1123,7 +1128,9 @@ __device__ void givens_column(int r, int nb, int j, int restart, const double *h
 template <typename VT>
 __global__ __launch_bounds__(256) void k_gs_update_norm(int64_t len, int nb, int nd, const double *__restrict__ h,
                                                         const VT *__restrict__ V, int64_t vstride,
-                                                        VT *__restrict__ w, double *__restrict__ partial) {
+                                                        VT *__restrict__ w, double *__restrict__ partial,
+                                                        const int *__restrict__ run) {
+    if (run && !*run) return;   // the lagged step was taken instead (k_pyth_givens)
     __shared__ double sh[1][256];
     const int rpb = rows_per_block(nb);
     const int tid = threadIdx.x;
@@ -1167,7 +1174,9 @@ __global__ __launch_bounds__(256) void k_gs_update_norm(int64_t len, int nb, int
 __global__ __launch_bounds__(256) void k_norm_givens(int nblk, int nb, const double *__restrict__ partial,
                                                      double *__restrict__ hn, int j, int restart,
                                                      const double *__restrict__ hcol, double *__restrict__ gm,
-                                                     const double *__restrict__ bnorm, double *__restrict__ resid) {
+                                                     const double *__restrict__ bnorm, double *__restrict__ resid,
+                                                     const int *__restrict__ run) {
+    if (run && !*run) return;
     const int r = blockIdx.x;
     const double v = block_sum_partials(partial, nblk, nb, r);
     if (threadIdx.x == 0) {
@@ -1175,6 +1184,40 @@ __global__ __launch_bounds__(256) void k_norm_givens(int nblk, int nb, const dou
         hn[r] = n;
         givens_column(r, nb, j, restart, hcol, n, gm, bnorm, resid);
     }
+}
+
+// The norm of w - sum_{d <= j} h_d V_d from the dot products of the same pass
+// (hcol[j + 1] = ||w||^2): ||w||^2 - sum h_d^2, exact for an orthonormal basis.
+// Its rounding error grows with the basis' loss of orthogonality relative to the
+// remaining norm, so it is used only when that norm keeps at least `floor` of
+// ||w||^2 for every right-hand side; then the Givens step follows and *expl = 0
+// (the update is left to the next V-cycle's first kernel).  Otherwise *expl = 1
+// and the explicit update pass (k_gs_update_norm, k_norm_givens) does both.
+// One block of 64 threads, nb <= 64.
+__global__ __launch_bounds__(64) void k_pyth_givens(int nb, int j, int restart, double floor,
+                                                    const double *__restrict__ hcol, double *__restrict__ hn,
+                                                    double *__restrict__ gm, const double *__restrict__ bnorm,
+                                                    double *__restrict__ resid, int *__restrict__ expl) {
+    __shared__ int bad;
+    const int r = threadIdx.x;
+    if (r == 0) bad = 0;
+    __syncthreads();
+    double s = 0.0;
+    if (r < nb) {
+        const double w2 = hcol[(size_t)(j + 1) * nb + r];
+        s = w2;
+        for (int i = 0; i <= j; ++i) {
+            const double h = hcol[(size_t)i * nb + r];
+            s -= h * h;
+        }
+        if (!(s >= floor * w2)) atomicOr(&bad, 1);
+    }
+    __syncthreads();
+    if (r == 0) *expl = bad;
+    if (bad || r >= nb) return;
+    const double n = sqrt(s);
+    hn[r] = n;
+    givens_column(r, nb, j, restart, hcol, n, gm, bnorm, resid);
 }
 
 // PCG update x += alpha p, r -= alpha w (alpha = num/den) and partials of ||r||^2
@@ -1576,7 +1619,8 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(sweep_rb_w
 template <int M, typename MT, typename RT, typename ZT, int RB>
 __global__ __launch_bounds__(256) void k_jacobi0_rb(int ne, int nb, const MT *__restrict__ Dw,
                                                     const RT *__restrict__ r, const double *__restrict__ scale,
-                                                    RT *__restrict__ rs, ZT *__restrict__ rc, ZT *__restrict__ z0) {
+                                                    RT *__restrict__ rs, ZT *__restrict__ rc, ZT *__restrict__ z0,
+                                                    GsLag gs) {
     using AT = typename Acc<MT>::type;
     constexpr int V = Wide<MT>::V, C = M * M, G = padded(C, V) / V;
     const int tpf = nb / RB;
@@ -1593,9 +1637,19 @@ __global__ __launch_bounds__(256) void k_jacobi0_rb(int ne, int nb, const MT *__
         const size_t o = ((size_t)e * M + k) * nb + r0;
         RT v[RB];
         load_raw<RB>(r + o, v);
+        double rk[RB];
+#pragma unroll
+        for (int q = 0; q < RB; ++q) rk[q] = (double)v[q];
+        const int gnd = (gs.done && *gs.done) ? 0 : gs.nd;
+        for (int d = 0; d < gnd; ++d) {
+            RT vd[RB];
+            load_raw<RB>(static_cast<const RT *>(gs.V) + (size_t)d * gs.vstride + o, vd);
+#pragma unroll
+            for (int q = 0; q < RB; ++q) rk[q] -= gs.h[(size_t)d * nb + r0 + q] * (double)vd[q];
+        }
 #pragma unroll
         for (int q = 0; q < RB; ++q) {
-            v[q] = (RT)((double)v[q] * sc[q]);   // the scaled vector as stored
+            v[q] = (RT)(rk[q] * sc[q]);          // the scaled vector as stored
             rz[k][q] = (ZT)v[q];                 // ... and as the V-cycle reads it
         }
         if (scale) store_raw<RB>(rs + o, v);
@@ -1695,19 +1749,19 @@ INST_TA(float, double, float)
 
 template <typename MT, typename RT, typename ZT>
 void launch_jacobi0(int M, int ne, int nb, const MT *Dw, const RT *r, const double *scale, RT *rs, ZT *rc, ZT *z0,
-                    hipStream_t s) {
+                    hipStream_t s, GsLag gs) {
     if (M <= 4 && nb % 4 == 0) {   // four right-hand sides per thread
-#define J0B(MM) hipLaunchKernelGGL((k_jacobi0_rb<MM, MT, RT, ZT, 4>), GRID8(ne * (nb / 4), 256), 0, s, ne, nb, Dw, r, scale, rs, rc, z0)
+#define J0B(MM) hipLaunchKernelGGL((k_jacobi0_rb<MM, MT, RT, ZT, 4>), GRID8(ne * (nb / 4), 256), 0, s, ne, nb, Dw, r, scale, rs, rc, z0, gs)
         M_SWITCH_RB(J0B)
 #undef J0B
         return;
     }
-#define J0(MM) hipLaunchKernelGGL((k_jacobi0<MM, MT, RT, ZT>), GRID8(ne * nb, 256), 0, s, ne, nb, Dw, r, scale, rs, rc, z0)
+#define J0(MM) hipLaunchKernelGGL((k_jacobi0<MM, MT, RT, ZT>), GRID8(ne * nb, 256), 0, s, ne, nb, Dw, r, scale, rs, rc, z0, gs)
     M_SWITCH(J0)
 #undef J0
 }
 #define INST_J0(MT, RT, ZT) \
-    template void launch_jacobi0<MT, RT, ZT>(int, int, int, const MT *, const RT *, const double *, RT *, ZT *, ZT *, hipStream_t);
+    template void launch_jacobi0<MT, RT, ZT>(int, int, int, const MT *, const RT *, const double *, RT *, ZT *, ZT *, hipStream_t, GsLag);
 INST_J0(double, double, double)
 INST_J0(float, double, double)
 INST_J0(double, float, float)
@@ -1863,11 +1917,16 @@ void launch_dots(int64_t len, int nb, int nd, const VT *X, int64_t xstride, cons
 template <typename VT>
 void launch_gs_norm_givens(int64_t len, int nb, int nd, const double *h, const VT *V, int64_t vstride, VT *w,
                            double *partial, double *hn, int j, int restart, double *gm, const double *bnorm,
-                           double *resid_host, hipStream_t s) {
+                           double *resid_host, hipStream_t s, const int *run) {
     const int g = red_grid(len, nb);
-    hipLaunchKernelGGL(k_gs_update_norm<VT>, dim3(g), dim3(256), 0, s, len, nb, nd, h, V, vstride, w, partial);
+    hipLaunchKernelGGL(k_gs_update_norm<VT>, dim3(g), dim3(256), 0, s, len, nb, nd, h, V, vstride, w, partial, run);
     hipLaunchKernelGGL(k_norm_givens, dim3(nb), dim3(256), 0, s, g, nb, partial, hn, j, restart, h, gm, bnorm,
-                       resid_host);
+                       resid_host, run);
+}
+void launch_pyth_givens(int nb, int j, int restart, double floor, const double *hcol, double *hn, double *gm,
+                        const double *bnorm, double *resid_host, int *expl, hipStream_t s) {
+    hipLaunchKernelGGL(k_pyth_givens, dim3(1), dim3(64), 0, s, nb, j, restart, floor, hcol, hn, gm, bnorm, resid_host,
+                       expl);
 }
 void launch_pcg_update_norm(int64_t len, int nb, const double *num, const double *den, const double *p,
                             const double *w, double *x, double *res, double *partial, double *rr_host,
@@ -1892,10 +1951,10 @@ template void launch_dots<float>(int64_t, int, int, const float *, int64_t, cons
                                  double *, hipStream_t);
 template void launch_gs_norm_givens<double>(int64_t, int, int, const double *, const double *, int64_t, double *,
                                             double *, double *, int, int, double *, const double *, double *,
-                                            hipStream_t);
+                                            hipStream_t, const int *);
 template void launch_gs_norm_givens<float>(int64_t, int, int, const double *, const float *, int64_t, float *,
                                            double *, double *, int, int, double *, const double *, double *,
-                                           hipStream_t);
+                                           hipStream_t, const int *);
 template void launch_lincomb<double>(int64_t, int, int, const double *, const double *, int64_t, double *,
                                      hipStream_t);
 template void launch_lincomb<float>(int64_t, int, int, const double *, const float *, int64_t, double *,
