@@ -628,10 +628,28 @@ bool any_nonfinite(const std::vector<double> &v) {
 }
 
 // rel[r] = ||rhat - S lam|| / ||rhat|| with the FP64 operator; the residual stays in out.
+// the true residual rhat - S lam with the FP64 operator, and its norm relative to ||rhat||;
+// out32: stored as FP32 (rounded once, straight into the FP32 inner solve's first basis slot)
+// and its norm taken from that FP32 vector
 void true_residual(hdg_ctx *c, int nb, const double *rhat, const double *lam, double *out,
-                   std::vector<double> &rel, hipStream_t s) {
-    op_apply(c, nb, HDG_FP64, lam, rhat, out, s, HDG_KERNEL_RESIDUAL);
-    const double *h = dots_now(c, nb, out, out, scal(c, SC_RR), s);
+                   std::vector<double> &rel, hipStream_t s, bool out32 = false) {
+    const double *h;
+    if (out32) {
+        const double m = c->m, ne = c->n_facet;
+        Timed t(c, HDG_KERNEL_RESIDUAL, HDG_FP64, s, nb, 8, 4, ne * (5 * m * m * 8 + 16) + nb * ne * m * (8 + 8 + 4));
+        for (int rep = 0; rep < t.repeats(); ++rep)
+            hdg::launch_trace_residual_f32(c->m, c->n_facet, nb, c->S64, c->nbr, lam, rhat,
+                                           reinterpret_cast<float *>(out), s, c->rhs_block);
+        check_launch();
+        hdg::launch_dots<float>(vec_len(c), nb, 1, reinterpret_cast<const float *>(out), 0,
+                                reinterpret_cast<const float *>(out), c->red, scal(c, SC_RR), lag_dev(c, 2), s);
+        check_launch();
+        HDG_HIP_CHECK(hipStreamSynchronize(s));
+        h = c->hlag + 64 * 2;
+    } else {
+        op_apply(c, nb, HDG_FP64, lam, rhat, out, s, HDG_KERNEL_RESIDUAL);
+        h = dots_now(c, nb, out, out, scal(c, SC_RR), s);
+    }
     for (int r = 0; r < nb; ++r) {
         const double bn2 = c->hbn2[r];
         rel[r] = bn2 > 0 ? std::sqrt(h[r] / bn2) : std::sqrt(h[r]);
@@ -738,11 +756,7 @@ int solve_fgmres(hdg_ctx *c, int nb, int vc_prec, int op_prec, double inner_eta,
     };
     while (true) {
         set32(false);
-        true_residual(c, nb, rhat, lam, f32 ? c->kr : c->kV, rel, s);
-        if (f32) {
-            hdg::launch_to_f32(n * nb, c->kr, reinterpret_cast<float *>(c->kV), s);
-            check_launch();
-        }
+        true_residual(c, nb, rhat, lam, c->kV, rel, s, f32);
         if (any_nonfinite(rel)) return done_info(HDG_EBREAKDOWN);
         if (all_below(rel, rtol)) return done_info(HDG_OK);
         if (its >= c->opt.maxit) return done_info(HDG_ENOTCONV);

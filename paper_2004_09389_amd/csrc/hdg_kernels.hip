@@ -378,10 +378,10 @@ __global__ void k_facet_rows(int ne, int nk, const double *__restrict__ Sloc, co
 // five facets of its block row and produces all m rows, so every matrix
 // entry is read exactly once per apply and there are no write conflicts.
 
-template <int M, typename MT, typename XT, typename YT, bool NB1>
+template <int M, typename MT, typename XT, typename YT, bool NB1, typename BT = YT>
 __global__ __launch_bounds__(256) void k_trace_apply(int ne, int nb, const MT *__restrict__ S,
                                                      const int *__restrict__ nbr, const XT *__restrict__ x,
-                                                     const YT *__restrict__ b, YT *__restrict__ y) {
+                                                     const BT *__restrict__ b, YT *__restrict__ y) {
     using AT = typename Acc<MT>::type;
     constexpr int V = Wide<MT>::V, C = 5 * M * M, G = padded(C, V) / V;
     const int t = xcd_block() * blockDim.x + threadIdx.x;
@@ -1437,10 +1437,10 @@ __device__ __forceinline__ void store_raw(T *__restrict__ p, const T (&d)[RB]) {
 // Latency: a lane requests its four neighbour ids and its own facet's values
 // before the block stages its rows, so those waits overlap the staging; each
 // neighbour then costs one wait (its values), not two (id, then values).
-template <int M, typename MT, typename XT, typename YT, int RB>
+template <int M, typename MT, typename XT, typename YT, int RB, typename BT = YT>
 __global__ __launch_bounds__(1024) void k_trace_apply_rb(int ne, int nb, const MT *__restrict__ S,
                                                          const int *__restrict__ nbr, const XT *__restrict__ x,
-                                                         const YT *__restrict__ b, YT *__restrict__ y) {
+                                                         const BT *__restrict__ b, YT *__restrict__ y) {
     using AT = typename Acc<MT>::type;
     constexpr int V = Wide<MT>::V, C = 5 * M * M, G = padded(C, V) / V;
     __shared__ __attribute__((aligned(16))) MT sm[G * RB_FACETS * V];
@@ -1735,6 +1735,22 @@ void launch_trace_apply(int M, int ne, int nb, const MT *S, const int *nbr, cons
     M_SWITCH(TA)
 #undef TA
 }
+// FP64 residual b - S x rounded once to FP32 on output (the first vector of the
+// FP32 inner solve of a refinement step)
+void launch_trace_residual_f32(int M, int ne, int nb, const double *S, const int *nbr, const double *x,
+                               const double *b, float *y, hipStream_t s, int rhs_block) {
+    if (rhs_blocked_m(M, nb, rhs_block)) {
+#define TAB(MM) hipLaunchKernelGGL((k_trace_apply_rb<MM, double, double, float, 4, double>), GRID_RB(ne, nb), 0, s, ne, nb, S, nbr, x, b, y)
+        M_SWITCH_RB(TAB)
+#undef TAB
+        return;
+    }
+#define TA(MM)                                                                                          \
+    if (nb == 1) hipLaunchKernelGGL((k_trace_apply<MM, double, double, float, true, double>), GRID8(ne * nb, 256), 0, s, ne, nb, S, nbr, x, b, y); \
+    else hipLaunchKernelGGL((k_trace_apply<MM, double, double, float, false, double>), GRID8(ne * nb, 256), 0, s, ne, nb, S, nbr, x, b, y)
+    M_SWITCH(TA)
+#undef TA
+}
 #define INST_TA(MT, XT, YT) \
     template void launch_trace_apply<MT, XT, YT>(int, int, int, const MT *, const int *, const XT *, const YT *, YT *, hipStream_t, int);
 INST_TA(double, double, double)
@@ -1805,13 +1821,6 @@ void launch_restrict_trace(int p, int nv, int nb, const int *vf_row, const int *
 template void launch_restrict_trace<double>(int, int, int, const int *, const int *, const double *, double *, hipStream_t);
 template void launch_restrict_trace<float>(int, int, int, const int *, const int *, const float *, double *, hipStream_t);
 
-__global__ void k_to_f32(int64_t n, const double *__restrict__ src, float *__restrict__ dst) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) dst[i] = (float)src[i];
-}
-void launch_to_f32(int64_t n, const double *src, float *dst, hipStream_t s) {
-    hipLaunchKernelGGL(k_to_f32, GRID(n, 256), 0, s, n, src, dst);
-}
 
 // P1 launchers: the level vectors hold double values, or float values in the
 // same buffers when f32 is set (the V-cycle of a mixed-precision solve).
