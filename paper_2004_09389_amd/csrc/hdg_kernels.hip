@@ -49,7 +49,9 @@ __global__ __launch_bounds__(64) void k_cell_condense(int nk, const double *__re
     __shared__ double Cm[nt * nc];
     __shared__ double fac[nc];
     __shared__ double fq[nq];
-    const int K = blockIdx.x;
+    // each XCD takes a contiguous range of cells, so the outputs (component-major,
+    // cells fastest) of neighbouring cells meet in one L2 before they are written back
+    const int K = xcd_block();
     const int lane = threadIdx.x;
     if (K >= nk) return;
 
@@ -223,9 +225,13 @@ __global__ __launch_bounds__(64) void k_cell_condense(int nk, const double *__re
         for (int c = lane; c < LD; c += 64) aug[k * LD + c] *= ip;
         for (int r = lane; r < nc; r += 64) fac[r] = aug[r * LD + k];
         __syncthreads();
-        for (int idx = lane; idx < nc * (LD - k); idx += 64) {
-            const int r = idx / (LD - k), c = k + idx % (LD - k);
-            if (r != k) aug[r * LD + c] -= fac[r] * aug[k * LD + c];
+        // a lane per column (the pivot row's entry in a register), all rows down it:
+        // no index division, consecutive lanes on consecutive LDS words
+        for (int c = k + lane; c < LD; c += 64) {
+            const double pk = aug[k * LD + c];
+#pragma unroll
+            for (int r = 0; r < nc; ++r)
+                if (r != k) aug[r * LD + c] -= fac[r] * pk;
         }
         __syncthreads();
     }
@@ -1695,7 +1701,7 @@ bool rhs_blocked(int nb, int rhs_block) {
 void launch_cell_condense(int p, int nu, int nk, const double *corners, const double *ref, CellParams cp,
                           double *Sloc, double *Zr, double *Ar, double *Wr, int *err, hipStream_t s, double *Aout,
                           double *Bnout) {
-#define CK(P, NU) hipLaunchKernelGGL((k_cell_condense<P, NU>), dim3(nk), dim3(64), 0, s, nk, corners, ref, cp, Sloc, Zr, Ar, Wr, err, Aout, Bnout)
+#define CK(P, NU) hipLaunchKernelGGL((k_cell_condense<P, NU>), dim3((unsigned)((nk + N_XCD - 1) / N_XCD * N_XCD)), dim3(64), 0, s, nk, corners, ref, cp, Sloc, Zr, Ar, Wr, err, Aout, Bnout)
     if (nu == 1) { switch (p) { case 1: CK(1, 1); break; case 2: CK(2, 1); break; case 3: CK(3, 1); break; } }
     else { switch (p) { case 1: CK(1, 2); break; case 2: CK(2, 2); break; case 3: CK(3, 2); break; } }
 #undef CK
