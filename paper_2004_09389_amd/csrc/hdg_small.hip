@@ -20,8 +20,10 @@
 // omega D^-1 r), restriction pi^T, one P1 multigrid V-cycle (damped Jacobi,
 // its first two sweeps fused, linear-interpolation transfers, dense coarsest
 // inverse) and prolongation pi fused into the first post-sweep.  Only the
-// order of the reduction sums differs (one workgroup instead of block
-// partials).
+// rounding differs: the order of the reduction sums (one workgroup instead of
+// block partials) and, for hierarchies of at most SMALL_P1_DENSE finest
+// vertices, the P1 V-cycle applied as its matrix (formed on the host by
+// applying the same cycle to unit vectors).
 #include "hdg_device.h"
 #include "hdg_kernels.h"
 
