@@ -287,23 +287,25 @@ double *p1_vcycle(hdg_ctx *c, int l, int nb, hipStream_t s, bool f32) {
         return L.x;
     }
     const double w = c->opt.p1_omega;
+    const int rb = c->rhs_block;
     double *x = L.x, *y = L.y;
     if (c->opt.p1_nu == 1) {
-        hdg::launch_p1_first(L.n, nb, L.dinv, w, L.b, x, s, f32);
+        hdg::launch_p1_first(L.n, nb, L.dinv, w, L.b, x, s, f32, rb);
     } else {
-        hdg::launch_p1_pre2(L.n, L.w, nb, L.col, L.val, L.diag, L.dinv, w, L.b, x, s, f32);
+        hdg::launch_p1_pre2(L.n, L.w, nb, L.col, L.val, L.diag, L.dinv, w, L.b, x, s, f32, rb);
         for (int k = 2; k < c->opt.p1_nu; ++k) {
-            hdg::launch_p1_sweep(L.n, L.w, nb, L.col, L.val, L.diag, L.dinv, w, L.b, x, nullptr, nullptr, y, s, f32);
+            hdg::launch_p1_sweep(L.n, L.w, nb, L.col, L.val, L.diag, L.dinv, w, L.b, x, nullptr, nullptr, y, s, f32,
+                                 rb);
             std::swap(x, y);
         }
     }
-    hdg::launch_p1_resid(L.n, L.w, nb, L.col, L.val, L.diag, L.b, x, y, s, f32);
+    hdg::launch_p1_resid(L.n, L.w, nb, L.col, L.val, L.diag, L.b, x, y, s, f32, rb);
     hdg::P1LevelDev &C = c->lev[l - 1];
-    hdg::launch_p1_restrict(C.n, nb, L.crow, L.ccol, L.cw, y, C.b, s, f32);
+    hdg::launch_p1_restrict(C.n, nb, L.crow, L.ccol, L.cw, y, C.b, s, f32, rb);
     const double *xc = p1_vcycle(c, l - 1, nb, s, f32);
     for (int k = 0; k < c->opt.p1_nu; ++k) {
         hdg::launch_p1_sweep(L.n, L.w, nb, L.col, L.val, L.diag, L.dinv, w, L.b, x, k == 0 ? xc : nullptr,
-                             L.parents, y, s, f32);
+                             L.parents, y, s, f32, rb);
         std::swap(x, y);
     }
     return x;

@@ -153,18 +153,22 @@ void launch_restrict_trace(int p, int nv, int nb, const int *vf_row, const int *
 
 // P1 level kernels; f32: the level vectors (b, x, y, xc, r, bc) hold float values
 // in their double buffers (the V-cycle of a mixed-precision solve)
+// P1 level launchers: rb == 4 with nb % 4 == 0 takes four right-hand sides per
+// thread (the same bits as rb == 1).
 void launch_p1_first(int n, int nb, const double *dinv, double omega, const double *b, double *x, hipStream_t s,
-                     bool f32 = false);
+                     bool f32 = false, int rb = 1);
 void launch_p1_pre2(int n, int W, int nb, const int *col, const double *val, const double *diag,
-                    const double *dinv, double omega, const double *b, double *x, hipStream_t s, bool f32 = false);
+                    const double *dinv, double omega, const double *b, double *x, hipStream_t s, bool f32 = false,
+                    int rb = 1);
 // y = x + w D^-1 (b - A x); with xc != nullptr, x is first updated in place to x + P xc
 void launch_p1_sweep(int n, int W, int nb, const int *col, const double *val, const double *diag,
                      const double *dinv, double omega, const double *b, double *x, const double *xc,
-                     const int *parents, double *y, hipStream_t s, bool f32 = false);
+                     const int *parents, double *y, hipStream_t s, bool f32 = false, int rb = 1);
 void launch_p1_resid(int n, int W, int nb, const int *col, const double *val, const double *diag,
-                     const double *b, const double *x, double *y, hipStream_t s, bool f32 = false);
+                     const double *b, const double *x, double *y, hipStream_t s, bool f32 = false,
+                     int rb = 1);
 void launch_p1_restrict(int nc, int nb, const int *crow, const int *ccol, const double *cw, const double *r,
-                        double *bc, hipStream_t s, bool f32 = false);
+                        double *bc, hipStream_t s, bool f32 = false, int rb = 1);
 void launch_dense_mv(int n, int nb, const double *Ainv, const double *b, double *x, hipStream_t s, bool f32 = false);
 void launch_p1_tail(const P1Tail &T, int nb, hipStream_t s, bool f32 = false);
 

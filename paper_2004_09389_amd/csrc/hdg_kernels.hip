@@ -1438,6 +1438,216 @@ __device__ __forceinline__ void store_raw(T *__restrict__ p, const T (&d)[RB]) {
     }
 }
 
+// ---------------------------------------------------------------- P1 levels, four right-hand sides per thread
+// With nb % 4 == 0 a thread of the P1 level kernels takes four consecutive
+// right-hand sides of one vertex: each index and matrix entry is loaded once
+// for four values, vector values move in 16-byte loads (32 bytes for FP64
+// vectors), and a launch has a quarter of the wavefronts of the per-(vertex,
+// rhs) form, each with four times the loads in flight.  The arithmetic per
+// entry is the per-(vertex, rhs) kernels', so the two shapes give the same bits.
+
+template <typename VT>
+__device__ __forceinline__ void p1_st4(VT *__restrict__ p, const double (&d)[4]) {
+    if constexpr (std::is_same<VT, double>::value) {
+        *reinterpret_cast<dbl2_t *>(p) = dbl2_t{d[0], d[1]};
+        *reinterpret_cast<dbl2_t *>(p + 2) = dbl2_t{d[2], d[3]};
+    } else {
+        *reinterpret_cast<trace_flt4_t *>(p) = trace_flt4_t{(float)d[0], (float)d[1], (float)d[2], (float)d[3]};
+    }
+}
+
+// s = (A x)[v] at right-hand sides r0..r0+3: diagonal term first, then the ELL entries in order
+template <int WT, typename VT>
+__device__ __forceinline__ void p1_ax4(int v, int n, int W, int nb, int r0, const int *ell_col,
+                                       const double *ell_val, const double *diag, const VT *x, double (&s)[4]) {
+    if (WT) W = WT;
+    double xv[4];
+    load_rb<4>(x + (size_t)v * nb + r0, xv);
+    const double d = diag[v];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) s[q] = d * xv[q];
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        const double a = ell_val[(size_t)k * n + v];
+        double xu[4];
+        load_rb<4>(x + (size_t)ell_col[(size_t)k * n + v] * nb + r0, xu);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) s[q] += a * xu[q];
+    }
+}
+
+// thread -> (vertex v, first right-hand side r0); false past the end
+__device__ __forceinline__ bool p1_thread4(int n, int nb, int &v, int &r0) {
+    const int tpv = nb >> 2;
+    const int t = xcd_block() * blockDim.x + threadIdx.x;
+    if (t >= n * tpv) return false;
+    v = t / tpv;
+    r0 = (t - v * tpv) * 4;
+    return true;
+}
+
+template <typename VT>
+__global__ void k_p1_first4(int n, int nb, const double *__restrict__ dinv, double omega,
+                            const VT *__restrict__ b, VT *__restrict__ x) {
+    int v, r0;
+    if (!p1_thread4(n, nb, v, r0)) return;
+    const size_t o = (size_t)v * nb + r0;
+    double bv[4], out[4];
+    load_rb<4>(b + o, bv);
+    const double dv = dinv[v];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) out[q] = omega * dv * bv[q];
+    p1_st4(x + o, out);
+}
+
+template <int WT, typename VT>
+__global__ void k_p1_pre2_4(int n, int W, int nb, const int *__restrict__ ell_col, const double *__restrict__ ell_val,
+                            const double *__restrict__ diag, const double *__restrict__ dinv, double omega,
+                            const VT *__restrict__ b, VT *__restrict__ x) {
+    int v, r0;
+    if (!p1_thread4(n, nb, v, r0)) return;
+    if (WT) W = WT;
+    const size_t o = (size_t)v * nb + r0;
+    double bv[4], ax[4], out[4];
+    load_rb<4>(b + o, bv);
+    const double dv = dinv[v], dd = diag[v];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) ax[q] = dd * omega * dv * bv[q];
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        const int u = ell_col[(size_t)k * n + v];
+        const double a = ell_val[(size_t)k * n + v], du = dinv[u];
+        double bu[4];
+        load_rb<4>(b + (size_t)u * nb + r0, bu);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) ax[q] += a * omega * du * bu[q];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const double x1 = omega * dv * bv[q];
+        out[q] = x1 + omega * dv * (bv[q] - ax[q]);
+    }
+    p1_st4(x + o, out);
+}
+
+template <int WT, typename VT>
+__global__ void k_p1_sweep4(int n, int W, int nb, const int *__restrict__ ell_col, const double *__restrict__ ell_val,
+                            const double *__restrict__ diag, const double *__restrict__ dinv, double omega,
+                            const VT *__restrict__ b, const VT *__restrict__ x, VT *__restrict__ y) {
+    int v, r0;
+    if (!p1_thread4(n, nb, v, r0)) return;
+    const size_t o = (size_t)v * nb + r0;
+    double ax[4], xv[4], bv[4], out[4];
+    p1_ax4<WT>(v, n, W, nb, r0, ell_col, ell_val, diag, x, ax);
+    load_rb<4>(x + o, xv);
+    load_rb<4>(b + o, bv);
+    const double dv = dinv[v];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) out[q] = xv[q] + omega * dv * (bv[q] - ax[q]);
+    p1_st4(y + o, out);
+}
+
+template <typename VT>
+__global__ void k_p1_prolong4(int n, int nb, const int *__restrict__ parents, const VT *__restrict__ xc,
+                              VT *__restrict__ x) {
+    int v, r0;
+    if (!p1_thread4(n, nb, v, r0)) return;
+    const size_t o = (size_t)v * nb + r0;
+    double xv[4], c0[4], c1[4], out[4];
+    load_rb<4>(x + o, xv);
+    load_rb<4>(xc + (size_t)parents[2 * v] * nb + r0, c0);
+    load_rb<4>(xc + (size_t)parents[2 * v + 1] * nb + r0, c1);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) out[q] = xv[q] + 0.5 * (c0[q] + c1[q]);
+    p1_st4(x + o, out);
+}
+
+template <int WT, typename VT>
+__global__ void k_p1_resid4(int n, int W, int nb, const int *__restrict__ ell_col, const double *__restrict__ ell_val,
+                            const double *__restrict__ diag, const VT *__restrict__ b, const VT *__restrict__ x,
+                            VT *__restrict__ y) {
+    int v, r0;
+    if (!p1_thread4(n, nb, v, r0)) return;
+    const size_t o = (size_t)v * nb + r0;
+    double ax[4], bv[4], out[4];
+    p1_ax4<WT>(v, n, W, nb, r0, ell_col, ell_val, diag, x, ax);
+    load_rb<4>(b + o, bv);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) out[q] = bv[q] - ax[q];
+    p1_st4(y + o, out);
+}
+
+// the children of a coarse vertex eight at a time (index clamped, surplus terms
+// dropped), summed in list order as in the per-(vertex, rhs) restriction
+template <typename VT>
+__global__ void k_p1_restrict4(int nc, int nb, const int *__restrict__ crow, const int *__restrict__ ccol,
+                               const double *__restrict__ cw, const VT *__restrict__ r, VT *__restrict__ bc) {
+    int c, r0;
+    if (!p1_thread4(nc, nb, c, r0)) return;
+    const int k0 = crow[c], cnt = crow[c + 1] - k0;
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int g = 0; g < cnt; g += 8) {
+        double t[8][4];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int k = k0 + min(g + u, cnt - 1);
+            const double w = cw[k];
+            double rv[4];
+            load_rb<4>(r + (size_t)ccol[k] * nb + r0, rv);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) t[u][q] = w * rv[q];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) s[q] = g + u < cnt ? s[q] + t[u][q] : s[q];
+    }
+    p1_st4(bc + (size_t)c * nb + r0, s);
+}
+
+// x = Ainv b on the coarsest level, one 256-thread block per row i.  A thread
+// takes G consecutive right-hand sides (G = 4 when nb = 4 NQ with NQ a power of
+// two, G = 1 when nb = 1) and one of the block's 256 / NQ phases j = phase +
+// k (256 / NQ), four columns' loads in flight at a time.  The partial sums are
+// combined by a butterfly within each wavefront and then over the four
+// wavefronts in order: a fixed summation order for a given nb.
+template <int G, typename VT>
+__global__ __launch_bounds__(256) void k_dense_row(int n, int nb, const double *__restrict__ Ainv,
+                                                   const VT *__restrict__ b, VT *__restrict__ x) {
+    __shared__ double part[4][64];
+    const int i = blockIdx.x, tid = threadIdx.x;
+    const int NQ = nb / G, JP = 256 / NQ;
+    const int rq = tid & (NQ - 1), jp = tid / NQ, r0 = rq * G;
+    const double *Ai = Ainv + (size_t)i * n;
+    double s[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) s[g] = 0.0;
+    for (int j0 = jp; j0 < n; j0 += 4 * JP) {
+        double a[4], bv[4][G];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int j = min(j0 + u * JP, n - 1);
+            a[u] = Ai[j];
+            if constexpr (G == 4) load_rb<4>(b + (size_t)j * nb + r0, bv[u]);
+            else bv[u][0] = (double)b[j];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (j0 + u * JP < n)
+#pragma unroll
+                for (int g = 0; g < G; ++g) s[g] += a[u] * bv[u][g];
+    }
+    for (int off = NQ; off < 64; off <<= 1)
+#pragma unroll
+        for (int g = 0; g < G; ++g) s[g] += __shfl_xor(s[g], off, 64);
+    const int wv = tid >> 6, lane = tid & 63;
+    if (lane < NQ)
+#pragma unroll
+        for (int g = 0; g < G; ++g) part[wv][lane * G + g] = s[g];
+    __syncthreads();
+    if (tid < nb) x[(size_t)i * nb + tid] = (VT)(((part[0][tid] + part[1][tid]) + part[2][tid]) + part[3][tid]);
+}
+
 // y = S x or y = b - S x
 //
 // Latency: a lane requests its four neighbour ids and its own facet's values
@@ -1837,42 +2047,69 @@ static const VT *pv(const double *p) { return reinterpret_cast<const VT *>(p); }
 #define P1_TYPED(CALL) \
     if (f32) { using VT = float; CALL; } else { using VT = double; CALL; }
 
+// rb == 4 with nb % 4 == 0: four right-hand sides per thread (same bits)
+static bool p1_r4(int rb, int nb) { return rb == 4 && nb % 4 == 0; }
+#define P1_GRID(n, nb, r4) GRID8((int64_t)(n) * ((r4) ? (nb) / 4 : (nb)), 256)
+
 void launch_p1_first(int n, int nb, const double *dinv, double omega, const double *b, double *x, hipStream_t s,
-                     bool f32) {
-    P1_TYPED(hipLaunchKernelGGL(k_p1_first<VT>, GRID8(n * nb, 256), 0, s, n, nb, dinv, omega, pv<VT>(b), pv<VT>(x)))
+                     bool f32, int rb) {
+    const bool r4 = p1_r4(rb, nb);
+    P1_TYPED(if (r4) hipLaunchKernelGGL(k_p1_first4<VT>, P1_GRID(n, nb, r4), 0, s, n, nb, dinv, omega, pv<VT>(b),
+                                        pv<VT>(x));
+             else hipLaunchKernelGGL(k_p1_first<VT>, P1_GRID(n, nb, r4), 0, s, n, nb, dinv, omega, pv<VT>(b),
+                                     pv<VT>(x)))
 }
 void launch_p1_pre2(int n, int W, int nb, const int *col, const double *val, const double *diag,
-                    const double *dinv, double omega, const double *b, double *x, hipStream_t s, bool f32) {
-    P1_TYPED(if (W == 6) hipLaunchKernelGGL((k_p1_pre2<6, VT>), GRID8(n * nb, 256), 0, s, n, W, nb, col, val, diag,
-                                             dinv, omega, pv<VT>(b), pv<VT>(x));
-             else hipLaunchKernelGGL((k_p1_pre2<0, VT>), GRID8(n * nb, 256), 0, s, n, W, nb, col, val, diag, dinv,
-                                     omega, pv<VT>(b), pv<VT>(x)))
+                    const double *dinv, double omega, const double *b, double *x, hipStream_t s, bool f32, int rb) {
+    const bool r4 = p1_r4(rb, nb);
+#define PRE2(K, WW) hipLaunchKernelGGL((K<WW, VT>), P1_GRID(n, nb, r4), 0, s, n, W, nb, col, val, diag, dinv, omega, \
+                                       pv<VT>(b), pv<VT>(x))
+    P1_TYPED(if (r4) { if (W == 6) PRE2(k_p1_pre2_4, 6); else PRE2(k_p1_pre2_4, 0); }
+             else { if (W == 6) PRE2(k_p1_pre2, 6); else PRE2(k_p1_pre2, 0); })
+#undef PRE2
 }
 void launch_p1_sweep(int n, int W, int nb, const int *col, const double *val, const double *diag,
                      const double *dinv, double omega, const double *b, double *x, const double *xc,
-                     const int *parents, double *y, hipStream_t s, bool f32) {
+                     const int *parents, double *y, hipStream_t s, bool f32, int rb) {
+    const bool r4 = p1_r4(rb, nb);
+#define SWP(K, WW) hipLaunchKernelGGL((K<WW, VT>), P1_GRID(n, nb, r4), 0, s, n, W, nb, col, val, diag, dinv, omega, \
+                                      pv<VT>(b), pv<VT>(x), pv<VT>(y))
     P1_TYPED(
-        if (xc) hipLaunchKernelGGL(k_p1_prolong<VT>, GRID8(n * nb, 256), 0, s, n, nb, parents, pv<VT>(xc), pv<VT>(x));
-        if (W == 6) hipLaunchKernelGGL((k_p1_sweep<6, VT>), GRID8(n * nb, 256), 0, s, n, W, nb, col, val, diag, dinv,
-                                       omega, pv<VT>(b), pv<VT>(x), pv<VT>(y));
-        else hipLaunchKernelGGL((k_p1_sweep<0, VT>), GRID8(n * nb, 256), 0, s, n, W, nb, col, val, diag, dinv, omega,
-                                pv<VT>(b), pv<VT>(x), pv<VT>(y)))
+        if (xc) {
+            if (r4) hipLaunchKernelGGL(k_p1_prolong4<VT>, P1_GRID(n, nb, r4), 0, s, n, nb, parents, pv<VT>(xc), pv<VT>(x));
+            else hipLaunchKernelGGL(k_p1_prolong<VT>, P1_GRID(n, nb, r4), 0, s, n, nb, parents, pv<VT>(xc), pv<VT>(x));
+        }
+        if (r4) { if (W == 6) SWP(k_p1_sweep4, 6); else SWP(k_p1_sweep4, 0); }
+        else { if (W == 6) SWP(k_p1_sweep, 6); else SWP(k_p1_sweep, 0); })
+#undef SWP
 }
 void launch_p1_resid(int n, int W, int nb, const int *col, const double *val, const double *diag,
-                     const double *b, const double *x, double *y, hipStream_t s, bool f32) {
-    P1_TYPED(if (W == 6) hipLaunchKernelGGL((k_p1_resid<6, VT>), GRID8(n * nb, 256), 0, s, n, W, nb, col, val, diag,
-                                             pv<VT>(b), pv<VT>(x), pv<VT>(y));
-             else hipLaunchKernelGGL((k_p1_resid<0, VT>), GRID8(n * nb, 256), 0, s, n, W, nb, col, val, diag,
-                                     pv<VT>(b), pv<VT>(x), pv<VT>(y)))
+                     const double *b, const double *x, double *y, hipStream_t s, bool f32, int rb) {
+    const bool r4 = p1_r4(rb, nb);
+#define RES(K, WW) hipLaunchKernelGGL((K<WW, VT>), P1_GRID(n, nb, r4), 0, s, n, W, nb, col, val, diag, pv<VT>(b), \
+                                      pv<VT>(x), pv<VT>(y))
+    P1_TYPED(if (r4) { if (W == 6) RES(k_p1_resid4, 6); else RES(k_p1_resid4, 0); }
+             else { if (W == 6) RES(k_p1_resid, 6); else RES(k_p1_resid, 0); })
+#undef RES
 }
 void launch_p1_restrict(int nc, int nb, const int *crow, const int *ccol, const double *cw, const double *r,
-                        double *bc, hipStream_t s, bool f32) {
-    P1_TYPED(hipLaunchKernelGGL(k_p1_restrict<VT>, GRID8(nc * nb, 256), 0, s, nc, nb, crow, ccol, cw, pv<VT>(r),
-                                pv<VT>(bc)))
+                        double *bc, hipStream_t s, bool f32, int rb) {
+    const bool r4 = p1_r4(rb, nb);
+    P1_TYPED(if (r4) hipLaunchKernelGGL(k_p1_restrict4<VT>, P1_GRID(nc, nb, r4), 0, s, nc, nb, crow, ccol, cw,
+                                        pv<VT>(r), pv<VT>(bc));
+             else hipLaunchKernelGGL(k_p1_restrict<VT>, P1_GRID(nc, nb, r4), 0, s, nc, nb, crow, ccol, cw, pv<VT>(r),
+                                     pv<VT>(bc)))
 }
+#undef P1_GRID
+// the row-block product for nb = 1 and nb = 4 NQ (NQ = 1, 2, 4, 8, 16), else a
+// wavefront per (row, chunk of 8 right-hand sides)
 void launch_dense_mv(int n, int nb, const double *Ainv, const double *b, double *x, hipStream_t s, bool f32) {
-    P1_TYPED(if (nb == 1) hipLaunchKernelGGL((k_dense_mv<1, VT>), GRID((int64_t)n * 64, 256), 0, s, n, nb, Ainv,
-                                              pv<VT>(b), pv<VT>(x));
+    const int nq = nb / 4;
+    const bool g4 = nb % 4 == 0 && nq <= 16 && (nq & (nq - 1)) == 0;
+    P1_TYPED(if (nb == 1) hipLaunchKernelGGL((k_dense_row<1, VT>), dim3(n), dim3(256), 0, s, n, nb, Ainv, pv<VT>(b),
+                                              pv<VT>(x));
+             else if (g4) hipLaunchKernelGGL((k_dense_row<4, VT>), dim3(n), dim3(256), 0, s, n, nb, Ainv, pv<VT>(b),
+                                             pv<VT>(x));
              else hipLaunchKernelGGL((k_dense_mv<8, VT>), GRID((int64_t)n * ((nb + 7) / 8) * 64, 256), 0, s, n, nb,
                                      Ainv, pv<VT>(b), pv<VT>(x)))
 }
