@@ -256,7 +256,8 @@ int hdg_mg_vcycle(hdg_ctx *ctx, int32_t nrhs, int32_t precision, const double *r
 
 /* Step 2: solve S lam = rhat to ||rhat - S lam|| <= rtol ||rhat|| per RHS.
  * lam is the initial guess on entry (device, [n_facet][facet_dofs][nrhs]) and the
- * solution on exit.  info: (host) [nrhs], may be NULL.  Synchronises the stream. */
+ * solution on exit.  info: (host) [nrhs], may be NULL.  Returns when lam and info
+ * are complete (as hdg_stage_solve). */
 int hdg_solve(hdg_ctx *ctx, int32_t nrhs, const double *rhat, double *lam,
               hdg_solve_info *info, void *stream);
 
@@ -274,7 +275,9 @@ int hdg_recover(hdg_ctx *ctx, int32_t nrhs, const double *r_cell, const double *
  * (device) [n_cell][3][n_loc][nrhs]; lam: (device, output)
  * [n_facet][facet_dofs][nrhs]; info: (host) [nrhs], may be NULL.  Returns as
  * hdg_solve (HDG_ENOTCONV / HDG_EBREAKDOWN with lam and q_cell still written).
- * Synchronises the stream. */
+ * Returns when lam, q_cell and info are complete: the stream is synchronised,
+ * or, on the single-launch path, every workgroup has published its record
+ * (written after its outputs, behind a system-scope fence). */
 int hdg_stage_solve(hdg_ctx *ctx, int32_t nrhs, const double *r_cell, double *lam, double *q_cell,
                     hdg_solve_info *info, void *stream);
 

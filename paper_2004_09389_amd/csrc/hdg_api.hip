@@ -2,6 +2,7 @@
 // solve (condense, Krylov on the trace system, recover), the non-nested
 // V-cycle and measurement helpers.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -873,6 +874,7 @@ int solve_small(hdg_ctx *c, int nb, int kry, bool stage, const double *rhat, con
     A.nb = nb;
     A.nlev = (int)c->lev.size();
     A.stage_ops = c->small_stage_ops ? 1 : 0;
+    A.image = c->small_image;
     A.p1B = c->small_p1B;
     A.krylov = kry;
     A.restart = c->opt.restart;
@@ -910,12 +912,29 @@ int solve_small(hdg_ctx *c, int nb, int kry, bool stage, const double *rhat, con
     A.V = c->small_V;
     A.Z = c->small_Z;
     A.info = c->small_info;
+    // each workgroup writes its record's status last (after a system-scope fence):
+    // wait for those instead of for the stream, which reports the end of the
+    // launch a few microseconds later; bounded, then the stream decides
+    volatile double *rec = c->small_hinfo;
+    constexpr double pending = 1e300;
+    for (int r = 0; r < nb; ++r) rec[4 * r + 2] = pending;
     hdg::launch_solve_small(c->p, stage, A, c->small_lds, s);
     check_launch();
-    HDG_HIP_CHECK(hipStreamSynchronize(s));
+    {
+        const auto t0 = std::chrono::steady_clock::now();
+        int r = 0;
+        while (r < nb) {
+            if (rec[4 * r + 2] != pending) {
+                ++r;
+            } else if (std::chrono::steady_clock::now() - t0 > std::chrono::seconds(2)) {
+                break;
+            }
+        }
+        if (r < nb) HDG_HIP_CHECK(hipStreamSynchronize(s));
+    }
     int status = HDG_OK;
     for (int r = 0; r < nb; ++r) {
-        const double *h = c->small_hinfo + 4 * r;
+        const volatile double *h = c->small_hinfo + 4 * r;
         const int st = (int)h[2];
         if (st == HDG_EBREAKDOWN) status = HDG_EBREAKDOWN;
         else if (st == HDG_ENOTCONV && status == HDG_OK) status = HDG_ENOTCONV;
@@ -1289,7 +1308,44 @@ void setup_impl(const hdg_mesh *levels, int nlev, const int32_t *const *parents,
             c->small_ok = true;
             c->small_stage_ops = with_ops <= limit;
             c->small_lds = lds;
-            if (nB) c->small_p1B = dev_upload(c, p1B);
+            if (nB) {
+                // transposed: the kernel's lanes take consecutive rows
+                std::vector<double> bt((size_t)nB * nB);
+                for (int i = 0; i < nB; ++i)
+                    for (int j = 0; j < nB; ++j) bt[(size_t)j * nB + i] = p1B[(size_t)i * nB + j];
+                c->small_p1B = dev_upload(c, bt);
+            }
+            if (c->small_stage_ops) {
+                // the operators packed once in the layout of their LDS copies
+                const size_t bytes = hdg::small_image_bytes(ne, m, lv.data(), (int)lv.size(), nB);
+                c->small_image = dev_alloc<char>(c, bytes);
+                HDG_HIP_CHECK(hipDeviceSynchronize());   // every operator is complete
+                hdg::small_image_walk(ne, m, lv.data(), (int)lv.size(), nB,
+                                      [&](hdg::SmallPart part, int l, size_t off, size_t nbytes) {
+                    const hdg::P1LevelDev &L = c->lev[l];
+                    const void *src = nullptr;
+                    switch (part) {
+                    case hdg::SP_S: src = c->S64; break;
+                    case hdg::SP_T: src = c->T64; break;
+                    case hdg::SP_DW: src = c->Dw64; break;
+                    case hdg::SP_NBR: src = c->nbr; break;
+                    case hdg::SP_FVERT: src = c->facet_vert; break;
+                    case hdg::SP_VF_ROW: src = c->vf_row; break;
+                    case hdg::SP_VF_COL: src = c->vf_col; break;
+                    case hdg::SP_B: src = c->small_p1B; break;
+                    case hdg::SP_COL: src = L.col; break;
+                    case hdg::SP_VAL: src = L.val; break;
+                    case hdg::SP_DIAG: src = L.diag; break;
+                    case hdg::SP_DINV: src = L.dinv; break;
+                    case hdg::SP_PARENTS: src = L.parents; break;
+                    case hdg::SP_CROW: src = L.crow; break;
+                    case hdg::SP_CCOL: src = L.ccol; break;
+                    case hdg::SP_CW: src = L.cw; break;
+                    case hdg::SP_AINV: src = c->coarse_inv; break;
+                    }
+                    HDG_HIP_CHECK(hipMemcpy(c->small_image + off, src, nbytes, hipMemcpyDeviceToDevice));
+                });
+            }
             const size_t v1 = (size_t)ne * m;
             c->small_V = dev_alloc<double>(c, (size_t)mr * (hdg::SMALL_MAXR + 1) * v1);
             c->small_Z = dev_alloc<double>(c, (size_t)mr * hdg::SMALL_MAXR * v1);

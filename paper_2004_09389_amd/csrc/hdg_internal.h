@@ -192,7 +192,8 @@ struct hdg_ctx {
     // persistent single-launch solve of small systems (hdg_small.hip)
     bool small_ok = false;                // the context qualifies (upwind flux, LDS footprint)
     bool small_stage_ops = false;         // ... and its operators fit in LDS as well
-    double *small_p1B = nullptr;          // the P1 V-cycle as a dense matrix (small hierarchies), or null
+    double *small_p1B = nullptr;          // the P1 V-cycle as a dense matrix, transposed (small hierarchies), or null
+    char *small_image = nullptr;          // the operators packed in the layout of their LDS copies
     size_t small_lds = 0;                 // dynamic LDS per workgroup
     double *small_V = nullptr, *small_Z = nullptr;   // FGMRES bases per right-hand side
     double *small_info = nullptr;         // [max_rhs][4] record of each solve: device view of small_hinfo

@@ -210,16 +210,66 @@ void launch_sqrt(int nb, const double *in, double *out, hipStream_t s);
 constexpr int SMALL_THREADS = 256;    // threads per workgroup (one workgroup per right-hand side)
 constexpr int SMALL_MAXR = 32;        // largest FGMRES restart length of the persistent solve
 constexpr int SMALL_P1_DENSE = 64;    // finest P1 levels up to this size apply the V-cycle as its matrix
+// The operators the persistent solve copies into LDS, packed once at setup into
+// one device image in the order and 16-byte alignment of their LDS copies, so
+// that the copy at the start of a launch is one loop with many loads in flight.
+// small_image_walk calls f(part, level, byte offset, bytes) for each operator in
+// image order (the levels only without the dense V-cycle matrix B, B only with
+// it) and returns the image size; the host packs with it and the kernel
+// publishes the LDS addresses with it (no per-level tables in private memory).
+enum SmallPart { SP_S, SP_T, SP_DW, SP_NBR, SP_FVERT, SP_VF_ROW, SP_VF_COL, SP_B, SP_COL, SP_VAL, SP_DIAG, SP_DINV,
+                 SP_PARENTS, SP_CROW, SP_CCOL, SP_CW, SP_AINV };
+template <typename F>
+__host__ __device__ inline size_t small_image_walk(int ne, int m, const P1Lev *lev, int nlev, int nB, F &&f) {
+    size_t o = 0;
+    auto put = [&](SmallPart part, int l, size_t bytes) {
+        f(part, l, o, bytes);
+        o += (bytes + 15) / 16 * 16;
+    };
+    const auto pad2 = [](int c) { return (size_t)((c + 1) / 2 * 2); };
+    const size_t NE = (size_t)ne;
+    put(SP_S, 0, 8 * pad2(5 * m * m) * NE);
+    put(SP_T, 0, 8 * pad2(4 * m * m) * NE);
+    put(SP_DW, 0, 8 * pad2(m * m) * NE);
+    put(SP_NBR, 0, 16 * NE);
+    put(SP_FVERT, 0, 8 * NE);
+    put(SP_VF_ROW, 0, 4 * ((size_t)lev[nlev - 1].n + 1));
+    put(SP_VF_COL, 0, 8 * NE);
+    if (nB) {
+        put(SP_B, 0, 8 * (size_t)nB * nB);
+    } else {
+        for (int l = 0; l < nlev; ++l) {
+            const size_t n = lev[l].n, w = lev[l].w;
+            put(SP_COL, l, 4 * w * n);
+            put(SP_VAL, l, 8 * w * n);
+            put(SP_DIAG, l, 8 * n);
+            put(SP_DINV, l, 8 * n);
+            if (l > 0) {
+                put(SP_PARENTS, l, 8 * n);
+                put(SP_CROW, l, 4 * ((size_t)lev[l - 1].n + 1));
+                put(SP_CCOL, l, 8 * n);
+                put(SP_CW, l, 16 * n);
+            }
+        }
+        put(SP_AINV, 0, 8 * (size_t)lev[0].n * lev[0].n);
+    }
+    return o;
+}
+__host__ __device__ inline size_t small_image_bytes(int ne, int m, const P1Lev *lev, int nlev, int nB) {
+    return small_image_walk(ne, m, lev, nlev, nB, [](SmallPart, int, size_t, size_t) {});
+}
+
 struct SmallArgs {
     int ne, m, nk, nb, nlev;
     int stage_ops;                      // copy the operators below into LDS at the start
+    const char *image;                  // with stage_ops: the packed operators (small_image_walk order)
     int krylov, restart, maxit, nu_pre, nu_post, p1_nu;
     double omega, p1_omega, rtol;
     const double *S, *T, *Dw;           // FP64 facet rows (16-byte groups)
     const int *nbr, *fvert, *vf_row, *vf_col;
     P1Lev lev[P1_TAIL_LEVELS];          // P1 levels, 0 coarsest (work vectors unused: LDS)
     const double *Ainv;                 // dense inverse of level 0
-    const double *p1B;                  // the whole P1 V-cycle as a matrix [n][n] (finest level), or null
+    const double *p1B;                  // the whole P1 V-cycle as a matrix, transposed [j][i] (finest level), or null
     // Steps 1 and 3 inside the launch (stage solve)
     const double *Zr, *Ar, *Wr;
     const int *fcell, *floc, *cell_facet;

@@ -23,7 +23,7 @@
 // rounding differs: the order of the reduction sums (one workgroup instead of
 // block partials) and, for hierarchies of at most SMALL_P1_DENSE finest
 // vertices, the P1 V-cycle applied as its matrix (formed on the host by
-// applying the same cycle to unit vectors).
+// applying the same cycle to unit vectors, stored transposed).
 #include "hdg_device.h"
 #include "hdg_kernels.h"
 
@@ -32,6 +32,7 @@ namespace hdg {
 namespace {
 
 constexpr int SW = SMALL_THREADS / 64;   // wavefronts per workgroup
+static_assert(SW == 4 && SMALL_P1_DENSE <= 64, "the dense P1 phase: four wavefronts, a row per lane");
 
 // The trace unknowns a thread owns: the m unknowns of facets tid, tid + SMALL_THREADS, ...
 // -- the items the facet kernels below write -- so that element-wise updates
@@ -74,6 +75,7 @@ __device__ __forceinline__ void ld2(const double *p, double (&o)[2]) {
 typedef __attribute__((address_space(3))) const double lds_double;
 typedef __attribute__((address_space(3))) const int lds_int;
 typedef __attribute__((address_space(3))) const dbl2_t lds_double2;
+typedef __attribute__((address_space(3))) double lds_dbl;   // P1 level vectors (always in LDS)
 
 template <bool OL>
 __device__ __forceinline__ void opr2(const double *p, double (&o)[2]) {
@@ -206,6 +208,85 @@ __device__ __forceinline__ void jacobi_at(const Ops &O, size_t NE, int f, const 
     }
 }
 
+// omega D_f^-1 rv for the values rv of facet f
+template <int M, bool OL>
+__device__ __forceinline__ void jacobi_of(const Ops &O, size_t NE, int f, const double (&rv)[M], double (&z)[M]) {
+    constexpr int C = M * M, G = padded(C, 2) / 2;
+    const double *Dw = O.Dw;
+#pragma unroll
+    for (int k = 0; k < M; ++k) z[k] = 0.0;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        double w[2];
+        opr2<OL>(Dw + ((size_t)g * NE + f) * 2, w);
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+            const int c = 2 * g + v;
+            if (c < C) z[c / M] += w[v] * rv[c % M];
+        }
+    }
+}
+
+// The PCG update fused with the first V-cycle phase of the next preconditioner
+// application: at this thread's facets lam += alpha p and rn = r - alpha w (into
+// a second buffer: the old r is still read at the patch facets), then z0 =
+// omega D^-1 rn and, with y != nullptr, the first sweep from zero, rn at the
+// patch facets evaluated in place (the same expression, so the same bits).
+// Returns this thread's part of rn . rn.
+template <int M, bool OL>
+__device__ double s_update_first_sweep(int ne, const Ops &O, double omega, double alpha, const double *p,
+                                       const double *w, const double *r, double *rn, double *lam, double *z0,
+                                       double *y) {
+    constexpr int C = 4 * M * M, G = padded(C, 2) / 2;
+    const size_t NE = (size_t)ne;
+    const double *T = O.T;
+    const int *nbr = O.nbr;
+    const SweepCoef cf{1.0 - omega, 1.0, 1.0, 0.0, nullptr, nullptr};
+    double part = 0.0;
+    for (int e = threadIdx.x; e < ne; e += SMALL_THREADS) {
+        double rv[M], zv[5][M];
+#pragma unroll
+        for (int a = 0; a < M; ++a) {
+            const int i = e * M + a;
+            rv[a] = r[i] - alpha * w[i];
+            rn[i] = rv[a];
+            lam[i] += alpha * p[i];
+            part += rv[a] * rv[a];
+        }
+        jacobi_of<M, OL>(O, NE, e, rv, zv[0]);
+#pragma unroll
+        for (int a = 0; a < M; ++a) z0[e * M + a] = zv[0][a];
+        if (!y) continue;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int f = opri<OL>(nbr + j * NE + e);
+            double rj[M];
+#pragma unroll
+            for (int k = 0; k < M; ++k) rj[k] = r[f * M + k] - alpha * w[f * M + k];
+            jacobi_of<M, OL>(O, NE, f, rj, zv[j + 1]);
+        }
+        double acc[M];
+#pragma unroll
+        for (int a = 0; a < M; ++a) acc[a] = 0.0;
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            double wt[2];
+            opr2<OL>(T + ((size_t)g * NE + e) * 2, wt);
+#pragma unroll
+            for (int v = 0; v < 2; ++v) {
+                const int c = 2 * g + v;
+                if (c < C) {
+                    const int j = c / (M * M), a = (c / M) % M, k = c % M;
+                    acc[a] += wt[v] * zv[j + 1][k];
+                }
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < M; ++a) y[e * M + a] = sweep_combine(cf, zv[0][a], zv[0][a], acc[a]);
+    }
+    return part;
+}
+
 // z0 = omega D^-1 r at this thread's facets and, with y != nullptr, the first
 // damped block-Jacobi sweep from zero y = (1 - omega) z0 + z0 - sum_j T_j z0_j
 // (z0 at the patch facets computed in place)
@@ -248,7 +329,7 @@ __device__ void s_first_sweep(int ne, const Ops &O, double omega, const double *
 // damped block-Jacobi sweep y = (1 - omega) x' + z0 - sum_j T_j x'_j, x' = x + pi qc;
 // returns this thread's part of d . y when d is given
 template <int M, bool OL>
-__device__ double s_sweep(int ne, const Ops &O, double omega, const double *x, const double *z0, const double *qc,
+__device__ double s_sweep(int ne, const Ops &O, double omega, const double *x, const double *z0, const lds_dbl *qc,
                           double *y, const double *d = nullptr) {
     double part = 0.0;
     const double *T = O.T;
@@ -300,7 +381,7 @@ __device__ double s_sweep(int ne, const Ops &O, double omega, const double *x, c
 
 // pi^T: rc[v] = sum over facet ends at v of sum_k w_end(k) res[e][k]
 template <int M, bool OL>
-__device__ void s_restrict_trace(int nv, const Ops &O, const double *res, double *rc) {
+__device__ void s_restrict_trace(int nv, const Ops &O, const double *res, lds_dbl *rc) {
     constexpr int P = M - 1;
     const int *vf_row = O.vf_row, *vf_col = O.vf_col;
     for (int v = threadIdx.x; v < nv; v += SMALL_THREADS) {
@@ -339,21 +420,25 @@ __device__ __forceinline__ double range_sum(int cnt, F &&f) {
     return s;
 }
 
-__device__ __forceinline__ double s_p1_ax(const P1Lev &L, int v, const double *x) {
-    const double s = L.diag[v] * x[v];
-    return s + range_sum(L.w, [&](int k) { return L.val[(size_t)k * L.n + v] * x[L.col[(size_t)k * L.n + v]]; });
+template <bool OL>
+__device__ __forceinline__ double s_p1_ax(const P1Lev &L, int v, const lds_dbl *x) {
+    const double s = oprd<OL>(L.diag + v) * x[v];
+    return s + range_sum(L.w, [&](int k) {
+        return oprd<OL>(L.val + (size_t)k * L.n + v) * x[opri<OL>(L.col + (size_t)k * L.n + v)];
+    });
 }
 
 // Level vectors of the P1 hierarchy in LDS: b, x, y of level l (tables in LDS,
 // runtime-indexed).  Which of x, y holds a level's iterate follows from the
 // sweep count alone, so no pointer has to be published between the phases.
 struct P1Vecs {
-    double *b[P1_TAIL_LEVELS], *x[P1_TAIL_LEVELS], *y[P1_TAIL_LEVELS];
+    lds_dbl *b[P1_TAIL_LEVELS], *x[P1_TAIL_LEVELS], *y[P1_TAIL_LEVELS];
 };
 
 // One P1 multigrid V-cycle from the finest level's right-hand side; returns the
 // LDS vector holding the result.
-__device__ double *s_p1_vcycle(int nlev, int nu, double w, const Ops &O, const P1Vecs *pv) {
+template <bool OL>
+__device__ lds_dbl *s_p1_vcycle(int nlev, int nu, double w, const Ops &O, const P1Vecs *pv) {
     const int top = nlev - 1, tid = threadIdx.x;
     // after pre-smoothing the iterate is in x when the sweeps after the first
     // fused pair are even in number; after post-smoothing in that buffer when nu is even
@@ -363,65 +448,70 @@ __device__ double *s_p1_vcycle(int nlev, int nu, double w, const Ops &O, const P
     auto fin = [&](int l) { return l == 0 ? pv->x[0] : (fin_pre ? pre(l) : other(l)); };
     for (int l = top; l >= 1; --l) {
         const P1Lev &L = O.lev[l];
-        double *x = pv->x[l], *y = pv->y[l];
-        const double *b = pv->b[l];
+        lds_dbl *x = pv->x[l], *y = pv->y[l];
+        const lds_dbl *b = pv->b[l];
+        auto dinv = [&](int v) { return oprd<OL>(L.dinv + v); };
         if (nu == 1) {
-            for (int v = tid; v < L.n; v += SMALL_THREADS) x[v] = w * L.dinv[v] * b[v];
+            for (int v = tid; v < L.n; v += SMALL_THREADS) x[v] = w * dinv(v) * b[v];
         } else {
             // two sweeps from zero: x1 = w D^-1 b (evaluated where needed), x2 = x1 + w D^-1 (b - A x1)
             for (int v = tid; v < L.n; v += SMALL_THREADS) {
-                const double x1 = w * L.dinv[v] * b[v];
-                const double ax = L.diag[v] * x1 + range_sum(L.w, [&](int k) {
-                    const int u = L.col[(size_t)k * L.n + v];
-                    return L.val[(size_t)k * L.n + v] * (w * L.dinv[u] * b[u]);
+                const double x1 = w * dinv(v) * b[v];
+                const double ax = oprd<OL>(L.diag + v) * x1 + range_sum(L.w, [&](int k) {
+                    const int u = opri<OL>(L.col + (size_t)k * L.n + v);
+                    return oprd<OL>(L.val + (size_t)k * L.n + v) * (w * dinv(u) * b[u]);
                 });
-                x[v] = x1 + w * L.dinv[v] * (b[v] - ax);
+                x[v] = x1 + w * dinv(v) * (b[v] - ax);
             }
         }
         __syncthreads();
         for (int k = 2; k < nu; ++k) {
-            for (int v = tid; v < L.n; v += SMALL_THREADS) y[v] = x[v] + w * L.dinv[v] * (b[v] - s_p1_ax(L, v, x));
+            for (int v = tid; v < L.n; v += SMALL_THREADS) y[v] = x[v] + w * dinv(v) * (b[v] - s_p1_ax<OL>(L, v, x));
             __syncthreads();
-            double *t = x;
+            lds_dbl *t = x;
             x = y;
             y = t;
         }
-        for (int v = tid; v < L.n; v += SMALL_THREADS) y[v] = b[v] - s_p1_ax(L, v, x);
+        for (int v = tid; v < L.n; v += SMALL_THREADS) y[v] = b[v] - s_p1_ax<OL>(L, v, x);
         __syncthreads();
         const P1Lev &Cl = O.lev[l - 1];
-        double *bc = pv->b[l - 1];
+        lds_dbl *bc = pv->b[l - 1];
         for (int c = tid; c < Cl.n; c += SMALL_THREADS) {
-            const int k0 = L.crow[c];
-            bc[c] = range_sum(L.crow[c + 1] - k0, [&](int k) { return L.cw[k0 + k] * y[L.ccol[k0 + k]]; });
+            const int k0 = opri<OL>(L.crow + c);
+            bc[c] = range_sum(opri<OL>(L.crow + c + 1) - k0,
+                              [&](int k) { return oprd<OL>(L.cw + k0 + k) * y[opri<OL>(L.ccol + k0 + k)]; });
         }
         __syncthreads();
     }
     {
         const int n0 = O.lev[0].n;
-        const double *b0 = pv->b[0];
-        double *x0 = pv->x[0];
+        const lds_dbl *b0 = pv->b[0];
+        lds_dbl *x0 = pv->x[0];
         for (int i = tid; i < n0; i += SMALL_THREADS)
-            x0[i] = range_sum(n0, [&](int j) { return O.Ainv[(size_t)i * n0 + j] * b0[j]; });
+            x0[i] = range_sum(n0, [&](int j) { return oprd<OL>(O.Ainv + (size_t)i * n0 + j) * b0[j]; });
         __syncthreads();
     }
     for (int l = 1; l <= top; ++l) {
         const P1Lev &L = O.lev[l];
-        double *x = pre(l), *y = other(l);
-        const double *xc = fin(l - 1), *b = pv->b[l];
+        lds_dbl *x = pre(l), *y = other(l);
+        const lds_dbl *xc = fin(l - 1), *b = pv->b[l];
         for (int k = 0; k < nu; ++k) {
             for (int v = tid; v < L.n; v += SMALL_THREADS) {
                 auto xin = [&](int u) -> double {
                     double s = x[u];
-                    if (k == 0) s += 0.5 * (xc[L.parents[2 * u]] + xc[L.parents[2 * u + 1]]);
+                    if (k == 0)
+                        s += 0.5 * (xc[opri<OL>(L.parents + 2 * u)] + xc[opri<OL>(L.parents + 2 * u + 1)]);
                     return s;
                 };
-                double ax = range_sum(L.w, [&](int q) { return L.val[(size_t)q * L.n + v] * xin(L.col[(size_t)q * L.n + v]); });
+                double ax = range_sum(L.w, [&](int q) {
+                    return oprd<OL>(L.val + (size_t)q * L.n + v) * xin(opri<OL>(L.col + (size_t)q * L.n + v));
+                });
                 const double xv = xin(v);
-                ax += L.diag[v] * xv;
-                y[v] = xv + w * L.dinv[v] * (b[v] - ax);
+                ax += oprd<OL>(L.diag + v) * xv;
+                y[v] = xv + w * oprd<OL>(L.dinv + v) * (b[v] - ax);
             }
             __syncthreads();
-            double *t = x;
+            lds_dbl *t = x;
             x = y;
             y = t;
         }
@@ -433,35 +523,19 @@ __device__ double *s_p1_vcycle(int nlev, int nu, double w, const Ops &O, const P
 struct SmallLds {
     const Ops *ops;
     P1Vecs *pv;
-    double *lam, *r, *z, *p, *p2, *w, *z0, *x, *x2, *res, *b;
+    double *lam, *r, *r2, *z, *p, *p2, *w, *z0, *x, *x2, *res, *b;
     double *red;     // [2][SMALL_MAXR + 1][SW] reduction partials
+    double *dpart;   // [4][64] partial sums of the dense P1 product
     double *hv;      // [SMALL_MAXR + 1] Gram-Schmidt coefficients
     double *H;       // Hessenberg, column j at H + j (SMALL_MAXR + 1)
     double *cs, *sn, *g, *y;
     double *scal;    // broadcast scalars
+    char *img;       // LDS copy of the operator image (stage_ops), else null
 };
 
 constexpr size_t small_fixed_doubles() {
-    return 2 * (SMALL_MAXR + 1) * SW + (SMALL_MAXR + 1) + (SMALL_MAXR + 1) * SMALL_MAXR + 3 * SMALL_MAXR +
+    return 2 * (SMALL_MAXR + 1) * SW + 4 * 64 + (SMALL_MAXR + 1) + (SMALL_MAXR + 1) * SMALL_MAXR + 3 * SMALL_MAXR +
            (SMALL_MAXR + 1) + 8;
-}
-
-// copy count items of src into LDS at q (16-byte aligned), advancing q; every
-// thread computes the same addresses
-template <typename T>
-__device__ const T *stage(char *&q, const T *src, size_t count) {
-    typedef unsigned u4 __attribute__((ext_vector_type(4)));
-    T *dst = reinterpret_cast<T *>(q);
-    const size_t bytes = count * sizeof(T), n16 = bytes / 16;
-    const u4 *s16 = reinterpret_cast<const u4 *>(src);   // device allocations are 256-byte aligned
-    u4 *d16 = reinterpret_cast<u4 *>(dst);
-#pragma unroll 4
-    for (size_t i = threadIdx.x; i < n16; i += SMALL_THREADS) d16[i] = s16[i];
-    const unsigned *s4 = reinterpret_cast<const unsigned *>(src);
-    unsigned *d4 = reinterpret_cast<unsigned *>(dst);
-    for (size_t i = n16 * 4 + threadIdx.x; i < bytes / 4; i += SMALL_THREADS) d4[i] = s4[i];
-    q += (bytes + 15) / 16 * 16;
-    return dst;
 }
 
 __device__ SmallLds carve(const SmallArgs &A, Ops *ops, P1Vecs *pv, double *base) {
@@ -470,22 +544,24 @@ __device__ SmallLds carve(const SmallArgs &A, Ops *ops, P1Vecs *pv, double *base
     L.pv = pv;
     const int nt = A.ne * A.m;
     double *q = base;
-    double **vec[11] = {&L.lam, &L.r, &L.z, &L.p, &L.p2, &L.w, &L.z0, &L.x, &L.x2, &L.res, &L.b};
-    for (int i = 0; i < 11; ++i) {
+    double **vec[12] = {&L.lam, &L.r, &L.r2, &L.z, &L.p, &L.p2, &L.w, &L.z0, &L.x, &L.x2, &L.res, &L.b};
+    for (int i = 0; i < 12; ++i) {
         *vec[i] = q;
         q += nt;
     }
     for (int l = 0; l < A.nlev; ++l) {
         const int n = ops->lev[l].n;
         if (threadIdx.x == 0) {
-            pv->b[l] = q;
-            pv->x[l] = q + n;
-            pv->y[l] = q + 2 * n;
+            pv->b[l] = (lds_dbl *)q;
+            pv->x[l] = (lds_dbl *)(q + n);
+            pv->y[l] = (lds_dbl *)(q + 2 * n);
         }
         q += 3 * n;
     }
     L.red = q;
     q += 2 * (SMALL_MAXR + 1) * SW;
+    L.dpart = q;
+    q += 4 * 64;
     L.hv = q;
     q += SMALL_MAXR + 1;
     L.H = q;
@@ -500,80 +576,26 @@ __device__ SmallLds carve(const SmallArgs &A, Ops *ops, P1Vecs *pv, double *base
     q += SMALL_MAXR;
     L.scal = q;
     q += 8;
+    L.img = nullptr;
     if (A.stage_ops) {
-        // operators into LDS (same layouts, 16-byte aligned), after the vectors; thread 0
-        // publishes the pointers
+        // the operator image goes after the vectors, 16-byte aligned (copied by the kernel)
         char *c = reinterpret_cast<char *>(q);
         c += (16 - (reinterpret_cast<uintptr_t>(c) & 15)) & 15;
-        const int ne = A.ne, m = A.m;
-        const double *S = stage(c, A.S, (size_t)padded(5 * m * m, 2) * ne);
-        const double *T = stage(c, A.T, (size_t)padded(4 * m * m, 2) * ne);
-        const double *Dw = stage(c, A.Dw, (size_t)padded(m * m, 2) * ne);
-        const int *nbr = stage(c, A.nbr, (size_t)4 * ne);
-        const int *fvert = stage(c, A.fvert, (size_t)2 * ne);
-        const int nv = ops->lev[A.nlev - 1].n;
-        const int *vf_row = stage(c, A.vf_row, (size_t)nv + 1);
-        const int *vf_col = stage(c, A.vf_col, (size_t)2 * ne);
-        const double *B = A.p1B ? stage(c, A.p1B, (size_t)nv * nv) : nullptr;
-        for (int l = 0; l < (A.p1B ? 0 : A.nlev); ++l) {
-            const P1Lev &G = ops->lev[l];
-            const int *col = stage(c, G.col, (size_t)G.w * G.n);
-            const double *val = stage(c, G.val, (size_t)G.w * G.n);
-            const double *diag = stage(c, G.diag, (size_t)G.n);
-            const double *dinv = stage(c, G.dinv, (size_t)G.n);
-            const int *parents = nullptr, *crow = nullptr, *ccol = nullptr;
-            const double *cw = nullptr;
-            if (l > 0) {
-                const int nc = ops->lev[l - 1].n;
-                parents = stage(c, G.parents, (size_t)2 * G.n);
-                crow = stage(c, G.crow, (size_t)nc + 1);
-                ccol = stage(c, G.ccol, (size_t)2 * G.n);
-                cw = stage(c, G.cw, (size_t)2 * G.n);
-            }
-            __syncthreads();   // every thread has read the global descriptor of level l
-            if (threadIdx.x == 0) {
-                P1Lev &D = ops->lev[l];
-                D.col = col;
-                D.val = val;
-                D.diag = diag;
-                D.dinv = dinv;
-                if (l > 0) {
-                    D.parents = parents;
-                    D.crow = crow;
-                    D.ccol = ccol;
-                    D.cw = cw;
-                }
-            }
-        }
-        const int n0 = ops->lev[0].n;
-        const double *Ainv = A.p1B ? ops->Ainv : stage(c, ops->Ainv, (size_t)n0 * n0);
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            ops->B = B;
-            ops->S = S;
-            ops->T = T;
-            ops->Dw = Dw;
-            ops->Ainv = Ainv;
-            ops->nbr = nbr;
-            ops->fvert = fvert;
-            ops->vf_row = vf_row;
-            ops->vf_col = vf_col;
-        }
+        L.img = c;
     }
     return L;
 }
 
 // z = V(r): r and z in LDS.  With d given, returns this thread's part of d . z and
 // leaves the barrier after the last sweep to the caller's reduction.
+// The V-cycle after its first phase (z0 and the first sweep from zero in L.z0, L.x).
 template <int M, bool OL>
-__device__ double s_vcycle(const SmallArgs &A, SmallLds &L, const double *r, double *z, const double *d = nullptr) {
+__device__ double s_vcycle_rest(const SmallArgs &A, SmallLds &L, const double *r, double *z, const double *d) {
     const Ops &O = *L.ops;
     const int ne = A.ne, tid = threadIdx.x;
     double *bufs[2] = {L.x, L.x2};
     int bi = 0;
     double *cur = L.z0;
-    s_first_sweep<M, OL>(ne, O, A.omega, r, L.z0, A.nu_pre >= 2 ? L.x : nullptr);
-    __syncthreads();
     if (A.nu_pre >= 2) {
         cur = L.x;
         bi = 1;
@@ -590,25 +612,28 @@ __device__ double s_vcycle(const SmallArgs &A, SmallLds &L, const double *r, dou
     const int top = A.nlev - 1;
     s_restrict_trace<M, OL>(O.lev[top].n, O, L.res, L.pv->b[top]);
     __syncthreads();
-    const double *xl;
+    const lds_dbl *xl;
     if (O.B) {
-        // the P1 V-cycle as its matrix: four lanes per row, combined by shuffles
+        // the P1 V-cycle as its matrix, stored transposed: lane i of each wavefront takes
+        // row i (consecutive doubles across the lanes: no LDS bank conflicts), wavefront w
+        // a quarter of the columns; the four partial sums are added in a second step
         const int nv = O.lev[top].n;
-        const double *bv = L.pv->b[top], *B = O.B;
-        double *xv = L.pv->x[top];
-        for (int i0 = 0; i0 < nv; i0 += SMALL_THREADS / 4) {
-            const int i = i0 + (tid >> 2), q = tid & 3;
-            double s = 0.0;
-            if (i < nv)
-                for (int j = q; j < nv; j += 4) s += oprd<OL>(B + (size_t)i * nv + j) * bv[j];
-            s += __shfl_xor(s, 1, 64);
-            s += __shfl_xor(s, 2, 64);
-            if (i < nv && q == 0) xv[i] = s;
+        const lds_dbl *bv = L.pv->b[top];
+        const double *BT = O.B;
+        lds_dbl *xv = L.pv->x[top];
+        const int wv = tid >> 6, lane = tid & 63, jc = (nv + 3) / 4, j0 = wv * jc, j1 = min(nv, j0 + jc);
+        double s = 0.0;
+        if (lane < nv) {
+#pragma unroll 8
+            for (int j = j0; j < j1; ++j) s += oprd<OL>(BT + (size_t)j * nv + lane) * bv[j];
         }
+        L.dpart[wv * 64 + lane] = s;
+        __syncthreads();
+        if (tid < nv) xv[tid] = (L.dpart[tid] + L.dpart[64 + tid]) + (L.dpart[128 + tid] + L.dpart[192 + tid]);
         __syncthreads();
         xl = xv;
     } else {
-        xl = s_p1_vcycle(A.nlev, A.p1_nu, A.p1_omega, O, L.pv);
+        xl = s_p1_vcycle<OL>(A.nlev, A.p1_nu, A.p1_omega, O, L.pv);
     }
     double part = 0.0;
     for (int k = 0; k < A.nu_post; ++k) {
@@ -631,13 +656,53 @@ __device__ double s_vcycle(const SmallArgs &A, SmallLds &L, const double *r, dou
     return part;
 }
 
+template <int M, bool OL>
+__device__ double s_vcycle(const SmallArgs &A, SmallLds &L, const double *r, double *z, const double *d = nullptr) {
+    s_first_sweep<M, OL>(A.ne, *L.ops, A.omega, r, L.z0, A.nu_pre >= 2 ? L.x : nullptr);
+    __syncthreads();
+    return s_vcycle_rest<M, OL>(A, L, r, z, d);
+}
+
+// thread 0 points the operator table at the LDS copy of the image
+__device__ void publish_image(const SmallArgs &A, Ops *ops, const char *c) {
+    const int nB = A.p1B ? ops->lev[A.nlev - 1].n : 0;
+    small_image_walk(A.ne, A.m, ops->lev, A.nlev, nB, [&](SmallPart part, int l, size_t off, size_t) {
+        const char *a = c + off;
+        const double *d = reinterpret_cast<const double *>(a);
+        const int *k = reinterpret_cast<const int *>(a);
+        P1Lev &D = ops->lev[l];
+        switch (part) {
+        case SP_S: ops->S = d; break;
+        case SP_T: ops->T = d; break;
+        case SP_DW: ops->Dw = d; break;
+        case SP_NBR: ops->nbr = k; break;
+        case SP_FVERT: ops->fvert = k; break;
+        case SP_VF_ROW: ops->vf_row = k; break;
+        case SP_VF_COL: ops->vf_col = k; break;
+        case SP_B: ops->B = d; break;
+        case SP_COL: D.col = k; break;
+        case SP_VAL: D.val = d; break;
+        case SP_DIAG: D.diag = d; break;
+        case SP_DINV: D.dinv = d; break;
+        case SP_PARENTS: D.parents = k; break;
+        case SP_CROW: D.crow = k; break;
+        case SP_CCOL: D.ccol = k; break;
+        case SP_CW: D.cw = d; break;
+        case SP_AINV: ops->Ainv = d; break;
+        }
+    });
+}
+
 template <int P, bool STAGE, bool OL>
 __global__ __launch_bounds__(SMALL_THREADS) void k_solve_small(const SmallArgs A) {
     constexpr int M = P + 1, n = (P + 1) * (P + 2) / 2, nc = 3 * n, nt = 3 * M, ZW = cell_zw(P);
     extern __shared__ double lds[];
     __shared__ Ops sops;
     __shared__ P1Vecs spv;
-    if (threadIdx.x == 0) {
+    // the operator table into LDS: the level descriptors one per lane (their argument
+    // loads in flight together), the rest by the next lane
+    if (threadIdx.x < A.nlev) sops.lev[threadIdx.x] = A.lev[threadIdx.x];
+    if (threadIdx.x == 63) {
         sops.S = A.S;
         sops.T = A.T;
         sops.Dw = A.Dw;
@@ -647,14 +712,27 @@ __global__ __launch_bounds__(SMALL_THREADS) void k_solve_small(const SmallArgs A
         sops.fvert = A.fvert;
         sops.vf_row = A.vf_row;
         sops.vf_col = A.vf_col;
-#pragma unroll
-        for (int l = 0; l < P1_TAIL_LEVELS; ++l) sops.lev[l] = A.lev[l];
     }
     __syncthreads();
     SmallLds L = carve(A, &sops, &spv, lds);
     __syncthreads();
     const Ops &O = sops;
     const int tid = threadIdx.x, rh = blockIdx.x, nb = A.nb, ne = A.ne;
+    // The packed operator image into LDS: the first up-to-32 16-byte loads per thread
+    // go out before the right-hand side below is read, so that both are in flight
+    // together; their stores, any further rounds and the table follow it.
+    typedef unsigned u4 __attribute__((ext_vector_type(4)));
+    constexpr int IU = 32;
+    const int n16 = L.img ? (int)(small_image_bytes(ne, A.m, sops.lev, A.nlev, A.p1B ? sops.lev[A.nlev - 1].n : 0) / 16)
+                          : 0;
+    const u4 *isrc = reinterpret_cast<const u4 *>(A.image);   // device allocations are 256-byte aligned
+    u4 *idst = reinterpret_cast<u4 *>(L.img);
+    u4 iv[IU];
+#pragma unroll
+    for (int u = 0; u < IU; ++u) {
+        const int i = tid + u * SMALL_THREADS;
+        if (i < n16) iv[u] = isrc[i];
+    }
     const size_t NK = (size_t)A.nk;
     double *red0 = L.red, *red1 = L.red + (SMALL_MAXR + 1) * SW;
     int rsel = 0;
@@ -690,6 +768,25 @@ __global__ __launch_bounds__(SMALL_THREADS) void k_solve_small(const SmallArgs A
             L.lam[i] = A.lam[(size_t)i * nb + rh];
         });
     }
+#pragma unroll
+    for (int u = 0; u < IU; ++u) {
+        const int i = tid + u * SMALL_THREADS;
+        if (i < n16) idst[i] = iv[u];
+    }
+    for (int i0 = tid + IU * SMALL_THREADS; i0 < n16; i0 += IU * SMALL_THREADS) {
+#pragma unroll
+        for (int u = 0; u < IU; ++u) {
+            const int i = i0 + u * SMALL_THREADS;
+            if (i < n16) iv[u] = isrc[i];
+        }
+#pragma unroll
+        for (int u = 0; u < IU; ++u) {
+            const int i = i0 + u * SMALL_THREADS;
+            if (i < n16) idst[i] = iv[u];
+        }
+    }
+    __syncthreads();   // every thread has read the level sizes above
+    if (L.img && tid == 0) publish_image(A, &sops, L.img);
     __syncthreads();
     double part = 0.0;
     for_own<M>(ne, [&](int i) { part += L.b[i] * L.b[i]; });
@@ -720,29 +817,31 @@ __global__ __launch_bounds__(SMALL_THREADS) void k_solve_small(const SmallArgs A
         if (A.krylov == HDG_KRYLOV_PCG) {
             // p_0 = z_0; then per iteration: p = z + beta p (fused into w = S p), alpha = rz / p.w,
             // lam += alpha p, r -= alpha w, z = V(r), beta = r.z / rz
+            // (the update of lam and r rides in the first phase of the next V-cycle;
+            // r alternates between two buffers)
             double rz = block_sum(s_vcycle<M, OL>(A, L, L.r, L.z, L.r), red());
             double beta = 0.0;
             double *pbuf[2] = {L.p, L.p2};
+            double *rc = L.r, *rnx = L.r2;
             int pc = 0;
             const double *po = L.z;   // first direction: z itself (beta = 0)
             while (its < A.maxit) {
                 double *pn = pbuf[pc];
                 const double pw = block_sum(s_apply_dir<M, OL>(ne, O, L.z, beta, po, pn, L.w), red());
                 const double alpha = rz / pw;
-                part = 0.0;
-                for_own<M>(ne, [&](int i) {
-                    L.lam[i] += alpha * pn[i];
-                    L.r[i] -= alpha * L.w[i];
-                    part += L.r[i] * L.r[i];
-                });
-                const double rrk = block_sum(part, red());
+                const double rrk = block_sum(s_update_first_sweep<M, OL>(ne, O, A.omega, alpha, pn, L.w, rc, rnx, L.lam,
+                                                                         L.z0, A.nu_pre >= 2 ? L.x : nullptr),
+                                             red());
                 ++its;
                 if (!isfinite(rrk) || rrk <= rtol * rtol * bn2) break;
-                const double rzn = block_sum(s_vcycle<M, OL>(A, L, L.r, L.z, L.r), red());
+                const double rzn = block_sum(s_vcycle_rest<M, OL>(A, L, rnx, L.z, rnx), red());
                 beta = rzn / rz;
                 rz = rzn;
                 po = pn;
                 pc ^= 1;
+                double *t = rc;
+                rc = rnx;
+                rnx = t;
             }
         } else {
             // flexible GMRES(R), classical Gram-Schmidt; the basis in global memory
@@ -840,34 +939,51 @@ __global__ __launch_bounds__(SMALL_THREADS) void k_solve_small(const SmallArgs A
         }
     }
 
-    // ---- outputs: lam, the info record, and (stage) the recovered cell fields
+    // ---- outputs: lam, (stage) the recovered cell fields, then the info record
     for_own<M>(ne, [&](int i) { A.lam[(size_t)i * nb + rh] = L.lam[i]; });
-    if (tid == 0) {
-        A.info[4 * rh + 0] = its;
-        A.info[4 * rh + 1] = restarts;
-        A.info[4 * rh + 2] = status;
-        A.info[4 * rh + 3] = rel;
-    }
     if (STAGE) {
         __syncthreads();
-        // Step 3: q = Ar r_cell - Wr lam_K per cell
+        // Step 3: q = Ar r_cell - Wr lam_K per cell.  The cell's right-hand side is
+        // read once; outputs go three at a time, each group's row loads issued
+        // together before its stores (which could alias them).
+        constexpr int QG = 3;
+        static_assert(nc % QG == 0, "three fields per node");
         for (int K = tid; K < A.nk; K += SMALL_THREADS) {
-            double l[nt];
+            double l[nt], rc[nc];
+#pragma unroll
+            for (int j = 0; j < nc; ++j) rc[j] = A.r_cell[((size_t)K * nc + j) * nb + rh];
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
                 const int e = A.cell_facet[i * NK + K];
                 const int rev = A.cell_rev[i * NK + K];
 #pragma unroll
-                for (int a = 0; a < M; ++a) l[loc_trace<P, 1>(i, a, rev)] = L.lam[e * M + a];
+                for (int t = 0; t < M; ++t) l[i * M + t] = L.lam[e * M + (rev ? P - t : t)];   // l[loc_trace(i, a, rev)] = lam[e][a]
             }
-            for (int a = 0; a < nc; ++a) {
-                double s = 0.0;
-                for (int j = 0; j < nc; ++j) s += A.Ar[(size_t)(a * nc + j) * NK + K] * A.r_cell[((size_t)K * nc + j) * nb + rh];
+            for (int a0 = 0; a0 < nc; a0 += QG) {
+                double s[QG];
 #pragma unroll
-                for (int j = 0; j < nt; ++j) s -= A.Wr[(size_t)(a * nt + j) * NK + K] * l[j];
-                A.q_cell[((size_t)K * nc + a) * nb + rh] = s;
+                for (int g = 0; g < QG; ++g) {
+                    const int a = a0 + g;
+                    s[g] = 0.0;
+#pragma unroll
+                    for (int j = 0; j < nc; ++j) s[g] += A.Ar[(size_t)(a * nc + j) * NK + K] * rc[j];
+#pragma unroll
+                    for (int j = 0; j < nt; ++j) s[g] -= A.Wr[(size_t)(a * nt + j) * NK + K] * l[j];
+                }
+#pragma unroll
+                for (int g = 0; g < QG; ++g) A.q_cell[((size_t)K * nc + a0 + g) * nb + rh] = s[g];
             }
         }
+    }
+    // the record goes to host-mapped memory last, its status after a system-scope
+    // fence: the host returns once every right-hand side's status has arrived
+    __syncthreads();
+    if (tid == 0) {
+        A.info[4 * rh + 0] = its;
+        A.info[4 * rh + 1] = restarts;
+        A.info[4 * rh + 3] = rel;
+        __threadfence_system();
+        A.info[4 * rh + 2] = status;
     }
 }
 
@@ -876,25 +992,10 @@ size_t round16(size_t b) { return (b + 15) / 16 * 16; }
 }  // namespace
 
 size_t small_lds_bytes(int ne, int m, const P1Lev *lev, int nlev, bool stage_ops, int nB) {
-    size_t d = (size_t)11 * ne * m;
+    size_t d = (size_t)12 * ne * m;
     for (int l = 0; l < nlev; ++l) d += 3 * (size_t)lev[l].n;
     size_t bytes = (d + small_fixed_doubles()) * sizeof(double);
-    if (stage_ops) {
-        bytes += 16 + round16(8 * (size_t)padded(5 * m * m, 2) * ne) + round16(8 * (size_t)padded(4 * m * m, 2) * ne) +
-                 round16(8 * (size_t)padded(m * m, 2) * ne) + round16(16 * (size_t)ne) + round16(8 * (size_t)ne) +
-                 round16(4 * ((size_t)lev[nlev - 1].n + 1)) + round16(8 * (size_t)ne);
-        if (nB) {
-            bytes += round16(8 * (size_t)nB * nB);
-        } else {
-            for (int l = 0; l < nlev; ++l) {
-                const size_t n = lev[l].n, w = lev[l].w;
-                bytes += round16(4 * w * n) + round16(8 * w * n) + 2 * round16(8 * n);
-                if (l > 0)
-                    bytes += round16(8 * n) + round16(4 * ((size_t)lev[l - 1].n + 1)) + round16(8 * n) + round16(16 * n);
-            }
-            bytes += round16(8 * (size_t)lev[0].n * lev[0].n);
-        }
-    }
+    if (stage_ops) bytes += 16 + small_image_bytes(ne, m, lev, nlev, nB);   // alignment + the operator image
     return bytes;
 }
 

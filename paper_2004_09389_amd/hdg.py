@@ -170,7 +170,12 @@ def _ptr(t) -> ctypes.c_void_p:
 
 
 def _stream():
+    """The current HIP stream of the current device (torch's raw-handle query when
+    this torch build has it: it builds no Stream object)."""
     import torch
+    raw = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+    if raw is not None:
+        return ctypes.c_void_p(raw(torch.cuda.current_device()))
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
@@ -274,7 +279,7 @@ class HdgSolver:
             raise ValueError(f"{name}: tensor is on cuda:{t.device.index}, the context on cuda:{self.device}")
         if not t.is_contiguous():
             raise ValueError(f"{name}: expected a contiguous tensor")
-        if tuple(t.shape) != tuple(shape):
+        if t.shape != tuple(shape):
             raise ValueError(f"{name}: expected shape {tuple(shape)}, got {tuple(t.shape)}")
         return t
 
