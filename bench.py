@@ -75,6 +75,8 @@ def parse():
     ap.add_argument("--sphere-rhs", default="fourier", choices=["fourier", "iid"],
                     help="level-7 right-hand sides: smooth 3-D Fourier fields or iid coefficients")
     ap.add_argument("--no-torus", action="store_true", help="skip the 256x256 torus leg")
+    ap.add_argument("--torus-only", action="store_true",
+                    help="only the 256x256 torus leg")
     ap.add_argument("--no-traj", action="store_true", help="skip the level-6 trajectory leg")
     ap.add_argument("--no-gain", action="store_true", help="skip the learned-smoother gain leg")
     ap.add_argument("--no-imex", action="store_true", help="skip the IMEX time-stepping leg")
@@ -1000,6 +1002,9 @@ def main():
         return
     if args.dg_only:
         print(json.dumps({"dg_leg": dg_leg(args, args.degree, args.n, run_steps=min(args.steps, 3))}), flush=True)
+        return
+    if args.torus_only:   # the leg trains the learned smoother itself unless --no-learned
+        print(json.dumps({"torus_leg": torus_leg(args, {})}), flush=True)
         return
 
     # ---- the learned smoother's weights: trained once on the GPU on the 256x256 torus (config 2 mesh)

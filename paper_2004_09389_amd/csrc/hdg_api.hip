@@ -300,9 +300,13 @@ double *p1_vcycle(hdg_ctx *c, int l, int nb, hipStream_t s, bool f32) {
             std::swap(x, y);
         }
     }
-    hdg::launch_p1_resid(L.n, L.w, nb, L.col, L.val, L.diag, L.b, x, y, s, f32, rb);
     hdg::P1LevelDev &C = c->lev[l - 1];
-    hdg::launch_p1_restrict(C.n, nb, L.crow, L.ccol, L.cw, y, C.b, s, f32, rb);
+    if (nb == 1) {
+        hdg::launch_p1_resid_restrict(L.n, L.w, L.col, L.val, L.diag, L.b, x, C.n, L.crow, L.ccol, L.cw, C.b, s, f32);
+    } else {
+        hdg::launch_p1_resid(L.n, L.w, nb, L.col, L.val, L.diag, L.b, x, y, s, f32, rb);
+        hdg::launch_p1_restrict(C.n, nb, L.crow, L.ccol, L.cw, y, C.b, s, f32, rb);
+    }
     const double *xc = p1_vcycle(c, l - 1, nb, s, f32);
     for (int k = 0; k < c->opt.p1_nu; ++k) {
         hdg::launch_p1_sweep(L.n, L.w, nb, L.col, L.val, L.diag, L.dinv, w, L.b, x, k == 0 ? xc : nullptr,

@@ -160,7 +160,8 @@ void launch_p1_first(int n, int nb, const double *dinv, double omega, const doub
 void launch_p1_pre2(int n, int W, int nb, const int *col, const double *val, const double *diag,
                     const double *dinv, double omega, const double *b, double *x, hipStream_t s, bool f32 = false,
                     int rb = 1);
-// y = x + w D^-1 (b - A x); with xc != nullptr, x is first updated in place to x + P xc
+// y = x + w D^-1 (b - A x); with xc != nullptr, x is first updated in place to x + P xc (with one
+// right-hand side the prolonged values are formed inside the sweep instead and x is left as it is)
 void launch_p1_sweep(int n, int W, int nb, const int *col, const double *val, const double *diag,
                      const double *dinv, double omega, const double *b, double *x, const double *xc,
                      const int *parents, double *y, hipStream_t s, bool f32 = false, int rb = 1);
@@ -169,6 +170,10 @@ void launch_p1_resid(int n, int W, int nb, const int *col, const double *val, co
                      int rb = 1);
 void launch_p1_restrict(int nc, int nb, const int *crow, const int *ccol, const double *cw, const double *r,
                         double *bc, hipStream_t s, bool f32 = false, int rb = 1);
+// one right-hand side: bc = R (b - A x) from the fine level to the coarse one in one launch
+void launch_p1_resid_restrict(int n, int W, const int *col, const double *val, const double *diag, const double *b,
+                              const double *x, int nc, const int *crow, const int *ccol, const double *cw, double *bc,
+                              hipStream_t s, bool f32 = false);
 void launch_dense_mv(int n, int nb, const double *Ainv, const double *b, double *x, hipStream_t s, bool f32 = false);
 void launch_p1_tail(const P1Tail &T, int nb, hipStream_t s, bool f32 = false);
 

@@ -668,6 +668,55 @@ __global__ void k_p1_resid(int n, int W, int nb, const int *__restrict__ ell_col
     y[t] = (VT)((double)b[t] - p1_ax<WT>(v, n, W, nb, r, ell_col, ell_val, diag, x));
 }
 
+// One right-hand side (nb == 1), where a level's kernels are a few waves and a
+// launch costs more than its work: the residual fused into the restriction.
+// Eight lanes per coarse vertex each evaluate one child's residual in place (the
+// expression of k_p1_resid, rounded to the vector type as it stores it) and the
+// weighted values are summed by shuffles within the eight lanes.
+template <int WT, typename VT>
+__global__ void k_p1_resid_restrict(int n, int W, const int *__restrict__ ell_col, const double *__restrict__ ell_val,
+                                    const double *__restrict__ diag, const VT *__restrict__ b,
+                                    const VT *__restrict__ x, int nc, const int *__restrict__ crow,
+                                    const int *__restrict__ ccol, const double *__restrict__ cw,
+                                    VT *__restrict__ bc) {
+    const int t = xcd_block() * blockDim.x + threadIdx.x;
+    const int c = t >> 3, sub = t & 7;
+    double v = 0.0;   // every lane of a group takes part in the shuffles below
+    if (c < nc) {
+        const int k0 = crow[c], cnt = crow[c + 1] - k0;
+        for (int k = sub; k < cnt; k += 8) {
+            const int u = ccol[k0 + k];
+            const VT ru = (VT)((double)b[u] - p1_ax<WT>(u, n, W, 1, 0, ell_col, ell_val, diag, x));
+            v += cw[k0 + k] * (double)ru;
+        }
+    }
+    v += __shfl_xor(v, 1, 8);
+    v += __shfl_xor(v, 2, 8);
+    v += __shfl_xor(v, 4, 8);
+    if (c < nc && sub == 0) bc[c] = (VT)v;
+}
+
+// One right-hand side: the first post-sweep with the prolongation x' = x + P xc
+// evaluated at the vertex and its neighbours in place (rounded to the vector type
+// as k_p1_prolong stores it: the same bits as the two kernels)
+template <int WT, typename VT>
+__global__ void k_p1_sweep_prolong(int n, int W, const int *__restrict__ ell_col, const double *__restrict__ ell_val,
+                                   const double *__restrict__ diag, const double *__restrict__ dinv, double omega,
+                                   const VT *__restrict__ b, const VT *__restrict__ x, const int *__restrict__ parents,
+                                   const VT *__restrict__ xc, VT *__restrict__ y) {
+    const int v = xcd_block() * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    if (WT) W = WT;
+    auto xp = [&](int u) {
+        return (double)(VT)((double)x[u] + 0.5 * ((double)xc[parents[2 * u]] + (double)xc[parents[2 * u + 1]]));
+    };
+    const double xv = xp(v);
+    double s = diag[v] * xv;
+#pragma unroll
+    for (int k = 0; k < W; ++k) s += ell_val[(size_t)k * n + v] * xp(ell_col[(size_t)k * n + v]);
+    y[v] = (VT)(xv + omega * dinv[v] * ((double)b[v] - s));
+}
+
 // bc[c] = sum over children of w * r[child]  (transpose of the interpolation); the
 // children (7 on the icosahedral hierarchy) are read eight at a time, all loads in flight
 template <typename VT>
@@ -2068,6 +2117,8 @@ void launch_p1_pre2(int n, int W, int nb, const int *col, const double *val, con
              else { if (W == 6) PRE2(k_p1_pre2, 6); else PRE2(k_p1_pre2, 0); })
 #undef PRE2
 }
+#define SWPP(WW) hipLaunchKernelGGL((k_p1_sweep_prolong<WW, VT>), P1_GRID(n, 1, false), 0, s, n, W, col, val, diag, \
+                                    dinv, omega, pv<VT>(b), pv<VT>(x), parents, pv<VT>(xc), pv<VT>(y))
 void launch_p1_sweep(int n, int W, int nb, const int *col, const double *val, const double *diag,
                      const double *dinv, double omega, const double *b, double *x, const double *xc,
                      const int *parents, double *y, hipStream_t s, bool f32, int rb) {
@@ -2075,6 +2126,10 @@ void launch_p1_sweep(int n, int W, int nb, const int *col, const double *val, co
 #define SWP(K, WW) hipLaunchKernelGGL((K<WW, VT>), P1_GRID(n, nb, r4), 0, s, n, W, nb, col, val, diag, dinv, omega, \
                                       pv<VT>(b), pv<VT>(x), pv<VT>(y))
     P1_TYPED(
+        if (xc && nb == 1) {
+            if (W == 6) SWPP(6); else SWPP(0);
+            return;
+        }
         if (xc) {
             if (r4) hipLaunchKernelGGL(k_p1_prolong4<VT>, P1_GRID(n, nb, r4), 0, s, n, nb, parents, pv<VT>(xc), pv<VT>(x));
             else hipLaunchKernelGGL(k_p1_prolong<VT>, P1_GRID(n, nb, r4), 0, s, n, nb, parents, pv<VT>(xc), pv<VT>(x));
@@ -2083,6 +2138,7 @@ void launch_p1_sweep(int n, int W, int nb, const int *col, const double *val, co
         else { if (W == 6) SWP(k_p1_sweep, 6); else SWP(k_p1_sweep, 0); })
 #undef SWP
 }
+#undef SWPP
 void launch_p1_resid(int n, int W, int nb, const int *col, const double *val, const double *diag,
                      const double *b, const double *x, double *y, hipStream_t s, bool f32, int rb) {
     const bool r4 = p1_r4(rb, nb);
@@ -2099,6 +2155,15 @@ void launch_p1_restrict(int nc, int nb, const int *crow, const int *ccol, const 
                                         pv<VT>(r), pv<VT>(bc));
              else hipLaunchKernelGGL(k_p1_restrict<VT>, P1_GRID(nc, nb, r4), 0, s, nc, nb, crow, ccol, cw, pv<VT>(r),
                                      pv<VT>(bc)))
+}
+void launch_p1_resid_restrict(int n, int W, const int *col, const double *val, const double *diag, const double *b,
+                              const double *x, int nc, const int *crow, const int *ccol, const double *cw, double *bc,
+                              hipStream_t s, bool f32) {
+#define RR(WW) hipLaunchKernelGGL((k_p1_resid_restrict<WW, VT>), P1_GRID((int64_t)nc * 8, 1, false), 0, s, n, W, col, \
+                                  val, diag, \
+                                  pv<VT>(b), pv<VT>(x), nc, crow, ccol, cw, pv<VT>(bc))
+    P1_TYPED(if (W == 6) RR(6); else RR(0))
+#undef RR
 }
 #undef P1_GRID
 // the row-block product for nb = 1 and nb = 4 NQ (NQ = 1, 2, 4, 8, 16), else a
