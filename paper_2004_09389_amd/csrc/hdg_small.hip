@@ -379,23 +379,31 @@ __device__ double s_sweep(int ne, const Ops &O, double omega, const double *x, c
     return part;
 }
 
-// pi^T: rc[v] = sum over facet ends at v of sum_k w_end(k) res[e][k]
+// pi^T: rc[v] = sum over facet ends at v of sum_k w_end(k) res[e][k].  Four lanes
+// per vertex take every fourth facet end and add their sums by shuffles, so that
+// the whole workgroup shares the short per-vertex lists.
 template <int M, bool OL>
 __device__ void s_restrict_trace(int nv, const Ops &O, const double *res, lds_dbl *rc) {
     constexpr int P = M - 1;
     const int *vf_row = O.vf_row, *vf_col = O.vf_col;
-    for (int v = threadIdx.x; v < nv; v += SMALL_THREADS) {
-        const int c0 = opri<OL>(vf_row + v);
-        rc[v] = range_sum(opri<OL>(vf_row + v + 1) - c0, [&](int k) {
-            const int code = opri<OL>(vf_col + c0 + k), e = code >> 1, end = code & 1;
-            double acc = 0.0;
+    const int nvr = (nv + SMALL_THREADS / 4 - 1) / (SMALL_THREADS / 4) * (SMALL_THREADS / 4);   // uniform trip count
+    for (int v0 = 0; v0 < nvr; v0 += SMALL_THREADS / 4) {
+        const int v = v0 + (threadIdx.x >> 2), sub = threadIdx.x & 3;
+        double acc = 0.0;
+        if (v < nv) {
+            const int c1 = opri<OL>(vf_row + v + 1);
+            for (int k = opri<OL>(vf_row + v) + sub; k < c1; k += 4) {
+                const int code = opri<OL>(vf_col + k), e = code >> 1, end = code & 1;
 #pragma unroll
-            for (int q = 0; q < M; ++q) {
-                const double w = end ? (double)q / P : 1.0 - (double)q / P;
-                acc += w * res[e * M + q];
+                for (int q = 0; q < M; ++q) {
+                    const double w = end ? (double)q / P : 1.0 - (double)q / P;
+                    acc += w * res[e * M + q];
+                }
             }
-            return acc;
-        });
+        }
+        acc += __shfl_xor(acc, 1, 64);
+        acc += __shfl_xor(acc, 2, 64);
+        if (v < nv && sub == 0) rc[v] = acc;
     }
 }
 
