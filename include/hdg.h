@@ -147,7 +147,9 @@ typedef struct {
                                    geometric mean over the current restart cycle, checked from
                                    its second iteration on (default 0.5) */
     int32_t p1_tail_max;        /* P1 levels with at most this many vertices run inside one
-                                   single-workgroup kernel (default 4096, max 4096, 0 = never) */
+                                   single-workgroup kernel (default 4096, max 4096, 0 = never);
+                                   only when the coarsest level has at most 256 vertices, and
+                                   per call only when nrhs x the top tail level's vertices <= 4096 */
     int32_t p1_galerkin;        /* (upwind flux only) 0: the rediscretised coarse form (1/kappa)(M_1 + kappa^2 K_1) on
                                    every P1 level (default); 1: the Galerkin form S_c = pi^T S pi on
                                    the finest P1 level (the footnoted alternative of the non-nested

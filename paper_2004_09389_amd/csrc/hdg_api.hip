@@ -279,7 +279,7 @@ void op_sweep(hdg_ctx *c, int nb, int prec, const double *x, const double *z0, c
 // (inside a V-cycle whose trace vectors are FP32, the P1 vectors are too).
 double *p1_vcycle(hdg_ctx *c, int l, int nb, hipStream_t s, bool f32) {
     hdg::P1LevelDev &L = c->lev[l];
-    if (l == c->tail_top) {
+    if (l == c->tail_top && (int64_t)nb * L.n <= hdg::P1_TAIL_MAX) {   // one workgroup: few values only
         hdg::launch_p1_tail(c->tail, nb, s, f32);
         return L.x;
     }
@@ -1221,10 +1221,12 @@ void setup_impl(const hdg_mesh *levels, int nlev, const int32_t *const *parents,
     }
 
     // ---- tail of the P1 hierarchy (levels small enough for one workgroup)
+    // (one workgroup also reads the dense coarsest inverse: only for a small coarsest level)
     c->tail_top = -1;
-    for (int l = 0; l < (int)c->lev.size() && l < hdg::P1_TAIL_LEVELS; ++l)
-        if (c->lev[l].n <= opt.p1_tail_max) c->tail_top = l;
-        else break;
+    if (!c->lev.empty() && c->lev[0].n <= hdg::P1_TAIL_DENSE_MAX)   // (no P1 hierarchy with the LF flux)
+        for (int l = 0; l < (int)c->lev.size() && l < hdg::P1_TAIL_LEVELS; ++l)
+            if (c->lev[l].n <= opt.p1_tail_max) c->tail_top = l;
+            else break;
     if (c->tail_top >= 0) {
         hdg::P1Tail &T = c->tail;
         T.top = c->tail_top;

@@ -45,6 +45,7 @@ struct P1LevelDev {
 };
 
 constexpr int P1_TAIL_MAX = 4096;   // levels up to this many vertices run in the tail kernel
+constexpr int P1_TAIL_DENSE_MAX = 256;   // the tail also takes the dense coarsest product: only this small
 constexpr int P1_TAIL_LEVELS = 8;
 
 struct P1Lev {
