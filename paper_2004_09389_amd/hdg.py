@@ -196,6 +196,9 @@ class HdgSolver:
     layouts of the C ABI: cell arrays (n_cell, 3, n_loc, nrhs), trace arrays
     (n_facet, facet_dofs, nrhs) with facet_dofs = p+1 (upwind flux) or
     2(p+1) (flux=HDG_FLUX_LF: x components at the nodes, then y).
+
+    omega is the Earth's rotation rate (the Coriolis term); the block-Jacobi
+    damping, the options field of the same name, is set with damping=.
     """
 
     def __init__(self, hierarchy, degree: int, dt: float, g: float = 1.0, H: float = 1.0,
@@ -206,6 +209,8 @@ class HdgSolver:
         self.device = torch.cuda.current_device()
         self.hier = hierarchy
         opt = default_options()
+        if "damping" in options:
+            opt.omega = float(options.pop("damping"))
         for k, v in options.items():
             if not hasattr(opt, k):
                 raise ValueError(f"unknown option {k}")

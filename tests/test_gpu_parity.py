@@ -110,6 +110,19 @@ def test_vcycle(name):
     assert rel(z16, ref) < 3e-2
 
 
+@pytest.mark.parametrize("damping", [0.55, 0.9])
+def test_vcycle_damping_option(damping):
+    """The block-Jacobi damping set through the binding (damping=, the options
+    field omega) reaches the kernels: V-cycle against the oracle's at that damping."""
+    from oracle.p1 import TraceMultigrid
+    hier, solver, oracle, _ = setup_case("torus16_p3_f1", damping=damping)
+    mg = TraceMultigrid(oracle, hier, omega=damping)
+    r = np.random.default_rng(6).standard_normal((solver.n_facet, solver.m, 1))
+    ref = mg.vcycle(r[..., 0].ravel())
+    assert rel(trace_np(solver.mg_vcycle(to_dev(r)))[..., 0].ravel(), ref) < 1e-11
+    assert rel(ref, TraceMultigrid(oracle, hier).vcycle(r[..., 0].ravel())) > 1e-3   # the damping matters
+
+
 @pytest.mark.parametrize("name", ["config1_torus8_p1", "torus96_p1_deep", "sphere_L2_p2"])
 def test_vcycle_without_tail_kernel(name):
     """Every P1 level as separate kernels (and the dense coarsest solve as a
