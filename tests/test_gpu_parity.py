@@ -110,6 +110,27 @@ def test_vcycle(name):
     assert rel(z16, ref) < 3e-2
 
 
+@pytest.mark.parametrize("name", ["torus16_p3_f1", "sphere_L2_p2", "torus96_p1_deep"])
+def test_one_rhs_p1_kernels_match_the_batched_path(name):
+    """At one right-hand side the P1 residual is fused into the restriction (its
+    children summed by shuffles instead of in list order) and the prolongation
+    into the first post-sweep; the one-column V-cycle agrees with column 0 of the
+    four-column one (one thread per (vertex, rhs), separate kernels) to rounding:
+    1e-13 in FP64, 1e-5 with FP32 P1 vectors; both against the oracle (P1 tail
+    off, so every level runs its kernels)."""
+    from paper_2004_09389_amd.hdg import HDG_MIXED
+    hier, s, oracle, mg = setup_case(name, p1_tail_max=0, max_rhs=4)
+    s.set_tuning(rhs_block=1)
+    x = np.random.default_rng(61).standard_normal((s.n_facet, s.m, 4))
+    ref = mg.vcycle(x[..., 0].ravel())
+    for prec, tol, otol in ((0, 1e-13, 1e-11), (HDG_MIXED, 1e-5, 3e-2)):
+        z4 = trace_np(s.mg_vcycle(to_dev(x), prec))
+        z1 = trace_np(s.mg_vcycle(to_dev(np.ascontiguousarray(x[..., :1])), prec))
+        assert rel(z1[..., 0].ravel(), z4[..., 0].ravel()) < tol, prec
+        assert rel(z1[..., 0].ravel(), ref) < otol, prec
+    s.set_tuning(rhs_block=4)
+
+
 @pytest.mark.parametrize("damping", [0.55, 0.9])
 def test_vcycle_damping_option(damping):
     """The block-Jacobi damping set through the binding (damping=, the options
