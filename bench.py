@@ -1007,7 +1007,7 @@ def main():
         print(json.dumps({"torus_leg": torus_leg(args, {})}), flush=True)
         return
 
-    # ---- the learned smoother's weights: trained once on the GPU on the 256x256 torus (config 2 mesh)
+    # ---- the learned smoother's weights: trained once on the GPU on the 256x256 torus (p = 3, Courant 8)
     trained = {}
     head = args.sphere_headline
     if not args.no_learned and "learned_ir" in args.sphere_legs.split(","):

@@ -60,7 +60,7 @@ def _sphere(level, p, dt):
     return hier, dict(degree=p, dt=dt, g=9.81, H=5960.0, f0=0.0, omega=7.292e-5), rhs
 
 
-CONFIGS = {
+FULL_SIZE_CASES = {
     "torus256_p1": (lambda: _torus256(1), 1),
     "torus256_p2": (lambda: _torus256(2), 1),
     "torus256_p3": (lambda: _torus256(3), 1),
@@ -74,7 +74,7 @@ CONFIGS = {
 def problem(name):
     from oracle.hdg import HdgOracle
     from oracle.p1 import TraceMultigrid
-    mk, nb = CONFIGS[name]
+    mk, nb = FULL_SIZE_CASES[name]
     hier, phys, rhs = mk()
     print(f"[fullsize] oracle {name}", flush=True)
     o = HdgOracle(hier.fine, phys["degree"], phys["dt"], phys["g"], phys["H"], phys["f0"], phys["omega"])
@@ -105,7 +105,7 @@ def host(t):
     return t.detach().cpu().numpy()
 
 
-@pytest.mark.parametrize("name", list(CONFIGS))
+@pytest.mark.parametrize("name", list(FULL_SIZE_CASES))
 def test_operators_full_size(name):
     """rhat, S x (FP64 and FP32 rows), recovery and the V-cycle over every entry."""
     from paper_2004_09389_amd.hdg import HDG_MIXED
@@ -132,7 +132,7 @@ def test_operators_full_size(name):
     s.close()
 
 
-@pytest.mark.parametrize("name", list(CONFIGS))
+@pytest.mark.parametrize("name", list(FULL_SIZE_CASES))
 @pytest.mark.parametrize("precision", ["fp64", "mixed", "mixed_ir"])
 def test_solve_full_size_certified(name, precision):
     """Batched solve to 1e-8 in the benchmark's configuration; the oracle

@@ -337,22 +337,22 @@ def _gain(hier, p, dt, f0, kind, rtol, seeds=range(2000, 2010)):
     return hist, np.array(its), np.array(ms)
 
 
-def test_config1_training_and_gain():
-    """Config 1 (8 x 8 torus, p = 1, f = 0, Courant 4, iid right-hand sides):
+def test_torus8_p1_training_and_gain():
+    """The 8 x 8 torus (p = 1, f = 0, Courant 4, iid right-hand sides):
     on unseen seeds 2000-2009 the trained network needs fewer FGMRES
     iterations to 1e-8 than block-Jacobi on average and never more on a seed;
     the time per solve of both is reported (at 384 unknowns each iteration is
     a chain of launches, so the learned step's extra launch costs time)."""
     hier = hi.torus_hierarchy(8, 4)
     hist, its, ms = _gain(hier, 1, 0.5, 0.0, "iid", 1e-8)
-    print(f"config 1 loss {hist[0]:.3f} -> {hist[-1]:.3f}; iterations (block-Jacobi, learned): {its.tolist()}; "
+    print(f"8x8 torus loss {hist[0]:.3f} -> {hist[-1]:.3f}; iterations (block-Jacobi, learned): {its.tolist()}; "
           f"mean ms per solve {ms.mean(0).round(4).tolist()}")
     assert hist[-1] < hist[0]
     assert its[:, 1].mean() < its[:, 0].mean() and np.all(its[:, 1] <= its[:, 0])
 
 
-def test_config2_gain_iterations_and_time():
-    """Config 2 (256 x 256 torus, p = 3, f = 1, Courant 8, Fourier right-hand
+def test_torus256_p3_gain_iterations_and_time():
+    """The 256 x 256 torus (p = 3, f = 1, Courant 8, Fourier right-hand
     sides): on unseen seeds 2000-2009, iterations and time to 1e-8 of the
     learned smoother against block-Jacobi.  The network must gain in at least
     one of the two (it gains iterations: about one per solve); both are printed."""
@@ -360,7 +360,7 @@ def test_config2_gain_iterations_and_time():
     hist, its, ms = _gain(hier, 3, 8.0 / 256, 1.0, "fourier", 1e-8)
     gain_its = its[:, 0].mean() - its[:, 1].mean()
     gain_time = ms[:, 0].mean() - ms[:, 1].mean()
-    print(f"config 2 loss {hist[0]:.3f} -> {hist[-1]:.3f}; iterations (block-Jacobi, learned): {its.tolist()}; "
+    print(f"256x256 torus loss {hist[0]:.3f} -> {hist[-1]:.3f}; iterations (block-Jacobi, learned): {its.tolist()}; "
           f"mean ms per solve {ms.mean(0).round(4).tolist()} (gain {gain_its:.2f} iterations, {gain_time:.4f} ms)")
     assert gain_its > 0 or gain_time > 0
     assert np.all(its[:, 1] <= its[:, 0] + 1)

@@ -18,7 +18,7 @@ HMS = 6.371e6
 def _cases():
     return {
         # name: (hierarchy factory, p, dt, g, H, f0, omega)
-        "config1_torus8_p1": (lambda: hi.torus_hierarchy(8, 4), 1, 0.5, 1.0, 1.0, 0.0, 0.0),
+        "torus8_p1_courant4": (lambda: hi.torus_hierarchy(8, 4), 1, 0.5, 1.0, 1.0, 0.0, 0.0),
         "torus12_p2_coriolis": (lambda: hi.torus_hierarchy(12, 3), 2, 0.3, 2.0, 0.5, 0.7, 0.0),
         "torus16_p3_f1": (lambda: hi.torus_hierarchy(16, 4), 3, 0.5, 1.0, 1.0, 1.0, 0.0),
         "torus1_twocell_p1": (lambda: hi.torus_hierarchy(1, 1), 1, 0.5, 1.0, 1.0, 0.0, 0.0),
@@ -144,7 +144,7 @@ def test_vcycle_damping_option(damping):
     assert rel(ref, TraceMultigrid(oracle, hier).vcycle(r[..., 0].ravel())) > 1e-3   # the damping matters
 
 
-@pytest.mark.parametrize("name", ["config1_torus8_p1", "torus96_p1_deep", "sphere_L2_p2"])
+@pytest.mark.parametrize("name", ["torus8_p1_courant4", "torus96_p1_deep", "sphere_L2_p2"])
 def test_vcycle_without_tail_kernel(name):
     """Every P1 level as separate kernels (and the dense coarsest solve as a
     multi-block mat-vec) gives the same V-cycle as the single-workgroup tail."""
@@ -170,7 +170,7 @@ def test_solve_and_recover_fp64(name):
         assert rel(q[:, fld], q_ref[:, fld]) < 1e-10
 
 
-@pytest.mark.parametrize("name", ["config1_torus8_p1", "torus16_p3_f1", "sphere_L2_p2"])
+@pytest.mark.parametrize("name", ["torus8_p1_courant4", "torus16_p3_f1", "sphere_L2_p2"])
 def test_solve_mixed(name):
     from paper_2004_09389_amd.hdg import HDG_MIXED, HDG_KRYLOV_FGMRES
     hier, solver, oracle, _ = setup_case(name, rtol=1e-10, precision=HDG_MIXED, krylov=HDG_KRYLOV_FGMRES)
@@ -185,7 +185,7 @@ def test_solve_mixed(name):
         assert rel(q[:, fld], q_ref[:, fld]) < 1e-8
 
 
-@pytest.mark.parametrize("name", ["config1_torus8_p1", "torus16_p3_f1", "sphere_L2_p2"])
+@pytest.mark.parametrize("name", ["torus8_p1_courant4", "torus16_p3_f1", "sphere_L2_p2"])
 @pytest.mark.parametrize("nb", [1, 3, 4])
 def test_solve_mixed_ir(name, nb):
     """HDG_MIXED_IR: FP64 refinement around an inner FGMRES whose basis and
@@ -206,7 +206,7 @@ def test_solve_mixed_ir(name, nb):
     print(f"{name} nb={nb}: {info[0]}")
 
 
-@pytest.mark.parametrize("name", ["config1_torus8_p1", "torus12_p2_coriolis"])
+@pytest.mark.parametrize("name", ["torus8_p1_courant4", "torus12_p2_coriolis"])
 def test_batched_matches_single(name):
     hier, solver, oracle, _ = setup_case(name, rtol=1e-12, max_rhs=3)
     r = hi.iid_rhs(hier.fine, solver.p, 41, nrhs=3)
@@ -219,7 +219,7 @@ def test_batched_matches_single(name):
             assert rel(qb[:, fld, :, k], q_ref[:, fld]) < 1e-10
 
 
-@pytest.mark.parametrize("name,prec", [("config1_torus8_p1", 0), ("torus16_p3_f1", 0), ("torus16_p3_f1", 1),
+@pytest.mark.parametrize("name,prec", [("torus8_p1_courant4", 0), ("torus16_p3_f1", 0), ("torus16_p3_f1", 1),
                                        ("torus16_p3_f1", 2)])
 def test_graph_replay_matches_eager(name, prec):
     """Captured Krylov iterations replayed several times, with eager work and
@@ -238,7 +238,7 @@ def test_graph_replay_matches_eager(name, prec):
         assert torch.equal(lg, le) and torch.equal(qg, qe), (seed, float(junk))
 
 
-@pytest.mark.parametrize("name", ["config1_torus8_p1", "torus12_p2_coriolis", "torus16_p3_f1"])
+@pytest.mark.parametrize("name", ["torus8_p1_courant4", "torus12_p2_coriolis", "torus16_p3_f1"])
 @pytest.mark.parametrize("nb", [4, 8, 16])
 def test_rhs_blocked_rows_bitwise(name, nb):
     """Four right-hand sides per thread with LDS-staged rows accumulate in the
@@ -274,7 +274,7 @@ def _rhs_blocked_bitwise(name, nb):
         assert rel(outs[4][2][..., k].ravel(), mg.vcycle(x[..., k].ravel())) < 1e-11
 
 
-@pytest.mark.parametrize("name", ["config1_torus8_p1", "torus12_p2_coriolis", "torus16_p3_f1", "sphere_L2_p2"])
+@pytest.mark.parametrize("name", ["torus8_p1_courant4", "torus12_p2_coriolis", "torus16_p3_f1", "sphere_L2_p2"])
 def test_batched_cell_kernels_bitwise(name):
     """Condense and recover with 8 right-hand sides equal the one-column calls
     bit for bit and the oracle to 1e-12."""
@@ -295,7 +295,7 @@ def test_batched_cell_kernels_bitwise(name):
             assert rel(q_b[:, fld, :, k], q_ref[:, fld]) < 1e-12
 
 
-CHEB_CASES = ["config1_torus8_p1", "torus12_p2_coriolis", "torus16_p3_f1", "sphere_L2_p2"]
+CHEB_CASES = ["torus8_p1_courant4", "torus12_p2_coriolis", "torus16_p3_f1", "sphere_L2_p2"]
 
 
 @pytest.mark.parametrize("name", CHEB_CASES)
@@ -327,7 +327,7 @@ def test_chebyshev_rhs_blocked_bitwise(name):
         assert np.array_equal(a, b)
 
 
-@pytest.mark.parametrize("name,prec", [("config1_torus8_p1", 0), ("torus16_p3_f1", 0), ("torus16_p3_f1", 1),
+@pytest.mark.parametrize("name,prec", [("torus8_p1_courant4", 0), ("torus16_p3_f1", 0), ("torus16_p3_f1", 1),
                                        ("sphere_L2_p2", 1)])
 def test_chebyshev_solve(name, prec):
     """Solves with the Chebyshev smoother (PCG when symmetric, else FGMRES)."""
@@ -343,7 +343,7 @@ def test_chebyshev_solve(name, prec):
         assert rel(trace_np(q)[:, fld, :, 0], q_ref[:, fld]) < 1e-9
 
 
-@pytest.mark.parametrize("name", ["config1_torus8_p1", "torus12_p2_coriolis", "torus16_p3_f1", "sphere_L2_p2",
+@pytest.mark.parametrize("name", ["torus8_p1_courant4", "torus12_p2_coriolis", "torus16_p3_f1", "sphere_L2_p2",
                                   "torus96_p1_deep"])
 def test_galerkin_coarse_form(name):
     """Galerkin P1 hierarchy (S_c = pi^T S pi, then P^T A P) against the oracle's:

@@ -39,7 +39,7 @@ def check_vs_oracle(q, lam, r, mesh, p, dt, f0=0.0, omega=0.0, g=1.0, H=1.0, tol
             assert rel(q[:, fld, :, k], q_ref[:, fld]) < tol, (k, fld)
 
 
-def test_config1_qualifies_and_matches_the_oracle():
+def test_torus8_p1_qualifies_and_matches_the_oracle():
     """8x8 torus (128 cells), p = 1, f = 0, Courant 4: the context qualifies
     for the persistent solve; Steps 1-3 in one launch equal the oracle's direct
     solve (PCG, rtol 1e-12)."""
