@@ -26,8 +26,8 @@ __device__ __forceinline__ int xcd_block() {
 typedef double trace_dbl2_t __attribute__((ext_vector_type(2)));
 typedef float trace_flt2_t __attribute__((ext_vector_type(2)));
 typedef float trace_flt4_t __attribute__((ext_vector_type(4)));
-template <int M, bool NB1, typename T>
-__device__ __forceinline__ void load_trace(const T *__restrict__ v, size_t base, int nb, double (&d)[M]) {
+template <int M, bool NB1, typename T, typename D>
+__device__ __forceinline__ void load_trace(const T *__restrict__ v, size_t base, int nb, D (&d)[M]) {
     if constexpr (NB1 && std::is_same<T, double>::value && M % 2 == 0) {
 #pragma unroll
         for (int j = 0; j < M; j += 2) {
@@ -53,11 +53,11 @@ __device__ __forceinline__ void load_trace(const T *__restrict__ v, size_t base,
         }
     } else {
 #pragma unroll
-        for (int j = 0; j < M; ++j) d[j] = (double)v[base + (size_t)(NB1 ? j : j * nb)];
+        for (int j = 0; j < M; ++j) d[j] = (D)v[base + (size_t)(NB1 ? j : j * nb)];
     }
 }
-template <int M, bool NB1, typename T>
-__device__ __forceinline__ void store_trace(T *__restrict__ v, size_t base, int nb, const double (&d)[M]) {
+template <int M, bool NB1, typename T, typename D>
+__device__ __forceinline__ void store_trace(T *__restrict__ v, size_t base, int nb, const D (&d)[M]) {
     if constexpr (NB1 && std::is_same<T, double>::value && M % 2 == 0) {
 #pragma unroll
         for (int j = 0; j < M; j += 2)
@@ -86,6 +86,11 @@ __device__ __forceinline__ double p1_node(int k, double q0, double q1) {
     const double t = (double)k / P;
     return __builtin_fma(t, q1, (1.0 - t) * q0);
 }
+template <int P>
+__device__ __forceinline__ float p1_node(int k, float q0, float q1) {
+    const float t = (float)k / P;
+    return __builtin_fmaf(t, q1, (1.0f - t) * q0);
+}
 
 // Coefficients of the generalised smoothing sweep
 //   y = a0 x' + a1 z0 - a3 T x' + a2 xprev'
@@ -103,6 +108,18 @@ struct SweepCoef {
 __device__ __forceinline__ double sweep_combine(const SweepCoef &cf, double x, double z, double acc) {
     return __builtin_fma(-cf.a3, acc, __builtin_fma(cf.a0, x, cf.a1 * z));
 }
+// Sweeps on FP32 vectors (the mixed V-cycle) evaluate the same formulas in FP32:
+// the combination, the prolongation term and the previous-iterate term.
+__device__ __forceinline__ float sweep_combine(const SweepCoef &cf, float x, float z, float acc) {
+    return __builtin_fmaf(-(float)cf.a3, acc, __builtin_fmaf((float)cf.a0, x, (float)cf.a1 * z));
+}
+__device__ __forceinline__ double sweep_prev(double a2, double pv, double out) { return __builtin_fma(a2, pv, out); }
+__device__ __forceinline__ float sweep_prev(double a2, float pv, float out) {
+    return __builtin_fmaf((float)a2, pv, out);
+}
+// the arithmetic type of a sweep on vectors of type VT
+template <typename VT>
+using SweepT = typename std::conditional<std::is_same<VT, float>::value, float, double>::type;
 
 // The condensation rows Zr (C A^-1 Mtilde, length nc per trace row) are stored
 // in 16-byte pairs [entry / 2][n_cell][2], rows padded to an even length.

@@ -488,6 +488,7 @@ __global__ __launch_bounds__(256) void k_sweep(int ne, int nb, const MT *__restr
                                                const int *__restrict__ fvert, SweepCoef cf,
                                                VT *__restrict__ y) {
     using AT = typename Acc<MT>::type;
+    using CT = SweepT<VT>;
     constexpr int P = M - 1;
     constexpr int V = Wide<MT>::V, C = 4 * M * M, G = padded(C, V) / V;
     const int t = xcd_block() * blockDim.x + threadIdx.x;
@@ -498,13 +499,13 @@ __global__ __launch_bounds__(256) void k_sweep(int ne, int nb, const MT *__restr
     id[0] = e;
 #pragma unroll
     for (int j = 0; j < 4; ++j) id[j + 1] = nbr[j * NE + e];
-    double xv[5][M];
+    CT xv[5][M];
 #pragma unroll
     for (int j = 0; j < 5; ++j) {
         load_trace<M, NB1>(x, id[j] * MB + r, nb, xv[j]);
         if (qc) {
-            const double q0 = (double)qc[(size_t)fvert[2 * id[j]] * nb + r];
-            const double q1 = (double)qc[(size_t)fvert[2 * id[j] + 1] * nb + r];
+            const CT q0 = (CT)qc[(size_t)fvert[2 * id[j]] * nb + r];
+            const CT q1 = (CT)qc[(size_t)fvert[2 * id[j] + 1] * nb + r];
 #pragma unroll
             for (int k = 0; k < M; ++k) xv[j][k] += p1_node<P>(k, q0, q1);
         }
@@ -525,21 +526,21 @@ __global__ __launch_bounds__(256) void k_sweep(int ne, int nb, const MT *__restr
             }
         }
     }
-    double zv[M], out[M];
+    CT zv[M], out[M];
     load_trace<M, NB1>(z0, e * MB + r, nb, zv);
 #pragma unroll
-    for (int a = 0; a < M; ++a) out[a] = sweep_combine(cf, xv[0][a], zv[a], (double)acc[a]);
+    for (int a = 0; a < M; ++a) out[a] = sweep_combine(cf, xv[0][a], zv[a], (CT)acc[a]);
     if (cf.xprev) {
-        double pv[M];
+        CT pv[M];
         load_trace<M, NB1>(static_cast<const VT *>(cf.xprev), e * MB + r, nb, pv);
         if (cf.qcprev) {
             const VT *qp = static_cast<const VT *>(cf.qcprev);
-            const double q0 = (double)qp[(size_t)fvert[2 * e] * nb + r], q1 = (double)qp[(size_t)fvert[2 * e + 1] * nb + r];
+            const CT q0 = (CT)qp[(size_t)fvert[2 * e] * nb + r], q1 = (CT)qp[(size_t)fvert[2 * e + 1] * nb + r];
 #pragma unroll
             for (int a = 0; a < M; ++a) pv[a] += p1_node<P>(a, q0, q1);
         }
 #pragma unroll
-        for (int a = 0; a < M; ++a) out[a] = __builtin_fma(cf.a2, pv[a], out[a]);
+        for (int a = 0; a < M; ++a) out[a] = sweep_prev(cf.a2, pv[a], out[a]);
     }
     store_trace<M, NB1>(y, e * MB + r, nb, out);
 }
@@ -1487,6 +1488,25 @@ __device__ __forceinline__ void store_raw(T *__restrict__ p, const T (&d)[RB]) {
     }
 }
 
+// RB consecutive values of a sweep's vectors in its arithmetic type (SweepT):
+// FP32 vectors stay FP32, FP64 vectors (or FP32 ones in an FP64 sweep) are read as double
+template <int RB, typename T, typename C>
+__device__ __forceinline__ void load_ct(const T *__restrict__ p, C (&d)[RB]) {
+    if constexpr (std::is_same<C, double>::value) load_rb<RB>(p, d);
+    else load_raw<RB>(p, d);
+}
+template <int RB, typename T, typename C>
+__device__ __forceinline__ void store_ct(T *__restrict__ p, const C (&d)[RB]) {
+    if constexpr (std::is_same<C, double>::value) {
+        store_rb<RB>(p, d);
+    } else {
+#pragma unroll
+        for (int q = 0; q < RB; q += 4)
+            __builtin_nontemporal_store(trace_flt4_t{d[q], d[q + 1], d[q + 2], d[q + 3]},
+                                        reinterpret_cast<trace_flt4_t *>(p + q));
+    }
+}
+
 // ---------------------------------------------------------------- P1 levels, four right-hand sides per thread
 // With nb % 4 == 0 a thread of the P1 level kernels takes four consecutive
 // right-hand sides of one vertex: each index and matrix entry is loaded once
@@ -1779,6 +1799,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(sweep_rb_w
                                                    const int *__restrict__ fvert, SweepCoef cf,
                                                    VT *__restrict__ y) {
     using AT = typename Acc<MT>::type;
+    using CT = SweepT<VT>;
     constexpr int P = M - 1;
     constexpr int V = Wide<MT>::V, C = 4 * M * M, G = padded(C, V) / V;
     __shared__ __attribute__((aligned(16))) MT sm[G * RB_FACETS * V];
@@ -1821,13 +1842,13 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(sweep_rb_w
         if (qc) {
             const int v0 = j == 0 ? iv[0][0] : j == 1 ? iv[1][0] : j == 2 ? iv[2][0] : iv[3][0];
             const int v1 = j == 0 ? iv[0][1] : j == 1 ? iv[1][1] : j == 2 ? iv[2][1] : iv[3][1];
-            double q0[RB], q1[RB];
-            load_rb<RB>(qc + (size_t)v0 * nb + r0, q0);
-            load_rb<RB>(qc + (size_t)v1 * nb + r0, q1);
+            CT q0[RB], q1[RB];
+            load_ct<RB>(qc + (size_t)v0 * nb + r0, q0);
+            load_ct<RB>(qc + (size_t)v1 * nb + r0, q1);
 #pragma unroll
             for (int k = 0; k < M; ++k)
 #pragma unroll
-                for (int q = 0; q < RB; ++q) xv[k][q] = (AT)((double)raw[k][q] + p1_node<P>(k, q0[q], q1[q]));
+                for (int q = 0; q < RB; ++q) xv[k][q] = (AT)((CT)raw[k][q] + p1_node<P>(k, q0[q], q1[q]));
         } else {
 #pragma unroll
             for (int k = 0; k < M; ++k)
@@ -1844,37 +1865,37 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(sweep_rb_w
                 for (int q = 0; q < RB; ++q) acc[a][q] += w * xv[k][q];
             }
     }
-    double q0[RB], q1[RB], p0[RB], p1[RB];
+    CT q0[RB], q1[RB], p0[RB], p1[RB];
     if (qc) {
-        load_rb<RB>(qc + (size_t)fvert[2 * e] * nb + r0, q0);
-        load_rb<RB>(qc + (size_t)fvert[2 * e + 1] * nb + r0, q1);
+        load_ct<RB>(qc + (size_t)fvert[2 * e] * nb + r0, q0);
+        load_ct<RB>(qc + (size_t)fvert[2 * e + 1] * nb + r0, q1);
     }
     if (cf.xprev && cf.qcprev) {
         const VT *qp = static_cast<const VT *>(cf.qcprev);
-        load_rb<RB>(qp + (size_t)fvert[2 * e] * nb + r0, p0);
-        load_rb<RB>(qp + (size_t)fvert[2 * e + 1] * nb + r0, p1);
+        load_ct<RB>(qp + (size_t)fvert[2 * e] * nb + r0, p0);
+        load_ct<RB>(qp + (size_t)fvert[2 * e + 1] * nb + r0, p1);
     }
 #pragma unroll
     for (int a = 0; a < M; ++a) {
         const size_t o = ((size_t)e * M + a) * nb + r0;
-        double xe[RB], zv[RB], out[RB];
-        load_rb<RB>(x + o, xe);
-        load_rb<RB>(z0 + o, zv);
+        CT xe[RB], zv[RB], out[RB];
+        load_ct<RB>(x + o, xe);
+        load_ct<RB>(z0 + o, zv);
         if (qc)
 #pragma unroll
             for (int q = 0; q < RB; ++q) xe[q] += p1_node<P>(a, q0[q], q1[q]);
 #pragma unroll
-        for (int q = 0; q < RB; ++q) out[q] = sweep_combine(cf, xe[q], zv[q], (double)acc[a][q]);
+        for (int q = 0; q < RB; ++q) out[q] = sweep_combine(cf, xe[q], zv[q], (CT)acc[a][q]);
         if (cf.xprev) {
-            double pv[RB];
-            load_rb<RB>(static_cast<const VT *>(cf.xprev) + o, pv);
+            CT pv[RB];
+            load_ct<RB>(static_cast<const VT *>(cf.xprev) + o, pv);
             if (cf.qcprev)
 #pragma unroll
                 for (int q = 0; q < RB; ++q) pv[q] += p1_node<P>(a, p0[q], p1[q]);
 #pragma unroll
-            for (int q = 0; q < RB; ++q) out[q] = __builtin_fma(cf.a2, pv[q], out[q]);
+            for (int q = 0; q < RB; ++q) out[q] = sweep_prev(cf.a2, pv[q], out[q]);
         }
-        store_rb<RB>(y + o, out);
+        store_ct<RB>(y + o, out);
     }
 }
 
