@@ -13,8 +13,9 @@ namespace hdg {
 
 // ------------------------------------------------------------------ setup: per-cell condensation
 //
-// One wavefront per cell.  The local HDG blocks (Eq. ABCMform) are assembled
-// from reference-element tables and the cell's affine map:
+// Two cells per wavefront: each 32-lane half takes a cell, a lane per row of
+// the local system, the row held in registers.  The local HDG blocks (Eq.
+// ABCMform) are assembled from reference-element tables and the cell's affine map:
 //   A = [[M + k t sum_f E_f,  k G_1,  k G_2],
 //        [-k G_1^T,           M,     -dt Mf],
 //        [-k G_2^T,           dt Mf,  M   ]]
@@ -24,8 +25,8 @@ namespace hdg {
 // facet mass / facet-trace / trace mass on local facet f.  (This is the HDG
 // form of Eq. bilinear_HDG_upwind after integrating the volume flux term by
 // parts.)  [A | B | Mtilde] is reduced by Gauss-Jordan with partial pivoting
-// in LDS, giving W = A^-1 B and A^-1 Mtilde, then S_K = Mt + C W (Step 2
-// operator) and C A^-1 Mtilde (Step 1 map) are formed.
+// across the lanes of the half, giving W = A^-1 B and A^-1 Mtilde, then
+// S_K = Mt + C W (Step 2 operator) and C A^-1 Mtilde (Step 1 map) are formed.
 //
 // NU = 2: the Lax-Friedrichs form (Eq. bilinear_HDG_lax) with the vector
 // trace uhat, local trace unknown (f, d, k) at f*2m + d*m + k:
@@ -36,6 +37,25 @@ namespace hdg {
 //   B = [k n_fd T_f ; -k t T_f on component d],  C = [n_fd T_f^T, t T_f^T on
 //   component d],  Mt = t F_f per facet and component.
 
+constexpr int CONDENSE_XB = 14;   // solution columns staged per round of the products
+
+// DPP lane moves (all lanes have a source): xor 1 and xor 2 within a quad,
+// lane i <-> 7 - i within 8, lane i <-> 15 - i within 16
+constexpr int DPP_XOR1 = 0xB1, DPP_XOR2 = 0x4E, DPP_HALF_MIRROR = 0x141, DPP_MIRROR = 0x140;
+template <int CTRL>
+__device__ __forceinline__ int dpp_i32(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const long long b = __double_as_longlong(v);
+    const unsigned lo = (unsigned)dpp_i32<CTRL>((int)b), hi = (unsigned)dpp_i32<CTRL>((int)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// one of three per-facet values without indexing a register array at run time
+__device__ __forceinline__ double facet_sel(const double (&v)[3], int f) { return f == 0 ? v[0] : (f == 1 ? v[1] : v[2]); }
+
 template <int P, int NU>
 __global__ __launch_bounds__(64) void k_cell_condense(int nk, const double *__restrict__ corners,
                                                       const double *__restrict__ ref, CellParams cp,
@@ -44,25 +64,33 @@ __global__ __launch_bounds__(64) void k_cell_condense(int nk, const double *__re
                                                       int *__restrict__ err, double *__restrict__ Aout,
                                                       double *__restrict__ Bnout) {
     constexpr int n = (P + 1) * (P + 2) / 2, m = P + 1, nc = 3 * n, M = NU * m, nt = 3 * M, nq = (P + 3) * (P + 3);
-    constexpr int LD = nc + nt + nc;
-    __shared__ double aug[nc * LD];
-    __shared__ double Cm[nt * nc];
-    __shared__ double fac[nc];
-    __shared__ double fq[nq];
-    // each XCD takes a contiguous range of cells, so the outputs (component-major,
+    constexpr int LD = nc + nt + nc, NX = nt + nc, XB = CONDENSE_XB, NR = (NX + XB - 1) / XB, ZW = cell_zw(P);
+    static_assert(nc <= 32, "a 32-lane half holds the rows of a cell");
+    // pool: the reference tables and basis values while the rows are assembled,
+    // then the pivot rows [2][LD] and a round of solution columns [2][nc][XB]
+    constexpr int TAB = 6 * n * n + 3 * n * m, POOL_A = TAB + nq * n, POOL_B = 2 * LD + 2 * nc * XB;
+    __shared__ double pool[POOL_A > POOL_B ? POOL_A : POOL_B];
+    __shared__ double fq[2][nq];
+    __shared__ double Mf[2][n * n];   // (f phi_j, phi_i)_K
+    __shared__ double Cm[2][nt * nc];
+    double *const tM = pool, *const tG = tM + n * n, *const tE = tG + 2 * n * n, *const tT = tE + 3 * n * n;
+    double *const sphi = pool + TAB;   // reference basis values at the quadrature points
+    const int lane = threadIdx.x, h = lane >> 5, r = lane & 31;
+    double *const prow = pool + h * LD;   // this half's pivot row (set by the lane that takes it)
+    auto xs = [&](int row, int u) -> double & { return pool[2 * LD + (h * nc + row) * XB + u]; };
+    // each XCD takes a contiguous range of cell pairs, so the outputs (component-major,
     // cells fastest) of neighbouring cells meet in one L2 before they are written back
-    const int K = xcd_block();
-    const int lane = threadIdx.x;
-    if (K >= nk) return;
+    const int pair = xcd_block();
+    if (2 * pair >= nk) return;   // the whole wavefront
+    const bool live = 2 * pair + h < nk;
+    const int K = live ? 2 * pair + h : nk - 1;   // a spare half repeats the last cell and writes nothing
 
     const double *rM = ref;
-    const double *rG = rM + n * n;
-    const double *rE = rG + 2 * n * n;
-    const double *rT = rE + 3 * n * n;
-    const double *rF = rT + 3 * n * m;
+    const double *rF = rM + 6 * n * n + 3 * n * m;
     const double *rq = rF + m * m;
     const double *rw = rq + 2 * nq;
     const double *rPhi = rw + nq;
+    for (int t = lane; t < TAB + nq * n; t += 64) pool[t] = t < TAB ? rM[t] : rPhi[t - TAB];   // M, G, E, T; basis
 
     // ---- geometry of the flat cell
     const double *X = corners + 9 * (size_t)K;
@@ -90,15 +118,13 @@ __global__ __launch_bounds__(64) void k_cell_condense(int nk, const double *__re
     const double Pcx = ac[0] * e1[0] + ac[1] * e1[1] + ac[2] * e1[2];
     const double Pcy = ac[0] * e2[0] + ac[1] * e2[1] + ac[2] * e2[2];
     const double det = Pbx * Pcy - Pby * Pcx;
-    if (!(det > 0.0)) {
-        if (lane == 0) atomicOr(err, 1);
-        return;
-    }
+    const bool det_ok = det > 0.0;   // otherwise the cell is reported and nothing of it written
     // Jinv[r][d] = d xi_r / d x_d
     const double J00 = Pcy / det, J01 = -Pcx / det, J10 = -Pby / det, J11 = Pbx / det;
     double L[3], nx[3], ny[3];
     {
         const double Px[3] = {0.0, Pbx, Pcx}, Py[3] = {0.0, Pby, Pcy};
+#pragma unroll
         for (int f = 0; f < 3; ++f) {
             double tx = Px[(f + 2) % 3] - Px[(f + 1) % 3], ty = Py[(f + 2) % 3] - Py[(f + 1) % 3];
             L[f] = sqrt(tx * tx + ty * ty);
@@ -107,7 +133,7 @@ __global__ __launch_bounds__(64) void k_cell_condense(int nk, const double *__re
         }
     }
     const double kap = cp.kappa, tau = cp.tau, dt = cp.dt;
-    for (int q = lane; q < nq; q += 64) {
+    for (int q = r; q < nq; q += 32) {
         double f = cp.f0;
         if (cp.geom == HDG_SPHERE && cp.omega != 0.0) {
             double x0 = X[0] + rq[2 * q] * ab[0] + rq[2 * q + 1] * ac[0];
@@ -115,153 +141,200 @@ __global__ __launch_bounds__(64) void k_cell_condense(int nk, const double *__re
             double x2 = X[2] + rq[2 * q] * ab[2] + rq[2 * q + 1] * ac[2];
             f += 2.0 * cp.omega * x2 / sqrt(x0 * x0 + x1 * x1 + x2 * x2);
         }
-        fq[q] = f * rw[q];
+        fq[h][q] = f * rw[q];
+    }
+    __syncthreads();
+    for (int t = r; t < n * n; t += 32) {
+        const int i = t / n, j = t - (t / n) * n;
+        double mf = 0.0;
+        for (int q = 0; q < nq; ++q) mf += fq[h][q] * sphi[q * n + i] * sphi[q * n + j];
+        Mf[h][t] = mf * det;
+    }
+    for (int idx = r; idx < nt * nc; idx += 32) {
+        const int row = idx / nc, col = idx % nc;
+        const int f = row / M, d = (row % M) / m, k = row % m, fc = col / n, j = col % n;
+        const double t = facet_sel(L, f) * tT[f * n * m + j * m + k];
+        if constexpr (NU == 1)
+            Cm[h][idx] = fc == 0 ? tau * t : (fc == 1 ? facet_sel(nx, f) : facet_sel(ny, f)) * t;
+        else
+            Cm[h][idx] = fc == 0 ? (d == 0 ? facet_sel(nx, f) : facet_sel(ny, f)) * t : (fc == d + 1 ? tau * t : 0.0);
     }
     __syncthreads();
 
-    // ---- assemble [A | B | Mtilde] and C in LDS
-    auto mass_f = [&](int i, int j) {   // (f phi_j, phi_i)_K
-        double mf = 0.0;
-        for (int q = 0; q < nq; ++q) mf += fq[q] * rPhi[q * n + i] * rPhi[q * n + j];
-        return mf * det;
-    };
-    // (d_d phi_j, phi_i)_K / det for d = 0, 1
-    auto grad_ij = [&](int d, int i, int j) {
+    // ---- row r of [A | B | Mtilde] of this half's cell, in registers
+    const bool row_ok = r < nc;
+    const int fr = row_ok ? r / n : 0, i = row_ok ? r % n : 0;
+    // (d_d phi_jj, phi_ii)_K / det for d = 0, 1
+    auto grad_ij = [&](int d, int ii, int jj) {
         const double c0 = d == 0 ? J00 : J01, c1 = d == 0 ? J10 : J11;
-        return c0 * rG[i * n + j] + c1 * rG[n * n + i * n + j];
+        return c0 * tG[ii * n + jj] + c1 * tG[n * n + ii * n + jj];
     };
-    for (int idx = lane; idx < nc * LD; idx += 64) {
-        const int row = idx / LD, col = idx % LD;
-        const int fr = row / n, i = row % n;
+    auto entry = [&](int col) -> double {
         double v = 0.0;
         if (col < nc) {
             const int fc = col / n, j = col % n;
             if constexpr (NU == 1) {
                 if (fr == 0 && fc == 0) {
-                    v = det * rM[i * n + j];
-                    for (int f = 0; f < 3; ++f) v += kap * tau * L[f] * rE[f * n * n + i * n + j];
+                    v = det * tM[i * n + j];
+                    for (int f = 0; f < 3; ++f) v += kap * tau * L[f] * tE[f * n * n + i * n + j];
                 } else if (fr == 0) {
                     v = kap * det * grad_ij(fc - 1, i, j);
                 } else if (fc == 0) {
                     v = -kap * det * grad_ij(fr - 1, j, i);
                 } else if (fr == fc) {
-                    v = det * rM[i * n + j];
+                    v = det * tM[i * n + j];
                 } else {
-                    v = (fr == 1) ? -dt * mass_f(i, j) : dt * mass_f(i, j);
+                    v = (fr == 1) ? -dt * Mf[h][i * n + j] : dt * Mf[h][i * n + j];
                 }
             } else {
                 if (fr == 0 && fc == 0) {
-                    v = det * rM[i * n + j];
+                    v = det * tM[i * n + j];
                 } else if (fr == 0) {
                     v = -kap * det * grad_ij(fc - 1, j, i);
                 } else if (fc == 0) {
                     v = -kap * det * grad_ij(fr - 1, j, i);
                     for (int f = 0; f < 3; ++f)
-                        v += kap * (fr == 1 ? nx[f] : ny[f]) * L[f] * rE[f * n * n + i * n + j];
+                        v += kap * (fr == 1 ? nx[f] : ny[f]) * L[f] * tE[f * n * n + i * n + j];
                 } else if (fr == fc) {
-                    v = det * rM[i * n + j];
-                    for (int f = 0; f < 3; ++f) v += kap * tau * L[f] * rE[f * n * n + i * n + j];
+                    v = det * tM[i * n + j];
+                    for (int f = 0; f < 3; ++f) v += kap * tau * L[f] * tE[f * n * n + i * n + j];
                 } else {
-                    v = (fr == 1) ? -dt * mass_f(i, j) : dt * mass_f(i, j);
+                    v = (fr == 1) ? -dt * Mf[h][i * n + j] : dt * Mf[h][i * n + j];
                 }
             }
         } else if (col < nc + nt) {
             const int c = col - nc, f = c / M, d = (c % M) / m, k = c % m;
-            const double t = L[f] * rT[f * n * m + i * m + k];
+            const double t = L[f] * tT[f * n * m + i * m + k];
             if constexpr (NU == 1)
                 v = fr == 0 ? -kap * tau * t : kap * (fr == 1 ? nx[f] : ny[f]) * t;
             else
                 v = fr == 0 ? kap * (d == 0 ? nx[f] : ny[f]) * t : (fr == d + 1 ? -kap * tau * t : 0.0);
         } else {
             const int c = col - nc - nt, fc = c / n, j = c % n;
-            if (fc == fr) v = (fr == 0 ? cp.hscale : 1.0) * det * rM[i * n + j];
+            if (fc == fr) v = (fr == 0 ? cp.hscale : 1.0) * det * tM[i * n + j];
         }
-        aug[idx] = v;
-    }
-    for (int idx = lane; idx < nt * nc; idx += 64) {
-        const int row = idx / nc, col = idx % nc;
-        const int f = row / M, d = (row % M) / m, k = row % m, fc = col / n, j = col % n;
-        const double t = L[f] * rT[f * n * m + j * m + k];
-        if constexpr (NU == 1)
-            Cm[idx] = fc == 0 ? tau * t : (fc == 1 ? nx[f] : ny[f]) * t;
-        else
-            Cm[idx] = fc == 0 ? (d == 0 ? nx[f] : ny[f]) * t : (fc == d + 1 ? tau * t : 0.0);
-    }
-    __syncthreads();
+        return v;
+    };
+    double a[LD];
+#pragma unroll
+    for (int c = 0; c < LD; ++c) a[c] = row_ok ? entry(c) : 0.0;
+    __syncthreads();   // the tables are done with: the pool now holds pivot rows
+
+    const size_t NK = (size_t)nk;
     if (Aout) {   // store A and -B only (the standard DG operator is A q + B lam(q))
-        const size_t NKs = (size_t)nk;
-        for (int idx = lane; idx < nc * nc; idx += 64) Aout[(size_t)idx * NKs + K] = aug[(idx / nc) * LD + idx % nc];
-        for (int idx = lane; idx < nc * nt; idx += 64)
-            Bnout[(size_t)idx * NKs + K] = -aug[(idx / nt) * LD + nc + idx % nt];
+        if (live && det_ok && row_ok) {
+#pragma unroll
+            for (int c = 0; c < nc; ++c) Aout[(size_t)(r * nc + c) * NK + K] = a[c];
+#pragma unroll
+            for (int c = 0; c < nt; ++c) Bnout[(size_t)(r * nt + c) * NK + K] = -a[nc + c];
+        }
+        if (live && !det_ok && r == 0) atomicOr(err, 1);
         return;
     }
 
-    // ---- Gauss-Jordan with partial pivoting
-    for (int k = 0; k < nc; ++k) {
-        double best = (lane >= k && lane < nc) ? fabs(aug[lane * LD + k]) : -1.0;
-        int bi = lane;
-        for (int off = 32; off > 0; off >>= 1) {
-            double ob = __shfl_xor(best, off, 64);
-            int oi = __shfl_xor(bi, off, 64);
-            if (ob > best || (ob == best && oi < bi)) {
-                best = ob;
-                bi = oi;
-            }
-        }
-        if (!(best > 0.0)) {
-            if (lane == 0) atomicOr(err, 2);
-            return;
-        }
-        if (bi != k) {
-            for (int c = lane; c < LD; c += 64) {
-                double t = aug[k * LD + c];
-                aug[k * LD + c] = aug[bi * LD + c];
-                aug[bi * LD + c] = t;
-            }
-        }
-        __syncthreads();
-        const double ip = 1.0 / aug[k * LD + k];
-        __syncthreads();
-        for (int c = lane; c < LD; c += 64) aug[k * LD + c] *= ip;
-        for (int r = lane; r < nc; r += 64) fac[r] = aug[r * LD + k];
-        __syncthreads();
-        // a lane per column (the pivot row's entry in a register), all rows down it:
-        // no index division, consecutive lanes on consecutive LDS words
-        for (int c = k + lane; c < LD; c += 64) {
-            const double pk = aug[k * LD + c];
+    // ---- Gauss-Jordan with partial pivoting.  Rows stay in their lanes: the
+    // pivot of column k is the unused row of largest magnitude (lowest row on
+    // ties), found by a reduction over the half (DPP moves within 16 lanes,
+    // then one exchange between the 16-lane rows); its lane posts its row and
+    // the pivot's reciprocal ip, and every other row is eliminated with the
+    // scaled row, the factor ip folded into its multiplier.  The pivot's lane
+    // keeps its row unscaled with the factor beside it (myip): later
+    // eliminations of that row are the same either way.  The lane that took
+    // pivot k then holds row k of A^-1 [A | B | Mtilde] divided by myip.
+    // Columns <= k are not read again once pivot k is taken.
+    bool used = !row_ok, bad = false;
+    int myk = -1;
+    double myip = 1.0;
 #pragma unroll
-            for (int r = 0; r < nc; ++r)
-                if (r != k) aug[r * LD + c] -= fac[r] * pk;
+    for (int k = 0; k < nc; ++k) {
+        const double ip = 1.0 / a[k];   // every lane: the pivot's lane is not known yet
+        double best = used ? -1.0 : fabs(a[k]);
+        int bl = r;
+        // (value, row) pairs ordered by value, then by lower row: the
+        // combination is associative and commutative, so any pairing works
+        auto take = [&](double ob, int ol) {
+            if (ob > best || (ob == best && ol < bl)) {
+                best = ob;
+                bl = ol;
+            }
+        };
+        take(dpp_f64<DPP_XOR1>(best), dpp_i32<DPP_XOR1>(bl));
+        take(dpp_f64<DPP_XOR2>(best), dpp_i32<DPP_XOR2>(bl));
+        take(dpp_f64<DPP_HALF_MIRROR>(best), dpp_i32<DPP_HALF_MIRROR>(bl));
+        take(dpp_f64<DPP_MIRROR>(best), dpp_i32<DPP_MIRROR>(bl));
+        take(__shfl_xor(best, 16, 64), __shfl_xor(bl, 16, 64));
+        bad |= !(best > 0.0);
+        if (r == bl) {
+#pragma unroll
+            for (int c = k + 1; c < LD; ++c) prow[c] = a[c];
+            prow[k] = ip;
+            used = true;
+            myk = k;
+            myip = ip;
+        }
+        __syncthreads();
+        if (r != bl) {   // (a branch, not a zero multiplier: it keeps the register count down)
+            const double g = a[k] * prow[k];
+#pragma unroll
+            for (int c = k + 1; c < LD; ++c) a[c] -= g * prow[c];
         }
         __syncthreads();
     }
+    const bool hbad = ((__ballot(bad) >> (32 * h)) & 0xffffffffull) != 0;
+    if (live && r == 0) {
+        if (!det_ok) atomicOr(err, 1);
+        else if (hbad) atomicOr(err, 2);
+    }
+    const bool ok = live && det_ok && !hbad;
 
-    // ---- products and outputs
-    const size_t NK = (size_t)nk;
-    for (int idx = lane; idx < nt * nt; idx += 64) {
-        const int a = idx / nt, b = idx % nt;
-        double s = 0.0;
-        if (a / m == b / m) s = tau * L[a / M] * rF[(a % m) * m + (b % m)];   // same facet and component
-        for (int j = 0; j < nc; ++j) s += Cm[a * nc + j] * aug[j * LD + nc + b];
-        Sloc[(size_t)idx * NK + K] = s;
-    }
-    // Zr = C A^-1 Mtilde, rows padded to ZW (zeros), stored as 16-byte pairs
-    constexpr int ZW = cell_zw(P);
-    for (int idx = lane; idx < nt * ZW; idx += 64) {
-        const int a = idx / ZW, b = idx % ZW;
-        double s = 0.0;
-        if (b < nc)
-            for (int j = 0; j < nc; ++j) s += Cm[a * nc + j] * aug[j * LD + nc + nt + b];
-        Zr[((size_t)(idx / 2) * NK + K) * 2 + idx % 2] = s;
-    }
+    // ---- outputs: A^-1 Mtilde and W = A^-1 B (scaled back to the unscaled
+    // depth unknown) from the registers, then S_K = Mt + C W and C A^-1 Mtilde
+    // from the solution staged through LDS a round of columns at a time
     const double ih = 1.0 / cp.hscale;
-    for (int idx = lane; idx < nc * nc; idx += 64) {
-        const int a = idx / nc, b = idx % nc;
-        Ar[(size_t)idx * NK + K] = (a < n ? ih : 1.0) * aug[a * LD + nc + nt + b];
+    if (ok && myk >= 0) {
+        const double sc = myk < n ? ih : 1.0;
+#pragma unroll
+        for (int b = 0; b < nc; ++b) Ar[(size_t)(myk * nc + b) * NK + K] = sc * (myip * a[nc + nt + b]);
+#pragma unroll
+        for (int b = 0; b < nt; ++b) Wr[(size_t)(myk * nt + b) * NK + K] = sc * (myip * a[nc + b]);
     }
-    for (int idx = lane; idx < nc * nt; idx += 64) {
-        const int a = idx / nt, b = idx % nt;
-        Wr[(size_t)idx * NK + K] = (a < n ? ih : 1.0) * aug[a * LD + nc + b];
+#pragma unroll
+    for (int rho = 0; rho < NR; ++rho) {
+        const int lo = rho * XB, hi = lo + XB < NX ? lo + XB : NX;
+        __syncthreads();
+        if (myk >= 0) {
+#pragma unroll
+            for (int u = 0; u < XB; ++u)
+                if (lo + u < hi) xs(myk, u) = myip * a[nc + lo + u];
+        }
+        __syncthreads();
+        if (!ok) continue;
+        if (lo < nt) {   // S_K columns [lo, min(hi, nt))
+            const int b1 = hi < nt ? hi : nt, w = b1 - lo;
+            for (int t = r; t < nt * w; t += 32) {
+                const int aa = t / w, b = lo + t % w;
+                double s = 0.0;
+                if (aa / m == b / m) s = tau * facet_sel(L, aa / M) * rF[(aa % m) * m + (b % m)];   // same facet and component
+                for (int j = 0; j < nc; ++j) s += Cm[h][aa * nc + j] * xs(j, b - lo);
+                Sloc[(size_t)(aa * nt + b) * NK + K] = s;
+            }
+        }
+        if (hi > nt) {   // C A^-1 Mtilde columns [max(lo, nt), hi) - nt, rows padded to ZW, 16-byte pairs
+            const int x0 = lo > nt ? lo : nt, w = hi - x0;
+            for (int t = r; t < nt * w; t += 32) {
+                const int aa = t / w, b = x0 - nt + t % w;
+                double s = 0.0;
+                for (int j = 0; j < nc; ++j) s += Cm[h][aa * nc + j] * xs(j, nt + b - lo);
+                const int idx = aa * ZW + b;
+                Zr[((size_t)(idx / 2) * NK + K) * 2 + idx % 2] = s;
+            }
+        }
+    }
+    if constexpr (ZW > nc) {
+        for (int t = r; ok && t < nt * (ZW - nc); t += 32) {
+            const int idx = (t / (ZW - nc)) * ZW + nc + t % (ZW - nc);
+            Zr[((size_t)(idx / 2) * NK + K) * 2 + idx % 2] = 0.0;
+        }
     }
 }
 
@@ -1981,7 +2054,8 @@ bool rhs_blocked(int nb, int rhs_block) {
 void launch_cell_condense(int p, int nu, int nk, const double *corners, const double *ref, CellParams cp,
                           double *Sloc, double *Zr, double *Ar, double *Wr, int *err, hipStream_t s, double *Aout,
                           double *Bnout) {
-#define CK(P, NU) hipLaunchKernelGGL((k_cell_condense<P, NU>), dim3((unsigned)((nk + N_XCD - 1) / N_XCD * N_XCD)), dim3(64), 0, s, nk, corners, ref, cp, Sloc, Zr, Ar, Wr, err, Aout, Bnout)
+    const int pairs = (nk + 1) / 2;   // two cells per wavefront
+#define CK(P, NU) hipLaunchKernelGGL((k_cell_condense<P, NU>), dim3((unsigned)((pairs + N_XCD - 1) / N_XCD * N_XCD)), dim3(64), 0, s, nk, corners, ref, cp, Sloc, Zr, Ar, Wr, err, Aout, Bnout)
     if (nu == 1) { switch (p) { case 1: CK(1, 1); break; case 2: CK(2, 1); break; case 3: CK(3, 1); break; } }
     else { switch (p) { case 1: CK(1, 2); break; case 2: CK(2, 2); break; case 3: CK(3, 2); break; } }
 #undef CK
