@@ -1030,10 +1030,20 @@ __global__ __launch_bounds__(RECOVER_TILE) void k_recover_n1(int nk, const doubl
 // chunks of CELL_ROWS rows, loaded once per block with coalesced reads; every
 // thread keeps its right-hand side's inputs in registers.  Same arithmetic
 // order as the one-thread-per-(cell, rhs) kernels.
-constexpr int CELL_ROWS = 6;
+// Condensation: when a chunk is at most CELL_PF entries per thread (6 rl <= 8 nb:
+// 32 right-hand sides at p = 3), the next chunk is loaded into registers while
+// the current one is used, through two LDS buffers and one barrier per chunk
+// (recovery keeps one buffer: with the prefetch registers it would drop from
+// four waves per SIMD to three, and measured slower).
+constexpr int CELL_ROWS = 6, CELL_PF = 8;
 // cells per block for row length rl: at most 256 threads and 64 KiB of staged rows
 inline int cell_block_cells(int nb, int rl) {
     return std::max(1, std::min(std::min(32, 256 / nb), 65536 / (int)(sizeof(double) * CELL_ROWS * rl)));
+}
+__host__ __device__ constexpr bool cell_prefetch(int nb, int rl) { return CELL_ROWS * rl <= CELL_PF * nb; }
+// dynamic LDS of a batched cell kernel: one or two staging buffers
+inline size_t cell_stage_bytes(int nb, int rl) {
+    return sizeof(double) * CELL_ROWS * rl * cell_block_cells(nb, rl) * (cell_prefetch(nb, rl) ? 2 : 1);
 }
 
 template <int P, int NU>
@@ -1089,7 +1099,7 @@ template <int P, int NU>
 __global__ __launch_bounds__(256) void k_condense_cell_b(int nk, int nb, int cb, const double *__restrict__ Zr,
                                                          const double *__restrict__ rc, double *__restrict__ loc) {
     constexpr int n = (P + 1) * (P + 2) / 2, m = P + 1, nc = 3 * n, nt = 3 * NU * m, ZW = cell_zw(P);
-    extern __shared__ double sm[];   // [row][entry][cell], CELL_ROWS * ZW * cb doubles
+    extern __shared__ double sm[];   // [row][entry][cell], CELL_ROWS * ZW * cb doubles (twice with prefetch)
     const int K0 = xcd_block() * cb, tid = threadIdx.x;
     const int cl = tid / nb, r = tid - cl * nb, K = K0 + cl;
     const bool live = cl < cb && K < nk;
@@ -1097,26 +1107,55 @@ __global__ __launch_bounds__(256) void k_condense_cell_b(int nk, int nb, int cb,
     double f[ZW];
 #pragma unroll
     for (int j = 0; j < ZW; ++j) f[j] = (live && j < nc) ? rc[((size_t)K * nc + j) * nb + r] : 0.0;
+    // staged entry i of the chunk at row a0 (its LDS slot is i: [row][entry][cell])
+    auto entry = [&](int a0, int i) {
+        const int c = i % cb, jr = i / cb, row = jr / ZW, j = jr - row * ZW, Kc = K0 + c;
+        const int idx = (a0 + row) * ZW + j;   // pair layout [idx / 2][NK][2]
+        return Kc < nk ? Zr[((size_t)(idx / 2) * NK + Kc) * 2 + idx % 2] : 0.0;
+    };
+    auto use = [&](const double *buf, int a0, int rows) {
+        for (int row = 0; row < rows; ++row) {
+            double s = 0.0;
+#pragma unroll
+            for (int jp = 0; jp < ZW / 2; ++jp) {
+                s += buf[(row * ZW + 2 * jp) * cb + cl] * f[2 * jp];
+                if (2 * jp + 1 < nc) s += buf[(row * ZW + 2 * jp + 1) * cb + cl] * f[2 * jp + 1];
+            }
+            loc[((size_t)(a0 + row) * NK + K) * nb + r] = s;
+        }
+    };
+    if (cell_prefetch(nb, ZW)) {
+        const int per = CELL_ROWS * ZW * cb, nthr = blockDim.x;
+        double v[CELL_PF];
+        auto fetch = [&](int a0) {
+            const int cnt = min(CELL_ROWS, nt - a0) * ZW * cb;
+#pragma unroll
+            for (int u = 0; u < CELL_PF; ++u) v[u] = tid + u * nthr < cnt ? entry(a0, tid + u * nthr) : 0.0;
+        };
+        auto put = [&](int a0, double *buf) {
+            const int cnt = min(CELL_ROWS, nt - a0) * ZW * cb;
+#pragma unroll
+            for (int u = 0; u < CELL_PF; ++u)
+                if (tid + u * nthr < cnt) buf[tid + u * nthr] = v[u];
+        };
+        fetch(0);
+        put(0, sm);
+        __syncthreads();
+        for (int a0 = 0, ch = 0; a0 < nt; a0 += CELL_ROWS, ++ch) {
+            const bool more = a0 + CELL_ROWS < nt;
+            if (more) fetch(a0 + CELL_ROWS);
+            if (live) use(sm + (ch & 1) * per, a0, min(CELL_ROWS, nt - a0));
+            if (more) put(a0 + CELL_ROWS, sm + ((ch + 1) & 1) * per);
+            __syncthreads();
+        }
+        return;
+    }
     for (int a0 = 0; a0 < nt; a0 += CELL_ROWS) {
         const int rows = min(CELL_ROWS, nt - a0);
         __syncthreads();
-        for (int i = tid; i < rows * ZW * cb; i += blockDim.x) {
-            const int c = i % cb, jr = i / cb, row = jr / ZW, j = jr - row * ZW, Kc = K0 + c;
-            const int idx = (a0 + row) * ZW + j;   // pair layout [idx / 2][NK][2]
-            sm[(row * ZW + j) * cb + c] = Kc < nk ? Zr[((size_t)(idx / 2) * NK + Kc) * 2 + idx % 2] : 0.0;
-        }
+        for (int i = tid; i < rows * ZW * cb; i += blockDim.x) sm[i] = entry(a0, i);
         __syncthreads();
-        if (live) {
-            for (int row = 0; row < rows; ++row) {
-                double s = 0.0;
-#pragma unroll
-                for (int jp = 0; jp < ZW / 2; ++jp) {
-                    s += sm[(row * ZW + 2 * jp) * cb + cl] * f[2 * jp];
-                    if (2 * jp + 1 < nc) s += sm[(row * ZW + 2 * jp + 1) * cb + cl] * f[2 * jp + 1];
-                }
-                loc[((size_t)(a0 + row) * NK + K) * nb + r] = s;
-            }
-        }
+        if (live) use(sm, a0, rows);
     }
 }
 
@@ -2285,7 +2324,7 @@ void launch_condense(int p, int nu, int nk, int ne, int nb, const double *Zr, co
         hipLaunchKernelGGL((k_condense_cell_n1<P, NU>), GRID8(nk, RECOVER_TILE), 0, s, nk, Zr, rc, loc);          \
     else                                                                                                          \
         hipLaunchKernelGGL((k_condense_cell_b<P, NU>), GRID8((int64_t)nk * nb, cell_block_cells(nb, cell_zw(P)) * nb), \
-                           sizeof(double) * CELL_ROWS * cell_zw(P) * cell_block_cells(nb, cell_zw(P)), s, nk, nb,  \
+                           cell_stage_bytes(nb, cell_zw(P)), s, nk, nb,                                            \
                            cell_block_cells(nb, cell_zw(P)), Zr, rc, loc);                                        \
     hipLaunchKernelGGL((k_condense_gather<P, NU>), GRID8(ne * NU * (P + 1) * nb, 256), 0, s, ne, nk, nb,          \
                        facet_cell, facet_loc, loc, rhat)
