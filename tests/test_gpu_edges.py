@@ -1,6 +1,7 @@
 """Edge cases of the C ABI on the GPU: argument errors caught on the host
 before any launch, zero right-hand sides (alone and inside a batch), the
-largest batch (64 right-hand sides) and the smallest mesh."""
+largest batch (64 right-hand sides), the smallest mesh, and a clockwise cell
+reported by the setup's per-cell condensation."""
 import numpy as np
 import pytest
 
@@ -186,3 +187,24 @@ def test_ir_inner_rtol_is_validated():
     with pytest.raises(HdgError) as e:
         make(ir_inner_rtol=1.5)
     assert "ir_inner_rtol" in str(e.value)
+
+
+@pytest.mark.parametrize("p", [1, 3])
+def test_inverted_cell_is_reported(p):
+    """A clockwise cell (one vertex of the 4 x 4 torus moved across the
+    opposite edge of a neighbouring cell): the per-cell condensation flags the
+    non-positive area and setup fails with that message; a valid mesh set up
+    afterwards still solves."""
+    from paper_2004_09389_amd.hdg import HdgError, HdgSolver
+    hier = hi.torus_hierarchy(4, 4)
+    m = hier.fine
+    m.vert_xyz = m.vert_xyz.copy()
+    # vertex (1, 1) to x = -h/2: the cell (0, 0), (1, 1), (0, 1) of the first square turns clockwise
+    m.vert_xyz[1 * 4 + 1, 0] = -0.5 * m.period / 4
+    with pytest.raises(HdgError, match="non-positive area"):
+        HdgSolver(hier, p, 0.4, 1.0, 1.0, 0.5, 0.0)
+    s = make(4, p)
+    r = np.random.default_rng(3).standard_normal((s.n_cell, 3, s.n_loc, 1))
+    q, lam, info = s.step(to_dev(r))
+    assert info[0].status == 0
+    s.close()
