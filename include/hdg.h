@@ -445,6 +445,10 @@ typedef struct {
     int32_t rhs_block;          /* facet-row kernels (apply, residual, sweep) at nrhs = 4, 8, ..., 64:
                                    1 = one thread per (facet, rhs); 4 = four right-hand sides per
                                    thread with the block's rows staged in LDS (default 4) */
+    int32_t cell_cells;         /* cells per block of the batched condensation and recovery
+                                   kernels (nrhs >= 2; a block is cells x nrhs threads): 0 = the
+                                   most that fit in 256 threads and 64 KiB of staged rows (default),
+                                   1..32 = at most that many (larger values are clamped) */
 } hdg_tuning;
 int hdg_get_tuning(const hdg_ctx *ctx, hdg_tuning *out);
 int hdg_set_tuning(hdg_ctx *ctx, const hdg_tuning *tuning);

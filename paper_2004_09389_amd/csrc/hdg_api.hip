@@ -1565,7 +1565,7 @@ extern "C" int hdg_condense(hdg_ctx *c, int32_t nb, const double *r_cell, double
         Timed t(c, HDG_KERNEL_CONDENSE, HDG_FP64, s, nb);
         for (int rep = 0; rep < t.repeats(); ++rep)
             hdg::launch_condense(c->p, c->nu, c->n_cell, c->n_facet, nb, c->Zr, r_cell, c->loc, c->d_fcell, c->d_floc, rhat,
-                                 s);
+                                 s, c->cell_cells);
         check_launch();
     });
 }
@@ -1582,7 +1582,7 @@ extern "C" int hdg_condense_noalloc(hdg_ctx *c, int32_t nb, const double *r_cell
                                         std::to_string(NOALLOC_SCRATCH_DOUBLES) + ": use hdg_condense"};
         HDG_REQUIRE(c->noalloc_scratch, "static scratch not resolved for this device");
         hdg::launch_condense(c->p, c->nu, c->n_cell, c->n_facet, nb, c->Zr, r_cell, c->noalloc_scratch, c->d_fcell,
-                             c->d_floc, rhat, as_stream(stream));
+                             c->d_floc, rhat, as_stream(stream), c->cell_cells);
         check_launch();
     });
 }
@@ -1664,12 +1664,12 @@ extern "C" int hdg_stage_solve(hdg_ctx *c, int32_t nb, const double *r_cell, dou
             return;
         }
         hdg::launch_condense(c->p, c->nu, c->n_cell, c->n_facet, nb, c->Zr, r_cell, c->loc, c->d_fcell, c->d_floc,
-                             c->stage_rhat, s);
+                             c->stage_rhat, s, c->cell_cells);
         check_launch();
         HDG_HIP_CHECK(hipMemsetAsync(lam, 0, sizeof(double) * (size_t)vec_len(c) * nb, s));
         status = solve_impl(c, nb, c->stage_rhat, lam, info, s);
         hdg::launch_recover(c->p, c->nu, c->n_cell, nb, c->Ar, c->Wr, c->cell_facet, c->cell_rev, r_cell, lam, q_cell,
-                            s);
+                            s, c->cell_cells);
         check_launch();
         HDG_HIP_CHECK(hipStreamSynchronize(s));
     });
@@ -1689,7 +1689,7 @@ extern "C" int hdg_recover(hdg_ctx *c, int32_t nb, const double *r_cell, const d
         Timed t(c, HDG_KERNEL_RECOVER, HDG_FP64, s, nb);
         for (int rep = 0; rep < t.repeats(); ++rep)
             hdg::launch_recover(c->p, c->nu, c->n_cell, nb, c->Ar, c->Wr, c->cell_facet, c->cell_rev, r_cell, lam, q_cell,
-                                s);
+                                s, c->cell_cells);
         check_launch();
     });
 }
@@ -1893,6 +1893,7 @@ void check_tuning(const hdg_tuning &t) {
     const int v = t.mlp_samples_per_lane;
     HDG_REQUIRE(v == 1 || v == 2 || v == 4, "mlp_samples_per_lane must be 1, 2 or 4");
     HDG_REQUIRE(t.rhs_block == 1 || t.rhs_block == 4, "rhs_block must be 1 or 4");
+    HDG_REQUIRE(t.cell_cells >= 0 && t.cell_cells <= 32, "cell_cells must be in 0..32");
 }
 
 // mean duration (ms) of `reps` launches of fn, after one untimed launch
@@ -1920,6 +1921,7 @@ extern "C" int hdg_get_tuning(const hdg_ctx *c, hdg_tuning *out) {
     if (!c || !out) return HDG_EINVAL;
     out->mlp_samples_per_lane = c->mlp_spl;
     out->rhs_block = c->rhs_block;
+    out->cell_cells = c->cell_cells;
     return HDG_OK;
 }
 
@@ -1932,6 +1934,7 @@ extern "C" int hdg_set_tuning(hdg_ctx *c, const hdg_tuning *t) {
         drop_graphs(c);
         c->mlp_spl = t->mlp_samples_per_lane;
         c->rhs_block = t->rhs_block;
+        c->cell_cells = t->cell_cells;
     });
 }
 
@@ -1977,9 +1980,39 @@ extern "C" int hdg_autotune(hdg_ctx *c, int32_t nb, hdg_tuning *chosen, void *st
             }
         }
         c->rhs_block = best_rb;
+        // batched cell kernels (condensation, recovery): the most cells per block
+        // that fit, half or a quarter of them
+        int best_cc = 0;
+        if (nb >= 2) {
+            const size_t cell_bytes = sizeof(double) * (size_t)c->n_cell * c->nc * nb;
+            double *rc = nullptr, *qc = nullptr;
+            HDG_HIP_CHECK(hipMalloc(&rc, cell_bytes));
+            HDG_HIP_CHECK(hipMalloc(&qc, cell_bytes));
+            HDG_HIP_CHECK(hipMemsetAsync(rc, 0, cell_bytes, s));
+            best = 1e300;
+            for (int div : {1, 2, 4}) {
+                const int mx = std::max(1, std::min(32, 256 / nb));   // upper bound; the launcher clamps further
+                const int cc = div == 1 ? 0 : std::max(1, mx / div);
+                const double ms = time_launches(s, 5, [&] {
+                    hdg::launch_condense(c->p, c->nu, c->n_cell, c->n_facet, nb, c->Zr, rc, c->loc, c->d_fcell,
+                                         c->d_floc, c->vres, s, cc);
+                    hdg::launch_recover(c->p, c->nu, c->n_cell, nb, c->Ar, c->Wr, c->cell_facet, c->cell_rev, rc,
+                                        c->vx, qc, s, cc);
+                });
+                if (ms < best) {
+                    best = ms;
+                    best_cc = cc;
+                }
+            }
+            HDG_HIP_CHECK(hipStreamSynchronize(s));
+            HDG_HIP_CHECK(hipFree(rc));
+            HDG_HIP_CHECK(hipFree(qc));
+        }
+        c->cell_cells = best_cc;
         if (chosen) {
             chosen->mlp_samples_per_lane = best_spl;
             chosen->rhs_block = best_rb;
+            chosen->cell_cells = best_cc;
         }
     });
 }

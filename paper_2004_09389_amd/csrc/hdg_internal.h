@@ -205,6 +205,7 @@ struct hdg_ctx {
     int mlp_n1 = 0, mlp_n2 = 0, mlp_step = 0;
     int mlp_spl = 1;                      // samples per lane in the learned smoothing kernel
     int rhs_block = 4;                    // facet-row kernels: RHS per thread when nrhs allows (1 or 4)
+    int cell_cells = 0;                   // batched cell kernels: cells per block (0 = the most that fit)
     float *mlp_w = nullptr, *mlp_m1 = nullptr, *mlp_m2 = nullptr, *mlp_g = nullptr;
     short *mlp_wb = nullptr;
     float *mlp_pdW1 = nullptr, *mlp_pdW2 = nullptr, *mlp_ploss = nullptr;

@@ -194,10 +194,13 @@ void launch_p1_resid_restrict(int n, int W, const int *col, const double *val, c
 void launch_dense_mv(int n, int nb, const double *Ainv, const double *b, double *x, hipStream_t s, bool f32 = false);
 void launch_p1_tail(const P1Tail &T, int nb, hipStream_t s, bool f32 = false);
 
+// cells: cells per block of the batched (nb >= 2) cell kernels; 0 = the most
+// that fit (256 threads, 64 KiB of staged rows), larger requests are clamped
 void launch_condense(int p, int nu, int nk, int ne, int nb, const double *Zr, const double *rc, double *loc,
-                     const int *facet_cell, const int *facet_loc, double *rhat, hipStream_t s);
+                     const int *facet_cell, const int *facet_loc, double *rhat, hipStream_t s, int cells = 0);
 void launch_recover(int p, int nu, int nk, int nb, const double *Ar, const double *Wr, const int *cell_facet,
-                    const int8_t *cell_rev, const double *rc, const double *lam, double *q, hipStream_t s);
+                    const int8_t *cell_rev, const double *rc, const double *lam, double *q, hipStream_t s,
+                    int cells = 0);
 
 int red_grid(int64_t len, int nb);
 template <typename VT>

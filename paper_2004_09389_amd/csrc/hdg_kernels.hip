@@ -1040,10 +1040,15 @@ constexpr int CELL_ROWS = 6, CELL_PF = 8;
 inline int cell_block_cells(int nb, int rl) {
     return std::max(1, std::min(std::min(32, 256 / nb), 65536 / (int)(sizeof(double) * CELL_ROWS * rl)));
 }
+// cells per block actually launched: a request (tuning) of at most the default
+inline int cell_cells(int nb, int rl, int req) {
+    const int mx = cell_block_cells(nb, rl);
+    return req > 0 && req < mx ? req : mx;
+}
 __host__ __device__ constexpr bool cell_prefetch(int nb, int rl) { return CELL_ROWS * rl <= CELL_PF * nb; }
-// dynamic LDS of a batched cell kernel: one or two staging buffers
-inline size_t cell_stage_bytes(int nb, int rl) {
-    return sizeof(double) * CELL_ROWS * rl * cell_block_cells(nb, rl) * (cell_prefetch(nb, rl) ? 2 : 1);
+// dynamic LDS of a batched cell kernel with cb cells per block: one or two staging buffers
+inline size_t cell_stage_bytes(int nb, int rl, int cb) {
+    return sizeof(double) * CELL_ROWS * rl * cb * (cell_prefetch(nb, rl) ? 2 : 1);
 }
 
 template <int P, int NU>
@@ -2318,14 +2323,14 @@ void launch_p1_tail(const P1Tail &T, int nb, hipStream_t s, bool f32) {
 #undef P1_TYPED
 
 void launch_condense(int p, int nu, int nk, int ne, int nb, const double *Zr, const double *rc, double *loc,
-                     const int *facet_cell, const int *facet_loc, double *rhat, hipStream_t s) {
+                     const int *facet_cell, const int *facet_loc, double *rhat, hipStream_t s, int cells) {
 #define CC(P, NU)                                                                                                 \
     if (nb == 1)                                                                                                  \
         hipLaunchKernelGGL((k_condense_cell_n1<P, NU>), GRID8(nk, RECOVER_TILE), 0, s, nk, Zr, rc, loc);          \
     else                                                                                                          \
-        hipLaunchKernelGGL((k_condense_cell_b<P, NU>), GRID8((int64_t)nk * nb, cell_block_cells(nb, cell_zw(P)) * nb), \
-                           cell_stage_bytes(nb, cell_zw(P)), s, nk, nb,                                            \
-                           cell_block_cells(nb, cell_zw(P)), Zr, rc, loc);                                        \
+        hipLaunchKernelGGL((k_condense_cell_b<P, NU>), GRID8((int64_t)nk * nb, cell_cells(nb, cell_zw(P), cells) * nb), \
+                           cell_stage_bytes(nb, cell_zw(P), cell_cells(nb, cell_zw(P), cells)), s, nk, nb,          \
+                           cell_cells(nb, cell_zw(P), cells), Zr, rc, loc);                                       \
     hipLaunchKernelGGL((k_condense_gather<P, NU>), GRID8(ne * NU * (P + 1) * nb, 256), 0, s, ne, nk, nb,          \
                        facet_cell, facet_loc, loc, rhat)
     if (nu == 1) { switch (p) { case 1: CC(1, 1); break; case 2: CC(2, 1); break; case 3: CC(3, 1); break; } }
@@ -2335,15 +2340,16 @@ void launch_condense(int p, int nu, int nk, int ne, int nb, const double *Zr, co
 
 #define RL_REC(P, NU) (3 * (P + 1) * (P + 2) / 2 + 3 * (NU) * (P + 1))   // recovery row: A^-1 Mt and W entries
 void launch_recover(int p, int nu, int nk, int nb, const double *Ar, const double *Wr, const int *cell_facet,
-                    const int8_t *cell_rev, const double *rc, const double *lam, double *q, hipStream_t s) {
+                    const int8_t *cell_rev, const double *rc, const double *lam, double *q, hipStream_t s,
+                    int cells) {
 #define RC(P, NU)                                                                                              \
     if (nb == 1)                                                                                               \
         hipLaunchKernelGGL((k_recover_n1<P, NU>), GRID8(nk, RECOVER_TILE), 0, s, nk, Ar, Wr, cell_facet, cell_rev, \
                            rc, lam, q);                                                                        \
     else                                                                                                       \
-        hipLaunchKernelGGL((k_recover_b<P, NU>), GRID8((int64_t)nk * nb, cell_block_cells(nb, RL_REC(P, NU)) * nb), \
-                           sizeof(double) * CELL_ROWS * RL_REC(P, NU) * cell_block_cells(nb, RL_REC(P, NU)), s, nk, \
-                           nb, cell_block_cells(nb, RL_REC(P, NU)), Ar, Wr, cell_facet, cell_rev, rc, lam, q)
+        hipLaunchKernelGGL((k_recover_b<P, NU>), GRID8((int64_t)nk * nb, cell_cells(nb, RL_REC(P, NU), cells) * nb), \
+                           sizeof(double) * CELL_ROWS * RL_REC(P, NU) * cell_cells(nb, RL_REC(P, NU), cells), s, nk, \
+                           nb, cell_cells(nb, RL_REC(P, NU), cells), Ar, Wr, cell_facet, cell_rev, rc, lam, q)
     if (nu == 1) { switch (p) { case 1: RC(1, 1); break; case 2: RC(2, 1); break; case 3: RC(3, 1); break; } }
     else { switch (p) { case 1: RC(1, 2); break; case 2: RC(2, 2); break; case 3: RC(3, 2); break; } }
 #undef RC

@@ -62,7 +62,8 @@ class HdgSizes(ctypes.Structure):
 
 
 class HdgTuning(ctypes.Structure):
-    _fields_ = [("mlp_samples_per_lane", ctypes.c_int32), ("rhs_block", ctypes.c_int32)]
+    _fields_ = [("mlp_samples_per_lane", ctypes.c_int32), ("rhs_block", ctypes.c_int32),
+                ("cell_cells", ctypes.c_int32)]
 
 
 HDG_IMEX_THETA, HDG_IMEX_ARS232, HDG_IMEX_SSP322, HDG_IMEX_ARS443 = 0, 1, 2, 3
@@ -507,7 +508,7 @@ class HdgSolver:
     def get_tuning(self) -> dict:
         t = HdgTuning()
         _check(self.lib.hdg_get_tuning(self.ctx, ctypes.byref(t)))
-        return {"mlp_samples_per_lane": t.mlp_samples_per_lane, "rhs_block": t.rhs_block}
+        return _tuning_dict(t)
 
     def set_tuning(self, **kw):
         t = HdgTuning()
@@ -516,10 +517,30 @@ class HdgSolver:
             setattr(t, k, int(v))
         _check(self.lib.hdg_set_tuning(self.ctx, ctypes.byref(t)))
 
-    def autotune(self, nrhs: int = 1) -> dict:
+    def autotune(self, nrhs: int = 1, cache: str | None = None) -> dict:
+        """hdg_autotune at nrhs right-hand sides.  With `cache` (a JSON file path)
+        the choice is looked up first, under a key naming the device, the mesh,
+        the degree, the flux, the precision, the smoother and nrhs, and a new
+        choice is stored there."""
+        key = self.tuning_key(nrhs) if cache is not None else None
+        if key is not None:
+            hit = tuning_cache_get(cache, key)
+            if hit is not None:
+                self.set_tuning(**hit)
+                return self.get_tuning()
         t = HdgTuning()
         _check(self.lib.hdg_autotune(self.ctx, int(nrhs), ctypes.byref(t), _stream()))
-        return {"mlp_samples_per_lane": t.mlp_samples_per_lane, "rhs_block": t.rhs_block}
+        chosen = _tuning_dict(t)
+        if key is not None:
+            tuning_cache_put(cache, key, chosen)
+        return chosen
+
+    def tuning_key(self, nrhs: int) -> str:
+        import torch
+        o = self.options
+        return "|".join(str(v) for v in (torch.cuda.get_device_name(self.device), self.hier.fine.kind,
+                                          self.n_cell, self.n_facet, self.p, self.flux, o.precision,
+                                          o.smoother, int(nrhs)))
 
     # ------------------------------------------------------------------ measurement
     def set_timing(self, repeat: int):
@@ -534,6 +555,47 @@ class HdgSolver:
         _check(self.lib.hdg_kernel_stats(self.ctx, KERNELS[kernel], precision, ctypes.byref(n),
                                          ctypes.byref(ms), ctypes.byref(b)))
         return int(n.value), float(ms.value), float(b.value)
+
+
+def _tuning_dict(t: HdgTuning) -> dict:
+    return {f: int(getattr(t, f)) for f, _ in HdgTuning._fields_}
+
+
+def tuning_cache_get(path: str, key: str):
+    """The tuning stored under key in the JSON file at path, or None (no file,
+    no entry, or an entry that does not name every tuning field)."""
+    import json
+    try:
+        with open(path) as f:
+            entry = json.load(f).get("entries", {}).get(key)
+    except (OSError, ValueError):
+        return None
+    fields = [f for f, _ in HdgTuning._fields_]
+    if not isinstance(entry, dict) or any(not isinstance(entry.get(f), int) for f in fields):
+        return None
+    return {f: entry[f] for f in fields}
+
+
+def tuning_cache_put(path: str, key: str, tuning: dict) -> None:
+    """Store tuning under key in the JSON file at path (other entries kept;
+    written to a temporary file and renamed into place)."""
+    import json
+    import os
+    import tempfile
+    data = {"version": 1, "entries": {}}
+    try:
+        with open(path) as f:
+            old = json.load(f)
+        if isinstance(old, dict) and isinstance(old.get("entries"), dict):
+            data["entries"] = old["entries"]
+    except (OSError, ValueError):
+        pass
+    data["entries"][key] = {f: int(tuning[f]) for f, _ in HdgTuning._fields_}
+    d = os.path.dirname(os.path.abspath(path))
+    fd, tmp = tempfile.mkstemp(dir=d, prefix=".hdg_tuning.")
+    with os.fdopen(fd, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
 
 
 def device_copy(src, dst):

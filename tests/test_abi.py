@@ -54,7 +54,7 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(hdg.HdgSolveInfo) == 4 * 4 + 8
     # ... + ir_inner_rtol (8) + persistent (4, padded to 8)
     assert ctypes.sizeof(hdg.HdgOptions) == 4 * 6 + 8 + 4 + 4 + 8 + 8 + 4 * 4 + 8 + 4 + 4 + 4 + 4 + 8 + 8 + 8
-    assert ctypes.sizeof(hdg.HdgTuning) == 8
+    assert ctypes.sizeof(hdg.HdgTuning) == 12
     assert ctypes.sizeof(hdg.HdgSizes) == 8 * 4 + 8 + 2 * 8 + 8
 
 

@@ -295,6 +295,33 @@ def test_batched_cell_kernels_bitwise(name):
             assert rel(q_b[:, fld, :, k], q_ref[:, fld]) < 1e-12
 
 
+@pytest.mark.parametrize("name", ["torus16_p3_f1", "sphere_L2_p2"])
+def test_cells_per_block_tuning_bitwise(name, tmp_path):
+    """The cells per block of the batched condensation and recovery kernels
+    (tuning field cell_cells) changes no bit, at 4 and at 32 right-hand sides
+    (the latter with the prefetched staging of condensation); hdg_autotune
+    picks one of its candidates, and a tuning cache file returns the same
+    choice."""
+    hier, s, _, _ = setup_case(name, max_rhs=32)
+    for nb in (4, 32):
+        r = hi.iid_rhs(hier.fine, s.p, 80 + nb, nrhs=nb)
+        lam = np.random.default_rng(81 + nb).standard_normal((s.n_facet, s.m, nb))
+        ref = None
+        for cc in (0, 1, 3, 8, 32):
+            s.set_tuning(cell_cells=cc)
+            got = (trace_np(s.condense(to_dev(r))), trace_np(s.recover(to_dev(r), to_dev(lam))))
+            if ref is None:
+                ref = got
+            else:
+                assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), (nb, cc)
+        chosen = s.autotune(nb, cache=str(tmp_path / "tuning.json"))
+        assert chosen["cell_cells"] in (0, 1, 2, 4, 8, 16), chosen
+        assert s.get_tuning() == chosen
+        assert s.autotune(nb, cache=str(tmp_path / "tuning.json")) == chosen
+        assert np.array_equal(trace_np(s.condense(to_dev(r))), ref[0])
+    s.set_tuning(cell_cells=0)
+
+
 CHEB_CASES = ["torus8_p1_courant4", "torus12_p2_coriolis", "torus16_p3_f1", "sphere_L2_p2"]
 
 
