@@ -345,7 +345,7 @@ const double *vcycle_start(hdg_ctx *c, int nb, int prec, const double *r, const 
 void restrict_p1(hdg_ctx *c, int nb, const double *res, double *rc, hipStream_t s) {
     vt_call(c->vcyc32, [&](auto tag) {
         using VT = std::remove_pointer_t<decltype(tag)>;
-        hdg::launch_restrict_trace<VT>(c->p, c->n_vert, nb, c->vf_row, c->vf_col, vt<VT>(res), rc, s, c->vorder);
+        hdg::launch_restrict_trace<VT>(c->p, c->n_vert, nb, c->vf_row, c->vf_col, vt<VT>(res), rc, s);
     });
 }
 
@@ -1131,17 +1131,6 @@ void setup_impl(const hdg_mesh *levels, int nlev, const int32_t *const *parents,
             for (int end = 0; end < 2; ++end) col[fill[c->topo.facet_vert[2 * e + end]]++] = 2 * e + end;
         c->vf_row = dev_upload(c, cnt);
         c->vf_col = dev_upload(c, col);
-        // pi^T takes the vertices by their first incident facet: the facets follow
-        // the cells' order, so the two ends of a facet come close together and
-        // fall in one XCD's range (numbering by level puts a refined level's new
-        // edge midpoints after all its old vertices)
-        std::vector<int32_t> first(nv, ne), ord(nv);
-        for (int v = 0; v < nv; ++v) {
-            for (int k = cnt[v]; k < cnt[v + 1]; ++k) first[v] = std::min(first[v], col[k] >> 1);
-            ord[v] = v;
-        }
-        std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return first[a] < first[b]; });
-        c->vorder = dev_upload(c, ord);
     }
 
     HDG_REQUIRE(levels[nlev - 1].n_vert == nv, "the finest hierarchy level must be the HDG mesh");
@@ -1728,7 +1717,7 @@ void mlp_pair(hdg_ctx *c, int nb, int coarse_its, const double *e, double *r, do
     const int64_t nv = (int64_t)F.n * nb;
     op_apply(c, nb, HDG_FP64, e, nullptr, r, s, HDG_KERNEL_APPLY);
     jacobi0(c, nb, HDG_FP64, r, nullptr, nullptr, nullptr, u, s);
-    hdg::launch_restrict_trace(c->p, c->n_vert, nb, c->vf_row, c->vf_col, r, c->p1_keep, s, c->vorder);
+    hdg::launch_restrict_trace(c->p, c->n_vert, nb, c->vf_row, c->vf_col, r, c->p1_keep, s);
     for (int k = 0; k < coarse_its; ++k) {
         if (k == 0)
             hdg::launch_copy(nv, c->p1_keep, F.b, s);

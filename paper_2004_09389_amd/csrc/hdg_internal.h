@@ -153,7 +153,6 @@ struct hdg_ctx {
     int32_t *d_fcell = nullptr;     // [n_facet][2] owner, other cell
     int32_t *d_floc = nullptr;      // [n_facet][2] local facet index in each
     int32_t *vf_row = nullptr, *vf_col = nullptr;  // vertex -> (facet, end) CSR, col = 2 e + end
-    int32_t *vorder = nullptr;  // order of the vertices in pi^T: by their first incident facet
 
     // P1 hierarchy, level 0 coarsest
     std::vector<hdg::P1LevelDev> lev;

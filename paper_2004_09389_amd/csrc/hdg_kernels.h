@@ -163,12 +163,10 @@ void launch_sweep(int M, int ne, int nb, const MT *T, const int *nbr, const VT *
 // FP64 residual y = b - S x with the FP64 operator, stored as FP32
 void launch_trace_residual_f32(int M, int ne, int nb, const double *S, const int *nbr, const double *x,
                                const double *b, float *y, hipStream_t s, int rhs_block = 1);
-// pi^T res onto the P1 vertices; rc receives values of the residual's type VT.
-// vorder (may be NULL): the order in which the vertices are taken, a permutation
-// of 0..nv-1 (each XCD takes a contiguous range of it)
+// pi^T res onto the P1 vertices; rc receives values of the residual's type VT
 template <typename VT>
 void launch_restrict_trace(int p, int nv, int nb, const int *vf_row, const int *vf_col, const VT *res, double *rc,
-                           hipStream_t s, const int *vorder = nullptr);
+                           hipStream_t s);
 
 // P1 level kernels; f32: the level vectors (b, x, y, xc, r, bc) hold float values
 // in their double buffers (the V-cycle of a mixed-precision solve)

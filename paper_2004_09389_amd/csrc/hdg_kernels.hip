@@ -622,16 +622,14 @@ __global__ __launch_bounds__(256) void k_sweep(int ne, int nb, const MT *__restr
 // rc[v] = sum over facet ends at v of sum_k w_end(k) res[e][k], w_0 = 1 - k/p, w_1 = k/p.
 // The facet ends of a vertex (5-7 on these meshes) are taken up to eight at a
 // time with every load in flight together (index clamped into the list, the
-// surplus ends not added; the sum keeps its order).  Vertices are taken in the
-// order vorder (when given), which keeps the two ends of a facet in one XCD's
-// range of it, so the facet's values are fetched into one L2.
+// surplus ends not added; the sum keeps its order).
 template <int M, typename VT>
 __global__ void k_restrict_trace(int nv, int nb, const int *__restrict__ vf_row, const int *__restrict__ vf_col,
-                                 const VT *__restrict__ res, VT *__restrict__ rc, const int *__restrict__ vorder) {
+                                 const VT *__restrict__ res, VT *__restrict__ rc) {
     constexpr int P = M - 1, U = 8;
     const int t = xcd_block() * blockDim.x + threadIdx.x;
     if (t >= nv * nb) return;
-    const int i = t / nb, r = t - i * nb, v = vorder ? vorder[i] : i;
+    const int v = t / nb, r = t - v * nb;
     const int c0 = vf_row[v], cnt = vf_row[v + 1] - c0;
     double acc = 0.0;
     for (int k0 = 0; k0 < cnt; k0 += U) {
@@ -2218,14 +2216,14 @@ template void launch_sweep<double, float>(int, int, int, const double *, const i
 
 template <typename VT>
 void launch_restrict_trace(int p, int nv, int nb, const int *vf_row, const int *vf_col, const VT *res, double *rc,
-                           hipStream_t s, const int *vorder) {
+                           hipStream_t s) {
     VT *rcv = reinterpret_cast<VT *>(rc);   // the P1 vector in the residual's type
-#define RT(P) hipLaunchKernelGGL((k_restrict_trace<P + 1, VT>), GRID8(nv * nb, 256), 0, s, nv, nb, vf_row, vf_col, res, rcv, vorder)
+#define RT(P) hipLaunchKernelGGL((k_restrict_trace<P + 1, VT>), GRID8(nv * nb, 256), 0, s, nv, nb, vf_row, vf_col, res, rcv)
     switch (p) { case 1: RT(1); break; case 2: RT(2); break; case 3: RT(3); break; }
 #undef RT
 }
-template void launch_restrict_trace<double>(int, int, int, const int *, const int *, const double *, double *, hipStream_t, const int *);
-template void launch_restrict_trace<float>(int, int, int, const int *, const int *, const float *, double *, hipStream_t, const int *);
+template void launch_restrict_trace<double>(int, int, int, const int *, const int *, const double *, double *, hipStream_t);
+template void launch_restrict_trace<float>(int, int, int, const int *, const int *, const float *, double *, hipStream_t);
 
 
 // P1 launchers: the level vectors hold double values, or float values in the
