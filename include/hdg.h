@@ -436,7 +436,9 @@ int hdg_mlp_train(hdg_ctx *ctx, int32_t nrhs, const double *e0, int32_t cycles, 
  * Launch shapes that do not change results.  hdg_autotune times each
  * candidate on the context's own mesh at nrhs right-hand sides (HIP events,
  * a few launches each, on the stream) and keeps the fastest; hdg_set_tuning
- * imposes values.  Both drop the captured graphs.  Synchronous. */
+ * imposes values.  Both drop the captured graphs.  Synchronous.  At nrhs >= 2
+ * hdg_autotune allocates two cell arrays of nrhs columns for its timing and
+ * frees them before it returns (HDG_EHIP if the allocation fails). */
 typedef struct {
     int32_t mlp_samples_per_lane; /* samples (facet, rhs) each lane gathers in the learned
                                      smoothing kernel: 1 or 2 (default 1), or 4 = four consecutive

@@ -1985,9 +1985,15 @@ extern "C" int hdg_autotune(hdg_ctx *c, int32_t nb, hdg_tuning *chosen, void *st
         int best_cc = 0;
         if (nb >= 2) {
             const size_t cell_bytes = sizeof(double) * (size_t)c->n_cell * c->nc * nb;
-            double *rc = nullptr, *qc = nullptr;
-            HDG_HIP_CHECK(hipMalloc(&rc, cell_bytes));
-            HDG_HIP_CHECK(hipMalloc(&qc, cell_bytes));
+            struct Scratch {   // freed on every way out, errors included
+                double *p = nullptr;
+                ~Scratch() {
+                    if (p) (void)hipFree(p);
+                }
+            } rcb, qcb;
+            HDG_HIP_CHECK(hipMalloc(&rcb.p, cell_bytes));
+            HDG_HIP_CHECK(hipMalloc(&qcb.p, cell_bytes));
+            double *const rc = rcb.p, *const qc = qcb.p;
             HDG_HIP_CHECK(hipMemsetAsync(rc, 0, cell_bytes, s));
             best = 1e300;
             for (int div : {1, 2, 4}) {
@@ -2005,8 +2011,6 @@ extern "C" int hdg_autotune(hdg_ctx *c, int32_t nb, hdg_tuning *chosen, void *st
                 }
             }
             HDG_HIP_CHECK(hipStreamSynchronize(s));
-            HDG_HIP_CHECK(hipFree(rc));
-            HDG_HIP_CHECK(hipFree(qc));
         }
         c->cell_cells = best_cc;
         if (chosen) {
